@@ -1,0 +1,202 @@
+/*
+ * bard.h -- C ABI of the MI355X (gfx950) batched rigid-body dynamics library.
+ *
+ * One call evaluates a kinematic tree for B independent configurations
+ * ("instances") at once: forward kinematics, the geometric Jacobian, inverse
+ * dynamics (RNEA), the joint-space mass matrix (CRBA), forward dynamics (ABA),
+ * a fused RNEA + CRBA + Jacobian chain, and vector-Jacobian products of RNEA and
+ * FK.  The algorithms are Featherstone's recursions that the paper restructures
+ * for batched GPU evaluation (Sec. 3); the joint transforms use precomputed
+ * Rodrigues constants (Sec. 3.2, eqs. (2)-(5)), traversals go level by level
+ * (Sec. 3.3, eq. (6)) and Jacobian columns are built directly (Sec. 3.4, eq. (7)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns a bard_status (0 on success, negative on error)
+ *   and never aborts or throws.  bard_last_error() returns a thread-local
+ *   message for the last failure.  Argument and topology errors are detected on
+ *   the host before any launch; an asynchronous device fault surfaces as
+ *   BARD_E_DEVICE on a later call.
+ * Memory: model arrays given to bard_model_create are host arrays, copied (the
+ *   caller keeps ownership).  Every operator I/O pointer is a DEVICE pointer
+ *   owned by the caller; the library never frees or retains it past the call.
+ *   Operators launch asynchronously on `stream` (a hipStream_t, NULL = the
+ *   default stream) and allocate nothing per call.
+ * Layout: each operator takes `L`, an array with one bard_layout per array
+ *   argument, in the order the arguments appear (inputs first, as listed in the
+ *   operator's comment).  Element k of instance b of an array lives at
+ *   base[b * stride_b + k * stride_k], where k is the flattened per-instance
+ *   index (row-major over the per-instance shape).  L == NULL means every array
+ *   is instance-minor ("SoA"): stride_b = 1, stride_k = B.  Strides are in
+ *   elements and must be >= 1.
+ * Scalars: `dtype` selects float or double for every floating array of a call.
+ * Spatial conventions: joint axes are unit vectors in the joint frame (they are
+ *   normalised at create).  Free joints use q = [x y z qx qy qz qw] (the
+ *   quaternion is normalised on read), velocity = body-frame twist [v; w], and
+ *   the generalised force of a free joint is the body-frame wrench [f; n].
+ *   Gravity is a world-frame vector (default {0, 0, -9.81}).
+ *   Jacobian rows are [linear; angular] (eq. (7)).  BARD_WORLD gives the
+ *   velocity of the body-fixed point at the world origin (the p x w form of
+ *   eq. (7)); BARD_LOCAL_WORLD_ALIGNED gives the velocity of the end-effector
+ *   origin, in world axes.
+ * Poses: 3x4 row-major [R | p] per body, the body frame in the world frame.
+ * B == 0 is a no-op returning BARD_OK.
+ */
+#ifndef BARD_H
+#define BARD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bard_model* bard_model_t;
+typedef struct bard_ws* bard_ws_t;
+typedef struct bard_plan* bard_plan_t;
+
+typedef enum {
+  BARD_OK = 0,
+  BARD_E_ARG = -1,         /* bad pointer, size, stride or enum value */
+  BARD_E_TOPOLOGY = -2,    /* parent[i] >= i, bad joint type, free joint not at a root, zero axis */
+  BARD_E_INERTIA = -3,     /* mass <= 0 or COM inertia not positive definite */
+  BARD_E_NOMEM = -4,       /* device or host allocation failed (create calls only) */
+  BARD_E_DEVICE = -5,      /* a HIP call failed, or an earlier asynchronous fault */
+  BARD_E_CAPACITY = -6,    /* batch larger than a workspace/plan capacity, or model too large */
+  BARD_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+} bard_status;
+
+typedef enum { BARD_F32 = 0, BARD_F64 = 1 } bard_dtype;
+typedef enum { BARD_REVOLUTE = 0, BARD_PRISMATIC = 1, BARD_FREE = 2, BARD_FIXED = 3 } bard_joint;
+typedef enum { BARD_WORLD = 0, BARD_LOCAL_WORLD_ALIGNED = 1 } bard_frame;
+
+typedef struct {
+  int64_t stride_b; /* elements between instance b and b+1 */
+  int64_t stride_k; /* elements between per-instance entries k and k+1 */
+} bard_layout;
+
+/* Human-readable name of a status code (static storage). */
+const char* bard_status_str(int status);
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* bard_last_error(void);
+/* Library version string, e.g. "bard 0.1 gfx950". */
+const char* bard_version(void);
+
+/* ---------------------------------------------------------------- model ----
+ * Build an immutable model (the paper's parse-once model, Fig. 1 / Sec. 3).
+ *   n_bodies   number of bodies, 1..BARD_MAX_BODIES (64)
+ *   parent     [n] parent index, -1 for a body attached to the world; parent[i] < i
+ *   joint_type [n] bard_joint; BARD_FREE only on body 0 with parent -1;
+ *              BARD_FIXED is rejected with BARD_E_UNSUPPORTED
+ *   axis       [n][3] joint axis in the joint frame (normalised here; ignored for FREE)
+ *   X_tree     [n][3][4] row-major [R_pre | t_pre]: pose of joint i's frame in
+ *              the parent body frame; the body frame is the joint frame after
+ *              the joint motion
+ *   inertia    [n][10] m, h = m*c (3), then I_xx I_xy I_yy I_xz I_yz I_zz of the
+ *              rotational inertia about the body-frame origin
+ * The host-side compile (level schedule, Rodrigues constants of eqs. (2)-(3),
+ * tables) happens here; device constants are uploaded on the first operator
+ * call on a device.  Errors: BARD_E_ARG, BARD_E_TOPOLOGY, BARD_E_INERTIA,
+ * BARD_E_UNSUPPORTED, BARD_E_NOMEM.  *out is set only on success. */
+int bard_model_create(int32_t n_bodies, const int32_t* parent, const int32_t* joint_type,
+                      const double* axis, const double* X_tree, const double* inertia,
+                      bard_model_t* out);
+/* Set the world-frame gravity vector (host array of 3). Default {0, 0, -9.81}. */
+int bard_model_set_gravity(bard_model_t model, const double* g);
+/* Sizes of a model. Any output pointer may be NULL. */
+int bard_model_info(bard_model_t model, int32_t* nq, int32_t* nv, int32_t* n_bodies, int32_t* depth);
+/* Level schedule chosen by the compiler: lanes per instance and levels. */
+int bard_model_schedule(bard_model_t model, int32_t* lanes_per_instance, int32_t* levels);
+/* Host-side evaluation of one joint's parent-to-child transform from the Rodrigues
+ * constants (eqs. (4)-(5)), in FP64, for testing the compile step without a GPU.
+ * out_R: [3][3] row-major, out_t: [3].  Free joints take q as 7 values. */
+int bard_model_joint_transform(bard_model_t model, int32_t body, const double* q, double* out_R,
+                               double* out_t);
+int bard_model_destroy(bard_model_t model);
+
+/* ------------------------------------------------------------ workspace ----
+ * A workspace owns the tiered cache of one stream (Sec. 3.1: poses, then
+ * velocities, then bias forces, then M), sized for max_batch instances.
+ * Operators accept ws == NULL (no caching).  Errors: BARD_E_ARG, BARD_E_NOMEM. */
+int bard_ws_create(bard_model_t model, bard_dtype dtype, int64_t max_batch, bard_ws_t* out);
+int bard_ws_destroy(bard_ws_t ws);
+
+/* ------------------------------------------------------------ operators ----
+ * q_tag / qd_tag: caller version tags of q and qd for the cache; 0 = unknown
+ * (always recompute).  Equal non-zero tags promise unchanged contents. */
+
+/* FK (world pose of every body, Sec. 3.1 tier 3).
+ * Arrays (L order): q [nq] in, poses [n_bodies*12] out. */
+int bard_fk(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, void* poses,
+            const bard_layout* L, uint64_t q_tag, int64_t B, void* stream);
+
+/* Geometric Jacobian of n_ee end-effector bodies (eq. (7)); zeros off the
+ * root-to-body path.  ee_body is a HOST array of body indices.
+ * Arrays: q [nq] in, J [n_ee*6*nv] out (per end effector a 6 x nv block). */
+int bard_jacobian(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, int32_t n_ee,
+                  const int32_t* ee_body, bard_frame frame, void* J, const bard_layout* L,
+                  uint64_t q_tag, int64_t B, void* stream);
+
+/* Inverse dynamics tau = M(q) qdd + C(q, qd) qd + g(q) (RNEA, Sec. 3.3).
+ * inertia_override: NULL or a DEVICE array [n_bodies][10] (same dtype, shared by
+ * all instances) replacing the model's inertial parameters.
+ * Arrays: q [nq], qd [nv], qdd [nv] in, tau [nv] out. */
+int bard_rnea(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd,
+              const void* qdd, const void* inertia_override, void* tau, const bard_layout* L,
+              uint64_t q_tag, uint64_t qd_tag, int64_t B, void* stream);
+
+/* Joint-space mass matrix (CRBA); both triangles written, bitwise symmetric.
+ * Arrays: q [nq] in, M [nv*nv] out (row-major). */
+int bard_crba(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, void* M,
+              const bard_layout* L, uint64_t q_tag, int64_t B, void* stream);
+
+/* Forward dynamics qdd = M^-1 (tau - C qd - g) (ABA, three passes).
+ * Arrays: q [nq], qd [nv], tau [nv] in, qdd [nv] out. */
+int bard_aba(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd,
+             const void* tau, void* qdd, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
+             int64_t B, void* stream);
+
+/* Fused RNEA + CRBA + Jacobian: one forward and one backward sweep per
+ * instance sharing the per-body transforms.  Results equal the three separate
+ * operators.  Arrays: q [nq], qd [nv], qdd [nv] in; tau [nv], M [nv*nv],
+ * J [n_ee*6*nv] out. */
+int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd,
+               const void* qdd, int32_t n_ee, const int32_t* ee_body, bard_frame frame, void* tau,
+               void* M, void* J, const bard_layout* L, int64_t B, void* stream);
+
+/* ------------------------------------------------------------- adjoints ----
+ * Vector-Jacobian products (the gradients Sec. 4.3 takes through RNEA).
+ * rnea_vjp: given tau_bar, writes q_bar [nq], qd_bar [nv], qdd_bar [nv] per
+ * instance and, if inertia_bar != NULL, the gradient with respect to the
+ * [n_bodies][10] inertial parameters summed over the batch (a DEVICE array,
+ * overwritten, reduced in a fixed order so results are run-to-run identical).
+ * Arrays (L order): q, qd, qdd, tau_bar in; q_bar, qd_bar, qdd_bar out
+ * (inertia_bar is dense [n_bodies*10] and takes no layout).
+ * Trees with a free joint return BARD_E_UNSUPPORTED. */
+int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* qd,
+                  const void* qdd, const void* inertia_override, const void* tau_bar, void* q_bar,
+                  void* qd_bar, void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B,
+                  void* stream);
+/* fk_vjp: given poses_bar [n_bodies*12], writes q_bar [nq].
+ * Arrays: q, poses_bar in; q_bar out.  Free joints: BARD_E_UNSUPPORTED. */
+int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* poses_bar,
+                void* q_bar, const bard_layout* L, int64_t B, void* stream);
+
+/* ---------------------------------------------------- multi-tree plans ----
+ * A plan batches several models with their own batch sizes into one
+ * persistent launch over a work queue.  op_mask: bit 0 RNEA, bit 1 CRBA,
+ * bit 2 Jacobian (their tip end effectors, see bard_plan_create).
+ * io: per model 6 device pointers q, qd, qdd, tau, M, J (SoA layouts;
+ * unused outputs may be NULL).  bard_plan_run captures the launch into a HIP
+ * graph on first use and replays it afterwards. */
+int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch,
+                     uint32_t op_mask, bard_dtype dtype, bard_plan_t* out);
+int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms);
+int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream);
+int bard_plan_destroy(bard_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BARD_H */

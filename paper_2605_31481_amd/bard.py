@@ -1,0 +1,282 @@
+"""ctypes binding of libbard.so.
+
+Argument marshalling only: every step of every operator runs in the HIP
+kernels of ``libbard.so``.  Device tensors come from PyTorch, which is used for
+device memory and the current stream.  If the library is missing this module
+raises at import time; there is no CPU fallback.
+
+Layouts.  ``layout="soa"`` (default) means instance-minor arrays of shape
+``[K, B]`` (element k of instance b at ``[k, b]``), the layout the kernels
+store fastest.  ``layout="aos"`` means ``[B, K]``.  Multi-index outputs are
+flattened row-major per instance (e.g. ``M`` is ``nv*nv`` per instance), and
+``as_batch_major`` turns any of them into a ``[B, ...]`` view without copying.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbard.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bard.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with paper_2605_31481_amd.build.build() "
+        "(hipcc --offload-arch=gfx950).  There is no fallback implementation.")
+
+# PyTorch ships its own HIP runtime with the same soname as the system one that
+# libbard.so links against.  Loading torch first makes libbard.so bind to the
+# runtime already in the process, so one runtime owns the device and streams.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+F32, F64 = 0, 1
+REVOLUTE, PRISMATIC, FREE, FIXED = 0, 1, 2, 3
+WORLD, LOCAL_WORLD_ALIGNED = 0, 1
+
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int32
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("stride_b", ctypes.c_int64), ("stride_k", ctypes.c_int64)]
+
+
+_LP = ctypes.POINTER(Layout)
+
+
+def _sig(name, argtypes, restype=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+bard_status_str = _sig("bard_status_str", [ctypes.c_int], ctypes.c_char_p)
+bard_last_error = _sig("bard_last_error", [], ctypes.c_char_p)
+bard_version = _sig("bard_version", [], ctypes.c_char_p)
+bard_model_create = _sig("bard_model_create", [_i32, _c_i32p, _c_i32p, _c_dp, _c_dp, _c_dp, ctypes.POINTER(_vp)])
+bard_model_set_gravity = _sig("bard_model_set_gravity", [_vp, _c_dp])
+bard_model_info = _sig("bard_model_info", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
+bard_model_schedule = _sig("bard_model_schedule", [_vp, _c_i32p, _c_i32p])
+bard_model_joint_transform = _sig("bard_model_joint_transform", [_vp, _i32, _c_dp, _c_dp, _c_dp])
+bard_model_destroy = _sig("bard_model_destroy", [_vp])
+bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
+bard_ws_destroy = _sig("bard_ws_destroy", [_vp])
+bard_fk = _sig("bard_fk", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
+bard_jacobian = _sig("bard_jacobian", [_vp, _vp, ctypes.c_int, _vp, _i32, _c_i32p, ctypes.c_int, _vp, _LP, _u64,
+                                       _i64, _vp])
+bard_rnea = _sig("bard_rnea", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _LP, _u64, _u64, _i64, _vp])
+bard_crba = _sig("bard_crba", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
+bard_aba = _sig("bard_aba", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _LP, _u64, _u64, _i64, _vp])
+bard_chain = _sig("bard_chain", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _i32, _c_i32p, ctypes.c_int, _vp, _vp, _vp,
+                                 _LP, _i64, _vp])
+bard_rnea_vjp = _sig("bard_rnea_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64,
+                                       _vp])
+bard_fk_vjp = _sig("bard_fk_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
+
+
+def declared_symbols() -> list:
+    """Names of every function declared in include/bard.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bard_[a-z0-9_]+)\s*\(", text)))
+
+
+class BardError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = bard_status_str(status).decode()
+        detail = bard_last_error().decode()
+        super().__init__(f"{where}: {msg}: {detail}")
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise BardError(rc, where)
+
+
+def _i32arr(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+    return a, a.ctypes.data_as(_c_i32p)
+
+
+def _f64arr(x):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return a, a.ctypes.data_as(_c_dp)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _stream_ptr(t):
+    torch = _torch()
+    return _vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _batch_of(t, K: int, layout: str) -> int:
+    if t.dim() != 2:
+        raise ValueError("operator arrays are 2-D: [K, B] (soa) or [B, K] (aos)")
+    if layout == "soa":
+        if t.shape[0] != K:
+            raise ValueError(f"expected [{K}, B], got {tuple(t.shape)}")
+        return int(t.shape[1])
+    if t.shape[1] != K:
+        raise ValueError(f"expected [B, {K}], got {tuple(t.shape)}")
+    return int(t.shape[0])
+
+
+def _layouts(tensors, layout: str):
+    arr = (Layout * len(tensors))()
+    for i, t in enumerate(tensors):
+        if layout == "soa":
+            arr[i].stride_k, arr[i].stride_b = t.stride(0), t.stride(1)
+        else:
+            arr[i].stride_b, arr[i].stride_k = t.stride(0), t.stride(1)
+    return arr
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _new(ref, K: int, B: int, layout: str):
+    torch = _torch()
+    shape = (K, B) if layout == "soa" else (B, K)
+    return torch.empty(shape, dtype=ref.dtype, device=ref.device)
+
+
+def as_batch_major(t, *shape, layout: str = "soa"):
+    """View an operator array as [B, *shape] without copying."""
+    if layout == "soa":
+        return t.t().unflatten(1, shape)
+    return t.unflatten(1, shape)
+
+
+class Model:
+    """A compiled kinematic tree (see include/bard.h, bard_model_create)."""
+
+    def __init__(self, parent, joint_type, axis, X_tree, inertia, gravity=None):
+        self._parent, p_parent = _i32arr(parent)
+        self._jtype, p_jt = _i32arr(joint_type)
+        self._axis, p_axis = _f64arr(axis)
+        self._xt, p_xt = _f64arr(X_tree)
+        self._pi, p_pi = _f64arr(inertia)
+        n = int(self._parent.shape[0])
+        h = _vp()
+        _check(bard_model_create(n, p_parent, p_jt, p_axis, p_xt, p_pi, ctypes.byref(h)), "bard_model_create")
+        self._h = h
+        if gravity is not None:
+            g, pg = _f64arr(gravity)
+            _check(bard_model_set_gravity(self._h, pg), "bard_model_set_gravity")
+        nq, nv, nb, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(bard_model_info(self._h, ctypes.byref(nq), ctypes.byref(nv), ctypes.byref(nb), ctypes.byref(d)),
+               "bard_model_info")
+        self.nq, self.nv, self.n_bodies, self.depth = nq.value, nv.value, nb.value, d.value
+        lanes, levels = ctypes.c_int32(), ctypes.c_int32()
+        _check(bard_model_schedule(self._h, ctypes.byref(lanes), ctypes.byref(levels)), "bard_model_schedule")
+        self.lanes_per_instance = lanes.value
+
+    @classmethod
+    def from_tree(cls, tree):
+        return cls(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia,
+                   getattr(tree, "gravity", None))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            bard_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def joint_transform(self, body: int, q):
+        qa, pq = _f64arr(q)
+        R = np.zeros(9)
+        t = np.zeros(3)
+        _check(bard_model_joint_transform(self._h, int(body), pq, R.ctypes.data_as(_c_dp), t.ctypes.data_as(_c_dp)),
+               "bard_model_joint_transform")
+        return R.reshape(3, 3), t
+
+    # ---------------------------------------------------------------- ops --
+    def fk(self, q, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        out = out if out is not None else _new(q, 12 * self.n_bodies, B, layout)
+        L = _layouts([q, out], layout)
+        _check(bard_fk(self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q)), "bard_fk")
+        return out
+
+    def jacobian(self, q, ee: Sequence[int], frame: int = WORLD, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        ee_a, pee = _i32arr(ee)
+        out = out if out is not None else _new(q, 6 * self.nv * len(ee_a), B, layout)
+        L = _layouts([q, out], layout)
+        _check(bard_jacobian(self._h, None, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, 0, B,
+                             _stream_ptr(q)), "bard_jacobian")
+        return out
+
+    def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        out = out if out is not None else _new(q, self.nv, B, layout)
+        L = _layouts([q, qd, qdd, out], layout)
+        if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
+            raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
+        _check(bard_rnea(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
+                         0, 0, B, _stream_ptr(q)), "bard_rnea")
+        return out
+
+    def crba(self, q, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        out = out if out is not None else _new(q, self.nv * self.nv, B, layout)
+        L = _layouts([q, out], layout)
+        _check(bard_crba(self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q)), "bard_crba")
+        return out
+
+    def aba(self, q, qd, tau, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        out = out if out is not None else _new(q, self.nv, B, layout)
+        L = _layouts([q, qd, tau, out], layout)
+        _check(bard_aba(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out), L, 0, 0, B,
+                        _stream_ptr(q)), "bard_aba")
+        return out
+
+    def chain(self, q, qd, qdd, ee: Sequence[int], frame: int = WORLD, out=None, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        ee_a, pee = _i32arr(ee)
+        if out is None:
+            out = (_new(q, self.nv, B, layout), _new(q, self.nv * self.nv, B, layout),
+                   _new(q, 6 * self.nv * len(ee_a), B, layout))
+        tau, M, J = out
+        L = _layouts([q, qd, qdd, tau, M, J], layout)
+        _check(bard_chain(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), len(ee_a), pee, int(frame),
+                          _ptr(tau), _ptr(M), _ptr(J), L, B, _stream_ptr(q)), "bard_chain")
+        return tau, M, J

@@ -1,0 +1,50 @@
+"""Build libbard.so (HIP kernels for gfx950 + host compiler + C ABI) in-tree."""
+
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csrc")
+_OUT = os.path.join(_HERE, "libbard.so")
+_BUILD = os.path.join(os.path.dirname(_HERE), "_build", "bard")
+
+SOURCES = ["kernels.hip", "api.cpp", "compiler.cpp"]
+
+# Packed FP32 instructions are turned off for every HIP translation unit.
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
+
+
+def library_path() -> str:
+    return _OUT
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(_BUILD, src.replace(".", "_") + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = ["hipcc", *lang, *HIP_FLAGS, "-c", os.path.join(_SRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(_BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = _OUT + ".tmp"
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _OUT)
+    return _OUT
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

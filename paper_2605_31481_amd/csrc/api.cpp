@@ -1,0 +1,605 @@
+// C ABI of the library: argument checks, per-device model upload, launch
+// configuration.  Every operator validates on the host before launching and
+// never allocates per call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "status.h"
+
+namespace bard {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// Launch shape chosen per model: T instances per workgroup.
+struct Shape {
+  int waves, logT, T, log2P;
+};
+
+}  // namespace bard
+
+struct bard_ws {
+  bard_model* model;
+  bard_dtype dtype;
+  int64_t max_batch;
+};
+
+using namespace bard;
+
+namespace {
+
+int check_device_state() {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BARD_E_DEVICE, std::string("earlier device error: ") + hipGetErrorString(e));
+  }
+  return BARD_OK;
+}
+
+size_t lds_limit(int dev) {
+  static size_t cache[BARD_MAX_DEVICES] = {0};
+  if (dev < 0 || dev >= BARD_MAX_DEVICES) return 65536;
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cache[dev] = (size_t)v;
+  }
+  return cache[dev];
+}
+
+int default_target_T() {
+  const char* e = getenv("BARD_TILE");
+  if (e) {
+    int t = atoi(e);
+    if (t >= 1 && t <= 256) return t;
+  }
+  return 16;
+}
+
+// Upload the compiled model to the current device (once per device).
+int ensure_device(bard_model* m, DeviceCopy** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BARD_E_DEVICE, "hipGetDevice failed (no GPU?)");
+  if (dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "device index out of range");
+  DeviceCopy& dc = m->dev[dev];
+  if (dc.ready) {
+    *out = &dc;
+    return BARD_OK;
+  }
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (dc.ready) {
+    *out = &dc;
+    return BARD_OK;
+  }
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off_c32 = 0;
+  size_t off_c64 = align(off_c32 + m->cst32.size() * sizeof(float));
+  size_t off_meta = align(off_c64 + m->cst64.size() * sizeof(double));
+  size_t off_sb = align(off_meta + m->n * sizeof(I4));
+  size_t off_ss = align(off_sb + m->sched_body.size() * sizeof(int16_t));
+  size_t off_cs = align(off_ss + m->sched_src.size());
+  size_t off_li = align(off_cs + m->child_slot.size());
+  size_t off_mt = align(off_li + m->level_info.size() * sizeof(int));
+  size_t total = align(off_mt + m->mtab.size() * sizeof(int));
+  std::vector<unsigned char> host(total, 0);
+  std::memcpy(&host[off_c32], m->cst32.data(), m->cst32.size() * sizeof(float));
+  std::memcpy(&host[off_c64], m->cst64.data(), m->cst64.size() * sizeof(double));
+  std::vector<I4> meta(m->n);
+  for (int i = 0; i < m->n; ++i) meta[i] = I4{m->parent[i], m->jtype[i], m->qi[i], m->vi[i]};
+  std::memcpy(&host[off_meta], meta.data(), meta.size() * sizeof(I4));
+  std::memcpy(&host[off_sb], m->sched_body.data(), m->sched_body.size() * sizeof(int16_t));
+  std::memcpy(&host[off_ss], m->sched_src.data(), m->sched_src.size());
+  std::memcpy(&host[off_cs], m->child_slot.data(), m->child_slot.size());
+  std::memcpy(&host[off_li], m->level_info.data(), m->level_info.size() * sizeof(int));
+  std::memcpy(&host[off_mt], m->mtab.data(), m->mtab.size() * sizeof(int));
+  void* blob = nullptr;
+  if (hipMalloc(&blob, total) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc of the model constants failed");
+  if (hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(blob);
+    return fail(BARD_E_DEVICE, "upload of the model constants failed");
+  }
+  unsigned char* base = (unsigned char*)blob;
+  DevModel& dm = dc.dm;
+  dm.c32 = (const float*)(base + off_c32);
+  dm.c64 = (const double*)(base + off_c64);
+  dm.meta = (const I4*)(base + off_meta);
+  dm.sched_body = (const int16_t*)(base + off_sb);
+  dm.sched_src = (const int8_t*)(base + off_ss);
+  dm.child_slot = (const int8_t*)(base + off_cs);
+  dm.level_info = (const int*)(base + off_li);
+  dm.mtab = (const int*)(base + off_mt);
+  dm.n = m->n;
+  dm.nq = m->nq;
+  dm.nv = m->nv;
+  dm.depth = m->depth;
+  dm.P = m->P;
+  dm.log2P = m->log2P;
+  dm.kmax = m->kmax;
+  dm.free_root = m->free_root ? 1 : 0;
+  for (int k = 0; k < 3; ++k) {
+    dm.g32[k] = (float)m->g[k];
+    dm.g64[k] = m->g[k];
+  }
+  dc.blob = blob;
+  dc.ready = true;
+  *out = &dc;
+  return BARD_OK;
+}
+
+int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out) {
+  if (n_ee < 1 || n_ee > BARD_MAX_EE) return fail(BARD_E_ARG, "n_ee must be in 1..16");
+  if (!ee_body) return fail(BARD_E_ARG, "ee_body is NULL");
+  std::vector<int> key(ee_body, ee_body + n_ee);
+  for (int b : key)
+    if (b < 0 || b >= m->n) return fail(BARD_E_ARG, "end-effector body index out of range");
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = dc->ee_sets.find(key);
+  if (it != dc->ee_sets.end()) {
+    *out = it->second.second;
+    return BARD_OK;
+  }
+  std::vector<int> jt = jacobian_table(m, key);
+  std::vector<int> host(jt.size() + key.size());
+  std::copy(jt.begin(), jt.end(), host.begin());
+  std::copy(key.begin(), key.end(), host.begin() + jt.size());
+  void* p = nullptr;
+  if (hipMalloc(&p, host.size() * sizeof(int)) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc failed");
+  if (hipMemcpy(p, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p);
+    return fail(BARD_E_DEVICE, "upload of the end-effector table failed");
+  }
+  DevEE e;
+  e.jtab = (const int*)p;
+  e.ee_body = (const int*)p + jt.size();
+  e.n_ee = n_ee;
+  dc->ee_sets[key] = {p, e};
+  *out = e;
+  return BARD_OK;
+}
+
+bool layout_of(const bard_layout* L, int idx, int64_t B, int64_t K, int64_t* sb, int64_t* sk) {
+  if (!L) {
+    *sb = 1;
+    *sk = B;
+    return true;
+  }
+  *sb = L[idx].stride_b;
+  *sk = L[idx].stride_k;
+  if (*sb < 1 || *sk < 1) return false;
+  (void)K;
+  return true;
+}
+
+Shape pick_shape(const bard_model* m, size_t per_inst_bytes, int dev) {
+  // Instances per workgroup T = waves * (64 >> log2P).  Start from the model's
+  // lanes per instance and the target tile; shrink the tile (fewer waves, then
+  // more lanes per instance) until the on-chip staging fits.
+  int log2P = m->log2P;
+  int target = default_target_T();
+  int waves = std::max(1, std::min(4, target / (64 >> log2P)));
+  size_t lim = lds_limit(dev);
+  for (;;) {
+    size_t T = (size_t)waves * (64 >> log2P);
+    if (T * per_inst_bytes <= lim) break;
+    if (waves > 1) waves >>= 1;
+    else if (log2P < 6) ++log2P;
+    else break;
+  }
+  int T = waves * (64 >> log2P);
+  int logT = 0;
+  while ((1 << logT) < T) ++logT;
+  return Shape{waves, logT, T, log2P};
+}
+
+int common_checks(bard_model* m, bard_ws_t ws, int dtype, int64_t B) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "dtype must be BARD_F32 or BARD_F64");
+  if (B < 0) return fail(BARD_E_ARG, "batch must be >= 0");
+  if (B > ((int64_t)1 << 40)) return fail(BARD_E_CAPACITY, "batch too large");
+  if (ws) {
+    if (ws->model != m) return fail(BARD_E_ARG, "workspace belongs to another model");
+    if (ws->dtype != dtype) return fail(BARD_E_ARG, "workspace dtype differs from the call's dtype");
+    if (B > ws->max_batch) return fail(BARD_E_CAPACITY, "batch exceeds the workspace capacity");
+  }
+  return BARD_OK;
+}
+
+template <class Real>
+Args<Real> blank_args(int64_t B) {
+  Args<Real> a;
+  std::memset(&a, 0, sizeof(a));
+  a.B = B;
+  a.xcd_remap = 1;
+  return a;
+}
+
+size_t tree_lds_per_inst(const bard_model* m, int ops, int n_ee, int frame, size_t rs) {
+  size_t f = 0;
+  bool need_s = ops & (OP_JAC | OP_RNEA | OP_CRBA);
+  if (need_s) f += 6 * m->nv;
+  if (ops & OP_CRBA) f += 6 * m->nv + 10 * m->n;
+  if (ops & OP_RNEA) f += 6 * m->n;
+  f += 3;
+  if ((ops & OP_JAC) && frame == 1) f += 3 * n_ee;
+  return f * rs;
+}
+
+template <class Real, int OPS>
+int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int frame, hipStream_t st) {
+  DeviceCopy* dc = nullptr;
+  int rc = ensure_device(m, &dc);
+  if (rc) return rc;
+  DevEE ee{nullptr, nullptr, 0};
+  if (OPS & OP_JAC) {
+    rc = ensure_ee(m, dc, n_ee, ee_body, &ee);
+    if (rc) return rc;
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  size_t per = tree_lds_per_inst(m, OPS, n_ee, frame, sizeof(Real));
+  Shape sh = pick_shape(m, per, dev);
+  size_t lds = per * sh.T;
+  if (lds > lds_limit(dev)) return fail(BARD_E_CAPACITY, "model too large for on-chip staging");
+  ar.logT = sh.logT;
+  ar.log2P = sh.log2P;
+  ar.frame = frame;
+  int64_t grid = (ar.B + sh.T - 1) / sh.T;
+  if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
+  hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, sh.waves * 64, lds, st);
+  if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BARD_OK;
+}
+
+template <class Real>
+int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
+  DeviceCopy* dc = nullptr;
+  int rc = ensure_device(m, &dc);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  size_t per = (6 * m->nv + (6 + 21 + 6 + 8) * m->n) * sizeof(Real);
+  Shape sh = pick_shape(m, per, dev);
+  size_t lds = per * sh.T;
+  if (lds > lds_limit(dev)) return fail(BARD_E_CAPACITY, "model too large for on-chip staging");
+  ar.logT = sh.logT;
+  ar.log2P = sh.log2P;
+  int64_t grid = (ar.B + sh.T - 1) / sh.T;
+  if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
+  hipError_t e = launch_aba<Real>(dc->dm, ar, (int)grid, sh.waves * 64, lds, st);
+  if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BARD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bard_status_str(int s) {
+  switch (s) {
+    case BARD_OK: return "BARD_OK";
+    case BARD_E_ARG: return "BARD_E_ARG";
+    case BARD_E_TOPOLOGY: return "BARD_E_TOPOLOGY";
+    case BARD_E_INERTIA: return "BARD_E_INERTIA";
+    case BARD_E_NOMEM: return "BARD_E_NOMEM";
+    case BARD_E_DEVICE: return "BARD_E_DEVICE";
+    case BARD_E_CAPACITY: return "BARD_E_CAPACITY";
+    case BARD_E_UNSUPPORTED: return "BARD_E_UNSUPPORTED";
+    default: return "BARD_E_UNKNOWN";
+  }
+}
+
+const char* bard_last_error(void) { return g_err.c_str(); }
+
+const char* bard_version(void) { return "bard 0.1 gfx950"; }
+
+int bard_model_create(int32_t n, const int32_t* parent, const int32_t* joint_type, const double* axis,
+                      const double* X_tree, const double* inertia, bard_model_t* out) {
+  g_err.clear();
+  if (!out) return fail(BARD_E_ARG, "out is NULL");
+  if (!parent || !joint_type || !axis || !X_tree || !inertia) return fail(BARD_E_ARG, "NULL model array");
+  if (n < 1 || n > BARD_MAX_BODIES) return fail(BARD_E_ARG, "n_bodies must be in 1..64");
+  bard_model* m = new (std::nothrow) bard_model();
+  if (!m) return fail(BARD_E_NOMEM, "host allocation failed");
+  m->n = n;
+  m->parent.assign(parent, parent + n);
+  m->jtype.assign(joint_type, joint_type + n);
+  m->axis.assign(axis, axis + 3 * n);
+  m->xtree.assign(X_tree, X_tree + 12 * n);
+  m->inertia.assign(inertia, inertia + 10 * n);
+  for (double x : m->axis)
+    if (!std::isfinite(x)) { delete m; return fail(BARD_E_ARG, "non-finite axis"); }
+  for (double x : m->xtree)
+    if (!std::isfinite(x)) { delete m; return fail(BARD_E_ARG, "non-finite X_tree"); }
+  for (double x : m->inertia)
+    if (!std::isfinite(x)) { delete m; return fail(BARD_E_INERTIA, "non-finite inertia"); }
+  std::string err;
+  int rc = compile_model(m, &err);
+  if (rc != BARD_OK) {
+    delete m;
+    return fail(rc, err);
+  }
+  *out = m;
+  return BARD_OK;
+}
+
+int bard_model_set_gravity(bard_model_t m, const double* g) {
+  if (!m || !g) return fail(BARD_E_ARG, "NULL argument");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(g[k])) return fail(BARD_E_ARG, "non-finite gravity");
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (int k = 0; k < 3; ++k) m->g[k] = g[k];
+  for (auto& dc : m->dev)
+    if (dc.ready)
+      for (int k = 0; k < 3; ++k) {
+        dc.dm.g32[k] = (float)g[k];
+        dc.dm.g64[k] = g[k];
+      }
+  return BARD_OK;
+}
+
+int bard_model_info(bard_model_t m, int32_t* nq, int32_t* nv, int32_t* n_bodies, int32_t* depth) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  if (nq) *nq = m->nq;
+  if (nv) *nv = m->nv;
+  if (n_bodies) *n_bodies = m->n;
+  if (depth) *depth = m->depth;
+  return BARD_OK;
+}
+
+int bard_model_schedule(bard_model_t m, int32_t* lanes, int32_t* levels) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  if (lanes) *lanes = m->P;
+  if (levels) *levels = m->depth;
+  return BARD_OK;
+}
+
+int bard_model_joint_transform(bard_model_t m, int32_t body, const double* q, double* R, double* t) {
+  if (!m || !q || !R || !t) return fail(BARD_E_ARG, "NULL argument");
+  if (body < 0 || body >= m->n) return fail(BARD_E_ARG, "body out of range");
+  const double* c = &m->cst64[(size_t)body * CST];
+  if (m->jtype[body] == J_FREE) {
+    double x = q[3], y = q[4], z = q[5], w = q[6];
+    double inv = 1.0 / std::sqrt(x * x + y * y + z * z + w * w);
+    x *= inv; y *= inv; z *= inv; w *= inv;
+    double Rq[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                    2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                    2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j)
+        R[3 * i + j] = c[C_R0 + 3 * i] * Rq[j] + c[C_R0 + 3 * i + 1] * Rq[3 + j] + c[C_R0 + 3 * i + 2] * Rq[6 + j];
+      t[i] = c[C_R0 + 3 * i] * q[0] + c[C_R0 + 3 * i + 1] * q[1] + c[C_R0 + 3 * i + 2] * q[2] + c[C_T0 + i];
+    }
+    return BARD_OK;
+  }
+  double s = std::sin(q[0]), co = std::cos(q[0]);
+  for (int k = 0; k < 9; ++k) R[k] = c[C_R0 + k] + s * c[C_A + k] + (1.0 - co) * c[C_B + k];
+  for (int k = 0; k < 3; ++k) t[k] = c[C_T0 + k] + q[0] * c[C_D + k];
+  return BARD_OK;
+}
+
+int bard_model_destroy(bard_model_t m) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (int d = 0; d < BARD_MAX_DEVICES; ++d) {
+    DeviceCopy& dc = m->dev[d];
+    if (!dc.ready) continue;
+    (void)hipSetDevice(d);
+    (void)hipFree(dc.blob);
+    for (auto& kv : dc.ee_sets) (void)hipFree(kv.second.first);
+  }
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete m;
+  return BARD_OK;
+}
+
+int bard_ws_create(bard_model_t m, bard_dtype dtype, int64_t max_batch, bard_ws_t* out) {
+  if (!m || !out) return fail(BARD_E_ARG, "NULL argument");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
+  if (max_batch < 1) return fail(BARD_E_ARG, "max_batch must be >= 1");
+  bard_ws* w = new (std::nothrow) bard_ws();
+  if (!w) return fail(BARD_E_NOMEM, "host allocation failed");
+  w->model = m;
+  w->dtype = dtype;
+  w->max_batch = max_batch;
+  *out = w;
+  return BARD_OK;
+}
+
+int bard_ws_destroy(bard_ws_t w) {
+  if (!w) return fail(BARD_E_ARG, "NULL workspace");
+  delete w;
+  return BARD_OK;
+}
+
+#define BARD_DISPATCH_DTYPE(dtype, CALL_F, CALL_D) ((dtype) == BARD_F32 ? (CALL_F) : (CALL_D))
+
+int bard_fk(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void* poses, const bard_layout* L,
+            uint64_t q_tag, int64_t B, void* stream) {
+  (void)q_tag;
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !poses) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.poses = (R*)poses;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 12 * m->n, &a.sp_b, &a.sp_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_FK>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, int32_t n_ee,
+                  const int32_t* ee_body, bard_frame frame, void* J, const bard_layout* L, uint64_t q_tag, int64_t B,
+                  void* stream) {
+  (void)q_tag;
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (frame != BARD_WORLD && frame != BARD_LOCAL_WORLD_ALIGNED) return fail(BARD_E_ARG, "bad frame");
+  if (n_ee < 1 || n_ee > BARD_MAX_EE || !ee_body) return fail(BARD_E_ARG, "n_ee must be in 1..16 with ee_body");
+  if (B == 0) return BARD_OK;
+  if (!q || !J) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.J = (R*)J;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 6 * m->nv * n_ee, &a.sJ_b, &a.sJ_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+              const void* inertia_override, void* tau, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
+              int64_t B, void* stream) {
+  (void)q_tag;
+  (void)qd_tag;
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !qd || !qdd || !tau) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.qd = (const R*)qd;
+    a.qdd = (const R*)qdd;
+    a.pi_ovr = (const R*)inertia_override;
+    a.tau = (R*)tau;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
+        !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.st_b, &a.st_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void* M, const bard_layout* L,
+              uint64_t q_tag, int64_t B, void* stream) {
+  (void)q_tag;
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !M) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.M = (R*)M;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv * m->nv, &a.sM_b, &a.sM_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_aba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* tau,
+             void* qdd, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag, int64_t B, void* stream) {
+  (void)q_tag;
+  (void)qd_tag;
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !qd || !tau || !qdd) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.qd = (const R*)qd;
+    a.tau_in = (const R*)tau;
+    a.qdd_out = (R*)qdd;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
+        !layout_of(L, 2, B, m->nv, &a.sti_b, &a.sti_k) || !layout_of(L, 3, B, m->nv, &a.sqo_b, &a.sqo_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_aba<R>(m, a, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+               int32_t n_ee, const int32_t* ee_body, bard_frame frame, void* tau, void* M, void* J,
+               const bard_layout* L, int64_t B, void* stream) {
+  int rc = common_checks(m, ws, dtype, B);
+  if (rc) return rc;
+  if (frame != BARD_WORLD && frame != BARD_LOCAL_WORLD_ALIGNED) return fail(BARD_E_ARG, "bad frame");
+  if (n_ee < 1 || n_ee > BARD_MAX_EE || !ee_body) return fail(BARD_E_ARG, "n_ee must be in 1..16 with ee_body");
+  if (B == 0) return BARD_OK;
+  if (!q || !qd || !qdd || !tau || !M || !J) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.qd = (const R*)qd;
+    a.qdd = (const R*)qdd;
+    a.tau = (R*)tau;
+    a.M = (R*)M;
+    a.J = (R*)J;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
+        !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.st_b, &a.st_k) ||
+        !layout_of(L, 4, B, m->nv * m->nv, &a.sM_b, &a.sM_k) ||
+        !layout_of(L, 5, B, 6 * m->nv * n_ee, &a.sJ_b, &a.sJ_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                  const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar, void* qdd_bar,
+                  void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
+  (void)m; (void)dtype; (void)q; (void)qd; (void)qdd; (void)inertia_override; (void)tau_bar; (void)q_bar;
+  (void)qd_bar; (void)qdd_bar; (void)inertia_bar; (void)L; (void)B; (void)stream;
+  return fail(BARD_E_UNSUPPORTED, "rnea_vjp is not built yet");
+}
+
+int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* poses_bar, void* q_bar,
+                const bard_layout* L, int64_t B, void* stream) {
+  (void)m; (void)dtype; (void)q; (void)poses_bar; (void)q_bar; (void)L; (void)B; (void)stream;
+  return fail(BARD_E_UNSUPPORTED, "fk_vjp is not built yet");
+}
+
+int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch, uint32_t op_mask,
+                     bard_dtype dtype, bard_plan_t* out) {
+  (void)models; (void)n_models; (void)batch; (void)op_mask; (void)dtype; (void)out;
+  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
+}
+
+int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms) {
+  (void)plan; (void)stream; (void)budget_ms;
+  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
+}
+
+int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream) {
+  (void)plan; (void)io; (void)stream;
+  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
+}
+
+int bard_plan_destroy(bard_plan_t plan) {
+  (void)plan;
+  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
+}
+
+}  // extern "C"

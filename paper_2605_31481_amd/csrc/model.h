@@ -1,0 +1,90 @@
+// Internal model representation shared by the host-side compiler, the launch
+// code and the kernels.  Not part of the public ABI (see include/bard.h).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#define BARD_MAX_BODIES 64
+#define BARD_MAX_NV 128
+#define BARD_MAX_DEVICES 16
+#define BARD_MAX_EE 16
+
+namespace bard {
+
+enum JointType { J_REV = 0, J_PRI = 1, J_FREE = 2, J_FIXED = 3 };
+
+// Per-body constant record (CST scalars, FP32 and FP64 copies).
+//   [0..8]   R0 = R_pre R_post                     (eq. (2); R_post = I through the ABI)
+//   [9..17]  A  = R_pre K R_post, K = [axis]x      (eq. (2))
+//   [18..26] Bq = R_pre K^2 R_post                 (eq. (2))
+//   [27..29] t0 = R_pre t_post + t_pre             (eq. (3); t_post = 0 so a = b = 0)
+//   [30..32] axis in the body frame
+//   [33..35] d = R_pre axis (prismatic translation direction in the parent frame)
+//   [36..45] inertial parameters m, h(3), I_O(6) about the body origin
+// Revolute:  R_pc = R0 + sin(q) A + (1 - cos q) Bq,  t_pc = t0           (eqs. (4)-(5))
+// Prismatic: R_pc = R0,  t_pc = t0 + q d
+// Free:      R_pc = R0 R(quat),  t_pc = R0 p + t0
+constexpr int CST = 48;
+constexpr int C_R0 = 0, C_A = 9, C_B = 18, C_T0 = 27, C_AX = 30, C_D = 33, C_PI = 36;
+
+struct I4 {
+  int x, y, z, w;
+};
+
+// Device view of a compiled model; a POD passed to kernels by value.
+struct DevModel {
+  const float* c32;          // [n][CST]
+  const double* c64;         // [n][CST]
+  const I4* meta;            // [n] {parent, joint type, q index, v index}
+  const int16_t* sched_body; // [depth][P]  body processed by each lane slot at each level, -1 idle
+  const int8_t* sched_src;   // [depth][P]  slot holding the parent's state after the previous level
+  const int8_t* child_slot;  // [depth][P][kmax] slots of the children at the next level, -1 pad
+  const int* level_info;     // [depth][2]  {number of children to gather, forward exchange needed}
+  const int* mtab;           // [nv*nv] mass-matrix entry source: (a << 16) | d, or -1 (structural zero)
+  int n, nq, nv, depth, P, log2P, kmax, free_root;
+  float g32[3];
+  double g64[3];
+};
+
+// Per end-effector-set tables used by the Jacobian output.
+struct DevEE {
+  const int* jtab;     // [n_ee*nv] column source dof or -1
+  const int* ee_body;  // [n_ee]
+  int n_ee;
+};
+
+struct DeviceCopy {
+  bool ready = false;
+  void* blob = nullptr;
+  DevModel dm{};
+  std::map<std::vector<int>, std::pair<void*, DevEE>> ee_sets;
+};
+
+}  // namespace bard
+
+struct bard_model {
+  int n = 0, nq = 0, nv = 0, depth = 0, P = 1, log2P = 0, kmax = 0;
+  bool free_root = false;
+  std::vector<int> parent, jtype, qi, vi, nvi, level_of, slot_of;
+  std::vector<double> axis, xtree, inertia;
+  double g[3] = {0.0, 0.0, -9.81};
+  std::vector<double> cst64;
+  std::vector<float> cst32;
+  std::vector<int16_t> sched_body;
+  std::vector<int8_t> sched_src, child_slot;
+  std::vector<int> level_info, mtab;
+  std::vector<std::vector<int>> children;
+  bard::DeviceCopy dev[BARD_MAX_DEVICES];
+  std::mutex mu;
+};
+
+namespace bard {
+// Host-side compile of a model (compiler.cpp).  Returns a bard_status.
+int compile_model(bard_model* m, std::string* err);
+// Column-source table of the Jacobian for a set of end effectors.
+std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee);
+}  // namespace bard

@@ -1,0 +1,84 @@
+"""Helpers shared by the GPU parity tests: seeded inputs on the device and the
+tolerance contract.
+
+Tolerance contract.  Inputs are rounded to the kernel's precision first and
+the FP64 oracle runs on exactly those values.  For FK, Jacobian, RNEA and CRBA
+the check is normwise per (instance, output block):
+``max_k |gpu - ref| <= atol + rtol * max_k |ref|`` with FP32 rtol = 1e-5,
+atol = 1e-6 and FP64 rtol = atol = 1e-12.  ABA is checked by its backward
+error, ``|RNEA_ref(q, qd, qdd_gpu) - tau|_inf <= atol + rtol * (|tau|_inf +
+|M|_inf |qdd_gpu|_inf + |RNEA_ref(q, qd, 0)|_inf)``, because its forward error
+is only bounded by cond(M) times the unit roundoff.
+"""
+
+import sys
+
+import numpy as np
+
+import synth
+from oracle import OracleModel
+
+TOL = {"float32": (1e-5, 1e-6), "float64": (1e-12, 1e-12)}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def inputs(tree, B, seed, dtype):
+    q, qd, qdd = synth.random_state(tree, B, seed)
+    if dtype == "float32":
+        q, qd, qdd = synth.to_fp32_grid(q), synth.to_fp32_grid(qd), synth.to_fp32_grid(qdd)
+    return q, qd, qdd
+
+
+def to_dev(x, dtype, layout="soa"):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x)).to(getattr(torch, dtype))
+    if layout == "soa":
+        t = t.t().contiguous()
+    return t.cuda()
+
+
+def from_dev(t, layout="soa"):
+    a = t.detach().cpu().double().numpy()
+    return a.T.copy() if layout == "soa" else a
+
+
+def normwise(gpu, ref, rtol, atol):
+    """gpu, ref: [B, blocks, K].  Returns (ok mask [B, blocks], worst ratio)."""
+    err = np.abs(gpu - ref).max(axis=-1)
+    scale = np.abs(ref).max(axis=-1)
+    bound = atol + rtol * scale
+    return err <= bound, float((err / bound).max())
+
+
+def assert_normwise(name, gpu, ref, dtype):
+    rtol, atol = TOL[dtype]
+    ok, worst = normwise(gpu, ref, rtol, atol)
+    assert ok.all(), f"{name}: {int((~ok).sum())} blocks out of tolerance, worst err/bound = {worst:.3g}"
+    return worst
+
+
+def aba_backward_error(om, q, qd, tau, qdd_gpu, dtype):
+    rtol, atol = TOL[dtype]
+    res = om.rnea(q, qd, qdd_gpu) - tau
+    M = om.crba(q)
+    bias = om.rnea(q, qd, np.zeros_like(qd))
+    scale = (np.abs(tau).max(axis=1) + np.abs(M).sum(axis=2).max(axis=1) * np.abs(qdd_gpu).max(axis=1)
+             + np.abs(bias).max(axis=1))
+    err = np.abs(res).max(axis=1)
+    bound = atol + rtol * scale
+    return err <= bound, float((err / bound).max())
+
+
+def fk_ref_blocks(om, q):
+    T = om.fk(q)                       # [B, n, 3, 4]
+    B, n = T.shape[:2]
+    out = np.concatenate([T[:, :, :, :3].reshape(B, n, 9), T[:, :, :, 3]], axis=2)
+    return out                         # [B, n, 12]
+
+
+def oracle_for(tree):
+    return OracleModel.from_tree(tree)
