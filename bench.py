@@ -1,0 +1,263 @@
+"""Throughput of the fused RNEA + CRBA + Jacobian chain on one MI355X.
+
+One step = one call of the fused chain (bard_chain: inverse dynamics, mass
+matrix and 4 end-effector Jacobians) over a batch of fresh synthetic
+configurations of the 36-velocity-DOF humanoid tree (free root, 3-DOF waist,
+1-DOF neck, two 7-DOF arms, two 6-DOF legs; FP32, batch 4096).  Input/output
+sets rotate so every step reads new inputs and the working set exceeds the
+256 MB Infinity Cache.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--no-cpu] [--no-extra]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "evals/sec RNEA+CRBA+Jacobian, 23-DOF tree, batch 4096 FP32 (err vs FP64 oracle)"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_humanoid_large_b4096.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_31481_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def chain_bytes_per_eval(tree, n_ee, scalar=4):
+    """Algorithmic bytes of one evaluation: q, qd, qdd read; tau, M, J written."""
+    return scalar * (tree.nq + 2 * tree.nv + tree.nv + tree.nv * tree.nv + n_ee * 6 * tree.nv)
+
+
+def make_sets(torch, tree, B, nsets, seed):
+    import synth
+    sets = []
+    for s in range(nsets):
+        q, qd, qdd = synth.random_state(tree, B, seed + s)
+        dev = [torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qdd)]
+        n_ee = len(tree.ee_bodies)
+        outs = [torch.empty((k, B), dtype=torch.float32, device="cuda")
+                for k in (tree.nv, tree.nv * tree.nv, n_ee * 6 * tree.nv)]
+        sets.append((dev, outs, (q, qd, qdd)))
+    return sets
+
+
+def time_calls(torch, calls, steps, warmup):
+    """Warm up, then time exactly `steps` calls; per-launch HIP events on the
+    launch stream give the kernel time, the host clock the step rate."""
+    n = len(calls)
+    for k in range(warmup):
+        calls[k % n]()
+    st = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    en = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        st[k].record()
+        calls[k % n]()
+        en[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = [st[k].elapsed_time(en[k]) for k in range(steps)]
+    return wall, float(np.mean(kms)), float(np.median(kms))
+
+
+def time_graph(torch, make_calls, replays):
+    """Capture one pass over the rotation sets in a HIP graph and replay it.
+    `make_calls` binds the calls to the stream current when it runs, so the
+    launches made during capture land on the capturing stream."""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for c in make_calls():
+            c()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        calls = make_calls()
+        for c in calls:
+            c()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / (replays * len(calls))
+
+
+def parity_sample(tree, sets, n_sample=256):
+    """Normwise error of the last timed outputs of set 0 against the FP64 oracle."""
+    from oracle import OracleModel
+    import synth
+    (dev, outs, host) = sets[0]
+    q, qd, qdd = (synth.to_fp32_grid(x) for x in host)
+    B = q.shape[0]
+    idx = np.random.default_rng(0).choice(B, min(n_sample, B), replace=False)
+    om = OracleModel.from_tree(tree)
+    rt, rM, rJ = om.chain(q[idx], qd[idx], qdd[idx], tree.ee_bodies)
+    worst = 0.0
+    for g, r in ((outs[0], rt.reshape(len(idx), -1)), (outs[1], rM.reshape(len(idx), -1)),
+                 (outs[2], rJ.reshape(len(idx), len(tree.ee_bodies), -1))):
+        gg = g.cpu().double().numpy().T[idx].reshape(r.shape)
+        if gg.ndim == 2:
+            gg, r = gg[:, None], r[:, None]
+        err = np.abs(gg - r).max(axis=-1)
+        bound = 1e-6 + 1e-5 * np.abs(r).max(axis=-1)
+        worst = max(worst, float((err / bound).max()))
+    return {"max_err_over_tol": worst, "instances": int(len(idx)), "tolerance": "normwise rtol 1e-5 atol 1e-6",
+            "pass": worst <= 1.0}
+
+
+def cpu_baseline(tree, target_s=10.0, max_s=30.0):
+    """The FP64 oracle (untuned) on a bounded sample of the same workload."""
+    from oracle import OracleModel
+    import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    om = OracleModel.from_tree(tree)
+    chunk = 4096
+    q, qd, qdd = synth.random_state(tree, chunk, 7777)
+    om.chain(q[:64], qd[:64], qdd[:64], tree.ee_bodies, threads=threads)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        om.chain(q, qd, qdd, tree.ee_bodies, threads=threads)
+        done += chunk
+        el = time.perf_counter() - t0
+        if el >= target_s or el >= max_s:
+            break
+    return {"value": done / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} configurations of the same tree (RNEA+CRBA+4-EE Jacobian, FP64), "
+                      f"{el:.1f} s on {threads} OpenMP threads"}
+
+
+def traffic_if_current():
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernels_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the batch would shard "
+              "across GPUs with no exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2605_31481_amd import bard
+
+    torch.cuda.set_device(0)
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    B = args.batch
+    ee = tree.ee_bodies
+    bpe = chain_bytes_per_eval(tree, len(ee))
+    per_call = bpe * B
+    nsets = max(14, math.ceil(512e6 / per_call))
+    log(f"[bench] workload humanoid_large nv={tree.nv} B={B} bytes/call={per_call/1e6:.1f} MB sets={nsets}")
+    sets = make_sets(torch, tree, B, nsets, 2002)
+    def make_calls():
+        return [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
+    calls = make_calls()
+
+    wall, kavg, kmed = time_calls(torch, calls, args.steps, args.warmup)
+    value = B * args.steps / wall
+    achieved = per_call / (kavg * 1e-3) / 1e9
+    log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us (median {kmed*1e3:.2f} us)")
+    parity = parity_sample(tree, sets)
+    log(f"[bench] parity {parity}")
+
+    extra = {}
+    if not args.no_extra:
+        # plain per-operator kernels (three launches) on the same sets
+        plain = []
+        for (d, o, _) in sets:
+            plain.append((m.bind_rnea(d[0], d[1], d[2], o[0]), m.bind_crba(d[0], o[1]),
+                          m.bind_jacobian(d[0], ee, o[2])))
+        pcalls = [(lambda t=t: (t[0](), t[1](), t[2]())) for t in plain]
+        pw, pk, _ = time_calls(torch, pcalls, max(100, args.steps // 4), 10)
+        extra["plain_3_launches_evals_per_s"] = B * max(100, args.steps // 4) / pw
+        extra["graph_replay_evals_per_s"] = B / time_graph(torch, make_calls, max(5, args.steps // nsets))
+        # same buffers every call (working set in the Infinity Cache)
+        sw, sk, _ = time_calls(torch, calls[:1], max(100, args.steps // 4), 10)
+        extra["same_buffers_kernel_us"] = sk * 1e3
+        # larger batch
+        B2 = 16384
+        sets2 = make_sets(torch, tree, B2, max(4, math.ceil(512e6 / (bpe * B2))), 4002)
+        calls2 = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets2]
+        w2, k2, _ = time_calls(torch, calls2, max(100, args.steps // 4), 10)
+        extra["batch16384_evals_per_s"] = B2 * max(100, args.steps // 4) / w2
+        extra["batch16384_kernel_us"] = k2 * 1e3
+        extra["batch16384_hbm_frac"] = bpe * B2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS
+        del sets2, calls2
+        # the 23-velocity-DOF companion tree
+        ts = synth.humanoid_small()
+        ms = bard.Model.from_tree(ts)
+        bpe_s = chain_bytes_per_eval(ts, len(ts.ee_bodies))
+        sets3 = make_sets(torch, ts, B, max(14, math.ceil(512e6 / (bpe_s * B))), 5002)
+        calls3 = [ms.bind_chain(d[0], d[1], d[2], ts.ee_bodies, tuple(o)) for (d, o, _) in sets3]
+        w3, k3, _ = time_calls(torch, calls3, args.steps, 10)
+        extra["nv23_tree_evals_per_s"] = B * args.steps / w3
+        extra["nv23_tree_kernel_us"] = k3 * 1e3
+        del sets3, calls3
+        log(f"[bench] extra {extra}")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(tree)
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "humanoid tree: free root + 3-DOF waist + 1-DOF neck + two 7-DOF arms + "
+                               "two 6-DOF legs (31 bodies, nq 37, nv 36, depth 9), 4 end effectors; "
+                               "fused RNEA+CRBA+Jacobian, eager C-ABI launches, fresh inputs every step",
+                   "batch": B, "tree": "humanoid_large", "rotating_sets": nsets,
+                   "bytes_per_eval": bpe},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_if_current(),
+                     "kernel": "tree_kernel<float, RNEA|CRBA|JAC>", "kernel_avg_us": kavg * 1e3},
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

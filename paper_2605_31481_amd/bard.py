@@ -280,3 +280,64 @@ class Model:
         _check(bard_chain(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), len(ee_a), pee, int(frame),
                           _ptr(tau), _ptr(M), _ptr(J), L, B, _stream_ptr(q)), "bard_chain")
         return tau, M, J
+
+    # ------------------------------------------------------- bound calls --
+    def bind_chain(self, q, qd, qdd, ee: Sequence[int], out, frame: int = WORLD, layout: str = "soa"):
+        """Marshal the arguments of one chain call once; the returned callable
+        only issues the foreign call (on the stream current at bind time)."""
+        B = _batch_of(q, self.nq, layout)
+        ee_a, pee = _i32arr(ee)
+        tau, M, J = out
+        L = _layouts([q, qd, qdd, tau, M, J], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), len(ee_a), pee, int(frame), _ptr(tau),
+                _ptr(M), _ptr(J), L, B, _stream_ptr(q))
+        keep = (ee_a, L, q, qd, qdd, tau, M, J)
+
+        def call():
+            rc = bard_chain(*args)
+            if rc:
+                raise BardError(rc, "bard_chain")
+            return keep
+        return call
+
+    def bind_rnea(self, q, qd, qdd, out, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        L = _layouts([q, qd, qdd, out], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _vp(0), _ptr(out), L, 0, 0, B,
+                _stream_ptr(q))
+        keep = (L, q, qd, qdd, out)
+
+        def call():
+            rc = bard_rnea(*args)
+            if rc:
+                raise BardError(rc, "bard_rnea")
+            return keep
+        return call
+
+    def bind_crba(self, q, out, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        L = _layouts([q, out], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q))
+        keep = (L, q, out)
+
+        def call():
+            rc = bard_crba(*args)
+            if rc:
+                raise BardError(rc, "bard_crba")
+            return keep
+        return call
+
+    def bind_jacobian(self, q, ee: Sequence[int], out, frame: int = WORLD, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        ee_a, pee = _i32arr(ee)
+        L = _layouts([q, out], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, 0, B,
+                _stream_ptr(q))
+        keep = (ee_a, L, q, out)
+
+        def call():
+            rc = bard_jacobian(*args)
+            if rc:
+                raise BardError(rc, "bard_jacobian")
+            return keep
+        return call

@@ -67,6 +67,27 @@ int default_target_T() {
   return 16;
 }
 
+// Host image of the model tables with constants of scalar size rs (layout tab_layout()).
+std::vector<unsigned char> table_image(const bard_model* m, int rs) {
+  const TabLayout t = tab_layout(m->n, m->P, m->depth, m->kmax, m->nv, rs);
+  std::vector<unsigned char> img(t.end, 0);
+  if (rs == 4) std::memcpy(&img[t.cst], m->cst32.data(), m->cst32.size() * sizeof(float));
+  else std::memcpy(&img[t.cst], m->cst64.data(), m->cst64.size() * sizeof(double));
+  std::vector<I4> meta(m->n);
+  for (int i = 0; i < m->n; ++i) meta[i] = I4{m->parent[i], m->jtype[i], m->qi[i], m->vi[i]};
+  std::memcpy(&img[t.meta], meta.data(), meta.size() * sizeof(I4));
+  std::memcpy(&img[t.sbody], m->sched_body.data(), m->sched_body.size() * sizeof(int16_t));
+  std::memcpy(&img[t.ssrc], m->sched_src.data(), m->sched_src.size());
+  std::memcpy(&img[t.cslot], m->child_slot.data(), m->child_slot.size());
+  std::memcpy(&img[t.linfo], m->level_info.data(), m->level_info.size() * sizeof(int));
+  std::vector<I4> bm2(m->n);
+  for (int i = 0; i < m->n; ++i) bm2[i] = I4{m->dfs[i], m->sub_size[i], m->vi[i], m->nvi[i]};
+  std::memcpy(&img[t.bm2], bm2.data(), bm2.size() * sizeof(I4));
+  std::memcpy(&img[t.dlist], m->dlist.data(), m->dlist.size() * sizeof(int));
+  std::memcpy(&img[t.mtab], m->mtab.data(), m->mtab.size() * sizeof(int));
+  return img;
+}
+
 // Upload the compiled model to the current device (once per device).
 int ensure_device(bard_model* m, DeviceCopy** out) {
   int dev = 0;
@@ -82,43 +103,19 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
     *out = &dc;
     return BARD_OK;
   }
-  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t off_c32 = 0;
-  size_t off_c64 = align(off_c32 + m->cst32.size() * sizeof(float));
-  size_t off_meta = align(off_c64 + m->cst64.size() * sizeof(double));
-  size_t off_sb = align(off_meta + m->n * sizeof(I4));
-  size_t off_ss = align(off_sb + m->sched_body.size() * sizeof(int16_t));
-  size_t off_cs = align(off_ss + m->sched_src.size());
-  size_t off_li = align(off_cs + m->child_slot.size());
-  size_t off_mt = align(off_li + m->level_info.size() * sizeof(int));
-  size_t total = align(off_mt + m->mtab.size() * sizeof(int));
-  std::vector<unsigned char> host(total, 0);
-  std::memcpy(&host[off_c32], m->cst32.data(), m->cst32.size() * sizeof(float));
-  std::memcpy(&host[off_c64], m->cst64.data(), m->cst64.size() * sizeof(double));
-  std::vector<I4> meta(m->n);
-  for (int i = 0; i < m->n; ++i) meta[i] = I4{m->parent[i], m->jtype[i], m->qi[i], m->vi[i]};
-  std::memcpy(&host[off_meta], meta.data(), meta.size() * sizeof(I4));
-  std::memcpy(&host[off_sb], m->sched_body.data(), m->sched_body.size() * sizeof(int16_t));
-  std::memcpy(&host[off_ss], m->sched_src.data(), m->sched_src.size());
-  std::memcpy(&host[off_cs], m->child_slot.data(), m->child_slot.size());
-  std::memcpy(&host[off_li], m->level_info.data(), m->level_info.size() * sizeof(int));
-  std::memcpy(&host[off_mt], m->mtab.data(), m->mtab.size() * sizeof(int));
+  std::vector<unsigned char> i32 = table_image(m, 4), i64 = table_image(m, 8);
+  std::vector<unsigned char> host(i32.size() + i64.size());
+  std::memcpy(host.data(), i32.data(), i32.size());
+  std::memcpy(host.data() + i32.size(), i64.data(), i64.size());
   void* blob = nullptr;
-  if (hipMalloc(&blob, total) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc of the model constants failed");
-  if (hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMalloc(&blob, host.size()) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc of the model tables failed");
+  if (hipMemcpy(blob, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(blob);
-    return fail(BARD_E_DEVICE, "upload of the model constants failed");
+    return fail(BARD_E_DEVICE, "upload of the model tables failed");
   }
-  unsigned char* base = (unsigned char*)blob;
   DevModel& dm = dc.dm;
-  dm.c32 = (const float*)(base + off_c32);
-  dm.c64 = (const double*)(base + off_c64);
-  dm.meta = (const I4*)(base + off_meta);
-  dm.sched_body = (const int16_t*)(base + off_sb);
-  dm.sched_src = (const int8_t*)(base + off_ss);
-  dm.child_slot = (const int8_t*)(base + off_cs);
-  dm.level_info = (const int*)(base + off_li);
-  dm.mtab = (const int*)(base + off_mt);
+  dm.img32 = (const unsigned char*)blob;
+  dm.img64 = (const unsigned char*)blob + i32.size();
   dm.n = m->n;
   dm.nq = m->nq;
   dm.nv = m->nv;
@@ -150,18 +147,18 @@ int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, D
     return BARD_OK;
   }
   std::vector<int> jt = jacobian_table(m, key);
-  std::vector<int> host(jt.size() + key.size());
-  std::copy(jt.begin(), jt.end(), host.begin());
-  std::copy(key.begin(), key.end(), host.begin() + jt.size());
+  const int bytes = ee_image_bytes(n_ee, m->nv);
+  std::vector<unsigned char> host(bytes, 0);
+  std::memcpy(host.data(), jt.data(), jt.size() * sizeof(int));
+  std::memcpy(host.data() + lds_align((int)jt.size() * 4), key.data(), key.size() * sizeof(int));
   void* p = nullptr;
-  if (hipMalloc(&p, host.size() * sizeof(int)) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc failed");
-  if (hipMemcpy(p, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc failed");
+  if (hipMemcpy(p, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(p);
     return fail(BARD_E_DEVICE, "upload of the end-effector table failed");
   }
   DevEE e;
-  e.jtab = (const int*)p;
-  e.ee_body = (const int*)p + jt.size();
+  e.img = (const unsigned char*)p;
   e.n_ee = n_ee;
   dc->ee_sets[key] = {p, e};
   *out = e;
@@ -181,25 +178,42 @@ bool layout_of(const bard_layout* L, int idx, int64_t B, int64_t K, int64_t* sb,
   return true;
 }
 
-Shape pick_shape(const bard_model* m, size_t per_inst_bytes, int dev) {
-  // Instances per workgroup T = waves * (64 >> log2P).  Start from the model's
-  // lanes per instance and the target tile; shrink the tile (fewer waves, then
-  // more lanes per instance) until the on-chip staging fits.
+// Instances per workgroup T = wavesA * (64 >> log2P).  Start from the model's
+// lanes per instance and the target tile; shrink the tile (fewer sweep waves,
+// then more lanes per instance) until the LDS plan fits.
+template <class PlanBytes>
+Shape pick_shape(const bard_model* m, int dev, PlanBytes bytes_for) {
+  // T = waves * (64 >> log2P) instances per workgroup, a power of two in
+  // [8, 64] (the kernels are instantiated for those tiles).  Start from the
+  // model's lanes per instance and the target tile; shrink the tile (fewer
+  // sweep waves, then more lanes per instance) until the LDS plan fits.
   int log2P = m->log2P;
   int target = default_target_T();
   int waves = std::max(1, std::min(4, target / (64 >> log2P)));
+  while (waves * (64 >> log2P) < 8) ++waves;  // wide trees: at least 8 instances
   size_t lim = lds_limit(dev);
   for (;;) {
-    size_t T = (size_t)waves * (64 >> log2P);
-    if (T * per_inst_bytes <= lim) break;
+    int T = waves * (64 >> log2P);
+    if ((size_t)bytes_for(T, log2P) <= lim || T <= 8) break;
     if (waves > 1) waves >>= 1;
-    else if (log2P < 6) ++log2P;
-    else break;
+    else ++log2P;
   }
   int T = waves * (64 >> log2P);
   int logT = 0;
   while ((1 << logT) < T) ++logT;
   return Shape{waves, logT, T, log2P};
+}
+
+// Waves per workgroup for the phases after the level sweep (body, subtree,
+// dense outputs), which have no serial dependency and hide LDS latency with
+// more waves.
+int out_waves() {
+  const char* e = getenv("BARD_OUT_WAVES");
+  if (e) {
+    int w = atoi(e);
+    if (w >= 1 && w <= 8) return w;
+  }
+  return 8;
 }
 
 int common_checks(bard_model* m, bard_ws_t ws, int dtype, int64_t B) {
@@ -224,39 +238,33 @@ Args<Real> blank_args(int64_t B) {
   return a;
 }
 
-size_t tree_lds_per_inst(const bard_model* m, int ops, int n_ee, int frame, size_t rs) {
-  size_t f = 0;
-  bool need_s = ops & (OP_JAC | OP_RNEA | OP_CRBA);
-  if (need_s) f += 6 * m->nv;
-  if (ops & OP_CRBA) f += 6 * m->nv + 10 * m->n;
-  if (ops & OP_RNEA) f += 6 * m->n;
-  f += 3;
-  if ((ops & OP_JAC) && frame == 1) f += 3 * n_ee;
-  return f * rs;
-}
-
 template <class Real, int OPS>
 int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int frame, hipStream_t st) {
   DeviceCopy* dc = nullptr;
   int rc = ensure_device(m, &dc);
   if (rc) return rc;
-  DevEE ee{nullptr, nullptr, 0};
+  DevEE ee{nullptr, 0};
   if (OPS & OP_JAC) {
     rc = ensure_ee(m, dc, n_ee, ee_body, &ee);
     if (rc) return rc;
   }
   int dev = 0;
   (void)hipGetDevice(&dev);
-  size_t per = tree_lds_per_inst(m, OPS, n_ee, frame, sizeof(Real));
-  Shape sh = pick_shape(m, per, dev);
-  size_t lds = per * sh.T;
+  const int ne = (OPS & OP_JAC) ? n_ee : 0;
+  auto bytes_for = [&](int T, int) {
+    return lds_plan(0, OPS, m->n, m->nq, m->nv, ne, frame, T, (int)sizeof(Real), m->P, m->depth, m->kmax).total;
+  };
+  Shape sh = pick_shape(m, dev, bytes_for);
+  size_t lds = (size_t)bytes_for(sh.T, sh.log2P);
   if (lds > lds_limit(dev)) return fail(BARD_E_CAPACITY, "model too large for on-chip staging");
   ar.logT = sh.logT;
   ar.log2P = sh.log2P;
   ar.frame = frame;
+  int waves = (sh.T << sh.log2P) >> 6;
+  if (OPS & (OP_CRBA | OP_JAC | OP_RNEA | OP_FK)) waves = std::max(waves, out_waves());
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
-  hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, sh.waves * 64, lds, st);
+  hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, waves * 64, lds, st);
   if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BARD_OK;
 }
@@ -268,15 +276,18 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   if (rc) return rc;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  size_t per = (6 * m->nv + (6 + 21 + 6 + 8) * m->n) * sizeof(Real);
-  Shape sh = pick_shape(m, per, dev);
-  size_t lds = per * sh.T;
+  auto bytes_for = [&](int T, int) {
+    return lds_plan(1, 0, m->n, m->nq, m->nv, 0, 0, T, (int)sizeof(Real), m->P, m->depth, m->kmax).total;
+  };
+  Shape sh = pick_shape(m, dev, bytes_for);
+  size_t lds = (size_t)bytes_for(sh.T, sh.log2P);
   if (lds > lds_limit(dev)) return fail(BARD_E_CAPACITY, "model too large for on-chip staging");
   ar.logT = sh.logT;
   ar.log2P = sh.log2P;
+  int waves = (sh.T << sh.log2P) >> 6;
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
-  hipError_t e = launch_aba<Real>(dc->dm, ar, (int)grid, sh.waves * 64, lds, st);
+  hipError_t e = launch_aba<Real>(dc->dm, ar, (int)grid, waves * 64, lds, st);
   if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BARD_OK;
 }

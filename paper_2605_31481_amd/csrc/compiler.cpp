@@ -201,6 +201,29 @@ int compile_model(bard_model* m, std::string* err) {
     m->level_info[2 * l + 1] = shuffle;
   }
 
+  // ---- preorder positions: every subtree is a contiguous range of positions ----
+  m->dfs.assign(n, 0);
+  m->sub_size.assign(n, 1);
+  for (int i = n - 1; i >= 0; --i)
+    if (m->parent[i] >= 0) m->sub_size[m->parent[i]] += m->sub_size[i];
+  {
+    int pos = 0;
+    std::vector<int> stack;
+    for (int i = n - 1; i >= 0; --i)
+      if (m->parent[i] < 0) stack.push_back(i);
+    while (!stack.empty()) {
+      int b = stack.back();
+      stack.pop_back();
+      m->dfs[b] = pos++;
+      const auto& ch = m->children[b];
+      for (int k = (int)ch.size() - 1; k >= 0; --k) stack.push_back(ch[k]);
+    }
+  }
+  m->dlist.resize(n);
+  for (int i = 0; i < n; ++i) m->dlist[i] = i;
+  std::stable_sort(m->dlist.begin(), m->dlist.end(),
+                   [&](int a, int b) { return m->sub_size[a] > m->sub_size[b]; });
+
   // ---- joint constants (eqs. (2)-(3)) and inertial parameters ----
   m->cst64.assign((size_t)n * CST, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -232,7 +255,7 @@ int compile_model(bard_model* m, std::string* err) {
   m->cst32.resize(m->cst64.size());
   for (size_t k = 0; k < m->cst64.size(); ++k) m->cst32[k] = (float)m->cst64[k];
 
-  // ---- mass-matrix entry table: M[r][c] = s_a . (Ic_body(d) s_d) ----
+  // ---- mass-matrix entry table: M[r][c] = s_a . (Ic_body(d) s_d), zeros read row nv ----
   std::vector<int> body_of(m->nv);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < m->nvi[i]; ++k) body_of[m->vi[i] + k] = i;
@@ -251,16 +274,26 @@ int compile_model(bard_model* m, std::string* err) {
         a = cc;
         d = r;
       }
-      if (a >= 0) m->mtab[(size_t)r * m->nv + cc] = (a << 16) | d;
+      if (a < 0) a = d = m->nv;  // structural zero: both operands read the all-zero row
+      m->mtab[(size_t)r * m->nv + cc] = (a << 16) | d;
     }
   return BARD_OK;
 }
 
 std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee) {
-  std::vector<int> t((size_t)ee.size() * m->nv, -1);
-  for (size_t e = 0; e < ee.size(); ++e)
+  // Row (e, r, c) of the [n_ee][6][nv] output is entry r of column c of end
+  // effector e's block.  Code: src dof | r << 8 | e << 12, with src = nv (the
+  // all-zero row) when dof c is not on the root path of e.
+  const int nv = m->nv;
+  std::vector<char> on(nv);
+  std::vector<int> t((size_t)ee.size() * 6 * nv);
+  for (size_t e = 0; e < ee.size(); ++e) {
+    std::fill(on.begin(), on.end(), 0);
     for (int k = ee[e]; k >= 0; k = m->parent[k])
-      for (int j = 0; j < m->nvi[k]; ++j) t[e * m->nv + m->vi[k] + j] = m->vi[k] + j;
+      for (int j = 0; j < m->nvi[k]; ++j) on[m->vi[k] + j] = 1;
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < nv; ++c) t[(e * 6 + r) * nv + c] = (on[c] ? c : nv) | (r << 8) | ((int)e << 12);
+  }
   return t;
 }
 

@@ -1,9 +1,10 @@
 // Batched tree traversals for gfx950 (CDNA4, wave64).
 //
-// Mapping.  A workgroup owns T consecutive instances.  Inside a wave, each
-// instance gets P adjacent lanes ("slots", P = next power of two >= the widest
-// tree level); the model compiler assigns every body a slot so that one level
-// of the tree (Sec. 3.3, eq. (6)) is one step for all slots at once.  A child
+// Mapping.  A workgroup owns T consecutive instances (T is a compile-time
+// power of two so every LDS offset is an immediate).  Inside a wave, each
+// instance gets 2^log2P adjacent lanes ("slots", at least the widest tree
+// level); the model compiler assigns every body a slot so that one level of
+// the tree (Sec. 3.3, eq. (6)) is one step for all slots at once.  A child
 // normally continues in its parent's slot, so per-body link state stays in
 // registers; where the tree branches the state is pulled across lanes with
 // one bpermute per scalar.  All lanes of a wave execute every level (idle
@@ -20,21 +21,24 @@
 // (the update Sec. 3.5 singles out as the cost of CRBA and ABA).  Putting the
 // origin at the base keeps coordinates small for FP32.
 //
-// Phases.  A: forward sweep over levels (joint transform from the Rodrigues
-// constants, eqs. (4)-(5); world pose; s_i; velocities; world inertia; body
-// forces).  Back: reverse sweep gathering each body's children
-// (tau_i = s_i . F_i, F_i = f_i + sum children F; Ic_i = I_i + sum Ic).
-// B: the workgroup writes the dense outputs (M, J) from LDS with lanes over
-// instances, so stores of the instance-minor layout coalesce.
+// Phases.  Staging: the workgroup copies the model's table image and its
+// input tile into LDS.  Level sweep: joint transform from the Rodrigues
+// constants (eqs. (4)-(5)), world pose, s_i, velocity and acceleration.  Body
+// phase: world inertia and body force per (body, instance).  Subtree phase:
+// because the frame is common, F_i (forces) and Ic_i (composite inertias) are
+// plain sums over the subtree, which is a contiguous range of preorder
+// positions; tau_i = s_i . F_i.  Output: every wave writes the dense M and J
+// from LDS with lanes over instances, so stores of the instance-minor layout
+// coalesce.  Only the level sweep is serial over the tree.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
 
 namespace bard {
 
-template <class Real> __device__ __forceinline__ const Real* consts(const DevModel& dm);
-template <> __device__ __forceinline__ const float* consts<float>(const DevModel& dm) { return dm.c32; }
-template <> __device__ __forceinline__ const double* consts<double>(const DevModel& dm) { return dm.c64; }
+template <class Real> __device__ __forceinline__ const unsigned char* image(const DevModel& dm);
+template <> __device__ __forceinline__ const unsigned char* image<float>(const DevModel& dm) { return dm.img32; }
+template <> __device__ __forceinline__ const unsigned char* image<double>(const DevModel& dm) { return dm.img64; }
 template <class Real> __device__ __forceinline__ Real grav(const DevModel& dm, int k);
 template <> __device__ __forceinline__ float grav<float>(const DevModel& dm, int k) { return dm.g32[k]; }
 template <> __device__ __forceinline__ double grav<double>(const DevModel& dm, int k) { return dm.g64[k]; }
@@ -78,12 +82,12 @@ __device__ __forceinline__ void world_inertia(const Real* pi, const Real* R, con
   Real X[9];
   mul33(R, Ib, X);
   // Y = X R^T (symmetric; six entries)
-  Real yxx = X[0] * R[0] + X[1] * R[1] + X[2] * R[2];
-  Real yxy = X[0] * R[3] + X[1] * R[4] + X[2] * R[5];
-  Real yyy = X[3] * R[3] + X[4] * R[4] + X[5] * R[5];
-  Real yxz = X[0] * R[6] + X[1] * R[7] + X[2] * R[8];
-  Real yyz = X[3] * R[6] + X[4] * R[7] + X[5] * R[8];
-  Real yzz = X[6] * R[6] + X[7] * R[7] + X[8] * R[8];
+  const Real yxx = X[0] * R[0] + X[1] * R[1] + X[2] * R[2];
+  const Real yxy = X[0] * R[3] + X[1] * R[4] + X[2] * R[5];
+  const Real yyy = X[3] * R[3] + X[4] * R[4] + X[5] * R[5];
+  const Real yxz = X[0] * R[6] + X[1] * R[7] + X[2] * R[8];
+  const Real yyz = X[3] * R[6] + X[4] * R[7] + X[5] * R[8];
+  const Real yzz = X[6] * R[6] + X[7] * R[7] + X[8] * R[8];
   const Real pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
   const Real ph = p[0] * hr[0] + p[1] * hr[1] + p[2] * hr[2];
   const Real dg = m * pp + Real(2) * ph;
@@ -153,10 +157,125 @@ __device__ __forceinline__ int tile_index(int xcd_remap) {
 }
 
 // --------------------------------------------------------------------------
-// FK / Jacobian / RNEA / CRBA and their fusion (OPS bit mask).
+// Workgroup staging.
 // --------------------------------------------------------------------------
-template <class Real, int OPS>
-__global__ void __launch_bounds__(256) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
+// Copy `bytes` (a multiple of 16) from global to LDS in 16-byte chunks.
+__device__ __forceinline__ void copy16(unsigned char* dst, const unsigned char* src, int bytes, int tid, int nt) {
+  const int4* s = reinterpret_cast<const int4*>(src);
+  int4* d = reinterpret_cast<int4*>(dst);
+  const int n16 = bytes >> 4;
+#pragma unroll 4
+  for (int i = tid; i < n16; i += nt) d[i] = s[i];
+}
+
+// Input tile [K][T] from a strided array; instances past B repeat the last one.
+template <class Real, int LOGT>
+__device__ __forceinline__ void stage_input(const Real* src, int64_t sb, int64_t sk, int K, int64_t tile0, int64_t B,
+                                            Real* dst, int tid, int nt) {
+  constexpr int T = 1 << LOGT;
+#pragma unroll 8
+  for (int i = tid; i < K * T; i += nt) {
+    const int k = i >> LOGT;
+    int64_t b = tile0 + (i & (T - 1));
+    if (b >= B) b = B - 1;
+    dst[i] = src[b * sb + (int64_t)k * sk];
+  }
+}
+
+// Free-root pose from [x y z qx qy qz qw]: R = R0 R(quat), position R0 p + t0.
+template <class Real>
+__device__ __forceinline__ void free_root_pose(const Real* c, const Real* qv, Real* Rw, Real* o) {
+  Real qx = qv[3], qy = qv[4], qz = qv[5], qw = qv[6];
+  const Real inv = Real(1) / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  qx *= inv; qy *= inv; qz *= inv; qw *= inv;
+  const Real Rq[9] = {Real(1) - Real(2) * (qy * qy + qz * qz), Real(2) * (qx * qy - qz * qw), Real(2) * (qx * qz + qy * qw),
+                      Real(2) * (qx * qy + qz * qw), Real(1) - Real(2) * (qx * qx + qz * qz), Real(2) * (qy * qz - qx * qw),
+                      Real(2) * (qx * qz - qy * qw), Real(2) * (qy * qz + qx * qw), Real(1) - Real(2) * (qx * qx + qy * qy)};
+  mul33(c + C_R0, Rq, Rw);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    o[i] = c[C_R0 + 3 * i] * qv[0] + c[C_R0 + 3 * i + 1] * qv[1] + c[C_R0 + 3 * i + 2] * qv[2] + c[C_T0 + i];
+}
+
+// One joint step: parent pose (Rw, pw) -> body pose, and the body's motion
+// subspace s = [u; p x u] (revolute) or [0; u] (prismatic), u = R axis.
+template <class Real>
+__device__ __forceinline__ void joint_step(const Real* c, bool rev, Real qv, Real* Rw, Real* pw, Real* s) {
+  // eqs. (4)-(5): R_pc = R0 + sin q A + (1 - cos q) B ; t_pc = t0 (+ q d for a prismatic joint)
+  Real sq, cq;
+  sincos_r(qv, &sq, &cq);
+  const Real omc = Real(1) - cq;
+  Real Rpc[9], tpc[3], Rn[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rpc[k] = c[C_R0 + k] + sq * c[C_A + k] + omc * c[C_B + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) tpc[k] = c[C_T0 + k] + qv * c[C_D + k];
+  mul33(Rw, Rpc, Rn);
+  Real pn[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pn[i] = Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2] + pw[i];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pw[k] = pn[k];
+  // motion subspace in the base frame = direct Jacobian column (eq. (7))
+  Real u[3], pxu[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * c[C_AX] + Rw[3 * i + 1] * c[C_AX + 1] + Rw[3 * i + 2] * c[C_AX + 2];
+  cross3(pw, u, pxu);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s[i] = rev ? u[i] : Real(0);
+    s[3 + i] = rev ? pxu[i] : u[i];
+  }
+}
+
+// Views of the staged table image.
+template <class Real>
+struct Tables {
+  const Real* cst;
+  const I4* meta;
+  const int16_t* sbody;
+  const int8_t* ssrc;
+  const int8_t* cslot;
+  const int* linfo;
+  const I4* bm2;
+  const int* dlist;
+  const int* mtab;
+};
+
+template <class Real>
+__device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const DevModel& dm) {
+  const TabLayout t = tab_layout(dm.n, dm.P, dm.depth, dm.kmax, dm.nv, (int)sizeof(Real));
+  Tables<Real> v;
+  v.cst = reinterpret_cast<const Real*>(base + t.cst);
+  v.meta = reinterpret_cast<const I4*>(base + t.meta);
+  v.sbody = reinterpret_cast<const int16_t*>(base + t.sbody);
+  v.ssrc = reinterpret_cast<const int8_t*>(base + t.ssrc);
+  v.cslot = reinterpret_cast<const int8_t*>(base + t.cslot);
+  v.linfo = reinterpret_cast<const int*>(base + t.linfo);
+  v.bm2 = reinterpret_cast<const I4*>(base + t.bm2);
+  v.dlist = reinterpret_cast<const int*>(base + t.dlist);
+  v.mtab = reinterpret_cast<const int*>(base + t.mtab);
+  return v;
+}
+
+// --------------------------------------------------------------------------
+// FK / Jacobian / RNEA / CRBA and their fusion (OPS bit mask).
+//   1. staging (all waves);
+//   2. level sweep (waves [0, WA), T instances x 2^log2P lanes): pose, s_i,
+//      and for RNEA the velocity and acceleration, left in per-body LDS blocks;
+//   3. body phase (all waves, one (body, instance) item per lane): world
+//      inertia I_i and body force f_i = I_i a_i + v_i x* I_i v_i;
+//   4. subtree phase (all waves): F_i = sum of f over the subtree and
+//      Ic_i = sum of I over the subtree (contiguous preorder ranges), then
+//      tau_i = s_i . F_i and Fc_i = Ic_i s_i;
+//   5. dense outputs (all waves, lanes over instances).
+// The level sweep is the only serial part; phases 3-5 have no cross-lane
+// dependencies, and sums are taken in a fixed order (deterministic results).
+// --------------------------------------------------------------------------
+template <class Real, int OPS, int LOGT>
+__global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
   constexpr bool FK = OPS & OP_FK;
   constexpr bool JAC = OPS & OP_JAC;
   constexpr bool RNEA = OPS & OP_RNEA;
@@ -164,162 +283,128 @@ __global__ void __launch_bounds__(256) tree_kernel(DevModel dm, DevEE ee, Args<R
   constexpr bool VEL = RNEA;
   constexpr bool BACK = RNEA || CRBA;
   constexpr bool NEED_S = JAC || RNEA || CRBA;
+  constexpr bool NEED_BODY = FK || RNEA || CRBA;
+  constexpr int T = 1 << LOGT;
+  constexpr int SD = 6 * T + block_pad(T, sizeof(Real));   // per-dof block stride (elements)
+  constexpr int SB = 24 * T + block_pad(T, sizeof(Real));  // per-body block stride (elements)
 
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Real* smem = reinterpret_cast<Real*>(smem_raw);
-
-  const int T = 1 << ar.logT;
+  extern __shared__ __align__(16) unsigned char smem[];
   const int nv = dm.nv, n = dm.n;
-  Real* s_l = smem;                                   // [nv][6][T]
-  Real* fc_l = s_l + (NEED_S ? nv * 6 * T : 0);       // [nv][6][T]
-  Real* f_l = fc_l + (CRBA ? nv * 6 * T : 0);         // [n][6][T]
-  Real* i0_l = f_l + (RNEA ? n * 6 * T : 0);          // [n][10][T]
-  Real* o_l = i0_l + (CRBA ? n * 10 * T : 0);         // [3][T]
-  Real* pe_l = o_l + 3 * T;                           // [n_ee][3][T]
-
-  const Real* cst = consts<Real>(dm);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int log2P = ar.log2P;      // lanes per instance used by this launch (>= dm.P)
-  const int P = dm.P;              // slots in the model's schedule tables
-  const int iw = lane >> log2P;
-  const int slot_raw = lane & ((1 << log2P) - 1);
-  const bool in_sched = slot_raw < P;
-  const int slot = in_sched ? slot_raw : 0;
-  const int inst = (wave << (6 - log2P)) + iw;
+  const LdsPlan L = lds_plan(0, OPS, n, dm.nq, nv, ee.n_ee, ar.frame, T, (int)sizeof(Real), dm.P, dm.depth,
+                             dm.kmax);
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t tile = tile_index(ar.xcd_remap);
-  const int64_t b = tile * T + inst;
-  const bool bvalid = b < ar.B;
-  const int64_t bl = bvalid ? b : (ar.B - 1);
-  const int lane0 = iw << log2P;
+  const int64_t tile0 = tile * T;
+  const bool full = tile0 + T <= ar.B;
 
-  const Real a0[6] = {Real(0), Real(0), Real(0), -grav<Real>(dm, 0), -grav<Real>(dm, 1), -grav<Real>(dm, 2)};
-
-  // Link state of the last body processed by this slot.
-  Real Rw[9], pw[3], v[6], a[6];
-  Real o[3] = {Real(0), Real(0), Real(0)};
-
-  auto qin = [&](int k) { return ar.q[bl * ar.sq_b + (int64_t)k * ar.sq_k]; };
-  auto qdin = [&](int k) { return ar.qd[bl * ar.sqd_b + (int64_t)k * ar.sqd_k]; };
-  auto qddin = [&](int k) { return ar.qdd[bl * ar.sqdd_b + (int64_t)k * ar.sqdd_k]; };
-  auto pi_of = [&](int body, int k) -> Real {
-    return ar.pi_ovr ? ar.pi_ovr[body * 10 + k] : cst[body * CST + C_PI + k];
-  };
-
-  // ---------------- phase A: forward sweep ----------------
-  int lstart = 0;
-  if (dm.free_root) {
-    // Level 0 holds only the free root (body 0); every slot computes it, slot 0 stores.
-    const Real* c = cst;
-    const bool act = (slot_raw == 0);
-    Real qx = qin(3), qy = qin(4), qz = qin(5), qw = qin(6);
-    const Real inv = Real(1) / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
-    qx *= inv; qy *= inv; qz *= inv; qw *= inv;
-    const Real Rq[9] = {Real(1) - Real(2) * (qy * qy + qz * qz), Real(2) * (qx * qy - qz * qw), Real(2) * (qx * qz + qy * qw),
-                        Real(2) * (qx * qy + qz * qw), Real(1) - Real(2) * (qx * qx + qz * qz), Real(2) * (qy * qz - qx * qw),
-                        Real(2) * (qx * qz - qy * qw), Real(2) * (qy * qz + qx * qw), Real(1) - Real(2) * (qx * qx + qy * qy)};
-    mul33(c + C_R0, Rq, Rw);
-    const Real pr[3] = {qin(0), qin(1), qin(2)};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      o[i] = c[C_R0 + 3 * i] * pr[0] + c[C_R0 + 3 * i + 1] * pr[1] + c[C_R0 + 3 * i + 2] * pr[2] + c[C_T0 + i];
-      pw[i] = Real(0);
-    }
-    // s columns: v_k -> [0; R e_k], w_k -> [R e_k; 0]  (base-centred: root at the origin)
-    if (NEED_S && act) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          s_l[((k)*6 + i) * T + inst] = Real(0);
-          s_l[((k)*6 + 3 + i) * T + inst] = Rw[3 * i + k];
-          s_l[((3 + k) * 6 + i) * T + inst] = Rw[3 * i + k];
-          s_l[((3 + k) * 6 + 3 + i) * T + inst] = Real(0);
-        }
-    }
-    Real I0[10];
-    if (BACK) {
-      Real pic[10];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) pic[k] = pi_of(0, k);
-      world_inertia(pic, Rw, pw, I0);
-      if (CRBA && act)
-#pragma unroll
-        for (int k = 0; k < 10; ++k) i0_l[k * T + inst] = I0[k];
-    }
-    if (VEL) {
-      const Real vb[3] = {qdin(0), qdin(1), qdin(2)}, wb[3] = {qdin(3), qdin(4), qdin(5)};
-      const Real ab[3] = {qddin(0), qddin(1), qddin(2)}, wdb[3] = {qddin(3), qddin(4), qddin(5)};
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        v[i] = Rw[3 * i] * wb[0] + Rw[3 * i + 1] * wb[1] + Rw[3 * i + 2] * wb[2];
-        v[3 + i] = Rw[3 * i] * vb[0] + Rw[3 * i + 1] * vb[1] + Rw[3 * i + 2] * vb[2];
-        a[i] = a0[i] + Rw[3 * i] * wdb[0] + Rw[3 * i + 1] * wdb[1] + Rw[3 * i + 2] * wdb[2];
-        a[3 + i] = a0[3 + i] + Rw[3 * i] * ab[0] + Rw[3 * i + 1] * ab[1] + Rw[3 * i + 2] * ab[2];
-      }
-      Real Ia[6], Iv[6], vxIv[6], f[6];
-      inertia_mul(I0, a, Ia);
-      inertia_mul(I0, v, Iv);
-      crf(v, Iv, vxIv);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) f[k] = Ia[k] + vxIv[k];
-      if (act)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) f_l[k * T + inst] = f[k];
-    }
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) o_l[i * T + inst] = o[i];
-    }
-    if (FK && act && bvalid) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) ar.poses[b * ar.sp_b + (int64_t)k * ar.sp_k] = Rw[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) ar.poses[b * ar.sp_b + (int64_t)(9 + k) * ar.sp_k] = o[k];
-    }
-    if (JAC && ar.frame == 1 && act) {
-      for (int e = 0; e < ee.n_ee; ++e)
-        if (ee.ee_body[e] == 0)
-#pragma unroll
-          for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = Real(0);
-    }
-    lstart = 1;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pw[k] = Real(0);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      v[k] = Real(0);
-      a[k] = a0[k];
-    }
-    if (slot_raw == 0)
-#pragma unroll
-      for (int i = 0; i < 3; ++i) o_l[i * T + inst] = Real(0);
+  // ---------------- 1. staging ----------------
+  copy16(smem + L.tab, image<Real>(dm), L.tab_bytes, tid, nt);
+  if (JAC) copy16(smem + L.ee, ee.img, ee_image_bytes(ee.n_ee, nv), tid, nt);
+  Real* q_l = reinterpret_cast<Real*>(smem + L.q);
+  Real* qd_l = reinterpret_cast<Real*>(smem + L.qd);
+  Real* qdd_l = reinterpret_cast<Real*>(smem + L.qdd);
+  stage_input<Real, LOGT>(ar.q, ar.sq_b, ar.sq_k, dm.nq, tile0, ar.B, q_l, tid, nt);
+  if (VEL) {
+    stage_input<Real, LOGT>(ar.qd, ar.sqd_b, ar.sqd_k, nv, tile0, ar.B, qd_l, tid, nt);
+    stage_input<Real, LOGT>(ar.qdd, ar.sqdd_b, ar.sqdd_k, nv, tile0, ar.B, qdd_l, tid, nt);
   }
-  // Every slot of an instance evaluated the root, so o is known in every lane.
+  Real* s_l = reinterpret_cast<Real*>(smem + L.s);        // [nv+1] blocks of 6 rows, block nv = 0
+  Real* fc_l = reinterpret_cast<Real*>(smem + L.fc);      // [nv+1] blocks of 6 rows, block nv = 0
+  Real* body_l = reinterpret_cast<Real*>(smem + L.body);  // [n] blocks of 24 rows, by preorder position
+  Real* o_l = reinterpret_cast<Real*>(smem + L.o);        // [3][T]
+  Real* pe_l = reinterpret_cast<Real*>(smem + L.pe);      // [n_ee][3][T]
+  if (NEED_S)
+    for (int i = tid; i < 6 * T; i += nt) s_l[nv * SD + (i >> LOGT) * T + (i & (T - 1))] = Real(0);
+  if (CRBA)
+    for (int i = tid; i < 6 * T; i += nt) fc_l[nv * SD + (i >> LOGT) * T + (i & (T - 1))] = Real(0);
+  __syncthreads();
 
-  for (int l = lstart; l < dm.depth; ++l) {
-    const int body = in_sched ? dm.sched_body[l * P + slot] : -1;
-    const bool act = body >= 0;
-    const int bb = act ? body : 0;
-    if (dm.level_info[2 * l + 1]) {
-      const int src = lane0 + (in_sched ? (int)dm.sched_src[l * P + slot] : slot_raw);
+  const Tables<Real> tb = tables<Real>(smem + L.tab, dm);
+  const int* jrow = reinterpret_cast<const int*>(smem + L.ee);
+  const int* eeb_l = jrow + lds_align(ee.n_ee * 6 * nv * 4) / 4;
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int log2P = ar.log2P;
+  const int WA = (T << log2P) >> 6;
+
+  // ---------------- 2. level sweep ----------------
+  if (wave < WA) {
+    const int P = dm.P;
+    const int iw = lane >> log2P;
+    const int slot_raw = lane & ((1 << log2P) - 1);
+    const bool in_sched = slot_raw < P;
+    const int slot = in_sched ? slot_raw : 0;
+    const int inst = (wave << (6 - log2P)) + iw;
+    const int lane0 = iw << log2P;
+    const Real a0[6] = {Real(0), Real(0), Real(0), -grav<Real>(dm, 0), -grav<Real>(dm, 1), -grav<Real>(dm, 2)};
+    const Real* qi_l = q_l + inst;
+    const Real* qdi_l = qd_l + inst;
+    const Real* qddi_l = qdd_l + inst;
+
+    Real Rw[9], pw[3], v[6], a[6];
+    int lstart = 0;
+    auto store_body = [&](int bb) {
+      Real* br = body_l + tb.bm2[bb].x * SB + inst;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
+      for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) pw[k] = xch(pw[k], src);
+      for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
       if (VEL) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          v[k] = xch(v[k], src);
-          a[k] = xch(a[k], src);
+          br[(12 + k) * T] = v[k];
+          br[(18 + k) * T] = a[k];
         }
       }
-    }
-    const I4 meta = dm.meta[bb];
-    if (meta.x < 0) {  // attached to the world (only at level 0 of a fixed base)
+    };
+    if (dm.free_root) {
+      // Level 0 holds only the free root; every slot evaluates it, slot 0 stores.
+      const bool act = (slot_raw == 0);
+      Real qr[7], o[3];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) qr[k] = qi_l[k * T];
+      free_root_pose(tb.cst, qr, Rw, o);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) pw[i] = Real(0);
+      if (VEL) {
+        const Real vb[3] = {qdi_l[0], qdi_l[T], qdi_l[2 * T]};
+        const Real wb[3] = {qdi_l[3 * T], qdi_l[4 * T], qdi_l[5 * T]};
+        const Real ab[3] = {qddi_l[0], qddi_l[T], qddi_l[2 * T]};
+        const Real wdb[3] = {qddi_l[3 * T], qddi_l[4 * T], qddi_l[5 * T]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          v[i] = Rw[3 * i] * wb[0] + Rw[3 * i + 1] * wb[1] + Rw[3 * i + 2] * wb[2];
+          v[3 + i] = Rw[3 * i] * vb[0] + Rw[3 * i + 1] * vb[1] + Rw[3 * i + 2] * vb[2];
+          a[i] = a0[i] + Rw[3 * i] * wdb[0] + Rw[3 * i + 1] * wdb[1] + Rw[3 * i + 2] * wdb[2];
+          a[3 + i] = a0[3 + i] + Rw[3 * i] * ab[0] + Rw[3 * i + 1] * ab[1] + Rw[3 * i + 2] * ab[2];
+        }
+      }
+      if (act) {
+        if (NEED_S) {
+          // s columns: v_k -> [0; R e_k], w_k -> [R e_k; 0] (the root sits at the origin)
+          Real* sr = s_l + inst;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              sr[k * SD + i * T] = Real(0);
+              sr[k * SD + (3 + i) * T] = Rw[3 * i + k];
+              sr[(3 + k) * SD + i * T] = Rw[3 * i + k];
+              sr[(3 + k) * SD + (3 + i) * T] = Real(0);
+            }
+        }
+        if (NEED_BODY) store_body(0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) o_l[i * T + inst] = o[i];
+        if (JAC && ar.frame == 1)
+          for (int e = 0; e < ee.n_ee; ++e)
+            if (eeb_l[e] == 0)
+#pragma unroll
+              for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = Real(0);
+      }
+      lstart = 1;
+    } else {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
 #pragma unroll
@@ -329,206 +414,223 @@ __global__ void __launch_bounds__(256) tree_kernel(DevModel dm, DevEE ee, Args<R
         v[k] = Real(0);
         a[k] = a0[k];
       }
+      if (slot_raw == 0)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) o_l[i * T + inst] = Real(0);
     }
-    const Real* c = cst + bb * CST;
-    const bool rev = (meta.y == J_REV);
-    const Real qv = qin(meta.z);
-    // eqs. (4)-(5): R_pc = R0 + sin q A + (1 - cos q) B ; t_pc = t0 (+ q d for a prismatic joint)
-    Real sq, cq;
-    sincos_r(qv, &sq, &cq);
-    const Real omc = Real(1) - cq;
-    Real Rpc[9], tpc[3];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rpc[k] = c[C_R0 + k] + sq * c[C_A + k] + omc * c[C_B + k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) tpc[k] = c[C_T0 + k] + qv * c[C_D + k];
-    // world pose: R = R_p R_pc, p = R_p t_pc + p_p
-    Real Rn[9], pn[3];
-    mul33(Rw, Rpc, Rn);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) pn[i] = Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2] + pw[i];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pw[k] = pn[k];
 
-    if (FK && act && bvalid) {
-      const int64_t base = b * ar.sp_b + (int64_t)(bb * 12) * ar.sp_k;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) ar.poses[base + (int64_t)k * ar.sp_k] = Rw[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) ar.poses[base + (int64_t)(9 + k) * ar.sp_k] = pw[k] + o[k];
-    }
-    if (JAC && ar.frame == 1 && act) {
-      for (int e = 0; e < ee.n_ee; ++e)
-        if (ee.ee_body[e] == bb)
-#pragma unroll
-          for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
-    }
-    if (!NEED_S) continue;
-    // motion subspace in the base frame = direct Jacobian column (eq. (7))
-    Real u[3], s[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * c[C_AX] + Rw[3 * i + 1] * c[C_AX + 1] + Rw[3 * i + 2] * c[C_AX + 2];
-    Real pxu[3];
-    cross3(pw, u, pxu);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      s[i] = rev ? u[i] : Real(0);
-      s[3 + i] = rev ? pxu[i] : u[i];
-    }
-    if (act)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) s_l[(meta.w * 6 + k) * T + inst] = s[k];
-    if (!BACK) continue;
-    Real pic[10], I0[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) pic[k] = pi_of(bb, k);
-    world_inertia(pic, Rw, pw, I0);
-    if (CRBA && act)
-#pragma unroll
-      for (int k = 0; k < 10; ++k) i0_l[(bb * 10 + k) * T + inst] = I0[k];
-    if (VEL) {
-      const Real qdv = qdin(meta.w), qddv = qddin(meta.w);
-      Real vJ[6], cJ[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
-      crm(v, vJ, cJ);  // v_parent x (s qd)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        a[k] = a[k] + s[k] * qddv + cJ[k];
-        v[k] = v[k] + vJ[k];
-      }
-      Real Ia[6], Iv[6], vxIv[6];
-      inertia_mul(I0, a, Ia);
-      inertia_mul(I0, v, Iv);
-      crf(v, Iv, vxIv);
-      if (act)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) f_l[(bb * 6 + k) * T + inst] = Ia[k] + vxIv[k];
-    }
-  }
-
-  // ---------------- backward sweep: gather children ----------------
-  if (BACK) {
-    Real F[6], Ic[10];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) F[k] = Real(0);
-#pragma unroll
-    for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
-    for (int l = dm.depth - 1; l >= 0; --l) {
-      const int body = in_sched ? dm.sched_body[l * P + slot] : -1;
+    for (int l = lstart; l < dm.depth; ++l) {
+      const int body = in_sched ? tb.sbody[l * P + slot] : -1;
       const bool act = body >= 0;
       const int bb = act ? body : 0;
-      Real Fn[6], Icn[10];
-      if (RNEA)
+      if (tb.linfo[2 * l + 1]) {
+        const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Fn[k] = f_l[(bb * 6 + k) * T + inst];
-      if (CRBA)
+        for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) Icn[k] = i0_l[(bb * 10 + k) * T + inst];
-      const int K = dm.level_info[2 * l];
-      for (int j = 0; j < K; ++j) {
-        const int cs = in_sched ? dm.child_slot[(l * P + slot) * dm.kmax + j] : -1;
-        const int src = lane0 + (cs >= 0 ? cs : slot_raw);
-        if (RNEA)
+        for (int k = 0; k < 3; ++k) pw[k] = xch(pw[k], src);
+        if (VEL) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
-            Real x = xch(F[k], src);
-            Fn[k] += (cs >= 0) ? x : Real(0);
+            v[k] = xch(v[k], src);
+            a[k] = xch(a[k], src);
           }
-        if (CRBA)
-#pragma unroll
-          for (int k = 0; k < 10; ++k) {
-            Real x = xch(Ic[k], src);
-            Icn[k] += (cs >= 0) ? x : Real(0);
-          }
+        }
       }
-      if (RNEA)
+      const I4 meta = tb.meta[bb];
+      if (meta.x < 0) {  // attached to the world (level 0 of a fixed base)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) F[k] = Fn[k];
-      if (CRBA)
+        for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
 #pragma unroll
-        for (int k = 0; k < 10; ++k) Ic[k] = Icn[k];
-      if (!act) continue;
-      const I4 meta = dm.meta[bb];
-      const int ndof = (meta.y == J_FREE) ? 6 : 1;
-      for (int d = 0; d < ndof; ++d) {
-        Real s[6];
+        for (int k = 0; k < 3; ++k) pw[k] = Real(0);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = s_l[((meta.w + d) * 6 + k) * T + inst];
-        if (RNEA && bvalid) {
-          Real t = s[0] * F[0] + s[1] * F[1] + s[2] * F[2] + s[3] * F[3] + s[4] * F[4] + s[5] * F[5];
-          ar.tau[b * ar.st_b + (int64_t)(meta.w + d) * ar.st_k] = t;
+        for (int k = 0; k < 6; ++k) {
+          v[k] = Real(0);
+          a[k] = a0[k];
         }
-        if (CRBA) {
-          Real fc[6];
-          inertia_mul(Ic, s, fc);
+      }
+      Real s[6];
+      joint_step(tb.cst + bb * CST, meta.y == J_REV, qi_l[meta.z * T], Rw, pw, s);
+      if (VEL) {
+        const Real qdv = qdi_l[meta.w * T], qddv = qddi_l[meta.w * T];
+        Real vJ[6], cJ[6];
 #pragma unroll
-          for (int k = 0; k < 6; ++k) fc_l[((meta.w + d) * 6 + k) * T + inst] = fc[k];
+        for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
+        crm(v, vJ, cJ);  // v_parent x (s qd)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          a[k] = a[k] + s[k] * qddv + cJ[k];
+          v[k] = v[k] + vJ[k];
         }
+      }
+      if (act) {
+        if (NEED_S) {
+          Real* sr = s_l + meta.w * SD + inst;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
+        }
+        if (NEED_BODY) store_body(bb);
+        if (JAC && ar.frame == 1)
+          for (int e = 0; e < ee.n_ee; ++e)
+            if (eeb_l[e] == bb)
+#pragma unroll
+              for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
       }
     }
   }
 
-  if (!(CRBA || JAC)) return;
-  __syncthreads();
+  if (BACK || FK || JAC) __syncthreads();
 
-  // ---------------- phase B: dense outputs, lanes over instances ----------------
-  const int nthreads = blockDim.x;
-  const int64_t tile0 = tile * T;
-  const int Tm = T - 1;
-  if (CRBA) {
-    const int total = nv * nv * T;
-    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
-      const int row = idx >> ar.logT;
-      const int in = idx & Tm;
-      const int64_t bo = tile0 + in;
-      if (bo >= ar.B) continue;
-      const int e = dm.mtab[row];
-      Real val = Real(0);
-      if (e >= 0) {
-        const int ad = e >> 16, dd = e & 0xffff;
-        const Real* sa = s_l + (ad * 6) * T + in;
-        const Real* fd = fc_l + (dd * 6) * T + in;
-        val = sa[0] * fd[0] + sa[T] * fd[T] + sa[2 * T] * fd[2 * T] + sa[3 * T] * fd[3 * T] +
-              sa[4 * T] * fd[4 * T] + sa[5 * T] * fd[5 * T];
+  // Phases 3-5 give every thread one fixed instance of the tile and stride over
+  // items, so output addresses advance by a constant and loads from
+  // independent items overlap.
+  const int in = tid & (T - 1);
+  const int r0 = tid >> LOGT;
+  const int rstep = nt >> LOGT;
+  const int64_t bo = tile0 + in;
+  const bool bok = full || bo < ar.B;
+
+  // ---------------- 3. body phase: world inertia and body force ----------------
+  if (BACK) {
+    for (int bb = r0; bb < n; bb += rstep) {
+      Real* br = body_l + tb.bm2[bb].x * SB + in;
+      Real R[9], p[3], pic[10], I0[10];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) R[k] = br[k * T];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[k] = br[(9 + k) * T];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) pic[k] = ar.pi_ovr ? ar.pi_ovr[bb * 10 + k] : tb.cst[bb * CST + C_PI + k];
+      world_inertia(pic, R, p, I0);
+      Real f[6];
+      if (VEL) {
+        Real v[6], a[6], Ia[6], Iv[6], vxIv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          v[k] = br[(12 + k) * T];
+          a[k] = br[(18 + k) * T];
+        }
+        inertia_mul(I0, a, Ia);
+        inertia_mul(I0, v, Iv);
+        crf(v, Iv, vxIv);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[k] = Ia[k] + vxIv[k];
       }
-      ar.M[bo * ar.sM_b + (int64_t)row * ar.sM_k] = val;
+      // overwrite this body's block in place: rows 0-5 f, rows 6-15 I
+      if (VEL)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) br[k * T] = f[k];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) br[(6 + k) * T] = I0[k];
+    }
+    __syncthreads();
+
+    // ---------------- 4. subtree phase ----------------
+    for (int j = r0; j < n; j += rstep) {
+      const int bb = tb.dlist[j];
+      const I4 m2 = tb.bm2[bb];  // {preorder position, subtree size, v index, dofs}
+      Real F[6], Ic[10];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) F[k] = Real(0);
+#pragma unroll
+      for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
+      const Real* br = body_l + m2.x * SB + in;
+      for (int c = 0; c < m2.y; ++c, br += SB) {
+        if (RNEA)
+#pragma unroll
+          for (int k = 0; k < 6; ++k) F[k] += br[k * T];
+        if (CRBA)
+#pragma unroll
+          for (int k = 0; k < 10; ++k) Ic[k] += br[(6 + k) * T];
+      }
+      for (int d = 0; d < m2.w; ++d) {
+        const Real* sr = s_l + (m2.z + d) * SD + in;
+        Real s[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
+        if (RNEA && bok) {
+          const Real t = s[0] * F[0] + s[1] * F[1] + s[2] * F[2] + s[3] * F[3] + s[4] * F[4] + s[5] * F[5];
+          ar.tau[bo * ar.st_b + (int64_t)(m2.z + d) * ar.st_k] = t;
+        }
+        if (CRBA) {
+          Real fcv[6];
+          inertia_mul(Ic, s, fcv);
+          Real* fo = fc_l + (m2.z + d) * SD + in;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) fo[k * T] = fcv[k];
+        }
+      }
+    }
+    if (CRBA) __syncthreads();
+  }
+
+  // ---------------- 5. dense outputs, lanes over instances ----------------
+  // Structural zeros read the all-zero block nv, so the loops carry no
+  // branches apart from the batch bound of the last tile.  Rows are taken four
+  // at a time so their LDS reads are in flight together.
+  if (!bok) return;
+  if (FK) {
+    const int NR = n * 12;
+    Real* out = ar.poses + bo * ar.sp_b;
+    for (int row = r0; row < NR; row += rstep) {
+      const int bb = row / 12;
+      const int k = row - bb * 12;
+      Real val = body_l[tb.bm2[bb].x * SB + k * T + in];
+      if (k >= 9) val += o_l[(k - 9) * T + in];
+      out[(int64_t)row * ar.sp_k] = val;
+    }
+  }
+  if (CRBA) {
+    const int NR = nv * nv;
+    Real* out = ar.M + bo * ar.sM_b;
+    const int64_t ostep = (int64_t)rstep * ar.sM_k;
+    const int zcode = (nv << 16) | nv;
+    for (int row = r0; row < NR; row += 4 * rstep) {
+      Real val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = row + u * rstep;
+        const int e = (rr < NR) ? tb.mtab[rr] : zcode;
+        const Real* sa = s_l + (e >> 16) * SD + in;
+        const Real* fd = fc_l + (e & 0xffff) * SD + in;
+        val[u] = sa[0] * fd[0] + sa[T] * fd[T] + sa[2 * T] * fd[2 * T] + sa[3 * T] * fd[3 * T] +
+                 sa[4 * T] * fd[4 * T] + sa[5 * T] * fd[5 * T];
+      }
+      Real* o = out + (int64_t)row * ar.sM_k;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (row + u * rstep < NR) o[u * ostep] = val[u];
     }
   }
   if (JAC) {
-    const int total = ee.n_ee * 6 * nv * T;
-    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
-      const int row = idx >> ar.logT;
-      const int in = idx & Tm;
-      const int64_t bo = tile0 + in;
-      if (bo >= ar.B) continue;
-      const int col = row % nv;
-      const int er = row / nv;
-      const int r = er % 6;
-      const int e = er / 6;
-      const int src = ee.jtab[e * nv + col];
-      Real val = Real(0);
-      if (src >= 0) {
-        const Real* s = s_l + (src * 6) * T + in;
-        if (r >= 3) {
-          val = s[(r - 3) * T];
-        } else {
-          const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
-          // linear row: v + o x w (world origin) or v + w x p_e (end-effector origin)
-          Real x1, x2;
-          if (ar.frame == 0) {
-            x1 = o_l[r1 * T + in] * s[r2 * T];
-            x2 = o_l[r2 * T + in] * s[r1 * T];
-          } else {
-            x1 = s[r1 * T] * pe_l[(e * 3 + r2) * T + in];
-            x2 = s[r2 * T] * pe_l[(e * 3 + r1) * T + in];
-          }
-          val = s[(3 + r) * T] + (x1 - x2);
-        }
+    const int NR = ee.n_ee * 6 * nv;
+    const bool world = ar.frame == 0;
+    Real* out = ar.J + bo * ar.sJ_b;
+    const int64_t ostep = (int64_t)rstep * ar.sJ_k;
+    const int zcode = nv;  // row 0 of the zero block
+    for (int row = r0; row < NR; row += 4 * rstep) {
+      Real val[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = row + u * rstep;
+        const int code = (rr < NR) ? jrow[rr] : zcode;
+        const int r = (code >> 8) & 0xf;
+        const int e = code >> 12;
+        const Real* s = s_l + (code & 0xff) * SD + in;
+        // rows 0-2: v + o x w (world origin) or v + w x p_e (end-effector origin); rows 3-5: w
+        const bool lin = r < 3;
+        const int rv = lin ? r : r - 3;
+        const int r1 = (rv == 2) ? 0 : rv + 1;
+        const int r2 = (rv == 0) ? 2 : rv - 1;
+        const Real* P = world ? (o_l + in) : (pe_l + e * 3 * T + in);
+        const Real cross = world ? (P[r1 * T] * s[r2 * T] - P[r2 * T] * s[r1 * T])
+                                 : (s[r1 * T] * P[r2 * T] - s[r2 * T] * P[r1 * T]);
+        val[u] = lin ? s[(3 + rv) * T] + cross : s[rv * T];
       }
-      ar.J[bo * ar.sJ_b + (int64_t)row * ar.sJ_k] = val;
+      Real* o = out + (int64_t)row * ar.sJ_k;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (row + u * rstep < NR) o[u * ostep] = val[u];
     }
   }
 }
@@ -555,7 +657,6 @@ __device__ __forceinline__ void rigid_to_sym(const Real* I0, Real* S) {
   const Real hx = I0[1], hy = I0[2], hz = I0[3], m = I0[0];
   S[sym6(0, 0)] = I0[4]; S[sym6(0, 1)] = I0[5]; S[sym6(1, 1)] = I0[6];
   S[sym6(0, 2)] = I0[7]; S[sym6(1, 2)] = I0[8]; S[sym6(2, 2)] = I0[9];
-  // top-right block h^ = [[0,-hz,hy],[hz,0,-hx],[-hy,hx,0]]
   S[sym6(0, 3)] = Real(0); S[sym6(0, 4)] = -hz; S[sym6(0, 5)] = hy;
   S[sym6(1, 3)] = hz; S[sym6(1, 4)] = Real(0); S[sym6(1, 5)] = -hx;
   S[sym6(2, 3)] = -hy; S[sym6(2, 4)] = hx; S[sym6(2, 5)] = Real(0);
@@ -574,55 +675,63 @@ __device__ __forceinline__ void sym_mul(const Real* S, const Real* x, Real* y) {
   }
 }
 
-template <class Real>
+template <class Real, int LOGT>
 __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  Real* smem = reinterpret_cast<Real*>(smem_raw);
-  const int T = 1 << ar.logT;
-  const int n = dm.n;
-  // per body: s(6*ndof) is per dof; c(6), IA(21), pA(6), U(6), Dinv(1), u(1) per body
-  Real* s_l = smem;                        // [nv][6][T]
-  Real* c_l = s_l + dm.nv * 6 * T;         // [n][6][T]
-  Real* ia_l = c_l + n * 6 * T;            // [n][21][T]
-  Real* pa_l = ia_l + n * 21 * T;          // [n][6][T]
-  Real* u_l = pa_l + n * 6 * T;            // [n][8][T] : U(6), 1/D, u
+  constexpr int T = 1 << LOGT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nv = dm.nv;
+  const LdsPlan L = lds_plan(1, 0, dm.n, dm.nq, nv, 0, 0, T, (int)sizeof(Real), dm.P, dm.depth, dm.kmax);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t tile = tile_index(ar.xcd_remap);
+  const int64_t tile0 = tile * T;
 
-  const Real* cst = consts<Real>(dm);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int log2P = ar.log2P;      // lanes per instance used by this launch (>= dm.P)
-  const int P = dm.P;              // slots in the model's schedule tables
+  copy16(smem + L.tab, image<Real>(dm), L.tab_bytes, tid, nt);
+  Real* q_l = reinterpret_cast<Real*>(smem + L.q);
+  Real* qd_l = reinterpret_cast<Real*>(smem + L.qd);
+  Real* t_l = reinterpret_cast<Real*>(smem + L.tin);
+  stage_input<Real, LOGT>(ar.q, ar.sq_b, ar.sq_k, dm.nq, tile0, ar.B, q_l, tid, nt);
+  stage_input<Real, LOGT>(ar.qd, ar.sqd_b, ar.sqd_k, nv, tile0, ar.B, qd_l, tid, nt);
+  stage_input<Real, LOGT>(ar.tau_in, ar.sti_b, ar.sti_k, nv, tile0, ar.B, t_l, tid, nt);
+  __syncthreads();
+
+  const Tables<Real> tb = tables<Real>(smem + L.tab, dm);
+  Real* s_l = reinterpret_cast<Real*>(smem + L.s);    // [nv][6][T]
+  Real* c_l = reinterpret_cast<Real*>(smem + L.c);    // [n][6][T]
+  Real* ia_l = reinterpret_cast<Real*>(smem + L.ia);  // [n][21][T]
+  Real* pa_l = reinterpret_cast<Real*>(smem + L.pa);  // [n][6][T]
+  Real* u_l = reinterpret_cast<Real*>(smem + L.u);    // [n][8][T] : U(6), 1/D, u
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int log2P = ar.log2P;
+  const int WA = (T << log2P) >> 6;
+  if (wave >= WA) return;  // no cross-wave phase follows
+
+  const int P = dm.P;
   const int iw = lane >> log2P;
   const int slot_raw = lane & ((1 << log2P) - 1);
   const bool in_sched = slot_raw < P;
   const int slot = in_sched ? slot_raw : 0;
   const int inst = (wave << (6 - log2P)) + iw;
-  const int64_t tile = tile_index(ar.xcd_remap);
-  const int64_t b = tile * T + inst;
+  const int64_t b = tile0 + inst;
   const bool bvalid = b < ar.B;
-  const int64_t bl = bvalid ? b : (ar.B - 1);
   const int lane0 = iw << log2P;
   const Real a0[6] = {Real(0), Real(0), Real(0), -grav<Real>(dm, 0), -grav<Real>(dm, 1), -grav<Real>(dm, 2)};
-
-  auto qin = [&](int k) { return ar.q[bl * ar.sq_b + (int64_t)k * ar.sq_k]; };
-  auto qdin = [&](int k) { return ar.qd[bl * ar.sqd_b + (int64_t)k * ar.sqd_k]; };
-  auto tauin = [&](int k) { return ar.tau_in[bl * ar.sti_b + (int64_t)k * ar.sti_k]; };
+  const Real* qi_l = q_l + inst;
+  const Real* qdi_l = qd_l + inst;
+  const Real* ti_l = t_l + inst;
 
   Real Rw[9], pw[3], v[6];
   int lstart = 0;
   if (dm.free_root) {
-    const Real* c = cst;
     const bool act = (slot_raw == 0);
-    Real qx = qin(3), qy = qin(4), qz = qin(5), qw = qin(6);
-    const Real inv = Real(1) / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
-    qx *= inv; qy *= inv; qz *= inv; qw *= inv;
-    const Real Rq[9] = {Real(1) - Real(2) * (qy * qy + qz * qz), Real(2) * (qx * qy - qz * qw), Real(2) * (qx * qz + qy * qw),
-                        Real(2) * (qx * qy + qz * qw), Real(1) - Real(2) * (qx * qx + qz * qz), Real(2) * (qy * qz - qx * qw),
-                        Real(2) * (qx * qz - qy * qw), Real(2) * (qy * qz + qx * qw), Real(1) - Real(2) * (qx * qx + qy * qy)};
-    mul33(c + C_R0, Rq, Rw);
+    Real qr[7], o[3];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) qr[k] = qi_l[k * T];
+    free_root_pose(tb.cst, qr, Rw, o);
 #pragma unroll
     for (int i = 0; i < 3; ++i) pw[i] = Real(0);
-    const Real vb[3] = {qdin(0), qdin(1), qdin(2)}, wb[3] = {qdin(3), qdin(4), qdin(5)};
+    const Real vb[3] = {qdi_l[0], qdi_l[T], qdi_l[2 * T]}, wb[3] = {qdi_l[3 * T], qdi_l[4 * T], qdi_l[5 * T]};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       v[i] = Rw[3 * i] * wb[0] + Rw[3 * i + 1] * wb[1] + Rw[3 * i + 2] * wb[2];
@@ -630,20 +739,21 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
     }
     Real pic[10], I0[10], IA[21], Iv[6], pA[6];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) pic[k] = c[C_PI + k];
+    for (int k = 0; k < 10; ++k) pic[k] = tb.cst[C_PI + k];
     world_inertia(pic, Rw, pw, I0);
     rigid_to_sym(I0, IA);
     inertia_mul(I0, v, Iv);
     crf(v, Iv, pA);
     if (act) {
+      Real* sr = s_l + inst;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          s_l[((k)*6 + i) * T + inst] = Real(0);
-          s_l[((k)*6 + 3 + i) * T + inst] = Rw[3 * i + k];
-          s_l[((3 + k) * 6 + i) * T + inst] = Rw[3 * i + k];
-          s_l[((3 + k) * 6 + 3 + i) * T + inst] = Real(0);
+          sr[(k * 6 + i) * T] = Real(0);
+          sr[(k * 6 + 3 + i) * T] = Rw[3 * i + k];
+          sr[((3 + k) * 6 + i) * T] = Rw[3 * i + k];
+          sr[((3 + k) * 6 + 3 + i) * T] = Real(0);
         }
 #pragma unroll
       for (int k = 0; k < 6; ++k) c_l[k * T + inst] = Real(0);
@@ -664,11 +774,11 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 
   // ---- sweep 1 ----
   for (int l = lstart; l < dm.depth; ++l) {
-    const int body = in_sched ? dm.sched_body[l * P + slot] : -1;
+    const int body = in_sched ? tb.sbody[l * P + slot] : -1;
     const bool act = body >= 0;
     const int bb = act ? body : 0;
-    if (dm.level_info[2 * l + 1]) {
-      const int src = lane0 + (in_sched ? (int)dm.sched_src[l * P + slot] : slot_raw);
+    if (tb.linfo[2 * l + 1]) {
+      const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
@@ -676,7 +786,7 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) v[k] = xch(v[k], src);
     }
-    const I4 meta = dm.meta[bb];
+    const I4 meta = tb.meta[bb];
     if (meta.x < 0) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
@@ -685,34 +795,10 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) v[k] = Real(0);
     }
-    const Real* c = cst + bb * CST;
-    const bool rev = (meta.y == J_REV);
-    const Real qv = qin(meta.z);
-    Real sq, cq;
-    sincos_r(qv, &sq, &cq);
-    const Real omc = Real(1) - cq;
-    Real Rpc[9], tpc[3], Rn[9], pn[3];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rpc[k] = c[C_R0 + k] + sq * c[C_A + k] + omc * c[C_B + k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) tpc[k] = c[C_T0 + k] + qv * c[C_D + k];
-    mul33(Rw, Rpc, Rn);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) pn[i] = Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2] + pw[i];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) pw[k] = pn[k];
-    Real u[3], s[6], pxu[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * c[C_AX] + Rw[3 * i + 1] * c[C_AX + 1] + Rw[3 * i + 2] * c[C_AX + 2];
-    cross3(pw, u, pxu);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      s[i] = rev ? u[i] : Real(0);
-      s[3 + i] = rev ? pxu[i] : u[i];
-    }
-    const Real qdv = qdin(meta.w);
+    const Real* c = tb.cst + bb * CST;
+    Real s[6];
+    joint_step(c, meta.y == J_REV, qi_l[meta.z * T], Rw, pw, s);
+    const Real qdv = qdi_l[meta.w * T];
     Real vJ[6], cJ[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
@@ -727,14 +813,18 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
     inertia_mul(I0, v, Iv);
     crf(v, Iv, pA);
     if (act) {
+      Real* sr = s_l + meta.w * 6 * T + inst;
+      Real* cr = c_l + bb * 6 * T + inst;
+      Real* ir = ia_l + bb * 21 * T + inst;
+      Real* pr = pa_l + bb * 6 * T + inst;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) s_l[(meta.w * 6 + k) * T + inst] = s[k];
+      for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) c_l[(bb * 6 + k) * T + inst] = cJ[k];
+      for (int k = 0; k < 6; ++k) cr[k * T] = cJ[k];
 #pragma unroll
-      for (int k = 0; k < 21; ++k) ia_l[(bb * 21 + k) * T + inst] = IA[k];
+      for (int k = 0; k < 21; ++k) ir[k * T] = IA[k];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) pa_l[(bb * 6 + k) * T + inst] = pA[k];
+      for (int k = 0; k < 6; ++k) pr[k * T] = pA[k];
     }
   }
 
@@ -744,21 +834,25 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
   for (int k = 0; k < 21; ++k) Ia[k] = Real(0);
 #pragma unroll
   for (int k = 0; k < 6; ++k) pa[k] = Real(0);
-  Real Lroot[21];   // Cholesky factor of the free root's D (lower, packed by sym6 index)
+  Real Lroot[21];   // Cholesky factor of the free root's D, packed by sym6(r, c), r >= c
   Real uroot[6];
   Real Uroot[36];   // U columns of the free root, [dof][6]
   for (int l = dm.depth - 1; l >= 0; --l) {
-    const int body = in_sched ? dm.sched_body[l * P + slot] : -1;
+    const int body = in_sched ? tb.sbody[l * P + slot] : -1;
     const bool act = body >= 0;
     const int bb = act ? body : 0;
     Real IA[21], pA[6];
+    {
+      const Real* ir = ia_l + bb * 21 * T + inst;
+      const Real* pr = pa_l + bb * 6 * T + inst;
 #pragma unroll
-    for (int k = 0; k < 21; ++k) IA[k] = ia_l[(bb * 21 + k) * T + inst];
+      for (int k = 0; k < 21; ++k) IA[k] = ir[k * T];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pA[k] = pa_l[(bb * 6 + k) * T + inst];
-    const int K = dm.level_info[2 * l];
+      for (int k = 0; k < 6; ++k) pA[k] = pr[k * T];
+    }
+    const int K = tb.linfo[2 * l];
     for (int j = 0; j < K; ++j) {
-      const int cs = in_sched ? dm.child_slot[(l * P + slot) * dm.kmax + j] : -1;
+      const int cs = in_sched ? tb.cslot[(l * P + slot) * dm.kmax + j] : -1;
       const int src = lane0 + (cs >= 0 ? cs : slot_raw);
 #pragma unroll
       for (int k = 0; k < 21; ++k) {
@@ -771,9 +865,9 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
         pA[k] += (cs >= 0) ? x : Real(0);
       }
     }
-    const I4 meta = dm.meta[bb];
+    const I4 meta = tb.meta[bb];
     if (dm.free_root && l == 0) {
-      // Free root: U = IA S (6 columns), D = S^T IA S, u = tau - S^T pA; keep the Cholesky factor of D.
+      // Free root: U = IA S (6 columns), D = S^T IA S, u = tau - S^T pA; factor D = L L^T.
       Real Dm[21];
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
@@ -783,7 +877,8 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
         sym_mul(IA, sd, Ud);
 #pragma unroll
         for (int k = 0; k < 6; ++k) Uroot[d * 6 + k] = Ud[k];
-        uroot[d] = tauin(d) - (sd[0] * pA[0] + sd[1] * pA[1] + sd[2] * pA[2] + sd[3] * pA[3] + sd[4] * pA[4] + sd[5] * pA[5]);
+        uroot[d] = ti_l[d * T] - (sd[0] * pA[0] + sd[1] * pA[1] + sd[2] * pA[2] + sd[3] * pA[3] + sd[4] * pA[4] +
+                                  sd[5] * pA[5]);
       }
 #pragma unroll
       for (int r = 0; r < 6; ++r)
@@ -794,7 +889,6 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
           for (int k = 0; k < 6; ++k) acc += s_l[(r * 6 + k) * T + inst] * Uroot[cc * 6 + k];
           Dm[sym6(r, cc)] = acc;
         }
-      // Cholesky D = L L^T, L packed with index sym6(r, c) for r >= c.
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
         Real d = Dm[sym6(j, j)];
@@ -814,15 +908,20 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
       continue;
     }
     Real s[6], cJ[6];
+    {
+      const Real* sr = s_l + meta.w * 6 * T + inst;
+      const Real* cr = c_l + bb * 6 * T + inst;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s[k] = s_l[(meta.w * 6 + k) * T + inst];
+      for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cJ[k] = c_l[(bb * 6 + k) * T + inst];
+      for (int k = 0; k < 6; ++k) cJ[k] = cr[k * T];
+    }
     Real U[6];
     sym_mul(IA, s, U);
     const Real D = s[0] * U[0] + s[1] * U[1] + s[2] * U[2] + s[3] * U[3] + s[4] * U[4] + s[5] * U[5];
     const Real Dinv = Real(1) / D;
-    const Real uu = tauin(meta.w) - (s[0] * pA[0] + s[1] * pA[1] + s[2] * pA[2] + s[3] * pA[3] + s[4] * pA[4] + s[5] * pA[5]);
+    const Real uu = ti_l[meta.w * T] - (s[0] * pA[0] + s[1] * pA[1] + s[2] * pA[2] + s[3] * pA[3] + s[4] * pA[4] +
+                                        s[5] * pA[5]);
     // Ia = IA - U U^T / D ; pa = pA + Ia c + U u / D
 #pragma unroll
     for (int r = 0; r < 6; ++r)
@@ -834,10 +933,11 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) pa[k] = pA[k] + Iac[k] + U[k] * uD;
     if (act) {
+      Real* ur = u_l + bb * 8 * T + inst;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) u_l[(bb * 8 + k) * T + inst] = U[k];
-      u_l[(bb * 8 + 6) * T + inst] = Dinv;
-      u_l[(bb * 8 + 7) * T + inst] = uu;
+      for (int k = 0; k < 6; ++k) ur[k * T] = U[k];
+      ur[6 * T] = Dinv;
+      ur[7 * T] = uu;
     }
   }
 
@@ -854,7 +954,6 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
       for (int k = 0; k < 6; ++k) t -= Uroot[d * 6 + k] * a0[k];
       rhs[d] = t;
     }
-    // forward then backward substitution
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       Real t = rhs[i];
@@ -883,28 +982,32 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
     for (int k = 0; k < 6; ++k) acc[k] = a0[k];
   }
   for (int l = lstart; l < dm.depth; ++l) {
-    const int body = in_sched ? dm.sched_body[l * P + slot] : -1;
+    const int body = in_sched ? tb.sbody[l * P + slot] : -1;
     const bool act = body >= 0;
     const int bb = act ? body : 0;
-    if (dm.level_info[2 * l + 1]) {
-      const int src = lane0 + (in_sched ? (int)dm.sched_src[l * P + slot] : slot_raw);
+    if (tb.linfo[2 * l + 1]) {
+      const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[k] = xch(acc[k], src);
     }
-    const I4 meta = dm.meta[bb];
+    const I4 meta = tb.meta[bb];
     if (meta.x < 0)
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[k] = a0[k];
     Real s[6], U[6];
+    const Real* sr = s_l + meta.w * 6 * T + inst;
+    const Real* ur = u_l + bb * 8 * T + inst;
+    const Real* cr = c_l + bb * 6 * T + inst;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      s[k] = s_l[(meta.w * 6 + k) * T + inst];
-      U[k] = u_l[(bb * 8 + k) * T + inst];
-      acc[k] += c_l[(bb * 6 + k) * T + inst];
+      s[k] = sr[k * T];
+      U[k] = ur[k * T];
+      acc[k] += cr[k * T];
     }
-    const Real Dinv = u_l[(bb * 8 + 6) * T + inst];
-    const Real uu = u_l[(bb * 8 + 7) * T + inst];
-    const Real qddv = (uu - (U[0] * acc[0] + U[1] * acc[1] + U[2] * acc[2] + U[3] * acc[3] + U[4] * acc[4] + U[5] * acc[5])) * Dinv;
+    const Real Dinv = ur[6 * T];
+    const Real uu = ur[7 * T];
+    const Real qddv =
+        (uu - (U[0] * acc[0] + U[1] * acc[1] + U[2] * acc[2] + U[3] * acc[3] + U[4] * acc[4] + U[5] * acc[5])) * Dinv;
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] += s[k] * qddv;
     if (act && bvalid) ar.qdd_out[b * ar.sqo_b + (int64_t)meta.w * ar.sqo_k] = qddv;
@@ -912,29 +1015,53 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 }
 
 // --------------------------------------------------------------------------
-// Host-visible launchers.
+// Host-visible launchers: pick the compile-time tile and launch.
 // --------------------------------------------------------------------------
+template <class K>
+static hipError_t raise_lds(K kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <class Real, int OPS, int LOGT>
+static hipError_t launch_tree_t(const DevModel& dm, const DevEE& ee, const Args<Real>& ar, int grid, int block,
+                                size_t lds, hipStream_t st) {
+  hipError_t e = raise_lds(tree_kernel<Real, OPS, LOGT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((tree_kernel<Real, OPS, LOGT>), dim3(grid), dim3(block), lds, st, dm, ee, ar);
+  return hipGetLastError();
+}
+
 template <class Real, int OPS>
 hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar, int grid, int block, size_t lds,
                        hipStream_t st) {
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)tree_kernel<Real, OPS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  switch (ar.logT) {
+    case 3: return launch_tree_t<Real, OPS, 3>(dm, ee, ar, grid, block, lds, st);
+    case 4: return launch_tree_t<Real, OPS, 4>(dm, ee, ar, grid, block, lds, st);
+    case 5: return launch_tree_t<Real, OPS, 5>(dm, ee, ar, grid, block, lds, st);
+    case 6: return launch_tree_t<Real, OPS, 6>(dm, ee, ar, grid, block, lds, st);
+    default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((tree_kernel<Real, OPS>), dim3(grid), dim3(block), lds, st, dm, ee, ar);
+}
+
+template <class Real, int LOGT>
+static hipError_t launch_aba_t(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds,
+                               hipStream_t st) {
+  hipError_t e = raise_lds(aba_kernel<Real, LOGT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((aba_kernel<Real, LOGT>), dim3(grid), dim3(block), lds, st, dm, ar);
   return hipGetLastError();
 }
 
 template <class Real>
 hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds, hipStream_t st) {
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)aba_kernel<Real>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
+  switch (ar.logT) {
+    case 3: return launch_aba_t<Real, 3>(dm, ar, grid, block, lds, st);
+    case 4: return launch_aba_t<Real, 4>(dm, ar, grid, block, lds, st);
+    case 5: return launch_aba_t<Real, 5>(dm, ar, grid, block, lds, st);
+    case 6: return launch_aba_t<Real, 6>(dm, ar, grid, block, lds, st);
+    default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((aba_kernel<Real>), dim3(grid), dim3(block), lds, st, dm, ar);
-  return hipGetLastError();
 }
 
 #define BARD_INST(R)                                                                                              \

@@ -36,4 +36,103 @@ hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar
 template <class Real>
 hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds, hipStream_t st);
 
+__host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
+
+// Layout of the model's table image.  The device keeps one image per scalar
+// type laid out exactly as the workgroup wants it in LDS, so staging is a
+// single copy of 16-byte chunks.  mtab comes last so kernels that do not need
+// it copy only the prefix.
+struct TabLayout {
+  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, mtab, end_nomtab, end;
+};
+
+__host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kmax, int nv, int rs) {
+  TabLayout t{};
+  int off = 0;
+  auto take = [&](int bytes) {
+    int at = off;
+    off = lds_align(off + bytes);
+    return at;
+  };
+  t.cst = take(n * CST * rs);
+  t.meta = take(n * 16);
+  t.sbody = take(depth * P * 2);
+  t.ssrc = take(depth * P);
+  t.cslot = take(depth * P * kmax);
+  t.linfo = take(depth * 2 * 4);
+  t.bm2 = take(n * 16);    // per body {preorder position, subtree size, v index, dofs}
+  t.dlist = take(n * 4);   // bodies by decreasing subtree size
+  t.end_nomtab = off;
+  t.mtab = take(nv * nv * 4);
+  t.end = off;
+  return t;
+}
+
+// Byte size of an end-effector image: jrow [n_ee*6*nv] then ee_body [n_ee].
+__host__ __device__ inline int ee_image_bytes(int n_ee, int nv) {
+  return lds_align(n_ee * 6 * nv * 4) + lds_align(n_ee * 4);
+}
+
+// Padding (in elements) added to the stride of every per-dof and per-body
+// block of rows.  A row holds one scalar of the T instances of a tile; with
+// FP32 and T = 16 a 64-lane access touches four blocks at once and unpadded
+// block strides are multiples of the 32 LDS banks.
+__host__ __device__ constexpr int block_pad(int T, int rs) { return (rs == 4 && T == 16) ? 16 : 0; }
+
+// Byte offsets of the regions a workgroup stages in LDS.  Computed by the same
+// function on the host (to size the launch) and in the kernels.  Per-dof
+// blocks (s, fc) hold 6 rows and get one extra all-zero block (index nv) that
+// structural zeros of the dense outputs read, so the output loops need no
+// branches.  Per-body blocks hold 24 rows (R, p, v, a after the sweep; f and
+// the world inertia after the body phase) and are indexed by preorder position
+// so every subtree is a contiguous range.
+struct LdsPlan {
+  int q, qd, qdd, tin;        // input tiles [K][T]
+  int s, fc, body, o, pe;     // tree-kernel state
+  int c, ia, pa, u;           // ABA state
+  int tab;                    // table image
+  int tab_bytes;              // bytes of the image this kernel stages
+  int ee;                     // end-effector image
+  int total;
+};
+
+// kind: 0 = tree kernel with op mask `ops`, 1 = ABA kernel.
+__host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, int nv, int n_ee, int frame, int T,
+                                            int rs, int P, int depth, int kmax) {
+  LdsPlan L{};
+  int off = 0;
+  auto take = [&](int bytes) {
+    int at = off;
+    off = lds_align(off + bytes);
+    return at;
+  };
+  const int pad = block_pad(T, rs);
+  const bool vel = kind == 1 || (ops & OP_RNEA);
+  L.q = take(nq * T * rs);
+  L.qd = vel ? take(nv * T * rs) : off;
+  L.qdd = (kind == 0 && (ops & OP_RNEA)) ? take(nv * T * rs) : off;
+  L.tin = (kind == 1) ? take(nv * T * rs) : off;
+  if (kind == 0) {
+    const bool need_s = ops & (OP_JAC | OP_RNEA | OP_CRBA);
+    const bool need_body = ops & (OP_FK | OP_RNEA | OP_CRBA);
+    L.s = need_s ? take((nv + 1) * (6 * T + pad) * rs) : off;
+    L.body = need_body ? take(n * (24 * T + pad) * rs) : off;
+    L.fc = (ops & OP_CRBA) ? take((nv + 1) * (6 * T + pad) * rs) : off;
+    L.o = take(3 * T * rs);
+    L.pe = ((ops & OP_JAC) && frame == 1) ? take(n_ee * 3 * T * rs) : off;
+  } else {
+    L.s = take(nv * 6 * T * rs);
+    L.c = take(n * 6 * T * rs);
+    L.ia = take(n * 21 * T * rs);
+    L.pa = take(n * 6 * T * rs);
+    L.u = take(n * 8 * T * rs);
+  }
+  const TabLayout tl = tab_layout(n, P, depth, kmax, nv, rs);
+  L.tab_bytes = (kind == 0 && (ops & OP_CRBA)) ? tl.end : tl.end_nomtab;
+  L.tab = take(L.tab_bytes);
+  L.ee = (kind == 0 && (ops & OP_JAC)) ? take(ee_image_bytes(n_ee, nv)) : off;
+  L.total = off;
+  return L;
+}
+
 }  // namespace bard

@@ -35,25 +35,21 @@ struct I4 {
   int x, y, z, w;
 };
 
-// Device view of a compiled model; a POD passed to kernels by value.
+// Device view of a compiled model; a POD passed to kernels by value.  The
+// tables live in two images (FP32 and FP64 constants) whose layout is
+// tab_layout() in launch.h; kernels copy them into LDS.
 struct DevModel {
-  const float* c32;          // [n][CST]
-  const double* c64;         // [n][CST]
-  const I4* meta;            // [n] {parent, joint type, q index, v index}
-  const int16_t* sched_body; // [depth][P]  body processed by each lane slot at each level, -1 idle
-  const int8_t* sched_src;   // [depth][P]  slot holding the parent's state after the previous level
-  const int8_t* child_slot;  // [depth][P][kmax] slots of the children at the next level, -1 pad
-  const int* level_info;     // [depth][2]  {number of children to gather, forward exchange needed}
-  const int* mtab;           // [nv*nv] mass-matrix entry source: (a << 16) | d, or -1 (structural zero)
+  const unsigned char* img32;
+  const unsigned char* img64;
   int n, nq, nv, depth, P, log2P, kmax, free_root;
   float g32[3];
   double g64[3];
 };
 
-// Per end-effector-set tables used by the Jacobian output.
+// Per end-effector-set image: jrow [n_ee*6*nv] (per output row: src dof |
+// row-in-block << 8 | ee << 12, src = nv for a structural zero) then ee_body.
 struct DevEE {
-  const int* jtab;     // [n_ee*nv] column source dof or -1
-  const int* ee_body;  // [n_ee]
+  const unsigned char* img;
   int n_ee;
 };
 
@@ -70,6 +66,7 @@ struct bard_model {
   int n = 0, nq = 0, nv = 0, depth = 0, P = 1, log2P = 0, kmax = 0;
   bool free_root = false;
   std::vector<int> parent, jtype, qi, vi, nvi, level_of, slot_of;
+  std::vector<int> dfs, sub_size, dlist;  // preorder position, subtree size, bodies by subtree size
   std::vector<double> axis, xtree, inertia;
   double g[3] = {0.0, 0.0, -9.81};
   std::vector<double> cst64;
@@ -85,6 +82,6 @@ struct bard_model {
 namespace bard {
 // Host-side compile of a model (compiler.cpp).  Returns a bard_status.
 int compile_model(bard_model* m, std::string* err);
-// Column-source table of the Jacobian for a set of end effectors.
+// Per-row source table of the dense Jacobian output for a set of end effectors.
 std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee);
 }  // namespace bard
