@@ -54,23 +54,24 @@ def make_sets(torch, tree, B, nsets, seed):
 
 
 def time_calls(torch, calls, steps, warmup):
-    """Warm up, then time exactly `steps` calls; per-launch HIP events on the
-    launch stream give the kernel time, the host clock the step rate."""
+    """Warm up, then time exactly `steps` back-to-back calls.  One pair of HIP
+    events on the launch stream brackets the timed region (events between
+    launches would add work to every step); the host clock, bracketed by
+    device synchronisation, gives the step rate."""
     n = len(calls)
     for k in range(warmup):
         calls[k % n]()
-    st = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    en = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    st = torch.cuda.Event(enable_timing=True)
+    en = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    st.record()
     for k in range(steps):
-        st[k].record()
         calls[k % n]()
-        en[k].record()
+    en.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = [st[k].elapsed_time(en[k]) for k in range(steps)]
-    return wall, float(np.mean(kms)), float(np.median(kms))
+    return wall, st.elapsed_time(en) / steps
 
 
 def time_graph(torch, make_calls, replays):
@@ -184,10 +185,10 @@ def main():
         return [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
     calls = make_calls()
 
-    wall, kavg, kmed = time_calls(torch, calls, args.steps, args.warmup)
+    wall, kavg = time_calls(torch, calls, args.steps, args.warmup)
     value = B * args.steps / wall
     achieved = per_call / (kavg * 1e-3) / 1e9
-    log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us (median {kmed*1e3:.2f} us)")
+    log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us")
     parity = parity_sample(tree, sets)
     log(f"[bench] parity {parity}")
 
@@ -199,17 +200,17 @@ def main():
             plain.append((m.bind_rnea(d[0], d[1], d[2], o[0]), m.bind_crba(d[0], o[1]),
                           m.bind_jacobian(d[0], ee, o[2])))
         pcalls = [(lambda t=t: (t[0](), t[1](), t[2]())) for t in plain]
-        pw, pk, _ = time_calls(torch, pcalls, max(100, args.steps // 4), 10)
+        pw, pk = time_calls(torch, pcalls, max(100, args.steps // 4), 10)
         extra["plain_3_launches_evals_per_s"] = B * max(100, args.steps // 4) / pw
         extra["graph_replay_evals_per_s"] = B / time_graph(torch, make_calls, max(5, args.steps // nsets))
         # same buffers every call (working set in the Infinity Cache)
-        sw, sk, _ = time_calls(torch, calls[:1], max(100, args.steps // 4), 10)
+        sw, sk = time_calls(torch, calls[:1], max(100, args.steps // 4), 10)
         extra["same_buffers_kernel_us"] = sk * 1e3
         # larger batch
         B2 = 16384
         sets2 = make_sets(torch, tree, B2, max(4, math.ceil(512e6 / (bpe * B2))), 4002)
         calls2 = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets2]
-        w2, k2, _ = time_calls(torch, calls2, max(100, args.steps // 4), 10)
+        w2, k2 = time_calls(torch, calls2, max(100, args.steps // 4), 10)
         extra["batch16384_evals_per_s"] = B2 * max(100, args.steps // 4) / w2
         extra["batch16384_kernel_us"] = k2 * 1e3
         extra["batch16384_hbm_frac"] = bpe * B2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -220,7 +221,7 @@ def main():
         bpe_s = chain_bytes_per_eval(ts, len(ts.ee_bodies))
         sets3 = make_sets(torch, ts, B, max(14, math.ceil(512e6 / (bpe_s * B))), 5002)
         calls3 = [ms.bind_chain(d[0], d[1], d[2], ts.ee_bodies, tuple(o)) for (d, o, _) in sets3]
-        w3, k3, _ = time_calls(torch, calls3, args.steps, 10)
+        w3, k3 = time_calls(torch, calls3, args.steps, 10)
         extra["nv23_tree_evals_per_s"] = B * args.steps / w3
         extra["nv23_tree_kernel_us"] = k3 * 1e3
         del sets3, calls3

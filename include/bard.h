@@ -165,20 +165,37 @@ int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q
                void* M, void* J, const bard_layout* L, int64_t B, void* stream);
 
 /* ------------------------------------------------------------- adjoints ----
- * Vector-Jacobian products (the gradients Sec. 4.3 takes through RNEA).
- * rnea_vjp: given tau_bar, writes q_bar [nq], qd_bar [nv], qdd_bar [nv] per
- * instance and, if inertia_bar != NULL, the gradient with respect to the
- * [n_bodies][10] inertial parameters summed over the batch (a DEVICE array,
- * overwritten, reduced in a fixed order so results are run-to-run identical).
+ * Vector-Jacobian products: the gradients Sec. 4.3 takes through RNEA with
+ * respect to the state and the inertial parameters (system identification),
+ * and the FK gradient of the functional mode (Sec. 3.1).  Both run as one
+ * level sweep and subtree sums in the world frame (the gradient for q_j is
+ * s_j . W_j, W_j a sum over the subtree of body j), with no stored tape.
+ *
+ * rnea_vjp: given tau_bar, writes per instance q_bar = (dtau/dq)^T tau_bar
+ * [nq], qd_bar [nv] and qdd_bar [nv]; if inertia_bar != NULL, also the
+ * gradient with respect to the [n_bodies][10] inertial parameters (the layout
+ * of bard_model_create), summed over the batch.  inertia_bar is a dense
+ * DEVICE array of the call's dtype, overwritten; the batch sum is accumulated
+ * in FP64 in a fixed order (two stages: per-workgroup sums over a fixed grid,
+ * then a fixed-order sum of those), so results are identical run to run.
+ * inertia_override (nullable, device [n_bodies][10]) replaces the model's
+ * parameters as in bard_rnea.
  * Arrays (L order): q, qd, qdd, tau_bar in; q_bar, qd_bar, qdd_bar out
- * (inertia_bar is dense [n_bodies*10] and takes no layout).
- * Trees with a free joint return BARD_E_UNSUPPORTED. */
+ * (inertia_override and inertia_bar take no layout).
+ * Scratch: a call with inertia_bar != NULL uses a per-model, per-device FP64
+ * buffer of 2048 * n_bodies * 10 values, allocated on the first such call;
+ * such calls on one model and device must not overlap (different streams
+ * included).
+ * Errors: BARD_E_ARG (NULL array, bad stride), BARD_E_UNSUPPORTED (the tree
+ * has a free joint), BARD_E_NOMEM, BARD_E_CAPACITY, BARD_E_DEVICE. */
 int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* qd,
                   const void* qdd, const void* inertia_override, const void* tau_bar, void* q_bar,
                   void* qd_bar, void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B,
                   void* stream);
-/* fk_vjp: given poses_bar [n_bodies*12], writes q_bar [nq].
- * Arrays: q, poses_bar in; q_bar out.  Free joints: BARD_E_UNSUPPORTED. */
+/* fk_vjp: given poses_bar (per body the 3x4 row-major [R_bar | p_bar] of the
+ * bard_fk output), writes q_bar [nq] = (d poses / dq)^T poses_bar.
+ * Arrays (L order): q, poses_bar [n_bodies*12] in; q_bar out.
+ * Errors: as bard_rnea_vjp (free joints: BARD_E_UNSUPPORTED). */
 int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* poses_bar,
                 void* q_bar, const bard_layout* L, int64_t B, void* stream);
 

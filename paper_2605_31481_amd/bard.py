@@ -281,6 +281,38 @@ class Model:
                           _ptr(tau), _ptr(M), _ptr(J), L, B, _stream_ptr(q)), "bard_chain")
         return tau, M, J
 
+    # ----------------------------------------------------------- adjoints --
+    def rnea_vjp(self, q, qd, qdd, tau_bar, inertia=None, inertia_grad: bool = True, layout: str = "soa"):
+        """Reverse-mode product of RNEA: returns (q_bar, qd_bar, qdd_bar,
+        inertia_bar) for the cotangent tau_bar; inertia_bar is [n_bodies, 10],
+        summed over the batch (None if inertia_grad is False).  Fixed-base
+        trees only."""
+        B = _batch_of(q, self.nq, layout)
+        if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
+            raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
+        qb = _new(q, self.nq, B, layout)
+        qdb = _new(q, self.nv, B, layout)
+        qddb = _new(q, self.nv, B, layout)
+        pib = None
+        if inertia_grad:
+            torch = _torch()
+            alloc = torch.zeros if B == 0 else torch.empty  # the sum over an empty batch
+            pib = alloc((self.n_bodies, 10), dtype=q.dtype, device=q.device)
+        L = _layouts([q, qd, qdd, tau_bar, qb, qdb, qddb], layout)
+        _check(bard_rnea_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(tau_bar),
+                             _ptr(qb), _ptr(qdb), _ptr(qddb), _ptr(pib), L, B, _stream_ptr(q)), "bard_rnea_vjp")
+        return qb, qdb, qddb, pib
+
+    def fk_vjp(self, q, poses_bar, layout: str = "soa"):
+        """Reverse-mode product of FK: q_bar for the cotangent poses_bar (per
+        body 3x4 row-major [R | p]).  Fixed-base trees only."""
+        B = _batch_of(q, self.nq, layout)
+        qb = _new(q, self.nq, B, layout)
+        L = _layouts([q, poses_bar, qb], layout)
+        _check(bard_fk_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(poses_bar), _ptr(qb), L, B, _stream_ptr(q)),
+               "bard_fk_vjp")
+        return qb
+
     # ------------------------------------------------------- bound calls --
     def bind_chain(self, q, qd, qdd, ee: Sequence[int], out, frame: int = WORLD, layout: str = "soa"):
         """Marshal the arguments of one chain call once; the returned callable
@@ -341,3 +373,46 @@ class Model:
                 raise BardError(rc, "bard_jacobian")
             return keep
         return call
+
+
+# ------------------------------------------------------------------ autograd --
+class _RneaFn(torch.autograd.Function):
+    """tau = RNEA(q, qd, qdd; inertia) with gradients for q, qd, qdd and the
+    [n_bodies, 10] inertial parameters (summed over the batch)."""
+
+    @staticmethod
+    def forward(ctx, model, q, qd, qdd, inertia):
+        ctx.model = model
+        ctx.save_for_backward(q, qd, qdd, inertia)
+        return model.rnea(q, qd, qdd, inertia=inertia)
+
+    @staticmethod
+    def backward(ctx, tau_bar):
+        q, qd, qdd, inertia = ctx.saved_tensors
+        want_pi = inertia is not None and ctx.needs_input_grad[4]
+        qb, qdb, qddb, pib = ctx.model.rnea_vjp(q, qd, qdd, tau_bar.contiguous(), inertia=inertia,
+                                                inertia_grad=want_pi)
+        return None, qb, qdb, qddb, pib
+
+
+class _FkFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, model, q):
+        ctx.model = model
+        ctx.save_for_backward(q)
+        return model.fk(q)
+
+    @staticmethod
+    def backward(ctx, poses_bar):
+        (q,) = ctx.saved_tensors
+        return None, ctx.model.fk_vjp(q, poses_bar.contiguous())
+
+
+def rnea(model: Model, q, qd, qdd, inertia=None):
+    """Differentiable inverse dynamics on [K, B] (instance-minor) tensors."""
+    return _RneaFn.apply(model, q, qd, qdd, inertia)
+
+
+def fk(model: Model, q):
+    """Differentiable forward kinematics on [nq, B] tensors; returns [12 n_bodies, B]."""
+    return _FkFn.apply(model, q)

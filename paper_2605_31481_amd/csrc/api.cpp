@@ -84,6 +84,8 @@ std::vector<unsigned char> table_image(const bard_model* m, int rs) {
   for (int i = 0; i < m->n; ++i) bm2[i] = I4{m->dfs[i], m->sub_size[i], m->vi[i], m->nvi[i]};
   std::memcpy(&img[t.bm2], bm2.data(), bm2.size() * sizeof(I4));
   std::memcpy(&img[t.dlist], m->dlist.data(), m->dlist.size() * sizeof(int));
+  for (int k = 0; k < 4; ++k)
+    std::memcpy(&img[t.ulist + k * 8 * m->n * 4], m->ulist[k].data(), m->ulist[k].size() * sizeof(int));
   std::memcpy(&img[t.mtab], m->mtab.data(), m->mtab.size() * sizeof(int));
   return img;
 }
@@ -124,6 +126,7 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
   dm.log2P = m->log2P;
   dm.kmax = m->kmax;
   dm.free_root = m->free_root ? 1 : 0;
+  for (int k = 0; k < 4; ++k) dm.ulen[k] = (int)m->ulist[k].size();
   for (int k = 0; k < 3; ++k) {
     dm.g32[k] = (float)m->g[k];
     dm.g64[k] = m->g[k];
@@ -235,6 +238,8 @@ Args<Real> blank_args(int64_t B) {
   std::memset(&a, 0, sizeof(a));
   a.B = B;
   a.xcd_remap = 1;
+  const char* e = getenv("BARD_STREAM_OUT");
+  a.stream_out = e ? atoi(e) : 1;
   return a;
 }
 
@@ -288,6 +293,52 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_aba<Real>(dc->dm, ar, (int)grid, waves * 64, lds, st);
+  if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BARD_OK;
+}
+
+// Workgroups of an RNEA adjoint launch that returns the inertial-parameter
+// gradient: each loops over tiles and keeps its own FP64 sums, so the batch
+// reduction is two fixed-order stages and its buffer is bounded by the model.
+constexpr int kAdjGroups = 2048;
+
+int ensure_adj_partial(bard_model* m, DeviceCopy* dc) {
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (dc->adj_partial) return BARD_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, (size_t)kAdjGroups * m->n * 10 * sizeof(double)) != hipSuccess)
+    return fail(BARD_E_NOMEM, "hipMalloc of the adjoint reduction buffer failed");
+  dc->adj_partial = (double*)p;
+  return BARD_OK;
+}
+
+template <class Real, bool RNEA>
+int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t st) {
+  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
+  DeviceCopy* dc = nullptr;
+  int rc = ensure_device(m, &dc);
+  if (rc) return rc;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto bytes_for = [&](int T, int) {
+    return adj_plan(RNEA, m->n, m->nq, m->nv, T, (int)sizeof(Real), m->P, m->depth, m->kmax).total;
+  };
+  Shape sh = pick_shape(m, dev, bytes_for);
+  size_t lds = (size_t)bytes_for(sh.T, sh.log2P);
+  if (lds > lds_limit(dev)) return fail(BARD_E_CAPACITY, "model too large for on-chip staging");
+  ar.logT = sh.logT;
+  ar.log2P = sh.log2P;
+  ar.ntiles = (ar.B + sh.T - 1) / sh.T;
+  const int waves = std::max((sh.T << sh.log2P) >> 6, 4);
+  int64_t grid = ar.ntiles;
+  if (RNEA && inertia_bar) {
+    if ((rc = ensure_adj_partial(m, dc))) return rc;
+    ar.partial = dc->adj_partial;
+    grid = std::min<int64_t>(grid, kAdjGroups);
+  }
+  if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
+  hipError_t e = launch_adjoint<Real, RNEA>(dc->dm, ar, (int)grid, waves * 64, lds, st);
+  if (e == hipSuccess && ar.partial) e = launch_param_reduce<Real>(ar.partial, (int)grid, m->n * 10, inertia_bar, st);
   if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BARD_OK;
 }
@@ -409,6 +460,7 @@ int bard_model_destroy(bard_model_t m) {
     (void)hipSetDevice(d);
     (void)hipFree(dc.blob);
     for (auto& kv : dc.ee_sets) (void)hipFree(kv.second.first);
+    if (dc.adj_partial) (void)hipFree(dc.adj_partial);
   }
   if (cur >= 0) (void)hipSetDevice(cur);
   delete m;
@@ -581,15 +633,57 @@ int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, co
 int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
                   const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar, void* qdd_bar,
                   void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
-  (void)m; (void)dtype; (void)q; (void)qd; (void)qdd; (void)inertia_override; (void)tau_bar; (void)q_bar;
-  (void)qd_bar; (void)qdd_bar; (void)inertia_bar; (void)L; (void)B; (void)stream;
-  return fail(BARD_E_UNSUPPORTED, "rnea_vjp is not built yet");
+  int rc = common_checks(m, nullptr, dtype, B);
+  if (rc) return rc;
+  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
+  if (B == 0) return BARD_OK;
+  if (!q || !qd || !qdd || !tau_bar || !q_bar || !qd_bar || !qdd_bar) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    AdjArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.B = B;
+    a.q = (const R*)q;
+    a.qd = (const R*)qd;
+    a.qdd = (const R*)qdd;
+    a.tau_bar = (const R*)tau_bar;
+    a.pi_ovr = (const R*)inertia_override;
+    a.q_bar = (R*)q_bar;
+    a.qd_bar = (R*)qd_bar;
+    a.qdd_bar = (R*)qdd_bar;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
+        !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.stb_b, &a.stb_k) ||
+        !layout_of(L, 4, B, m->nq, &a.sqo_b, &a.sqo_k) || !layout_of(L, 5, B, m->nv, &a.sqdo_b, &a.sqdo_k) ||
+        !layout_of(L, 6, B, m->nv, &a.sqddo_b, &a.sqddo_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_adjoint<R, true>(m, a, (R*)inertia_bar, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
 int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* poses_bar, void* q_bar,
                 const bard_layout* L, int64_t B, void* stream) {
-  (void)m; (void)dtype; (void)q; (void)poses_bar; (void)q_bar; (void)L; (void)B; (void)stream;
-  return fail(BARD_E_UNSUPPORTED, "fk_vjp is not built yet");
+  int rc = common_checks(m, nullptr, dtype, B);
+  if (rc) return rc;
+  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
+  if (B == 0) return BARD_OK;
+  if (!q || !poses_bar || !q_bar) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    AdjArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.B = B;
+    a.q = (const R*)q;
+    a.poses_bar = (const R*)poses_bar;
+    a.q_bar = (R*)q_bar;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 12 * m->n, &a.spb_b, &a.spb_k) ||
+        !layout_of(L, 2, B, m->nq, &a.sqo_b, &a.sqo_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_adjoint<R, false>(m, a, nullptr, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
 int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch, uint32_t op_mask,

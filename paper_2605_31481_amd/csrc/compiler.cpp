@@ -224,6 +224,8 @@ int compile_model(bard_model* m, std::string* err) {
   std::stable_sort(m->dlist.begin(), m->dlist.end(),
                    [&](int a, int b) { return m->sub_size[a] > m->sub_size[b]; });
 
+  for (int k = 0; k < 4; ++k) m->ulist[k] = subtree_units(m, 1 << k);
+
   // ---- joint constants (eqs. (2)-(3)) and inertial parameters ----
   m->cst64.assign((size_t)n * CST, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -278,6 +280,20 @@ int compile_model(bard_model* m, std::string* err) {
       m->mtab[(size_t)r * m->nv + cc] = (a << 16) | d;
     }
   return BARD_OK;
+}
+
+std::vector<int> subtree_units(const bard_model* m, int U) {
+  std::vector<int> out;
+  std::vector<int> small;
+  for (int b : m->dlist) {
+    if (U > 1 && m->sub_size[b] > 2 * U)
+      for (int p = 0; p < U; ++p) out.push_back(b | (p << 8) | (U << 12));
+    else
+      small.push_back(b | (1 << 12));
+  }
+  out.insert(out.end(), small.begin(), small.end());
+  while (out.size() % U) out.push_back(-1);
+  return out;
 }
 
 std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee) {

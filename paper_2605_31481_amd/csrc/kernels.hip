@@ -32,233 +32,9 @@
 // coalesce.  Only the level sweep is serial over the tree.
 #include <hip/hip_runtime.h>
 
-#include "launch.h"
+#include "device.h"
 
 namespace bard {
-
-template <class Real> __device__ __forceinline__ const unsigned char* image(const DevModel& dm);
-template <> __device__ __forceinline__ const unsigned char* image<float>(const DevModel& dm) { return dm.img32; }
-template <> __device__ __forceinline__ const unsigned char* image<double>(const DevModel& dm) { return dm.img64; }
-template <class Real> __device__ __forceinline__ Real grav(const DevModel& dm, int k);
-template <> __device__ __forceinline__ float grav<float>(const DevModel& dm, int k) { return dm.g32[k]; }
-template <> __device__ __forceinline__ double grav<double>(const DevModel& dm, int k) { return dm.g64[k]; }
-
-__device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
-
-template <class Real>
-__device__ __forceinline__ Real xch(Real v, int src_lane) {
-  return __shfl(v, src_lane, 64);
-}
-
-// c = a * b for row-major 3x3.
-template <class Real>
-__device__ __forceinline__ void mul33(const Real* a, const Real* b, Real* c) {
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) c[3 * i + j] = a[3 * i] * b[j] + a[3 * i + 1] * b[3 + j] + a[3 * i + 2] * b[6 + j];
-}
-
-template <class Real>
-__device__ __forceinline__ void cross3(const Real* a, const Real* b, Real* c) {
-  c[0] = a[1] * b[2] - a[2] * b[1];
-  c[1] = a[2] * b[0] - a[0] * b[2];
-  c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// Spatial inertia of a body about the frame origin o, in world axes, from its
-// parameters about the body origin (m, h, I_O) and its pose (R, p) relative to o:
-//   h_w = R h + m p,
-//   I_w = R I_O R^T + m (|p|^2 1 - p p^T) + 2 (p . R h) 1 - p (R h)^T - (R h) p^T.
-// Output [m, h(3), Ixx, Ixy, Iyy, Ixz, Iyz, Izz].
-template <class Real>
-__device__ __forceinline__ void world_inertia(const Real* pi, const Real* R, const Real* p, Real* I0) {
-  const Real m = pi[0];
-  Real hr[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) hr[i] = R[3 * i] * pi[1] + R[3 * i + 1] * pi[2] + R[3 * i + 2] * pi[3];
-  const Real Ib[9] = {pi[4], pi[5], pi[7], pi[5], pi[6], pi[8], pi[7], pi[8], pi[9]};
-  Real X[9];
-  mul33(R, Ib, X);
-  // Y = X R^T (symmetric; six entries)
-  const Real yxx = X[0] * R[0] + X[1] * R[1] + X[2] * R[2];
-  const Real yxy = X[0] * R[3] + X[1] * R[4] + X[2] * R[5];
-  const Real yyy = X[3] * R[3] + X[4] * R[4] + X[5] * R[5];
-  const Real yxz = X[0] * R[6] + X[1] * R[7] + X[2] * R[8];
-  const Real yyz = X[3] * R[6] + X[4] * R[7] + X[5] * R[8];
-  const Real yzz = X[6] * R[6] + X[7] * R[7] + X[8] * R[8];
-  const Real pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
-  const Real ph = p[0] * hr[0] + p[1] * hr[1] + p[2] * hr[2];
-  const Real dg = m * pp + Real(2) * ph;
-  I0[0] = m;
-  I0[1] = hr[0] + m * p[0];
-  I0[2] = hr[1] + m * p[1];
-  I0[3] = hr[2] + m * p[2];
-  I0[4] = yxx + dg - p[0] * (m * p[0] + Real(2) * hr[0]);
-  I0[5] = yxy - p[0] * (m * p[1] + hr[1]) - hr[0] * p[1];
-  I0[6] = yyy + dg - p[1] * (m * p[1] + Real(2) * hr[1]);
-  I0[7] = yxz - p[0] * (m * p[2] + hr[2]) - hr[0] * p[2];
-  I0[8] = yyz - p[1] * (m * p[2] + hr[2]) - hr[1] * p[2];
-  I0[9] = yzz + dg - p[2] * (m * p[2] + Real(2) * hr[2]);
-}
-
-// f = I m for a rigid-body inertia I = [m, h, Ibar] and motion m = [w; u]:
-//   f = [Ibar w + h x u; mass u - h x w].
-template <class Real>
-__device__ __forceinline__ void inertia_mul(const Real* I0, const Real* mv, Real* f) {
-  const Real* w = mv;
-  const Real* u = mv + 3;
-  const Real h[3] = {I0[1], I0[2], I0[3]};
-  Real hxu[3], hxw[3];
-  cross3(h, u, hxu);
-  cross3(h, w, hxw);
-  f[0] = I0[4] * w[0] + I0[5] * w[1] + I0[7] * w[2] + hxu[0];
-  f[1] = I0[5] * w[0] + I0[6] * w[1] + I0[8] * w[2] + hxu[1];
-  f[2] = I0[7] * w[0] + I0[8] * w[1] + I0[9] * w[2] + hxu[2];
-  f[3] = I0[0] * u[0] - hxw[0];
-  f[4] = I0[0] * u[1] - hxw[1];
-  f[5] = I0[0] * u[2] - hxw[2];
-}
-
-// Motion cross product a x b = [wa x wb; wa x ub + ua x wb].
-template <class Real>
-__device__ __forceinline__ void crm(const Real* a, const Real* b, Real* c) {
-  Real t0[3], t1[3];
-  cross3(a, b, c);
-  cross3(a, b + 3, t0);
-  cross3(a + 3, b, t1);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) c[3 + k] = t0[k] + t1[k];
-}
-
-// Force cross product v x* f = [w x n + u x f; w x f].
-template <class Real>
-__device__ __forceinline__ void crf(const Real* v, const Real* f, Real* c) {
-  Real t0[3], t1[3];
-  cross3(v, f, t0);
-  cross3(v + 3, f + 3, t1);
-  cross3(v, f + 3, c + 3);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) c[k] = t0[k] + t1[k];
-}
-
-__device__ __forceinline__ int tile_index(int xcd_remap) {
-  // Consecutive instance tiles go to the same XCD (workgroups are dealt to the
-  // 8 XCDs round-robin), so partial cache lines of neighbouring tiles meet in
-  // one L2.
-  int bid = blockIdx.x;
-  if (!xcd_remap) return bid;
-  int nb = gridDim.x;
-  int per = nb >> 3;
-  int full = per << 3;
-  if (bid >= full) return bid;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-// --------------------------------------------------------------------------
-// Workgroup staging.
-// --------------------------------------------------------------------------
-// Copy `bytes` (a multiple of 16) from global to LDS in 16-byte chunks.
-__device__ __forceinline__ void copy16(unsigned char* dst, const unsigned char* src, int bytes, int tid, int nt) {
-  const int4* s = reinterpret_cast<const int4*>(src);
-  int4* d = reinterpret_cast<int4*>(dst);
-  const int n16 = bytes >> 4;
-#pragma unroll 4
-  for (int i = tid; i < n16; i += nt) d[i] = s[i];
-}
-
-// Input tile [K][T] from a strided array; instances past B repeat the last one.
-template <class Real, int LOGT>
-__device__ __forceinline__ void stage_input(const Real* src, int64_t sb, int64_t sk, int K, int64_t tile0, int64_t B,
-                                            Real* dst, int tid, int nt) {
-  constexpr int T = 1 << LOGT;
-#pragma unroll 8
-  for (int i = tid; i < K * T; i += nt) {
-    const int k = i >> LOGT;
-    int64_t b = tile0 + (i & (T - 1));
-    if (b >= B) b = B - 1;
-    dst[i] = src[b * sb + (int64_t)k * sk];
-  }
-}
-
-// Free-root pose from [x y z qx qy qz qw]: R = R0 R(quat), position R0 p + t0.
-template <class Real>
-__device__ __forceinline__ void free_root_pose(const Real* c, const Real* qv, Real* Rw, Real* o) {
-  Real qx = qv[3], qy = qv[4], qz = qv[5], qw = qv[6];
-  const Real inv = Real(1) / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
-  qx *= inv; qy *= inv; qz *= inv; qw *= inv;
-  const Real Rq[9] = {Real(1) - Real(2) * (qy * qy + qz * qz), Real(2) * (qx * qy - qz * qw), Real(2) * (qx * qz + qy * qw),
-                      Real(2) * (qx * qy + qz * qw), Real(1) - Real(2) * (qx * qx + qz * qz), Real(2) * (qy * qz - qx * qw),
-                      Real(2) * (qx * qz - qy * qw), Real(2) * (qy * qz + qx * qw), Real(1) - Real(2) * (qx * qx + qy * qy)};
-  mul33(c + C_R0, Rq, Rw);
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-    o[i] = c[C_R0 + 3 * i] * qv[0] + c[C_R0 + 3 * i + 1] * qv[1] + c[C_R0 + 3 * i + 2] * qv[2] + c[C_T0 + i];
-}
-
-// One joint step: parent pose (Rw, pw) -> body pose, and the body's motion
-// subspace s = [u; p x u] (revolute) or [0; u] (prismatic), u = R axis.
-template <class Real>
-__device__ __forceinline__ void joint_step(const Real* c, bool rev, Real qv, Real* Rw, Real* pw, Real* s) {
-  // eqs. (4)-(5): R_pc = R0 + sin q A + (1 - cos q) B ; t_pc = t0 (+ q d for a prismatic joint)
-  Real sq, cq;
-  sincos_r(qv, &sq, &cq);
-  const Real omc = Real(1) - cq;
-  Real Rpc[9], tpc[3], Rn[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Rpc[k] = c[C_R0 + k] + sq * c[C_A + k] + omc * c[C_B + k];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) tpc[k] = c[C_T0 + k] + qv * c[C_D + k];
-  mul33(Rw, Rpc, Rn);
-  Real pn[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) pn[i] = Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2] + pw[i];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) pw[k] = pn[k];
-  // motion subspace in the base frame = direct Jacobian column (eq. (7))
-  Real u[3], pxu[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * c[C_AX] + Rw[3 * i + 1] * c[C_AX + 1] + Rw[3 * i + 2] * c[C_AX + 2];
-  cross3(pw, u, pxu);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    s[i] = rev ? u[i] : Real(0);
-    s[3 + i] = rev ? pxu[i] : u[i];
-  }
-}
-
-// Views of the staged table image.
-template <class Real>
-struct Tables {
-  const Real* cst;
-  const I4* meta;
-  const int16_t* sbody;
-  const int8_t* ssrc;
-  const int8_t* cslot;
-  const int* linfo;
-  const I4* bm2;
-  const int* dlist;
-  const int* mtab;
-};
-
-template <class Real>
-__device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const DevModel& dm) {
-  const TabLayout t = tab_layout(dm.n, dm.P, dm.depth, dm.kmax, dm.nv, (int)sizeof(Real));
-  Tables<Real> v;
-  v.cst = reinterpret_cast<const Real*>(base + t.cst);
-  v.meta = reinterpret_cast<const I4*>(base + t.meta);
-  v.sbody = reinterpret_cast<const int16_t*>(base + t.sbody);
-  v.ssrc = reinterpret_cast<const int8_t*>(base + t.ssrc);
-  v.cslot = reinterpret_cast<const int8_t*>(base + t.cslot);
-  v.linfo = reinterpret_cast<const int*>(base + t.linfo);
-  v.bm2 = reinterpret_cast<const I4*>(base + t.bm2);
-  v.dlist = reinterpret_cast<const int*>(base + t.dlist);
-  v.mtab = reinterpret_cast<const int*>(base + t.mtab);
-  return v;
-}
 
 // --------------------------------------------------------------------------
 // FK / Jacobian / RNEA / CRBA and their fusion (OPS bit mask).
@@ -275,7 +51,8 @@ __device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const 
 // dependencies, and sums are taken in a fixed order (deterministic results).
 // --------------------------------------------------------------------------
 template <class Real, int OPS, int LOGT>
-__global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
+__device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, const Args<Real>& ar,
+                                          const int64_t tile) {
   constexpr bool FK = OPS & OP_FK;
   constexpr bool JAC = OPS & OP_JAC;
   constexpr bool RNEA = OPS & OP_RNEA;
@@ -293,7 +70,6 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
   const LdsPlan L = lds_plan(0, OPS, n, dm.nq, nv, ee.n_ee, ar.frame, T, (int)sizeof(Real), dm.P, dm.depth,
                              dm.kmax);
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t tile = tile_index(ar.xcd_remap);
   const int64_t tile0 = tile * T;
   const bool full = tile0 + T <= ar.B;
 
@@ -419,12 +195,45 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
         for (int i = 0; i < 3; ++i) o_l[i * T + inst] = Real(0);
     }
 
-    for (int l = lstart; l < dm.depth; ++l) {
+    // Everything a level needs except the carried link state is loaded one
+    // level ahead, so its LDS latency overlaps the previous level's arithmetic.
+    struct LevelIn {
+      Real c[36];  // R0, A, B, t0, axis, d
+      Real q, qd, qdd;
+      int bb, act, src, parent, rev, vi, pos;
+    };
+    auto load_level = [&](int l, LevelIn& L) {
       const int body = in_sched ? tb.sbody[l * P + slot] : -1;
-      const bool act = body >= 0;
-      const int bb = act ? body : 0;
+      L.act = body >= 0;
+      L.bb = L.act ? body : 0;
+      L.src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
+      const I4 meta = tb.meta[L.bb];
+      L.parent = meta.x;
+      L.rev = meta.y == J_REV;
+      L.vi = meta.w;
+      L.pos = tb.bm2[L.bb].x;
+      L.q = qi_l[meta.z * T];
+      if (VEL) {
+        L.qd = qdi_l[meta.w * T];
+        L.qdd = qddi_l[meta.w * T];
+      }
+      const Real* c = tb.cst + L.bb * CST;
+#pragma unroll
+      for (int k = 0; k < 36; ++k) L.c[k] = c[k];
+    };
+    // FP64 keeps one level in registers (two would spill).
+    constexpr bool AHEAD = sizeof(Real) == 4;
+    LevelIn cur;
+    if (AHEAD && lstart < dm.depth) load_level(lstart, cur);
+    for (int l = lstart; l < dm.depth; ++l) {
+      LevelIn nxt;
+      if (AHEAD) {
+        if (l + 1 < dm.depth) load_level(l + 1, nxt);
+      } else {
+        load_level(l, cur);
+      }
       if (tb.linfo[2 * l + 1]) {
-        const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
+        const int src = cur.src;
 #pragma unroll
         for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
@@ -437,8 +246,7 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
           }
         }
       }
-      const I4 meta = tb.meta[bb];
-      if (meta.x < 0) {  // attached to the world (level 0 of a fixed base)
+      if (cur.parent < 0) {  // attached to the world (level 0 of a fixed base)
 #pragma unroll
         for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
 #pragma unroll
@@ -450,32 +258,45 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
         }
       }
       Real s[6];
-      joint_step(tb.cst + bb * CST, meta.y == J_REV, qi_l[meta.z * T], Rw, pw, s);
+      joint_step(cur.c, cur.rev, cur.q, Rw, pw, s);
       if (VEL) {
-        const Real qdv = qdi_l[meta.w * T], qddv = qddi_l[meta.w * T];
         Real vJ[6], cJ[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
+        for (int k = 0; k < 6; ++k) vJ[k] = s[k] * cur.qd;
         crm(v, vJ, cJ);  // v_parent x (s qd)
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          a[k] = a[k] + s[k] * qddv + cJ[k];
+          a[k] = a[k] + s[k] * cur.qdd + cJ[k];
           v[k] = v[k] + vJ[k];
         }
       }
-      if (act) {
+      if (cur.act) {
         if (NEED_S) {
-          Real* sr = s_l + meta.w * SD + inst;
+          Real* sr = s_l + cur.vi * SD + inst;
 #pragma unroll
           for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
         }
-        if (NEED_BODY) store_body(bb);
+        if (NEED_BODY) {
+          Real* br = body_l + cur.pos * SB + inst;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
+          if (VEL) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              br[(12 + k) * T] = v[k];
+              br[(18 + k) * T] = a[k];
+            }
+          }
+        }
         if (JAC && ar.frame == 1)
           for (int e = 0; e < ee.n_ee; ++e)
-            if (eeb_l[e] == bb)
+            if (eeb_l[e] == cur.bb)
 #pragma unroll
               for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
       }
+      if (AHEAD) cur = nxt;
     }
   }
 
@@ -526,38 +347,70 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
     __syncthreads();
 
     // ---------------- 4. subtree phase ----------------
-    for (int j = r0; j < n; j += rstep) {
-      const int bb = tb.dlist[j];
-      const I4 m2 = tb.bm2[bb];  // {preorder position, subtree size, v index, dofs}
-      Real F[6], Ic[10];
+    // A wave takes U = 64 / T work entries at a time (one row group of T lanes
+    // each).  Large subtrees come as U entries of one body, each summing a
+    // slice of its preorder range; the slices are combined with a butterfly
+    // over the row groups, which yields the same bits in every lane.
+    {
+      constexpr int U = 64 >> LOGT;
+      constexpr int ui = 6 - LOGT;
+      const int* ul = tb.ulist + ui * 8 * n;
+      const int nent = dm.ulen[ui];
+      const int rg = (tid >> LOGT) & (U - 1);
+      const int nw = nt >> 6;
+      for (int base = wave * U; base < nent; base += nw * U) {
+        const int code = ul[base + rg];
+        const bool valid = code >= 0;
+        const int bb = valid ? (code & 0xff) : 0;
+        const int part = (code >> 8) & 0xf;
+        const int np = valid ? ((code >> 12) & 0xf) : 1;
+        const bool split = ((ul[base] >> 12) & 0xf) > 1;  // same for the whole wave
+        const I4 m2 = tb.bm2[bb];  // {preorder position, subtree size, v index, dofs}
+        const int chunk = (m2.y + np - 1) / np;
+        const int c0 = part * chunk;
+        const int c1 = valid ? min(m2.y, c0 + chunk) : 0;
+        Real F[6], Ic[10];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) F[k] = Real(0);
+        for (int k = 0; k < 6; ++k) F[k] = Real(0);
 #pragma unroll
-      for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
-      const Real* br = body_l + m2.x * SB + in;
-      for (int c = 0; c < m2.y; ++c, br += SB) {
-        if (RNEA)
+        for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
+        const Real* br = body_l + (m2.x + c0) * SB + in;
+        for (int c = c0; c < c1; ++c, br += SB) {
+          if (RNEA)
 #pragma unroll
-          for (int k = 0; k < 6; ++k) F[k] += br[k * T];
-        if (CRBA)
+            for (int k = 0; k < 6; ++k) F[k] += br[k * T];
+          if (CRBA)
 #pragma unroll
-          for (int k = 0; k < 10; ++k) Ic[k] += br[(6 + k) * T];
-      }
-      for (int d = 0; d < m2.w; ++d) {
-        const Real* sr = s_l + (m2.z + d) * SD + in;
-        Real s[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
-        if (RNEA && bok) {
-          const Real t = s[0] * F[0] + s[1] * F[1] + s[2] * F[2] + s[3] * F[3] + s[4] * F[4] + s[5] * F[5];
-          ar.tau[bo * ar.st_b + (int64_t)(m2.z + d) * ar.st_k] = t;
+            for (int k = 0; k < 10; ++k) Ic[k] += br[(6 + k) * T];
         }
-        if (CRBA) {
-          Real fcv[6];
-          inertia_mul(Ic, s, fcv);
-          Real* fo = fc_l + (m2.z + d) * SD + in;
+        if (U > 1 && split) {
 #pragma unroll
-          for (int k = 0; k < 6; ++k) fo[k * T] = fcv[k];
+          for (int sh = T; sh < 64; sh <<= 1) {
+            if (RNEA)
+#pragma unroll
+              for (int k = 0; k < 6; ++k) F[k] += xch(F[k], lane ^ sh);
+            if (CRBA)
+#pragma unroll
+              for (int k = 0; k < 10; ++k) Ic[k] += xch(Ic[k], lane ^ sh);
+          }
+        }
+        if (!valid) continue;
+        for (int d = part; d < m2.w; d += np) {
+          const Real* sr = s_l + (m2.z + d) * SD + in;
+          Real s[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
+          if (RNEA && bok) {
+            const Real t = s[0] * F[0] + s[1] * F[1] + s[2] * F[2] + s[3] * F[3] + s[4] * F[4] + s[5] * F[5];
+            put(&ar.tau[bo * ar.st_b + (int64_t)(m2.z + d) * ar.st_k], t, ar.stream_out);
+          }
+          if (CRBA) {
+            Real fcv[6];
+            inertia_mul(Ic, s, fcv);
+            Real* fo = fc_l + (m2.z + d) * SD + in;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) fo[k * T] = fcv[k];
+          }
         }
       }
     }
@@ -573,11 +426,14 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
     const int NR = n * 12;
     Real* out = ar.poses + bo * ar.sp_b;
     for (int row = r0; row < NR; row += rstep) {
+      // pose element (r, c) of the 3x4 [R | p]; body rows hold R row-major, then p
       const int bb = row / 12;
       const int k = row - bb * 12;
-      Real val = body_l[tb.bm2[bb].x * SB + k * T + in];
-      if (k >= 9) val += o_l[(k - 9) * T + in];
-      out[(int64_t)row * ar.sp_k] = val;
+      const int r = k >> 2, c = k & 3;
+      const int src = (c == 3) ? 9 + r : 3 * r + c;
+      Real val = body_l[tb.bm2[bb].x * SB + src * T + in];
+      if (c == 3) val += o_l[r * T + in];
+      put(&out[(int64_t)row * ar.sp_k], val, ar.stream_out);
     }
   }
   if (CRBA) {
@@ -599,7 +455,7 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
       Real* o = out + (int64_t)row * ar.sM_k;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (row + u * rstep < NR) o[u * ostep] = val[u];
+        if (row + u * rstep < NR) put(&o[u * ostep], val[u], ar.stream_out);
     }
   }
   if (JAC) {
@@ -630,9 +486,26 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
       Real* o = out + (int64_t)row * ar.sJ_k;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (row + u * rstep < NR) o[u * ostep] = val[u];
+        if (row + u * rstep < NR) put(&o[u * ostep], val[u], ar.stream_out);
     }
   }
+}
+
+// One tree, one tile per workgroup.
+template <class Real, int OPS, int LOGT>
+__global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
+  tree_tile<Real, OPS, LOGT>(dm, ee, ar, tile_index(ar.xcd_remap));
+}
+
+// Several trees in one launch.  Workgroup b runs the work item
+// items[item0 + b] = {model, tile}; the items are sorted longest first, so the
+// hardware dispatcher, which hands out workgroups in order as slots free up,
+// acts as a longest-processing-time work queue.  Each model's tables, end
+// effectors and I/O arguments come from device arrays (uniform loads).
+template <class Real, int OPS, int LOGT>
+__global__ void __launch_bounds__(512) plan_kernel(PlanPtrs<Real> pp) {
+  const int2 it = pp.items[pp.item0 + blockIdx.x];
+  tree_tile<Real, OPS, LOGT>(pp.dm[it.x], pp.ee[it.x], pp.args[it.x], it.y);
 }
 
 // --------------------------------------------------------------------------
@@ -1044,6 +917,24 @@ hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar
   }
 }
 
+template <class Real, int OPS, int LOGT>
+static hipError_t launch_plan_t(const PlanPtrs<Real>& pp, int grid, int block, size_t lds, hipStream_t st) {
+  hipError_t e = raise_lds(plan_kernel<Real, OPS, LOGT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((plan_kernel<Real, OPS, LOGT>), dim3(grid), dim3(block), lds, st, pp);
+  return hipGetLastError();
+}
+
+template <class Real, int OPS>
+hipError_t launch_plan(const PlanPtrs<Real>& pp, int logT, int grid, int block, size_t lds, hipStream_t st) {
+  switch (logT) {
+    case 3: return launch_plan_t<Real, OPS, 3>(pp, grid, block, lds, st);
+    case 4: return launch_plan_t<Real, OPS, 4>(pp, grid, block, lds, st);
+    case 5: return launch_plan_t<Real, OPS, 5>(pp, grid, block, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class Real, int LOGT>
 static hipError_t launch_aba_t(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds,
                                hipStream_t st) {
@@ -1075,7 +966,12 @@ hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int bl
                                                hipStream_t);                                                      \
   template hipError_t launch_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(const DevModel&, const DevEE&, const Args<R>&,   \
                                                                  int, int, size_t, hipStream_t);                  \
-  template hipError_t launch_aba<R>(const DevModel&, const Args<R>&, int, int, size_t, hipStream_t);
+  template hipError_t launch_aba<R>(const DevModel&, const Args<R>&, int, int, size_t, hipStream_t);          \
+  template hipError_t launch_plan<R, OP_RNEA>(const PlanPtrs<R>&, int, int, int, size_t, hipStream_t);           \
+  template hipError_t launch_plan<R, OP_CRBA>(const PlanPtrs<R>&, int, int, int, size_t, hipStream_t);           \
+  template hipError_t launch_plan<R, OP_JAC>(const PlanPtrs<R>&, int, int, int, size_t, hipStream_t);            \
+  template hipError_t launch_plan<R, OP_RNEA | OP_CRBA | OP_JAC>(const PlanPtrs<R>&, int, int, int, size_t,      \
+                                                                 hipStream_t);
 
 BARD_INST(float)
 BARD_INST(double)

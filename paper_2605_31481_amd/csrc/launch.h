@@ -28,11 +28,26 @@ struct Args {
   int log2P;  // lanes per instance of this launch, log2 (>= the model's minimum)
   int frame;
   int xcd_remap;
+  int stream_out;  // 1: dense outputs use non-temporal (streaming) stores
 };
 
 template <class Real, int OPS>
 hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar, int grid, int block, size_t lds,
                        hipStream_t st);
+
+// Device arrays of a multi-tree launch: per model its tables, end effectors
+// and I/O arguments, and the work items {model, tile} of the launch starting
+// at item0 (one workgroup each).
+template <class Real>
+struct PlanPtrs {
+  const DevModel* dm;
+  const DevEE* ee;
+  const Args<Real>* args;
+  const int2* items;
+  int item0;
+};
+template <class Real, int OPS>
+hipError_t launch_plan(const PlanPtrs<Real>& pp, int logT, int grid, int block, size_t lds, hipStream_t st);
 template <class Real>
 hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds, hipStream_t st);
 
@@ -43,7 +58,7 @@ __host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
 // single copy of 16-byte chunks.  mtab comes last so kernels that do not need
 // it copy only the prefix.
 struct TabLayout {
-  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, mtab, end_nomtab, end;
+  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, ulist, mtab, end_nomtab, end;
 };
 
 __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kmax, int nv, int rs) {
@@ -62,6 +77,7 @@ __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kma
   t.linfo = take(depth * 2 * 4);
   t.bm2 = take(n * 16);    // per body {preorder position, subtree size, v index, dofs}
   t.dlist = take(n * 4);   // bodies by decreasing subtree size
+  t.ulist = take(4 * 8 * n * 4);  // subtree-phase work lists for 1, 2, 4, 8 row groups per wave
   t.end_nomtab = off;
   t.mtab = take(nv * nv * 4);
   t.end = off;
@@ -134,5 +150,68 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
   L.total = off;
   return L;
 }
+
+// ----------------------------------------------------------------------------
+// Reverse-mode kernels (adjoint.hip): FK and RNEA vector-Jacobian products.
+// ----------------------------------------------------------------------------
+template <class Real>
+struct AdjArgs {
+  const Real* q;
+  const Real* qd;
+  const Real* qdd;
+  const Real* tau_bar;
+  const Real* pi_ovr;
+  const Real* poses_bar;
+  Real* q_bar;
+  Real* qd_bar;
+  Real* qdd_bar;
+  double* partial;  // [gridDim.x][n][10] per-workgroup inertial-parameter gradients, or NULL
+  int64_t sq_b, sq_k, sqd_b, sqd_k, sqdd_b, sqdd_k, stb_b, stb_k, spb_b, spb_k;
+  int64_t sqo_b, sqo_k, sqdo_b, sqdo_k, sqddo_b, sqddo_k;
+  int64_t B, ntiles;
+  int logT;
+  int log2P;
+};
+
+// Rows of a per-body LDS block: RNEA adjoint 30 (R, p, v, a, phi after the
+// sweep), FK adjoint 12 (R, p).
+__host__ __device__ constexpr int adj_rows(bool rnea) { return rnea ? 30 : 12; }
+
+struct AdjPlan {
+  int q, qd, qdd, tb;  // input tiles [K][T]
+  int s, body;         // per-dof and per-body blocks
+  int acc;             // [n][10] FP64 inertial-parameter sums of the workgroup
+  int tab, tab_bytes, total;
+};
+
+__host__ __device__ inline AdjPlan adj_plan(bool rnea, int n, int nq, int nv, int T, int rs, int P, int depth,
+                                            int kmax) {
+  AdjPlan L{};
+  int off = 0;
+  auto take = [&](int bytes) {
+    int at = off;
+    off = lds_align(off + bytes);
+    return at;
+  };
+  const int pad = block_pad(T, rs);
+  L.q = take(nq * T * rs);
+  L.qd = rnea ? take(nv * T * rs) : off;
+  L.qdd = rnea ? take(nv * T * rs) : off;
+  L.tb = rnea ? take(nv * T * rs) : off;
+  L.s = take(nv * (6 * T + pad) * rs);
+  L.body = take(n * (adj_rows(rnea) * T + pad) * rs);
+  L.acc = rnea ? take(n * 10 * 8) : off;
+  L.tab_bytes = tab_layout(n, P, depth, kmax, nv, rs).end_nomtab;
+  L.tab = take(L.tab_bytes);
+  L.total = off;
+  return L;
+}
+
+template <class Real, bool RNEA>
+hipError_t launch_adjoint(const DevModel& dm, const AdjArgs<Real>& ar, int grid, int block, size_t lds,
+                          hipStream_t st);
+// out[i] = sum over g < groups of partial[g * count + i], in a fixed order.
+template <class Real>
+hipError_t launch_param_reduce(const double* partial, int groups, int count, Real* out, hipStream_t st);
 
 }  // namespace bard

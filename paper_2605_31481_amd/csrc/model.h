@@ -42,6 +42,7 @@ struct DevModel {
   const unsigned char* img32;
   const unsigned char* img64;
   int n, nq, nv, depth, P, log2P, kmax, free_root;
+  int ulen[4];  // entries of the subtree work lists for 1, 2, 4, 8 row groups per wave
   float g32[3];
   double g64[3];
 };
@@ -58,6 +59,7 @@ struct DeviceCopy {
   void* blob = nullptr;
   DevModel dm{};
   std::map<std::vector<int>, std::pair<void*, DevEE>> ee_sets;
+  double* adj_partial = nullptr;  // per-workgroup inertial-parameter sums of the RNEA adjoint
 };
 
 }  // namespace bard
@@ -67,6 +69,7 @@ struct bard_model {
   bool free_root = false;
   std::vector<int> parent, jtype, qi, vi, nvi, level_of, slot_of;
   std::vector<int> dfs, sub_size, dlist;  // preorder position, subtree size, bodies by subtree size
+  std::vector<int> ulist[4];              // subtree work lists (see subtree_units)
   std::vector<double> axis, xtree, inertia;
   double g[3] = {0.0, 0.0, -9.81};
   std::vector<double> cst64;
@@ -82,6 +85,10 @@ struct bard_model {
 namespace bard {
 // Host-side compile of a model (compiler.cpp).  Returns a bard_status.
 int compile_model(bard_model* m, std::string* err);
+// Subtree-phase work list for U row groups per wave: entries body | part << 8 |
+// parts << 12 (-1 = idle).  Bodies whose subtree exceeds 2U bodies come first
+// as U-entry groups, each aligned to a wave, so one wave splits the sum.
+std::vector<int> subtree_units(const bard_model* m, int U);
 // Per-row source table of the dense Jacobian output for a set of end effectors.
 std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee);
 }  // namespace bard

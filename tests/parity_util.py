@@ -75,9 +75,7 @@ def aba_backward_error(om, q, qd, tau, qdd_gpu, dtype):
 
 def fk_ref_blocks(om, q):
     T = om.fk(q)                       # [B, n, 3, 4]
-    B, n = T.shape[:2]
-    out = np.concatenate([T[:, :, :, :3].reshape(B, n, 9), T[:, :, :, 3]], axis=2)
-    return out                         # [B, n, 12]
+    return T.reshape(T.shape[0], T.shape[1], 12)
 
 
 def oracle_for(tree):

@@ -142,3 +142,24 @@ def test_workspace_capacity_checked_on_host():
     assert bard.bard_crba(m.handle, ws, 0, None, None, None, 0, 129, None) == -6
     assert bard.bard_crba(m.handle, ws, 1, None, None, None, 0, 16, None) == -1
     assert bard.bard_ws_destroy(ws) == 0
+
+
+def test_adjoint_argument_errors_without_device():
+    m = bard.Model.from_tree(synth.quadruped_spine())
+    h = m.handle
+    # B = 0 is a no-op
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 0, None) == 0
+    assert bard.bard_fk_vjp(h, 0, None, None, None, None, 0, None) == 0
+    # NULL arrays, bad dtype, negative batch
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 8, None) == -1
+    assert bard.bard_fk_vjp(h, 0, None, None, None, None, 8, None) == -1
+    assert bard.bard_fk_vjp(h, 3, None, None, None, None, 8, None) == -1
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, -2, None) == -1
+
+
+def test_adjoints_of_free_joint_trees_are_rejected():
+    m = bard.Model.from_tree(synth.humanoid_small())
+    h = m.handle
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 8, None) == -7
+    assert bard.bard_fk_vjp(h, 0, None, None, None, None, 8, None) == -7
+    assert "free joint" in bard.bard_last_error().decode()
