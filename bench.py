@@ -161,6 +161,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run 3 plain device-to-device copies of this many MiB (a kernel of known traffic "
+                         "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the batch would shard "
@@ -172,6 +175,14 @@ def main():
     from paper_2605_31481_amd import bard
 
     torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {args.copy_mib} MiB")
+        del src, dst
     tree = synth.humanoid_large()
     m = bard.Model.from_tree(tree)
     B = args.batch
