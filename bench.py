@@ -143,6 +143,91 @@ def cpu_baseline(tree, target_s=10.0, max_s=30.0):
                       f"{el:.1f} s on {threads} OpenMP threads"}
 
 
+def _rate(torch, calls, steps, warmup=10):
+    wall, kavg = time_calls(torch, calls, steps, warmup)
+    return wall / steps, kavg * 1e-3
+
+
+def bench_plan(torch, bard, steps):
+    """Five random trees (7, 11, 12, 18, 23 DOF; batches 512..8192 = 15,872
+    instances; RNEA + CRBA + tip Jacobians): one plan (graph replay) against
+    five separate chain launches."""
+    import synth
+    trees = synth.multi_trees()
+    batches = synth.MULTI_BATCHES
+    models = [bard.Model.from_tree(t) for t in trees]
+    plan = bard.Plan(models, batches)
+    ins = []
+    for k, (t, B) in enumerate(zip(trees, batches)):
+        q, qd, qdd = synth.random_state(t, B, 6000 + k)
+        ins.append(tuple(torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qdd)))
+    total = sum(batches)
+    nbytes = sum(4 * B * (t.nq + 3 * t.nv + t.nv * t.nv + 6 * t.nv * len(plan.ee(k)))
+                 for k, (t, B) in enumerate(zip(trees, batches)))
+    plan.run(ins)
+    plan.run(ins)
+    torch.cuda.synchronize()
+    n = max(50, steps // 4)
+    t_plan, k_plan = _rate(torch, [lambda: plan.run(ins)], n)
+    outs = [tuple(torch.empty((K, B), device="cuda") for K in (t.nv, t.nv * t.nv, 6 * t.nv * len(plan.ee(k))))
+            for k, (t, B) in enumerate(zip(trees, batches))]
+    sep = [m.bind_chain(i[0], i[1], i[2], plan.ee(k), o) for k, (m, i, o) in enumerate(zip(models, ins, outs))]
+    t_sep, k_sep = _rate(torch, [lambda: [c() for c in sep]], n)
+    return {"plan5_evals_per_s": total / t_plan, "plan5_gpu_us": k_plan * 1e6,
+            "plan5_hbm_frac": nbytes / k_plan / 1e9 / HBM_PEAK_GBS, "plan5_config": plan.config,
+            "separate5_evals_per_s": total / t_sep, "separate5_gpu_us": k_sep * 1e6}
+
+
+def bench_adjoints(torch, bard, steps):
+    """RNEA adjoint on the identification workload (11-DOF quadruped, 4096
+    trajectories x 200 steps = 819,200 instances, FP32) with the batch-summed
+    inertial-parameter gradient; FK adjoint at the same size."""
+    import synth
+    tree = synth.quadruped_spine()
+    m = bard.Model.from_tree(tree)
+    q, qd, qdd = synth.sinusoid_trajectories(tree, 4096, 200, seed=4242)
+    B = q.shape[0]
+    dev = [torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qdd)]
+    tb = torch.randn((tree.nv, B), device="cuda")
+    n = max(20, steps // 20)
+    t_v, k_v = _rate(torch, [lambda: m.rnea_vjp(dev[0], dev[1], dev[2], tb)], n, 3)
+    bytes_v = 4 * B * (tree.nq + 3 * tree.nv + tree.nq + 2 * tree.nv)
+    pb = torch.randn((12 * tree.n_bodies, B), device="cuda")
+    t_f, k_f = _rate(torch, [lambda: m.fk_vjp(dev[0], pb)], n, 3)
+    bytes_f = 4 * B * (tree.nq + 12 * tree.n_bodies + tree.nq)
+    return {"rnea_vjp_819200_evals_per_s": B / t_v, "rnea_vjp_819200_gpu_us": k_v * 1e6,
+            "rnea_vjp_819200_hbm_frac": bytes_v / k_v / 1e9 / HBM_PEAK_GBS,
+            "fk_vjp_819200_evals_per_s": B / t_f, "fk_vjp_819200_gpu_us": k_f * 1e6,
+            "fk_vjp_819200_hbm_frac": bytes_f / k_f / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_workspace(torch, bard, steps):
+    """FK, Jacobian, CRBA and RNEA on one q (36-DOF humanoid, B = 4096) as
+    four separate calls: without a workspace, and with the kinematics tier
+    (after one miss, every call is a hit)."""
+    import synth
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    B = 4096
+    q, qd, qdd = (torch.from_numpy(x.T.copy()).float().cuda() for x in synth.random_state(tree, B, 7000))
+    ee = tree.ee_bodies
+    outs = dict(fk=torch.empty((12 * tree.n_bodies, B), device="cuda"),
+                j=torch.empty((24 * tree.nv, B), device="cuda"),
+                M=torch.empty((tree.nv * tree.nv, B), device="cuda"), tau=torch.empty((tree.nv, B), device="cuda"))
+    ws = bard.Workspace(m, B)
+
+    def four(w):
+        m.fk(q, out=outs["fk"], ws=w)
+        m.jacobian(q, ee, out=outs["j"], ws=w)
+        m.crba(q, out=outs["M"], ws=w)
+        m.rnea(q, qd, qdd, out=outs["tau"], ws=w)
+    n = max(50, steps // 4)
+    t0, k0 = _rate(torch, [lambda: four(None)], n)
+    t1, k1 = _rate(torch, [lambda: four(ws)], n)
+    return {"four_ops_no_ws_gpu_us": k0 * 1e6, "four_ops_ws_hits_gpu_us": k1 * 1e6,
+            "four_ops_no_ws_evals_per_s": B / t0, "four_ops_ws_hits_evals_per_s": B / t1}
+
+
 def traffic_if_current():
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -236,6 +321,9 @@ def main():
         extra["nv23_tree_evals_per_s"] = B * args.steps / w3
         extra["nv23_tree_kernel_us"] = k3 * 1e3
         del sets3, calls3
+        extra.update(bench_plan(torch, bard, args.steps))
+        extra.update(bench_adjoints(torch, bard, args.steps))
+        extra.update(bench_workspace(torch, bard, args.steps))
         log(f"[bench] extra {extra}")
 
     cpu = None

@@ -115,15 +115,33 @@ int bard_model_joint_transform(bard_model_t model, int32_t body, const double* q
 int bard_model_destroy(bard_model_t model);
 
 /* ------------------------------------------------------------ workspace ----
- * A workspace owns the tiered cache of one stream (Sec. 3.1: poses, then
- * velocities, then bias forces, then M), sized for max_batch instances.
- * Operators accept ws == NULL (no caching).  Errors: BARD_E_ARG, BARD_E_NOMEM. */
+ * A workspace holds the cached kinematic state of one stream (Sec. 3.1's
+ * tiered lazy evaluation): for up to max_batch instances, the world pose of
+ * every body, every joint's motion subspace and the base origin, each
+ * component tagged with the q_tag it was computed for.  An operator called
+ * with ws != NULL and q_tag != 0 either
+ *   - loads these components instead of computing them, when every component
+ *     it needs was computed for the same q_tag and the same B (FK, Jacobian
+ *     and CRBA then skip the level sweep; RNEA keeps only the velocity and
+ *     acceleration propagation), or
+ *   - computes them and stores the components it computed under q_tag.
+ * bard_fk, bard_jacobian, bard_rnea and bard_crba use the workspace;
+ * bard_aba and bard_chain accept it for argument checks only.  Equal non-zero
+ * tags promise equal q contents; the library never inspects q to check.
+ * The tier (4 or 8 bytes x (12 n_bodies + 6 nv + 3) x max_batch) is allocated on
+ * the device of the first call that uses it; a workspace stays on that device
+ * and serves one stream at a time.
+ * Errors: BARD_E_ARG, BARD_E_NOMEM. */
 int bard_ws_create(bard_model_t model, bard_dtype dtype, int64_t max_batch, bard_ws_t* out);
 int bard_ws_destroy(bard_ws_t ws);
+/* policy 1 (default): store on a miss, load on a hit; 0: the workspace is not
+ * used (every call computes everything). */
+int bard_ws_set_policy(bard_ws_t ws, int32_t policy);
 
 /* ------------------------------------------------------------ operators ----
- * q_tag / qd_tag: caller version tags of q and qd for the cache; 0 = unknown
- * (always recompute).  Equal non-zero tags promise unchanged contents. */
+ * q_tag / qd_tag: caller version tags of q and qd for the workspace; 0 =
+ * unknown (always recompute).  qd-dependent state is always recomputed, so
+ * qd_tag is accepted but unused. */
 
 /* FK (world pose of every body, Sec. 3.1 tier 3).
  * Arrays (L order): q [nq] in, poses [n_bodies*12] out. */
@@ -200,17 +218,48 @@ int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void*
                 void* q_bar, const bard_layout* L, int64_t B, void* stream);
 
 /* ---------------------------------------------------- multi-tree plans ----
- * A plan batches several models with their own batch sizes into one
- * persistent launch over a work queue.  op_mask: bit 0 RNEA, bit 1 CRBA,
- * bit 2 Jacobian (their tip end effectors, see bard_plan_create).
- * io: per model 6 device pointers q, qd, qdd, tau, M, J (SoA layouts;
- * unused outputs may be NULL).  bard_plan_run captures the launch into a HIP
- * graph on first use and replays it afterwards. */
+ * A plan evaluates several models, each with its own batch size, in one
+ * launch over a list of work items (model, tile of instances): the paper's
+ * batching of heterogeneous trees whose small batches are launch-bound
+ * (Sec. 4.1, the multi-tree configuration).  Items are ordered longest first,
+ * so the hardware workgroup dispatcher, which hands out workgroups in order,
+ * acts as a longest-processing-time work queue.
+ *
+ * op_mask: bit 0 RNEA, bit 1 CRBA, bit 2 Jacobian.  The Jacobian of a model
+ * covers its tip end effectors: its leaves of greatest depth, at most four,
+ * ties to the lowest body index (bard_plan_ee lists them), in BARD_WORLD.
+ * io: per model 6 DEVICE pointers q, qd, qdd, tau, M, J, every array
+ * instance-minor [K][batch] (the default layout of the operators); pointers
+ * an op_mask does not need may be NULL.
+ * bard_plan_run: the first run of a configuration launches directly; later
+ * runs replay one HIP graph captured from it.  When io changes, the new
+ * pointers are copied to the plan's device descriptor in stream order, so the
+ * graph is never recaptured.  A plan runs on the device of its first run and
+ * on one stream at a time.  Preparing a configuration (first run, first run
+ * after bard_plan_configure or bard_plan_autotune) synchronizes the device.
+ * bard_plan_autotune: times every valid configuration (tile 8, 16 or 32 instances;
+ * fusion 0 = one launch for all models, 1 = one launch per model, 2 = one
+ * launch per operator; item order 0 = longest first, 1 = model order) on
+ * zero-filled scratch arrays for about budget_ms, keeps the fastest and
+ * records it in a JSON cache (file $BARD_TUNE_CACHE, else
+ * $HOME/.cache/bard_plan_tune.json) keyed by the GPU, dtype, op_mask, tree
+ * topologies and batches; bard_plan_create applies a cached choice.
+ * Errors: BARD_E_ARG, BARD_E_NOMEM, BARD_E_CAPACITY (a tree does not fit the
+ * tile's on-chip staging), BARD_E_DEVICE. */
 int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch,
                      uint32_t op_mask, bard_dtype dtype, bard_plan_t* out);
 int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms);
 int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream);
 int bard_plan_destroy(bard_plan_t plan);
+/* Pin a configuration (what bard_plan_autotune chooses): tile 8, 16 or 32,
+ * fusion 0..2, order 0..1 as above.  Fusion 0 and 1 need op_mask to be one
+ * operator or all three. */
+int bard_plan_configure(bard_plan_t plan, int32_t tile, int32_t fusion, int32_t order);
+/* Current configuration; from_cache = 1 if it came from the tuning cache. */
+int bard_plan_get_config(bard_plan_t plan, int32_t* tile, int32_t* fusion, int32_t* order,
+                         int32_t* from_cache);
+/* Tip end effectors of model `model_index` (ee_body: room for 4 entries). */
+int bard_plan_ee(bard_plan_t plan, int32_t model_index, int32_t* n_ee, int32_t* ee_body);
 
 #ifdef __cplusplus
 }

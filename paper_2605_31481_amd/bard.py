@@ -15,6 +15,7 @@ flattened row-major per instance (e.g. ``M`` is ``nv*nv`` per instance), and
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 import re
 from typing import Optional, Sequence
@@ -74,6 +75,7 @@ bard_model_joint_transform = _sig("bard_model_joint_transform", [_vp, _i32, _c_d
 bard_model_destroy = _sig("bard_model_destroy", [_vp])
 bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
 bard_ws_destroy = _sig("bard_ws_destroy", [_vp])
+bard_ws_set_policy = _sig("bard_ws_set_policy", [_vp, _i32])
 bard_fk = _sig("bard_fk", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
 bard_jacobian = _sig("bard_jacobian", [_vp, _vp, ctypes.c_int, _vp, _i32, _c_i32p, ctypes.c_int, _vp, _LP, _u64,
                                        _i64, _vp])
@@ -85,6 +87,16 @@ bard_chain = _sig("bard_chain", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _i32, _c
 bard_rnea_vjp = _sig("bard_rnea_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64,
                                        _vp])
 bard_fk_vjp = _sig("bard_fk_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
+bard_plan_create = _sig("bard_plan_create", [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64), ctypes.c_uint32,
+                                             ctypes.c_int, ctypes.POINTER(_vp)])
+bard_plan_autotune = _sig("bard_plan_autotune", [_vp, _vp, _i32])
+bard_plan_run = _sig("bard_plan_run", [_vp, ctypes.POINTER(_vp), _vp])
+bard_plan_destroy = _sig("bard_plan_destroy", [_vp])
+bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32])
+bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
+bard_plan_ee = _sig("bard_plan_ee", [_vp, _i32, _c_i32p, _c_i32p])
+
+PLAN_RNEA, PLAN_CRBA, PLAN_JACOBIAN = 1, 2, 4
 
 
 def declared_symbols() -> list:
@@ -175,6 +187,59 @@ def as_batch_major(t, *shape, layout: str = "soa"):
     return t.unflatten(1, shape)
 
 
+_tag_ids = itertools.count(1)
+
+
+def version_tag(t) -> int:
+    """A non-zero tag that changes whenever ``t`` is modified in place: an id
+    given to the tensor object on first use, combined with PyTorch's version
+    counter.  A new tensor (even at a recycled address) gets a new id."""
+    i = getattr(t, "_bard_tag_id", None)
+    if i is None:
+        i = next(_tag_ids)
+        t._bard_tag_id = i
+    return ((i & ((1 << 43) - 1)) << 20) | (t._version & 0xFFFFF)
+
+
+class Workspace:
+    """Cached kinematic state of one stream (bard_ws_*): operators called with
+    ``ws=`` reuse the poses and motion subspaces computed for an unchanged q."""
+
+    def __init__(self, model: "Model", max_batch: int, dtype=None, policy: int = 1):
+        torch = _torch()
+        dtype = dtype if dtype is not None else torch.float32
+        code = F32 if dtype == torch.float32 else F64
+        h = _vp()
+        _check(bard_ws_create(model.handle, code, int(max_batch), ctypes.byref(h)), "bard_ws_create")
+        self._h = h
+        self.model = model
+        self.set_policy(policy)
+
+    def set_policy(self, policy: int):
+        _check(bard_ws_set_policy(self._h, int(policy)), "bard_ws_set_policy")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            bard_ws_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ws_args(ws, q, q_tag):
+    if ws is None:
+        return None, 0
+    return ws.handle, (int(q_tag) if q_tag is not None else version_tag(q))
+
+
 class Model:
     """A compiled kinematic tree (see include/bard.h, bard_model_create)."""
 
@@ -228,37 +293,43 @@ class Model:
         return R.reshape(3, 3), t
 
     # ---------------------------------------------------------------- ops --
-    def fk(self, q, out=None, layout: str = "soa"):
+    def fk(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, 12 * self.n_bodies, B, layout)
         L = _layouts([q, out], layout)
-        _check(bard_fk(self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q)), "bard_fk")
+        wh, tag = _ws_args(ws, q, q_tag)
+        _check(bard_fk(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_fk")
         return out
 
-    def jacobian(self, q, ee: Sequence[int], frame: int = WORLD, out=None, layout: str = "soa"):
+    def jacobian(self, q, ee: Sequence[int], frame: int = WORLD, out=None, layout: str = "soa",
+                 ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
         out = out if out is not None else _new(q, 6 * self.nv * len(ee_a), B, layout)
         L = _layouts([q, out], layout)
-        _check(bard_jacobian(self._h, None, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, 0, B,
+        wh, tag = _ws_args(ws, q, q_tag)
+        _check(bard_jacobian(self._h, wh, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, tag, B,
                              _stream_ptr(q)), "bard_jacobian")
         return out
 
-    def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa"):
+    def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa", ws: Optional[Workspace] = None,
+             q_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv, B, layout)
         L = _layouts([q, qd, qdd, out], layout)
         if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
             raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
-        _check(bard_rnea(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
-                         0, 0, B, _stream_ptr(q)), "bard_rnea")
+        wh, tag = _ws_args(ws, q, q_tag)
+        _check(bard_rnea(self._h, wh, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
+                         tag, 0, B, _stream_ptr(q)), "bard_rnea")
         return out
 
-    def crba(self, q, out=None, layout: str = "soa"):
+    def crba(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv * self.nv, B, layout)
         L = _layouts([q, out], layout)
-        _check(bard_crba(self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q)), "bard_crba")
+        wh, tag = _ws_args(ws, q, q_tag)
+        _check(bard_crba(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_crba")
         return out
 
     def aba(self, q, qd, tau, out=None, layout: str = "soa"):
@@ -374,6 +445,92 @@ class Model:
             return keep
         return call
 
+
+
+class Plan:
+    """Several models with their own batch sizes in one launch (bard_plan_*).
+
+    ``run(inputs)`` takes per model a tuple (q, qd, qdd) of instance-minor
+    tensors and returns per model (tau, M, J) (entries the op mask does not
+    produce are None).  Output tensors are allocated once per plan and reused
+    by every run, so the replayed graph keeps writing to the same memory.
+    """
+
+    def __init__(self, models: Sequence[Model], batches: Sequence[int], op_mask: int = 7, dtype=None):
+        torch = _torch()
+        self.models = list(models)
+        self.batches = [int(b) for b in batches]
+        self.op_mask = int(op_mask)
+        self.dtype = dtype if dtype is not None else torch.float32
+        code = F32 if self.dtype == torch.float32 else F64
+        hs = (_vp * len(self.models))(*[m.handle for m in self.models])
+        bs = (_i64 * len(self.batches))(*self.batches)
+        h = _vp()
+        _check(bard_plan_create(hs, len(self.models), bs, self.op_mask, code, ctypes.byref(h)), "bard_plan_create")
+        self._h = h
+        self._outs = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            bard_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ee(self, i: int) -> list:
+        n = ctypes.c_int32()
+        buf = (ctypes.c_int32 * 4)()
+        _check(bard_plan_ee(self._h, int(i), ctypes.byref(n), buf), "bard_plan_ee")
+        return list(buf[:n.value])
+
+    def configure(self, tile: int, fusion: int, order: int = 0):
+        _check(bard_plan_configure(self._h, int(tile), int(fusion), int(order)), "bard_plan_configure")
+
+    @property
+    def config(self) -> dict:
+        t, f, o, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(bard_plan_get_config(self._h, ctypes.byref(t), ctypes.byref(f), ctypes.byref(o), ctypes.byref(c)),
+               "bard_plan_get_config")
+        return {"tile": t.value, "fusion": f.value, "order": o.value, "from_cache": bool(c.value)}
+
+    def autotune(self, budget_ms: int = 2000):
+        torch = _torch()
+        _check(bard_plan_autotune(self._h, _vp(torch.cuda.current_stream().cuda_stream), int(budget_ms)),
+               "bard_plan_autotune")
+
+    def _outputs(self, device):
+        torch = _torch()
+        if self._outs is None:
+            outs = []
+            for i, (m, B) in enumerate(zip(self.models, self.batches)):
+                ne = len(self.ee(i))
+                mk = lambda k: torch.empty((k, B), dtype=self.dtype, device=device)
+                outs.append((mk(m.nv) if self.op_mask & 1 else None,
+                             mk(m.nv * m.nv) if self.op_mask & 2 else None,
+                             mk(6 * m.nv * ne) if self.op_mask & 4 else None))
+            self._outs = outs
+        return self._outs
+
+    def run(self, inputs, stream=None):
+        torch = _torch()
+        if len(inputs) != len(self.models):
+            raise ValueError("one (q, qd, qdd) tuple per model")
+        dev = inputs[0][0].device
+        outs = self._outputs(dev)
+        ptrs = []
+        for (q, qd, qdd), (tau, M, J), m, B in zip(inputs, outs, self.models, self.batches):
+            for t, K in ((q, m.nq), (qd, m.nv), (qdd, m.nv)):
+                if t is not None and (tuple(t.shape) != (K, B) or not t.is_contiguous() or t.dtype != self.dtype):
+                    raise ValueError(f"plan inputs must be contiguous [{K}, {B}] tensors of {self.dtype}")
+            ptrs += [t.data_ptr() if t is not None else 0 for t in (q, qd, qdd, tau, M, J)]
+        io = (_vp * len(ptrs))(*ptrs)
+        st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        _check(bard_plan_run(self._h, io, _vp(st)), "bard_plan_run")
+        return outs
 
 # ------------------------------------------------------------------ autograd --
 class _RneaFn(torch.autograd.Function):

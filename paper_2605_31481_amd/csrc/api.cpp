@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "internal.h"
 #include "launch.h"
 #include "status.h"
 
@@ -28,15 +29,24 @@ struct Shape {
 
 }  // namespace bard
 
+// A workspace: the kinematics tier of one stream (Sec. 3.1's cached
+// kinematic state).  Each component (poses, motion subspaces, base origin)
+// records the q tag it was computed for; the tier is allocated on the first
+// call that uses it.
 struct bard_ws {
   bard_model* model;
   bard_dtype dtype;
   int64_t max_batch;
+  int policy = 1;  // 1: store on a miss and load on a hit; 0: off
+  void* kin = nullptr;
+  int dev = -1;
+  int64_t tier_B = -1;
+  uint64_t pose_tag = 0, s_tag = 0, o_tag = 0;
 };
 
 using namespace bard;
 
-namespace {
+namespace bard {
 
 int check_device_state() {
   hipError_t e = hipPeekAtLastError();
@@ -127,6 +137,8 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
   dm.kmax = m->kmax;
   dm.free_root = m->free_root ? 1 : 0;
   for (int k = 0; k < 4; ++k) dm.ulen[k] = (int)m->ulist[k].size();
+  dm.n_mpair = m->n_mpair;
+  dm.n_mzero = m->n_mzero;
   for (int k = 0; k < 3; ++k) {
     dm.g32[k] = (float)m->g[k];
     dm.g64[k] = m->g[k];
@@ -149,11 +161,12 @@ int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, D
     *out = it->second.second;
     return BARD_OK;
   }
-  std::vector<int> jt = jacobian_table(m, key);
+  int n_col = 0, n_zero = 0;
+  std::vector<int> jt = jacobian_table(m, key, &n_col, &n_zero);
   const int bytes = ee_image_bytes(n_ee, m->nv);
   std::vector<unsigned char> host(bytes, 0);
   std::memcpy(host.data(), jt.data(), jt.size() * sizeof(int));
-  std::memcpy(host.data() + lds_align((int)jt.size() * 4), key.data(), key.size() * sizeof(int));
+  std::memcpy(host.data() + lds_align(n_ee * 6 * m->nv * 4), key.data(), key.size() * sizeof(int));  // offset as in ee_image_bytes
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc failed");
   if (hipMemcpy(p, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -163,10 +176,28 @@ int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, D
   DevEE e;
   e.img = (const unsigned char*)p;
   e.n_ee = n_ee;
+  e.n_col = n_col;
+  e.n_zero = n_zero;
   dc->ee_sets[key] = {p, e};
   *out = e;
   return BARD_OK;
 }
+
+// Waves per workgroup for the phases after the level sweep (body, subtree,
+// dense outputs), which have no serial dependency and hide LDS latency with
+// more waves.
+int out_waves() {
+  const char* e = getenv("BARD_OUT_WAVES");
+  if (e) {
+    int w = atoi(e);
+    if (w >= 1 && w <= 8) return w;
+  }
+  return 8;
+}
+
+}  // namespace bard
+
+namespace {
 
 bool layout_of(const bard_layout* L, int idx, int64_t B, int64_t K, int64_t* sb, int64_t* sk) {
   if (!L) {
@@ -207,18 +238,6 @@ Shape pick_shape(const bard_model* m, int dev, PlanBytes bytes_for) {
   return Shape{waves, logT, T, log2P};
 }
 
-// Waves per workgroup for the phases after the level sweep (body, subtree,
-// dense outputs), which have no serial dependency and hide LDS latency with
-// more waves.
-int out_waves() {
-  const char* e = getenv("BARD_OUT_WAVES");
-  if (e) {
-    int w = atoi(e);
-    if (w >= 1 && w <= 8) return w;
-  }
-  return 8;
-}
-
 int common_checks(bard_model* m, bard_ws_t ws, int dtype, int64_t B) {
   if (!m) return fail(BARD_E_ARG, "model is NULL");
   if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "dtype must be BARD_F32 or BARD_F64");
@@ -243,11 +262,63 @@ Args<Real> blank_args(int64_t B) {
   return a;
 }
 
+// Decide how a launch uses the workspace's kinematics tier: load it when
+// every component the kernel needs was computed for q_tag on this batch,
+// else store what the kernel computes.  Returns the tag bookkeeping to apply
+// after a successful launch.
+struct TierUse {
+  int mode = 0;
+  bool pose = false, s = false;
+};
+
 template <class Real, int OPS>
-int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int frame, hipStream_t st) {
+int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, Args<Real>* ar, TierUse* tu) {
+  if (!ws || !ws->policy || q_tag == 0) return BARD_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (ws->kin && ws->dev != dev) return fail(BARD_E_ARG, "workspace used on another device");
+  if (!ws->kin) {
+    const size_t bytes = (size_t)kin_rows(m->n, m->nv) * ws->max_batch * sizeof(Real);
+    if (hipMalloc(&ws->kin, bytes) != hipSuccess) {
+      ws->kin = nullptr;
+      return fail(BARD_E_NOMEM, "hipMalloc of the workspace tier failed");
+    }
+    ws->dev = dev;
+  }
+  const bool need_body = OPS & (OP_FK | OP_RNEA | OP_CRBA);
+  const bool need_s = OPS & (OP_JAC | OP_RNEA | OP_CRBA);
+  const bool need_pose = need_body || ((OPS & OP_JAC) && frame == 1);
+  const bool same = ws->tier_B == B;
+  const bool hit = same && ws->o_tag == q_tag && (!need_pose || ws->pose_tag == q_tag) &&
+                   (!need_s || ws->s_tag == q_tag);
+  ar->kin = (Real*)ws->kin;
+  ar->kin_ld = ws->max_batch;
+  tu->mode = hit ? 2 : 1;
+  tu->pose = need_body;
+  tu->s = need_s;
+  ar->kin_mode = tu->mode;
+  return BARD_OK;
+}
+
+void commit_tier(bard_ws* ws, uint64_t q_tag, int64_t B, const TierUse& tu) {
+  if (tu.mode != 1) return;
+  if (ws->tier_B != B) {
+    ws->pose_tag = ws->s_tag = ws->o_tag = 0;
+    ws->tier_B = B;
+  }
+  if (tu.pose) ws->pose_tag = q_tag;
+  if (tu.s) ws->s_tag = q_tag;
+  ws->o_tag = q_tag;
+}
+
+template <class Real, int OPS>
+int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int frame, hipStream_t st,
+             bard_ws* ws = nullptr, uint64_t q_tag = 0) {
   DeviceCopy* dc = nullptr;
   int rc = ensure_device(m, &dc);
   if (rc) return rc;
+  TierUse tu;
+  if ((rc = plan_tier<Real, OPS>(m, ws, q_tag, ar.B, frame, &ar, &tu))) return rc;
   DevEE ee{nullptr, 0};
   if (OPS & OP_JAC) {
     rc = ensure_ee(m, dc, n_ee, ee_body, &ee);
@@ -271,6 +342,7 @@ int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, waves * 64, lds, st);
   if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (ws) commit_tier(ws, q_tag, ar.B, tu);
   return BARD_OK;
 }
 
@@ -482,7 +554,22 @@ int bard_ws_create(bard_model_t m, bard_dtype dtype, int64_t max_batch, bard_ws_
 
 int bard_ws_destroy(bard_ws_t w) {
   if (!w) return fail(BARD_E_ARG, "NULL workspace");
+  if (w->kin) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(w->dev);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(w->kin);
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
   delete w;
+  return BARD_OK;
+}
+
+int bard_ws_set_policy(bard_ws_t w, int32_t policy) {
+  if (!w) return fail(BARD_E_ARG, "NULL workspace");
+  if (policy != 0 && policy != 1) return fail(BARD_E_ARG, "policy must be 0 or 1");
+  w->policy = policy;
   return BARD_OK;
 }
 
@@ -490,8 +577,7 @@ int bard_ws_destroy(bard_ws_t w) {
 
 int bard_fk(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void* poses, const bard_layout* L,
             uint64_t q_tag, int64_t B, void* stream) {
-  (void)q_tag;
-  int rc = common_checks(m, ws, dtype, B);
+    int rc = common_checks(m, ws, dtype, B);
   if (rc) return rc;
   if (B == 0) return BARD_OK;
   if (!q || !poses) return fail(BARD_E_ARG, "NULL array");
@@ -503,7 +589,7 @@ int bard_fk(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void*
     a.poses = (R*)poses;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 12 * m->n, &a.sp_b, &a.sp_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_FK>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+    return run_tree<R, OP_FK>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
@@ -511,8 +597,7 @@ int bard_fk(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void*
 int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, int32_t n_ee,
                   const int32_t* ee_body, bard_frame frame, void* J, const bard_layout* L, uint64_t q_tag, int64_t B,
                   void* stream) {
-  (void)q_tag;
-  int rc = common_checks(m, ws, dtype, B);
+    int rc = common_checks(m, ws, dtype, B);
   if (rc) return rc;
   if (frame != BARD_WORLD && frame != BARD_LOCAL_WORLD_ALIGNED) return fail(BARD_E_ARG, "bad frame");
   if (n_ee < 1 || n_ee > BARD_MAX_EE || !ee_body) return fail(BARD_E_ARG, "n_ee must be in 1..16 with ee_body");
@@ -526,7 +611,7 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
     a.J = (R*)J;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 6 * m->nv * n_ee, &a.sJ_b, &a.sJ_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
+    return run_tree<R, OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
@@ -534,8 +619,7 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
 int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
               const void* inertia_override, void* tau, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
               int64_t B, void* stream) {
-  (void)q_tag;
-  (void)qd_tag;
+    (void)qd_tag;
   int rc = common_checks(m, ws, dtype, B);
   if (rc) return rc;
   if (B == 0) return BARD_OK;
@@ -552,15 +636,14 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
         !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.st_b, &a.st_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+    return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
 int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void* M, const bard_layout* L,
               uint64_t q_tag, int64_t B, void* stream) {
-  (void)q_tag;
-  int rc = common_checks(m, ws, dtype, B);
+    int rc = common_checks(m, ws, dtype, B);
   if (rc) return rc;
   if (B == 0) return BARD_OK;
   if (!q || !M) return fail(BARD_E_ARG, "NULL array");
@@ -572,7 +655,7 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
     a.M = (R*)M;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv * m->nv, &a.sM_b, &a.sM_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, (hipStream_t)stream);
+    return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
@@ -684,27 +767,6 @@ int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* pos
     return run_adjoint<R, false>(m, a, nullptr, (hipStream_t)stream);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
-}
-
-int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch, uint32_t op_mask,
-                     bard_dtype dtype, bard_plan_t* out) {
-  (void)models; (void)n_models; (void)batch; (void)op_mask; (void)dtype; (void)out;
-  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
-}
-
-int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms) {
-  (void)plan; (void)stream; (void)budget_ms;
-  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
-}
-
-int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream) {
-  (void)plan; (void)io; (void)stream;
-  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
-}
-
-int bard_plan_destroy(bard_plan_t plan) {
-  (void)plan;
-  return fail(BARD_E_UNSUPPORTED, "multi-tree plans are not built yet");
 }
 
 }  // extern "C"

@@ -257,28 +257,42 @@ int compile_model(bard_model* m, std::string* err) {
   m->cst32.resize(m->cst64.size());
   for (size_t k = 0; k < m->cst64.size(); ++k) m->cst32[k] = (float)m->cst64[k];
 
-  // ---- mass-matrix entry table: M[r][c] = s_a . (Ic_body(d) s_d), zeros read row nv ----
+  // ---- mass-matrix output lists ----
+  // Pairs: every dof pair (a, d) where body(a) is an ancestor of body(d), or
+  // the same body with a <= d; M[a][d] = M[d][a] = s_a . (Ic_body(d) s_d).
+  // Code a | d << 16.  Zeros: the row-major index of every other entry.
+  // Both lists share one region of nv*nv ints (pairs first); their lengths
+  // add up to nv*nv - n_pairs + nv <= nv*nv.
   std::vector<int> body_of(m->nv);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < m->nvi[i]; ++k) body_of[m->vi[i] + k] = i;
-  m->mtab.assign((size_t)m->nv * m->nv, -1);
+  std::vector<int> pairs, zeros;
   for (int r = 0; r < m->nv; ++r)
     for (int cc = 0; cc < m->nv; ++cc) {
-      int br = body_of[r], bc = body_of[cc];
-      int a = -1, d = -1;
+      const int br = body_of[r], bc = body_of[cc];
+      const bool related = br == bc || is_ancestor(m, br, bc) || is_ancestor(m, bc, br);
+      if (!related) {
+        zeros.push_back(r * m->nv + cc);
+        continue;
+      }
+      // record each unordered pair once, from the upper triangle of its (a, d) order
+      int a, d;
       if (br == bc) {
         a = std::min(r, cc);
         d = std::max(r, cc);
       } else if (is_ancestor(m, br, bc)) {
         a = r;
         d = cc;
-      } else if (is_ancestor(m, bc, br)) {
+      } else {
         a = cc;
         d = r;
       }
-      if (a < 0) a = d = m->nv;  // structural zero: both operands read the all-zero row
-      m->mtab[(size_t)r * m->nv + cc] = (a << 16) | d;
+      if (r == a && cc == d) pairs.push_back(a | (d << 16));
     }
+  m->n_mpair = (int)pairs.size();
+  m->n_mzero = (int)zeros.size();
+  m->mtab = pairs;
+  m->mtab.insert(m->mtab.end(), zeros.begin(), zeros.end());
   return BARD_OK;
 }
 
@@ -296,21 +310,27 @@ std::vector<int> subtree_units(const bard_model* m, int U) {
   return out;
 }
 
-std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee) {
-  // Row (e, r, c) of the [n_ee][6][nv] output is entry r of column c of end
-  // effector e's block.  Code: src dof | r << 8 | e << 12, with src = nv (the
-  // all-zero row) when dof c is not on the root path of e.
+std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee, int* n_cols, int* n_zeros) {
+  // Columns: every (end effector e, dof c) with c on the root path of e; the
+  // kernel writes its 6 rows from s_c.  Code c | e << 8.  Zeros: the index of
+  // every row (e, r, c) of the [n_ee][6][nv] output whose dof is off the path.
   const int nv = m->nv;
   std::vector<char> on(nv);
-  std::vector<int> t((size_t)ee.size() * 6 * nv);
+  std::vector<int> cols, zeros;
   for (size_t e = 0; e < ee.size(); ++e) {
     std::fill(on.begin(), on.end(), 0);
     for (int k = ee[e]; k >= 0; k = m->parent[k])
       for (int j = 0; j < m->nvi[k]; ++j) on[m->vi[k] + j] = 1;
+    for (int c = 0; c < nv; ++c)
+      if (on[c]) cols.push_back(c | ((int)e << 8));
     for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < nv; ++c) t[(e * 6 + r) * nv + c] = (on[c] ? c : nv) | (r << 8) | ((int)e << 12);
+      for (int c = 0; c < nv; ++c)
+        if (!on[c]) zeros.push_back(((int)e * 6 + r) * nv + c);
   }
-  return t;
+  *n_cols = (int)cols.size();
+  *n_zeros = (int)zeros.size();
+  cols.insert(cols.end(), zeros.begin(), zeros.end());
+  return cols;
 }
 
 }  // namespace bard

@@ -1,0 +1,24 @@
+// Host helpers of the C ABI shared by its translation units (not public).
+#pragma once
+
+#include <string>
+
+#include "launch.h"
+#include "status.h"
+
+namespace bard {
+
+// Record `msg` as the calling thread's last error and return `code`.
+int fail(int code, const std::string& msg);
+// BARD_E_DEVICE if an earlier asynchronous device error is pending (and clear it).
+int check_device_state();
+// Largest dynamic LDS allocation of one workgroup on device `dev`.
+size_t lds_limit(int dev);
+// Upload the model's tables to the current device (once per device).
+int ensure_device(bard_model* m, DeviceCopy** out);
+// Device image of the Jacobian output lists for an end-effector set (cached per set).
+int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out);
+// Waves per workgroup for the phases after the level sweep.
+int out_waves();
+
+}  // namespace bard

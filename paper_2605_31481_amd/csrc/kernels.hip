@@ -93,19 +93,51 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     for (int i = tid; i < 6 * T; i += nt) s_l[nv * SD + (i >> LOGT) * T + (i & (T - 1))] = Real(0);
   if (CRBA)
     for (int i = tid; i < 6 * T; i += nt) fc_l[nv * SD + (i >> LOGT) * T + (i & (T - 1))] = Real(0);
+  // A kinematics-tier hit stages the poses, motion subspaces and base origin
+  // computed by an earlier call on the same configurations; the level sweep
+  // then only propagates velocities and accelerations (or does not run).
+  const bool hit = ar.kin_mode == 2;
+  const int64_t kld = ar.kin_ld;
+  const int KP = 12 * n, KS = 6 * nv;
+  if (hit) {
+    const Real* kin = ar.kin;
+    if (NEED_BODY)
+      for (int i = tid; i < KP * T; i += nt) {
+        const int k = i >> LOGT, in = i & (T - 1);
+        const int64_t b = (tile0 + in < ar.B) ? tile0 + in : ar.B - 1;
+        body_l[(k / 12) * SB + (k % 12) * T + in] = kin[k * kld + b];
+      }
+    if (NEED_S)
+      for (int i = tid; i < KS * T; i += nt) {
+        const int k = i >> LOGT, in = i & (T - 1);
+        const int64_t b = (tile0 + in < ar.B) ? tile0 + in : ar.B - 1;
+        s_l[(k / 6) * SD + (k % 6) * T + in] = kin[(KP + k) * kld + b];
+      }
+    for (int i = tid; i < 3 * T; i += nt) {
+      const int k = i >> LOGT, in = i & (T - 1);
+      o_l[k * T + in] = kin[(KP + KS + k) * kld + ((tile0 + in < ar.B) ? tile0 + in : ar.B - 1)];
+    }
+  }
   __syncthreads();
 
   const Tables<Real> tb = tables<Real>(smem + L.tab, dm);
   const int* jrow = reinterpret_cast<const int*>(smem + L.ee);
   const int* eeb_l = jrow + lds_align(ee.n_ee * 6 * nv * 4) / 4;
+  if (JAC && hit && ar.frame == 1)  // end-effector origins from the staged tier
+    for (int i = tid; i < ee.n_ee * 3 * T; i += nt) {
+      const int r = i >> LOGT, in = i & (T - 1);
+      const int e = r / 3, c = r - 3 * e;
+      pe_l[i] = ar.kin[(12 * tb.bm2[eeb_l[e]].x + 9 + c) * kld + ((tile0 + in < ar.B) ? tile0 + in : ar.B - 1)];
+    }
 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int log2P = ar.log2P;
   const int WA = (T << log2P) >> 6;
+  const bool early_zero = nt > WA * 64;  // some waves are free during the sweep
 
   // ---------------- 2. level sweep ----------------
-  if (wave < WA) {
+  if (wave < WA && !(hit && !VEL)) {
     const int P = dm.P;
     const int iw = lane >> log2P;
     const int slot_raw = lane & ((1 << log2P) - 1);
@@ -138,9 +170,15 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       // Level 0 holds only the free root; every slot evaluates it, slot 0 stores.
       const bool act = (slot_raw == 0);
       Real qr[7], o[3];
+      if (hit) {
+        const Real* rr = body_l + tb.bm2[0].x * SB + inst;
 #pragma unroll
-      for (int k = 0; k < 7; ++k) qr[k] = qi_l[k * T];
-      free_root_pose(tb.cst, qr, Rw, o);
+        for (int k = 0; k < 9; ++k) Rw[k] = rr[k * T];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) qr[k] = qi_l[k * T];
+        free_root_pose(tb.cst, qr, Rw, o);
+      }
 #pragma unroll
       for (int i = 0; i < 3; ++i) pw[i] = Real(0);
       if (VEL) {
@@ -156,7 +194,15 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           a[3 + i] = a0[3 + i] + Rw[3 * i] * ab[0] + Rw[3 * i + 1] * ab[1] + Rw[3 * i + 2] * ab[2];
         }
       }
-      if (act) {
+      if (act && hit) {
+        Real* br = body_l + tb.bm2[0].x * SB + inst;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          br[(12 + k) * T] = v[k];
+          br[(18 + k) * T] = a[k];
+        }
+      }
+      if (act && !hit) {
         if (NEED_S) {
           // s columns: v_k -> [0; R e_k], w_k -> [R e_k; 0] (the root sits at the origin)
           Real* sr = s_l + inst;
@@ -190,7 +236,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         v[k] = Real(0);
         a[k] = a0[k];
       }
-      if (slot_raw == 0)
+      if (slot_raw == 0 && !hit)
 #pragma unroll
         for (int i = 0; i < 3; ++i) o_l[i * T + inst] = Real(0);
     }
@@ -217,9 +263,11 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         L.qd = qdi_l[meta.w * T];
         L.qdd = qddi_l[meta.w * T];
       }
-      const Real* c = tb.cst + L.bb * CST;
+      if (!hit) {
+        const Real* c = tb.cst + L.bb * CST;
 #pragma unroll
-      for (int k = 0; k < 36; ++k) L.c[k] = c[k];
+        for (int k = 0; k < 36; ++k) L.c[k] = c[k];
+      }
     };
     // FP64 keeps one level in registers (two would spill).
     constexpr bool AHEAD = sizeof(Real) == 4;
@@ -234,10 +282,12 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
       if (tb.linfo[2 * l + 1]) {
         const int src = cur.src;
+        if (!hit) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
+          for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pw[k] = xch(pw[k], src);
+          for (int k = 0; k < 3; ++k) pw[k] = xch(pw[k], src);
+        }
         if (VEL) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
@@ -258,7 +308,13 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         }
       }
       Real s[6];
-      joint_step(cur.c, cur.rev, cur.q, Rw, pw, s);
+      if (hit) {
+        const Real* sr = s_l + cur.vi * SD + inst;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
+      } else {
+        joint_step(cur.c, cur.rev, cur.q, Rw, pw, s);
+      }
       if (VEL) {
         Real vJ[6], cJ[6];
 #pragma unroll
@@ -271,17 +327,19 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         }
       }
       if (cur.act) {
-        if (NEED_S) {
+        if (NEED_S && !hit) {
           Real* sr = s_l + cur.vi * SD + inst;
 #pragma unroll
           for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
         }
         if (NEED_BODY) {
           Real* br = body_l + cur.pos * SB + inst;
+          if (!hit) {
 #pragma unroll
-          for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
+            for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
+            for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
+          }
           if (VEL) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
@@ -290,7 +348,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
             }
           }
         }
-        if (JAC && ar.frame == 1)
+        if (JAC && ar.frame == 1 && !hit)
           for (int e = 0; e < ee.n_ee; ++e)
             if (eeb_l[e] == cur.bb)
 #pragma unroll
@@ -298,9 +356,48 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
       if (AHEAD) cur = nxt;
     }
+  } else if (wave >= WA && (CRBA || JAC)) {
+    // The structural zeros of M and J depend on nothing the sweep computes:
+    // the waves the sweep leaves idle store them meanwhile.
+    const int tz = tid - WA * 64, nz = nt - WA * 64;
+    const int64_t b = tile0 + (tid & (T - 1));
+    if (b < ar.B) {
+      const int r0z = tz >> LOGT, rsz = nz >> LOGT;
+      if (CRBA) {
+        Real* out = ar.M + b * ar.sM_b;
+        const int* mz = tb.mtab + dm.n_mpair;
+        for (int k = r0z; k < dm.n_mzero; k += rsz) put(&out[(int64_t)mz[k] * ar.sM_k], Real(0), ar.stream_out);
+      }
+      if (JAC) {
+        Real* out = ar.J + b * ar.sJ_b;
+        const int* jz = jrow + ee.n_col;
+        for (int k = r0z; k < ee.n_zero; k += rsz) put(&out[(int64_t)jz[k] * ar.sJ_k], Real(0), ar.stream_out);
+      }
+    }
   }
 
   if (BACK || FK || JAC) __syncthreads();
+
+  // Kinematics-tier store: this launch's poses (by preorder position), motion
+  // subspaces and base origin, before the body phase overwrites the poses.
+  if (ar.kin_mode == 1) {
+    Real* kin = ar.kin;
+    if (NEED_BODY)
+      for (int i = tid; i < KP * T; i += nt) {
+        const int k = i >> LOGT, in = i & (T - 1);
+        if (tile0 + in < ar.B) kin[k * kld + tile0 + in] = body_l[(k / 12) * SB + (k % 12) * T + in];
+      }
+    if (NEED_S)
+      for (int i = tid; i < KS * T; i += nt) {
+        const int k = i >> LOGT, in = i & (T - 1);
+        if (tile0 + in < ar.B) kin[(KP + k) * kld + tile0 + in] = s_l[(k / 6) * SD + (k % 6) * T + in];
+      }
+    for (int i = tid; i < 3 * T; i += nt) {
+      const int k = i >> LOGT, in = i & (T - 1);
+      if (tile0 + in < ar.B) kin[(KP + KS + k) * kld + tile0 + in] = o_l[k * T + in];
+    }
+    __syncthreads();
+  }
 
   // Phases 3-5 give every thread one fixed instance of the tile and stride over
   // items, so output addresses advance by a constant and loads from
@@ -418,9 +515,8 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   }
 
   // ---------------- 5. dense outputs, lanes over instances ----------------
-  // Structural zeros read the all-zero block nv, so the loops carry no
-  // branches apart from the batch bound of the last tile.  Rows are taken four
-  // at a time so their LDS reads are in flight together.
+  // Compiled lists drive M and J: one entry per non-zero pair or column (LDS
+  // reads only for those), then plain stores of the structural zeros.
   if (!bok) return;
   if (FK) {
     const int NR = n * 12;
@@ -437,56 +533,77 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     }
   }
   if (CRBA) {
-    const int NR = nv * nv;
+    // Related pairs: M[a][d] = M[d][a] = s_a . Fc_d, both triangles from one
+    // register (M is bitwise symmetric).  Entries go four at a time so their
+    // LDS reads are in flight together; the tail reads the all-zero block and
+    // stores nothing.
+    const int NP = dm.n_mpair;
     Real* out = ar.M + bo * ar.sM_b;
-    const int64_t ostep = (int64_t)rstep * ar.sM_k;
     const int zcode = (nv << 16) | nv;
-    for (int row = r0; row < NR; row += 4 * rstep) {
+    for (int k = r0; k < NP; k += 4 * rstep) {
       Real val[4];
+      int code[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int rr = row + u * rstep;
-        const int e = (rr < NR) ? tb.mtab[rr] : zcode;
-        const Real* sa = s_l + (e >> 16) * SD + in;
-        const Real* fd = fc_l + (e & 0xffff) * SD + in;
+        const int kk = k + u * rstep;
+        code[u] = (kk < NP) ? tb.mtab[kk] : zcode;
+        const Real* sa = s_l + (code[u] & 0xffff) * SD + in;
+        const Real* fd = fc_l + (code[u] >> 16) * SD + in;
         val[u] = sa[0] * fd[0] + sa[T] * fd[T] + sa[2 * T] * fd[2 * T] + sa[3 * T] * fd[3 * T] +
                  sa[4 * T] * fd[4 * T] + sa[5 * T] * fd[5 * T];
       }
-      Real* o = out + (int64_t)row * ar.sM_k;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (row + u * rstep < NR) put(&o[u * ostep], val[u], ar.stream_out);
+        if (k + u * rstep < NP) {
+          const int a = code[u] & 0xffff, d = code[u] >> 16;
+          put(&out[(int64_t)(a * nv + d) * ar.sM_k], val[u], ar.stream_out);
+          put(&out[(int64_t)(d * nv + a) * ar.sM_k], val[u], ar.stream_out);
+        }
+    }
+    if (!early_zero) {
+      const int* mz = tb.mtab + NP;
+      for (int k = r0; k < dm.n_mzero; k += rstep) put(&out[(int64_t)mz[k] * ar.sM_k], Real(0), ar.stream_out);
     }
   }
   if (JAC) {
-    const int NR = ee.n_ee * 6 * nv;
+    // Columns on an end effector's root path: the 6 rows of column c of block
+    // e are [v + sgn p x w; w] from s_c = [w; v], with p the world origin
+    // relative to the base (o, sgn = +1) or the end-effector origin (p_e,
+    // sgn = -1).  Off-path rows are zeros from their own list.
+    const int NC = ee.n_col;
     const bool world = ar.frame == 0;
+    const Real sgn = world ? Real(1) : Real(-1);
     Real* out = ar.J + bo * ar.sJ_b;
-    const int64_t ostep = (int64_t)rstep * ar.sJ_k;
-    const int zcode = nv;  // row 0 of the zero block
-    for (int row = r0; row < NR; row += 4 * rstep) {
-      Real val[4];
+    for (int k = r0; k < NC; k += 2 * rstep) {
+      Real val[2][6];
+      int code[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int rr = row + u * rstep;
-        const int code = (rr < NR) ? jrow[rr] : zcode;
-        const int r = (code >> 8) & 0xf;
-        const int e = code >> 12;
-        const Real* s = s_l + (code & 0xff) * SD + in;
-        // rows 0-2: v + o x w (world origin) or v + w x p_e (end-effector origin); rows 3-5: w
-        const bool lin = r < 3;
-        const int rv = lin ? r : r - 3;
-        const int r1 = (rv == 2) ? 0 : rv + 1;
-        const int r2 = (rv == 0) ? 2 : rv - 1;
-        const Real* P = world ? (o_l + in) : (pe_l + e * 3 * T + in);
-        const Real cross = world ? (P[r1 * T] * s[r2 * T] - P[r2 * T] * s[r1 * T])
-                                 : (s[r1 * T] * P[r2 * T] - s[r2 * T] * P[r1 * T]);
-        val[u] = lin ? s[(3 + rv) * T] + cross : s[rv * T];
+      for (int u = 0; u < 2; ++u) {
+        const int kk = k + u * rstep;
+        code[u] = (kk < NC) ? jrow[kk] : nv;  // the tail reads the all-zero block
+        const Real* s = s_l + (code[u] & 0xff) * SD + in;
+        const Real* P = world ? (o_l + in) : (pe_l + (code[u] >> 8) * 3 * T + in);
+        const Real w0 = s[0], w1 = s[T], w2 = s[2 * T];
+        const Real p0 = P[0], p1 = P[T], p2 = P[2 * T];
+        val[u][0] = s[3 * T] + sgn * (p1 * w2 - p2 * w1);
+        val[u][1] = s[4 * T] + sgn * (p2 * w0 - p0 * w2);
+        val[u][2] = s[5 * T] + sgn * (p0 * w1 - p1 * w0);
+        val[u][3] = w0;
+        val[u][4] = w1;
+        val[u][5] = w2;
       }
-      Real* o = out + (int64_t)row * ar.sJ_k;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (row + u * rstep < NR) put(&o[u * ostep], val[u], ar.stream_out);
+      for (int u = 0; u < 2; ++u)
+        if (k + u * rstep < NC) {
+          const int c = code[u] & 0xff, e = code[u] >> 8;
+          Real* o = out + (int64_t)(e * 6 * nv + c) * ar.sJ_k;
+#pragma unroll
+          for (int r = 0; r < 6; ++r) put(&o[(int64_t)(r * nv) * ar.sJ_k], val[u][r], ar.stream_out);
+        }
+    }
+    if (!early_zero) {
+      const int* jz = jrow + NC;
+      for (int k = r0; k < ee.n_zero; k += rstep) put(&out[(int64_t)jz[k] * ar.sJ_k], Real(0), ar.stream_out);
     }
   }
 }
@@ -890,10 +1007,19 @@ __global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
 // --------------------------------------------------------------------------
 // Host-visible launchers: pick the compile-time tile and launch.
 // --------------------------------------------------------------------------
+// Allow `lds` bytes of dynamic LDS for `kernel`.  The largest size granted so
+// far is remembered per device (one static per kernel instantiation), so
+// repeated launches, and launches recorded into a graph, make no further call.
 template <class K>
 static hipError_t raise_lds(K kernel, size_t lds) {
   if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static size_t granted[BARD_MAX_DEVICES] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) dev = 0;
+  if (lds <= granted[dev]) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) granted[dev] = lds;
+  return e;
 }
 
 template <class Real, int OPS, int LOGT>

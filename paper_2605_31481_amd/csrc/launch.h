@@ -29,7 +29,18 @@ struct Args {
   int frame;
   int xcd_remap;
   int stream_out;  // 1: dense outputs use non-temporal (streaming) stores
+  // Kinematics tier of a workspace (see kin_rows): instance-minor rows with
+  // stride kin_ld.  kin_mode 0: unused; 1: store the poses, motion subspaces
+  // and base origin this launch computes; 2: load them instead of computing.
+  Real* kin;
+  int64_t kin_ld;
+  int kin_mode;
 };
+
+// Rows of the kinematics tier per instance: 12 per body by preorder position
+// (world R row-major, then p relative to the base origin), 6 per dof (s),
+// then the base origin o (3).
+__host__ __device__ inline int kin_rows(int n, int nv) { return 12 * n + 6 * nv + 3; }
 
 template <class Real, int OPS>
 hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar, int grid, int block, size_t lds,

@@ -43,15 +43,17 @@ struct DevModel {
   const unsigned char* img64;
   int n, nq, nv, depth, P, log2P, kmax, free_root;
   int ulen[4];  // entries of the subtree work lists for 1, 2, 4, 8 row groups per wave
+  int n_mpair, n_mzero;  // mass-matrix output lists (pairs, then zero entries)
   float g32[3];
   double g64[3];
 };
 
-// Per end-effector-set image: jrow [n_ee*6*nv] (per output row: src dof |
-// row-in-block << 8 | ee << 12, src = nv for a structural zero) then ee_body.
+// Per end-effector-set image: the Jacobian column list (dof | ee << 8) and
+// then the zero-row list, in a region of n_ee*6*nv ints, then ee_body.
 struct DevEE {
   const unsigned char* img;
   int n_ee;
+  int n_col, n_zero;
 };
 
 struct DeviceCopy {
@@ -76,7 +78,8 @@ struct bard_model {
   std::vector<float> cst32;
   std::vector<int16_t> sched_body;
   std::vector<int8_t> sched_src, child_slot;
-  std::vector<int> level_info, mtab;
+  std::vector<int> level_info, mtab;  // mtab: mass-matrix pair list, then zero list
+  int n_mpair = 0, n_mzero = 0;
   std::vector<std::vector<int>> children;
   bard::DeviceCopy dev[BARD_MAX_DEVICES];
   std::mutex mu;
@@ -89,6 +92,7 @@ int compile_model(bard_model* m, std::string* err);
 // parts << 12 (-1 = idle).  Bodies whose subtree exceeds 2U bodies come first
 // as U-entry groups, each aligned to a wave, so one wave splits the sum.
 std::vector<int> subtree_units(const bard_model* m, int U);
-// Per-row source table of the dense Jacobian output for a set of end effectors.
-std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee);
+// Output lists of the dense Jacobian for a set of end effectors: the column
+// list (n_cols entries) followed by the zero-row list (n_zeros entries).
+std::vector<int> jacobian_table(const bard_model* m, const std::vector<int>& ee, int* n_cols, int* n_zeros);
 }  // namespace bard

@@ -163,3 +163,31 @@ def test_adjoints_of_free_joint_trees_are_rejected():
     assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 8, None) == -7
     assert bard.bard_fk_vjp(h, 0, None, None, None, None, 8, None) == -7
     assert "free joint" in bard.bard_last_error().decode()
+
+
+def test_plan_host_side():
+    """Plan creation, tip end effectors and configuration need no device."""
+    trees = synth.multi_trees()
+    ms = [bard.Model.from_tree(t) for t in trees]
+    p = bard.Plan(ms, synth.MULTI_BATCHES)
+    for i, t in enumerate(trees):
+        assert p.ee(i) == list(t.ee_bodies)
+    assert p.config == {"tile": 16, "fusion": 0, "order": 0, "from_cache": False}
+    p.configure(32, 2, 1)
+    assert p.config["tile"] == 32 and p.config["fusion"] == 2
+    with pytest.raises(bard.BardError):
+        p.configure(12, 0, 0)
+    with pytest.raises(bard.BardError):
+        p.configure(16, 3, 0)
+    # two operators have no fused kernel: only one launch per operator is valid
+    p2 = bard.Plan(ms, synth.MULTI_BATCHES, op_mask=bard.PLAN_RNEA | bard.PLAN_CRBA)
+    assert p2.config["fusion"] == 2
+    with pytest.raises(bard.BardError):
+        p2.configure(16, 0, 0)
+    h = ctypes.c_void_p()
+    hs = (ctypes.c_void_p * 1)(ms[0].handle)
+    bs = (ctypes.c_int64 * 1)(8)
+    assert bard.bard_plan_create(hs, 1, bs, 0, 0, ctypes.byref(h)) == -1
+    assert bard.bard_plan_create(hs, 0, bs, 7, 0, ctypes.byref(h)) == -1
+    assert bard.bard_plan_create(hs, 1, bs, 7, 2, ctypes.byref(h)) == -1
+    assert bard.bard_plan_run(None, None, None) == -1

@@ -1,0 +1,138 @@
+"""GPU parity of multi-tree plans: the five random trees of 7, 11, 12, 18 and
+23 DOF with batches 512, 1024, 2048, 4096 and 8192 (15,872 instances) in one
+plan, checked against the oracle on sampled instances of every tree, for each
+fusion mode, tile and item order; graph replays with new inputs between them;
+the autotuner and its cache.  Tolerance contract as in parity_util."""
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2605_31481_amd import bard
+from parity_util import assert_normwise, from_dev, inputs, oracle_for, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(dtype="float32", seed=2300, batches=None):
+    trees = synth.multi_trees()
+    batches = batches or synth.MULTI_BATCHES
+    models = [bard.Model.from_tree(t) for t in trees]
+    host = [inputs(t, B, seed + k, dtype) for k, (t, B) in enumerate(zip(trees, batches))]
+    dev = [tuple(to_dev(x, dtype) for x in h) for h in host]
+    return trees, models, batches, host, dev
+
+
+def _snapshot(outs):
+    return [tuple(None if x is None else x.clone() for x in o) for o in outs]
+
+
+def _check(plan, trees, host, outs, dtype, n_sample=96, seed=0):
+    rng = np.random.default_rng(seed)
+    for k, (tree, (q, qd, qdd), (tau, M, J)) in enumerate(zip(trees, host, outs)):
+        B = q.shape[0]
+        idx = np.sort(rng.choice(B, min(n_sample, B), replace=False))
+        ee = plan.ee(k)
+        rt, rM, rJ = oracle_for(tree).chain(q[idx], qd[idx], qdd[idx], ee)
+        if tau is not None:
+            assert_normwise(f"tau[{k}]", from_dev(tau)[idx][:, None], rt[:, None], dtype)
+        if M is not None:
+            assert_normwise(f"M[{k}]", from_dev(M)[idx][:, None], rM.reshape(len(idx), 1, -1), dtype)
+        if J is not None:
+            assert_normwise(f"J[{k}]", from_dev(J)[idx].reshape(len(idx), len(ee), -1),
+                            rJ.reshape(len(idx), len(ee), -1), dtype)
+
+
+CONFIGS = [(16, 0, 0), (8, 1, 0), (32, 2, 1), (16, 2, 0), (8, 0, 1), (32, 0, 0)]
+
+
+@pytest.mark.parametrize("tile,fusion,order", CONFIGS)
+def test_plan_configurations(tile, fusion, order):
+    import torch
+    say(f"[gpu] plan tile={tile} fusion={fusion} order={order}")
+    trees, models, batches, host, dev = _setup()
+    plan = bard.Plan(models, batches)
+    plan.configure(tile, fusion, order)
+    first = _snapshot(plan.run(dev))          # eager launch
+    torch.cuda.synchronize()
+    _check(plan, trees, host, first, "float32")
+    for _ in range(2):                        # captured graph, then a replay
+        again = plan.run(dev)
+        torch.cuda.synchronize()
+        for a, b in zip(first, again):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y)
+
+
+def test_plan_graph_replay_with_new_inputs():
+    import torch
+    say("[gpu] plan graph replay, inputs swapped between replays")
+    trees, models, batches, host_a, dev_a = _setup(seed=2400)
+    _, _, _, host_b, dev_b = _setup(seed=2500)
+    plan = bard.Plan(models, batches)
+    ref_a = _snapshot(plan.run(dev_a))
+    torch.cuda.synchronize()
+    for rep in range(3):
+        scratch = torch.randn(1 << 20, device="cuda")     # eager work between replays
+        (scratch * 2).sum().item()
+        out = _snapshot(plan.run(dev_b if rep % 2 == 0 else dev_a))
+        torch.cuda.synchronize()
+        if rep % 2 == 0:
+            _check(plan, trees, host_b, out, "float32", n_sample=48, seed=rep)
+        else:
+            for a, b in zip(ref_a, out):
+                for x, y in zip(a, b):
+                    assert torch.equal(x, y)
+
+
+def test_plan_fp64_and_single_operators():
+    import torch
+    say("[gpu] plan fp64; single-operator masks")
+    trees, models, batches, host, dev = _setup("float64", batches=[64, 37, 129, 8, 200])
+    plan = bard.Plan(models, batches, dtype=torch.float64)
+    outs = plan.run(dev)
+    torch.cuda.synchronize()
+    _check(plan, trees, host, outs, "float64", n_sample=32)
+    trees, models, batches, host, dev = _setup(batches=[300, 17, 0, 1000, 64])
+    for mask in (bard.PLAN_RNEA, bard.PLAN_CRBA, bard.PLAN_JACOBIAN, bard.PLAN_RNEA | bard.PLAN_JACOBIAN):
+        plan = bard.Plan(models, batches, op_mask=mask)
+        outs = plan.run(dev)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(mask)
+        for k, B in enumerate(batches):
+            tau, M, J = outs[k]
+            assert (tau is not None) == bool(mask & 1) and (M is not None) == bool(mask & 2)
+            assert (J is not None) == bool(mask & 4)
+            if B == 0:
+                continue
+            q, qd, qdd = host[k]
+            ee = plan.ee(k)
+            idx = np.sort(rng.choice(B, min(32, B), replace=False))
+            rt, rM, rJ = oracle_for(trees[k]).chain(q[idx], qd[idx], qdd[idx], ee)
+            if tau is not None:
+                assert_normwise("tau", from_dev(tau)[idx][:, None], rt[:, None], "float32")
+            if M is not None:
+                assert_normwise("M", from_dev(M)[idx][:, None], rM.reshape(len(idx), 1, -1), "float32")
+            if J is not None:
+                assert_normwise("J", from_dev(J)[idx].reshape(len(idx), len(ee), -1),
+                                rJ.reshape(len(idx), len(ee), -1), "float32")
+
+
+def test_plan_autotune_and_cache(tmp_path, monkeypatch):
+    import torch
+    say("[gpu] plan autotune")
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("BARD_TUNE_CACHE", str(cache))
+    trees, models, batches, host, dev = _setup(seed=2600)
+    plan = bard.Plan(models, batches)
+    plan.autotune(1500)
+    cfg = plan.config
+    assert cfg["tile"] in (8, 16, 32) and cfg["fusion"] in (0, 1, 2) and not cfg["from_cache"]
+    outs = plan.run(dev)
+    torch.cuda.synchronize()
+    _check(plan, trees, host, outs, "float32", n_sample=48)
+    text = cache.read_text()
+    assert text.count('"tile"') == 1
+    again = bard.Plan(models, batches)
+    c2 = again.config
+    assert c2["from_cache"] and (c2["tile"], c2["fusion"], c2["order"]) == (cfg["tile"], cfg["fusion"], cfg["order"])
