@@ -243,37 +243,50 @@ __device__ __forceinline__ void free_root_pose(const Real* c, const Real* qv, Re
     o[i] = c[C_R0 + 3 * i] * qv[0] + c[C_R0 + 3 * i + 1] * qv[1] + c[C_R0 + 3 * i + 2] * qv[2] + c[C_T0 + i];
 }
 
-// One joint step: parent pose (Rw, pw) -> body pose, and the body's motion
-// subspace s = [u; p x u] (revolute) or [0; u] (prismatic), u = R axis.
+// Joint transform from the Rodrigues constants (eqs. (4)-(5)):
+// R_pc = R0 + sin q A + (1 - cos q) B, t_pc = t0 (+ q d for a prismatic joint).
 template <class Real>
-__device__ __forceinline__ void joint_step(const Real* c, bool rev, Real qv, Real* Rw, Real* pw, Real* s) {
-  // eqs. (4)-(5): R_pc = R0 + sin q A + (1 - cos q) B ; t_pc = t0 (+ q d for a prismatic joint)
+__device__ __forceinline__ void joint_transform(const Real* c, Real qv, Real* Rpc, Real* tpc) {
   Real sq, cq;
   sincos_r(qv, &sq, &cq);
   const Real omc = Real(1) - cq;
-  Real Rpc[9], tpc[3], Rn[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rpc[k] = c[C_R0 + k] + sq * c[C_A + k] + omc * c[C_B + k];
 #pragma unroll
   for (int k = 0; k < 3; ++k) tpc[k] = c[C_T0 + k] + qv * c[C_D + k];
+}
+
+// Parent pose (Rw, pw) and joint transform (Rpc, tpc) -> body pose, and the
+// body's motion subspace s = [u; p x u] (revolute) or [0; u] (prismatic) with
+// u = R axis: in the base frame s is the direct Jacobian column of eq. (7).
+template <class Real>
+__device__ __forceinline__ void compose_joint(const Real* Rpc, const Real* tpc, const Real* ax, bool rev, Real* Rw,
+                                              Real* pw, Real* s) {
+  Real Rn[9], pn[3];
   mul33(Rw, Rpc, Rn);
-  Real pn[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) pn[i] = Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2] + pw[i];
 #pragma unroll
   for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
 #pragma unroll
   for (int k = 0; k < 3; ++k) pw[k] = pn[k];
-  // motion subspace in the base frame = direct Jacobian column (eq. (7))
   Real u[3], pxu[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * c[C_AX] + Rw[3 * i + 1] * c[C_AX + 1] + Rw[3 * i + 2] * c[C_AX + 2];
+  for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * ax[0] + Rw[3 * i + 1] * ax[1] + Rw[3 * i + 2] * ax[2];
   cross3(pw, u, pxu);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     s[i] = rev ? u[i] : Real(0);
     s[3 + i] = rev ? pxu[i] : u[i];
   }
+}
+
+// One joint step: joint transform, then the composed pose and motion subspace.
+template <class Real>
+__device__ __forceinline__ void joint_step(const Real* c, bool rev, Real qv, Real* Rw, Real* pw, Real* s) {
+  Real Rpc[9], tpc[3];
+  joint_transform(c, qv, Rpc, tpc);
+  compose_joint(Rpc, tpc, c + C_AX, rev, Rw, pw, s);
 }
 
 // Views of the staged table image.

@@ -136,6 +136,27 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   const int WA = (T << log2P) >> 6;
   const bool early_zero = nt > WA * 64;  // some waves are free during the sweep
 
+  // Joint transforms (eqs. (4)-(5)) depend on q only, so every wave computes
+  // them, one (body, instance) item per thread, into rows 12-23 of the body's
+  // block, which the sweep overwrites with v and a after reading them.  The
+  // serial sweep is left with the composition of poses.
+  constexpr bool PRE = NEED_BODY;
+  if (PRE && !hit) {
+    const int inx = tid & (T - 1);
+    for (int bb = tid >> LOGT; bb < n; bb += nt >> LOGT) {
+      const I4 meta = tb.meta[bb];
+      if (meta.y == J_FREE) continue;
+      Real Rpc[9], tpc[3];
+      joint_transform(tb.cst + bb * CST, q_l[meta.z * T + inx], Rpc, tpc);
+      Real* br = body_l + tb.bm2[bb].x * SB + inx;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) br[(12 + k) * T] = Rpc[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) br[(21 + k) * T] = tpc[k];
+    }
+    __syncthreads();
+  }
+
   // ---------------- 2. level sweep ----------------
   if (wave < WA && !(hit && !VEL)) {
     const int P = dm.P;
@@ -241,10 +262,11 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         for (int i = 0; i < 3; ++i) o_l[i * T + inst] = Real(0);
     }
 
-    // Everything a level needs except the carried link state is loaded one
-    // level ahead, so its LDS latency overlaps the previous level's arithmetic.
+    // What a level needs besides the carried link state.  (Loading it one level
+    // ahead measured slower: the copies between the two records cost more than
+    // the LDS latency they hide.)
     struct LevelIn {
-      Real c[36];  // R0, A, B, t0, axis, d
+      Real c[PRE ? 15 : 36];  // PRE: R_pc, t_pc, axis; else the constants R0, A, B, t0, axis, d
       Real q, qd, qdd;
       int bb, act, src, parent, rev, vi, pos;
     };
@@ -265,21 +287,21 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
       if (!hit) {
         const Real* c = tb.cst + L.bb * CST;
+        if constexpr (PRE) {
+          const Real* br = body_l + L.pos * SB + inst;
 #pragma unroll
-        for (int k = 0; k < 36; ++k) L.c[k] = c[k];
+          for (int k = 0; k < 12; ++k) L.c[k] = br[(12 + k) * T];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) L.c[12 + k] = c[C_AX + k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 36; ++k) L.c[k] = c[k];
+        }
       }
     };
-    // FP64 keeps one level in registers (two would spill).
-    constexpr bool AHEAD = sizeof(Real) == 4;
-    LevelIn cur;
-    if (AHEAD && lstart < dm.depth) load_level(lstart, cur);
     for (int l = lstart; l < dm.depth; ++l) {
-      LevelIn nxt;
-      if (AHEAD) {
-        if (l + 1 < dm.depth) load_level(l + 1, nxt);
-      } else {
-        load_level(l, cur);
-      }
+      LevelIn cur;
+      load_level(l, cur);
       if (tb.linfo[2 * l + 1]) {
         const int src = cur.src;
         if (!hit) {
@@ -313,7 +335,8 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
 #pragma unroll
         for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
       } else {
-        joint_step(cur.c, cur.rev, cur.q, Rw, pw, s);
+        if constexpr (PRE) compose_joint(cur.c, cur.c + 9, cur.c + 12, cur.rev != 0, Rw, pw, s);
+        else joint_step(cur.c, cur.rev != 0, cur.q, Rw, pw, s);
       }
       if (VEL) {
         Real vJ[6], cJ[6];
@@ -354,7 +377,6 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
 #pragma unroll
               for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
       }
-      if (AHEAD) cur = nxt;
     }
   } else if (wave >= WA && (CRBA || JAC)) {
     // The structural zeros of M and J depend on nothing the sweep computes:
