@@ -231,8 +231,9 @@ __global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real>
             }
           }
         }
+        // Bodies on the world all sit at level 0, where every lane starts from
+        // the base state set above; the carried state is never reset.
         const I4 meta = tb.meta[bb];  // {parent, joint type, q index, v index}
-        if (meta.x < 0) reset();
         Real s[6];
         joint_step(tb.cst + bb * CST, meta.y == J_REV, q_l[meta.z * T + inst], Rw, pw, s);
         if (RNEA) {

@@ -77,6 +77,11 @@ int compile_model(bard_model* m, std::string* err) {
       *err = "a free joint is only allowed on body 0 attached to the world";
       return BARD_E_TOPOLOGY;
     }
+    if (i > 0 && p == -1 && m->jtype[0] == J_FREE) {
+      *err = "with a free root every other body must descend from it (body " + std::to_string(i) +
+             " is attached to the world)";
+      return BARD_E_TOPOLOGY;
+    }
     if (t != J_FREE) {
       double* a = &m->axis[3 * i];
       double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);

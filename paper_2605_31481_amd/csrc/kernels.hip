@@ -268,7 +268,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     struct LevelIn {
       Real c[PRE ? 15 : 36];  // PRE: R_pc, t_pc, axis; else the constants R0, A, B, t0, axis, d
       Real q, qd, qdd;
-      int bb, act, src, parent, rev, vi, pos;
+      int bb, act, src, rev, vi, pos;
     };
     auto load_level = [&](int l, LevelIn& L) {
       const int body = in_sched ? tb.sbody[l * P + slot] : -1;
@@ -276,7 +276,6 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       L.bb = L.act ? body : 0;
       L.src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
       const I4 meta = tb.meta[L.bb];
-      L.parent = meta.x;
       L.rev = meta.y == J_REV;
       L.vi = meta.w;
       L.pos = tb.bm2[L.bb].x;
@@ -285,7 +284,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         L.qd = qdi_l[meta.w * T];
         L.qdd = qddi_l[meta.w * T];
       }
-      if (!hit) {
+      {
         const Real* c = tb.cst + L.bb * CST;
         if constexpr (PRE) {
           const Real* br = body_l + L.pos * SB + inst;
@@ -299,83 +298,97 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         }
       }
     };
-    for (int l = lstart; l < dm.depth; ++l) {
-      LevelIn cur;
-      load_level(l, cur);
-      if (tb.linfo[2 * l + 1]) {
-        const int src = cur.src;
-        if (!hit) {
+    // Every body attached to the world sits at level 0 (a free root is the only
+    // such body when there is one), where all lanes start from the base state
+    // set above, so the loop never resets the carried state.
+    // v_i = v_parent + s_i qd_i, a_i = a_parent + s_i qdd_i + v_parent x (s_i qd_i)
+    auto propagate = [&](const Real* s, Real qdv, Real qddv) {
+      Real vJ[6], cJ[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
+      crm(v, vJ, cJ);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        a[k] = a[k] + s[k] * qddv + cJ[k];
+        v[k] = v[k] + vJ[k];
+      }
+    };
+    if (!hit) {
+      for (int l = lstart; l < dm.depth; ++l) {
+        LevelIn cur;
+        load_level(l, cur);
+        if (tb.linfo[2 * l + 1]) {
+          const int src = cur.src;
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
           for (int k = 0; k < 3; ++k) pw[k] = xch(pw[k], src);
+          if (VEL) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              v[k] = xch(v[k], src);
+              a[k] = xch(a[k], src);
+            }
+          }
         }
-        if (VEL) {
+        Real s[6];
+        if constexpr (PRE) compose_joint(cur.c, cur.c + 9, cur.c + 12, cur.rev != 0, Rw, pw, s);
+        else joint_step(cur.c, cur.rev != 0, cur.q, Rw, pw, s);
+        if (VEL) propagate(s, cur.qd, cur.qdd);
+        if (cur.act) {
+          if (NEED_S) {
+            Real* sr = s_l + cur.vi * SD + inst;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
+          }
+          if (NEED_BODY) {
+            Real* br = body_l + cur.pos * SB + inst;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
+            if (VEL) {
+#pragma unroll
+              for (int k = 0; k < 6; ++k) {
+                br[(12 + k) * T] = v[k];
+                br[(18 + k) * T] = a[k];
+              }
+            }
+          }
+          if (JAC && ar.frame == 1)
+            for (int e = 0; e < ee.n_ee; ++e)
+              if (eeb_l[e] == cur.bb)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
+        }
+      }
+    } else if (VEL) {
+      // Workspace hit: poses and s are staged; only v and a propagate.
+      for (int l = lstart; l < dm.depth; ++l) {
+        const int body = in_sched ? tb.sbody[l * P + slot] : -1;
+        const int bb = body >= 0 ? body : 0;
+        if (tb.linfo[2 * l + 1]) {
+          const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
             v[k] = xch(v[k], src);
             a[k] = xch(a[k], src);
           }
         }
-      }
-      if (cur.parent < 0) {  // attached to the world (level 0 of a fixed base)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pw[k] = Real(0);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          v[k] = Real(0);
-          a[k] = a0[k];
-        }
-      }
-      Real s[6];
-      if (hit) {
-        const Real* sr = s_l + cur.vi * SD + inst;
+        const I4 meta = tb.meta[bb];
+        Real s[6];
+        const Real* sr = s_l + meta.w * SD + inst;
 #pragma unroll
         for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
-      } else {
-        if constexpr (PRE) compose_joint(cur.c, cur.c + 9, cur.c + 12, cur.rev != 0, Rw, pw, s);
-        else joint_step(cur.c, cur.rev != 0, cur.q, Rw, pw, s);
-      }
-      if (VEL) {
-        Real vJ[6], cJ[6];
+        propagate(s, qdi_l[meta.w * T], qddi_l[meta.w * T]);
+        if (body >= 0) {
+          Real* br = body_l + tb.bm2[bb].x * SB + inst;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) vJ[k] = s[k] * cur.qd;
-        crm(v, vJ, cJ);  // v_parent x (s qd)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          a[k] = a[k] + s[k] * cur.qdd + cJ[k];
-          v[k] = v[k] + vJ[k];
-        }
-      }
-      if (cur.act) {
-        if (NEED_S && !hit) {
-          Real* sr = s_l + cur.vi * SD + inst;
-#pragma unroll
-          for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
-        }
-        if (NEED_BODY) {
-          Real* br = body_l + cur.pos * SB + inst;
-          if (!hit) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
-          }
-          if (VEL) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-              br[(12 + k) * T] = v[k];
-              br[(18 + k) * T] = a[k];
-            }
+          for (int k = 0; k < 6; ++k) {
+            br[(12 + k) * T] = v[k];
+            br[(18 + k) * T] = a[k];
           }
         }
-        if (JAC && ar.frame == 1 && !hit)
-          for (int e = 0; e < ee.n_ee; ++e)
-            if (eeb_l[e] == cur.bb)
-#pragma unroll
-              for (int i = 0; i < 3; ++i) pe_l[(e * 3 + i) * T + inst] = pw[i];
       }
     }
   } else if (wave >= WA && (CRBA || JAC)) {

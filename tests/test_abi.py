@@ -191,3 +191,12 @@ def test_plan_host_side():
     assert bard.bard_plan_create(hs, 0, bs, 7, 0, ctypes.byref(h)) == -1
     assert bard.bard_plan_create(hs, 1, bs, 7, 2, ctypes.byref(h)) == -1
     assert bard.bard_plan_run(None, None, None) == -1
+
+
+def test_free_root_must_be_the_only_world_body():
+    t = synth.humanoid_small()
+    parent = np.array(t.parent).copy()
+    parent[3] = -1          # a second body on the world next to the free root
+    with pytest.raises(bard.BardError) as e:
+        bard.Model(parent, t.joint_type, t.axis, t.X_tree, t.inertia)
+    assert e.value.status == -2
