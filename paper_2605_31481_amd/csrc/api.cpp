@@ -183,16 +183,19 @@ int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, D
   return BARD_OK;
 }
 
-// Waves per workgroup for the phases after the level sweep (body, subtree,
-// dense outputs), which have no serial dependency and hide LDS latency with
-// more waves.
-int out_waves() {
+// Waves per workgroup for the phases after the level sweep (no serial
+// dependency; more waves hide more LDS latency).  FP32 default 12 (measured
+// on the 36-DOF humanoid: 12 waves 19.9 us, 16 waves 20.1 us, 8 waves
+// 22.0 us per launch at B = 4096); BARD_OUT_WAVES overrides up to the most
+// the kernels are compiled for.
+int out_waves(int rs) {
+  const int cap = tree_max_threads(rs) / 64;
   const char* e = getenv("BARD_OUT_WAVES");
   if (e) {
     int w = atoi(e);
-    if (w >= 1 && w <= 8) return w;
+    if (w >= 1 && w <= cap) return w;
   }
-  return 8;
+  return rs == 4 ? 12 : cap;
 }
 
 }  // namespace bard
@@ -337,7 +340,7 @@ int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int
   ar.log2P = sh.log2P;
   ar.frame = frame;
   int waves = (sh.T << sh.log2P) >> 6;
-  if (OPS & (OP_CRBA | OP_JAC | OP_RNEA | OP_FK)) waves = std::max(waves, out_waves());
+  if (OPS & (OP_CRBA | OP_JAC | OP_RNEA | OP_FK)) waves = std::max(waves, out_waves((int)sizeof(Real)));
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, waves * 64, lds, st);

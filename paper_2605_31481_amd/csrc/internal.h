@@ -18,7 +18,7 @@ size_t lds_limit(int dev);
 int ensure_device(bard_model* m, DeviceCopy** out);
 // Device image of the Jacobian output lists for an end-effector set (cached per set).
 int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out);
-// Waves per workgroup for the phases after the level sweep.
-int out_waves();
+// Waves per workgroup for the phases after the level sweep (rs: scalar bytes).
+int out_waves(int rs);
 
 }  // namespace bard

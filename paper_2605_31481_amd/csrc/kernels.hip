@@ -645,7 +645,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
 
 // One tree, one tile per workgroup.
 template <class Real, int OPS, int LOGT>
-__global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
+__global__ void __launch_bounds__(tree_max_threads(sizeof(Real))) tree_kernel(DevModel dm, DevEE ee, Args<Real> ar) {
   tree_tile<Real, OPS, LOGT>(dm, ee, ar, tile_index(ar.xcd_remap));
 }
 
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(512) tree_kernel(DevModel dm, DevEE ee, Args<R
 // acts as a longest-processing-time work queue.  Each model's tables, end
 // effectors and I/O arguments come from device arrays (uniform loads).
 template <class Real, int OPS, int LOGT>
-__global__ void __launch_bounds__(512) plan_kernel(PlanPtrs<Real> pp) {
+__global__ void __launch_bounds__(tree_max_threads(sizeof(Real))) plan_kernel(PlanPtrs<Real> pp) {
   const int2 it = pp.items[pp.item0 + blockIdx.x];
   tree_tile<Real, OPS, LOGT>(pp.dm[it.x], pp.ee[it.x], pp.args[it.x], it.y);
 }

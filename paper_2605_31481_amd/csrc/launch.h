@@ -64,6 +64,12 @@ hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int bl
 
 __host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
 
+// Threads per workgroup the tree kernels are compiled for: 16 waves in FP32
+// (4 per SIMD; the kernels fit 128 VGPRs without spills), 8 in FP64 (whose
+// kernels need more registers).  The phases after the level sweep use every
+// wave, and more waves per SIMD hide more of their LDS latency.
+__host__ __device__ constexpr int tree_max_threads(int rs) { return rs == 4 ? 1024 : 512; }
+
 // Layout of the model's table image.  The device keeps one image per scalar
 // type laid out exactly as the workgroup wants it in LDS, so staging is a
 // single copy of 16-byte chunks.  mtab comes last so kernels that do not need

@@ -248,7 +248,7 @@ int prepare_t(bard_plan* p) {
   const size_t lim = lds_limit(dev);
   auto make_group = [&](int ops, int item0, int count, const std::vector<int>& which) -> int {
     Group g{ops, item0, count, 0, 0};
-    int waves = out_waves();
+    int waves = out_waves(rs);
     for (int i : which) {
       const bard_model* m = p->models[i];
       const int ne = (int)p->ee[i].size();
