@@ -147,7 +147,7 @@ __device__ __forceinline__ Real dot6(const Real* a, const Real* b) {
 // phases over all waves.  The inertial-parameter sums of a workgroup
 // accumulate in LDS in tile order and are written once at the end.
 template <class Real, bool RNEA, int LOGT>
-__global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real> ar) {
+__global__ void __launch_bounds__(512, sizeof(Real) == 4 ? 4 : 1) adjoint_kernel(DevModel dm, AdjArgs<Real> ar) {
   constexpr int T = 1 << LOGT;
   constexpr int SD = 6 * T + block_pad(T, sizeof(Real));
   constexpr int SB = adj_rows(RNEA) * T + block_pad(T, sizeof(Real));
@@ -156,10 +156,7 @@ __global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real>
   const AdjPlan L = adj_plan(RNEA, n, dm.nq, nv, T, (int)sizeof(Real), dm.P, dm.depth, dm.kmax);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6;
-  Real* q_l = reinterpret_cast<Real*>(smem + L.q);
-  Real* qd_l = reinterpret_cast<Real*>(smem + L.qd);
-  Real* qdd_l = reinterpret_cast<Real*>(smem + L.qdd);
-  Real* tb_l = reinterpret_cast<Real*>(smem + L.tb);
+  Real* const inbuf[2] = {reinterpret_cast<Real*>(smem + L.in0), reinterpret_cast<Real*>(smem + L.in1)};
   Real* s_l = reinterpret_cast<Real*>(smem + L.s);        // [nv] blocks of 6 rows
   Real* body_l = reinterpret_cast<Real*>(smem + L.body);  // [n] blocks by preorder position
   double* acc_l = reinterpret_cast<double*>(smem + L.acc);
@@ -176,17 +173,36 @@ __global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real>
   const int r0 = tid >> LOGT;
   const int rstep = nt >> LOGT;
 
+  // Element k of instance b of the concatenated input rows (q, then qd, qdd,
+  // tau_bar for RNEA); b is clamped into the batch.
+  const int KIN = adj_in_rows(RNEA, dm.nq, nv);
+  auto input = [&](int k, int64_t b) -> Real {
+    if (b >= ar.B) b = ar.B - 1;
+    if (k < dm.nq) return ar.q[b * ar.sq_b + (int64_t)k * ar.sq_k];
+    k -= dm.nq;
+    if (k < nv) return ar.qd[b * ar.sqd_b + (int64_t)k * ar.sqd_k];
+    k -= nv;
+    if (k < nv) return ar.qdd[b * ar.sqdd_b + (int64_t)k * ar.sqdd_k];
+    return ar.tau_bar[b * ar.stb_b + (int64_t)(k - nv) * ar.stb_k];
+  };
+  // The next tile's inputs are loaded into registers while this tile's body
+  // and subtree phases run, and written to the other input buffer at the end.
+  constexpr int PF = 4;
+  const bool can_pf = KIN * T <= PF * nt;
+  if (blockIdx.x < ar.ntiles)
+    for (int i = tid; i < KIN * T; i += nt) inbuf[0][i] = input(i >> LOGT, blockIdx.x * T + (i & (T - 1)));
+  int cur = 0;
+
   for (int64_t tile = blockIdx.x; tile < ar.ntiles; tile += gridDim.x) {
     const int64_t tile0 = tile * T;
     const int64_t bo = tile0 + in;
     const bool bok = bo < ar.B;
-    stage_input<Real, LOGT>(ar.q, ar.sq_b, ar.sq_k, dm.nq, tile0, ar.B, q_l, tid, nt);
-    if (RNEA) {
-      stage_input<Real, LOGT>(ar.qd, ar.sqd_b, ar.sqd_k, nv, tile0, ar.B, qd_l, tid, nt);
-      stage_input<Real, LOGT>(ar.qdd, ar.sqdd_b, ar.sqdd_k, nv, tile0, ar.B, qdd_l, tid, nt);
-      stage_input<Real, LOGT>(ar.tau_bar, ar.stb_b, ar.stb_k, nv, tile0, ar.B, tb_l, tid, nt);
-    }
-    __syncthreads();
+    const int64_t nxt = tile + gridDim.x;
+    Real* q_l = inbuf[cur];
+    Real* qd_l = q_l + dm.nq * T;
+    Real* qdd_l = qd_l + nv * T;
+    Real* tb_l = qdd_l + nv * T;
+    __syncthreads();  // inputs staged; the previous tile's phases are done
 
     // ---------------- level sweep: pose, s, v, a, phi ----------------
     if (wave < WA) {
@@ -272,6 +288,14 @@ __global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real>
       }
     }
     __syncthreads();
+
+    Real pf[PF];
+    if (can_pf && nxt < ar.ntiles)
+#pragma unroll
+      for (int j = 0; j < PF; ++j) {
+        const int i = tid + j * nt;
+        pf[j] = (i < KIN * T) ? input(i >> LOGT, nxt * T + (i & (T - 1))) : Real(0);
+      }
 
     // ---------------- body phase: one (body, instance) item per thread ----------------
     // The T lanes of a row group share the body, so the batch sum of the
@@ -419,8 +443,19 @@ __global__ void __launch_bounds__(512) adjoint_kernel(DevModel dm, AdjArgs<Real>
       for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
       ar.q_bar[bo * ar.sqo_b + (int64_t)tb.meta[bb].z * ar.sqo_k] = dot6(s, S);
     });
-    __syncthreads();  // the next tile restages LDS
+    if (nxt < ar.ntiles) {
+      Real* dst = inbuf[cur ^ 1];  // the previous tile's buffer, no longer read
+      if (can_pf) {
+#pragma unroll
+        for (int j = 0; j < PF; ++j)
+          if (tid + j * nt < KIN * T) dst[tid + j * nt] = pf[j];
+      } else {
+        for (int i = tid; i < KIN * T; i += nt) dst[i] = input(i >> LOGT, nxt * T + (i & (T - 1)));
+      }
+    }
+    cur ^= 1;
   }
+  __syncthreads();  // every thread's last inertial-parameter sums are in LDS
 
   if (want_pi) {
     double* out = ar.partial + (int64_t)blockIdx.x * n * 10;
@@ -468,6 +503,27 @@ hipError_t launch_adjoint(const DevModel& dm, const AdjArgs<Real>& ar, int grid,
   }
 }
 
+template <class Real, bool RNEA, int LOGT>
+static hipError_t adjoint_resident_t(int block, size_t lds, int* per_cu) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)adjoint_kernel<Real, RNEA, LOGT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, adjoint_kernel<Real, RNEA, LOGT>, block, lds);
+}
+
+template <class Real, bool RNEA>
+hipError_t adjoint_resident(int logT, int block, size_t lds, int* per_cu) {
+  switch (logT) {
+    case 3: return adjoint_resident_t<Real, RNEA, 3>(block, lds, per_cu);
+    case 4: return adjoint_resident_t<Real, RNEA, 4>(block, lds, per_cu);
+    case 5: return adjoint_resident_t<Real, RNEA, 5>(block, lds, per_cu);
+    case 6: return adjoint_resident_t<Real, RNEA, 6>(block, lds, per_cu);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <class Real>
 hipError_t launch_param_reduce(const double* partial, int groups, int count, Real* out, hipStream_t st) {
   hipLaunchKernelGGL((param_reduce_kernel<Real>), dim3(count), dim3(256), 0, st, partial, groups, count, out);
@@ -477,7 +533,9 @@ hipError_t launch_param_reduce(const double* partial, int groups, int count, Rea
 #define BARD_ADJ_INST(R)                                                                                      \
   template hipError_t launch_adjoint<R, true>(const DevModel&, const AdjArgs<R>&, int, int, size_t, hipStream_t); \
   template hipError_t launch_adjoint<R, false>(const DevModel&, const AdjArgs<R>&, int, int, size_t, hipStream_t); \
-  template hipError_t launch_param_reduce<R>(const double*, int, int, R*, hipStream_t);
+  template hipError_t launch_param_reduce<R>(const double*, int, int, R*, hipStream_t);                            \
+  template hipError_t adjoint_resident<R, true>(int, int, size_t, int*);                                          \
+  template hipError_t adjoint_resident<R, false>(int, int, size_t, int*);
 
 BARD_ADJ_INST(float)
 BARD_ADJ_INST(double)

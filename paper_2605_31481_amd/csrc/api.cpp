@@ -372,9 +372,11 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   return BARD_OK;
 }
 
-// Workgroups of an RNEA adjoint launch that returns the inertial-parameter
+// Most workgroups of an RNEA adjoint launch that returns the inertial-parameter
 // gradient: each loops over tiles and keeps its own FP64 sums, so the batch
 // reduction is two fixed-order stages and its buffer is bounded by the model.
+// The grid depends only on the batch, the tile and the device, so results
+// are identical run to run on one GPU model.
 constexpr int kAdjGroups = 2048;
 
 int ensure_adj_partial(bard_model* m, DeviceCopy* dc) {
@@ -405,7 +407,13 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
   ar.log2P = sh.log2P;
   ar.ntiles = (ar.B + sh.T - 1) / sh.T;
   const int waves = std::max((sh.T << sh.log2P) >> 6, 4);
-  int64_t grid = ar.ntiles;
+  // One workgroup per resident slot, each looping over tiles (it prefetches
+  // the next tile's inputs while it works on the current one).
+  int per_cu = 0, cus = 0;
+  hipError_t eo = adjoint_resident<Real, RNEA>(sh.logT, waves * 64, lds, &per_cu);
+  if (eo != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(BARD_E_DEVICE, "occupancy query failed");
+  int64_t grid = std::min<int64_t>(ar.ntiles, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
   if (RNEA && inertia_bar) {
     if ((rc = ensure_adj_partial(m, dc))) return rc;
     ar.partial = dc->adj_partial;

@@ -195,11 +195,14 @@ struct AdjArgs {
 __host__ __device__ constexpr int adj_rows(bool rnea) { return rnea ? 30 : 12; }
 
 struct AdjPlan {
-  int q, qd, qdd, tb;  // input tiles [K][T]
-  int s, body;         // per-dof and per-body blocks
-  int acc;             // [n][10] FP64 inertial-parameter sums of the workgroup
+  int in0, in1;  // two input tiles [K][T] (q, then for RNEA qd, qdd, tau_bar rows): one in use, one filling
+  int s, body;   // per-dof and per-body blocks
+  int acc;       // [n][10] FP64 inertial-parameter sums of the workgroup
   int tab, tab_bytes, total;
 };
+
+// Input rows of an adjoint tile.
+__host__ __device__ inline int adj_in_rows(bool rnea, int nq, int nv) { return rnea ? nq + 3 * nv : nq; }
 
 __host__ __device__ inline AdjPlan adj_plan(bool rnea, int n, int nq, int nv, int T, int rs, int P, int depth,
                                             int kmax) {
@@ -211,10 +214,8 @@ __host__ __device__ inline AdjPlan adj_plan(bool rnea, int n, int nq, int nv, in
     return at;
   };
   const int pad = block_pad(T, rs);
-  L.q = take(nq * T * rs);
-  L.qd = rnea ? take(nv * T * rs) : off;
-  L.qdd = rnea ? take(nv * T * rs) : off;
-  L.tb = rnea ? take(nv * T * rs) : off;
+  L.in0 = take(adj_in_rows(rnea, nq, nv) * T * rs);
+  L.in1 = take(adj_in_rows(rnea, nq, nv) * T * rs);
   L.s = take(nv * (6 * T + pad) * rs);
   L.body = take(n * (adj_rows(rnea) * T + pad) * rs);
   L.acc = rnea ? take(n * 10 * 8) : off;
@@ -227,6 +228,9 @@ __host__ __device__ inline AdjPlan adj_plan(bool rnea, int n, int nq, int nv, in
 template <class Real, bool RNEA>
 hipError_t launch_adjoint(const DevModel& dm, const AdjArgs<Real>& ar, int grid, int block, size_t lds,
                           hipStream_t st);
+// Workgroups of the adjoint kernel that fit one CU at once (also grants the LDS).
+template <class Real, bool RNEA>
+hipError_t adjoint_resident(int logT, int block, size_t lds, int* per_cu);
 // out[i] = sum over g < groups of partial[g * count + i], in a fixed order.
 template <class Real>
 hipError_t launch_param_reduce(const double* partial, int groups, int count, Real* out, hipStream_t st);
