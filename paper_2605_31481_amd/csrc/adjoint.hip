@@ -147,7 +147,8 @@ __device__ __forceinline__ Real dot6(const Real* a, const Real* b) {
 // phases over all waves.  The inertial-parameter sums of a workgroup
 // accumulate in LDS in tile order and are written once at the end.
 template <class Real, bool RNEA, int LOGT>
-__global__ void __launch_bounds__(512, sizeof(Real) == 4 ? 4 : 1) adjoint_kernel(DevModel dm, AdjArgs<Real> ar) {
+__global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adjoint_kernel(DevModel dm,
+                                                                                        AdjArgs<Real> ar) {
   constexpr int T = 1 << LOGT;
   constexpr int SD = 6 * T + block_pad(T, sizeof(Real));
   constexpr int SB = adj_rows(RNEA) * T + block_pad(T, sizeof(Real));

@@ -341,6 +341,8 @@ int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int
   ar.frame = frame;
   int waves = (sh.T << sh.log2P) >> 6;
   if (OPS & (OP_CRBA | OP_JAC | OP_RNEA | OP_FK)) waves = std::max(waves, out_waves((int)sizeof(Real)));
+  if (waves * 64 > tree_max_threads((int)sizeof(Real)))
+    return fail(BARD_E_CAPACITY, "tree too wide for one workgroup's level sweep");
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_tree<Real, OPS>(dc->dm, ee, ar, (int)grid, waves * 64, lds, st);
@@ -365,6 +367,8 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   ar.logT = sh.logT;
   ar.log2P = sh.log2P;
   int waves = (sh.T << sh.log2P) >> 6;
+  if (waves * 64 > aba_max_threads((int)sizeof(Real)))
+    return fail(BARD_E_CAPACITY, "tree too wide for the articulated-body kernel in this precision");
   int64_t grid = (ar.B + sh.T - 1) / sh.T;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_aba<Real>(dc->dm, ar, (int)grid, waves * 64, lds, st);
@@ -407,6 +411,7 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
   ar.log2P = sh.log2P;
   ar.ntiles = (ar.B + sh.T - 1) / sh.T;
   const int waves = std::max((sh.T << sh.log2P) >> 6, 4);
+  if (waves * 64 > kAdjMaxThreads) return fail(BARD_E_CAPACITY, "tree too wide for the adjoint kernel");
   // One workgroup per resident slot, each looping over tiles (it prefetches
   // the next tile's inputs while it works on the current one).
   int per_cu = 0, cus = 0;

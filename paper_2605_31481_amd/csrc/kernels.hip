@@ -701,7 +701,7 @@ __device__ __forceinline__ void sym_mul(const Real* S, const Real* x, Real* y) {
 }
 
 template <class Real, int LOGT>
-__global__ void __launch_bounds__(256) aba_kernel(DevModel dm, Args<Real> ar) {
+__global__ void __launch_bounds__(aba_max_threads(sizeof(Real))) aba_kernel(DevModel dm, Args<Real> ar) {
   constexpr int T = 1 << LOGT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nv = dm.nv;

@@ -69,6 +69,11 @@ __host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
 // kernels need more registers).  The phases after the level sweep use every
 // wave, and more waves per SIMD hide more of their LDS latency.
 __host__ __device__ constexpr int tree_max_threads(int rs) { return rs == 4 ? 1024 : 512; }
+// Threads per workgroup of the articulated-body kernel (its sweep waves only);
+// FP64 keeps 4 waves, whose register budget its 6x6 free-root solve needs.
+__host__ __device__ constexpr int aba_max_threads(int rs) { return rs == 4 ? 512 : 256; }
+// Threads per workgroup of the adjoint kernels.
+constexpr int kAdjMaxThreads = 512;
 
 // Layout of the model's table image.  The device keeps one image per scalar
 // type laid out exactly as the workgroup wants it in LDS, so staging is a

@@ -258,6 +258,7 @@ int prepare_t(bard_plan* p) {
       waves = std::max(waves, (T << p->log2P[i]) >> 6);
     }
     if (g.lds > lim) return fail(BARD_E_CAPACITY, "a tree is too large for on-chip staging at this tile size");
+    if (waves * 64 > tree_max_threads(rs)) return fail(BARD_E_CAPACITY, "a tree is too wide for this tile size");
     g.block = waves * 64;
     if (count > 0) p->groups.push_back(g);
     return BARD_OK;

@@ -22,12 +22,13 @@ velocity coordinates, the body-frame twist ``[v; w]``.
 
 from .trees import (Tree, REVOLUTE, PRISMATIC, FREE, FIXED, chain7, humanoid_large,
                     humanoid_small, random_tree, multi_trees, MULTI_BATCHES, quadruped_spine,
-                    pendulum, two_link_planar, random_inertia_params, tree_by_name)
+                    pendulum, two_link_planar, random_inertia_params, tree_by_name,
+                    edge_tree, EDGE_TREES)
 from .inputs import random_state, sinusoid_trajectories, to_fp32_grid
 
 __all__ = [
     "Tree", "REVOLUTE", "PRISMATIC", "FREE", "FIXED", "chain7", "humanoid_large",
-    "humanoid_small", "random_tree", "multi_trees", "MULTI_BATCHES", "quadruped_spine", "pendulum",
+    "humanoid_small", "random_tree", "multi_trees", "MULTI_BATCHES", "quadruped_spine", "pendulum", "edge_tree", "EDGE_TREES",
     "two_link_planar", "random_inertia_params", "tree_by_name", "random_state",
     "sinusoid_trajectories", "to_fp32_grid",
 ]

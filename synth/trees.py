@@ -261,6 +261,55 @@ def two_link_planar(m1=1.5, m2=0.9, l1=0.8, lc1=0.35, lc2=0.3, i1=0.04, i2=0.025
                 ee_bodies=[1])
 
 
+def edge_tree(name: str) -> Tree:
+    """Trees at the limits the model compiler accepts and the degenerate cases
+    of the method.  Joint axes, offsets and inertias are drawn as for the
+    random trees (seed 3500 + a fixed index per name).
+
+    * ``chain64``: 64 revolute bodies in series (most bodies, depth 64).
+    * ``star64``: one root body with 63 children (level width 63).
+    * ``free_branches61``: free root with four 15-body branches mixing
+      revolute and prismatic joints (61 bodies, nv 66).
+    * ``rev1`` / ``pri1`` / ``free1``: a single revolute, prismatic or free body.
+    * ``prismatic8``: eight prismatic joints in series.
+    """
+    specs = {
+        "chain64": (list(range(-1, 63)), [REVOLUTE] * 64),
+        "star64": ([-1] + [0] * 63, [REVOLUTE] * 64),
+        "rev1": ([-1], [REVOLUTE]),
+        "pri1": ([-1], [PRISMATIC]),
+        "free1": ([-1], [FREE]),
+        "prismatic8": (list(range(-1, 7)), [PRISMATIC] * 8),
+    }
+    if name == "free_branches61":
+        parents, types = [-1], [FREE]
+        for b in range(4):
+            p = 0
+            for j in range(15):
+                parents.append(p)
+                types.append(PRISMATIC if (j + b) % 4 == 3 else REVOLUTE)
+                p = len(parents) - 1
+        specs[name] = (parents, types)
+    if name not in specs:
+        raise KeyError(name)
+    parents, types = specs[name]
+    index = sorted(list(specs)).index(name)
+    rng = np.random.default_rng(3500 + index)
+    n = len(parents)
+    is_leaf = [True] * n
+    for q in parents:
+        if q >= 0:
+            is_leaf[q] = False
+    depth = []
+    for i, q in enumerate(parents):
+        depth.append(1 if q < 0 else depth[q] + 1)
+    leaves = sorted([i for i in range(n) if is_leaf[i]], key=lambda i: (-depth[i], i))
+    return _build(name, parents, types, rng, ee=leaves[:4])
+
+
+EDGE_TREES = ["chain64", "star64", "free_branches61", "rev1", "pri1", "free1", "prismatic8"]
+
+
 def tree_by_name(name: str) -> Tree:
     table = {
         "chain7": chain7,
@@ -270,6 +319,8 @@ def tree_by_name(name: str) -> Tree:
     }
     if name in table:
         return table[name]()
+    if name in EDGE_TREES:
+        return edge_tree(name)
     if name.startswith("random"):
         n = int(name[len("random"):])
         sizes = [7, 11, 12, 18, 23]

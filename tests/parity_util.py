@@ -8,7 +8,9 @@ the check is normwise per (instance, output block):
 atol = 1e-6 and FP64 rtol = atol = 1e-12.  ABA is checked by its backward
 error, ``|RNEA_ref(q, qd, qdd_gpu) - tau|_inf <= atol + rtol * (|tau|_inf +
 |M|_inf |qdd_gpu|_inf + |RNEA_ref(q, qd, 0)|_inf)``, because its forward error
-is only bounded by cond(M) times the unit roundoff.
+is only bounded by cond(M) times the unit roundoff.  Trees whose sums are
+badly conditioned (a root carrying tens of children) are checked against the
+size of the summed terms instead of the result (assert_normwise_scaled).
 """
 
 import sys
@@ -59,6 +61,45 @@ def assert_normwise(name, gpu, ref, dtype):
     ok, worst = normwise(gpu, ref, rtol, atol)
     assert ok.all(), f"{name}: {int((~ok).sum())} blocks out of tolerance, worst err/bound = {worst:.3g}"
     return worst
+
+
+def assert_normwise_scaled(name, gpu, ref, scale, dtype):
+    """Normwise check against ``atol + rtol * max(max_k |ref|, scale)`` per
+    (instance, block); ``scale`` [B] is the size of the terms the result is a
+    sum of (see term_scales)."""
+    rtol, atol = TOL[dtype]
+    err = np.abs(gpu - ref).max(axis=-1)
+    bound = atol + rtol * np.maximum(np.abs(ref).max(axis=-1), scale[:, None])
+    ok = err <= bound
+    worst = float((err / bound).max())
+    assert ok.all(), f"{name}: {int((~ok).sum())} blocks out of tolerance, worst err/bound = {worst:.3g}"
+    return worst
+
+
+def term_scales(om, tree, q, qd, qdd):
+    """Sizes of the terms whose sums are the torque and the mass matrix.
+
+    RNEA is linear in the inertial parameters, so tau = sum_k tau^(k) with
+    tau^(k) the RNEA of body k's parameters alone, and likewise M.  Per
+    instance this returns max_i sum_k |tau^(k)_i| and max_ij sum_k |M^(k)_ij|.
+    An FP32 evaluation rounds the terms before it sums them, so its error is
+    of the order of u times these sums (the summation bound of Higham,
+    Accuracy and Stability of Numerical Algorithms, Sec. 4.2), which for a
+    root carrying many children can far exceed u times the result."""
+    B = q.shape[0]
+    st = np.zeros((B, tree.nv))
+    sm = np.zeros((B, tree.nv, tree.nv))
+    zero = np.zeros((B, tree.nv))
+    for k in range(tree.n_bodies):
+        pi = np.zeros_like(tree.inertia)
+        pi[k] = tree.inertia[k]
+        st += np.abs(om.rnea(q, qd, qdd, inertia=pi))
+        g = om.rnea(q, zero, zero, inertia=pi)
+        for j in range(tree.nv):
+            e = zero.copy()
+            e[:, j] = 1.0
+            sm[:, :, j] += np.abs(om.rnea(q, zero, e, inertia=pi) - g)
+    return st.max(axis=1), sm.reshape(B, -1).max(axis=1)
 
 
 def aba_backward_error(om, q, qd, tau, qdd_gpu, dtype):

@@ -1,0 +1,177 @@
+"""GPU parity at the limits the model compiler accepts and for the method's
+degenerate cases: the most bodies (a 64-body chain, depth 64), the widest
+level (a 64-body star), a free root with long mixed branches (61 bodies),
+single-body trees of every joint type, an all-prismatic chain, joint angles
+beyond the three-part argument reduction, and an exactly zero torque.
+
+A configuration whose on-chip staging does not fit one workgroup must be
+refused with BARD_E_CAPACITY (FP64 at 60+ bodies); everything else is held
+to the tolerance contract of parity_util, with the torque and mass-matrix
+bounds taken relative to the size of the summed per-body terms (a 64-body
+star's root torque sums terms up to 200 times its size)."""
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2605_31481_amd import bard
+from parity_util import (TOL, aba_backward_error, assert_normwise, assert_normwise_scaled, fk_ref_blocks, from_dev,
+                         inputs, oracle_for, say, term_scales, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+CAPACITY = -6
+
+CASES = [(name, dtype) for name in synth.EDGE_TREES for dtype in ("float32", "float64")]
+
+
+def _run_or_capacity(fn):
+    """Run an operator; return None if it reports BARD_E_CAPACITY."""
+    try:
+        return fn()
+    except bard.BardError as e:
+        assert e.status == CAPACITY, str(e)
+        return None
+
+
+@pytest.mark.parametrize("name,dtype", CASES)
+def test_edge_forward_operators(name, dtype):
+    B = 77
+    say(f"[gpu] edge forward {name} {dtype} B={B}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    om = oracle_for(tree)
+    q, qd, qdd = inputs(tree, B, 2900, dtype)
+    dq, dqd, dqdd = (to_dev(x, dtype) for x in (q, qd, qdd))
+    ee = tree.ee_bodies
+    refused = []
+    out = _run_or_capacity(lambda: m.fk(dq))
+    if out is None:
+        refused.append("fk")
+    else:
+        assert_normwise("fk", from_dev(out).reshape(B, tree.n_bodies, 12), fk_ref_blocks(om, q), dtype)
+    for frame in (0, 1):
+        out = _run_or_capacity(lambda: m.jacobian(dq, ee, frame=frame))
+        if out is None:
+            refused.append(f"jacobian{frame}")
+        else:
+            assert_normwise("jacobian", from_dev(out).reshape(B, len(ee), -1),
+                            om.jacobian(q, ee, frame=frame).reshape(B, len(ee), -1), dtype)
+    st, sm = term_scales(om, tree, q, qd, qdd)
+    out = _run_or_capacity(lambda: m.rnea(dq, dqd, dqdd))
+    tau = om.rnea(q, qd, qdd)
+    if out is None:
+        refused.append("rnea")
+    else:
+        assert_normwise_scaled("rnea", from_dev(out)[:, None], tau[:, None], st, dtype)
+    out = _run_or_capacity(lambda: m.crba(dq))
+    if out is None:
+        refused.append("crba")
+    else:
+        Mg = from_dev(out).reshape(B, tree.nv, tree.nv)
+        assert_normwise_scaled("crba", Mg.reshape(B, 1, -1), om.crba(q).reshape(B, 1, -1), sm, dtype)
+        assert np.array_equal(Mg, np.transpose(Mg, (0, 2, 1)))
+    tau_in = synth.to_fp32_grid(tau) if dtype == "float32" else tau
+    out = _run_or_capacity(lambda: m.aba(dq, dqd, to_dev(tau_in, dtype)))
+    if out is None:
+        refused.append("aba")
+    else:
+        ok, worst = aba_backward_error(om, q, qd, tau_in, from_dev(out), dtype)
+        assert ok.all(), f"aba backward error {worst:.3g}"
+    res = _run_or_capacity(lambda: m.chain(dq, dqd, dqdd, ee))
+    if res is None:
+        refused.append("chain")
+    else:
+        rt, rM, rJ = om.chain(q, qd, qdd, ee)
+        assert_normwise_scaled("chain tau", from_dev(res[0])[:, None], rt[:, None], st, dtype)
+        assert_normwise_scaled("chain M", from_dev(res[1]).reshape(B, 1, -1), rM.reshape(B, 1, -1), sm, dtype)
+        assert_normwise("chain J", from_dev(res[2]).reshape(B, len(ee), -1), rJ.reshape(B, len(ee), -1), dtype)
+    if refused:
+        say(f"[gpu]   refused with BARD_E_CAPACITY: {refused}")
+        assert dtype == "float64" and tree.n_bodies >= 60, (name, dtype, refused)
+
+
+FIXED_EDGE = [n for n in synth.EDGE_TREES if synth.tree_by_name(n).joint_type[0] != synth.FREE]
+
+
+@pytest.mark.parametrize("name", FIXED_EDGE)
+def test_edge_adjoints(name):
+    dtype = "float32"
+    B = 65
+    say(f"[gpu] edge adjoints {name} B={B}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    om = oracle_for(tree)
+    q, qd, qdd = inputs(tree, B, 2950, dtype)
+    tb = synth.to_fp32_grid(np.random.default_rng(5).standard_normal((B, tree.nv)))
+    pb = synth.to_fp32_grid(np.random.default_rng(6).standard_normal((B, tree.n_bodies * 12)))
+    qb, qdb, qddb, pib = m.rnea_vjp(*(to_dev(x, dtype) for x in (q, qd, qdd, tb)))
+    rq, rqd, rqdd, rpi = om.rnea_vjp(q, qd, qdd, tb)
+    assert_normwise("q_bar", from_dev(qb)[:, None], rq[:, None], dtype)
+    assert_normwise("qd_bar", from_dev(qdb)[:, None], rqd[:, None], dtype)
+    assert_normwise("qdd_bar", from_dev(qddb)[:, None], rqdd[:, None], dtype)
+    rtol, atol = TOL[dtype]
+    bound = (atol + rtol * np.abs(rpi).max(axis=2)).sum(axis=0)
+    assert (np.abs(pib.cpu().double().numpy() - rpi.sum(axis=0)).max(axis=1) <= bound).all()
+    fq = m.fk_vjp(to_dev(q, dtype), to_dev(pb, dtype))
+    assert_normwise("fk q_bar", from_dev(fq)[:, None], om.fk_vjp(q, pb.reshape(B, -1, 3, 4))[:, None], dtype)
+
+
+def test_edge_trees_in_one_plan():
+    import torch
+    say("[gpu] edge trees in one plan")
+    names = synth.EDGE_TREES
+    trees = [synth.tree_by_name(n) for n in names]
+    batches = [40 + 13 * k for k in range(len(trees))]
+    models = [bard.Model.from_tree(t) for t in trees]
+    host = [inputs(t, B, 3050 + k, "float32") for k, (t, B) in enumerate(zip(trees, batches))]
+    dev = [tuple(to_dev(x, "float32") for x in h) for h in host]
+    plan = bard.Plan(models, batches)
+    plan.configure(8, 0, 0)   # the star needs 64 lanes per instance: only 8-instance tiles fit
+    outs = plan.run(dev)
+    torch.cuda.synchronize()
+    for k, (tree, (q, qd, qdd), (tau, M, J)) in enumerate(zip(trees, host, outs)):
+        ee = plan.ee(k)
+        rt, rM, rJ = oracle_for(tree).chain(q, qd, qdd, ee)
+        B = q.shape[0]
+        st, sm = term_scales(oracle_for(tree), tree, q, qd, qdd)
+        assert_normwise_scaled(f"plan tau {names[k]}", from_dev(tau)[:, None], rt[:, None], st, "float32")
+        assert_normwise_scaled(f"plan M {names[k]}", from_dev(M).reshape(B, 1, -1), rM.reshape(B, 1, -1), sm,
+                               "float32")
+        assert_normwise(f"plan J {names[k]}", from_dev(J).reshape(B, len(ee), -1), rJ.reshape(B, len(ee), -1),
+                        "float32")
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_large_joint_angles(dtype):
+    """Angles beyond 1e5 rad take the device library's sine and cosine; the
+    oracle's quaternion route gives the same rotations."""
+    say(f"[gpu] large joint angles {dtype}")
+    tree = synth.chain7()
+    m = bard.Model.from_tree(tree)
+    om = oracle_for(tree)
+    B = 96
+    rng = np.random.default_rng(11)
+    q = rng.uniform(-1.0, 1.0, size=(B, 7)) * np.array([1e6, 3e5, 2e5, np.pi, -np.pi, 1e5, 7e5])
+    qd, qdd = rng.standard_normal((B, 7)), rng.standard_normal((B, 7))
+    if dtype == "float32":
+        q, qd, qdd = (synth.to_fp32_grid(x) for x in (q, qd, qdd))
+    out = m.fk(to_dev(q, dtype))
+    assert_normwise("fk", from_dev(out).reshape(B, 7, 12), fk_ref_blocks(om, q), dtype)
+    tau = m.rnea(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype))
+    assert_normwise("rnea", from_dev(tau)[:, None], om.rnea(q, qd, qdd)[:, None], dtype)
+
+
+@pytest.mark.parametrize("name", ["humanoid_large", "quadruped_spine"])
+def test_zero_motion_without_gravity_gives_zero_torque(name):
+    """With g = 0, qd = 0 and qdd = 0 every term of RNEA vanishes, so the
+    torque is exactly zero (no rounding can create a non-zero value)."""
+    import torch
+    say(f"[gpu] zero torque {name}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, gravity=[0.0, 0.0, 0.0])
+    q, _, _ = inputs(tree, 300, 3100, "float32")
+    z = np.zeros((300, tree.nv))
+    tau = m.rnea(to_dev(q, "float32"), to_dev(z, "float32"), to_dev(z, "float32"))
+    torch.cuda.synchronize()
+    assert not tau.abs().max().item()
