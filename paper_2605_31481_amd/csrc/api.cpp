@@ -96,6 +96,7 @@ std::vector<unsigned char> table_image(const bard_model* m, int rs) {
   std::memcpy(&img[t.dlist], m->dlist.data(), m->dlist.size() * sizeof(int));
   for (int k = 0; k < 4; ++k)
     std::memcpy(&img[t.ulist + k * 8 * m->n * 4], m->ulist[k].data(), m->ulist[k].size() * sizeof(int));
+  if (!m->jump.empty()) std::memcpy(&img[t.jump], m->jump.data(), m->jump.size());
   std::memcpy(&img[t.mtab], m->mtab.data(), m->mtab.size() * sizeof(int));
   return img;
 }
@@ -139,6 +140,17 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
   for (int k = 0; k < 4; ++k) dm.ulen[k] = (int)m->ulist[k].size();
   dm.n_mpair = m->n_mpair;
   dm.n_mzero = m->n_mzero;
+  dm.jsteps = m->jsteps;
+  // Pointer jumping takes three scans of jsteps barrier steps plus three
+  // setup phases, each moving all state through LDS; the sweep keeps it in
+  // registers.  Measured per chain launch at B = 4096 (FP32): depth 64 chain
+  // 102 us scan vs 131 us sweep; depth 16 tree 62 vs 50; depth 9 humanoid
+  // 23 vs 20; depth 7-8 chains even.
+  dm.use_scan = m->depth >= 32 ? 1 : 0;
+  if (const char* k = getenv("BARD_KINEMATICS")) {  // "scan" or "sweep" forces one path
+    if (!strcmp(k, "scan")) dm.use_scan = 1;
+    if (!strcmp(k, "sweep")) dm.use_scan = 0;
+  }
   for (int k = 0; k < 3; ++k) {
     dm.g32[k] = (float)m->g[k];
     dm.g64[k] = m->g[k];
@@ -226,6 +238,10 @@ Shape pick_shape(const bard_model* m, int dev, PlanBytes bytes_for) {
   // sweep waves, then more lanes per instance) until the LDS plan fits.
   int log2P = m->log2P;
   int target = default_target_T();
+  // Narrow trees (a chain has one lane per instance) would put 64 instances
+  // in one wave; more lanes per instance keep the tile at the target, so a
+  // batch spreads over more workgroups (idle lanes cost nothing extra).
+  while ((64 >> log2P) > target && log2P < 6) ++log2P;
   int waves = std::max(1, std::min(4, target / (64 >> log2P)));
   while (waves * (64 >> log2P) < 8) ++waves;  // wide trees: at least 8 instances
   size_t lim = lds_limit(dev);

@@ -224,6 +224,16 @@ int compile_model(bard_model* m, std::string* err) {
       for (int k = (int)ch.size() - 1; k >= 0; --k) stack.push_back(ch[k]);
     }
   }
+  // ---- pointer-jumping tables: ancestor of each body at distance 2^s ----
+  m->jsteps = 0;
+  while ((1 << m->jsteps) < m->depth) ++m->jsteps;
+  m->jump.assign((size_t)m->jsteps * n, -1);
+  for (int s = 0; s < m->jsteps; ++s)
+    for (int i = 0; i < n; ++i) {
+      int a = i;
+      for (int k = 0; k < (1 << s) && a >= 0; ++k) a = m->parent[a];
+      m->jump[(size_t)s * n + i] = (int8_t)a;
+    }
   m->dlist.resize(n);
   for (int i = 0; i < n; ++i) m->dlist[i] = i;
   std::stable_sort(m->dlist.begin(), m->dlist.end(),

@@ -301,6 +301,7 @@ struct Tables {
   const I4* bm2;
   const int* dlist;
   const int* ulist;
+  const int8_t* jump;
   const int* mtab;
 };
 
@@ -317,6 +318,7 @@ __device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const 
   v.bm2 = reinterpret_cast<const I4*>(base + t.bm2);
   v.dlist = reinterpret_cast<const int*>(base + t.dlist);
   v.ulist = reinterpret_cast<const int*>(base + t.ulist);
+  v.jump = reinterpret_cast<const int8_t*>(base + t.jump);
   v.mtab = reinterpret_cast<const int*>(base + t.mtab);
   return v;
 }

@@ -134,7 +134,257 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   const int wave = tid >> 6;
   const int log2P = ar.log2P;
   const int WA = (T << log2P) >> 6;
-  const bool early_zero = nt > WA * 64;  // some waves are free during the sweep
+  // Deep trees take the kinematics by pointer jumping (all waves, LDS-resident
+  // state, ceil(log2(depth)) steps per quantity); others by the level sweep
+  // (registers, depth steps, exchanges only where the tree branches).  The
+  // model compiler picks the one with fewer steps.
+  const bool SCAN = NEED_BODY && dm.use_scan;
+  // Structural zeros are stored during the kinematics phase (by every
+  // thread in the scan, by the waves the level sweep leaves idle otherwise).
+  const bool early_zero = SCAN || nt > WA * 64;
+
+  if (SCAN) {
+    // ---------------- 2. kinematics by pointer jumping ----------------
+    // A body's pose is the product of the joint transforms on its root path
+    // and its velocity and acceleration are sums over that path, so all of
+    // them follow in ceil(log2(depth)) steps: at step k every body combines
+    // its partial result with that of its ancestor 2^k levels up.  Every
+    // (body, instance) item is one thread's work in every step.
+    const int inx = tid & (T - 1);
+    const int rb = tid >> LOGT, rbs = nt >> LOGT;
+    const int JS = dm.jsteps;
+    const Real a0[6] = {Real(0), Real(0), Real(0), -grav<Real>(dm, 0), -grav<Real>(dm, 1), -grav<Real>(dm, 2)};
+    auto blk = [&](int bb) { return body_l + tb.bm2[bb].x * SB + inx; };
+    // six-row per-body scratch for the velocity and acceleration scans: the
+    // fc blocks, unused until the subtree phase
+    auto scr = [&](int bb) { return fc_l + bb * SD + inx; };
+    // The structural zeros of M and J depend on nothing computed here; stored
+    // first, they drain while the scans run.
+    {
+      const int64_t bz = tile0 + inx;
+      if (bz < ar.B) {
+        if (CRBA) {
+          Real* out = ar.M + bz * ar.sM_b;
+          const int* mz = tb.mtab + dm.n_mpair;
+          for (int k = rb; k < dm.n_mzero; k += rbs) put(&out[(int64_t)mz[k] * ar.sM_k], Real(0), ar.stream_out);
+        }
+        if (JAC) {
+          Real* out = ar.J + bz * ar.sJ_b;
+          const int* jz = jrow + ee.n_col;
+          for (int k = rb; k < ee.n_zero; k += rbs) put(&out[(int64_t)jz[k] * ar.sJ_k], Real(0), ar.stream_out);
+        }
+      }
+    }
+    if (!hit) {
+      // joint transforms (eqs. (4)-(5); the free root's from its quaternion),
+      // placed so that the last pose step writes rows 0-11
+      const int rq = (JS & 1) ? 12 : 0;
+      for (int bb = rb; bb < n; bb += rbs) {
+        const I4 meta = tb.meta[bb];
+        Real R[9], p[3];
+        if (meta.y == J_FREE) {
+          Real qr[7], o[3];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) qr[k] = q_l[(meta.z + k) * T + inx];
+          free_root_pose(tb.cst + bb * CST, qr, R, o);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            p[k] = Real(0);
+            o_l[k * T + inx] = o[k];
+          }
+        } else {
+          joint_transform(tb.cst + bb * CST, q_l[meta.z * T + inx], R, p);
+        }
+        Real* br = blk(bb) + rq * T;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) br[k * T] = R[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) br[(9 + k) * T] = p[k];
+      }
+      if (!dm.free_root)
+        for (int i = tid; i < 3 * T; i += nt) o_l[i] = Real(0);
+      __syncthreads();
+      // poses: Q_i <- Q_jump(i) Q_i, rows 0-11 and 12-23 taking turns
+      for (int st = 0, cur = rq; st < JS; ++st, cur ^= 12) {
+        const int8_t* jmp = tb.jump + st * n;
+        for (int bb = rb; bb < n; bb += rbs) {
+          const Real* sr = blk(bb) + cur * T;
+          Real R[9], p[3];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) R[k] = sr[k * T];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) p[k] = sr[(9 + k) * T];
+          const int j = jmp[bb];
+          if (j >= 0) {
+            const Real* sa = blk(j) + cur * T;
+            Real Ra[9], pa[3], Rn[9], pn[3];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Ra[k] = sa[k * T];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pa[k] = sa[(9 + k) * T];
+            mul33(Ra, R, Rn);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) pn[i] = Ra[3 * i] * p[0] + Ra[3 * i + 1] * p[1] + Ra[3 * i + 2] * p[2] + pa[i];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) R[k] = Rn[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) p[k] = pn[k];
+          }
+          Real* dr = blk(bb) + (cur ^ 12) * T;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) dr[k * T] = R[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) dr[(9 + k) * T] = p[k];
+        }
+        __syncthreads();
+      }
+    }
+    // motion subspaces (eq. (7)) unless staged, and the velocity terms s qd;
+    // the velocity scan then ends in rows 12-17
+    auto vbuf = [&](int which, int bb) { return which ? scr(bb) : blk(bb) + 12 * T; };
+    auto abuf = [&](int which, int bb) { return which ? scr(bb) : blk(bb) + 18 * T; };
+    // (kernels without an s region, FK alone, stop at the poses)
+    if (NEED_S) for (int bb = rb; bb < n; bb += rbs) {
+      const I4 meta = tb.meta[bb];
+      const bool freej = meta.y == J_FREE;
+      const int nd = freej ? 6 : 1;
+      Real vs[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
+      if (!hit) {
+        const Real* br = blk(bb);
+        Real R[9], p[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = br[k * T];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[k] = br[(9 + k) * T];
+        for (int d = 0; d < nd; ++d) {
+          Real sv[6];
+          if (freej) {
+            // free root (at the base origin): v dofs -> [0; R e_k], w dofs -> [R e_k; 0]
+            const int k = d % 3;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              sv[i] = (d >= 3) ? R[3 * i + k] : Real(0);
+              sv[3 + i] = (d < 3) ? R[3 * i + k] : Real(0);
+            }
+          } else {
+            const Real* ax = tb.cst + bb * CST + C_AX;
+            Real u[3], pxu[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) u[i] = R[3 * i] * ax[0] + R[3 * i + 1] * ax[1] + R[3 * i + 2] * ax[2];
+            cross3(p, u, pxu);
+            const bool rev = meta.y == J_REV;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              sv[i] = rev ? u[i] : Real(0);
+              sv[3 + i] = rev ? pxu[i] : u[i];
+            }
+          }
+          Real* sr = s_l + (meta.w + d) * SD + inx;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) sr[k * T] = sv[k];
+          if (VEL) {
+            const Real qdv = qd_l[(meta.w + d) * T + inx];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) vs[k] += sv[k] * qdv;
+          }
+        }
+      } else if (VEL) {
+        for (int d = 0; d < nd; ++d) {
+          const Real* sr = s_l + (meta.w + d) * SD + inx;
+          const Real qdv = qd_l[(meta.w + d) * T + inx];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) vs[k] += sr[k * T] * qdv;
+        }
+      }
+      if (VEL) {
+        Real* vr = vbuf(JS & 1, bb);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) vr[k * T] = vs[k];
+      }
+    }
+    if (JAC && ar.frame == 1 && !hit)  // end-effector origins
+      for (int i = tid; i < ee.n_ee * 3 * T; i += nt) {
+        const int r = i >> LOGT, in = i & (T - 1);
+        const int e = r / 3, c = r - 3 * e;
+        pe_l[i] = body_l[tb.bm2[eeb_l[e]].x * SB + (9 + c) * T + in];
+      }
+    if (VEL) {
+      __syncthreads();
+      // velocities: V_i <- V_i + V_jump(i)
+      for (int st = 0, cur = JS & 1; st < JS; ++st, cur ^= 1) {
+        const int8_t* jmp = tb.jump + st * n;
+        for (int bb = rb; bb < n; bb += rbs) {
+          const Real* sr = vbuf(cur, bb);
+          Real V[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) V[k] = sr[k * T];
+          const int j = jmp[bb];
+          if (j >= 0) {
+            const Real* sa = vbuf(cur, j);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) V[k] += sa[k * T];
+          }
+          Real* dr = vbuf(cur ^ 1, bb);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) dr[k * T] = V[k];
+        }
+        __syncthreads();
+      }
+      // acceleration terms s qdd + v_parent x (s qd), plus a0 at the roots
+      for (int bb = rb; bb < n; bb += rbs) {
+        const I4 meta = tb.meta[bb];
+        const int nd = (meta.y == J_FREE) ? 6 : 1;
+        Real vJ[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
+        Real A[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) A[k] = (meta.x < 0) ? a0[k] : Real(0);
+        for (int d = 0; d < nd; ++d) {
+          const Real* sr = s_l + (meta.w + d) * SD + inx;
+          const Real qdv = qd_l[(meta.w + d) * T + inx];
+          const Real qddv = qdd_l[(meta.w + d) * T + inx];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) {
+            const Real sk = sr[k * T];
+            vJ[k] += sk * qdv;
+            A[k] += sk * qddv;
+          }
+        }
+        if (meta.x >= 0) {
+          const Real* vp = blk(meta.x) + 12 * T;
+          Real v6[6], c6[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) v6[k] = vp[k * T];
+          crm(v6, vJ, c6);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) A[k] += c6[k];
+        }
+        Real* ar_ = abuf(JS & 1, bb);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ar_[k * T] = A[k];
+      }
+      __syncthreads();
+      // accelerations: A_i <- A_i + A_jump(i), ending in rows 18-23
+      for (int st = 0, cur = JS & 1; st < JS; ++st, cur ^= 1) {
+        const int8_t* jmp = tb.jump + st * n;
+        for (int bb = rb; bb < n; bb += rbs) {
+          const Real* sr = abuf(cur, bb);
+          Real A[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) A[k] = sr[k * T];
+          const int j = jmp[bb];
+          if (j >= 0) {
+            const Real* sa = abuf(cur, j);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A[k] += sa[k * T];
+          }
+          Real* dr = abuf(cur ^ 1, bb);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) dr[k * T] = A[k];
+        }
+        __syncthreads();
+      }
+    }
+  } else {
 
   // Joint transforms (eqs. (4)-(5)) depend on q only, so every wave computes
   // them, one (body, instance) item per thread, into rows 12-23 of the body's
@@ -409,6 +659,8 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         for (int k = r0z; k < ee.n_zero; k += rsz) put(&out[(int64_t)jz[k] * ar.sJ_k], Real(0), ar.stream_out);
       }
     }
+  }
+
   }
 
   if (BACK || FK || JAC) __syncthreads();

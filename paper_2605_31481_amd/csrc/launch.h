@@ -80,7 +80,7 @@ constexpr int kAdjMaxThreads = 512;
 // single copy of 16-byte chunks.  mtab comes last so kernels that do not need
 // it copy only the prefix.
 struct TabLayout {
-  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, ulist, mtab, end_nomtab, end;
+  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, ulist, jump, mtab, end_nomtab, end;
 };
 
 __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kmax, int nv, int rs) {
@@ -100,6 +100,7 @@ __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kma
   t.bm2 = take(n * 16);    // per body {preorder position, subtree size, v index, dofs}
   t.dlist = take(n * 4);   // bodies by decreasing subtree size
   t.ulist = take(4 * 8 * n * 4);  // subtree-phase work lists for 1, 2, 4, 8 row groups per wave
+  t.jump = take(6 * n);           // pointer-jumping ancestors for up to 6 steps (depth <= 64)
   t.end_nomtab = off;
   t.mtab = take(nv * nv * 4);
   t.end = off;
@@ -155,7 +156,9 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
     const bool need_body = ops & (OP_FK | OP_RNEA | OP_CRBA);
     L.s = need_s ? take((nv + 1) * (6 * T + pad) * rs) : off;
     L.body = need_body ? take(n * (24 * T + pad) * rs) : off;
-    L.fc = (ops & OP_CRBA) ? take((nv + 1) * (6 * T + pad) * rs) : off;
+    // fc: CRBA's Ic_i s blocks; RNEA kernels use them first as the scratch of
+    // the velocity and acceleration scans
+    L.fc = (ops & (OP_CRBA | OP_RNEA)) ? take((nv + 1) * (6 * T + pad) * rs) : off;
     L.o = take(3 * T * rs);
     L.pe = ((ops & OP_JAC) && frame == 1) ? take(n_ee * 3 * T * rs) : off;
   } else {

@@ -44,6 +44,8 @@ struct DevModel {
   int n, nq, nv, depth, P, log2P, kmax, free_root;
   int ulen[4];  // entries of the subtree work lists for 1, 2, 4, 8 row groups per wave
   int n_mpair, n_mzero;  // mass-matrix output lists (pairs, then zero entries)
+  int jsteps;            // pointer-jumping steps: ceil(log2(depth))
+  int use_scan;          // 1: kinematics by pointer jumping instead of the level sweep
   float g32[3];
   double g64[3];
 };
@@ -71,6 +73,8 @@ struct bard_model {
   bool free_root = false;
   std::vector<int> parent, jtype, qi, vi, nvi, level_of, slot_of;
   std::vector<int> dfs, sub_size, dlist;  // preorder position, subtree size, bodies by subtree size
+  int jsteps = 0;
+  std::vector<int8_t> jump;               // [jsteps][n]: ancestor at distance 2^step, or -1
   std::vector<int> ulist[4];              // subtree work lists (see subtree_units)
   std::vector<double> axis, xtree, inertia;
   double g[3] = {0.0, 0.0, -9.81};
