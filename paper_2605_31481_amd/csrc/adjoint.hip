@@ -67,14 +67,13 @@ __device__ __forceinline__ void subtree_sums(const Tables<Real>& tb, const DevMo
     const int np = valid ? ((code >> 12) & 0xf) : 1;
     const bool split = ((ul[base] >> 12) & 0xf) > 1;  // same for the whole wave
     const I4 m2 = tb.bm2[bb];
-    const int chunk = (m2.y + np - 1) / np;
-    const int c0 = part * chunk;
-    const int c1 = valid ? min(m2.y, c0 + chunk) : 0;
+    // part p sums positions p, p + np, ... so row groups read adjacent blocks
+    const int c1 = valid ? m2.y : 0;
     Real S[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) S[k] = Real(0);
-    const Real* br = body_l + (m2.x + c0) * SB + R0 * T + in;
-    for (int c = c0; c < c1; ++c, br += SB)
+    const Real* br = body_l + (m2.x + part) * SB + R0 * T + in;
+    for (int c = part; c < c1; c += np, br += np * SB)
 #pragma unroll
       for (int k = 0; k < NR; ++k) S[k] += br[k * T];
     if (U > 1 && split)

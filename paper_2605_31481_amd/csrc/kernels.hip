@@ -750,16 +750,17 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         const int np = valid ? ((code >> 12) & 0xf) : 1;
         const bool split = ((ul[base] >> 12) & 0xf) > 1;  // same for the whole wave
         const I4 m2 = tb.bm2[bb];  // {preorder position, subtree size, v index, dofs}
-        const int chunk = (m2.y + np - 1) / np;
-        const int c0 = part * chunk;
-        const int c1 = valid ? min(m2.y, c0 + chunk) : 0;
+        // Part p of a split body sums positions p, p + np, p + 2 np, ... of
+        // its range, so the row groups of a wave read adjacent blocks (blocks
+        // a fixed distance apart would share LDS banks).
+        const int c1 = valid ? m2.y : 0;
         Real F[6], Ic[10];
 #pragma unroll
         for (int k = 0; k < 6; ++k) F[k] = Real(0);
 #pragma unroll
         for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
-        const Real* br = body_l + (m2.x + c0) * SB + in;
-        for (int c = c0; c < c1; ++c, br += SB) {
+        const Real* br = body_l + (m2.x + part) * SB + in;
+        for (int c = part; c < c1; c += np, br += np * SB) {
           if (RNEA)
 #pragma unroll
             for (int k = 0; k < 6; ++k) F[k] += br[k * T];

@@ -113,10 +113,11 @@ __host__ __device__ inline int ee_image_bytes(int n_ee, int nv) {
 }
 
 // Padding (in elements) added to the stride of every per-dof and per-body
-// block of rows.  A row holds one scalar of the T instances of a tile; with
-// FP32 and T = 16 a 64-lane access touches four blocks at once and unpadded
-// block strides are multiples of the 32 LDS banks.
-__host__ __device__ constexpr int block_pad(int T, int rs) { return (rs == 4 && T == 16) ? 16 : 0; }
+// block of rows.  A row holds one scalar of the T instances of a tile, so a
+// 64-lane FP32 access touches 64 / T blocks at once; unpadded strides (6T or
+// 24T words) are multiples of the 64 LDS banks for T = 8, 16, 32, and a pad
+// of T words puts those blocks on disjoint banks.
+__host__ __device__ constexpr int block_pad(int T, int rs) { return (rs == 4 && T < 64) ? T : 0; }
 
 // Byte offsets of the regions a workgroup stages in LDS.  Computed by the same
 // function on the host (to size the launch) and in the kernels.  Per-dof
