@@ -90,6 +90,7 @@ std::vector<unsigned char> table_image(const bard_model* m, int rs) {
   std::memcpy(&img[t.ssrc], m->sched_src.data(), m->sched_src.size());
   std::memcpy(&img[t.cslot], m->child_slot.data(), m->child_slot.size());
   std::memcpy(&img[t.linfo], m->level_info.data(), m->level_info.size() * sizeof(int));
+  std::memcpy(&img[t.srec], m->srec.data(), m->srec.size() * sizeof(I4));
   std::vector<I4> bm2(m->n);
   for (int i = 0; i < m->n; ++i) bm2[i] = I4{m->dfs[i], m->sub_size[i], m->vi[i], m->nvi[i]};
   std::memcpy(&img[t.bm2], bm2.data(), bm2.size() * sizeof(I4));
@@ -141,6 +142,7 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
   dm.n_mpair = m->n_mpair;
   dm.n_mzero = m->n_mzero;
   dm.jsteps = m->jsteps;
+  dm.xmask = m->xmask;
   // Pointer jumping takes three scans of jsteps barrier steps plus three
   // setup phases, each moving all state through LDS; the sweep keeps it in
   // registers.  Measured per chain launch at B = 4096 (FP32): depth 64 chain

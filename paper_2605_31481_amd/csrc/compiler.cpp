@@ -224,6 +224,23 @@ int compile_model(bard_model* m, std::string* err) {
       for (int k = (int)ch.size() - 1; k >= 0; --k) stack.push_back(ch[k]);
     }
   }
+  // ---- level-sweep records: everything one (level, slot) step needs, in one
+  // 16-byte entry, so a lane reads it a level ahead and issues all of the
+  // step's loads at once: {body, preorder position, q index,
+  // v index | source slot << 8 | active << 16 | revolute << 17}.  Empty slots
+  // step on body 0 and store nothing.
+  m->srec.assign((size_t)depth * P, I4{0, 0, 0, 0});
+  m->xmask = 0;
+  for (int l = 0; l < depth; ++l) {
+    if (m->level_info[2 * l + 1]) m->xmask |= 1ull << l;
+    for (int s = 0; s < P; ++s) {
+      const int b = m->sched_body[l * P + s];
+      const int bb = b >= 0 ? b : 0;
+      const int flags = m->vi[bb] | (int)(uint8_t)m->sched_src[l * P + s] << 8 | (b >= 0 ? 1 : 0) << 16 |
+                        (m->jtype[bb] == J_REV ? 1 : 0) << 17;
+      m->srec[(size_t)l * P + s] = I4{bb, m->dfs[bb], m->qi[bb], flags};
+    }
+  }
   // ---- pointer-jumping tables: ancestor of each body at distance 2^s ----
   m->jsteps = 0;
   while ((1 << m->jsteps) < m->depth) ++m->jsteps;

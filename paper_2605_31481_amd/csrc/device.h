@@ -298,6 +298,7 @@ struct Tables {
   const int8_t* ssrc;
   const int8_t* cslot;
   const int* linfo;
+  const I4* srec;
   const I4* bm2;
   const int* dlist;
   const int* ulist;
@@ -315,6 +316,7 @@ __device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const 
   v.ssrc = reinterpret_cast<const int8_t*>(base + t.ssrc);
   v.cslot = reinterpret_cast<const int8_t*>(base + t.cslot);
   v.linfo = reinterpret_cast<const int*>(base + t.linfo);
+  v.srec = reinterpret_cast<const I4*>(base + t.srec);
   v.bm2 = reinterpret_cast<const I4*>(base + t.bm2);
   v.dlist = reinterpret_cast<const int*>(base + t.dlist);
   v.ulist = reinterpret_cast<const int*>(base + t.ulist);

@@ -520,19 +520,21 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       Real q, qd, qdd;
       int bb, act, src, rev, vi, pos;
     };
-    auto load_level = [&](int l, LevelIn& L) {
-      const int body = in_sched ? tb.sbody[l * P + slot] : -1;
-      L.act = body >= 0;
-      L.bb = L.act ? body : 0;
-      L.src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
-      const I4 meta = tb.meta[L.bb];
-      L.rev = meta.y == J_REV;
-      L.vi = meta.w;
-      L.pos = tb.bm2[L.bb].x;
-      L.q = qi_l[meta.z * T];
+    // The (level, slot) record is read one level ahead, so every load of a
+    // step (joint transform, axis, q, qd, qdd) is issued at once, together
+    // with the exchange, instead of behind a chain of dependent table reads.
+    auto load_level = [&](const I4 rec, LevelIn& L) {
+      const int fl = rec.w;
+      L.act = in_sched && ((fl >> 16) & 1);
+      L.bb = rec.x;
+      L.src = lane0 + (in_sched ? ((fl >> 8) & 255) : slot_raw);
+      L.rev = (fl >> 17) & 1;
+      L.vi = fl & 255;
+      L.pos = rec.y;
+      L.q = qi_l[rec.z * T];
       if (VEL) {
-        L.qd = qdi_l[meta.w * T];
-        L.qdd = qddi_l[meta.w * T];
+        L.qd = qdi_l[L.vi * T];
+        L.qdd = qddi_l[L.vi * T];
       }
       {
         const Real* c = tb.cst + L.bb * CST;
@@ -564,10 +566,15 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
     };
     if (!hit) {
+      const I4* srec = tb.srec + slot;
+      I4 rnext = I4{0, 0, 0, 0};
+      if (lstart < dm.depth) rnext = srec[lstart * P];
       for (int l = lstart; l < dm.depth; ++l) {
+        const I4 rec = rnext;
+        if (l + 1 < dm.depth) rnext = srec[(l + 1) * P];
         LevelIn cur;
-        load_level(l, cur);
-        if (tb.linfo[2 * l + 1]) {
+        load_level(rec, cur);
+        if ((dm.xmask >> l) & 1) {
           const int src = cur.src;
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
@@ -614,25 +621,25 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
     } else if (VEL) {
       // Workspace hit: poses and s are staged; only v and a propagate.
+      const I4* srec = tb.srec + slot;
       for (int l = lstart; l < dm.depth; ++l) {
-        const int body = in_sched ? tb.sbody[l * P + slot] : -1;
-        const int bb = body >= 0 ? body : 0;
-        if (tb.linfo[2 * l + 1]) {
-          const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
+        const I4 rec = srec[l * P];
+        const int vi = rec.w & 255;
+        if ((dm.xmask >> l) & 1) {
+          const int src = lane0 + (in_sched ? ((rec.w >> 8) & 255) : slot_raw);
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
             v[k] = xch(v[k], src);
             a[k] = xch(a[k], src);
           }
         }
-        const I4 meta = tb.meta[bb];
         Real s[6];
-        const Real* sr = s_l + meta.w * SD + inst;
+        const Real* sr = s_l + vi * SD + inst;
 #pragma unroll
         for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
-        propagate(s, qdi_l[meta.w * T], qddi_l[meta.w * T]);
-        if (body >= 0) {
-          Real* br = body_l + tb.bm2[bb].x * SB + inst;
+        propagate(s, qdi_l[vi * T], qddi_l[vi * T]);
+        if (in_sched && ((rec.w >> 16) & 1)) {
+          Real* br = body_l + rec.y * SB + inst;
 #pragma unroll
           for (int k = 0; k < 6; ++k) {
             br[(12 + k) * T] = v[k];
@@ -695,8 +702,50 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   const int64_t bo = tile0 + in;
   const bool bok = full || bo < ar.B;
 
+  // Jacobian columns on an end effector's root path: the 6 rows of column c of
+  // block e are [v + sgn p x w; w] from s_c = [w; v], with p the world origin
+  // relative to the base (o, sgn = +1) or the end-effector origin (p_e,
+  // sgn = -1).  They depend on the kinematics only, so when the body phase
+  // leaves row groups idle (more row groups than bodies) those store them
+  // meanwhile, and the writes overlap the inertia arithmetic.
+  auto store_jac_columns = [&](int k0, int kstep) {
+    const int NC = ee.n_col;
+    const bool world = ar.frame == 0;
+    const Real sgn = world ? Real(1) : Real(-1);
+    Real* out = ar.J + bo * ar.sJ_b;
+    for (int k = k0; k < NC; k += 2 * kstep) {
+      Real val[2][6];
+      int code[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int kk = k + u * kstep;
+        code[u] = (kk < NC) ? jrow[kk] : nv;  // the tail reads the all-zero block
+        const Real* s = s_l + (code[u] & 0xff) * SD + in;
+        const Real* P = world ? (o_l + in) : (pe_l + (code[u] >> 8) * 3 * T + in);
+        const Real w0 = s[0], w1 = s[T], w2 = s[2 * T];
+        const Real p0 = P[0], p1 = P[T], p2 = P[2 * T];
+        val[u][0] = s[3 * T] + sgn * (p1 * w2 - p2 * w1);
+        val[u][1] = s[4 * T] + sgn * (p2 * w0 - p0 * w2);
+        val[u][2] = s[5 * T] + sgn * (p0 * w1 - p1 * w0);
+        val[u][3] = w0;
+        val[u][4] = w1;
+        val[u][5] = w2;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (k + u * kstep < NC) {
+          const int c = code[u] & 0xff, e = code[u] >> 8;
+          Real* o = out + (int64_t)(e * 6 * nv + c) * ar.sJ_k;
+#pragma unroll
+          for (int r = 0; r < 6; ++r) put(&o[(int64_t)(r * nv) * ar.sJ_k], val[u][r], ar.stream_out);
+        }
+    }
+  };
+  const bool jac_early = JAC && BACK && rstep > n;
+
   // ---------------- 3. body phase: world inertia and body force ----------------
   if (BACK) {
+    if (jac_early && r0 >= n && bok) store_jac_columns(r0 - n, rstep - n);
     for (int bb = r0; bb < n; bb += rstep) {
       Real* br = body_l + tb.bm2[bb].x * SB + in;
       Real R[9], p[3], pic[10], I0[10];
@@ -854,43 +903,10 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     }
   }
   if (JAC) {
-    // Columns on an end effector's root path: the 6 rows of column c of block
-    // e are [v + sgn p x w; w] from s_c = [w; v], with p the world origin
-    // relative to the base (o, sgn = +1) or the end-effector origin (p_e,
-    // sgn = -1).  Off-path rows are zeros from their own list.
-    const int NC = ee.n_col;
-    const bool world = ar.frame == 0;
-    const Real sgn = world ? Real(1) : Real(-1);
-    Real* out = ar.J + bo * ar.sJ_b;
-    for (int k = r0; k < NC; k += 2 * rstep) {
-      Real val[2][6];
-      int code[2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int kk = k + u * rstep;
-        code[u] = (kk < NC) ? jrow[kk] : nv;  // the tail reads the all-zero block
-        const Real* s = s_l + (code[u] & 0xff) * SD + in;
-        const Real* P = world ? (o_l + in) : (pe_l + (code[u] >> 8) * 3 * T + in);
-        const Real w0 = s[0], w1 = s[T], w2 = s[2 * T];
-        const Real p0 = P[0], p1 = P[T], p2 = P[2 * T];
-        val[u][0] = s[3 * T] + sgn * (p1 * w2 - p2 * w1);
-        val[u][1] = s[4 * T] + sgn * (p2 * w0 - p0 * w2);
-        val[u][2] = s[5 * T] + sgn * (p0 * w1 - p1 * w0);
-        val[u][3] = w0;
-        val[u][4] = w1;
-        val[u][5] = w2;
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        if (k + u * rstep < NC) {
-          const int c = code[u] & 0xff, e = code[u] >> 8;
-          Real* o = out + (int64_t)(e * 6 * nv + c) * ar.sJ_k;
-#pragma unroll
-          for (int r = 0; r < 6; ++r) put(&o[(int64_t)(r * nv) * ar.sJ_k], val[u][r], ar.stream_out);
-        }
-    }
+    if (!jac_early) store_jac_columns(r0, rstep);
     if (!early_zero) {
-      const int* jz = jrow + NC;
+      Real* out = ar.J + bo * ar.sJ_b;
+      const int* jz = jrow + ee.n_col;
       for (int k = r0; k < ee.n_zero; k += rstep) put(&out[(int64_t)jz[k] * ar.sJ_k], Real(0), ar.stream_out);
     }
   }

@@ -80,7 +80,7 @@ constexpr int kAdjMaxThreads = 512;
 // single copy of 16-byte chunks.  mtab comes last so kernels that do not need
 // it copy only the prefix.
 struct TabLayout {
-  int cst, meta, sbody, ssrc, cslot, linfo, bm2, dlist, ulist, jump, mtab, end_nomtab, end;
+  int cst, meta, sbody, ssrc, cslot, linfo, srec, bm2, dlist, ulist, jump, mtab, end_nomtab, end;
 };
 
 __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kmax, int nv, int rs) {
@@ -97,6 +97,7 @@ __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kma
   t.ssrc = take(depth * P);
   t.cslot = take(depth * P * kmax);
   t.linfo = take(depth * 2 * 4);
+  t.srec = take(depth * P * 16);  // per (level, slot) {body, position, q index, packed flags}
   t.bm2 = take(n * 16);    // per body {preorder position, subtree size, v index, dofs}
   t.dlist = take(n * 4);   // bodies by decreasing subtree size
   t.ulist = take(4 * 8 * n * 4);  // subtree-phase work lists for 1, 2, 4, 8 row groups per wave

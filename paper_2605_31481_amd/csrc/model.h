@@ -46,6 +46,7 @@ struct DevModel {
   int n_mpair, n_mzero;  // mass-matrix output lists (pairs, then zero entries)
   int jsteps;            // pointer-jumping steps: ceil(log2(depth))
   int use_scan;          // 1: kinematics by pointer jumping instead of the level sweep
+  unsigned long long xmask;  // bit l: level l pulls link state across lanes (a branching level)
   float g32[3];
   double g64[3];
 };
@@ -83,6 +84,8 @@ struct bard_model {
   std::vector<int16_t> sched_body;
   std::vector<int8_t> sched_src, child_slot;
   std::vector<int> level_info, mtab;  // mtab: mass-matrix pair list, then zero list
+  std::vector<bard::I4> srec;         // [depth][P] level-sweep records (see compile_model)
+  unsigned long long xmask = 0;       // bit l: level l exchanges state across lanes
   int n_mpair = 0, n_mzero = 0;
   std::vector<std::vector<int>> children;
   bard::DeviceCopy dev[BARD_MAX_DEVICES];
