@@ -115,33 +115,50 @@ int bard_model_joint_transform(bard_model_t model, int32_t body, const double* q
 int bard_model_destroy(bard_model_t model);
 
 /* ------------------------------------------------------------ workspace ----
- * A workspace holds the cached kinematic state of one stream (Sec. 3.1's
- * tiered lazy evaluation): for up to max_batch instances, the world pose of
- * every body, every joint's motion subspace and the base origin, each
- * component tagged with the q_tag it was computed for.  An operator called
- * with ws != NULL and q_tag != 0 either
- *   - loads these components instead of computing them, when every component
- *     it needs was computed for the same q_tag and the same B (FK, Jacobian
- *     and CRBA then skip the level sweep; RNEA keeps only the velocity and
- *     acceleration propagation), or
- *   - computes them and stores the components it computed under q_tag.
- * bard_fk, bard_jacobian, bard_rnea and bard_crba use the workspace;
- * bard_aba and bard_chain accept it for argument checks only.  Equal non-zero
- * tags promise equal q contents; the library never inspects q to check.
- * The tier (4 or 8 bytes x (12 n_bodies + 6 nv + 3) x max_batch) is allocated on
- * the device of the first call that uses it; a workspace stays on that device
- * and serves one stream at a time.
+ * A workspace holds cached state of one stream for up to max_batch instances
+ * (Sec. 3.1's tiered lazy evaluation, extended to dynamics results), in
+ * tiers keyed by caller version tags:
+ *   BARD_TIER_KINEMATICS (q_tag): the world pose of every body, every joint's
+ *     motion subspace and the base origin.  A call whose components were all
+ *     computed for its q_tag and B loads them instead of computing them (FK,
+ *     Jacobian and CRBA then skip the level sweep; RNEA keeps only the
+ *     velocity and acceleration propagation); otherwise it computes them and
+ *     stores what it computed.  Used by bard_fk, bard_jacobian, bard_rnea and
+ *     bard_crba.
+ *   BARD_TIER_MASS (q_tag): M(q).  bard_crba on a hit copies the cached
+ *     matrix into its output instead of launching the tree traversal; on a
+ *     miss it computes M and copies it into the tier.
+ *   BARD_TIER_BIAS (q_tag, qd_tag): the bias forces b = RNEA(q, qd, 0).
+ *     bard_rnea without an inertia override and with both tags non-zero, on a
+ *     hit of both this tier and the mass tier, returns tau = M qdd + b (RNEA
+ *     is affine in qdd with slope M) from one bandwidth-bound pass instead of
+ *     the traversal; when b is missing it computes tau and b in one traversal
+ *     and stores b (not on trees of depth 32 or more, which take the
+ *     pointer-jumping kinematics: there b is not cached).  The cached path
+ *     rounds differently: its error is bounded like ABA's backward error,
+ *     atol + rtol (|tau| + |M| |qdd| + |b|) in the infinity norm.
+ * bard_aba and bard_chain accept a workspace for argument checks only.  Equal
+ * non-zero tags promise equal contents; the library never inspects inputs to
+ * check.  Each tier (4 or 8 bytes x rows x max_batch; rows = 12 n_bodies +
+ * 6 nv + 3, nv*nv and nv) is allocated on the first call that uses it, on the
+ * workspace's device (that of its first use); a workspace serves one stream
+ * at a time.  Changing the model's gravity invalidates the bias tier.
  * Errors: BARD_E_ARG, BARD_E_NOMEM. */
+#define BARD_TIER_KINEMATICS 1
+#define BARD_TIER_MASS 2
+#define BARD_TIER_BIAS 4
 int bard_ws_create(bard_model_t model, bard_dtype dtype, int64_t max_batch, bard_ws_t* out);
 int bard_ws_destroy(bard_ws_t ws);
-/* policy 1 (default): store on a miss, load on a hit; 0: the workspace is not
- * used (every call computes everything). */
+/* policy: the OR of the BARD_TIER_* bits in use (default BARD_TIER_KINEMATICS;
+ * 0: the workspace is not used and every call computes everything).  Whether
+ * reloading cached state beats recomputing it depends on the tree and the
+ * batch; the policy is the knob that chooses.
+ * Errors: BARD_E_ARG (NULL workspace, unknown bits). */
 int bard_ws_set_policy(bard_ws_t ws, int32_t policy);
 
 /* ------------------------------------------------------------ operators ----
  * q_tag / qd_tag: caller version tags of q and qd for the workspace; 0 =
- * unknown (always recompute).  qd-dependent state is always recomputed, so
- * qd_tag is accepted but unused. */
+ * unknown (always recompute).  Only bard_rnea's bias tier uses qd_tag. */
 
 /* FK (world pose of every body, Sec. 3.1 tier 3).
  * Arrays (L order): q [nq] in, poses [n_bodies*12] out. */

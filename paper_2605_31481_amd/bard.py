@@ -41,6 +41,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 F32, F64 = 0, 1
 REVOLUTE, PRISMATIC, FREE, FIXED = 0, 1, 2, 3
 WORLD, LOCAL_WORLD_ALIGNED = 0, 1
+# workspace tiers (bard_ws_set_policy bits)
+TIER_KINEMATICS, TIER_MASS, TIER_BIAS = 1, 2, 4
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -202,10 +204,11 @@ def version_tag(t) -> int:
 
 
 class Workspace:
-    """Cached kinematic state of one stream (bard_ws_*): operators called with
-    ``ws=`` reuse the poses and motion subspaces computed for an unchanged q."""
+    """Cached state of one stream (bard_ws_*): operators called with ``ws=``
+    reuse what was computed for unchanged inputs, per the tiers in ``policy``
+    (an OR of TIER_KINEMATICS, TIER_MASS, TIER_BIAS)."""
 
-    def __init__(self, model: "Model", max_batch: int, dtype=None, policy: int = 1):
+    def __init__(self, model: "Model", max_batch: int, dtype=None, policy: int = TIER_KINEMATICS):
         torch = _torch()
         dtype = dtype if dtype is not None else torch.float32
         code = F32 if dtype == torch.float32 else F64
@@ -269,6 +272,11 @@ class Model:
         return cls(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia,
                    getattr(tree, "gravity", None))
 
+    def set_gravity(self, gravity):
+        """World-frame gravity (bard_model_set_gravity); invalidates workspace bias tiers."""
+        g, pg = _f64arr(gravity)
+        _check(bard_model_set_gravity(self._h, pg), "bard_model_set_gravity")
+
     @property
     def handle(self):
         return self._h
@@ -313,15 +321,16 @@ class Model:
         return out
 
     def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa", ws: Optional[Workspace] = None,
-             q_tag=None):
+             q_tag=None, qd_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv, B, layout)
         L = _layouts([q, qd, qdd, out], layout)
         if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
             raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
         wh, tag = _ws_args(ws, q, q_tag)
+        _, dtag = _ws_args(ws, qd, qd_tag)
         _check(bard_rnea(self._h, wh, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
-                         tag, 0, B, _stream_ptr(q)), "bard_rnea")
+                         tag, dtag, B, _stream_ptr(q)), "bard_rnea")
         return out
 
     def crba(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):

@@ -37,11 +37,15 @@ struct bard_ws {
   bard_model* model;
   bard_dtype dtype;
   int64_t max_batch;
-  int policy = 1;  // 1: store on a miss and load on a hit; 0: off
-  void* kin = nullptr;
+  int policy = BARD_TIER_KINEMATICS;  // tiers in use (bard_ws_set_policy)
+  void* kin = nullptr;                // kinematics tier [kin_rows][max_batch]
+  void* mt = nullptr;                 // mass-matrix tier [nv*nv][max_batch]
+  void* bt = nullptr;                 // bias-force tier [nv][max_batch]
   int dev = -1;
   int64_t tier_B = -1;
   uint64_t pose_tag = 0, s_tag = 0, o_tag = 0;
+  int64_t m_B = -1, b_B = -1;
+  uint64_t m_tag = 0, bq_tag = 0, bqd_tag = 0, b_gen = 0;
 };
 
 using namespace bard;
@@ -292,20 +296,28 @@ struct TierUse {
   bool pose = false, s = false;
 };
 
-template <class Real, int OPS>
-int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, Args<Real>* ar, TierUse* tu) {
-  if (!ws || !ws->policy || q_tag == 0) return BARD_OK;
+// Allocate one tier of `rows` instance-minor rows on the workspace's device
+// (the device of its first use).
+template <class Real>
+int ensure_tier(bard_ws* ws, void** tier, int rows) {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  if (ws->kin && ws->dev != dev) return fail(BARD_E_ARG, "workspace used on another device");
-  if (!ws->kin) {
-    const size_t bytes = (size_t)kin_rows(m->n, m->nv) * ws->max_batch * sizeof(Real);
-    if (hipMalloc(&ws->kin, bytes) != hipSuccess) {
-      ws->kin = nullptr;
-      return fail(BARD_E_NOMEM, "hipMalloc of the workspace tier failed");
-    }
-    ws->dev = dev;
+  if (ws->dev >= 0 && ws->dev != dev) return fail(BARD_E_ARG, "workspace used on another device");
+  if (*tier) return BARD_OK;
+  const size_t bytes = (size_t)rows * ws->max_batch * sizeof(Real);
+  if (hipMalloc(tier, bytes) != hipSuccess) {
+    *tier = nullptr;
+    return fail(BARD_E_NOMEM, "hipMalloc of a workspace tier failed");
   }
+  ws->dev = dev;
+  return BARD_OK;
+}
+
+template <class Real, int OPS>
+int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, Args<Real>* ar, TierUse* tu) {
+  if (!ws || !(ws->policy & BARD_TIER_KINEMATICS) || q_tag == 0) return BARD_OK;
+  int rc = ensure_tier<Real>(ws, &ws->kin, kin_rows(m->n, m->nv));
+  if (rc) return rc;
   const bool need_body = OPS & (OP_FK | OP_RNEA | OP_CRBA);
   const bool need_s = OPS & (OP_JAC | OP_RNEA | OP_CRBA);
   const bool need_pose = need_body || ((OPS & OP_JAC) && frame == 1);
@@ -507,6 +519,7 @@ int bard_model_set_gravity(bard_model_t m, const double* g) {
     if (!std::isfinite(g[k])) return fail(BARD_E_ARG, "non-finite gravity");
   std::lock_guard<std::mutex> lk(m->mu);
   for (int k = 0; k < 3; ++k) m->g[k] = g[k];
+  ++m->g_gen;
   for (auto& dc : m->dev)
     if (dc.ready)
       for (int k = 0; k < 3; ++k) {
@@ -588,12 +601,13 @@ int bard_ws_create(bard_model_t m, bard_dtype dtype, int64_t max_batch, bard_ws_
 
 int bard_ws_destroy(bard_ws_t w) {
   if (!w) return fail(BARD_E_ARG, "NULL workspace");
-  if (w->kin) {
+  if (w->dev >= 0) {
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(w->dev);
     (void)hipDeviceSynchronize();
-    (void)hipFree(w->kin);
+    for (void* t : {w->kin, w->mt, w->bt})
+      if (t) (void)hipFree(t);
     if (cur >= 0) (void)hipSetDevice(cur);
   }
   delete w;
@@ -602,7 +616,8 @@ int bard_ws_destroy(bard_ws_t w) {
 
 int bard_ws_set_policy(bard_ws_t w, int32_t policy) {
   if (!w) return fail(BARD_E_ARG, "NULL workspace");
-  if (policy != 0 && policy != 1) return fail(BARD_E_ARG, "policy must be 0 or 1");
+  if (policy & ~(BARD_TIER_KINEMATICS | BARD_TIER_MASS | BARD_TIER_BIAS))
+    return fail(BARD_E_ARG, "policy must be an OR of BARD_TIER_* bits");
   w->policy = policy;
   return BARD_OK;
 }
@@ -653,7 +668,6 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
 int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
               const void* inertia_override, void* tau, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
               int64_t B, void* stream) {
-    (void)qd_tag;
   int rc = common_checks(m, ws, dtype, B);
   if (rc) return rc;
   if (B == 0) return BARD_OK;
@@ -670,7 +684,35 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
         !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.st_b, &a.st_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
+    const hipStream_t st = (hipStream_t)stream;
+    if (!ws || !(ws->policy & BARD_TIER_BIAS) || q_tag == 0 || qd_tag == 0 || inertia_override)
+      return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, st, ws, q_tag);
+    DeviceCopy* dc = nullptr;
+    int rc2 = ensure_device(m, &dc);
+    if (rc2) return rc2;
+    if ((rc2 = ensure_tier<R>(ws, &ws->bt, m->nv))) return rc2;
+    const int64_t ld = ws->max_batch;
+    const bool b_hit = ws->b_B == B && ws->bq_tag == q_tag && ws->bqd_tag == qd_tag && ws->b_gen == m->g_gen;
+    const bool m_hit = ws->mt && ws->m_B == B && ws->m_tag == q_tag;
+    if (b_hit && m_hit) {
+      // tau = M qdd + b from the two tiers: no traversal
+      if (launch_tier_matvec<R>((const R*)ws->mt, (const R*)ws->bt, ld, a.qdd, a.sqdd_b, a.sqdd_k, a.tau, a.st_b,
+                                a.st_k, m->nv, B, st) != hipSuccess)
+        return fail(BARD_E_DEVICE, "tier launch failed");
+      return BARD_OK;
+    }
+    if (b_hit || dc->dm.use_scan) return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, st, ws, q_tag);
+    // one traversal for tau and b = RNEA(q, qd, 0), b into the tier
+    a.bias = (R*)ws->bt;
+    a.sb_b = 1;
+    a.sb_k = ld;
+    ws->bq_tag = 0;
+    if ((rc2 = run_tree<R, OP_RNEA | OP_BIAS>(m, a, 0, nullptr, 0, st, ws, q_tag))) return rc2;
+    ws->b_B = B;
+    ws->bq_tag = q_tag;
+    ws->bqd_tag = qd_tag;
+    ws->b_gen = m->g_gen;
+    return BARD_OK;
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
@@ -689,7 +731,28 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
     a.M = (R*)M;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv * m->nv, &a.sM_b, &a.sM_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
+    const hipStream_t st = (hipStream_t)stream;
+    const int nn = m->nv * m->nv;
+    if (!ws || !(ws->policy & BARD_TIER_MASS) || q_tag == 0)
+      return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, st, ws, q_tag);
+    int rc2 = ensure_tier<R>(ws, &ws->mt, nn);
+    if (rc2) return rc2;
+    R* mt = (R*)ws->mt;
+    const int64_t ld = ws->max_batch;
+    if (ws->m_B == B && ws->m_tag == q_tag) {
+      // mass-matrix tier hit: no traversal, one copy into the caller's layout
+      if (launch_tier_copy<R>(mt, 1, ld, a.M, a.sM_b, a.sM_k, nn, B, st) != hipSuccess)
+        return fail(BARD_E_DEVICE, "tier copy launch failed");
+      return BARD_OK;
+    }
+    if ((rc2 = run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, st, ws, q_tag))) return rc2;
+    if (launch_tier_copy<R>(a.M, a.sM_b, a.sM_k, mt, 1, ld, nn, B, st) != hipSuccess) {
+      ws->m_tag = 0;
+      return fail(BARD_E_DEVICE, "tier copy launch failed");
+    }
+    ws->m_B = B;
+    ws->m_tag = q_tag;
+    return BARD_OK;
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }

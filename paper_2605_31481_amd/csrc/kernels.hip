@@ -57,13 +57,14 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   constexpr bool JAC = OPS & OP_JAC;
   constexpr bool RNEA = OPS & OP_RNEA;
   constexpr bool CRBA = OPS & OP_CRBA;
+  constexpr bool BIAS = RNEA && (OPS & OP_BIAS);  // also RNEA(q, qd, 0); not on the scan path
   constexpr bool VEL = RNEA;
   constexpr bool BACK = RNEA || CRBA;
   constexpr bool NEED_S = JAC || RNEA || CRBA;
   constexpr bool NEED_BODY = FK || RNEA || CRBA;
   constexpr int T = 1 << LOGT;
   constexpr int SD = 6 * T + block_pad(T, sizeof(Real));   // per-dof block stride (elements)
-  constexpr int SB = 24 * T + block_pad(T, sizeof(Real));  // per-body block stride (elements)
+  constexpr int SB = body_rows(OPS) * T + block_pad(T, sizeof(Real));  // per-body block stride (elements)
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int nv = dm.nv, n = dm.n;
@@ -422,6 +423,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     const Real* qddi_l = qdd_l + inst;
 
     Real Rw[9], pw[3], v[6], a[6];
+    Real ab[6];  // BIAS: the acceleration without the qdd terms
     int lstart = 0;
     auto store_body = [&](int bb) {
       Real* br = body_l + tb.bm2[bb].x * SB + inst;
@@ -434,6 +436,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         for (int k = 0; k < 6; ++k) {
           br[(12 + k) * T] = v[k];
           br[(18 + k) * T] = a[k];
+          if (BIAS) br[(24 + k) * T] = ab[k];
         }
       }
     };
@@ -455,15 +458,17 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       if (VEL) {
         const Real vb[3] = {qdi_l[0], qdi_l[T], qdi_l[2 * T]};
         const Real wb[3] = {qdi_l[3 * T], qdi_l[4 * T], qdi_l[5 * T]};
-        const Real ab[3] = {qddi_l[0], qddi_l[T], qddi_l[2 * T]};
+        const Real ab_[3] = {qddi_l[0], qddi_l[T], qddi_l[2 * T]};
         const Real wdb[3] = {qddi_l[3 * T], qddi_l[4 * T], qddi_l[5 * T]};
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           v[i] = Rw[3 * i] * wb[0] + Rw[3 * i + 1] * wb[1] + Rw[3 * i + 2] * wb[2];
           v[3 + i] = Rw[3 * i] * vb[0] + Rw[3 * i + 1] * vb[1] + Rw[3 * i + 2] * vb[2];
           a[i] = a0[i] + Rw[3 * i] * wdb[0] + Rw[3 * i + 1] * wdb[1] + Rw[3 * i + 2] * wdb[2];
-          a[3 + i] = a0[3 + i] + Rw[3 * i] * ab[0] + Rw[3 * i + 1] * ab[1] + Rw[3 * i + 2] * ab[2];
+          a[3 + i] = a0[3 + i] + Rw[3 * i] * ab_[0] + Rw[3 * i + 1] * ab_[1] + Rw[3 * i + 2] * ab_[2];
         }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ab[k] = a0[k];
       }
       if (act && hit) {
         Real* br = body_l + tb.bm2[0].x * SB + inst;
@@ -471,6 +476,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         for (int k = 0; k < 6; ++k) {
           br[(12 + k) * T] = v[k];
           br[(18 + k) * T] = a[k];
+          if (BIAS) br[(24 + k) * T] = ab[k];
         }
       }
       if (act && !hit) {
@@ -506,6 +512,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       for (int k = 0; k < 6; ++k) {
         v[k] = Real(0);
         a[k] = a0[k];
+        ab[k] = a0[k];
       }
       if (slot_raw == 0 && !hit)
 #pragma unroll
@@ -562,6 +569,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         a[k] = a[k] + s[k] * qddv + cJ[k];
+        if (BIAS) ab[k] = ab[k] + cJ[k];
         v[k] = v[k] + vJ[k];
       }
     };
@@ -585,6 +593,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
             for (int k = 0; k < 6; ++k) {
               v[k] = xch(v[k], src);
               a[k] = xch(a[k], src);
+              if (BIAS) ab[k] = xch(ab[k], src);
             }
           }
         }
@@ -609,6 +618,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
               for (int k = 0; k < 6; ++k) {
                 br[(12 + k) * T] = v[k];
                 br[(18 + k) * T] = a[k];
+                if (BIAS) br[(24 + k) * T] = ab[k];
               }
             }
           }
@@ -631,6 +641,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           for (int k = 0; k < 6; ++k) {
             v[k] = xch(v[k], src);
             a[k] = xch(a[k], src);
+            if (BIAS) ab[k] = xch(ab[k], src);
           }
         }
         Real s[6];
@@ -644,6 +655,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           for (int k = 0; k < 6; ++k) {
             br[(12 + k) * T] = v[k];
             br[(18 + k) * T] = a[k];
+            if (BIAS) br[(24 + k) * T] = ab[k];
           }
         }
       }
@@ -756,7 +768,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
 #pragma unroll
       for (int k = 0; k < 10; ++k) pic[k] = ar.pi_ovr ? ar.pi_ovr[bb * 10 + k] : tb.cst[bb * CST + C_PI + k];
       world_inertia(pic, R, p, I0);
-      Real f[6];
+      Real f[6], fb[6];
       if (VEL) {
         Real v[6], a[6], Ia[6], Iv[6], vxIv[6];
 #pragma unroll
@@ -769,13 +781,25 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         crf(v, Iv, vxIv);
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[k] = Ia[k] + vxIv[k];
+        if (BIAS) {
+          Real abv[6], Iab[6];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) abv[k] = br[(24 + k) * T];
+          inertia_mul(I0, abv, Iab);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) fb[k] = Iab[k] + vxIv[k];
+        }
       }
-      // overwrite this body's block in place: rows 0-5 f, rows 6-15 I
+      // overwrite this body's block in place: rows 0-5 f, rows 6-15 I, and
+      // for BIAS rows 16-21 the bias force (v, a, ab were read above)
       if (VEL)
 #pragma unroll
         for (int k = 0; k < 6; ++k) br[k * T] = f[k];
 #pragma unroll
       for (int k = 0; k < 10; ++k) br[(6 + k) * T] = I0[k];
+      if (BIAS)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) br[(16 + k) * T] = fb[k];
     }
     __syncthreads();
 
@@ -803,9 +827,9 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         // its range, so the row groups of a wave read adjacent blocks (blocks
         // a fixed distance apart would share LDS banks).
         const int c1 = valid ? m2.y : 0;
-        Real F[6], Ic[10];
+        Real F[6], Ic[10], Fb[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) F[k] = Real(0);
+        for (int k = 0; k < 6; ++k) F[k] = Fb[k] = Real(0);
 #pragma unroll
         for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
         const Real* br = body_l + (m2.x + part) * SB + in;
@@ -816,6 +840,9 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           if (CRBA)
 #pragma unroll
             for (int k = 0; k < 10; ++k) Ic[k] += br[(6 + k) * T];
+          if (BIAS)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Fb[k] += br[(16 + k) * T];
         }
         if (U > 1 && split) {
 #pragma unroll
@@ -826,6 +853,9 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
             if (CRBA)
 #pragma unroll
               for (int k = 0; k < 10; ++k) Ic[k] += xch(Ic[k], lane ^ sh);
+            if (BIAS)
+#pragma unroll
+              for (int k = 0; k < 6; ++k) Fb[k] += xch(Fb[k], lane ^ sh);
           }
         }
         if (!valid) continue;
@@ -837,6 +867,10 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           if (RNEA && bok) {
             const Real t = s[0] * F[0] + s[1] * F[1] + s[2] * F[2] + s[3] * F[3] + s[4] * F[4] + s[5] * F[5];
             put(&ar.tau[bo * ar.st_b + (int64_t)(m2.z + d) * ar.st_k], t, ar.stream_out);
+            if (BIAS) {
+              const Real tb_ = s[0] * Fb[0] + s[1] * Fb[1] + s[2] * Fb[2] + s[3] * Fb[3] + s[4] * Fb[4] + s[5] * Fb[5];
+              put(&ar.bias[bo * ar.sb_b + (int64_t)(m2.z + d) * ar.sb_k], tb_, ar.stream_out);
+            }
           }
           if (CRBA) {
             Real fcv[6];
@@ -1394,6 +1428,8 @@ hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int bl
                                                hipStream_t);                                                      \
   template hipError_t launch_tree<R, OP_CRBA>(const DevModel&, const DevEE&, const Args<R>&, int, int, size_t,     \
                                                hipStream_t);                                                      \
+  template hipError_t launch_tree<R, OP_RNEA | OP_BIAS>(const DevModel&, const DevEE&, const Args<R>&, int, int,   \
+                                                        size_t, hipStream_t);                                     \
   template hipError_t launch_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(const DevModel&, const DevEE&, const Args<R>&,   \
                                                                  int, int, size_t, hipStream_t);                  \
   template hipError_t launch_aba<R>(const DevModel&, const Args<R>&, int, int, size_t, hipStream_t);          \

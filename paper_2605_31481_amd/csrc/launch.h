@@ -7,7 +7,12 @@
 
 namespace bard {
 
-enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8 };
+enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8, OP_BIAS = 16 };
+
+// Rows of a per-body LDS block: R, p, v, a (24); an RNEA launch that also
+// returns the bias forces RNEA(q, qd, 0) carries the acceleration without the
+// qdd terms in 6 more.
+__host__ __device__ constexpr int body_rows(int ops) { return (ops & OP_BIAS) ? 30 : 24; }
 
 template <class Real>
 struct Args {
@@ -21,7 +26,8 @@ struct Args {
   Real* tau;
   Real* M;
   Real* qdd_out;
-  int64_t sq_b, sq_k, sqd_b, sqd_k, sqdd_b, sqdd_k, sti_b, sti_k;
+  Real* bias;  // OP_BIAS: RNEA(q, qd, 0) [nv]
+  int64_t sq_b, sq_k, sqd_b, sqd_k, sqdd_b, sqdd_k, sti_b, sti_k, sb_b, sb_k;
   int64_t sp_b, sp_k, sJ_b, sJ_k, st_b, st_k, sM_b, sM_k, sqo_b, sqo_k;
   int64_t B;
   int logT;
@@ -45,6 +51,15 @@ __host__ __device__ inline int kin_rows(int n, int nv) { return 12 * n + 6 * nv 
 template <class Real, int OPS>
 hipError_t launch_tree(const DevModel& dm, const DevEE& ee, const Args<Real>& ar, int grid, int block, size_t lds,
                        hipStream_t st);
+
+// Workspace result tiers (tiers.hip): dst[k][b] = src[k][b] for `rows` rows,
+// and tau = M qdd + b from an M tier and a bias tier of row stride ld.
+template <class Real>
+hipError_t launch_tier_copy(const Real* src, int64_t s_b, int64_t s_k, Real* dst, int64_t d_b, int64_t d_k, int rows,
+                            int64_t B, hipStream_t st);
+template <class Real>
+hipError_t launch_tier_matvec(const Real* Mt, const Real* bt, int64_t ld, const Real* qdd, int64_t sq_b, int64_t sq_k,
+                              Real* tau, int64_t st_b, int64_t st_k, int nv, int64_t B, hipStream_t st);
 
 // Device arrays of a multi-tree launch: per model its tables, end effectors
 // and I/O arguments, and the work items {model, tile} of the launch starting
@@ -157,7 +172,7 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
     const bool need_s = ops & (OP_JAC | OP_RNEA | OP_CRBA);
     const bool need_body = ops & (OP_FK | OP_RNEA | OP_CRBA);
     L.s = need_s ? take((nv + 1) * (6 * T + pad) * rs) : off;
-    L.body = need_body ? take(n * (24 * T + pad) * rs) : off;
+    L.body = need_body ? take(n * (body_rows(ops) * T + pad) * rs) : off;
     // fc: CRBA's Ic_i s blocks; RNEA kernels use them first as the scratch of
     // the velocity and acceleration scans
     L.fc = (ops & (OP_CRBA | OP_RNEA)) ? take((nv + 1) * (6 * T + pad) * rs) : off;

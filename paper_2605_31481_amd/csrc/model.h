@@ -79,6 +79,7 @@ struct bard_model {
   std::vector<int> ulist[4];              // subtree work lists (see subtree_units)
   std::vector<double> axis, xtree, inertia;
   double g[3] = {0.0, 0.0, -9.81};
+  uint64_t g_gen = 0;  // bumped by every gravity change (keys the bias tier)
   std::vector<double> cst64;
   std::vector<float> cst32;
   std::vector<int16_t> sched_body;

@@ -114,6 +114,21 @@ def aba_backward_error(om, q, qd, tau, qdd_gpu, dtype):
     return err <= bound, float((err / bound).max())
 
 
+def affine_rnea_ok(om, q, qd, qdd, tau_gpu, dtype):
+    """Inverse dynamics evaluated as tau = M qdd + b from cached M and b: the
+    error bound is that of ABA's backward error, atol + rtol (|tau| + |M| |qdd|
+    + |b|) in the infinity norm, per instance."""
+    rtol, atol = TOL[dtype]
+    ref = om.rnea(q, qd, qdd)
+    M = om.crba(q)
+    bias = om.rnea(q, qd, np.zeros_like(qd))
+    scale = (np.abs(ref).max(axis=1) + np.abs(M).sum(axis=2).max(axis=1) * np.abs(qdd).max(axis=1)
+             + np.abs(bias).max(axis=1))
+    err = np.abs(tau_gpu - ref).max(axis=1)
+    bound = atol + rtol * scale
+    return err <= bound, float((err / bound).max())
+
+
 def fk_ref_blocks(om, q):
     T = om.fk(q)                       # [B, n, 3, 4]
     return T.reshape(T.shape[0], T.shape[1], 12)

@@ -141,6 +141,12 @@ def test_workspace_capacity_checked_on_host():
     assert bard.bard_ws_create(m.handle, 0, 128, ctypes.byref(ws)) == 0
     assert bard.bard_crba(m.handle, ws, 0, None, None, None, 0, 129, None) == -6
     assert bard.bard_crba(m.handle, ws, 1, None, None, None, 0, 16, None) == -1
+    # tier policy: any OR of the three tier bits, nothing else
+    for p in range(8):
+        assert bard.bard_ws_set_policy(ws, p) == 0
+    for p in (8, -1, 16, 9):
+        assert bard.bard_ws_set_policy(ws, p) == -1
+    assert (bard.TIER_KINEMATICS, bard.TIER_MASS, bard.TIER_BIAS) == (1, 2, 4)
     assert bard.bard_ws_destroy(ws) == 0
 
 
