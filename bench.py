@@ -138,14 +138,44 @@ def cpu_baseline(tree, target_s=10.0, max_s=30.0):
         el = time.perf_counter() - t0
         if el >= target_s or el >= max_s:
             break
+    # one thread, as a sequential loop over configurations
+    one, t1 = 0, time.perf_counter()
+    while True:
+        om.chain(q[:512], qd[:512], qdd[:512], tree.ee_bodies, threads=1)
+        one += 512
+        el1 = time.perf_counter() - t1
+        if el1 >= target_s / 2:
+            break
     return {"value": done / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} configurations of the same tree (RNEA+CRBA+4-EE Jacobian, FP64), "
-                      f"{el:.1f} s on {threads} OpenMP threads"}
+                      f"{el:.1f} s on {threads} OpenMP threads",
+            "value_1_thread": one / el1}
 
 
 def _rate(torch, calls, steps, warmup=10):
     wall, kavg = time_calls(torch, calls, steps, warmup)
     return wall / steps, kavg * 1e-3
+
+
+def bench_sweep(torch, bard, m, tree, bpe):
+    """The fused chain on the 36-DOF humanoid over batch sizes 64 .. 262,144:
+    evaluations per second from one event pair around back-to-back launches,
+    rotating input/output sets up to 512 MB (at most 64 sets, so the smallest
+    batches stay cache-resident and launch-bound)."""
+    ee = tree.ee_bodies
+    out = {}
+    for B in (64, 256, 1024, 4096, 16384, 65536, 262144):
+        nsets = max(1, min(64, math.ceil(512e6 / (bpe * B))))
+        sets = make_sets(torch, tree, B, nsets, 9000 + B)
+        calls = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
+        n = max(30, min(300, 4_000_000 // B))
+        wall, kavg = time_calls(torch, calls, n, 10)
+        out[f"sweep_B{B}_evals_per_s"] = B / (kavg * 1e-3)
+        out[f"sweep_B{B}_kernel_us"] = kavg * 1e3
+        out[f"sweep_B{B}_hbm_frac"] = bpe * B / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS
+        del sets, calls
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_plan(torch, bard, steps):
@@ -202,30 +232,68 @@ def bench_adjoints(torch, bard, steps):
 
 
 def bench_workspace(torch, bard, steps):
-    """FK, Jacobian, CRBA and RNEA on one q (36-DOF humanoid, B = 4096) as
-    four separate calls: without a workspace, and with the kinematics tier
-    (after one miss, every call is a hit)."""
+    """Cache patterns of the workspace tiers, B = 4096 FP32, on the 7-DOF
+    chain and the 36-DOF humanoid.  One step is FK, Jacobian, CRBA and RNEA on
+    one state, as four calls.  Patterns: P0 every input new (all tiers miss),
+    P1 the same q, qd, qdd again, P2 the same q with a new qd.  Policies: no
+    workspace, the kinematics tier alone, and kinematics + mass + bias tiers.
+    Each pattern's last RNEA and CRBA outputs are checked on 64 instances
+    against the FP64 oracle (tau under the affine bound when it came from the
+    tiers, M under the normwise contract)."""
     import synth
-    tree = synth.humanoid_large()
-    m = bard.Model.from_tree(tree)
-    B = 4096
-    q, qd, qdd = (torch.from_numpy(x.T.copy()).float().cuda() for x in synth.random_state(tree, B, 7000))
-    ee = tree.ee_bodies
-    outs = dict(fk=torch.empty((12 * tree.n_bodies, B), device="cuda"),
-                j=torch.empty((24 * tree.nv, B), device="cuda"),
-                M=torch.empty((tree.nv * tree.nv, B), device="cuda"), tau=torch.empty((tree.nv, B), device="cuda"))
-    ws = bard.Workspace(m, B)
+    from oracle import OracleModel
+    out = {}
+    for name in ("chain7", "humanoid_large"):
+        tree = synth.tree_by_name(name)
+        m = bard.Model.from_tree(tree)
+        om = OracleModel.from_tree(tree)
+        B = 4096
+        hq, hqd, hqdd = synth.random_state(tree, B, 7000)
+        _, hqd2, _ = synth.random_state(tree, B, 7001)
+        q, qd, qdd, qd2 = (torch.from_numpy(synth.to_fp32_grid(x).T.copy()).float().cuda()
+                           for x in (hq, hqd, hqdd, hqd2))
+        ee = tree.ee_bodies
+        outs = dict(fk=torch.empty((12 * tree.n_bodies, B), device="cuda"),
+                    j=torch.empty((6 * len(ee) * tree.nv, B), device="cuda"),
+                    M=torch.empty((tree.nv * tree.nv, B), device="cuda"), tau=torch.empty((tree.nv, B), device="cuda"))
+        ctr = [10]
 
-    def four(w):
-        m.fk(q, out=outs["fk"], ws=w)
-        m.jacobian(q, ee, out=outs["j"], ws=w)
-        m.crba(q, out=outs["M"], ws=w)
-        m.rnea(q, qd, qdd, out=outs["tau"], ws=w)
-    n = max(50, steps // 4)
-    t0, k0 = _rate(torch, [lambda: four(None)], n)
-    t1, k1 = _rate(torch, [lambda: four(ws)], n)
-    return {"four_ops_no_ws_gpu_us": k0 * 1e6, "four_ops_ws_hits_gpu_us": k1 * 1e6,
-            "four_ops_no_ws_evals_per_s": B / t0, "four_ops_ws_hits_evals_per_s": B / t1}
+        def step(w, pattern):
+            ctr[0] += 1
+            qt = ctr[0] if pattern == "P0" else 1
+            dt = 1 if pattern == "P1" else ctr[0]
+            v = qd if (pattern != "P2" or ctr[0] % 2) else qd2
+            m.fk(q, out=outs["fk"], ws=w, q_tag=qt)
+            m.jacobian(q, ee, out=outs["j"], ws=w, q_tag=qt)
+            m.crba(q, out=outs["M"], ws=w, q_tag=qt)
+            m.rnea(q, v, qdd, out=outs["tau"], ws=w, q_tag=qt, qd_tag=dt)
+            return v
+
+        idx = np.random.default_rng(1).choice(B, 64, replace=False)
+        n = max(50, steps // 4)
+        for label, pol in (("no_ws", None), ("kin", 1), ("all", 7)):
+            for pattern in ("P0", "P1", "P2"):
+                if pol is None and pattern != "P0":
+                    continue
+                w = bard.Workspace(m, B, policy=pol) if pol is not None else None
+                t, k = _rate(torch, [lambda: step(w, pattern)], n)
+                v = step(w, pattern)
+                torch.cuda.synchronize()
+                hv = (hqd if v is qd else hqd2)[idx]
+                tau = outs["tau"].cpu().double().numpy().T[idx]
+                Mg = outs["M"].cpu().double().numpy().T[idx]
+                rq, rqdd = synth.to_fp32_grid(hq)[idx], synth.to_fp32_grid(hqdd)[idx]
+                rv = synth.to_fp32_grid(hv)
+                ref_t, ref_M = om.rnea(rq, rv, rqdd), om.crba(rq).reshape(len(idx), -1)
+                ref_b = om.rnea(rq, rv, np.zeros_like(rqdd))
+                scale = (np.abs(ref_t).max(1) + np.abs(ref_M.reshape(len(idx), tree.nv, tree.nv)).sum(2).max(1)
+                         * np.abs(rqdd).max(1) + np.abs(ref_b).max(1))
+                et = float((np.abs(tau - ref_t).max(1) / (1e-6 + 1e-5 * scale)).max())
+                em = float((np.abs(Mg - ref_M).max(1) / (1e-6 + 1e-5 * np.abs(ref_M).max(1))).max())
+                key = f"{name}_{label}_{pattern}"
+                out[key + "_gpu_us"] = k * 1e6
+                out[key + "_err_over_tol"] = max(et, em)
+    return out
 
 
 def traffic_if_current():
@@ -321,6 +389,7 @@ def main():
         extra["nv23_tree_evals_per_s"] = B * args.steps / w3
         extra["nv23_tree_kernel_us"] = k3 * 1e3
         del sets3, calls3
+        extra.update(bench_sweep(torch, bard, m, tree, bpe))
         extra.update(bench_plan(torch, bard, args.steps))
         extra.update(bench_adjoints(torch, bard, args.steps))
         extra.update(bench_workspace(torch, bard, args.steps))

@@ -205,6 +205,10 @@ int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q
  * and the FK gradient of the functional mode (Sec. 3.1).  Both run as one
  * level sweep and subtree sums in the world frame (the gradient for q_j is
  * s_j . W_j, W_j a sum over the subtree of body j), with no stored tape.
+ * A free root's q_bar has 7 entries: position (zero for rnea_vjp, which does
+ * not depend on it) and quaternion [x y z w]; the quaternion is normalised on
+ * read, so its gradient is orthogonal to q (the change of q along itself
+ * changes nothing).
  *
  * rnea_vjp: given tau_bar, writes per instance q_bar = (dtau/dq)^T tau_bar
  * [nq], qd_bar [nv] and qdd_bar [nv]; if inertia_bar != NULL, also the
@@ -221,8 +225,8 @@ int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q
  * buffer of 2048 * n_bodies * 10 values, allocated on the first such call;
  * such calls on one model and device must not overlap (different streams
  * included).
- * Errors: BARD_E_ARG (NULL array, bad stride), BARD_E_UNSUPPORTED (the tree
- * has a free joint), BARD_E_NOMEM, BARD_E_CAPACITY, BARD_E_DEVICE. */
+ * Errors: BARD_E_ARG (NULL array, bad stride), BARD_E_NOMEM, BARD_E_CAPACITY,
+ * BARD_E_DEVICE. */
 int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* qd,
                   const void* qdd, const void* inertia_override, const void* tau_bar, void* q_bar,
                   void* qd_bar, void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B,
@@ -230,7 +234,7 @@ int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const voi
 /* fk_vjp: given poses_bar (per body the 3x4 row-major [R_bar | p_bar] of the
  * bard_fk output), writes q_bar [nq] = (d poses / dq)^T poses_bar.
  * Arrays (L order): q, poses_bar [n_bodies*12] in; q_bar out.
- * Errors: as bard_rnea_vjp (free joints: BARD_E_UNSUPPORTED). */
+ * Errors: as bard_rnea_vjp. */
 int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* poses_bar,
                 void* q_bar, const bard_layout* L, int64_t B, void* stream);
 

@@ -1,10 +1,11 @@
-// Reverse-mode products (vector-Jacobian products) of FK and RNEA for
-// fixed-base trees: the gradients Sec. 4.3 takes through RNEA with respect to
+// Reverse-mode products (vector-Jacobian products) of FK and RNEA: the
+// gradients Sec. 4.3 takes through RNEA with respect to
 // the state and the inertial parameters, and the FK gradient of the
 // functional mode.
 //
-// Base-frame form.  In the world frame of a fixed-base tree, a change dq of
-// q_j moves the whole subtree of body j rigidly along the screw s_j (its
+// Base-frame form.  In the frame with world axes and its origin at the base
+// (the world origin, or the free root's position), a change dq of a revolute
+// or prismatic q_j moves the whole subtree of body j rigidly along the screw s_j (its
 // motion subspace, which is the Jacobian column of eq. (7)): every motion
 // vector X riding on a body of that subtree changes by dq s_j x X, every
 // force vector by dq s_j x* X, every world inertia by the congruence of that
@@ -30,6 +31,10 @@
 // The gradient for the inertial parameters is the adjoint of the two products
 // I a and I v (with adjoints phi and psi) mapped back to the body-frame
 // parameters, summed over the batch in FP64 in a fixed order.
+//
+// A free root's coordinates move the whole tree: its rotation by a rotation
+// about the base origin, its position by a translation (which leaves RNEA
+// unchanged), so their gradients come from the sum over all bodies.
 //
 // FK adjoint, given (Rbar_k, pbar_k) per body:
 //   w_k = [vee(Rbar_k R_k^T) + p_k x pbar_k; pbar_k], q_bar_j = s_j . (sum of w),
@@ -145,7 +150,9 @@ __device__ __forceinline__ Real dot6(const Real* a, const Real* b) {
 // level sweep (waves [0, WA)), a body phase and one (FK) or two (RNEA) subtree
 // phases over all waves.  The inertial-parameter sums of a workgroup
 // accumulate in LDS in tile order and are written once at the end.
-template <class Real, bool RNEA, int LOGT>
+// FREE: the tree has a free root (a separate instantiation, so fixed-base
+// trees keep the single-dof code and its register budget).
+template <class Real, bool RNEA, bool FREE, int LOGT>
 __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adjoint_kernel(DevModel dm,
                                                                                         AdjArgs<Real> ar) {
   constexpr int T = 1 << LOGT;
@@ -228,7 +235,59 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
         }
       };
       reset();
-      for (int l = 0; l < dm.depth; ++l) {
+      int lstart = 0;
+      if (FREE) {
+        // Level 0 holds only the free root, at the base origin; every slot
+        // evaluates it (so every slot carries its state into level 1) and
+        // slot 0 stores it.  Its six motion subspace columns are [0; R e_k]
+        // for the linear and [R e_k; 0] for the angular velocity coordinates.
+        Real qr[7], o[3];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) qr[k] = q_l[k * T + inst];
+        free_root_pose(tb.cst, qr, Rw, o);
+        if (RNEA) {
+          const Real* qdi = qd_l + inst;
+          const Real* qddi = qdd_l + inst;
+          const Real* tbi = tb_l + inst;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            const Real* Ri = Rw + 3 * i;
+            v[i] = Ri[0] * qdi[3 * T] + Ri[1] * qdi[4 * T] + Ri[2] * qdi[5 * T];
+            v[3 + i] = Ri[0] * qdi[0] + Ri[1] * qdi[T] + Ri[2] * qdi[2 * T];
+            a[i] = a0[i] + Ri[0] * qddi[3 * T] + Ri[1] * qddi[4 * T] + Ri[2] * qddi[5 * T];
+            a[3 + i] = a0[3 + i] + Ri[0] * qddi[0] + Ri[1] * qddi[T] + Ri[2] * qddi[2 * T];
+            phi[i] = Ri[0] * tbi[3 * T] + Ri[1] * tbi[4 * T] + Ri[2] * tbi[5 * T];
+            phi[3 + i] = Ri[0] * tbi[0] + Ri[1] * tbi[T] + Ri[2] * tbi[2 * T];
+          }
+        }
+        if (slot_raw == 0) {
+          Real* sr = s_l + inst;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              sr[k * SD + i * T] = Real(0);
+              sr[k * SD + (3 + i) * T] = Rw[3 * i + k];
+              sr[(3 + k) * SD + i * T] = Rw[3 * i + k];
+              sr[(3 + k) * SD + (3 + i) * T] = Real(0);
+            }
+          Real* br = body_l + tb.bm2[0].x * SB + inst;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) br[(9 + k) * T] = pw[k];
+          if (RNEA) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+              br[(12 + k) * T] = v[k];
+              br[(18 + k) * T] = a[k];
+              br[(24 + k) * T] = phi[k];
+            }
+          }
+        }
+        lstart = 1;
+      }
+      for (int l = lstart; l < dm.depth; ++l) {
         const int body = in_sched ? tb.sbody[l * P + slot] : -1;
         const bool act = body >= 0;
         const int bb = act ? body : 0;
@@ -397,38 +456,51 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
     if (RNEA) {
       // ---------------- subtree phase 1: F, Abar, G -> qd_bar, qdd_bar, w ----------------
       subtree_sums<Real, 18, 0, LOGT, SB>(tb, dm, body_l, tid, nt, [&](int bb, const I4& m2, int part, const Real* S) {
-        if (part != 0) return;  // one dof per body
-        const int d = m2.z;
-        Real s[6], v[6], wI[6];
-        const Real* sr = s_l + d * SD + in;
+        if (part != 0) return;
+        // m2.w dofs from v index m2.z (one for a revolute or prismatic
+        // joint, six for the free root, whose parent velocity is zero)
+        Real v[6], w[6], vpar[6];
         Real* br = body_l + m2.x * SB + in;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-          s[k] = sr[k * T];
           v[k] = br[(18 + k) * T];
-          wI[k] = br[(24 + k) * T];
+          w[k] = br[(24 + k) * T];
+          vpar[k] = v[k];
         }
-        const Real qdv = qd_l[d * T + in], qddv = qdd_l[d * T + in], tbv = tb_l[d * T + in];
+        const int nd = FREE ? m2.w : 1;
+        for (int d = m2.z; d < m2.z + nd; ++d) {
+          const Real* sr = s_l + d * SD + in;
+          const Real qdv = qd_l[d * T + in];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) vpar[k] -= sr[k * T] * qdv;
+        }
         const Real* F = S;
         const Real* A = S + 6;
         const Real* G = S + 12;
-        Real vxA[6], vpar[6], vpxA[6], vJb[6], sb[6], w[6];
+        Real vxA[6], vpxA[6], vJb[6];
         crf(v, A, vxA);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) vpar[k] = v[k] - s[k] * qdv;
         crf(vpar, A, vpxA);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          vJb[k] = G[k] - vxA[k] - vpxA[k];
-          sb[k] = tbv * F[k] + qdv * vJb[k] + qddv * A[k];
-        }
-        crf(s, sb, w);
+        for (int k = 0; k < 6; ++k) vJb[k] = G[k] - vxA[k] - vpxA[k];
+        for (int d = m2.z; d < m2.z + nd; ++d) {
+          const Real* sr = s_l + d * SD + in;
+          const Real qdv = qd_l[d * T + in], qddv = qdd_l[d * T + in], tbv = tb_l[d * T + in];
+          Real s[6], sb[6], ws[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) br[(24 + k) * T] = w[k] + wI[k];
-        if (bok) {
-          ar.qd_bar[bo * ar.sqdo_b + (int64_t)d * ar.sqdo_k] = dot6(s, vJb);
-          ar.qdd_bar[bo * ar.sqddo_b + (int64_t)d * ar.sqddo_k] = dot6(s, A);
+          for (int k = 0; k < 6; ++k) {
+            s[k] = sr[k * T];
+            sb[k] = tbv * F[k] + qdv * vJb[k] + qddv * A[k];
+          }
+          crf(s, sb, ws);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) w[k] += ws[k];
+          if (bok) {
+            ar.qd_bar[bo * ar.sqdo_b + (int64_t)d * ar.sqdo_k] = dot6(s, vJb);
+            ar.qdd_bar[bo * ar.sqddo_b + (int64_t)d * ar.sqddo_k] = dot6(s, A);
+          }
         }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) br[(24 + k) * T] = w[k];
       });
       __syncthreads();
     }
@@ -437,11 +509,47 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
     constexpr int WROW = RNEA ? 24 : 0;
     subtree_sums<Real, 6, WROW, LOGT, SB>(tb, dm, body_l, tid, nt, [&](int bb, const I4& m2, int part, const Real* S) {
       if (part != 0 || !bok) return;
+      const I4 meta = tb.meta[bb];
+      Real* qo = ar.q_bar + bo * ar.sqo_b;
+      if (FREE && meta.y == J_FREE) {
+        // The free root's subtree is the whole tree, so S sums every body's
+        // sensitivity: its angular part is the gradient with respect to a
+        // rotation of the tree about the base origin, its linear part that
+        // with respect to a translation.  With R = R0 R(q^), q^ = q / |q|,
+        // a change of q^ rotates the tree by R0 dth, dth = 2 (w dv - dw v +
+        // v x dv) for q^ = (v, w) (quaternion product dq^ q^*), so
+        // vbar = 2 (w th - v x th), wbar = -2 v . th with th = R0^T (angular
+        // part); this is orthogonal to q^, so the normalisation only
+        // divides by |q|.  The position moves the tree by R0 dp; RNEA does
+        // not depend on it (the frame sits at the base).
+        const Real* c = tb.cst + bb * CST + C_R0;
+        Real th[3], pb[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          th[j] = c[j] * S[0] + c[3 + j] * S[1] + c[6 + j] * S[2];
+          pb[j] = RNEA ? Real(0) : c[j] * S[3] + c[3 + j] * S[4] + c[6 + j] * S[5];
+        }
+        const int qz = meta.z;
+        const Real x = q_l[(qz + 3) * T + in], y = q_l[(qz + 4) * T + in], z = q_l[(qz + 5) * T + in],
+                   ww = q_l[(qz + 6) * T + in];
+        const Real inv = Real(1) / sqrt(x * x + y * y + z * z + ww * ww);
+        const Real u[3] = {x * inv, y * inv, z * inv}, uw = ww * inv;
+        Real uxt[3];
+        cross3(u, th, uxt);
+        const Real g2 = Real(2) * inv;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          qo[(int64_t)(qz + j) * ar.sqo_k] = pb[j];
+          qo[(int64_t)(qz + 3 + j) * ar.sqo_k] = g2 * (uw * th[j] - uxt[j]);
+        }
+        qo[(int64_t)(qz + 6) * ar.sqo_k] = -g2 * (u[0] * th[0] + u[1] * th[1] + u[2] * th[2]);
+        return;
+      }
       const Real* sr = s_l + m2.z * SD + in;
       Real s[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) s[k] = sr[k * T];
-      ar.q_bar[bo * ar.sqo_b + (int64_t)tb.meta[bb].z * ar.sqo_k] = dot6(s, S);
+      qo[(int64_t)meta.z * ar.sqo_k] = dot6(s, S);
     });
     if (nxt < ar.ntiles) {
       Real* dst = inbuf[cur ^ 1];  // the previous tile's buffer, no longer read
@@ -479,49 +587,62 @@ __global__ void __launch_bounds__(256) param_reduce_kernel(const double* partial
   if (t == 0) out[idx] = (Real)red[0];
 }
 
-template <class Real, bool RNEA, int LOGT>
+template <class Real, bool RNEA, bool FREE, int LOGT>
 static hipError_t launch_adjoint_t(const DevModel& dm, const AdjArgs<Real>& ar, int grid, int block, size_t lds,
                                    hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)adjoint_kernel<Real, RNEA, LOGT>,
+    hipError_t e = hipFuncSetAttribute((const void*)adjoint_kernel<Real, RNEA, FREE, LOGT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((adjoint_kernel<Real, RNEA, LOGT>), dim3(grid), dim3(block), lds, st, dm, ar);
+  hipLaunchKernelGGL((adjoint_kernel<Real, RNEA, FREE, LOGT>), dim3(grid), dim3(block), lds, st, dm, ar);
   return hipGetLastError();
+}
+
+template <class Real, bool RNEA, bool FREE>
+static hipError_t launch_adjoint_f(const DevModel& dm, const AdjArgs<Real>& ar, int grid, int block, size_t lds,
+                                   hipStream_t st) {
+  switch (ar.logT) {
+    case 3: return launch_adjoint_t<Real, RNEA, FREE, 3>(dm, ar, grid, block, lds, st);
+    case 4: return launch_adjoint_t<Real, RNEA, FREE, 4>(dm, ar, grid, block, lds, st);
+    case 5: return launch_adjoint_t<Real, RNEA, FREE, 5>(dm, ar, grid, block, lds, st);
+    case 6: return launch_adjoint_t<Real, RNEA, FREE, 6>(dm, ar, grid, block, lds, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class Real, bool RNEA>
 hipError_t launch_adjoint(const DevModel& dm, const AdjArgs<Real>& ar, int grid, int block, size_t lds,
                           hipStream_t st) {
-  switch (ar.logT) {
-    case 3: return launch_adjoint_t<Real, RNEA, 3>(dm, ar, grid, block, lds, st);
-    case 4: return launch_adjoint_t<Real, RNEA, 4>(dm, ar, grid, block, lds, st);
-    case 5: return launch_adjoint_t<Real, RNEA, 5>(dm, ar, grid, block, lds, st);
-    case 6: return launch_adjoint_t<Real, RNEA, 6>(dm, ar, grid, block, lds, st);
-    default: return hipErrorInvalidValue;
-  }
+  return dm.free_root ? launch_adjoint_f<Real, RNEA, true>(dm, ar, grid, block, lds, st)
+                      : launch_adjoint_f<Real, RNEA, false>(dm, ar, grid, block, lds, st);
 }
 
-template <class Real, bool RNEA, int LOGT>
+template <class Real, bool RNEA, bool FREE, int LOGT>
 static hipError_t adjoint_resident_t(int block, size_t lds, int* per_cu) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)adjoint_kernel<Real, RNEA, LOGT>,
+    hipError_t e = hipFuncSetAttribute((const void*)adjoint_kernel<Real, RNEA, FREE, LOGT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, adjoint_kernel<Real, RNEA, LOGT>, block, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, adjoint_kernel<Real, RNEA, FREE, LOGT>, block, lds);
+}
+
+template <class Real, bool RNEA, bool FREE>
+static hipError_t adjoint_resident_f(int logT, int block, size_t lds, int* per_cu) {
+  switch (logT) {
+    case 3: return adjoint_resident_t<Real, RNEA, FREE, 3>(block, lds, per_cu);
+    case 4: return adjoint_resident_t<Real, RNEA, FREE, 4>(block, lds, per_cu);
+    case 5: return adjoint_resident_t<Real, RNEA, FREE, 5>(block, lds, per_cu);
+    case 6: return adjoint_resident_t<Real, RNEA, FREE, 6>(block, lds, per_cu);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class Real, bool RNEA>
-hipError_t adjoint_resident(int logT, int block, size_t lds, int* per_cu) {
-  switch (logT) {
-    case 3: return adjoint_resident_t<Real, RNEA, 3>(block, lds, per_cu);
-    case 4: return adjoint_resident_t<Real, RNEA, 4>(block, lds, per_cu);
-    case 5: return adjoint_resident_t<Real, RNEA, 5>(block, lds, per_cu);
-    case 6: return adjoint_resident_t<Real, RNEA, 6>(block, lds, per_cu);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t adjoint_resident(int logT, int free_root, int block, size_t lds, int* per_cu) {
+  return free_root ? adjoint_resident_f<Real, RNEA, true>(logT, block, lds, per_cu)
+                   : adjoint_resident_f<Real, RNEA, false>(logT, block, lds, per_cu);
 }
 
 template <class Real>
@@ -534,8 +655,8 @@ hipError_t launch_param_reduce(const double* partial, int groups, int count, Rea
   template hipError_t launch_adjoint<R, true>(const DevModel&, const AdjArgs<R>&, int, int, size_t, hipStream_t); \
   template hipError_t launch_adjoint<R, false>(const DevModel&, const AdjArgs<R>&, int, int, size_t, hipStream_t); \
   template hipError_t launch_param_reduce<R>(const double*, int, int, R*, hipStream_t);                            \
-  template hipError_t adjoint_resident<R, true>(int, int, size_t, int*);                                          \
-  template hipError_t adjoint_resident<R, false>(int, int, size_t, int*);
+  template hipError_t adjoint_resident<R, true>(int, int, int, size_t, int*);                                          \
+  template hipError_t adjoint_resident<R, false>(int, int, int, size_t, int*);
 
 BARD_ADJ_INST(float)
 BARD_ADJ_INST(double)

@@ -425,7 +425,6 @@ int ensure_adj_partial(bard_model* m, DeviceCopy* dc) {
 
 template <class Real, bool RNEA>
 int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t st) {
-  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
   DeviceCopy* dc = nullptr;
   int rc = ensure_device(m, &dc);
   if (rc) return rc;
@@ -445,7 +444,7 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
   // One workgroup per resident slot, each looping over tiles (it prefetches
   // the next tile's inputs while it works on the current one).
   int per_cu = 0, cus = 0;
-  hipError_t eo = adjoint_resident<Real, RNEA>(sh.logT, waves * 64, lds, &per_cu);
+  hipError_t eo = adjoint_resident<Real, RNEA>(sh.logT, dc->dm.free_root, waves * 64, lds, &per_cu);
   if (eo != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(BARD_E_DEVICE, "occupancy query failed");
   int64_t grid = std::min<int64_t>(ar.ntiles, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
@@ -815,7 +814,6 @@ int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* q
                   void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
   int rc = common_checks(m, nullptr, dtype, B);
   if (rc) return rc;
-  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
   if (B == 0) return BARD_OK;
   if (!q || !qd || !qdd || !tau_bar || !q_bar || !qd_bar || !qdd_bar) return fail(BARD_E_ARG, "NULL array");
   if ((rc = check_device_state())) return rc;
@@ -846,7 +844,6 @@ int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* pos
                 const bard_layout* L, int64_t B, void* stream) {
   int rc = common_checks(m, nullptr, dtype, B);
   if (rc) return rc;
-  if (m->free_root) return fail(BARD_E_UNSUPPORTED, "adjoints of trees with a free joint are not implemented");
   if (B == 0) return BARD_OK;
   if (!q || !poses_bar || !q_bar) return fail(BARD_E_ARG, "NULL array");
   if ((rc = check_device_state())) return rc;

@@ -255,7 +255,7 @@ hipError_t launch_adjoint(const DevModel& dm, const AdjArgs<Real>& ar, int grid,
                           hipStream_t st);
 // Workgroups of the adjoint kernel that fit one CU at once (also grants the LDS).
 template <class Real, bool RNEA>
-hipError_t adjoint_resident(int logT, int block, size_t lds, int* per_cu);
+hipError_t adjoint_resident(int logT, int free_root, int block, size_t lds, int* per_cu);
 // out[i] = sum over g < groups of partial[g * count + i], in a fixed order.
 template <class Real>
 hipError_t launch_param_reduce(const double* partial, int groups, int count, Real* out, hipStream_t st);

@@ -163,12 +163,15 @@ def test_adjoint_argument_errors_without_device():
     assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, -2, None) == -1
 
 
-def test_adjoints_of_free_joint_trees_are_rejected():
+def test_adjoints_of_free_joint_trees_check_arguments():
+    """Free-root trees have adjoints; their argument errors are still caught
+    on the host before any launch."""
     m = bard.Model.from_tree(synth.humanoid_small())
     h = m.handle
-    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 8, None) == -7
-    assert bard.bard_fk_vjp(h, 0, None, None, None, None, 8, None) == -7
-    assert "free joint" in bard.bard_last_error().decode()
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 0, None) == 0
+    assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, 8, None) == -1
+    assert bard.bard_fk_vjp(h, 0, None, None, None, None, 8, None) == -1
+    assert "NULL" in bard.bard_last_error().decode()
 
 
 def test_plan_host_side():

@@ -29,6 +29,10 @@ CASES = [
     ("random18", "float32", 300),
     ("random23", "float32", 300),
     ("random23", "float64", 40),
+    # free root (quaternion coordinates)
+    ("humanoid_small", "float32", 300),
+    ("humanoid_small", "float64", 40),
+    ("humanoid_large", "float32", 257),
 ]
 
 

@@ -91,10 +91,7 @@ def test_edge_forward_operators(name, dtype):
         assert dtype == "float64" and tree.n_bodies >= 60, (name, dtype, refused)
 
 
-FIXED_EDGE = [n for n in synth.EDGE_TREES if synth.tree_by_name(n).joint_type[0] != synth.FREE]
-
-
-@pytest.mark.parametrize("name", FIXED_EDGE)
+@pytest.mark.parametrize("name", synth.EDGE_TREES)
 def test_edge_adjoints(name):
     dtype = "float32"
     B = 65
