@@ -214,18 +214,59 @@ __device__ __forceinline__ void copy16(unsigned char* dst, const unsigned char* 
   for (int i = tid; i < n16; i += nt) d[i] = s[i];
 }
 
-// Input tile [K][T] from a strided array; instances past B repeat the last one.
+// K rows of a strided input array (element k of instance b at b*sb + k*sk),
+// staged as an LDS tile [K][T].
+template <class Real>
+struct InRows {
+  const Real* src;
+  int64_t sb, sk;
+  int K;
+  Real* dst;
+};
+
+// Staging of a workgroup: n0 16-byte chunks of img0 and n1 of img1 (model
+// tables, end-effector image) and the input tiles of up to three arrays
+// (instances past B repeat the last one).  Every thread issues its global
+// loads, from clamped indices so that no branch separates them, before its
+// first LDS write: the workgroup waits for one round trip to memory instead
+// of one per source.  Threads past the end rewrite the last element with its
+// own value.
 template <class Real, int LOGT>
-__device__ __forceinline__ void stage_input(const Real* src, int64_t sb, int64_t sk, int K, int64_t tile0, int64_t B,
-                                            Real* dst, int tid, int nt) {
+__device__ __forceinline__ void stage_tile(const int4* img0, int n0, int4* dst0, const int4* img1, int n1,
+                                           int4* dst1, const InRows<Real>& a, const InRows<Real>& b,
+                                           const InRows<Real>& c, int64_t tile0, int64_t B, int tid, int nt) {
   constexpr int T = 1 << LOGT;
-#pragma unroll 8
-  for (int i = tid; i < K * T; i += nt) {
+  const int n16 = n0 + n1;
+  const int nin = (a.K + b.K + c.K) * T;
+  auto chunk_src = [&](int i) { return i < n0 ? img0 + i : img1 + (i - n0); };
+  auto chunk_dst = [&](int i) { return i < n0 ? dst0 + i : dst1 + (i - n0); };
+  auto in_src = [&](int i) {
     const int k = i >> LOGT;
-    int64_t b = tile0 + (i & (T - 1));
-    if (b >= B) b = B - 1;
-    dst[i] = src[b * sb + (int64_t)k * sk];
-  }
+    int64_t bi = tile0 + (i & (T - 1));
+    if (bi >= B) bi = B - 1;
+    if (k < a.K) return a.src + bi * a.sb + (int64_t)k * a.sk;
+    if (k < a.K + b.K) return b.src + bi * b.sb + (int64_t)(k - a.K) * b.sk;
+    return c.src + bi * c.sb + (int64_t)(k - a.K - b.K) * c.sk;
+  };
+  auto in_dst = [&](int i) {
+    const int k = i >> LOGT;
+    if (k < a.K) return a.dst + i;
+    if (k < a.K + b.K) return b.dst + (i - a.K * T);
+    return c.dst + (i - (a.K + b.K) * T);
+  };
+  constexpr int CT = 4, CI = 4;  // loads per thread held in registers
+  int4 tv[CT];
+  Real iv[CI];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) tv[j] = *chunk_src(min(tid + j * nt, n16 - 1));
+#pragma unroll
+  for (int j = 0; j < CI; ++j) iv[j] = *in_src(min(tid + j * nt, nin - 1));
+#pragma unroll
+  for (int j = 0; j < CT; ++j) *chunk_dst(min(tid + j * nt, n16 - 1)) = tv[j];
+#pragma unroll
+  for (int j = 0; j < CI; ++j) *in_dst(min(tid + j * nt, nin - 1)) = iv[j];
+  for (int i = tid + CT * nt; i < n16; i += nt) *chunk_dst(i) = *chunk_src(i);
+  for (int i = tid + CI * nt; i < nin; i += nt) *in_dst(i) = *in_src(i);
 }
 
 // Free-root pose from [x y z qx qy qz qw]: R = R0 R(quat), position R0 p + t0.

@@ -75,55 +75,15 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   const bool full = tile0 + T <= ar.B;
 
   // ---------------- 1. staging ----------------
-  // The table image, the end-effector image and the input tile [K][T]
-  // (instances past B repeat the last one).  Every thread issues its global
-  // loads before any LDS write, so the workgroup waits for one round trip to
-  // memory instead of one per source.
   Real* q_l = reinterpret_cast<Real*>(smem + L.q);
   Real* qd_l = reinterpret_cast<Real*>(smem + L.qd);
   Real* qdd_l = reinterpret_cast<Real*>(smem + L.qdd);
-  {
-    const int n_tab = L.tab_bytes >> 4;
-    const int n16 = n_tab + (JAC ? ee_image_bytes(ee.n_ee, nv) >> 4 : 0);
-    const int KQ = dm.nq, KV = VEL ? nv : 0;
-    const int nin = (KQ + 2 * KV) * T;
-    const int4* tsrc = reinterpret_cast<const int4*>(image<Real>(dm));
-    const int4* esrc = reinterpret_cast<const int4*>(ee.img);
-    int4* tdst = reinterpret_cast<int4*>(smem + L.tab);
-    int4* edst = reinterpret_cast<int4*>(smem + L.ee);
-    auto chunk_src = [&](int c) { return c < n_tab ? tsrc + c : esrc + (c - n_tab); };
-    auto chunk_dst = [&](int c) { return c < n_tab ? tdst + c : edst + (c - n_tab); };
-    auto in_src = [&](int i) {
-      const int k = i >> LOGT;
-      int64_t b = tile0 + (i & (T - 1));
-      if (b >= ar.B) b = ar.B - 1;
-      if (k < KQ) return ar.q + b * ar.sq_b + (int64_t)k * ar.sq_k;
-      if (k < KQ + KV) return ar.qd + b * ar.sqd_b + (int64_t)(k - KQ) * ar.sqd_k;
-      return ar.qdd + b * ar.sqdd_b + (int64_t)(k - KQ - KV) * ar.sqdd_k;
-    };
-    auto in_dst = [&](int i) {
-      const int k = i >> LOGT;
-      if (k < KQ) return q_l + i;
-      if (k < KQ + KV) return qd_l + (i - KQ * T);
-      return qdd_l + (i - (KQ + KV) * T);
-    };
-    constexpr int CT = 4, CI = 4;
-    int4 tv[CT];
-    Real iv[CI];
-    // unconditional loads from clamped indices: no branch separates them, so
-    // they are all in flight before the first wait
-#pragma unroll
-    for (int j = 0; j < CT; ++j) tv[j] = *chunk_src(min(tid + j * nt, n16 - 1));
-#pragma unroll
-    for (int j = 0; j < CI; ++j) iv[j] = *in_src(min(tid + j * nt, nin - 1));
-    // (threads past the end rewrite the last element with its own value)
-#pragma unroll
-    for (int j = 0; j < CT; ++j) *chunk_dst(min(tid + j * nt, n16 - 1)) = tv[j];
-#pragma unroll
-    for (int j = 0; j < CI; ++j) *in_dst(min(tid + j * nt, nin - 1)) = iv[j];
-    for (int c = tid + CT * nt; c < n16; c += nt) *chunk_dst(c) = *chunk_src(c);
-    for (int i = tid + CI * nt; i < nin; i += nt) *in_dst(i) = *in_src(i);
-  }
+  stage_tile<Real, LOGT>(reinterpret_cast<const int4*>(image<Real>(dm)), L.tab_bytes >> 4,
+                         reinterpret_cast<int4*>(smem + L.tab), reinterpret_cast<const int4*>(ee.img),
+                         JAC ? ee_image_bytes(ee.n_ee, nv) >> 4 : 0, reinterpret_cast<int4*>(smem + L.ee),
+                         InRows<Real>{ar.q, ar.sq_b, ar.sq_k, dm.nq, q_l},
+                         InRows<Real>{ar.qd, ar.sqd_b, ar.sqd_k, VEL ? nv : 0, qd_l},
+                         InRows<Real>{ar.qdd, ar.sqdd_b, ar.sqdd_k, VEL ? nv : 0, qdd_l}, tile0, ar.B, tid, nt);
   Real* s_l = reinterpret_cast<Real*>(smem + L.s);        // [nv+1] blocks of 6 rows, block nv = 0
   Real* fc_l = reinterpret_cast<Real*>(smem + L.fc);      // [nv+1] blocks of 6 rows, block nv = 0
   Real* body_l = reinterpret_cast<Real*>(smem + L.body);  // [n] blocks of 24 rows, by preorder position
@@ -1052,13 +1012,14 @@ __global__ void __launch_bounds__(aba_max_threads(sizeof(Real))) aba_kernel(DevM
   const int64_t tile = tile_index(ar.xcd_remap);
   const int64_t tile0 = tile * T;
 
-  copy16(smem + L.tab, image<Real>(dm), L.tab_bytes, tid, nt);
   Real* q_l = reinterpret_cast<Real*>(smem + L.q);
   Real* qd_l = reinterpret_cast<Real*>(smem + L.qd);
   Real* t_l = reinterpret_cast<Real*>(smem + L.tin);
-  stage_input<Real, LOGT>(ar.q, ar.sq_b, ar.sq_k, dm.nq, tile0, ar.B, q_l, tid, nt);
-  stage_input<Real, LOGT>(ar.qd, ar.sqd_b, ar.sqd_k, nv, tile0, ar.B, qd_l, tid, nt);
-  stage_input<Real, LOGT>(ar.tau_in, ar.sti_b, ar.sti_k, nv, tile0, ar.B, t_l, tid, nt);
+  const int4* timg = reinterpret_cast<const int4*>(image<Real>(dm));
+  int4* tdst = reinterpret_cast<int4*>(smem + L.tab);
+  stage_tile<Real, LOGT>(timg, L.tab_bytes >> 4, tdst, timg, 0, tdst,
+                         InRows<Real>{ar.q, ar.sq_b, ar.sq_k, dm.nq, q_l}, InRows<Real>{ar.qd, ar.sqd_b, ar.sqd_k, nv, qd_l},
+                         InRows<Real>{ar.tau_in, ar.sti_b, ar.sti_k, nv, t_l}, tile0, ar.B, tid, nt);
   __syncthreads();
 
   const Tables<Real> tb = tables<Real>(smem + L.tab, dm);
