@@ -13,6 +13,7 @@ sets rotate so every step reads new inputs and the working set exceeds the
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -64,13 +65,20 @@ def time_calls(torch, calls, steps, warmup):
     st = torch.cuda.Event(enable_timing=True)
     en = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st.record()
-    for k in range(steps):
-        calls[k % n]()
-    en.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    # Python's collector is paused while timing: its pauses (hundreds of
+    # microseconds) would otherwise land between launches at random
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        st.record()
+        for k in range(steps):
+            calls[k % n]()
+        en.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
     return wall, st.elapsed_time(en) / steps
 
 

@@ -147,6 +147,9 @@ def _dtype_code(t) -> int:
 
 def _stream_ptr(t):
     torch = _torch()
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:  # the current stream's handle without building a Stream object
+        return _vp(raw(t.device.index if t.device.index is not None else torch.cuda.current_device()))
     return _vp(torch.cuda.current_stream(t.device).cuda_stream)
 
 
