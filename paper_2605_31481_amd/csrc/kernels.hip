@@ -86,7 +86,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
                          InRows<Real>{ar.qdd, ar.sqdd_b, ar.sqdd_k, VEL ? nv : 0, qdd_l}, tile0, ar.B, tid, nt);
   Real* s_l = reinterpret_cast<Real*>(smem + L.s);        // [nv+1] blocks of 6 rows, block nv = 0
   Real* fc_l = reinterpret_cast<Real*>(smem + L.fc);      // [nv+1] blocks of 6 rows, block nv = 0
-  Real* body_l = reinterpret_cast<Real*>(smem + L.body);  // [n] blocks of 24 rows, by preorder position
+  Real* body_l = reinterpret_cast<Real*>(smem + L.body);  // [n] blocks of SB, by preorder position
   Real* o_l = reinterpret_cast<Real*>(smem + L.o);        // [3][T]
   Real* pe_l = reinterpret_cast<Real*>(smem + L.pe);      // [n_ee][3][T]
   if (NEED_S)

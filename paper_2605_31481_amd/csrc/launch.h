@@ -139,9 +139,10 @@ __host__ __device__ constexpr int block_pad(int T, int rs) { return (rs == 4 && 
 // function on the host (to size the launch) and in the kernels.  Per-dof
 // blocks (s, fc) hold 6 rows and get one extra all-zero block (index nv) that
 // structural zeros of the dense outputs read, so the output loops need no
-// branches.  Per-body blocks hold 24 rows (R, p, v, a after the sweep; f and
-// the world inertia after the body phase) and are indexed by preorder position
-// so every subtree is a contiguous range.
+// branches.  Per-body blocks hold body_rows(ops) rows (R, p, v, a and, with
+// OP_BIAS, the acceleration without qdd terms after the sweep; f, the world
+// inertia and the bias force after the body phase) and are indexed by
+// preorder position so every subtree is a contiguous range.
 struct LdsPlan {
   int q, qd, qdd, tin;        // input tiles [K][T]
   int s, fc, body, o, pe;     // tree-kernel state
