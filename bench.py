@@ -239,6 +239,30 @@ def bench_adjoints(torch, bard, steps):
             "fk_vjp_819200_hbm_frac": bytes_f / k_f / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_sysid(torch, bard):
+    """Mass identification (Sec. 4.3's experiment) on 10,000 random
+    configurations of the 11-DOF quadruped, FP32: torques from the true
+    parameters by the library plus 5% Gaussian noise per joint, masses started
+    30% away from the truth, L-BFGS, 10 seeds."""
+    import synth
+    from paper_2605_31481_amd import sysid
+    tree = synth.quadruped_spine()
+    m = bard.Model.from_tree(tree)
+    q, qd, qdd = (torch.from_numpy(synth.to_fp32_grid(x).T.copy()).float().cuda()
+                  for x in synth.random_state(tree, 10000, 9100))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = sysid.identify(m, tree.inertia, q, qd, qdd, seeds=range(10), noise=0.05, max_iter=60)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per_seed = out["rel_error"].mean(axis=1) * 100
+    return {"sysid_mean_mass_error_pct": float(per_seed.mean()), "sysid_std_over_seeds_pct": float(per_seed.std()),
+            "sysid_worst_link_error_pct": float(out["rel_error"].max() * 100),
+            "sysid_iterations_mean": float(np.mean(out["iterations"])),
+            "sysid_evaluations_total": int(np.sum(out["evaluations"])),
+            "sysid_seconds_10_seeds": el}
+
+
 def bench_workspace(torch, bard, steps):
     """Cache patterns of the workspace tiers, B = 4096 FP32, on the 7-DOF
     chain and the 36-DOF humanoid.  One step is FK, Jacobian, CRBA and RNEA on
@@ -401,6 +425,7 @@ def main():
         extra.update(bench_plan(torch, bard, args.steps))
         extra.update(bench_adjoints(torch, bard, args.steps))
         extra.update(bench_workspace(torch, bard, args.steps))
+        extra.update(bench_sysid(torch, bard))
         log(f"[bench] extra {extra}")
 
     cpu = None

@@ -368,8 +368,7 @@ class Model:
     def rnea_vjp(self, q, qd, qdd, tau_bar, inertia=None, inertia_grad: bool = True, layout: str = "soa"):
         """Reverse-mode product of RNEA: returns (q_bar, qd_bar, qdd_bar,
         inertia_bar) for the cotangent tau_bar; inertia_bar is [n_bodies, 10],
-        summed over the batch (None if inertia_grad is False).  Fixed-base
-        trees only."""
+        summed over the batch (None if inertia_grad is False)."""
         B = _batch_of(q, self.nq, layout)
         if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
             raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
@@ -388,7 +387,7 @@ class Model:
 
     def fk_vjp(self, q, poses_bar, layout: str = "soa"):
         """Reverse-mode product of FK: q_bar for the cotangent poses_bar (per
-        body 3x4 row-major [R | p]).  Fixed-base trees only."""
+        body 3x4 row-major [R | p])."""
         B = _batch_of(q, self.nq, layout)
         qb = _new(q, self.nq, B, layout)
         L = _layouts([q, poses_bar, qb], layout)
