@@ -237,6 +237,19 @@ int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const voi
  * Errors: as bard_rnea_vjp. */
 int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* poses_bar,
                 void* q_bar, const bard_layout* L, int64_t B, void* stream);
+/* aba_vjp: reverse-mode product of forward dynamics qdd = ABA(q, qd, tau)
+ * (the analytical derivatives of forward dynamics).  Differentiating
+ * RNEA(q, qd, qdd) = tau gives dqdd = M^-1 (dtau - dRNEA/dq dq - dRNEA/dqd dqd),
+ * so for the cotangent qdd_bar: tau_bar = M^-1 qdd_bar (the articulated-body
+ * sweeps with no velocity and no gravity), and q_bar, qd_bar are the RNEA
+ * adjoint at (q, qd, qdd) for the cotangent -tau_bar.  qdd must be the
+ * forward-dynamics result for (q, qd, tau).
+ * Arrays (L order): q [nq], qd [nv], qdd [nv], qdd_bar [nv] in; q_bar [nq],
+ * qd_bar [nv], tau_bar [nv] out.  Two launches on `stream`.
+ * Errors: as bard_rnea_vjp. */
+int bard_aba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                 const void* qdd_bar, void* q_bar, void* qd_bar, void* tau_bar, const bard_layout* L,
+                 int64_t B, void* stream);
 
 /* ---------------------------------------------------- multi-tree plans ----
  * A plan evaluates several models, each with its own batch size, in one

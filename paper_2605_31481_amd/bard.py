@@ -89,6 +89,7 @@ bard_chain = _sig("bard_chain", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _i32, _c
 bard_rnea_vjp = _sig("bard_rnea_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64,
                                        _vp])
 bard_fk_vjp = _sig("bard_fk_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
+bard_aba_vjp = _sig("bard_aba_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64, _vp])
 bard_plan_create = _sig("bard_plan_create", [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64), ctypes.c_uint32,
                                              ctypes.c_int, ctypes.POINTER(_vp)])
 bard_plan_autotune = _sig("bard_plan_autotune", [_vp, _vp, _i32])
@@ -385,6 +386,19 @@ class Model:
                              _ptr(qb), _ptr(qdb), _ptr(qddb), _ptr(pib), L, B, _stream_ptr(q)), "bard_rnea_vjp")
         return qb, qdb, qddb, pib
 
+    def aba_vjp(self, q, qd, qdd, qdd_bar, layout: str = "soa"):
+        """Reverse-mode product of forward dynamics (bard_aba_vjp): returns
+        (q_bar, qd_bar, tau_bar) for the cotangent qdd_bar; qdd is the
+        forward-dynamics result for (q, qd, tau)."""
+        B = _batch_of(q, self.nq, layout)
+        qb = _new(q, self.nq, B, layout)
+        qdb = _new(q, self.nv, B, layout)
+        tb = _new(q, self.nv, B, layout)
+        L = _layouts([q, qd, qdd, qdd_bar, qb, qdb, tb], layout)
+        _check(bard_aba_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(qdd_bar), _ptr(qb),
+                            _ptr(qdb), _ptr(tb), L, B, _stream_ptr(q)), "bard_aba_vjp")
+        return qb, qdb, tb
+
     def fk_vjp(self, q, poses_bar, layout: str = "soa"):
         """Reverse-mode product of FK: q_bar for the cotangent poses_bar (per
         body 3x4 row-major [R | p])."""
@@ -574,6 +588,28 @@ class _FkFn(torch.autograd.Function):
     def backward(ctx, poses_bar):
         (q,) = ctx.saved_tensors
         return None, ctx.model.fk_vjp(q, poses_bar.contiguous())
+
+
+class _AbaFn(torch.autograd.Function):
+    """qdd = ABA(q, qd, tau) with gradients for q, qd and tau."""
+
+    @staticmethod
+    def forward(ctx, model, q, qd, tau):
+        ctx.model = model
+        qdd = model.aba(q, qd, tau)
+        ctx.save_for_backward(q, qd, qdd)
+        return qdd
+
+    @staticmethod
+    def backward(ctx, qdd_bar):
+        q, qd, qdd = ctx.saved_tensors
+        qb, qdb, tb = ctx.model.aba_vjp(q, qd, qdd, qdd_bar.contiguous())
+        return None, qb, qdb, tb
+
+
+def aba(model: Model, q, qd, tau):
+    """Differentiable forward dynamics on [K, B] (instance-minor) tensors."""
+    return _AbaFn.apply(model, q, qd, tau)
 
 
 def rnea(model: Model, q, qd, qdd, inertia=None):

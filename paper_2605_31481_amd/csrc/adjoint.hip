@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
     if (k < nv) return ar.qd[b * ar.sqd_b + (int64_t)k * ar.sqd_k];
     k -= nv;
     if (k < nv) return ar.qdd[b * ar.sqdd_b + (int64_t)k * ar.sqdd_k];
-    return ar.tau_bar[b * ar.stb_b + (int64_t)(k - nv) * ar.stb_k];
+    return ar.tb_scale * ar.tau_bar[b * ar.stb_b + (int64_t)(k - nv) * ar.stb_k];
   };
   // The next tile's inputs are loaded into registers while this tile's body
   // and subtree phases run, and written to the other input buffer at the end.
@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
           for (int k = 0; k < 6; ++k) w[k] += ws[k];
           if (bok) {
             ar.qd_bar[bo * ar.sqdo_b + (int64_t)d * ar.sqdo_k] = dot6(s, vJb);
-            ar.qdd_bar[bo * ar.sqddo_b + (int64_t)d * ar.sqddo_k] = dot6(s, A);
+            if (ar.qdd_bar) ar.qdd_bar[bo * ar.sqddo_b + (int64_t)d * ar.sqddo_k] = dot6(s, A);
           }
         }
 #pragma unroll

@@ -826,6 +826,7 @@ int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* q
     a.qd = (const R*)qd;
     a.qdd = (const R*)qdd;
     a.tau_bar = (const R*)tau_bar;
+    a.tb_scale = R(1);
     a.pi_ovr = (const R*)inertia_override;
     a.q_bar = (R*)q_bar;
     a.qd_bar = (R*)qd_bar;
@@ -859,6 +860,51 @@ int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* pos
         !layout_of(L, 2, B, m->nq, &a.sqo_b, &a.sqo_k))
       return fail(BARD_E_ARG, "bad layout stride");
     return run_adjoint<R, false>(m, a, nullptr, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_aba_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                 const void* qdd_bar, void* q_bar, void* qd_bar, void* tau_bar, const bard_layout* L, int64_t B,
+                 void* stream) {
+  int rc = common_checks(m, nullptr, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !qd || !qdd || !qdd_bar || !q_bar || !qd_bar || !tau_bar) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    const hipStream_t st = (hipStream_t)stream;
+    // 1. tau_bar = M^-1 qdd_bar: the articulated-body sweeps with no velocity
+    //    and no gravity (M is symmetric, so M^-T = M^-1)
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.qd = (const R*)qd;
+    a.tau_in = (const R*)qdd_bar;
+    a.qdd_out = (R*)tau_bar;
+    a.aba_solve = 1;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
+        !layout_of(L, 3, B, m->nv, &a.sti_b, &a.sti_k) || !layout_of(L, 6, B, m->nv, &a.sqo_b, &a.sqo_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    AdjArgs<R> j;
+    std::memset(&j, 0, sizeof(j));
+    j.B = B;
+    j.q = (const R*)q;
+    j.qd = (const R*)qd;
+    j.qdd = (const R*)qdd;
+    j.tau_bar = (const R*)tau_bar;
+    j.tb_scale = R(-1);
+    j.q_bar = (R*)q_bar;
+    j.qd_bar = (R*)qd_bar;
+    if (!layout_of(L, 0, B, m->nq, &j.sq_b, &j.sq_k) || !layout_of(L, 1, B, m->nv, &j.sqd_b, &j.sqd_k) ||
+        !layout_of(L, 2, B, m->nv, &j.sqdd_b, &j.sqdd_k) || !layout_of(L, 6, B, m->nv, &j.stb_b, &j.stb_k) ||
+        !layout_of(L, 4, B, m->nq, &j.sqo_b, &j.sqo_k) || !layout_of(L, 5, B, m->nv, &j.sqdo_b, &j.sqdo_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    int rc2 = run_aba<R>(m, a, st);
+    if (rc2) return rc2;
+    // 2. (q_bar, qd_bar) = -(dRNEA/d(q, qd))^T tau_bar at (q, qd, qdd): the
+    //    RNEA adjoint with the cotangent read negated
+    return run_adjoint<R, true>(m, j, nullptr, st);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }

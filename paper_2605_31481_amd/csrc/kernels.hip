@@ -1018,8 +1018,12 @@ __global__ void __launch_bounds__(aba_max_threads(sizeof(Real))) aba_kernel(DevM
   const int4* timg = reinterpret_cast<const int4*>(image<Real>(dm));
   int4* tdst = reinterpret_cast<int4*>(smem + L.tab);
   stage_tile<Real, LOGT>(timg, L.tab_bytes >> 4, tdst, timg, 0, tdst,
-                         InRows<Real>{ar.q, ar.sq_b, ar.sq_k, dm.nq, q_l}, InRows<Real>{ar.qd, ar.sqd_b, ar.sqd_k, nv, qd_l},
+                         InRows<Real>{ar.q, ar.sq_b, ar.sq_k, dm.nq, q_l},
+                         InRows<Real>{ar.qd, ar.sqd_b, ar.sqd_k, ar.aba_solve ? 0 : nv, qd_l},
                          InRows<Real>{ar.tau_in, ar.sti_b, ar.sti_k, nv, t_l}, tile0, ar.B, tid, nt);
+  // solve mode (qdd = M^-1 tau): zero velocities instead of staged ones
+  if (ar.aba_solve)
+    for (int i = tid; i < nv * T; i += nt) qd_l[i] = Real(0);
   __syncthreads();
 
   const Tables<Real> tb = tables<Real>(smem + L.tab, dm);
@@ -1044,7 +1048,9 @@ __global__ void __launch_bounds__(aba_max_threads(sizeof(Real))) aba_kernel(DevM
   const int64_t b = tile0 + inst;
   const bool bvalid = b < ar.B;
   const int lane0 = iw << log2P;
-  const Real a0[6] = {Real(0), Real(0), Real(0), -grav<Real>(dm, 0), -grav<Real>(dm, 1), -grav<Real>(dm, 2)};
+  const Real gs = ar.aba_solve ? Real(0) : Real(1);  // solve mode: no gravity
+  const Real a0[6] = {Real(0), Real(0), Real(0), -gs * grav<Real>(dm, 0), -gs * grav<Real>(dm, 1),
+                      -gs * grav<Real>(dm, 2)};
   const Real* qi_l = q_l + inst;
   const Real* qdi_l = qd_l + inst;
   const Real* ti_l = t_l + inst;

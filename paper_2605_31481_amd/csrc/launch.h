@@ -35,6 +35,7 @@ struct Args {
   int frame;
   int xcd_remap;
   int stream_out;  // 1: dense outputs use non-temporal (streaming) stores
+  int aba_solve;   // ABA only: 1 = qdd = M^-1 tau (no velocity, no gravity; qd not read)
   // Kinematics tier of a workspace (see kin_rows): instance-minor rows with
   // stride kin_ld.  kin_mode 0: unused; 1: store the poses, motion subspaces
   // and base origin this launch computes; 2: load them instead of computing.
@@ -209,6 +210,7 @@ struct AdjArgs {
   Real* qd_bar;
   Real* qdd_bar;
   double* partial;  // [gridDim.x][n][10] per-workgroup inertial-parameter gradients, or NULL
+  Real tb_scale;    // tau_bar is read as tb_scale * tau_bar (1 for the plain product)
   int64_t sq_b, sq_k, sqd_b, sqd_k, sqdd_b, sqdd_k, stb_b, stb_k, spb_b, spb_k;
   int64_t sqo_b, sqo_k, sqdo_b, sqdo_k, sqddo_b, sqddo_k;
   int64_t B, ntiles;

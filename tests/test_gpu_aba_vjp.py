@@ -1,0 +1,105 @@
+"""GPU reverse-mode product of forward dynamics (bard_aba_vjp) through the
+C ABI.
+
+FP64 runs are pinned to central differences of the oracle's articulated-body
+algorithm (h = 1e-6; the quaternion of a free root is perturbed component by
+component and normalised on read, as the kernels do) and to a dense solve
+with the oracle's mass matrix for tau_bar = M^-1 qdd_bar.  FP32 runs are
+checked stage by stage: tau_bar by its backward error (the ABA contract,
+since the forward error of a solve is bounded only by cond(M) u), and q_bar,
+qd_bar against the oracle's RNEA adjoint applied to that tau_bar, with the
+bound relative to the sum of the absolute per-dof terms."""
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2605_31481_amd import bard
+from parity_util import TOL, assert_normwise_scaled, from_dev, inputs, oracle_for, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name, B, seed, dtype):
+    tree = synth.tree_by_name(name)
+    om = oracle_for(tree)
+    q, qd, qdd0 = inputs(tree, B, seed, dtype)
+    tau = om.rnea(q, qd, qdd0)
+    if dtype == "float32":
+        tau = synth.to_fp32_grid(tau)
+    qdd = om.aba(q, qd, tau)
+    if dtype == "float32":
+        qdd = synth.to_fp32_grid(qdd)
+    cot = np.random.default_rng(seed + 1).standard_normal((B, tree.nv))
+    if dtype == "float32":
+        cot = synth.to_fp32_grid(cot)
+    return tree, bard.Model.from_tree(tree), om, q, qd, tau, qdd, cot
+
+
+@pytest.mark.parametrize("name,B", [("quadruped_spine", 64), ("humanoid_small", 40), ("chain7", 50),
+                                    ("random18", 30)])
+def test_aba_vjp_vs_central_differences(name, B):
+    dtype = "float64"
+    say(f"[gpu] aba_vjp {name} {dtype} B={B}")
+    tree, m, om, q, qd, tau, qdd, cot = _setup(name, B, 3600, dtype)
+    qb, qdb, tb = m.aba_vjp(*(to_dev(x, dtype) for x in (q, qd, qdd, cot)))
+    tb_ref = np.linalg.solve(om.crba(q), cot[..., None])[..., 0]
+    h = 1e-6
+    qb_ref = np.zeros((B, tree.nq))
+    for k in range(tree.nq):
+        e = np.zeros(tree.nq)
+        e[k] = h
+        qb_ref[:, k] = np.einsum("bi,bi->b", om.aba(q + e, qd, tau) - om.aba(q - e, qd, tau), cot) / (2 * h)
+    qdb_ref = np.zeros((B, tree.nv))
+    for k in range(tree.nv):
+        e = np.zeros(tree.nv)
+        e[k] = h
+        qdb_ref[:, k] = np.einsum("bi,bi->b", om.aba(q, qd + e, tau) - om.aba(q, qd - e, tau), cot) / (2 * h)
+
+    def close(label, gpu, ref, rtol):
+        err = np.abs(gpu - ref).max(axis=1)
+        bound = rtol * (1.0 + np.abs(ref).max(axis=1))
+        assert (err <= bound).all(), f"{label}: worst {float((err / bound).max()):.3g} of the bound"
+
+    close("tau_bar", from_dev(tb), tb_ref, 1e-9)
+    close("q_bar", from_dev(qb), qb_ref, 1e-6)      # central differences: O(h^2) + rounding / h
+    close("qd_bar", from_dev(qdb), qdb_ref, 1e-6)
+
+
+@pytest.mark.parametrize("name,B", [("quadruped_spine", 300), ("humanoid_large", 129)])
+def test_aba_vjp_fp32_stages(name, B):
+    dtype = "float32"
+    say(f"[gpu] aba_vjp {name} {dtype} B={B}")
+    tree, m, om, q, qd, tau, qdd, cot = _setup(name, B, 3700, dtype)
+    qb, qdb, tb = m.aba_vjp(*(to_dev(x, dtype) for x in (q, qd, qdd, cot)))
+    rtol, atol = TOL[dtype]
+    lam = from_dev(tb)
+    M = om.crba(q)
+    res = np.einsum("bij,bj->bi", M, lam) - cot
+    bound = atol + rtol * (np.abs(cot).max(axis=1) + np.abs(M).sum(axis=2).max(axis=1) * np.abs(lam).max(axis=1))
+    assert (np.abs(res).max(axis=1) <= bound).all()
+    rq, rqd, _, _ = om.rnea_vjp(q, qd, qdd, -lam)
+    # q_bar = -sum_j lam_j dtau_j/dq: the bound is relative to the sum of the
+    # absolute terms (as for the ill-conditioned sums of the edge cases),
+    # since tau_bar = M^-1 qdd_bar can be much larger than the result
+    sq = np.zeros_like(rq)
+    sqd = np.zeros_like(rqd)
+    for j in range(tree.nv):
+        e = np.zeros((B, tree.nv))
+        e[:, j] = 1.0
+        gq, gqd, _, _ = om.rnea_vjp(q, qd, qdd, e)
+        sq += np.abs(lam[:, j:j + 1] * gq)
+        sqd += np.abs(lam[:, j:j + 1] * gqd)
+    assert_normwise_scaled("q_bar", from_dev(qb)[:, None], rq[:, None], sq.max(axis=1), dtype)
+    assert_normwise_scaled("qd_bar", from_dev(qdb)[:, None], rqd[:, None], sqd.max(axis=1), dtype)
+
+
+def test_aba_autograd():
+    import torch
+    say("[gpu] aba autograd")
+    tree, m, om, q, qd, tau, qdd, cot = _setup("quadruped_spine", 33, 3800, "float64")
+    tq, tqd, ttau = (to_dev(x, "float64").requires_grad_(True) for x in (q, qd, tau))
+    out = bard.aba(m, tq, tqd, ttau)
+    (out * to_dev(cot, "float64")).sum().backward()
+    qb, qdb, tb = m.aba_vjp(*(to_dev(x, "float64") for x in (q, qd, from_dev(out.detach()), cot)))
+    assert torch.equal(tq.grad, qb) and torch.equal(tqd.grad, qdb) and torch.equal(ttau.grad, tb)
