@@ -163,6 +163,15 @@ def test_adjoint_argument_errors_without_device():
     assert bard.bard_rnea_vjp(h, 0, None, None, None, None, None, None, None, None, None, None, -2, None) == -1
 
 
+def test_aba_vjp_argument_errors_without_device():
+    m = bard.Model.from_tree(synth.humanoid_small())
+    h = m.handle
+    assert bard.bard_aba_vjp(h, 0, None, None, None, None, None, None, None, None, 0, None) == 0   # B = 0
+    assert bard.bard_aba_vjp(h, 0, None, None, None, None, None, None, None, None, 8, None) == -1  # NULL arrays
+    assert bard.bard_aba_vjp(h, 3, None, None, None, None, None, None, None, None, 8, None) == -1  # bad dtype
+    assert bard.bard_aba_vjp(None, 0, None, None, None, None, None, None, None, None, 8, None) == -1
+
+
 def test_adjoints_of_free_joint_trees_check_arguments():
     """Free-root trees have adjoints; their argument errors are still caught
     on the host before any launch."""
