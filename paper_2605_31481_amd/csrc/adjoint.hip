@@ -287,12 +287,21 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
         }
         lstart = 1;
       }
+      // one packed record per (level, slot), read a level ahead (as in the
+      // forward kernels), and the branching levels as a scalar mask
+      const I4* srec = tb.srec + slot;
+      I4 rnext = I4{0, 0, 0, 0};
+      if (lstart < dm.depth) rnext = srec[lstart * P];
       for (int l = lstart; l < dm.depth; ++l) {
-        const int body = in_sched ? tb.sbody[l * P + slot] : -1;
-        const bool act = body >= 0;
-        const int bb = act ? body : 0;
-        if (tb.linfo[2 * l + 1]) {
-          const int src = lane0 + (in_sched ? (int)tb.ssrc[l * P + slot] : slot_raw);
+        const I4 rec = rnext;
+        if (l + 1 < dm.depth) rnext = srec[(l + 1) * P];
+        const bool act = in_sched && ((rec.w >> 16) & 1);
+        const int bb = rec.x;
+        const int pos = rec.y, vi = rec.w & 255;
+        const bool rev = (rec.w >> 17) & 1;
+        const Real qv = q_l[rec.z * T + inst];
+        if ((dm.xmask >> l) & 1) {
+          const int src = lane0 + (in_sched ? ((rec.w >> 8) & 255) : slot_raw);
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rw[k] = xch(Rw[k], src);
 #pragma unroll
@@ -308,13 +317,12 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
         }
         // Bodies on the world all sit at level 0, where every lane starts from
         // the base state set above; the carried state is never reset.
-        const I4 meta = tb.meta[bb];  // {parent, joint type, q index, v index}
         Real s[6];
-        joint_step(tb.cst + bb * CST, meta.y == J_REV, q_l[meta.z * T + inst], Rw, pw, s);
+        joint_step(tb.cst + bb * CST, rev, qv, Rw, pw, s);
         if (RNEA) {
-          const Real qdv = qd_l[meta.w * T + inst];
-          const Real qddv = qdd_l[meta.w * T + inst];
-          const Real tbv = tb_l[meta.w * T + inst];
+          const Real qdv = qd_l[vi * T + inst];
+          const Real qddv = qdd_l[vi * T + inst];
+          const Real tbv = tb_l[vi * T + inst];
           Real vJ[6], cJ[6];
 #pragma unroll
           for (int k = 0; k < 6; ++k) vJ[k] = s[k] * qdv;
@@ -327,10 +335,10 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
           }
         }
         if (act) {
-          Real* sr = s_l + meta.w * SD + inst;
+          Real* sr = s_l + vi * SD + inst;
 #pragma unroll
           for (int k = 0; k < 6; ++k) sr[k * T] = s[k];
-          Real* br = body_l + tb.bm2[bb].x * SB + inst;
+          Real* br = body_l + pos * SB + inst;
 #pragma unroll
           for (int k = 0; k < 9; ++k) br[k * T] = Rw[k];
 #pragma unroll
