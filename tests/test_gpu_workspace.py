@@ -154,6 +154,10 @@ def test_bias_tier(name, dtype, B):
     assert ok.all(), worst
     t3 = m.rnea(q, qd2, qdd2, ws=ws, q_tag=1, qd_tag=1)      # stale qd tag: cached b is used
     assert torch.equal(t3, t2) or tree.depth >= 32
+    # the same hit into batch-major arrays: same arithmetic, same bits
+    ta = m.rnea(to_dev(hq, dtype, "aos"), to_dev(hqd, dtype, "aos"), to_dev(hqdd2, dtype, "aos"), ws=ws, q_tag=1,
+                qd_tag=1, layout="aos")
+    assert torch.equal(ta.t().contiguous(), t2) or tree.depth >= 32
     t4 = m.rnea(q, qd2, qdd2, ws=ws, q_tag=1, qd_tag=2)      # new qd tag: recomputed
     torch.cuda.synchronize()
     check("rnea new qd", t4, om, hq, hqd2, hqdd2)
