@@ -402,6 +402,23 @@ def main():
         # same buffers every call (working set in the Infinity Cache)
         sw, sk = time_calls(torch, calls[:1], max(100, args.steps // 4), 10)
         extra["same_buffers_kernel_us"] = sk * 1e3
+        # the paper's protocol: median of 100 individually timed calls (an
+        # event pair around each call, the device drained between calls), and
+        # the host time of one call through the C ABI (the launch is
+        # asynchronous, so this is the marshalling and launch cost)
+        per_call, host = [], []
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        for k in range(100):
+            torch.cuda.synchronize()
+            ev[k][0].record()
+            h0 = time.perf_counter()
+            calls[k % nsets]()
+            host.append(time.perf_counter() - h0)
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        per_call = [a.elapsed_time(b) * 1e3 for a, b in ev]
+        extra["median_of_100_calls_us"] = float(np.median(per_call))
+        extra["host_us_per_call"] = float(np.median(host)) * 1e6
         # larger batch
         B2 = 16384
         sets2 = make_sets(torch, tree, B2, max(4, math.ceil(512e6 / (bpe * B2))), 4002)
