@@ -351,8 +351,8 @@ def main():
                          "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the batch would shard "
-              "across GPUs with no exchange; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a batch would shard "
+              "across GPUs by instance ranges with no exchange). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

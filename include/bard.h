@@ -63,7 +63,7 @@ typedef enum {
   BARD_E_NOMEM = -4,       /* device or host allocation failed (create calls only) */
   BARD_E_DEVICE = -5,      /* a HIP call failed, or an earlier asynchronous fault */
   BARD_E_CAPACITY = -6,    /* batch larger than a workspace/plan capacity, or model too large */
-  BARD_E_UNSUPPORTED = -7  /* valid request this build does not implement */
+  BARD_E_UNSUPPORTED = -7  /* valid request the library does not implement */
 } bard_status;
 
 typedef enum { BARD_F32 = 0, BARD_F64 = 1 } bard_dtype;
