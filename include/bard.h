@@ -21,7 +21,14 @@
  *   caller keeps ownership).  Every operator I/O pointer is a DEVICE pointer
  *   owned by the caller; the library never frees or retains it past the call.
  *   Operators launch asynchronously on `stream` (a hipStream_t, NULL = the
- *   default stream) and allocate nothing per call.
+ *   default stream).  Device memory the library owns is allocated once, on
+ *   first use, never per call: the model's tables on the first call on a
+ *   device, an end-effector set's table on its first Jacobian or chain call,
+ *   the reduction buffer of bard_rnea_vjp on its first call with
+ *   inertia_bar, workspace tiers on their first use.  Those first uses also
+ *   copy synchronously.  bard_model_upload does the model's part ahead of
+ *   time; a call that would allocate while `stream` is being captured into a
+ *   HIP graph returns BARD_E_CAPTURE and launches nothing.
  * Layout: each operator takes `L`, an array with one bard_layout per array
  *   argument, in the order the arguments appear (inputs first, as listed in the
  *   operator's comment).  Element k of instance b of an array lives at
@@ -63,7 +70,10 @@ typedef enum {
   BARD_E_NOMEM = -4,       /* device or host allocation failed (create calls only) */
   BARD_E_DEVICE = -5,      /* a HIP call failed, or an earlier asynchronous fault */
   BARD_E_CAPACITY = -6,    /* batch larger than a workspace/plan capacity, or model too large */
-  BARD_E_UNSUPPORTED = -7  /* valid request the library does not implement */
+  BARD_E_UNSUPPORTED = -7, /* valid request the library does not implement */
+  BARD_E_CAPTURE = -8      /* the call would allocate or copy synchronously while its stream is
+                              captured into a HIP graph (run it once before capturing, or call
+                              bard_model_upload) */
 } bard_status;
 
 typedef enum { BARD_F32 = 0, BARD_F64 = 1 } bard_dtype;
@@ -96,7 +106,7 @@ const char* bard_version(void);
  *              rotational inertia about the body-frame origin
  * The host-side compile (level schedule, Rodrigues constants of eqs. (2)-(3),
  * tables) happens here; device constants are uploaded on the first operator
- * call on a device.  Errors: BARD_E_ARG, BARD_E_TOPOLOGY, BARD_E_INERTIA,
+ * call on a device, or by bard_model_upload.  Errors: BARD_E_ARG, BARD_E_TOPOLOGY, BARD_E_INERTIA,
  * BARD_E_UNSUPPORTED, BARD_E_NOMEM.  *out is set only on success. */
 int bard_model_create(int32_t n_bodies, const int32_t* parent, const int32_t* joint_type,
                       const double* axis, const double* X_tree, const double* inertia,
@@ -112,6 +122,16 @@ int bard_model_schedule(bard_model_t model, int32_t* lanes_per_instance, int32_t
  * out_R: [3][3] row-major, out_t: [3].  Free joints take q as 7 values. */
 int bard_model_joint_transform(bard_model_t model, int32_t body, const double* q, double* out_R,
                                double* out_t);
+/* Upload ahead of time what the first operator calls on the current device
+ * would upload: the model's tables, and if n_ee > 0 the table of the
+ * end-effector set ee_body (a HOST array of n_ee body indices, as passed to
+ * bard_jacobian / bard_chain), and with flags = BARD_UPLOAD_ADJOINT the
+ * reduction buffer of bard_rnea_vjp.  Synchronous and idempotent; after it,
+ * calls with that model (and end-effector set) on this device allocate
+ * nothing and may be captured into a HIP graph.  Call it outside any capture.
+ * Errors: BARD_E_ARG, BARD_E_NOMEM, BARD_E_DEVICE, BARD_E_CAPTURE. */
+#define BARD_UPLOAD_ADJOINT 1
+int bard_model_upload(bard_model_t model, int32_t n_ee, const int32_t* ee_body, int32_t flags);
 int bard_model_destroy(bard_model_t model);
 
 /* ------------------------------------------------------------ workspace ----
@@ -180,20 +200,32 @@ int bard_rnea(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q,
               const void* qdd, const void* inertia_override, void* tau, const bard_layout* L,
               uint64_t q_tag, uint64_t qd_tag, int64_t B, void* stream);
 
-/* Joint-space mass matrix (CRBA); both triangles written, bitwise symmetric.
+/* Joint-space mass matrix M(q) by the composite-rigid-body algorithm, one of
+ * the operators the paper restructures (Sec. 3; its composite-inertia update
+ * is the 6x6 congruence Sec. 3.5 names as the cost of CRBA and ABA, which the
+ * base-frame kernels here replace by plain sums).  Both triangles are
+ * written from one value, so M is bitwise symmetric.
  * Arrays: q [nq] in, M [nv*nv] out (row-major). */
 int bard_crba(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, void* M,
               const bard_layout* L, uint64_t q_tag, int64_t B, void* stream);
 
-/* Forward dynamics qdd = M^-1 (tau - C qd - g) (ABA, three passes).
+/* Forward dynamics qdd = M(q)^-1 (tau - C(q, qd) qd - g(q)) by the
+ * articulated-body algorithm (Sec. 3), whose three passes (velocities root to
+ * leaves, articulated inertias and bias forces leaves to root, accelerations
+ * root to leaves) Sec. 4.1 names as the reason its rounding error exceeds
+ * that of RNEA and CRBA.  A free root solves its 6x6 articulated system by
+ * Cholesky factorisation.
  * Arrays: q [nq], qd [nv], tau [nv] in, qdd [nv] out. */
 int bard_aba(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd,
              const void* tau, void* qdd, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
              int64_t B, void* stream);
 
 /* Fused RNEA + CRBA + Jacobian: one forward and one backward sweep per
- * instance sharing the per-body transforms.  Results equal the three separate
- * operators.  Arrays: q [nq], qd [nv], qdd [nv] in; tau [nv], M [nv*nv],
+ * instance sharing the per-body transforms.  The paper evaluates the three
+ * operators separately (its "full" pipeline chains them); this fused form and
+ * its throughput metric (evaluations of all three per second) are this
+ * library's addition.  Results equal the three separate operators up to
+ * rounding.  Arrays: q [nq], qd [nv], qdd [nv] in; tau [nv], M [nv*nv],
  * J [n_ee*6*nv] out. */
 int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd,
                const void* qdd, int32_t n_ee, const int32_t* ee_body, bard_frame frame, void* tau,
@@ -202,7 +234,7 @@ int bard_chain(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void* q
 /* ------------------------------------------------------------- adjoints ----
  * Vector-Jacobian products: the gradients Sec. 4.3 takes through RNEA with
  * respect to the state and the inertial parameters (system identification),
- * and the FK gradient of the functional mode (Sec. 3.1).  Both run as one
+ * and the FK gradient of the functional mode (Sec. 3.5).  Both run as one
  * level sweep and subtree sums in the world frame (the gradient for q_j is
  * s_j . W_j, W_j a sum over the subtree of body j), with no stored tape.
  * A free root's q_bar has 7 entries: position (zero for rnea_vjp, which does
@@ -253,9 +285,10 @@ int bard_aba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void
 
 /* ---------------------------------------------------- multi-tree plans ----
  * A plan evaluates several models, each with its own batch size, in one
- * launch over a list of work items (model, tile of instances): the paper's
- * batching of heterogeneous trees whose small batches are launch-bound
- * (Sec. 4.1, the multi-tree configuration).  Items are ordered longest first,
+ * launch over a list of work items (model, tile of instances).  The paper
+ * evaluates one robot per call and notes that small trees leave per-launch
+ * overhead dominant (Sec. 5); batching uneven trees into one launch is this
+ * library's addition for that regime.  Items are ordered longest first,
  * so the hardware workgroup dispatcher, which hands out workgroups in order,
  * acts as a longest-processing-time work queue.
  *
@@ -283,6 +316,9 @@ int bard_aba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void
 int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t* batch,
                      uint32_t op_mask, bard_dtype dtype, bard_plan_t* out);
 int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms);
+/* bard_plan_run on a stream the caller is capturing into a HIP graph: the
+ * plan must have run before (eagerly) with the same io; the call then records
+ * its kernel launches into the caller's graph (BARD_E_CAPTURE otherwise). */
 int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream);
 int bard_plan_destroy(bard_plan_t plan);
 /* Pin a configuration (what bard_plan_autotune chooses): tile 8, 16 or 32,

@@ -42,6 +42,7 @@ def _load():
     lib.orc_jacobian.argtypes = [P, i64, D, ci, I, ci, D, ci]
     lib.orc_rnea.argtypes = [P, i64, D, D, D, D, D, ci]
     lib.orc_crba.argtypes = [P, i64, D, D, ci]
+    lib.orc_crba_pi.argtypes = [P, i64, D, D, D, ci]
     lib.orc_aba.argtypes = [P, i64, D, D, D, D, ci]
     lib.orc_chain.argtypes = [P, i64, D, D, D, ci, I, ci, D, D, D, ci]
     lib.orc_energy.argtypes = [P, i64, D, D, D, D, ci]
@@ -119,10 +120,14 @@ class OracleModel:
                            None if pi is None else _d(pi), _d(out), threads)
         return out
 
-    def crba(self, q, threads=0):
+    def crba(self, q, inertia=None, threads=0):
         q = _f64(q, (-1, self.nq))
         out = np.empty((q.shape[0], self.nv, self.nv))
-        self._lib.orc_crba(self._h, q.shape[0], _d(q), _d(out), threads)
+        if inertia is None:
+            self._lib.orc_crba(self._h, q.shape[0], _d(q), _d(out), threads)
+        else:
+            pi = _f64(inertia, (self.n, 10))
+            self._lib.orc_crba_pi(self._h, q.shape[0], _d(q), _d(pi), _d(out), threads)
         return out
 
     def aba(self, q, qd, tau, threads=0):

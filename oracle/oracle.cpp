@@ -705,6 +705,15 @@ void orc_crba(void* m, int64_t B, const double* q, double* Mout, int nthreads) {
     crba_one<double>(M, q + b * M.nq, M.inertia.data(), Mout + b * (int64_t)M.nv * M.nv);
 }
 
+// CRBA with the inertial parameters [n][10] given by the caller (M is linear
+// in them, as RNEA is), e.g. one body's parameters alone.
+void orc_crba_pi(void* m, int64_t B, const double* q, const double* inertia, double* Mout, int nthreads) {
+  const Model& M = *(Model*)m;
+#pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
+  for (int64_t b = 0; b < B; ++b)
+    crba_one<double>(M, q + b * M.nq, inertia, Mout + b * (int64_t)M.nv * M.nv);
+}
+
 void orc_aba(void* m, int64_t B, const double* q, const double* qd, const double* tau, double* qdd,
              int nthreads) {
   const Model& M = *(Model*)m;

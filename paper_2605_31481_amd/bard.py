@@ -41,6 +41,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 F32, F64 = 0, 1
 REVOLUTE, PRISMATIC, FREE, FIXED = 0, 1, 2, 3
 WORLD, LOCAL_WORLD_ALIGNED = 0, 1
+E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
+UPLOAD_ADJOINT = 1
 # workspace tiers (bard_ws_set_policy bits)
 TIER_KINEMATICS, TIER_MASS, TIER_BIAS = 1, 2, 4
 
@@ -75,6 +77,7 @@ bard_model_info = _sig("bard_model_info", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i3
 bard_model_schedule = _sig("bard_model_schedule", [_vp, _c_i32p, _c_i32p])
 bard_model_joint_transform = _sig("bard_model_joint_transform", [_vp, _i32, _c_dp, _c_dp, _c_dp])
 bard_model_destroy = _sig("bard_model_destroy", [_vp])
+bard_model_upload = _sig("bard_model_upload", [_vp, _i32, _c_i32p, _i32])
 bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
 bard_ws_destroy = _sig("bard_ws_destroy", [_vp])
 bard_ws_set_policy = _sig("bard_ws_set_policy", [_vp, _i32])
@@ -155,6 +158,8 @@ def _stream_ptr(t):
 
 
 def _batch_of(t, K: int, layout: str) -> int:
+    if layout not in ("soa", "aos"):
+        raise ValueError(f"layout must be 'soa' or 'aos', got {layout!r}")
     if t.dim() != 2:
         raise ValueError("operator arrays are 2-D: [K, B] (soa) or [B, K] (aos)")
     if layout == "soa":
@@ -164,6 +169,44 @@ def _batch_of(t, K: int, layout: str) -> int:
     if t.shape[1] != K:
         raise ValueError(f"expected [B, {K}], got {tuple(t.shape)}")
     return int(t.shape[0])
+
+
+def _on_gpu(t, name: str):
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a GPU tensor (the kernels read device memory), got device {t.device}")
+
+
+def _check_arrays(q, arrays, B: int, layout: str):
+    """Every array of a call: shape [K, B] (soa) or [B, K] (aos), the dtype of
+    q and the GPU device of q.  The C ABI receives bare pointers and strides,
+    so a short or misplaced array would be read or written out of bounds;
+    these checks run before the foreign call.  ``arrays`` holds (tensor, K,
+    name) triples; a None tensor is skipped."""
+    _on_gpu(q, "q")
+    _dtype_code(q)
+    for t, K, name in arrays:
+        if t is None:
+            continue
+        _on_gpu(t, name)
+        if t.device != q.device:
+            raise ValueError(f"{name} is on device {t.device}, q on device {q.device}")
+        if t.dtype != q.dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}, q has {q.dtype}")
+        if _batch_of(t, K, layout) != B:
+            raise ValueError(f"{name}: batch {_batch_of(t, K, layout)} differs from q's batch {B}")
+        if min(t.stride()) < 1 and t.numel() > 0:
+            raise ValueError(f"{name} has a zero stride (an expanded view); pass a materialised tensor")
+
+
+def _check_inertia(q, inertia, n_bodies: int, name: str = "inertia"):
+    """A shared [n_bodies, 10] parameter tensor (override or gradient)."""
+    if inertia is None:
+        return
+    _on_gpu(inertia, name)
+    if inertia.device != q.device or inertia.dtype != q.dtype:
+        raise ValueError(f"{name} must be on q's device with q's dtype")
+    if tuple(inertia.shape) != (n_bodies, 10) or not inertia.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous [{n_bodies}, 10] tensor, got {tuple(inertia.shape)}")
 
 
 def _layouts(tensors, layout: str):
@@ -296,6 +339,17 @@ class Model:
         except Exception:
             pass
 
+    def upload(self, ee: Optional[Sequence[int]] = None, adjoint: bool = False):
+        """Upload the model's device tables (and an end-effector set's table,
+        and the adjoint reduction buffer) to the current device now, so that
+        later calls allocate nothing and can be captured (bard_model_upload)."""
+        if ee is not None and len(ee) > 0:
+            ee_a, pee = _i32arr(ee)
+            n = len(ee_a)
+        else:
+            ee_a, pee, n = None, None, 0
+        _check(bard_model_upload(self._h, n, pee, UPLOAD_ADJOINT if adjoint else 0), "bard_model_upload")
+
     def joint_transform(self, body: int, q):
         qa, pq = _f64arr(q)
         R = np.zeros(9)
@@ -308,6 +362,7 @@ class Model:
     def fk(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, 12 * self.n_bodies, B, layout)
+        _check_arrays(q, [(out, 12 * self.n_bodies, "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_fk(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_fk")
@@ -318,6 +373,7 @@ class Model:
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
         out = out if out is not None else _new(q, 6 * self.nv * len(ee_a), B, layout)
+        _check_arrays(q, [(out, 6 * self.nv * len(ee_a), "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_jacobian(self._h, wh, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, tag, B,
@@ -328,9 +384,9 @@ class Model:
              q_tag=None, qd_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv, B, layout)
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (out, self.nv, "out")], B, layout)
+        _check_inertia(q, inertia, self.n_bodies)
         L = _layouts([q, qd, qdd, out], layout)
-        if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
-            raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
         wh, tag = _ws_args(ws, q, q_tag)
         _, dtag = _ws_args(ws, qd, qd_tag)
         _check(bard_rnea(self._h, wh, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
@@ -340,6 +396,7 @@ class Model:
     def crba(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv * self.nv, B, layout)
+        _check_arrays(q, [(out, self.nv * self.nv, "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_crba(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_crba")
@@ -348,6 +405,7 @@ class Model:
     def aba(self, q, qd, tau, out=None, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
         out = out if out is not None else _new(q, self.nv, B, layout)
+        _check_arrays(q, [(qd, self.nv, "qd"), (tau, self.nv, "tau"), (out, self.nv, "out")], B, layout)
         L = _layouts([q, qd, tau, out], layout)
         _check(bard_aba(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out), L, 0, 0, B,
                         _stream_ptr(q)), "bard_aba")
@@ -360,6 +418,8 @@ class Model:
             out = (_new(q, self.nv, B, layout), _new(q, self.nv * self.nv, B, layout),
                    _new(q, 6 * self.nv * len(ee_a), B, layout))
         tau, M, J = out
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (tau, self.nv, "tau"),
+                          (M, self.nv * self.nv, "M"), (J, 6 * self.nv * len(ee_a), "J")], B, layout)
         L = _layouts([q, qd, qdd, tau, M, J], layout)
         _check(bard_chain(self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), len(ee_a), pee, int(frame),
                           _ptr(tau), _ptr(M), _ptr(J), L, B, _stream_ptr(q)), "bard_chain")
@@ -371,8 +431,8 @@ class Model:
         inertia_bar) for the cotangent tau_bar; inertia_bar is [n_bodies, 10],
         summed over the batch (None if inertia_grad is False)."""
         B = _batch_of(q, self.nq, layout)
-        if inertia is not None and (inertia.dtype != q.dtype or not inertia.is_contiguous()):
-            raise ValueError("inertia override must be a contiguous [n_bodies, 10] tensor of the same dtype")
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (tau_bar, self.nv, "tau_bar")], B, layout)
+        _check_inertia(q, inertia, self.n_bodies)
         qb = _new(q, self.nq, B, layout)
         qdb = _new(q, self.nv, B, layout)
         qddb = _new(q, self.nv, B, layout)
@@ -391,6 +451,7 @@ class Model:
         (q_bar, qd_bar, tau_bar) for the cotangent qdd_bar; qdd is the
         forward-dynamics result for (q, qd, tau)."""
         B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (qdd_bar, self.nv, "qdd_bar")], B, layout)
         qb = _new(q, self.nq, B, layout)
         qdb = _new(q, self.nv, B, layout)
         tb = _new(q, self.nv, B, layout)
@@ -403,6 +464,7 @@ class Model:
         """Reverse-mode product of FK: q_bar for the cotangent poses_bar (per
         body 3x4 row-major [R | p])."""
         B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(poses_bar, 12 * self.n_bodies, "poses_bar")], B, layout)
         qb = _new(q, self.nq, B, layout)
         L = _layouts([q, poses_bar, qb], layout)
         _check(bard_fk_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(poses_bar), _ptr(qb), L, B, _stream_ptr(q)),
@@ -416,6 +478,8 @@ class Model:
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
         tau, M, J = out
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (tau, self.nv, "tau"),
+                          (M, self.nv * self.nv, "M"), (J, 6 * self.nv * len(ee_a), "J")], B, layout)
         L = _layouts([q, qd, qdd, tau, M, J], layout)
         args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), len(ee_a), pee, int(frame), _ptr(tau),
                 _ptr(M), _ptr(J), L, B, _stream_ptr(q))
@@ -430,6 +494,7 @@ class Model:
 
     def bind_rnea(self, q, qd, qdd, out, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (out, self.nv, "out")], B, layout)
         L = _layouts([q, qd, qdd, out], layout)
         args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _vp(0), _ptr(out), L, 0, 0, B,
                 _stream_ptr(q))
@@ -444,6 +509,7 @@ class Model:
 
     def bind_crba(self, q, out, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(out, self.nv * self.nv, "out")], B, layout)
         L = _layouts([q, out], layout)
         args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q))
         keep = (L, q, out)
@@ -458,6 +524,7 @@ class Model:
     def bind_jacobian(self, q, ee: Sequence[int], out, frame: int = WORLD, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
+        _check_arrays(q, [(out, 6 * self.nv * len(ee_a), "out")], B, layout)
         L = _layouts([q, out], layout)
         args = (self._h, None, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, 0, B,
                 _stream_ptr(q))
@@ -545,6 +612,14 @@ class Plan:
         if len(inputs) != len(self.models):
             raise ValueError("one (q, qd, qdd) tuple per model")
         dev = inputs[0][0].device
+        if getattr(self, "_device", None) is None:
+            self._device = dev
+        for tup in inputs:
+            for t in tup:
+                if t is not None:
+                    _on_gpu(t, "plan input")
+                    if t.device != self._device:
+                        raise ValueError(f"plan inputs must all be on {self._device}, got {t.device}")
         outs = self._outputs(dev)
         ptrs = []
         for (q, qd, qdd), (tau, M, J), m, B in zip(inputs, outs, self.models, self.batches):

@@ -106,8 +106,25 @@ std::vector<unsigned char> table_image(const bard_model* m, int rs) {
   return img;
 }
 
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // the query's own failure is not a device fault
+    // the legacy default stream may not be used while another stream captures
+    return e == hipErrorStreamCaptureImplicit;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+static int capture_refusal(const char* what) {
+  return fail(BARD_E_CAPTURE, std::string(what) +
+                                  " would be allocated while the stream is being captured into a HIP graph; "
+                                  "run the call once before capturing (or call bard_model_upload)");
+}
+
 // Upload the compiled model to the current device (once per device).
-int ensure_device(bard_model* m, DeviceCopy** out) {
+int ensure_device(bard_model* m, DeviceCopy** out, hipStream_t st) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BARD_E_DEVICE, "hipGetDevice failed (no GPU?)");
   if (dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "device index out of range");
@@ -116,6 +133,7 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
     *out = &dc;
     return BARD_OK;
   }
+  if (capturing(st)) return capture_refusal("the model's device tables");
   std::lock_guard<std::mutex> lk(m->mu);
   if (dc.ready) {
     *out = &dc;
@@ -167,7 +185,7 @@ int ensure_device(bard_model* m, DeviceCopy** out) {
   return BARD_OK;
 }
 
-int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out) {
+int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out, hipStream_t st) {
   if (n_ee < 1 || n_ee > BARD_MAX_EE) return fail(BARD_E_ARG, "n_ee must be in 1..16");
   if (!ee_body) return fail(BARD_E_ARG, "ee_body is NULL");
   std::vector<int> key(ee_body, ee_body + n_ee);
@@ -179,6 +197,7 @@ int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, D
     *out = it->second.second;
     return BARD_OK;
   }
+  if (capturing(st)) return capture_refusal("the end-effector table");
   int n_col = 0, n_zero = 0;
   std::vector<int> jt = jacobian_table(m, key, &n_col, &n_zero);
   const int bytes = ee_image_bytes(n_ee, m->nv);
@@ -299,11 +318,12 @@ struct TierUse {
 // Allocate one tier of `rows` instance-minor rows on the workspace's device
 // (the device of its first use).
 template <class Real>
-int ensure_tier(bard_ws* ws, void** tier, int rows) {
+int ensure_tier(bard_ws* ws, void** tier, int rows, hipStream_t st) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   if (ws->dev >= 0 && ws->dev != dev) return fail(BARD_E_ARG, "workspace used on another device");
   if (*tier) return BARD_OK;
+  if (capturing(st)) return capture_refusal("a workspace tier");
   const size_t bytes = (size_t)rows * ws->max_batch * sizeof(Real);
   if (hipMalloc(tier, bytes) != hipSuccess) {
     *tier = nullptr;
@@ -314,9 +334,10 @@ int ensure_tier(bard_ws* ws, void** tier, int rows) {
 }
 
 template <class Real, int OPS>
-int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, Args<Real>* ar, TierUse* tu) {
+int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, Args<Real>* ar, TierUse* tu,
+              hipStream_t st) {
   if (!ws || !(ws->policy & BARD_TIER_KINEMATICS) || q_tag == 0) return BARD_OK;
-  int rc = ensure_tier<Real>(ws, &ws->kin, kin_rows(m->n, m->nv));
+  int rc = ensure_tier<Real>(ws, &ws->kin, kin_rows(m->n, m->nv), st);
   if (rc) return rc;
   const bool need_body = OPS & (OP_FK | OP_RNEA | OP_CRBA);
   const bool need_s = OPS & (OP_JAC | OP_RNEA | OP_CRBA);
@@ -348,13 +369,13 @@ template <class Real, int OPS>
 int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int frame, hipStream_t st,
              bard_ws* ws = nullptr, uint64_t q_tag = 0) {
   DeviceCopy* dc = nullptr;
-  int rc = ensure_device(m, &dc);
+  int rc = ensure_device(m, &dc, st);
   if (rc) return rc;
   TierUse tu;
-  if ((rc = plan_tier<Real, OPS>(m, ws, q_tag, ar.B, frame, &ar, &tu))) return rc;
+  if ((rc = plan_tier<Real, OPS>(m, ws, q_tag, ar.B, frame, &ar, &tu, st))) return rc;
   DevEE ee{nullptr, 0};
   if (OPS & OP_JAC) {
-    rc = ensure_ee(m, dc, n_ee, ee_body, &ee);
+    rc = ensure_ee(m, dc, n_ee, ee_body, &ee, st);
     if (rc) return rc;
   }
   int dev = 0;
@@ -384,7 +405,7 @@ int run_tree(bard_model* m, Args<Real> ar, int n_ee, const int32_t* ee_body, int
 template <class Real>
 int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   DeviceCopy* dc = nullptr;
-  int rc = ensure_device(m, &dc);
+  int rc = ensure_device(m, &dc, st);
   if (rc) return rc;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -413,9 +434,10 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
 // are identical run to run on one GPU model.
 constexpr int kAdjGroups = 2048;
 
-int ensure_adj_partial(bard_model* m, DeviceCopy* dc) {
+int ensure_adj_partial(bard_model* m, DeviceCopy* dc, hipStream_t st) {
   std::lock_guard<std::mutex> lk(m->mu);
   if (dc->adj_partial) return BARD_OK;
+  if (capturing(st)) return capture_refusal("the adjoint reduction buffer");
   void* p = nullptr;
   if (hipMalloc(&p, (size_t)kAdjGroups * m->n * 10 * sizeof(double)) != hipSuccess)
     return fail(BARD_E_NOMEM, "hipMalloc of the adjoint reduction buffer failed");
@@ -426,7 +448,7 @@ int ensure_adj_partial(bard_model* m, DeviceCopy* dc) {
 template <class Real, bool RNEA>
 int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t st) {
   DeviceCopy* dc = nullptr;
-  int rc = ensure_device(m, &dc);
+  int rc = ensure_device(m, &dc, st);
   if (rc) return rc;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -449,7 +471,7 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
     return fail(BARD_E_DEVICE, "occupancy query failed");
   int64_t grid = std::min<int64_t>(ar.ntiles, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
   if (RNEA && inertia_bar) {
-    if ((rc = ensure_adj_partial(m, dc))) return rc;
+    if ((rc = ensure_adj_partial(m, dc, st))) return rc;
     ar.partial = dc->adj_partial;
     grid = std::min<int64_t>(grid, kAdjGroups);
   }
@@ -474,6 +496,7 @@ const char* bard_status_str(int s) {
     case BARD_E_DEVICE: return "BARD_E_DEVICE";
     case BARD_E_CAPACITY: return "BARD_E_CAPACITY";
     case BARD_E_UNSUPPORTED: return "BARD_E_UNSUPPORTED";
+    case BARD_E_CAPTURE: return "BARD_E_CAPTURE";
     default: return "BARD_E_UNKNOWN";
   }
 }
@@ -565,6 +588,22 @@ int bard_model_joint_transform(bard_model_t m, int32_t body, const double* q, do
   double s = std::sin(q[0]), co = std::cos(q[0]);
   for (int k = 0; k < 9; ++k) R[k] = c[C_R0 + k] + s * c[C_A + k] + (1.0 - co) * c[C_B + k];
   for (int k = 0; k < 3; ++k) t[k] = c[C_T0 + k] + q[0] * c[C_D + k];
+  return BARD_OK;
+}
+
+int bard_model_upload(bard_model_t m, int32_t n_ee, const int32_t* ee_body, int32_t flags) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  if (flags & ~BARD_UPLOAD_ADJOINT) return fail(BARD_E_ARG, "flags must be 0 or BARD_UPLOAD_ADJOINT");
+  if (n_ee < 0 || n_ee > BARD_MAX_EE || (n_ee > 0 && !ee_body)) return fail(BARD_E_ARG, "n_ee must be in 0..16");
+  int rc = check_device_state();
+  if (rc) return rc;
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, nullptr))) return rc;
+  if (n_ee > 0) {
+    DevEE ee;
+    if ((rc = ensure_ee(m, dc, n_ee, ee_body, &ee, nullptr))) return rc;
+  }
+  if ((flags & BARD_UPLOAD_ADJOINT) && (rc = ensure_adj_partial(m, dc, nullptr))) return rc;
   return BARD_OK;
 }
 
@@ -687,9 +726,9 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
     if (!ws || !(ws->policy & BARD_TIER_BIAS) || q_tag == 0 || qd_tag == 0 || inertia_override)
       return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, st, ws, q_tag);
     DeviceCopy* dc = nullptr;
-    int rc2 = ensure_device(m, &dc);
+    int rc2 = ensure_device(m, &dc, st);
     if (rc2) return rc2;
-    if ((rc2 = ensure_tier<R>(ws, &ws->bt, m->nv))) return rc2;
+    if ((rc2 = ensure_tier<R>(ws, &ws->bt, m->nv, st))) return rc2;
     const int64_t ld = ws->max_batch;
     const bool b_hit = ws->b_B == B && ws->bq_tag == q_tag && ws->bqd_tag == qd_tag && ws->b_gen == m->g_gen;
     const bool m_hit = ws->mt && ws->m_B == B && ws->m_tag == q_tag;
@@ -734,7 +773,7 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
     const int nn = m->nv * m->nv;
     if (!ws || !(ws->policy & BARD_TIER_MASS) || q_tag == 0)
       return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, st, ws, q_tag);
-    int rc2 = ensure_tier<R>(ws, &ws->mt, nn);
+    int rc2 = ensure_tier<R>(ws, &ws->mt, nn, st);
     if (rc2) return rc2;
     R* mt = (R*)ws->mt;
     const int64_t ld = ws->max_batch;

@@ -14,10 +14,15 @@ int fail(int code, const std::string& msg);
 int check_device_state();
 // Largest dynamic LDS allocation of one workgroup on device `dev`.
 size_t lds_limit(int dev);
-// Upload the model's tables to the current device (once per device).
-int ensure_device(bard_model* m, DeviceCopy** out);
-// Device image of the Jacobian output lists for an end-effector set (cached per set).
-int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out);
+// True if `st` is being captured into a HIP graph (then nothing may be
+// allocated or copied synchronously on its behalf).
+bool capturing(hipStream_t st);
+// Upload the model's tables to the current device (once per device).  On a
+// first use while `st` is being captured: BARD_E_CAPTURE.
+int ensure_device(bard_model* m, DeviceCopy** out, hipStream_t st);
+// Device image of the Jacobian output lists for an end-effector set (cached
+// per set); BARD_E_CAPTURE as for ensure_device.
+int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out, hipStream_t st);
 // Waves per workgroup for the phases after the level sweep (rs: scalar bytes).
 int out_waves(int rs);
 

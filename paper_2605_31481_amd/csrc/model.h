@@ -2,6 +2,7 @@
 // code and the kernels.  Not part of the public ABI (see include/bard.h).
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -79,7 +80,7 @@ struct bard_model {
   std::vector<int> ulist[4];              // subtree work lists (see subtree_units)
   std::vector<double> axis, xtree, inertia;
   double g[3] = {0.0, 0.0, -9.81};
-  uint64_t g_gen = 0;  // bumped by every gravity change (keys the bias tier)
+  std::atomic<uint64_t> g_gen{0};  // bumped by every gravity change (keys the bias tier and plans)
   std::vector<double> cst64;
   std::vector<float> cst32;
   std::vector<int16_t> sched_body;

@@ -93,6 +93,7 @@ struct bard_plan {
   int runs = 0;  // runs since the configuration was prepared (the first is eager)
   std::vector<Group> groups;
   std::vector<int> log2P;
+  std::vector<uint64_t> g_gen;  // each model's gravity generation when the descriptor was uploaded
   int n_items = 0;
   unsigned char* d_buf = nullptr;
   size_t d_bytes = 0, off_ee = 0, off_args = 0, off_items = 0, args_bytes = 0;
@@ -207,16 +208,22 @@ int prepare_t(bard_plan* p) {
   std::vector<DevModel> dms(nm);
   std::vector<DevEE> ees(nm);
   p->log2P.assign(nm, 0);
+  p->g_gen.assign(nm, 0);
   std::vector<double> cost(nm);
   for (int i = 0; i < nm; ++i) {
     bard_model* m = p->models[i];
     DeviceCopy* dc = nullptr;
-    int rc = ensure_device(m, &dc);
+    int rc = ensure_device(m, &dc, nullptr);
     if (rc) return rc;
-    dms[i] = dc->dm;
+    {
+      // the device copy carries the model's current gravity; remember which
+      std::lock_guard<std::mutex> lk(m->mu);
+      dms[i] = dc->dm;
+      p->g_gen[i] = m->g_gen;
+    }
     ees[i] = DevEE{nullptr, 0, 0, 0};
     if (all_ops & OP_JAC) {
-      rc = ensure_ee(m, dc, (int)p->ee[i].size(), p->ee[i].data(), &ees[i]);
+      rc = ensure_ee(m, dc, (int)p->ee[i].size(), p->ee[i].data(), &ees[i], nullptr);
       if (rc) return rc;
     }
     int lp = std::max(m->log2P, 6 - p->cfg.logT);
@@ -396,7 +403,31 @@ hipError_t launch_groups(const bard_plan* p, hipStream_t st) {
   return p->dtype == BARD_F32 ? launch_groups_t<float>(p, st) : launch_groups_t<double>(p, st);
 }
 
+// A model's gravity lives in the plan's device descriptor (and so in its
+// captured graph): a change since the upload prepares the plan again.
+bool gravity_changed(const bard_plan* p) {
+  if (p->g_gen.size() != p->models.size()) return false;
+  for (size_t i = 0; i < p->models.size(); ++i)
+    if (p->models[i]->g_gen != p->g_gen[i]) return true;
+  return false;
+}
+
 int run_plan(bard_plan* p, const void* const* io, hipStream_t st, bool allow_graph) {
+  if (p->ready && gravity_changed(p)) p->ready = false;
+  if (capturing(st)) {
+    // The caller is capturing `st`: nothing may synchronize or allocate, and
+    // the plan's own graph is not launched inside another capture.  A plan
+    // that ran eagerly with the same io records its kernel launches.
+    if (!p->ready || p->runs == 0) return fail(BARD_E_CAPTURE, "a plan must run once before it is captured");
+    std::vector<unsigned char> args;
+    int rc = p->dtype == BARD_F32 ? build_args<float>(p, io, &args) : build_args<double>(p, io, &args);
+    if (rc) return rc;
+    if (args != p->h_last)
+      return fail(BARD_E_CAPTURE, "a captured plan run must use the io of the plan's previous run");
+    hipError_t e = launch_groups(p, st);
+    if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("plan launch failed: ") + hipGetErrorString(e));
+    return BARD_OK;
+  }
   int rc = prepare(p);
   if (rc) return rc;
   std::vector<unsigned char> args;

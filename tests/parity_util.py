@@ -2,15 +2,28 @@
 tolerance contract.
 
 Tolerance contract.  Inputs are rounded to the kernel's precision first and
-the FP64 oracle runs on exactly those values.  For FK, Jacobian, RNEA and CRBA
-the check is normwise per (instance, output block):
-``max_k |gpu - ref| <= atol + rtol * max_k |ref|`` with FP32 rtol = 1e-5,
-atol = 1e-6 and FP64 rtol = atol = 1e-12.  ABA is checked by its backward
-error, ``|RNEA_ref(q, qd, qdd_gpu) - tau|_inf <= atol + rtol * (|tau|_inf +
-|M|_inf |qdd_gpu|_inf + |RNEA_ref(q, qd, 0)|_inf)``, because its forward error
-is only bounded by cond(M) times the unit roundoff.  Trees whose sums are
-badly conditioned (a root carrying tens of children) are checked against the
-size of the summed terms instead of the result (assert_normwise_scaled).
+the FP64 oracle runs on exactly those values; FP32 rtol = 1e-5, atol = 1e-6,
+FP64 rtol = atol = 1e-12.
+
+* Torques and mass-matrix entries are held entry by entry:
+  ``|gpu_e - ref_e| <= atol + rtol * max(|ref_e|, S_e)``, where S_e is the sum
+  over bodies k of |the same entry computed with body k's inertial parameters
+  alone| (``body_terms``).  Both quantities are linear in the parameters, so
+  ref_e is the sum of those per-body terms; any evaluation that rounds each
+  term to the working precision before adding them errs by about u S_e
+  (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 4.2), so S_e
+  is the size the entry's accuracy can be measured against.  Where nothing
+  cancels S_e = |ref_e|.
+* Jacobian columns are held per column (6 rows of one end effector's column
+  against that column's largest entry): a column is a rotated unit axis and
+  its moment, whose rounding error follows the column's size.
+* FK is held per body block (the 12 entries of [R | p]).
+* ABA is held by its backward error per instance (aba_backward_error),
+  because its forward error is only bounded by cond(M) times the unit
+  roundoff.
+* Other outputs (adjoints) keep the normwise block check
+  ``max_k |gpu - ref| <= atol + rtol * max_k |ref|`` unless a test states
+  otherwise.
 """
 
 import sys
@@ -74,6 +87,76 @@ def assert_normwise_scaled(name, gpu, ref, scale, dtype):
     worst = float((err / bound).max())
     assert ok.all(), f"{name}: {int((~ok).sum())} blocks out of tolerance, worst err/bound = {worst:.3g}"
     return worst
+
+
+def body_terms(om, tree, q, qd=None, qdd=None, tau=True, mass=True):
+    """Per-entry sums of the absolute per-body terms of the torque and the mass
+    matrix: S_tau[b, i] = sum_k |RNEA_k(q, qd, qdd)_i| and
+    S_M[b, i*nv + j] = sum_k |CRBA_k(q)_ij|, with RNEA_k and CRBA_k using
+    body k's inertial parameters alone (zeros for every other body).  Returns
+    (S_tau or None, S_M or None)."""
+    B = q.shape[0]
+    st = np.zeros((B, tree.nv)) if tau else None
+    sm = np.zeros((B, tree.nv * tree.nv)) if mass else None
+    for k in range(tree.n_bodies):
+        pi = np.zeros_like(tree.inertia)
+        pi[k] = tree.inertia[k]
+        if tau:
+            st += np.abs(om.rnea(q, qd, qdd, inertia=pi))
+        if mass:
+            sm += np.abs(om.crba(q, inertia=pi)).reshape(B, -1)
+    return st, sm
+
+
+def entrywise(gpu, ref, scale, rtol, atol):
+    """Per-entry check ``|gpu - ref| <= atol + rtol * max(|ref|, scale)``.
+    Returns (ok mask, worst err/bound)."""
+    err = np.abs(gpu - ref)
+    bound = atol + rtol * np.maximum(np.abs(ref), scale)
+    ratio = err / bound
+    return ratio <= 1.0, float(ratio.max()) if ratio.size else 0.0
+
+
+def assert_entrywise(name, gpu, ref, scale, dtype):
+    rtol, atol = TOL[dtype]
+    gpu = np.asarray(gpu).reshape(ref.shape)
+    ok, worst = entrywise(gpu, ref, scale.reshape(ref.shape), rtol, atol)
+    assert ok.all(), f"{name}: {int((~ok).sum())} entries out of tolerance, worst err/bound = {worst:.3g}"
+    return worst
+
+
+def column_scale(J):
+    """J [B, n_ee, 6, nv] -> per-entry scale: the largest |entry| of its column."""
+    return np.broadcast_to(np.abs(J).max(axis=2, keepdims=True), J.shape)
+
+
+def assert_tau(name, gpu, ref, S, dtype):
+    return assert_entrywise(name, gpu, ref, S, dtype)
+
+
+def assert_mass(name, gpu, ref, S, dtype):
+    B = ref.shape[0]
+    return assert_entrywise(name, np.asarray(gpu).reshape(B, -1), ref.reshape(B, -1), S, dtype)
+
+
+def assert_jacobian(name, gpu, ref, dtype):
+    """ref [B, n_ee, 6, nv]; gpu any shape of the same size."""
+    return assert_entrywise(name, np.asarray(gpu).reshape(ref.shape), ref, column_scale(ref), dtype)
+
+
+def assert_chain(om, tree, q, qd, qdd, ee, tau, M, J, dtype, frame=0, label="chain", ref=None, S=None):
+    """Per-entry contract for the outputs of one chain evaluation (host arrays,
+    instance-major; any of tau, M, J may be None)."""
+    rt, rM, rJ = ref if ref is not None else om.chain(q, qd, qdd, ee, frame=frame)
+    st, sm = S if S is not None else body_terms(om, tree, q, qd, qdd, tau=tau is not None, mass=M is not None)
+    w = {}
+    if tau is not None:
+        w["tau"] = assert_tau(f"{label}.tau", tau, rt, st, dtype)
+    if M is not None:
+        w["M"] = assert_mass(f"{label}.M", M, rM, sm, dtype)
+    if J is not None:
+        w["J"] = assert_jacobian(f"{label}.J", J, rJ, dtype)
+    return w
 
 
 def term_scales(om, tree, q, qd, qdd):

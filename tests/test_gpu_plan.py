@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import OracleModel
 from paper_2605_31481_amd import bard
 from parity_util import assert_normwise, from_dev, inputs, oracle_for, say, to_dev
 
@@ -136,3 +137,29 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     again = bard.Plan(models, batches)
     c2 = again.config
     assert c2["from_cache"] and (c2["tile"], c2["fusion"], c2["order"]) == (cfg["tile"], cfg["fusion"], cfg["order"])
+
+
+def test_plan_follows_gravity_changes():
+    """A plan keeps each model's gravity in its device descriptor and graph:
+    after bard_model_set_gravity the next run must use the new value."""
+    import torch
+    say("[gpu] plan after a gravity change")
+    trees, models, batches, host, dev = _setup(seed=2800, batches=[64, 37, 129, 8, 200])
+    plan = bard.Plan(models, batches, op_mask=bard.PLAN_RNEA)
+    for _ in range(3):                        # eager run, graph capture, replay
+        outs = plan.run(dev)
+    torch.cuda.synchronize()
+    _check(plan, trees, host, outs, "float32", n_sample=32)
+    g_new = np.array([1.5, -2.0, -3.7])
+    for m in models:
+        m.set_gravity(g_new)
+    for _ in range(2):
+        outs = plan.run(dev)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        for k, (tree, (q, qd, qdd)) in enumerate(zip(trees, host)):
+            idx = np.sort(rng.choice(q.shape[0], min(32, q.shape[0]), replace=False))
+            om = OracleModel(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, g_new)
+            ref = om.rnea(q[idx], qd[idx], qdd[idx])
+            assert_normwise(f"tau[{k}] after set_gravity", from_dev(outs[k][0])[idx][:, None], ref[:, None],
+                            "float32")
