@@ -776,6 +776,39 @@ void orc_rnea_vjp(void* m, int64_t B, const double* q, const double* qd, const d
   }
 }
 
+// Reverse-mode gradient of <M_bar, CRBA(q; pi)> (M_bar [nv][nv] row-major per
+// instance): q_bar [nq] and, if inertia_bar is not null, the per-instance
+// parameter gradient [n][10].  The derivatives of the mass matrix that
+// analytical forward-dynamics derivatives need (the paper's outlook on
+// trajectory optimisation, Sec. 5).
+void orc_crba_vjp(void* m, int64_t B, const double* q, const double* M_bar, double* q_bar, double* inertia_bar,
+                  int nthreads) {
+  const Model& M = *(Model*)m;
+#pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    Tape tape;
+    g_tape = &tape;
+    int nq = M.nq, nv = M.nv, np = 10 * M.n;
+    std::vector<Var> vq(nq), vpi(np), vM(nv * nv);
+    for (int k = 0; k < nq; ++k) vq[k] = leaf(q[b * nq + k]);
+    for (int k = 0; k < np; ++k) vpi[k] = leaf(M.inertia[k]);
+    crba_one<Var>(M, vq.data(), vpi.data(), vM.data());
+    std::vector<double> adj(tape.nodes.size(), 0.0);
+    const double* mb = M_bar + b * (int64_t)nv * nv;
+    for (int k = 0; k < nv * nv; ++k)
+      if (vM[k].id >= 0) adj[vM[k].id] += mb[k];
+    for (int i = (int)tape.nodes.size() - 1; i >= 0; --i) {
+      const Node& nd = tape.nodes[i];
+      if (adj[i] == 0.0) continue;
+      if (nd.p0 >= 0) adj[nd.p0] += nd.d0 * adj[i];
+      if (nd.p1 >= 0) adj[nd.p1] += nd.d1 * adj[i];
+    }
+    for (int k = 0; k < nq; ++k) q_bar[b * nq + k] = adj[vq[k].id];
+    if (inertia_bar) for (int k = 0; k < np; ++k) inertia_bar[b * np + k] = adj[vpi[k].id];
+    g_tape = nullptr;
+  }
+}
+
 // Reverse-mode gradient of <poses_bar, FK(q)> with poses laid out [n][12] (3x4 [R|p]).
 void orc_fk_vjp(void* m, int64_t B, const double* q, const double* poses_bar, double* q_bar, int nthreads) {
   const Model& M = *(Model*)m;
