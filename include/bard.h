@@ -269,6 +269,22 @@ int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const voi
  * Errors: as bard_rnea_vjp. */
 int bard_fk_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* poses_bar,
                 void* q_bar, const bard_layout* L, int64_t B, void* stream);
+/* crba_vjp: given M_bar (per instance an nv x nv cotangent, row-major), writes
+ * q_bar [nq] = d<M_bar, M(q)>/dq, the derivatives of the mass matrix that
+ * analytical forward-dynamics derivatives and trajectory optimisation need
+ * (Sec. 2 names analytical dynamics derivatives as prior art; Sec. 5 names
+ * trajectory optimisation as the next use of the differentiable operators).
+ * One traversal: the CRBA sweeps, then per dof and per body the sensitivities
+ * of <M_bar, M> to each motion subspace and composite inertia, gathered over
+ * subtrees as for rnea_vjp.  Only the symmetric part of M_bar matters (M is
+ * symmetric).  A free root's seven entries are zero: with the root velocity
+ * in the root's body frame, M does not depend on the root's pose.
+ * Arrays (L order): q [nq], M_bar [nv*nv] in; q_bar [nq] out.
+ * Errors: BARD_E_ARG, BARD_E_CAPACITY (the tile's on-chip state does not fit,
+ * e.g. FP64 on trees of about 30 bodies or more), BARD_E_DEVICE,
+ * BARD_E_CAPTURE. */
+int bard_crba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void* M_bar, void* q_bar,
+                  const bard_layout* L, int64_t B, void* stream);
 /* aba_vjp: reverse-mode product of forward dynamics qdd = ABA(q, qd, tau)
  * (the analytical derivatives of forward dynamics).  Differentiating
  * RNEA(q, qd, qdd) = tau gives dqdd = M^-1 (dtau - dRNEA/dq dq - dRNEA/dqd dqd),

@@ -48,7 +48,7 @@ def _load():
     lib.orc_energy.argtypes = [P, i64, D, D, D, D, ci]
     lib.orc_rnea_vjp.argtypes = [P, i64, D, D, D, D, D, D, D, D, D, ci]
     lib.orc_fk_vjp.argtypes = [P, i64, D, D, D, ci]
-    lib.orc_crba_vjp.argtypes = [P, i64, D, D, D, D, ci]
+    lib.orc_crba_vjp.argtypes = [P, i64, D, D, D, D, D, ci]
     _lib = lib
     return lib
 
@@ -176,14 +176,15 @@ class OracleModel:
                                _d(tb), _d(qb), _d(qdb), _d(qddb), _d(pib), threads)
         return qb, qdb, qddb, pib
 
-    def crba_vjp(self, q, M_bar, threads=0):
+    def crba_vjp(self, q, M_bar, inertia=None, threads=0):
         """Reverse-mode gradients of <M_bar, M(q)>: (q_bar [B, nq], inertia_bar [B, n, 10])."""
         q = _f64(q, (-1, self.nq))
         mb = _f64(M_bar, (-1, self.nv * self.nv))
         B = q.shape[0]
         qb = np.empty((B, self.nq))
         pib = np.empty((B, self.n, 10))
-        self._lib.orc_crba_vjp(self._h, B, _d(q), _d(mb), _d(qb), _d(pib), threads)
+        pi = None if inertia is None else _f64(inertia, (self.n, 10))
+        self._lib.orc_crba_vjp(self._h, B, _d(q), None if pi is None else _d(pi), _d(mb), _d(qb), _d(pib), threads)
         return qb, pib
 
     def fk_vjp(self, q, poses_bar, threads=0):

@@ -781,9 +781,10 @@ void orc_rnea_vjp(void* m, int64_t B, const double* q, const double* qd, const d
 // parameter gradient [n][10].  The derivatives of the mass matrix that
 // analytical forward-dynamics derivatives need (the paper's outlook on
 // trajectory optimisation, Sec. 5).
-void orc_crba_vjp(void* m, int64_t B, const double* q, const double* M_bar, double* q_bar, double* inertia_bar,
-                  int nthreads) {
+void orc_crba_vjp(void* m, int64_t B, const double* q, const double* inertia_override, const double* M_bar,
+                  double* q_bar, double* inertia_bar, int nthreads) {
   const Model& M = *(Model*)m;
+  const double* pi0 = inertia_override ? inertia_override : M.inertia.data();
 #pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
   for (int64_t b = 0; b < B; ++b) {
     Tape tape;
@@ -791,7 +792,7 @@ void orc_crba_vjp(void* m, int64_t B, const double* q, const double* M_bar, doub
     int nq = M.nq, nv = M.nv, np = 10 * M.n;
     std::vector<Var> vq(nq), vpi(np), vM(nv * nv);
     for (int k = 0; k < nq; ++k) vq[k] = leaf(q[b * nq + k]);
-    for (int k = 0; k < np; ++k) vpi[k] = leaf(M.inertia[k]);
+    for (int k = 0; k < np; ++k) vpi[k] = leaf(pi0[k]);
     crba_one<Var>(M, vq.data(), vpi.data(), vM.data());
     std::vector<double> adj(tape.nodes.size(), 0.0);
     const double* mb = M_bar + b * (int64_t)nv * nv;

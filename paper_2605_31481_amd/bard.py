@@ -92,6 +92,7 @@ bard_chain = _sig("bard_chain", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _i32, _c
 bard_rnea_vjp = _sig("bard_rnea_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64,
                                        _vp])
 bard_fk_vjp = _sig("bard_fk_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
+bard_crba_vjp = _sig("bard_crba_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
 bard_aba_vjp = _sig("bard_aba_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64, _vp])
 bard_plan_create = _sig("bard_plan_create", [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64), ctypes.c_uint32,
                                              ctypes.c_int, ctypes.POINTER(_vp)])
@@ -460,6 +461,17 @@ class Model:
                             _ptr(qdb), _ptr(tb), L, B, _stream_ptr(q)), "bard_aba_vjp")
         return qb, qdb, tb
 
+    def crba_vjp(self, q, M_bar, layout: str = "soa"):
+        """Reverse-mode product of CRBA: q_bar = d<M_bar, M(q)>/dq for the
+        cotangent M_bar (per instance nv*nv, row-major)."""
+        B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(M_bar, self.nv * self.nv, "M_bar")], B, layout)
+        qb = _new(q, self.nq, B, layout)
+        L = _layouts([q, M_bar, qb], layout)
+        _check(bard_crba_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(M_bar), _ptr(qb), L, B, _stream_ptr(q)),
+               "bard_crba_vjp")
+        return qb
+
     def fk_vjp(self, q, poses_bar, layout: str = "soa"):
         """Reverse-mode product of FK: q_bar for the cotangent poses_bar (per
         body 3x4 row-major [R | p])."""
@@ -665,6 +677,21 @@ class _FkFn(torch.autograd.Function):
         return None, ctx.model.fk_vjp(q, poses_bar.contiguous())
 
 
+class _CrbaFn(torch.autograd.Function):
+    """M = CRBA(q) ([nv*nv, B]) with the gradient for q."""
+
+    @staticmethod
+    def forward(ctx, model, q):
+        ctx.model = model
+        ctx.save_for_backward(q)
+        return model.crba(q)
+
+    @staticmethod
+    def backward(ctx, M_bar):
+        (q,) = ctx.saved_tensors
+        return None, ctx.model.crba_vjp(q, M_bar.contiguous())
+
+
 class _AbaFn(torch.autograd.Function):
     """qdd = ABA(q, qd, tau) with gradients for q, qd and tau."""
 
@@ -690,6 +717,11 @@ def aba(model: Model, q, qd, tau):
 def rnea(model: Model, q, qd, qdd, inertia=None):
     """Differentiable inverse dynamics on [K, B] (instance-minor) tensors."""
     return _RneaFn.apply(model, q, qd, qdd, inertia)
+
+
+def crba(model: Model, q):
+    """Differentiable mass matrix on [nq, B] tensors; returns [nv*nv, B]."""
+    return _CrbaFn.apply(model, q)
 
 
 def fk(model: Model, q):

@@ -102,6 +102,7 @@ std::vector<unsigned char> table_image(const bard_model* m, int rs) {
   for (int k = 0; k < 4; ++k)
     std::memcpy(&img[t.ulist + k * 8 * m->n * 4], m->ulist[k].data(), m->ulist[k].size() * sizeof(int));
   if (!m->jump.empty()) std::memcpy(&img[t.jump], m->jump.data(), m->jump.size());
+  for (int i = 0; i < m->n; ++i) img[t.pre + m->dfs[i]] = (unsigned char)i;
   std::memcpy(&img[t.mtab], m->mtab.data(), m->mtab.size() * sizeof(int));
   return img;
 }
@@ -899,6 +900,27 @@ int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* pos
         !layout_of(L, 2, B, m->nq, &a.sqo_b, &a.sqo_k))
       return fail(BARD_E_ARG, "bad layout stride");
     return run_adjoint<R, false>(m, a, nullptr, (hipStream_t)stream);
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_crba_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* M_bar, void* q_bar,
+                  const bard_layout* L, int64_t B, void* stream) {
+  int rc = common_checks(m, nullptr, dtype, B);
+  if (rc) return rc;
+  if (B == 0) return BARD_OK;
+  if (!q || !M_bar || !q_bar) return fail(BARD_E_ARG, "NULL array");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    Args<R> a = blank_args<R>(B);
+    a.q = (const R*)q;
+    a.Mbar = (const R*)M_bar;
+    a.q_bar = (R*)q_bar;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv * m->nv, &a.sMb_b, &a.sMb_k) ||
+        !layout_of(L, 2, B, m->nq, &a.sqb_b, &a.sqb_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    return run_tree<R, OP_CRBA | OP_CVJP>(m, a, 0, nullptr, 0, (hipStream_t)stream);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }

@@ -330,6 +330,11 @@ __device__ __forceinline__ void joint_step(const Real* c, bool rev, Real qv, Rea
   compose_joint(Rpc, tpc, c + C_AX, rev, Rw, pw, s);
 }
 
+// Index of entry (r, c) of a symmetric 6x6 stored as its upper triangle, row-major (21 entries).
+__host__ __device__ __forceinline__ constexpr int sym6(int r, int c) {
+  return r <= c ? (r * 6 - (r * (r - 1)) / 2 + (c - r)) : (c * 6 - (c * (c - 1)) / 2 + (r - c));
+}
+
 // Views of the staged table image.
 template <class Real>
 struct Tables {
@@ -344,6 +349,7 @@ struct Tables {
   const int* dlist;
   const int* ulist;
   const int8_t* jump;
+  const int8_t* pre;
   const int* mtab;
 };
 
@@ -362,6 +368,7 @@ __device__ __forceinline__ Tables<Real> tables(const unsigned char* base, const 
   v.dlist = reinterpret_cast<const int*>(base + t.dlist);
   v.ulist = reinterpret_cast<const int*>(base + t.ulist);
   v.jump = reinterpret_cast<const int8_t*>(base + t.jump);
+  v.pre = reinterpret_cast<const int8_t*>(base + t.pre);
   v.mtab = reinterpret_cast<const int*>(base + t.mtab);
   return v;
 }

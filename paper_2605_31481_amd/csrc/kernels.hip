@@ -37,6 +37,232 @@
 namespace bard {
 
 // --------------------------------------------------------------------------
+// Reverse-mode product of CRBA: q_bar_j = d<M_bar, M(q)>/dq_j.
+//
+// In the base frame M_ad = s_a . Ic_b s_d, with b the deeper of the bodies of
+// dofs a and d, so L = <M_bar, M> depends on q through the motion subspaces s
+// and the world inertias.  A change of q_j moves the subtree of body j rigidly
+// along the screw s_j: riding motion vectors change at the rate s_j x m and
+// riding inertias at the rate s_j x* I - I s_j x.  With Sb = (M_bar + M_bar^T)/2,
+//   y_d  = sum over dofs a of strict ancestors of body(d) of Sb_ad s_a,
+//   z_d  = y_d + 1/2 sum over dofs a of body(d) of Sb_ad s_a,
+//   F_a  = Ic_body(a) y_a + sum over dofs d in the subtree of body(a) of Sb_ad Fc_d
+//          (the gradient of L with respect to s_a is 2 F_a),
+//   Pc_b = sum over dofs d of body b of s_d z_d^T + z_d s_d^T (the gradient of L
+//          with respect to Ic_b, a symmetric 6x6),
+//   Pa_b = sum of Pc over the strict ancestors of body b,
+//   wI(P, I): the 6-vector with s . wI = <P, s x* I - I s x>, equal to
+//          -2 [ax(Q11) + ax(Q22); ax(Q21)] for Q = I P (ax: the axial vector of
+//          the antisymmetric part of a 3x3 block, times 2),
+//   e_b  = wI(Pc_b, Ic_b) + sum over dofs a of body b of 2 s_a x* F_a,
+// and q_bar_j = s_j . (wI(Pa_j, Ic_j) + sum over bodies b in the subtree of j of e_b).
+// A free root's coordinates get zero: with the root velocity in its own body
+// frame, M does not depend on the root's pose.  Every phase is one item per
+// (dof or body, instance) with a fixed summation order (deterministic).
+// --------------------------------------------------------------------------
+template <class Real>
+__device__ __forceinline__ void axial_w(const Real* I0, const Real* P, Real* w) {
+  // I = [Ibar, hx; -hx, m 1] from [m, h, Ibar]; P symmetric, packed by sym6.
+  Real If[6][6], Pf[6][6];
+  const Real hx = I0[1], hy = I0[2], hz = I0[3], m = I0[0];
+  const Real Ib[9] = {I0[4], I0[5], I0[7], I0[5], I0[6], I0[8], I0[7], I0[8], I0[9]};
+  const Real H[9] = {Real(0), -hz, hy, hz, Real(0), -hx, -hy, hx, Real(0)};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      If[r][c] = Ib[3 * r + c];
+      If[r][3 + c] = H[3 * r + c];
+      If[3 + r][c] = -H[3 * r + c];
+      If[3 + r][3 + c] = (r == c) ? m : Real(0);
+    }
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Pf[r][c] = P[sym6(r, c)];
+  auto q = [&](int r, int c) {
+    Real acc = Real(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc += If[r][k] * Pf[k][c];
+    return acc;
+  };
+  // ax(A) = [A21 - A12, A02 - A20, A10 - A01] of the block at (r0, c0)
+  auto ax = [&](int r0, int c0, Real* o) {
+    o[0] = q(r0 + 2, c0 + 1) - q(r0 + 1, c0 + 2);
+    o[1] = q(r0 + 0, c0 + 2) - q(r0 + 2, c0 + 0);
+    o[2] = q(r0 + 1, c0 + 0) - q(r0 + 0, c0 + 1);
+  };
+  Real a11[3], a22[3], a21[3];
+  ax(0, 0, a11);
+  ax(3, 3, a22);
+  ax(3, 0, a21);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k] = Real(-2) * (a11[k] + a22[k]);
+    w[3 + k] = Real(-2) * a21[k];
+  }
+}
+
+template <class Real, int LOGT>
+__device__ __forceinline__ void crba_vjp_phases(const DevModel& dm, const Args<Real>& ar, const Tables<Real>& tb,
+                                                unsigned char* smem, const LdsPlan& L, const Real* s_l,
+                                                const Real* fc_l, int64_t tile0) {
+  constexpr int T = 1 << LOGT;
+  constexpr int SD = 6 * T + block_pad(T, sizeof(Real));
+  constexpr int SCD = cvjp_dof_rows() * T + block_pad(T, sizeof(Real));   // y 0-5, z 6-11, w_a 12-17
+  constexpr int SCB = cvjp_body_rows() * T + block_pad(T, sizeof(Real));  // Ic 0-9, Pc 10-30, e 31-36, t 37-42
+  const int n = dm.n, nv = dm.nv;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int in = tid & (T - 1), r0 = tid >> LOGT, rstep = nt >> LOGT;
+  const int64_t bo = tile0 + in;
+  const bool bok = bo < ar.B;
+  const Real* Mb = ar.Mbar + (bok ? bo : ar.B - 1) * ar.sMb_b;  // past the batch: repeat the last instance
+  Real* cvd = reinterpret_cast<Real*>(smem + L.cvd);
+  Real* cvb = reinterpret_cast<Real*>(smem + L.cvb);
+  auto sbar = [&](int a, int d) {
+    return Real(0.5) * (Mb[(int64_t)(a * nv + d) * ar.sMb_k] + Mb[(int64_t)(d * nv + a) * ar.sMb_k]);
+  };
+  auto load6 = [&](const Real* p, Real* v) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = p[k * T];
+  };
+  auto store6 = [&](Real* p, const Real* v) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k * T] = v[k];
+  };
+
+  // 1. y_d and z_d for every dof (items: bodies, all dofs of a body)
+  for (int bb = r0; bb < n; bb += rstep) {
+    const I4 m2 = tb.bm2[bb];  // {preorder position, subtree size, first dof, dofs}
+    for (int d = m2.z; d < m2.z + m2.w; ++d) {
+      Real y[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
+      for (int pb = tb.meta[bb].x; pb >= 0; pb = tb.meta[pb].x) {
+        const I4 pm = tb.bm2[pb];
+        for (int a = pm.z; a < pm.z + pm.w; ++a) {
+          const Real w = sbar(a, d);
+          Real sa[6];
+          load6(s_l + a * SD + in, sa);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) y[k] += w * sa[k];
+        }
+      }
+      Real z[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) z[k] = y[k];
+      for (int a = m2.z; a < m2.z + m2.w; ++a) {
+        const Real w = Real(0.5) * sbar(a, d);
+        Real sa[6];
+        load6(s_l + a * SD + in, sa);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) z[k] += w * sa[k];
+      }
+      store6(cvd + d * SCD + in, y);
+      store6(cvd + d * SCD + 6 * T + in, z);
+    }
+  }
+  __syncthreads();
+
+  // 2. per body: w_a = 2 s_a x* F_a for its dofs, and Pc_b
+  for (int bb = r0; bb < n; bb += rstep) {
+    const I4 m2 = tb.bm2[bb];
+    const Real* cb = cvb + m2.x * SCB + in;
+    Real Ic[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Ic[k] = cb[k * T];
+    for (int a = m2.z; a < m2.z + m2.w; ++a) {
+      Real y[6], F[6];
+      load6(cvd + a * SCD + in, y);
+      inertia_mul(Ic, y, F);
+      for (int p = m2.x; p < m2.x + m2.y; ++p) {  // the subtree, in preorder
+        const I4 n2 = tb.bm2[tb.pre[p]];
+        for (int d = n2.z; d < n2.z + n2.w; ++d) {
+          const Real w = sbar(a, d);
+          Real fc[6];
+          load6(fc_l + d * SD + in, fc);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) F[k] += w * fc[k];
+        }
+      }
+      Real sa[6], wa[6];
+      load6(s_l + a * SD + in, sa);
+      crf(sa, F, wa);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wa[k] *= Real(2);
+      store6(cvd + a * SCD + 12 * T + in, wa);
+    }
+    Real P[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = Real(0);
+    for (int d = m2.z; d < m2.z + m2.w; ++d) {
+      Real sd[6], z[6];
+      load6(s_l + d * SD + in, sd);
+      load6(cvd + d * SCD + 6 * T + in, z);
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = r; c < 6; ++c) P[sym6(r, c)] += sd[r] * z[c] + z[r] * sd[c];
+    }
+    Real* pc = cvb + m2.x * SCB + 10 * T + in;
+#pragma unroll
+    for (int k = 0; k < 21; ++k) pc[k * T] = P[k];
+  }
+  __syncthreads();
+
+  // 3. per body: e_b = wI(Pc_b, Ic_b) + sum of its w_a; t_b = wI(Pa_b, Ic_b)
+  for (int bb = r0; bb < n; bb += rstep) {
+    const I4 m2 = tb.bm2[bb];
+    Real* cb = cvb + m2.x * SCB + in;
+    Real Ic[10], P[21], e[6], t[6];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) Ic[k] = cb[k * T];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = cb[(10 + k) * T];
+    axial_w(Ic, P, e);
+    for (int a = m2.z; a < m2.z + m2.w; ++a) {
+      Real wa[6];
+      load6(cvd + a * SCD + 12 * T + in, wa);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] += wa[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 21; ++k) P[k] = Real(0);
+    for (int pb = tb.meta[bb].x; pb >= 0; pb = tb.meta[pb].x) {
+      const Real* pp = cvb + tb.bm2[pb].x * SCB + 10 * T + in;
+#pragma unroll
+      for (int k = 0; k < 21; ++k) P[k] += pp[k * T];
+    }
+    axial_w(Ic, P, t);
+    store6(cb + 31 * T, e);
+    store6(cb + 37 * T, t);
+  }
+  __syncthreads();
+
+  // 4. q_bar_j = s_j . (t_j + sum of e over the subtree of j); zero for a free root
+  if (!bok) return;
+  Real* qo = ar.q_bar + bo * ar.sqb_b;
+  for (int bb = r0; bb < n; bb += rstep) {
+    const I4 meta = tb.meta[bb];
+    const I4 m2 = tb.bm2[bb];
+    if (meta.y == J_FREE) {
+      for (int k = 0; k < 7; ++k) qo[(int64_t)(meta.z + k) * ar.sqb_k] = Real(0);
+      continue;
+    }
+    Real W[6];
+    load6(cvb + m2.x * SCB + 37 * T + in, W);
+    for (int p = m2.x; p < m2.x + m2.y; ++p) {
+      Real e[6];
+      load6(cvb + p * SCB + 31 * T + in, e);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) W[k] += e[k];
+    }
+    Real sj[6];
+    load6(s_l + m2.z * SD + in, sj);
+    qo[(int64_t)meta.z * ar.sqb_k] =
+        sj[0] * W[0] + sj[1] * W[1] + sj[2] * W[2] + sj[3] * W[3] + sj[4] * W[4] + sj[5] * W[5];
+  }
+}
+
+// --------------------------------------------------------------------------
 // FK / Jacobian / RNEA / CRBA and their fusion (OPS bit mask).
 //   1. staging (all waves);
 //   2. level sweep (waves [0, WA), T instances x 2^log2P lanes): pose, s_i,
@@ -58,6 +284,8 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   constexpr bool RNEA = OPS & OP_RNEA;
   constexpr bool CRBA = OPS & OP_CRBA;
   constexpr bool BIAS = RNEA && (OPS & OP_BIAS);  // also RNEA(q, qd, 0); not on the scan path
+  constexpr bool CVJP = CRBA && (OPS & OP_CVJP);   // CRBA's reverse-mode product instead of M
+  constexpr bool MOUT = CRBA && !CVJP;             // the dense mass-matrix output
   constexpr bool VEL = RNEA;
   constexpr bool BACK = RNEA || CRBA;
   constexpr bool NEED_S = JAC || RNEA || CRBA;
@@ -163,7 +391,7 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     {
       const int64_t bz = tile0 + inx;
       if (bz < ar.B) {
-        if (CRBA) {
+        if (MOUT) {
           Real* out = ar.M + bz * ar.sM_b;
           const int* mz = tb.mtab + dm.n_mpair;
           for (int k = rb; k < dm.n_mzero; k += rbs) put(&out[(int64_t)mz[k] * ar.sM_k], Real(0), ar.stream_out);
@@ -659,14 +887,14 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         }
       }
     }
-  } else if (wave >= WA && (CRBA || JAC)) {
+  } else if (wave >= WA && (MOUT || JAC)) {
     // The structural zeros of M and J depend on nothing the sweep computes:
     // the waves the sweep leaves idle store them meanwhile.
     const int tz = tid - WA * 64, nz = nt - WA * 64;
     const int64_t b = tile0 + (tid & (T - 1));
     if (b < ar.B) {
       const int r0z = tz >> LOGT, rsz = nz >> LOGT;
-      if (CRBA) {
+      if (MOUT) {
         Real* out = ar.M + b * ar.sM_b;
         const int* mz = tb.mtab + dm.n_mpair;
         for (int k = r0z; k < dm.n_mzero; k += rsz) put(&out[(int64_t)mz[k] * ar.sM_k], Real(0), ar.stream_out);
@@ -858,6 +1086,12 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
           }
         }
         if (!valid) continue;
+        if (CVJP && part == 0) {
+          // the composite inertia Ic_i, by preorder position, for the CRBA adjoint
+          Real* icr = reinterpret_cast<Real*>(smem + L.cvb) + m2.x * (cvjp_body_rows() * T + block_pad(T, sizeof(Real))) + in;
+#pragma unroll
+          for (int k = 0; k < 10; ++k) icr[k * T] = Ic[k];
+        }
         for (int d = part; d < m2.w; d += np) {
           const Real* sr = s_l + (m2.z + d) * SD + in;
           Real s[6];
@@ -882,6 +1116,11 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
       }
     }
     if (CRBA) __syncthreads();
+  }
+
+  if constexpr (CVJP) {
+    crba_vjp_phases<Real, LOGT>(dm, ar, tb, smem, L, s_l, fc_l, tile0);
+    return;
   }
 
   // ---------------- 5. dense outputs, lanes over instances ----------------
@@ -972,11 +1211,6 @@ __global__ void __launch_bounds__(tree_max_threads(sizeof(Real))) plan_kernel(Pl
 //   3 (root to leaves): a = a_p + c, qdd = (u - U.a) / D, a += s qdd.
 // The free root solves its 6x6 articulated system by Cholesky.
 // --------------------------------------------------------------------------
-
-// Symmetric 6x6 stored as the upper triangle, row-major (21 entries).
-__device__ __forceinline__ constexpr int sym6(int r, int c) {
-  return r <= c ? (r * 6 - (r * (r - 1)) / 2 + (c - r)) : (c * 6 - (c * (c - 1)) / 2 + (r - c));
-}
 
 template <class Real>
 __device__ __forceinline__ void rigid_to_sym(const Real* I0, Real* S) {
@@ -1438,6 +1672,8 @@ hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int bl
                                                         size_t, hipStream_t);                                     \
   template hipError_t launch_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(const DevModel&, const DevEE&, const Args<R>&,   \
                                                                  int, int, size_t, hipStream_t);                  \
+  template hipError_t launch_tree<R, OP_CRBA | OP_CVJP>(const DevModel&, const DevEE&, const Args<R>&, int, int,   \
+                                                        size_t, hipStream_t);                                     \
   template hipError_t launch_aba<R>(const DevModel&, const Args<R>&, int, int, size_t, hipStream_t);          \
   template hipError_t launch_plan<R, OP_RNEA>(const PlanPtrs<R>&, int, int, int, size_t, hipStream_t);           \
   template hipError_t launch_plan<R, OP_CRBA>(const PlanPtrs<R>&, int, int, int, size_t, hipStream_t);           \

@@ -7,7 +7,9 @@
 
 namespace bard {
 
-enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8, OP_BIAS = 16 };
+// OP_CVJP (with OP_CRBA): the reverse-mode product of CRBA, q_bar = d<M_bar, M(q)>/dq,
+// instead of the mass-matrix output.
+enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8, OP_BIAS = 16, OP_CVJP = 32 };
 
 // Rows of a per-body LDS block: R, p, v, a (24); an RNEA launch that also
 // returns the bias forces RNEA(q, qd, 0) carries the acceleration without the
@@ -42,6 +44,10 @@ struct Args {
   Real* kin;
   int64_t kin_ld;
   int kin_mode;
+  // OP_CVJP: the cotangent M_bar [nv*nv] in, q_bar [nq] out
+  const Real* Mbar;
+  Real* q_bar;
+  int64_t sMb_b, sMb_k, sqb_b, sqb_k;
 };
 
 // Rows of the kinematics tier per instance: 12 per body by preorder position
@@ -96,7 +102,7 @@ constexpr int kAdjMaxThreads = 512;
 // single copy of 16-byte chunks.  mtab comes last so kernels that do not need
 // it copy only the prefix.
 struct TabLayout {
-  int cst, meta, sbody, ssrc, cslot, linfo, srec, bm2, dlist, ulist, jump, mtab, end_nomtab, end;
+  int cst, meta, sbody, ssrc, cslot, linfo, srec, bm2, dlist, ulist, jump, pre, mtab, end_nomtab, end;
 };
 
 __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kmax, int nv, int rs) {
@@ -118,6 +124,7 @@ __host__ __device__ inline TabLayout tab_layout(int n, int P, int depth, int kma
   t.dlist = take(n * 4);   // bodies by decreasing subtree size
   t.ulist = take(4 * 8 * n * 4);  // subtree-phase work lists for 1, 2, 4, 8 row groups per wave
   t.jump = take(6 * n);           // pointer-jumping ancestors for up to 6 steps (depth <= 64)
+  t.pre = take(n);                // body at each preorder position
   t.end_nomtab = off;
   t.mtab = take(nv * nv * 4);
   t.end = off;
@@ -147,12 +154,19 @@ __host__ __device__ constexpr int block_pad(int T, int rs) { return (rs == 4 && 
 struct LdsPlan {
   int q, qd, qdd, tin;        // input tiles [K][T]
   int s, fc, body, o, pe;     // tree-kernel state
+  int cvd, cvb;               // OP_CVJP state: per dof (cvjp_dof_rows), per body by preorder position
   int c, ia, pa, u;           // ABA state
   int tab;                    // table image
   int tab_bytes;              // bytes of the image this kernel stages
   int ee;                     // end-effector image
   int total;
 };
+
+// Rows of the CRBA adjoint's blocks: per dof y (6), z (6), w_a (6); per body,
+// by preorder position, the composite inertia Ic (10), the packed symmetric
+// Pc (21), e (6) and t (6).
+__host__ __device__ constexpr int cvjp_dof_rows() { return 18; }
+__host__ __device__ constexpr int cvjp_body_rows() { return 43; }
 
 // kind: 0 = tree kernel with op mask `ops`, 1 = ABA kernel.
 __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, int nv, int n_ee, int frame, int T,
@@ -180,6 +194,8 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
     L.fc = (ops & (OP_CRBA | OP_RNEA)) ? take((nv + 1) * (6 * T + pad) * rs) : off;
     L.o = take(3 * T * rs);
     L.pe = ((ops & OP_JAC) && frame == 1) ? take(n_ee * 3 * T * rs) : off;
+    L.cvd = (ops & OP_CVJP) ? take(nv * (cvjp_dof_rows() * T + pad) * rs) : off;
+    L.cvb = (ops & OP_CVJP) ? take(n * (cvjp_body_rows() * T + pad) * rs) : off;
   } else {
     L.s = take(nv * 6 * T * rs);
     L.c = take(n * 6 * T * rs);
@@ -188,7 +204,7 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
     L.u = take(n * 8 * T * rs);
   }
   const TabLayout tl = tab_layout(n, P, depth, kmax, nv, rs);
-  L.tab_bytes = (kind == 0 && (ops & OP_CRBA)) ? tl.end : tl.end_nomtab;
+  L.tab_bytes = (kind == 0 && (ops & OP_CRBA) && !(ops & OP_CVJP)) ? tl.end : tl.end_nomtab;
   L.tab = take(L.tab_bytes);
   L.ee = (kind == 0 && (ops & OP_JAC)) ? take(ee_image_bytes(n_ee, nv)) : off;
   L.total = off;
