@@ -175,6 +175,11 @@ int bard_ws_destroy(bard_ws_t ws);
  * batch; the policy is the knob that chooses.
  * Errors: BARD_E_ARG (NULL workspace, unknown bits). */
 int bard_ws_set_policy(bard_ws_t ws, int32_t policy);
+/* Counters of the tier decisions taken so far, per tier in the order
+ * kinematics, mass, bias (arrays of 3; either may be NULL): a hit reused the
+ * tier, a miss computed (and stored) its contents.  A call counts once per
+ * tier it consults.  Errors: BARD_E_ARG. */
+int bard_ws_stats(bard_ws_t ws, uint64_t* hits, uint64_t* misses);
 
 /* ------------------------------------------------------------ operators ----
  * q_tag / qd_tag: caller version tags of q and qd for the workspace; 0 =
@@ -322,7 +327,8 @@ int bard_aba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void
  * after bard_plan_configure or bard_plan_autotune) synchronizes the device.
  * bard_plan_autotune: times every valid configuration (tile 8, 16 or 32 instances;
  * fusion 0 = one launch for all models, 1 = one launch per model, 2 = one
- * launch per operator; item order 0 = longest first, 1 = model order) on
+ * launch per operator; item order 0 = longest first, 1 = model order; lanes
+ * per instance at the model's minimum or twice that) on
  * zero-filled scratch arrays for about budget_ms, keeps the fastest and
  * records it in a JSON cache (file $BARD_TUNE_CACHE, else
  * $HOME/.cache/bard_plan_tune.json) keyed by the GPU, dtype, op_mask, tree
@@ -338,11 +344,14 @@ int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms);
 int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream);
 int bard_plan_destroy(bard_plan_t plan);
 /* Pin a configuration (what bard_plan_autotune chooses): tile 8, 16 or 32,
- * fusion 0..2, order 0..1 as above.  Fusion 0 and 1 need op_mask to be one
- * operator or all three. */
-int bard_plan_configure(bard_plan_t plan, int32_t tile, int32_t fusion, int32_t order);
+ * fusion 0..2, order 0..1 as above, lanes 0 or 1 (twice the lanes per
+ * instance of the level sweep when 1: each instance's bodies spread over
+ * more lanes, so a tile occupies more waves).  Fusion 0 and 1 need op_mask to
+ * be one operator or all three.  A configuration whose sweep needs more than
+ * 8 waves is refused by the first run with BARD_E_CAPACITY. */
+int bard_plan_configure(bard_plan_t plan, int32_t tile, int32_t fusion, int32_t order, int32_t lanes);
 /* Current configuration; from_cache = 1 if it came from the tuning cache. */
-int bard_plan_get_config(bard_plan_t plan, int32_t* tile, int32_t* fusion, int32_t* order,
+int bard_plan_get_config(bard_plan_t plan, int32_t* tile, int32_t* fusion, int32_t* order, int32_t* lanes,
                          int32_t* from_cache);
 /* Tip end effectors of model `model_index` (ee_body: room for 4 entries). */
 int bard_plan_ee(bard_plan_t plan, int32_t model_index, int32_t* n_ee, int32_t* ee_body);

@@ -43,8 +43,9 @@ REVOLUTE, PRISMATIC, FREE, FIXED = 0, 1, 2, 3
 WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
 UPLOAD_ADJOINT = 1
-# workspace tiers (bard_ws_set_policy bits)
-TIER_KINEMATICS, TIER_MASS, TIER_BIAS = 1, 2, 4
+# workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own
+# (see Workspace)
+TIER_KINEMATICS, TIER_MASS, TIER_BIAS, TIER_RESULTS = 1, 2, 4, 8
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -81,6 +82,7 @@ bard_model_upload = _sig("bard_model_upload", [_vp, _i32, _c_i32p, _i32])
 bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
 bard_ws_destroy = _sig("bard_ws_destroy", [_vp])
 bard_ws_set_policy = _sig("bard_ws_set_policy", [_vp, _i32])
+bard_ws_stats = _sig("bard_ws_stats", [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
 bard_fk = _sig("bard_fk", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
 bard_jacobian = _sig("bard_jacobian", [_vp, _vp, ctypes.c_int, _vp, _i32, _c_i32p, ctypes.c_int, _vp, _LP, _u64,
                                        _i64, _vp])
@@ -99,8 +101,8 @@ bard_plan_create = _sig("bard_plan_create", [ctypes.POINTER(_vp), _i32, ctypes.P
 bard_plan_autotune = _sig("bard_plan_autotune", [_vp, _vp, _i32])
 bard_plan_run = _sig("bard_plan_run", [_vp, ctypes.POINTER(_vp), _vp])
 bard_plan_destroy = _sig("bard_plan_destroy", [_vp])
-bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32])
-bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
+bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32, _i32])
+bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
 bard_plan_ee = _sig("bard_plan_ee", [_vp, _i32, _c_i32p, _c_i32p])
 
 PLAN_RNEA, PLAN_CRBA, PLAN_JACOBIAN = 1, 2, 4
@@ -254,7 +256,15 @@ def version_tag(t) -> int:
 class Workspace:
     """Cached state of one stream (bard_ws_*): operators called with ``ws=``
     reuse what was computed for unchanged inputs, per the tiers in ``policy``
-    (an OR of TIER_KINEMATICS, TIER_MASS, TIER_BIAS)."""
+    (an OR of TIER_KINEMATICS, TIER_MASS, TIER_BIAS, TIER_RESULTS).
+
+    TIER_RESULTS is kept by the binding: an operator call with no ``out``
+    whose inputs carry the same version tags as the previous call of that
+    operator on this workspace (and whose other arguments are equal) returns
+    the previous output tensor without any launch, provided that tensor has
+    not been modified in place since (PyTorch's version counter).  This is the
+    full hit of the lazy evaluation; the library itself cannot see whether a
+    caller's output buffer still holds its result."""
 
     def __init__(self, model: "Model", max_batch: int, dtype=None, policy: int = TIER_KINEMATICS):
         torch = _torch()
@@ -264,10 +274,37 @@ class Workspace:
         _check(bard_ws_create(model.handle, code, int(max_batch), ctypes.byref(h)), "bard_ws_create")
         self._h = h
         self.model = model
+        self._results = {}
+        self.skipped = 0
         self.set_policy(policy)
 
     def set_policy(self, policy: int):
-        _check(bard_ws_set_policy(self._h, int(policy)), "bard_ws_set_policy")
+        self.reuse_results = bool(policy & TIER_RESULTS)
+        self._results.clear()
+        _check(bard_ws_set_policy(self._h, int(policy) & ~TIER_RESULTS), "bard_ws_set_policy")
+
+    def stats(self) -> dict:
+        """Tier decisions so far: hits and misses per library tier, and the
+        binding's full hits (calls answered without a launch)."""
+        h, m = (_u64 * 3)(), (_u64 * 3)()
+        _check(bard_ws_stats(self._h, h, m), "bard_ws_stats")
+        names = ("kinematics", "mass", "bias")
+        out = {nm: {"hits": int(h[k]), "misses": int(m[k])} for k, nm in enumerate(names)}
+        out["results"] = {"hits": self.skipped}
+        return out
+
+    def _lookup(self, op: str, key):
+        if not self.reuse_results:
+            return None
+        ent = self._results.get(op)
+        if ent is not None and ent[0] == key and all(t._version == v for t, v in zip(ent[1], ent[2])):
+            self.skipped += 1
+            return ent[1]
+        return None
+
+    def _remember(self, op: str, key, outs):
+        if self.reuse_results:
+            self._results[op] = (key, outs, tuple(t._version for t in outs))
 
     @property
     def handle(self):
@@ -283,6 +320,30 @@ class Workspace:
             self.close()
         except Exception:
             pass
+
+
+class _T:
+    """A tensor argument of a result key: keyed by its explicit tag if the
+    caller gave one, else by its version tag and address."""
+
+    def __init__(self, t, tag=None):
+        self.t, self.tag = t, tag
+
+    def key(self):
+        if self.t is None:
+            return None
+        if self.tag is not None:
+            return ("tag", int(self.tag))
+        return ("v", version_tag(self.t), self.t.data_ptr())
+
+
+def _result_key(ws, out, q, q_tag, B, layout, *rest):
+    """Key of a call for the binding's result tier, or None when the tier is
+    not in use (no workspace, TIER_RESULTS off, or a caller-given output).
+    ``rest`` holds _T tensor arguments and plain values."""
+    if ws is None or not ws.reuse_results or out is not None:
+        return None
+    return (_T(q, q_tag).key(), B, layout, q.dtype) + tuple(r.key() if isinstance(r, _T) else r for r in rest)
 
 
 def _ws_args(ws, q, q_tag):
@@ -362,28 +423,41 @@ class Model:
     # ---------------------------------------------------------------- ops --
     def fk(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
+        key = _result_key(ws, out, q, q_tag, B, layout)
+        if key is not None and (hit := ws._lookup("fk", key)) is not None:
+            return hit[0]
         out = out if out is not None else _new(q, 12 * self.n_bodies, B, layout)
         _check_arrays(q, [(out, 12 * self.n_bodies, "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_fk(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_fk")
+        if key is not None:
+            ws._remember("fk", key, (out,))
         return out
 
     def jacobian(self, q, ee: Sequence[int], frame: int = WORLD, out=None, layout: str = "soa",
                  ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
+        key = _result_key(ws, out, q, q_tag, B, layout, tuple(int(e) for e in ee_a), int(frame))
+        if key is not None and (hit := ws._lookup("jacobian", key)) is not None:
+            return hit[0]
         out = out if out is not None else _new(q, 6 * self.nv * len(ee_a), B, layout)
         _check_arrays(q, [(out, 6 * self.nv * len(ee_a), "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_jacobian(self._h, wh, _dtype_code(q), _ptr(q), len(ee_a), pee, int(frame), _ptr(out), L, tag, B,
                              _stream_ptr(q)), "bard_jacobian")
+        if key is not None:
+            ws._remember("jacobian", key, (out,))
         return out
 
     def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa", ws: Optional[Workspace] = None,
              q_tag=None, qd_tag=None):
         B = _batch_of(q, self.nq, layout)
+        key = _result_key(ws, out, q, q_tag, B, layout, _T(qd, qd_tag), _T(qdd), _T(inertia))
+        if key is not None and (hit := ws._lookup("rnea", key)) is not None:
+            return hit[0]
         out = out if out is not None else _new(q, self.nv, B, layout)
         _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (out, self.nv, "out")], B, layout)
         _check_inertia(q, inertia, self.n_bodies)
@@ -392,15 +466,22 @@ class Model:
         _, dtag = _ws_args(ws, qd, qd_tag)
         _check(bard_rnea(self._h, wh, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(out), L,
                          tag, dtag, B, _stream_ptr(q)), "bard_rnea")
+        if key is not None:
+            ws._remember("rnea", key, (out,))
         return out
 
     def crba(self, q, out=None, layout: str = "soa", ws: Optional[Workspace] = None, q_tag=None):
         B = _batch_of(q, self.nq, layout)
+        key = _result_key(ws, out, q, q_tag, B, layout)
+        if key is not None and (hit := ws._lookup("crba", key)) is not None:
+            return hit[0]
         out = out if out is not None else _new(q, self.nv * self.nv, B, layout)
         _check_arrays(q, [(out, self.nv * self.nv, "out")], B, layout)
         L = _layouts([q, out], layout)
         wh, tag = _ws_args(ws, q, q_tag)
         _check(bard_crba(self._h, wh, _dtype_code(q), _ptr(q), _ptr(out), L, tag, B, _stream_ptr(q)), "bard_crba")
+        if key is not None:
+            ws._remember("crba", key, (out,))
         return out
 
     def aba(self, q, qd, tau, out=None, layout: str = "soa"):
@@ -591,15 +672,15 @@ class Plan:
         _check(bard_plan_ee(self._h, int(i), ctypes.byref(n), buf), "bard_plan_ee")
         return list(buf[:n.value])
 
-    def configure(self, tile: int, fusion: int, order: int = 0):
-        _check(bard_plan_configure(self._h, int(tile), int(fusion), int(order)), "bard_plan_configure")
+    def configure(self, tile: int, fusion: int, order: int = 0, lanes: int = 0):
+        _check(bard_plan_configure(self._h, int(tile), int(fusion), int(order), int(lanes)), "bard_plan_configure")
 
     @property
     def config(self) -> dict:
-        t, f, o, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(bard_plan_get_config(self._h, ctypes.byref(t), ctypes.byref(f), ctypes.byref(o), ctypes.byref(c)),
-               "bard_plan_get_config")
-        return {"tile": t.value, "fusion": f.value, "order": o.value, "from_cache": bool(c.value)}
+        t, f, o, ln, c = (ctypes.c_int32() for _ in range(5))
+        _check(bard_plan_get_config(self._h, ctypes.byref(t), ctypes.byref(f), ctypes.byref(o), ctypes.byref(ln),
+                                    ctypes.byref(c)), "bard_plan_get_config")
+        return {"tile": t.value, "fusion": f.value, "order": o.value, "lanes": ln.value, "from_cache": bool(c.value)}
 
     def autotune(self, budget_ms: int = 2000):
         torch = _torch()

@@ -14,7 +14,11 @@ _BUILD = os.path.join(os.path.dirname(_HERE), "_build", "bard")
 SOURCES = ["kernels.hip", "adjoint.hip", "tiers.hip", "api.cpp", "compiler.cpp", "plan.cpp"]
 
 # Packed FP32 instructions are turned off for every HIP translation unit.
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
+# Multiply-adds are fused only within one expression (-ffp-contract=on), so a
+# quantity rounds the same way in every kernel instantiation that computes it:
+# state one operator stores in a workspace tier has the bits another
+# operator would have computed itself.
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 

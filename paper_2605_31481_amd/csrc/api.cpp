@@ -46,6 +46,7 @@ struct bard_ws {
   uint64_t pose_tag = 0, s_tag = 0, o_tag = 0;
   int64_t m_B = -1, b_B = -1;
   uint64_t m_tag = 0, bq_tag = 0, bqd_tag = 0, b_gen = 0;
+  uint64_t hits[3] = {0, 0, 0}, misses[3] = {0, 0, 0};  // per tier: kinematics, mass, bias
 };
 
 using namespace bard;
@@ -349,6 +350,7 @@ int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, 
   ar->kin = (Real*)ws->kin;
   ar->kin_ld = ws->max_batch;
   tu->mode = hit ? 2 : 1;
+  ++(hit ? ws->hits : ws->misses)[0];
   tu->pose = need_body;
   tu->s = need_s;
   ar->kin_mode = tu->mode;
@@ -653,6 +655,15 @@ int bard_ws_destroy(bard_ws_t w) {
   return BARD_OK;
 }
 
+int bard_ws_stats(bard_ws_t w, uint64_t* hits, uint64_t* misses) {
+  if (!w) return fail(BARD_E_ARG, "NULL workspace");
+  for (int k = 0; k < 3; ++k) {
+    if (hits) hits[k] = w->hits[k];
+    if (misses) misses[k] = w->misses[k];
+  }
+  return BARD_OK;
+}
+
 int bard_ws_set_policy(bard_ws_t w, int32_t policy) {
   if (!w) return fail(BARD_E_ARG, "NULL workspace");
   if (policy & ~(BARD_TIER_KINEMATICS | BARD_TIER_MASS | BARD_TIER_BIAS))
@@ -733,6 +744,7 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
     const int64_t ld = ws->max_batch;
     const bool b_hit = ws->b_B == B && ws->bq_tag == q_tag && ws->bqd_tag == qd_tag && ws->b_gen == m->g_gen;
     const bool m_hit = ws->mt && ws->m_B == B && ws->m_tag == q_tag;
+    ++((b_hit && m_hit) ? ws->hits : ws->misses)[2];
     if (b_hit && m_hit) {
       // tau = M qdd + b from the two tiers: no traversal
       if (launch_tier_matvec<R>((const R*)ws->mt, (const R*)ws->bt, ld, a.qdd, a.sqdd_b, a.sqdd_k, a.tau, a.st_b,
@@ -778,7 +790,9 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
     if (rc2) return rc2;
     R* mt = (R*)ws->mt;
     const int64_t ld = ws->max_batch;
-    if (ws->m_B == B && ws->m_tag == q_tag) {
+    const bool mhit = ws->m_B == B && ws->m_tag == q_tag;
+    ++(mhit ? ws->hits : ws->misses)[1];
+    if (mhit) {
       // mass-matrix tier hit: no traversal, one copy into the caller's layout
       if (launch_tier_copy<R>(mt, 1, ld, a.M, a.sM_b, a.sM_k, nn, B, st) != hipSuccess)
         return fail(BARD_E_DEVICE, "tier copy launch failed");

@@ -36,6 +36,7 @@ struct PlanConfig {
   int logT = 4;
   int fusion = FUSE_ALL;
   int order = ORDER_LONGEST_FIRST;
+  int lanes = 0;  // extra lanes per instance in the level sweep, log2 (0 or 1)
 };
 
 struct Group {
@@ -143,7 +144,7 @@ std::string plan_key(const bard_plan* p) {
 }
 
 // The cache is a JSON object with one entry per line:
-//   "<key>": {"tile": 16, "fusion": 0, "order": 0, "us": 123.4}
+//   "<key>": {"tile": 16, "fusion": 0, "order": 0, "lanes": 0, "us": 123.4}
 std::map<std::string, std::pair<PlanConfig, double>> read_cache(const std::string& path) {
   std::map<std::string, std::pair<PlanConfig, double>> out;
   FILE* f = path.empty() ? nullptr : fopen(path.c_str(), "r");
@@ -151,16 +152,17 @@ std::map<std::string, std::pair<PlanConfig, double>> read_cache(const std::strin
   char line[512];
   while (fgets(line, sizeof(line), f)) {
     char key[65];
-    int tile = 0, fusion = 0, order = 0;
+    int tile = 0, fusion = 0, order = 0, lanes = 0;
     double us = 0;
-    if (sscanf(line, " \"%64[^\"]\": {\"tile\": %d, \"fusion\": %d, \"order\": %d, \"us\": %lf}", key, &tile, &fusion,
-               &order, &us) == 5) {
+    if (sscanf(line, " \"%64[^\"]\": {\"tile\": %d, \"fusion\": %d, \"order\": %d, \"lanes\": %d, \"us\": %lf}", key,
+               &tile, &fusion, &order, &lanes, &us) == 6) {
       PlanConfig c;
       int lt = 0;
       while ((1 << lt) < tile) ++lt;
       c.logT = lt;
       c.fusion = fusion;
       c.order = order;
+      c.lanes = lanes;
       out[key] = {c, us};
     }
   }
@@ -176,9 +178,9 @@ void write_cache(const std::string& path, const std::map<std::string, std::pair<
   fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : entries) {
-    fprintf(f, "\"%s\": {\"tile\": %d, \"fusion\": %d, \"order\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
-            1 << kv.second.first.logT, kv.second.first.fusion, kv.second.first.order, kv.second.second,
-            ++k < entries.size() ? "," : "");
+    fprintf(f, "\"%s\": {\"tile\": %d, \"fusion\": %d, \"order\": %d, \"lanes\": %d, \"us\": %.3f}%s\n",
+            kv.first.c_str(), 1 << kv.second.first.logT, kv.second.first.fusion, kv.second.first.order,
+            kv.second.first.lanes, kv.second.second, ++k < entries.size() ? "," : "");
   }
   fprintf(f, "}\n");
   fclose(f);
@@ -189,6 +191,7 @@ bool valid_config(const bard_plan* p, const PlanConfig& c) {
   if (c.logT < 3 || c.logT > 5) return false;
   if (c.fusion < FUSE_ALL || c.fusion > FUSE_PER_OP) return false;
   if (c.order != ORDER_LONGEST_FIRST && c.order != ORDER_MODEL) return false;
+  if (c.lanes < 0 || c.lanes > 1) return false;
   if (c.fusion != FUSE_PER_OP && !fusable(mask_to_ops(p->op_mask))) return false;
   return true;
 }
@@ -226,7 +229,7 @@ int prepare_t(bard_plan* p) {
       rc = ensure_ee(m, dc, (int)p->ee[i].size(), p->ee[i].data(), &ees[i], nullptr);
       if (rc) return rc;
     }
-    int lp = std::max(m->log2P, 6 - p->cfg.logT);
+    int lp = std::max(m->log2P, 6 - p->cfg.logT) + p->cfg.lanes;
     if (((T << lp) >> 6) > 8 || lp > 6) return fail(BARD_E_CAPACITY, "tree too wide for this tile size");
     p->log2P[i] = lp;
     // serial sweep plus output rows per instance of the tile
@@ -500,7 +503,7 @@ int bard_plan_create(const bard_model_t* models, int32_t n_models, const int64_t
   return BARD_OK;
 }
 
-int bard_plan_configure(bard_plan_t p, int32_t tile, int32_t fusion, int32_t order) {
+int bard_plan_configure(bard_plan_t p, int32_t tile, int32_t fusion, int32_t order, int32_t lanes) {
   if (!p) return fail(BARD_E_ARG, "plan is NULL");
   PlanConfig c;
   c.logT = 0;
@@ -508,14 +511,17 @@ int bard_plan_configure(bard_plan_t p, int32_t tile, int32_t fusion, int32_t ord
   if ((1 << c.logT) != tile) return fail(BARD_E_ARG, "tile must be 8, 16 or 32");
   c.fusion = fusion;
   c.order = order;
+  c.lanes = lanes;
   if (!valid_config(p, c)) return fail(BARD_E_ARG, "invalid plan configuration");
   p->cfg = c;
   p->ready = false;
   return BARD_OK;
 }
 
-int bard_plan_get_config(bard_plan_t p, int32_t* tile, int32_t* fusion, int32_t* order, int32_t* from_cache) {
+int bard_plan_get_config(bard_plan_t p, int32_t* tile, int32_t* fusion, int32_t* order, int32_t* lanes,
+                         int32_t* from_cache) {
   if (!p) return fail(BARD_E_ARG, "plan is NULL");
+  if (lanes) *lanes = p->cfg.lanes;
   if (tile) *tile = 1 << p->cfg.logT;
   if (fusion) *fusion = p->cfg.fusion;
   if (order) *order = p->cfg.order;
@@ -580,13 +586,14 @@ int bard_plan_autotune(bard_plan_t p, void* stream, int32_t budget_ms) {
   PlanConfig best = start;
   double best_us = 1e300;
   const auto t_start = std::chrono::steady_clock::now();
+  for (int ln = 0; ln <= 1; ++ln)
   for (int lt = 3; lt <= 5; ++lt)
     for (int fu = FUSE_ALL; fu <= FUSE_PER_OP; ++fu)
       for (int od = ORDER_LONGEST_FIRST; od <= ORDER_MODEL; ++od) {
         const double spent =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         if (spent > budget_ms && best_us < 1e300) continue;
-        PlanConfig c{lt, fu, od};
+        PlanConfig c{lt, fu, od, ln};
         if (!valid_config(p, c) || (fu == FUSE_PER_MODEL && od == ORDER_MODEL)) continue;
         p->cfg = c;
         p->ready = false;

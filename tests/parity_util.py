@@ -108,6 +108,20 @@ def body_terms(om, tree, q, qd=None, qdd=None, tau=True, mass=True):
     return st, sm
 
 
+def adjoint_body_terms(om, tree, q, qd, qdd, tau_bar):
+    """Per-entry sums of the absolute per-body terms of the RNEA adjoint's
+    q_bar, qd_bar and qdd_bar: for a fixed cotangent they are linear in the
+    inertial parameters, as tau is."""
+    B = q.shape[0]
+    out = [np.zeros((B, tree.nq)), np.zeros((B, tree.nv)), np.zeros((B, tree.nv))]
+    for k in range(tree.n_bodies):
+        pi = np.zeros_like(tree.inertia)
+        pi[k] = tree.inertia[k]
+        for acc, g in zip(out, om.rnea_vjp(q, qd, qdd, tau_bar, inertia=pi)[:3]):
+            acc += np.abs(g)
+    return out
+
+
 def entrywise(gpu, ref, scale, rtol, atol):
     """Per-entry check ``|gpu - ref| <= atol + rtol * max(|ref|, scale)``.
     Returns (ok mask, worst err/bound)."""

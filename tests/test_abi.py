@@ -190,13 +190,16 @@ def test_plan_host_side():
     p = bard.Plan(ms, synth.MULTI_BATCHES)
     for i, t in enumerate(trees):
         assert p.ee(i) == list(t.ee_bodies)
-    assert p.config == {"tile": 16, "fusion": 0, "order": 0, "from_cache": False}
-    p.configure(32, 2, 1)
+    assert p.config == {"tile": 16, "fusion": 0, "order": 0, "lanes": 0, "from_cache": False}
+    p.configure(32, 2, 1, 1)
+    assert p.config["lanes"] == 1
     assert p.config["tile"] == 32 and p.config["fusion"] == 2
     with pytest.raises(bard.BardError):
         p.configure(12, 0, 0)
     with pytest.raises(bard.BardError):
         p.configure(16, 3, 0)
+    with pytest.raises(bard.BardError):
+        p.configure(16, 0, 0, 2)
     # two operators have no fused kernel: only one launch per operator is valid
     p2 = bard.Plan(ms, synth.MULTI_BATCHES, op_mask=bard.PLAN_RNEA | bard.PLAN_CRBA)
     assert p2.config["fusion"] == 2

@@ -2,8 +2,10 @@
 oracle's tape reverse-mode AD.
 
 Calls go through the C ABI.  Inputs and cotangents are seeded and rounded to
-the kernel's precision; the oracle runs in FP64 on those values.  Per-instance
-gradients use the normwise contract of parity_util.  The inertial-parameter
+the kernel's precision; the oracle runs in FP64 on those values.  The RNEA adjoint's
+per-instance gradients are linear in the inertial parameters, as tau is, and
+are held entry by entry against the sum of their absolute per-body terms;
+the FK adjoint's are held normwise per instance (parity_util).  The inertial-parameter
 gradient is a batch sum, so its bound is the per-instance bound summed over
 the batch (triangle inequality): for every body,
 ``max_k |gpu_k - sum_b ref_bk| <= sum_b (atol + rtol * max_k |ref_bk|)``.
@@ -14,7 +16,8 @@ import pytest
 
 import synth
 from paper_2605_31481_amd import bard
-from parity_util import TOL, assert_normwise, from_dev, inputs, oracle_for, say, to_dev
+from parity_util import (TOL, adjoint_body_terms, assert_entrywise, assert_normwise, from_dev, inputs, oracle_for, say,
+                         to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +67,10 @@ def test_rnea_vjp(name, dtype, B):
     tb = cotangent((B, tree.nv), 7, dtype)
     qb, qdb, qddb, pib = m.rnea_vjp(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype), to_dev(tb, dtype))
     rq, rqd, rqdd, rpi = om.rnea_vjp(q, qd, qdd, tb)
-    assert_normwise("q_bar", from_dev(qb)[:, None], rq[:, None], dtype)
-    assert_normwise("qd_bar", from_dev(qdb)[:, None], rqd[:, None], dtype)
-    assert_normwise("qdd_bar", from_dev(qddb)[:, None], rqdd[:, None], dtype)
+    sq, sqd, sqdd = adjoint_body_terms(om, tree, q, qd, qdd, tb)
+    assert_entrywise("q_bar", from_dev(qb), rq, sq, dtype)
+    assert_entrywise("qd_bar", from_dev(qdb), rqd, sqd, dtype)
+    assert_entrywise("qdd_bar", from_dev(qddb), rqdd, sqdd, dtype)
     assert_param_grad(pib.cpu().double().numpy(), rpi, dtype)
 
 
@@ -193,3 +197,46 @@ def test_autograd_functions():
     (poses * to_dev(wp, dtype)).sum().backward()
     ref = om.fk_vjp(q, wp.reshape(50, -1, 3, 4))
     assert_normwise("fk q.grad", from_dev(tq2.grad)[:, None], ref[:, None], dtype)
+
+
+def _sampled_adjoint_case(name, dtype, B, n_sample, seed):
+    tree = synth.tree_by_name(name)
+    m, om = bard.Model.from_tree(tree), oracle_for(tree)
+    q, qd, qdd = inputs(tree, B, seed, dtype)
+    idx = np.sort(np.random.default_rng(seed + 1).choice(B, n_sample, replace=False))
+    return tree, m, om, q, qd, qdd, idx
+
+
+@pytest.mark.parametrize("name,dtype,B", [("humanoid_large", "float32", 262144), ("humanoid_small", "float64", 40000),
+                                          ("quadruped_spine", "float64", 65536)])
+def test_adjoints_loop_over_more_tiles_than_resident_workgroups(name, dtype, B):
+    """The adjoint kernels run one workgroup per resident slot and loop over
+    tiles, loading the next tile while working on the current one.  At these
+    batches every workgroup runs many tiles (free root in FP32 and FP64, fixed
+    base in FP64).  Cotangents are non-zero on a sampled subset, so the oracle
+    checks those instances one by one, the batch-summed parameter gradient
+    exactly, and every other instance must return exact zeros."""
+    import torch
+    say(f"[gpu] adjoint tile loop {name} {dtype} B={B}")
+    tree, m, om, q, qd, qdd, idx = _sampled_adjoint_case(name, dtype, B, 256, 2150)
+    tb = np.zeros((B, tree.nv))
+    tb[idx] = cotangent((len(idx), tree.nv), 17, dtype)
+    d = [to_dev(x, dtype) for x in (q, qd, qdd)]
+    qb, qdb, qddb, pib = m.rnea_vjp(*d, to_dev(tb, dtype))
+    pb = np.zeros((B, tree.n_bodies * 12))
+    pb[idx] = cotangent((len(idx), tree.n_bodies * 12), 18, dtype)
+    fq = m.fk_vjp(d[0], to_dev(pb, dtype))
+    torch.cuda.synchronize()
+    rq, rqd, rqdd, rpi = om.rnea_vjp(q[idx], qd[idx], qdd[idx], tb[idx])
+    S = adjoint_body_terms(om, tree, q[idx], qd[idx], qdd[idx], tb[idx])
+    g = [from_dev(x) for x in (qb, qdb, qddb)]
+    for lbl, gg, rr, ss in zip(("q_bar", "qd_bar", "qdd_bar"), g, (rq, rqd, rqdd), S):
+        assert_entrywise(lbl, gg[idx], rr, ss, dtype)
+    assert_param_grad(pib.cpu().double().numpy(), rpi, dtype)
+    fg = from_dev(fq)
+    assert_normwise("fk q_bar", fg[idx][:, None], om.fk_vjp(q[idx], pb[idx].reshape(len(idx), -1, 3, 4))[:, None],
+                    dtype)
+    mask = np.ones(B, bool)
+    mask[idx] = False
+    for x in g + [fg]:
+        assert not x[mask].any()

@@ -6,17 +6,17 @@ beyond the three-part argument reduction, and an exactly zero torque.
 
 A configuration whose on-chip staging does not fit one workgroup must be
 refused with BARD_E_CAPACITY (FP64 at 60+ bodies); everything else is held
-to the tolerance contract of parity_util, with the torque and mass-matrix
-bounds taken relative to the size of the summed per-body terms (a 64-body
-star's root torque sums terms up to 200 times its size)."""
+to the per-entry contract of parity_util, whose torque and mass-matrix bounds
+are relative to the summed per-body terms of each entry (a 64-body star's
+root torque sums terms up to 200 times its size)."""
 
 import numpy as np
 import pytest
 
 import synth
 from paper_2605_31481_amd import bard
-from parity_util import (TOL, aba_backward_error, assert_normwise, assert_normwise_scaled, fk_ref_blocks, from_dev,
-                         inputs, oracle_for, say, term_scales, to_dev)
+from parity_util import (TOL, aba_backward_error, assert_chain, assert_jacobian, assert_mass, assert_normwise,
+                         assert_tau, body_terms, fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -55,21 +55,20 @@ def test_edge_forward_operators(name, dtype):
         if out is None:
             refused.append(f"jacobian{frame}")
         else:
-            assert_normwise("jacobian", from_dev(out).reshape(B, len(ee), -1),
-                            om.jacobian(q, ee, frame=frame).reshape(B, len(ee), -1), dtype)
-    st, sm = term_scales(om, tree, q, qd, qdd)
+            assert_jacobian("jacobian", from_dev(out), om.jacobian(q, ee, frame=frame), dtype)
+    st, sm = body_terms(om, tree, q, qd, qdd)
     out = _run_or_capacity(lambda: m.rnea(dq, dqd, dqdd))
     tau = om.rnea(q, qd, qdd)
     if out is None:
         refused.append("rnea")
     else:
-        assert_normwise_scaled("rnea", from_dev(out)[:, None], tau[:, None], st, dtype)
+        assert_tau("rnea", from_dev(out), tau, st, dtype)
     out = _run_or_capacity(lambda: m.crba(dq))
     if out is None:
         refused.append("crba")
     else:
         Mg = from_dev(out).reshape(B, tree.nv, tree.nv)
-        assert_normwise_scaled("crba", Mg.reshape(B, 1, -1), om.crba(q).reshape(B, 1, -1), sm, dtype)
+        assert_mass("crba", Mg, om.crba(q), sm, dtype)
         assert np.array_equal(Mg, np.transpose(Mg, (0, 2, 1)))
     tau_in = synth.to_fp32_grid(tau) if dtype == "float32" else tau
     out = _run_or_capacity(lambda: m.aba(dq, dqd, to_dev(tau_in, dtype)))
@@ -82,10 +81,7 @@ def test_edge_forward_operators(name, dtype):
     if res is None:
         refused.append("chain")
     else:
-        rt, rM, rJ = om.chain(q, qd, qdd, ee)
-        assert_normwise_scaled("chain tau", from_dev(res[0])[:, None], rt[:, None], st, dtype)
-        assert_normwise_scaled("chain M", from_dev(res[1]).reshape(B, 1, -1), rM.reshape(B, 1, -1), sm, dtype)
-        assert_normwise("chain J", from_dev(res[2]).reshape(B, len(ee), -1), rJ.reshape(B, len(ee), -1), dtype)
+        assert_chain(om, tree, q, qd, qdd, ee, *(from_dev(x) for x in res), dtype, S=(st, sm))
     if refused:
         say(f"[gpu]   refused with BARD_E_CAPACITY: {refused}")
         assert dtype == "float64" and tree.n_bodies >= 60, (name, dtype, refused)
@@ -129,14 +125,8 @@ def test_edge_trees_in_one_plan():
     torch.cuda.synchronize()
     for k, (tree, (q, qd, qdd), (tau, M, J)) in enumerate(zip(trees, host, outs)):
         ee = plan.ee(k)
-        rt, rM, rJ = oracle_for(tree).chain(q, qd, qdd, ee)
-        B = q.shape[0]
-        st, sm = term_scales(oracle_for(tree), tree, q, qd, qdd)
-        assert_normwise_scaled(f"plan tau {names[k]}", from_dev(tau)[:, None], rt[:, None], st, "float32")
-        assert_normwise_scaled(f"plan M {names[k]}", from_dev(M).reshape(B, 1, -1), rM.reshape(B, 1, -1), sm,
-                               "float32")
-        assert_normwise(f"plan J {names[k]}", from_dev(J).reshape(B, len(ee), -1), rJ.reshape(B, len(ee), -1),
-                        "float32")
+        assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, from_dev(tau), from_dev(M), from_dev(J), "float32",
+                     label=f"plan {names[k]}")
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
@@ -156,7 +146,7 @@ def test_large_joint_angles(dtype):
     out = m.fk(to_dev(q, dtype))
     assert_normwise("fk", from_dev(out).reshape(B, 7, 12), fk_ref_blocks(om, q), dtype)
     tau = m.rnea(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype))
-    assert_normwise("rnea", from_dev(tau)[:, None], om.rnea(q, qd, qdd)[:, None], dtype)
+    assert_tau("rnea", from_dev(tau), om.rnea(q, qd, qdd), body_terms(om, tree, q, qd, qdd, mass=False)[0], dtype)
 
 
 @pytest.mark.parametrize("name", ["humanoid_large", "quadruped_spine"])

@@ -2,7 +2,8 @@
 23 DOF with batches 512, 1024, 2048, 4096 and 8192 (15,872 instances) in one
 plan, checked against the oracle on sampled instances of every tree, for each
 fusion mode, tile and item order; graph replays with new inputs between them;
-the autotuner and its cache.  Tolerance contract as in parity_util."""
+the autotuner and its cache; a gravity change between runs.  Per-entry
+tolerance contract as in parity_util."""
 
 import numpy as np
 import pytest
@@ -10,7 +11,7 @@ import pytest
 import synth
 from oracle import OracleModel
 from paper_2605_31481_amd import bard
-from parity_util import assert_normwise, from_dev, inputs, oracle_for, say, to_dev
+from parity_util import assert_chain, from_dev, inputs, oracle_for, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -34,26 +35,22 @@ def _check(plan, trees, host, outs, dtype, n_sample=96, seed=0):
         B = q.shape[0]
         idx = np.sort(rng.choice(B, min(n_sample, B), replace=False))
         ee = plan.ee(k)
-        rt, rM, rJ = oracle_for(tree).chain(q[idx], qd[idx], qdd[idx], ee)
-        if tau is not None:
-            assert_normwise(f"tau[{k}]", from_dev(tau)[idx][:, None], rt[:, None], dtype)
-        if M is not None:
-            assert_normwise(f"M[{k}]", from_dev(M)[idx][:, None], rM.reshape(len(idx), 1, -1), dtype)
-        if J is not None:
-            assert_normwise(f"J[{k}]", from_dev(J)[idx].reshape(len(idx), len(ee), -1),
-                            rJ.reshape(len(idx), len(ee), -1), dtype)
+        assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee,
+                     None if tau is None else from_dev(tau)[idx], None if M is None else from_dev(M)[idx],
+                     None if J is None else from_dev(J)[idx], dtype, label=f"plan[{k}]")
 
 
-CONFIGS = [(16, 0, 0), (8, 1, 0), (32, 2, 1), (16, 2, 0), (8, 0, 1), (32, 0, 0)]
+CONFIGS = [(16, 0, 0, 0), (8, 1, 0, 0), (32, 2, 1, 0), (16, 2, 0, 0), (8, 0, 1, 0), (32, 0, 0, 0), (16, 0, 0, 1),
+           (8, 2, 0, 1)]
 
 
-@pytest.mark.parametrize("tile,fusion,order", CONFIGS)
-def test_plan_configurations(tile, fusion, order):
+@pytest.mark.parametrize("tile,fusion,order,lanes", CONFIGS)
+def test_plan_configurations(tile, fusion, order, lanes):
     import torch
-    say(f"[gpu] plan tile={tile} fusion={fusion} order={order}")
+    say(f"[gpu] plan tile={tile} fusion={fusion} order={order} lanes={lanes}")
     trees, models, batches, host, dev = _setup()
     plan = bard.Plan(models, batches)
-    plan.configure(tile, fusion, order)
+    plan.configure(tile, fusion, order, lanes)
     first = _snapshot(plan.run(dev))          # eager launch
     torch.cuda.synchronize()
     _check(plan, trees, host, first, "float32")
@@ -109,14 +106,9 @@ def test_plan_fp64_and_single_operators():
             q, qd, qdd = host[k]
             ee = plan.ee(k)
             idx = np.sort(rng.choice(B, min(32, B), replace=False))
-            rt, rM, rJ = oracle_for(trees[k]).chain(q[idx], qd[idx], qdd[idx], ee)
-            if tau is not None:
-                assert_normwise("tau", from_dev(tau)[idx][:, None], rt[:, None], "float32")
-            if M is not None:
-                assert_normwise("M", from_dev(M)[idx][:, None], rM.reshape(len(idx), 1, -1), "float32")
-            if J is not None:
-                assert_normwise("J", from_dev(J)[idx].reshape(len(idx), len(ee), -1),
-                                rJ.reshape(len(idx), len(ee), -1), "float32")
+            assert_chain(oracle_for(trees[k]), trees[k], q[idx], qd[idx], qdd[idx], ee,
+                         None if tau is None else from_dev(tau)[idx], None if M is None else from_dev(M)[idx],
+                         None if J is None else from_dev(J)[idx], "float32", label=f"mask {mask} [{k}]")
 
 
 def test_plan_autotune_and_cache(tmp_path, monkeypatch):
@@ -136,7 +128,7 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     assert text.count('"tile"') == 1
     again = bard.Plan(models, batches)
     c2 = again.config
-    assert c2["from_cache"] and (c2["tile"], c2["fusion"], c2["order"]) == (cfg["tile"], cfg["fusion"], cfg["order"])
+    assert c2["from_cache"] and all(c2[k] == cfg[k] for k in ("tile", "fusion", "order", "lanes"))
 
 
 def test_plan_follows_gravity_changes():
@@ -160,6 +152,6 @@ def test_plan_follows_gravity_changes():
         for k, (tree, (q, qd, qdd)) in enumerate(zip(trees, host)):
             idx = np.sort(rng.choice(q.shape[0], min(32, q.shape[0]), replace=False))
             om = OracleModel(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, g_new)
-            ref = om.rnea(q[idx], qd[idx], qdd[idx])
-            assert_normwise(f"tau[{k}] after set_gravity", from_dev(outs[k][0])[idx][:, None], ref[:, None],
-                            "float32")
+            tg = synth.Tree(**{**tree.__dict__, "gravity": g_new})
+            assert_chain(om, tg, q[idx], qd[idx], qdd[idx], [], from_dev(outs[k][0])[idx], None, None, "float32",
+                         label=f"tau[{k}] after set_gravity")
