@@ -49,6 +49,10 @@ def _load():
     lib.orc_rnea_vjp.argtypes = [P, i64, D, D, D, D, D, D, D, D, D, ci]
     lib.orc_fk_vjp.argtypes = [P, i64, D, D, D, ci]
     lib.orc_crba_vjp.argtypes = [P, i64, D, D, D, D, D, ci]
+    lib.orc_rnea_forces.argtypes = [P, i64, D, D, D, D, D, ci]
+    Fp = ctypes.POINTER(ctypes.c_float)
+    lib.orc_rnea_f32.argtypes = [P, i64, Fp, Fp, Fp, Fp, Fp, ci]
+    lib.orc_crba_f32.argtypes = [P, i64, Fp, Fp, Fp, ci]
     _lib = lib
     return lib
 
@@ -159,6 +163,41 @@ class OracleModel:
         pe = np.empty(q.shape[0])
         self._lib.orc_energy(self._h, q.shape[0], _d(q), _d(qd), _d(ke), _d(pe), threads)
         return ke, pe
+
+    def rnea_forces(self, q, qd, qdd, inertia=None, threads=0):
+        """Spatial force transmitted across each joint, [B, n, 6] = [moment; force]
+        in body coordinates about the body origin (tau is its projection on the
+        joint's motion subspace)."""
+        q = _f64(q, (-1, self.nq))
+        qd = _f64(qd, (-1, self.nv))
+        qdd = _f64(qdd, (-1, self.nv))
+        B = q.shape[0]
+        out = np.empty((B, self.n, 6))
+        pi = None if inertia is None else _f64(inertia, (self.n, 10))
+        self._lib.orc_rnea_forces(self._h, B, _d(q), _d(qd), _d(qdd), None if pi is None else _d(pi), _d(out),
+                                  threads)
+        return out
+
+    def rnea_f32(self, q, qd, qdd, threads=0):
+        """The RNEA recursion evaluated in single precision (inputs and parameters
+        rounded to float); returns float64 [B, nv].  Used only to show what a plain
+        single-precision evaluation attains."""
+        f = lambda a, shape: np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))
+        q, qd, qdd = f(q, (-1, self.nq)), f(qd, (-1, self.nv)), f(qdd, (-1, self.nv))
+        pi = f(self.inertia, (self.n, 10))
+        out = np.empty((q.shape[0], self.nv), dtype=np.float32)
+        fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._lib.orc_rnea_f32(self._h, q.shape[0], fp(q), fp(qd), fp(qdd), fp(pi), fp(out), threads)
+        return out.astype(np.float64)
+
+    def crba_f32(self, q, threads=0):
+        """CRBA evaluated in single precision; float64 [B, nv, nv]."""
+        q = np.ascontiguousarray(np.asarray(q, dtype=np.float32).reshape(-1, self.nq))
+        pi = np.ascontiguousarray(np.asarray(self.inertia, dtype=np.float32).reshape(self.n, 10))
+        out = np.empty((q.shape[0], self.nv, self.nv), dtype=np.float32)
+        fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._lib.orc_crba_f32(self._h, q.shape[0], fp(q), fp(pi), fp(out), threads)
+        return out.astype(np.float64)
 
     def rnea_vjp(self, q, qd, qdd, tau_bar, inertia=None, threads=0):
         """Reverse-mode gradients; inertia_bar is per instance, shape [B, n, 10]."""

@@ -16,6 +16,10 @@
 //                   Featherstone's algorithms), in body coordinates with explicit
 //                   6x6 Plucker transforms, run sequentially over body index.
 //   * kinetic and potential energy, used by the invariant checks.
+//   * the spatial force each joint transmits (the RNEA backward pass's f_i),
+//     whose size sets the tests' per-entry torque tolerance; and the RNEA and
+//     CRBA recursions instantiated in single precision, which the tests use
+//     only to show that tolerance is attainable by a plain evaluation.
 //   * vector-Jacobian products of RNEA and FK by reverse-mode automatic
 //     differentiation on a private tape (Sec. 3.5 functional mode and Sec. 4.3
 //     gradient-based identification use autograd for the same derivatives).
@@ -425,8 +429,13 @@ template <class S> void jacobian_one(const Model& M, const S* q, int n_ee, const
 // ----------------------------------------------------------------------------
 // RNEA (body coordinates): tau = M(q) qdd + C(q, qd) qd + g(q).
 // ----------------------------------------------------------------------------
+// If f_joint is not null it receives, per body i, the spatial force the joint
+// transmits from the parent to body i (the f_i of the backward pass once every
+// descendant has been added), in body-i coordinates about the body origin,
+// which lies on the joint axis.
 template <class S>
-void rnea_one(const Model& M, const S* q, const S* qd, const S* qdd, const S* pi /*[n][10]*/, S* tau) {
+void rnea_one(const Model& M, const S* q, const S* qd, const S* qdd, const S* pi /*[n][10]*/, S* tau,
+              V6<S>* f_joint = nullptr) {
   int n = M.n;
   std::vector<M6<S>> X(n);
   std::vector<V6<S>> v(n), a(n), f(n);
@@ -453,6 +462,8 @@ void rnea_one(const Model& M, const S* q, const S* qd, const S* qdd, const S* pi
     int p = M.parent[i];
     if (p >= 0) f[p] = v6_add(f[p], m6tv(X[i], f[i]));
   }
+  if (f_joint)
+    for (int i = 0; i < n; ++i) f_joint[i] = f[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -739,6 +750,42 @@ void orc_energy(void* m, int64_t B, const double* q, const double* qd, double* k
 #pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
   for (int64_t b = 0; b < B; ++b)
     energy_one<double>(M, q + b * M.nq, qd + b * M.nv, M.inertia.data(), ke + b, pe + b);
+}
+
+// The spatial force transmitted across every joint by the RNEA backward pass,
+// f_out [B][n][6] = [moment; force] in body coordinates about the body origin
+// (tau_i is its projection on the joint's motion subspace).  inertia_override
+// may be null.
+void orc_rnea_forces(void* m, int64_t B, const double* q, const double* qd, const double* qdd,
+                     const double* inertia_override, double* f_out, int nthreads) {
+  const Model& M = *(Model*)m;
+  const double* pi = inertia_override ? inertia_override : M.inertia.data();
+#pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    std::vector<double> tau(M.nv);
+    std::vector<V6<double>> f(M.n);
+    rnea_one<double>(M, q + b * M.nq, qd + b * M.nv, qdd + b * M.nv, pi, tau.data(), f.data());
+    for (int i = 0; i < M.n; ++i)
+      for (int k = 0; k < 6; ++k) f_out[(b * M.n + i) * 6 + k] = f[i].a[k];
+  }
+}
+
+// The same RNEA and CRBA recursions evaluated in single precision, inputs and
+// parameters rounded to float.  Not a reference: the tests use them to show
+// that the single-precision tolerance is attainable by a plain evaluation of
+// the textbook recursion.
+void orc_rnea_f32(void* m, int64_t B, const float* q, const float* qd, const float* qdd, const float* inertia,
+                  float* tau, int nthreads) {
+  const Model& M = *(Model*)m;
+#pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
+  for (int64_t b = 0; b < B; ++b)
+    rnea_one<float>(M, q + b * M.nq, qd + b * M.nv, qdd + b * M.nv, inertia, tau + b * M.nv);
+}
+
+void orc_crba_f32(void* m, int64_t B, const float* q, const float* inertia, float* Mout, int nthreads) {
+  const Model& M = *(Model*)m;
+#pragma omp parallel for num_threads(threads_or_default(nthreads)) schedule(static)
+  for (int64_t b = 0; b < B; ++b) crba_one<float>(M, q + b * M.nq, inertia, Mout + b * (int64_t)M.nv * M.nv);
 }
 
 // Reverse-mode gradient of <tau_bar, RNEA(q, qd, qdd; pi)>.  inertia_bar is per instance
