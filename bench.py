@@ -108,26 +108,48 @@ def time_graph(torch, make_calls, replays):
 
 
 def parity_sample(tree, sets, n_sample=256):
-    """Normwise error of the last timed outputs of set 0 against the FP64 oracle."""
+    """Per-entry error of the last timed outputs of set 0 against the FP64
+    oracle on sampled instances, under the tests' contract: tau and M entries
+    against atol + rtol max(|ref|, S) with S the transmitted-wrench scale
+    (tau) or sqrt(M_ii M_jj) (M), Jacobian entries against their column's
+    largest entry.  Also reports the normwise-per-block ratio."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
     from oracle import OracleModel
+    from parity_util import TOL, column_scale, entry_scales
     import synth
     (dev, outs, host) = sets[0]
     q, qd, qdd = (synth.to_fp32_grid(x) for x in host)
     B = q.shape[0]
     idx = np.random.default_rng(0).choice(B, min(n_sample, B), replace=False)
+    q, qd, qdd = q[idx], qd[idx], qdd[idx]
     om = OracleModel.from_tree(tree)
-    rt, rM, rJ = om.chain(q[idx], qd[idx], qdd[idx], tree.ee_bodies)
-    worst = 0.0
-    for g, r in ((outs[0], rt.reshape(len(idx), -1)), (outs[1], rM.reshape(len(idx), -1)),
-                 (outs[2], rJ.reshape(len(idx), len(tree.ee_bodies), -1))):
-        gg = g.cpu().double().numpy().T[idx].reshape(r.shape)
-        if gg.ndim == 2:
-            gg, r = gg[:, None], r[:, None]
-        err = np.abs(gg - r).max(axis=-1)
-        bound = 1e-6 + 1e-5 * np.abs(r).max(axis=-1)
-        worst = max(worst, float((err / bound).max()))
-    return {"max_err_over_tol": worst, "instances": int(len(idx)), "tolerance": "normwise rtol 1e-5 atol 1e-6",
+    rt, rM, rJ = om.chain(q, qd, qdd, tree.ee_bodies)
+    st, sm = entry_scales(om, tree, q, qd, qdd)
+    rtol, atol = TOL["float32"]
+    n = len(idx)
+    g = [o.cpu().double().numpy().T[idx] for o in outs]
+    refs = (rt, rM.reshape(n, -1), rJ.reshape(n, -1))
+    scales = (st, sm, column_scale(rJ).reshape(n, -1))
+    per_entry = {}
+    for lbl, gg, r, sc in zip(("tau", "M", "J"), g, refs, scales):
+        per_entry[lbl] = float((np.abs(gg - r) / (atol + rtol * np.maximum(np.abs(r), sc))).max())
+    normwise = max(float((np.abs(gg - r).max(1) / (atol + rtol * np.abs(r).max(1))).max()) for gg, r in zip(g, refs))
+    worst = max(per_entry.values())
+    return {"max_err_over_tol": worst, "per_entry": per_entry, "normwise_per_block": normwise,
+            "instances": int(n),
+            "tolerance": "per entry |gpu-ref| <= 1e-6 + 1e-5 max(|ref|, S): S = transmitted-wrench scale (tau), "
+                         "sqrt(M_ii M_jj) (M), column max (J)",
             "pass": worst <= 1.0}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(tree, target_s=10.0, max_s=30.0):
@@ -157,7 +179,7 @@ def cpu_baseline(tree, target_s=10.0, max_s=30.0):
     return {"value": done / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} configurations of the same tree (RNEA+CRBA+4-EE Jacobian, FP64), "
                       f"{el:.1f} s on {threads} OpenMP threads",
-            "value_1_thread": one / el1}
+            "value_1_thread": one / el1, "cpu_model": cpu_model()}
 
 
 def _rate(torch, calls, steps, warmup=10):
@@ -186,10 +208,103 @@ def bench_sweep(torch, bard, m, tree, bpe):
     return out
 
 
+# FP32 VALU peaks: 256 CU x 4 SIMD x 16 lanes x 2 FLOP per FMA x 2.4 GHz unpacked (the
+# build turns packed FP32 instructions off), twice that packed
+VALU_PEAK_FP32 = 78.6e12
+VALU_PEAK_FP32_PACKED = 157.3e12
+
+
+def op_work(tree, n_ee, op):
+    """(algorithmic bytes, FLOP) of one evaluation of one operator in FP32.
+    Bytes: the inputs read and the outputs written.  FLOP: the per-body FMA
+    model (2 FLOP per FMA) -- joint transform 24, pose composition 36, RNEA
+    forward 130 and backward 33, ABA 380 -- for the operators bound by
+    arithmetic; None for the memory-bound ones."""
+    n, nq, nv = tree.n_bodies, tree.nq, tree.nv
+    if op == "fk":
+        return 4 * (nq + 12 * n), 2 * n * (24 + 36)
+    if op == "jacobian":
+        return 4 * (nq + 6 * nv * n_ee), None
+    if op == "rnea":
+        return 4 * (nq + 3 * nv), 2 * n * (24 + 130 + 33)
+    if op == "crba":
+        return 4 * (nq + nv * nv), None
+    if op == "aba":
+        return 4 * (nq + 3 * nv), 2 * n * (24 + 380)
+    raise ValueError(op)
+
+
+def bench_operators(torch, bard):
+    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA, CRBA,
+    ABA) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
+    at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
+    evaluations per second from the kernel time, the HBM fraction of its
+    algorithmic bytes, and for RNEA and ABA the FP32 VALU fraction of the
+    per-body FLOP model.  Then the 23-DOF humanoid at B = 16384: fused chain,
+    three plain launches and graph replay."""
+    import synth
+    out = {}
+    for name, B in (("humanoid_large", 4096), ("humanoid_large", 16384), ("chain7", 4096)):
+        tree = synth.tree_by_name(name)
+        m = bard.Model.from_tree(tree)
+        ee = tree.ee_bodies
+        per_eval = 4 * (tree.nq + 4 * tree.nv + 12 * tree.n_bodies + tree.nv * tree.nv + 6 * tree.nv * len(ee))
+        nsets = max(3, min(64, math.ceil(512e6 / (per_eval * B))))
+        sets = []
+        for k in range(nsets):
+            q, qd, qdd = synth.random_state(tree, B, 11000 + k)
+            d = [torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qdd)]
+            o = {"fk": torch.empty((12 * tree.n_bodies, B), device="cuda"),
+                 "jacobian": torch.empty((6 * tree.nv * len(ee), B), device="cuda"),
+                 "rnea": torch.empty((tree.nv, B), device="cuda"),
+                 "crba": torch.empty((tree.nv * tree.nv, B), device="cuda"),
+                 "aba": torch.empty((tree.nv, B), device="cuda")}
+            sets.append((d, o))
+        binders = {"fk": lambda d, o: m.bind_fk(d[0], o["fk"]),
+                   "jacobian": lambda d, o: m.bind_jacobian(d[0], ee, o["jacobian"]),
+                   "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),
+                   "crba": lambda d, o: m.bind_crba(d[0], o["crba"]),
+                   "aba": lambda d, o: m.bind_aba(d[0], d[1], d[2], o["aba"])}   # qdd's values as torques
+        n = max(100, min(1000, 4_000_000 // B))
+        for op, bind in binders.items():
+            calls = [bind(d, o) for (d, o) in sets]
+            _, kavg = time_calls(torch, calls, n, 10)
+            t = kavg * 1e-3
+            nbytes, flops = op_work(tree, len(ee), op)
+            key = f"op_{name}_B{B}_{op}"
+            out[key + "_evals_per_s"] = B / t
+            out[key + "_kernel_us"] = kavg * 1e3
+            out[key + "_hbm_frac"] = nbytes * B / t / 1e9 / HBM_PEAK_GBS
+            if flops is not None:
+                out[key + "_valu_frac"] = flops * B / t / VALU_PEAK_FP32
+        del sets
+        torch.cuda.empty_cache()
+    # the 23-velocity-DOF humanoid at B = 16384: fused, plain and graph forms
+    ts = synth.humanoid_small()
+    ms = bard.Model.from_tree(ts)
+    B = 16384
+    bpe = chain_bytes_per_eval(ts, len(ts.ee_bodies))
+    sets = make_sets(torch, ts, B, max(4, math.ceil(512e6 / (bpe * B))), 12000)
+    mk = lambda: [ms.bind_chain(d[0], d[1], d[2], ts.ee_bodies, tuple(o)) for (d, o, _) in sets]
+    calls = mk()
+    _, kf = time_calls(torch, calls, 200, 10)
+    plain = [(ms.bind_rnea(d[0], d[1], d[2], o[0]), ms.bind_crba(d[0], o[1]), ms.bind_jacobian(d[0], ts.ee_bodies, o[2]))
+             for (d, o, _) in sets]
+    _, kp = time_calls(torch, [(lambda t=t: (t[0](), t[1](), t[2]())) for t in plain], 200, 10)
+    out["nv23_B16384_chain_evals_per_s"] = B / (kf * 1e-3)
+    out["nv23_B16384_chain_hbm_frac"] = bpe * B / (kf * 1e-3) / 1e9 / HBM_PEAK_GBS
+    out["nv23_B16384_plain_3_launches_evals_per_s"] = B / (kp * 1e-3)
+    out["nv23_B16384_graph_replay_evals_per_s"] = B / time_graph(torch, mk, 20)
+    del sets, calls, plain
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_plan(torch, bard, steps):
     """Five random trees (7, 11, 12, 18, 23 DOF; batches 512..8192 = 15,872
-    instances; RNEA + CRBA + tip Jacobians): one plan (graph replay) against
-    five separate chain launches."""
+    instances; RNEA + CRBA + tip Jacobians): one plan (graph replay) with the
+    schedule the autotuner picks, against the untuned default and five
+    separate chain launches."""
     import synth
     trees = synth.multi_trees()
     batches = synth.MULTI_BATCHES
@@ -199,6 +314,11 @@ def bench_plan(torch, bard, steps):
     for k, (t, B) in enumerate(zip(trees, batches)):
         q, qd, qdd = synth.random_state(t, B, 6000 + k)
         ins.append(tuple(torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qdd)))
+    default_cfg = plan.config
+    plan.run(ins)
+    torch.cuda.synchronize()
+    t_def, k_def = _rate(torch, [lambda: plan.run(ins)], 50)
+    plan.autotune()
     total = sum(batches)
     nbytes = sum(4 * B * (t.nq + 3 * t.nv + t.nv * t.nv + 6 * t.nv * len(plan.ee(k)))
                  for k, (t, B) in enumerate(zip(trees, batches)))
@@ -213,6 +333,7 @@ def bench_plan(torch, bard, steps):
     t_sep, k_sep = _rate(torch, [lambda: [c() for c in sep]], n)
     return {"plan5_evals_per_s": total / t_plan, "plan5_gpu_us": k_plan * 1e6,
             "plan5_hbm_frac": nbytes / k_plan / 1e9 / HBM_PEAK_GBS, "plan5_config": plan.config,
+            "plan5_default_config": default_cfg, "plan5_default_gpu_us": k_def * 1e6,
             "separate5_evals_per_s": total / t_sep, "separate5_gpu_us": k_sep * 1e6}
 
 
@@ -239,20 +360,33 @@ def bench_adjoints(torch, bard, steps):
             "fk_vjp_819200_hbm_frac": bytes_f / k_f / 1e9 / HBM_PEAK_GBS}
 
 
-def bench_sysid(torch, bard):
+def sysid_data():
+    import synth
+    tree = synth.quadruped_spine()
+    return tree, [synth.to_fp32_grid(x) for x in synth.random_state(tree, 10000, 9100)]
+
+
+def sysid_reference_torques():
+    """Torques of the identification data at the true parameters, from the
+    FP64 oracle (part of the oracle leg)."""
+    from oracle import OracleModel
+    tree, (q, qd, qdd) = sysid_data()
+    return OracleModel.from_tree(tree).rnea(q, qd, qdd)
+
+
+def bench_sysid(torch, bard, tau_ref):
     """Mass identification (Sec. 4.3's experiment) on 10,000 random
     configurations of the 11-DOF quadruped, FP32: torques from the true
-    parameters by the library plus 5% Gaussian noise per joint, masses started
-    30% away from the truth, L-BFGS, 10 seeds."""
-    import synth
+    parameters by the FP64 oracle plus 5% Gaussian noise per joint, masses
+    started 30% away from the truth, L-BFGS, 10 seeds."""
     from paper_2605_31481_amd import sysid
-    tree = synth.quadruped_spine()
+    tree, host = sysid_data()
     m = bard.Model.from_tree(tree)
-    q, qd, qdd = (torch.from_numpy(synth.to_fp32_grid(x).T.copy()).float().cuda()
-                  for x in synth.random_state(tree, 10000, 9100))
+    q, qd, qdd = (torch.from_numpy(x.T.copy()).float().cuda() for x in host)
+    tau_true = torch.from_numpy(tau_ref.T.copy()).float().cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = sysid.identify(m, tree.inertia, q, qd, qdd, seeds=range(10), noise=0.05, max_iter=60)
+    out = sysid.identify(m, tree.inertia, q, qd, qdd, seeds=range(10), noise=0.05, max_iter=60, tau_true=tau_true)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     per_seed = out["rel_error"].mean(axis=1) * 100
@@ -269,16 +403,14 @@ def bench_workspace(torch, bard, steps):
     one state, as four calls.  Patterns: P0 every input new (all tiers miss),
     P1 the same q, qd, qdd again, P2 the same q with a new qd.  Policies: no
     workspace, the kinematics tier alone, and kinematics + mass + bias tiers.
-    Each pattern's last RNEA and CRBA outputs are checked on 64 instances
-    against the FP64 oracle (tau under the affine bound when it came from the
-    tiers, M under the normwise contract)."""
+    Each pattern's last outputs are compared with cold calls (no workspace) on
+    the same inputs: the largest difference relative to the output's size
+    (zero where the tier returns the cold call's bits)."""
     import synth
-    from oracle import OracleModel
     out = {}
     for name in ("chain7", "humanoid_large"):
         tree = synth.tree_by_name(name)
         m = bard.Model.from_tree(tree)
-        om = OracleModel.from_tree(tree)
         B = 4096
         hq, hqd, hqdd = synth.random_state(tree, B, 7000)
         _, hqd2, _ = synth.random_state(tree, B, 7001)
@@ -301,7 +433,6 @@ def bench_workspace(torch, bard, steps):
             m.rnea(q, v, qdd, out=outs["tau"], ws=w, q_tag=qt, qd_tag=dt)
             return v
 
-        idx = np.random.default_rng(1).choice(B, 64, replace=False)
         n = max(50, steps // 4)
         for label, pol in (("no_ws", None), ("kin", 1), ("all", 7)):
             for pattern in ("P0", "P1", "P2"):
@@ -310,21 +441,13 @@ def bench_workspace(torch, bard, steps):
                 w = bard.Workspace(m, B, policy=pol) if pol is not None else None
                 t, k = _rate(torch, [lambda: step(w, pattern)], n)
                 v = step(w, pattern)
+                cold = (m.fk(q), m.jacobian(q, ee), m.crba(q), m.rnea(q, v, qdd))
                 torch.cuda.synchronize()
-                hv = (hqd if v is qd else hqd2)[idx]
-                tau = outs["tau"].cpu().double().numpy().T[idx]
-                Mg = outs["M"].cpu().double().numpy().T[idx]
-                rq, rqdd = synth.to_fp32_grid(hq)[idx], synth.to_fp32_grid(hqdd)[idx]
-                rv = synth.to_fp32_grid(hv)
-                ref_t, ref_M = om.rnea(rq, rv, rqdd), om.crba(rq).reshape(len(idx), -1)
-                ref_b = om.rnea(rq, rv, np.zeros_like(rqdd))
-                scale = (np.abs(ref_t).max(1) + np.abs(ref_M.reshape(len(idx), tree.nv, tree.nv)).sum(2).max(1)
-                         * np.abs(rqdd).max(1) + np.abs(ref_b).max(1))
-                et = float((np.abs(tau - ref_t).max(1) / (1e-6 + 1e-5 * scale)).max())
-                em = float((np.abs(Mg - ref_M).max(1) / (1e-6 + 1e-5 * np.abs(ref_M).max(1))).max())
+                diff = max(float(((a - c).abs().max() / c.abs().max().clamp_min(1e-30)).item())
+                           for a, c in zip((outs["fk"], outs["j"], outs["M"], outs["tau"]), cold))
                 key = f"{name}_{label}_{pattern}"
                 out[key + "_gpu_us"] = k * 1e6
-                out[key + "_err_over_tol"] = max(et, em)
+                out[key + "_rel_diff_vs_cold"] = diff
     return out
 
 
@@ -385,8 +508,6 @@ def main():
     value = B * args.steps / wall
     achieved = per_call / (kavg * 1e-3) / 1e9
     log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us")
-    parity = parity_sample(tree, sets)
-    log(f"[bench] parity {parity}")
 
     extra = {}
     if not args.no_extra:
@@ -438,17 +559,25 @@ def main():
         extra["nv23_tree_evals_per_s"] = B * args.steps / w3
         extra["nv23_tree_kernel_us"] = k3 * 1e3
         del sets3, calls3
+        extra.update(bench_operators(torch, bard))
         extra.update(bench_sweep(torch, bard, m, tree, bpe))
         extra.update(bench_plan(torch, bard, args.steps))
         extra.update(bench_adjoints(torch, bard, args.steps))
         extra.update(bench_workspace(torch, bard, args.steps))
-        extra.update(bench_sysid(torch, bard))
         log(f"[bench] extra {extra}")
 
-    cpu = None
+    # The oracle leg: the FP64 oracle's throughput on a bounded sample (the
+    # CPU baseline), the parity of the timed outputs on sampled instances, and
+    # the reference torques of the identification experiment.
+    cpu = parity = None
     if not args.no_cpu:
+        parity = parity_sample(tree, sets)
+        log(f"[bench] parity {parity}")
         cpu = cpu_baseline(tree)
         log(f"[bench] cpu baseline {cpu}")
+        if not args.no_extra:
+            extra.update(bench_sysid(torch, bard, sysid_reference_torques()))
+            log(f"[bench] sysid {dict((k, v) for k, v in extra.items() if k.startswith('sysid'))}")
 
     out = {
         "metric": METRIC,

@@ -585,6 +585,34 @@ class Model:
             return keep
         return call
 
+    def bind_fk(self, q, out, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(out, 12 * self.n_bodies, "out")], B, layout)
+        L = _layouts([q, out], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(out), L, 0, B, _stream_ptr(q))
+        keep = (L, q, out)
+
+        def call():
+            rc = bard_fk(*args)
+            if rc:
+                raise BardError(rc, "bard_fk")
+            return keep
+        return call
+
+    def bind_aba(self, q, qd, tau, out, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(qd, self.nv, "qd"), (tau, self.nv, "tau"), (out, self.nv, "out")], B, layout)
+        L = _layouts([q, qd, tau, out], layout)
+        args = (self._h, None, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(tau), _ptr(out), L, 0, 0, B, _stream_ptr(q))
+        keep = (L, q, qd, tau, out)
+
+        def call():
+            rc = bard_aba(*args)
+            if rc:
+                raise BardError(rc, "bard_aba")
+            return keep
+        return call
+
     def bind_rnea(self, q, qd, qdd, out, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
         _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (out, self.nv, "out")], B, layout)

@@ -341,7 +341,7 @@ int plan_tier(bard_model* m, bard_ws* ws, uint64_t q_tag, int64_t B, int frame, 
   if (!ws || !(ws->policy & BARD_TIER_KINEMATICS) || q_tag == 0) return BARD_OK;
   int rc = ensure_tier<Real>(ws, &ws->kin, kin_rows(m->n, m->nv), st);
   if (rc) return rc;
-  const bool need_body = OPS & (OP_FK | OP_RNEA | OP_CRBA);
+  const bool need_body = OPS & (OP_FK | OP_RNEA | OP_CRBA | OP_KIN);
   const bool need_s = OPS & (OP_JAC | OP_RNEA | OP_CRBA);
   const bool need_pose = need_body || ((OPS & OP_JAC) && frame == 1);
   const bool same = ws->tier_B == B;
@@ -710,6 +710,11 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
     a.J = (R*)J;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 6 * m->nv * n_ee, &a.sJ_b, &a.sJ_k))
       return fail(BARD_E_ARG, "bad layout stride");
+    DeviceCopy* dc = nullptr;
+    int rc2 = ensure_device(m, &dc, (hipStream_t)stream);
+    if (rc2) return rc2;
+    if (dc->dm.use_scan)
+      return run_tree<R, OP_JAC | OP_KIN>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream, ws, q_tag);
     return run_tree<R, OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);

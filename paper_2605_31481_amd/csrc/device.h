@@ -113,6 +113,48 @@ __device__ __forceinline__ void cross3(const Real* a, const Real* b, Real* c) {
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Inertia of a body about its own origin in world axes, from its parameters
+// about the body origin (m, h, I_O) and its world rotation R:
+// [m, R h, R I_O R^T], packed [m, h(3), Ixx, Ixy, Iyy, Ixz, Iyz, Izz].
+template <class Real>
+__device__ __forceinline__ void rotate_inertia(const Real* pi, const Real* R, Real* Ip) {
+  Ip[0] = pi[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Ip[1 + i] = R[3 * i] * pi[1] + R[3 * i + 1] * pi[2] + R[3 * i + 2] * pi[3];
+  const Real Ib[9] = {pi[4], pi[5], pi[7], pi[5], pi[6], pi[8], pi[7], pi[8], pi[9]};
+  Real X[9];
+  mul33(R, Ib, X);
+  Ip[4] = X[0] * R[0] + X[1] * R[1] + X[2] * R[2];
+  Ip[5] = X[0] * R[3] + X[1] * R[4] + X[2] * R[5];
+  Ip[6] = X[3] * R[3] + X[4] * R[4] + X[5] * R[5];
+  Ip[7] = X[0] * R[6] + X[1] * R[7] + X[2] * R[8];
+  Ip[8] = X[3] * R[6] + X[4] * R[7] + X[5] * R[8];
+  Ip[9] = X[6] * R[6] + X[7] * R[7] + X[8] * R[8];
+}
+
+// A rigid-body inertia [m, h, Ibar] about a point x re-expressed about the
+// point x - r (r: the old reference point relative to the new one; same axes).
+// With c the centre of mass relative to x, the parallel-axis theorem gives
+//   h' = h + m r,
+//   Ibar' = Ibar + (m r.r + 2 r.h) 1 - m r r^T - r h^T - h r^T.
+template <class Real>
+__device__ __forceinline__ void shift_inertia(const Real* I, const Real* r, Real* o) {
+  const Real m = I[0];
+  const Real h[3] = {I[1], I[2], I[3]};
+  const Real g[3] = {m * r[0] + h[0], m * r[1] + h[1], m * r[2] + h[2]};
+  const Real dg = r[0] * (g[0] + h[0]) + r[1] * (g[1] + h[1]) + r[2] * (g[2] + h[2]);
+  o[0] = m;
+  o[1] = g[0];
+  o[2] = g[1];
+  o[3] = g[2];
+  o[4] = I[4] + dg - (r[0] * g[0] + h[0] * r[0]);
+  o[5] = I[5] - (r[0] * g[1] + h[0] * r[1]);
+  o[6] = I[6] + dg - (r[1] * g[1] + h[1] * r[1]);
+  o[7] = I[7] - (r[0] * g[2] + h[0] * r[2]);
+  o[8] = I[8] - (r[1] * g[2] + h[1] * r[2]);
+  o[9] = I[9] + dg - (r[2] * g[2] + h[2] * r[2]);
+}
+
 // Spatial inertia of a body about the frame origin o, in world axes, from its
 // parameters about the body origin (m, h, I_O) and its pose (R, p) relative to o:
 //   h_w = R h + m p,

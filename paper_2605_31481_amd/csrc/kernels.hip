@@ -16,20 +16,27 @@
 // base).  In that frame every body's motion subspace s_i is exactly the
 // direct Jacobian column of eq. (7), velocities and accelerations propagate
 // as v_i = v_p + s_i qd_i and a_i = a_p + s_i qdd_i + v_p x (s_i qd_i), and
-// the leaf-to-root sums of forces, composite inertias (CRBA) and articulated
-// inertias (ABA) are plain additions: no 6x6 congruence X^T I X is needed
-// (the update Sec. 3.5 singles out as the cost of CRBA and ABA).  Putting the
-// origin at the base keeps coordinates small for FP32.
+// the leaf-to-root sums of forces and articulated inertias (ABA) are plain
+// additions, and composite inertias (CRBA) need only a parallel-axis shift:
+// no 6x6 congruence X^T I X (the update Sec. 3.5 singles out as the cost of
+// CRBA and ABA).  Quantities whose size grows with the distance |p| from the
+// base are formed about each body's own origin first: the body force from the
+// velocity and acceleration moved to the body origin, the composite inertia
+// about each joint's origin from the bodies' positions relative to it.  Formed
+// about the base origin directly, they would carry terms of order |p|^2 that
+// cancel in the torques and mass-matrix entries of distal joints, which FP32
+// would then lose.
 //
 // Phases.  Staging: the workgroup copies the model's table image and its
 // input tile into LDS.  Level sweep: joint transform from the Rodrigues
 // constants (eqs. (4)-(5)), world pose, s_i, velocity and acceleration.  Body
-// phase: world inertia and body force per (body, instance).  Subtree phase:
-// because the frame is common, F_i (forces) and Ic_i (composite inertias) are
-// plain sums over the subtree, which is a contiguous range of preorder
-// positions; tau_i = s_i . F_i.  Output: every wave writes the dense M and J
-// from LDS with lanes over instances, so stores of the instance-minor layout
-// coalesce.  Only the level sweep is serial over the tree.
+// phase: inertia about the body origin (world axes) and body force per (body,
+// instance).  Subtree phase: the subtree is a contiguous range of preorder
+// positions; F_i is the plain sum of the body forces over it and
+// tau_i = s_i . F_i; Ic_i is the sum of the bodies' inertias shifted to joint
+// i's origin.  Output: every wave writes the dense M and J from LDS with lanes
+// over instances, so stores of the instance-minor layout coalesce.  Only the
+// level sweep is serial over the tree.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -289,10 +296,12 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
   constexpr bool VEL = RNEA;
   constexpr bool BACK = RNEA || CRBA;
   constexpr bool NEED_S = JAC || RNEA || CRBA;
-  constexpr bool NEED_BODY = FK || RNEA || CRBA;
+  constexpr bool NEED_BODY = FK || RNEA || CRBA || (OPS & OP_KIN);
   constexpr int T = 1 << LOGT;
   constexpr int SD = 6 * T + block_pad(T, sizeof(Real));   // per-dof block stride (elements)
   constexpr int SB = body_rows(OPS) * T + block_pad(T, sizeof(Real));  // per-body block stride (elements)
+  constexpr int PR = BIAS ? 22 : 16;  // body origin rows after the body phase
+  static_assert(PR + 3 <= body_rows(OPS), "body block too small for the origin rows");
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int nv = dm.nv, n = dm.n;
@@ -987,43 +996,70 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
     if (jac_early && r0 >= n && bok) store_jac_columns(r0 - n, rstep - n);
     for (int bb = r0; bb < n; bb += rstep) {
       Real* br = body_l + tb.bm2[bb].x * SB + in;
-      Real R[9], p[3], pic[10], I0[10];
+      Real R[9], p[3], pic[10];
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = br[k * T];
 #pragma unroll
       for (int k = 0; k < 3; ++k) p[k] = br[(9 + k) * T];
 #pragma unroll
       for (int k = 0; k < 10; ++k) pic[k] = ar.pi_ovr ? ar.pi_ovr[bb * 10 + k] : tb.cst[bb * CST + C_PI + k];
-      world_inertia(pic, R, p, I0);
+      // The block keeps the inertia about the body's own origin (world axes)
+      // and that origin: the subtree phase re-expresses composite inertias
+      // about each joint from relative positions.  The body force is formed
+      // about the body origin too, from the velocity and acceleration moved
+      // there (u_p = u_O + w x p), and then moved to the base origin
+      // (n_O = n_p + p x f).  Formed about the base origin directly, it would
+      // carry terms of order m |p|^2 |dw/dt| that cancel, and FP32 would lose
+      // the torques of joints far from the base.
+      Real Ip[10];
+      rotate_inertia(pic, R, Ip);
       Real f[6], fb[6];
       if (VEL) {
-        Real v[6], a[6], Ia[6], Iv[6], vxIv[6];
+        Real v[6], a[6], Ia[6], Iv[6], vxIv[6], t3[3];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           v[k] = br[(12 + k) * T];
           a[k] = br[(18 + k) * T];
         }
-        inertia_mul(I0, a, Ia);
-        inertia_mul(I0, v, Iv);
+        cross3(v, p, t3);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[3 + k] += t3[k];
+        cross3(a, p, t3);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[3 + k] += t3[k];
+        inertia_mul(Ip, a, Ia);
+        inertia_mul(Ip, v, Iv);
         crf(v, Iv, vxIv);
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[k] = Ia[k] + vxIv[k];
+        cross3(p, f + 3, t3);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[k] += t3[k];
         if (BIAS) {
           Real abv[6], Iab[6];
 #pragma unroll
           for (int k = 0; k < 6; ++k) abv[k] = br[(24 + k) * T];
-          inertia_mul(I0, abv, Iab);
+          cross3(abv, p, t3);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) abv[3 + k] += t3[k];
+          inertia_mul(Ip, abv, Iab);
 #pragma unroll
           for (int k = 0; k < 6; ++k) fb[k] = Iab[k] + vxIv[k];
+          cross3(p, fb + 3, t3);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) fb[k] += t3[k];
         }
       }
-      // overwrite this body's block in place: rows 0-5 f, rows 6-15 I, and
-      // for BIAS rows 16-21 the bias force (v, a, ab were read above)
+      // overwrite this body's block in place: rows 0-5 f, rows 6-15 the
+      // inertia about the body origin, rows PR-PR+2 that origin, and for BIAS
+      // rows 16-21 the bias force (R, p, v, a, ab were read above)
       if (VEL)
 #pragma unroll
         for (int k = 0; k < 6; ++k) br[k * T] = f[k];
 #pragma unroll
-      for (int k = 0; k < 10; ++k) br[(6 + k) * T] = I0[k];
+      for (int k = 0; k < 10; ++k) br[(6 + k) * T] = Ip[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) br[(PR + k) * T] = p[k];
       if (BIAS)
 #pragma unroll
         for (int k = 0; k < 6; ++k) br[(16 + k) * T] = fb[k];
@@ -1054,19 +1090,34 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         // its range, so the row groups of a wave read adjacent blocks (blocks
         // a fixed distance apart would share LDS banks).
         const int c1 = valid ? m2.y : 0;
-        Real F[6], Ic[10], Fb[6];
+        Real F[6], Ic[10], Fb[6], pj[3];
 #pragma unroll
         for (int k = 0; k < 6; ++k) F[k] = Fb[k] = Real(0);
 #pragma unroll
         for (int k = 0; k < 10; ++k) Ic[k] = Real(0);
+        // The composite inertia is summed about the subtree root's own origin
+        // p_j, each body's term shifted by its position relative to p_j.
+        // Taken about the base origin, the sum would carry terms of order
+        // m |p|^2 that cancel in s_j . Ic_j s_j, and FP32 would lose the
+        // mass-matrix entries of joints far from the base.
+        if (CRBA)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pj[k] = body_l[m2.x * SB + (PR + k) * T + in];
         const Real* br = body_l + (m2.x + part) * SB + in;
         for (int c = part; c < c1; c += np, br += np * SB) {
           if (RNEA)
 #pragma unroll
             for (int k = 0; k < 6; ++k) F[k] += br[k * T];
-          if (CRBA)
+          if (CRBA) {
+            Real Ik[10], d[3], Is[10];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) Ic[k] += br[(6 + k) * T];
+            for (int k = 0; k < 10; ++k) Ik[k] = br[(6 + k) * T];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[k] = br[(PR + k) * T] - pj[k];
+            shift_inertia(Ik, d, Is);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) Ic[k] += Is[k];
+          }
           if (BIAS)
 #pragma unroll
             for (int k = 0; k < 6; ++k) Fb[k] += br[(16 + k) * T];
@@ -1087,11 +1138,15 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
         }
         if (!valid) continue;
         if (CVJP && part == 0) {
-          // the composite inertia Ic_i, by preorder position, for the CRBA adjoint
+          // the composite inertia Ic_i about the base origin, by preorder
+          // position, for the CRBA adjoint
+          Real Ico[10];
+          shift_inertia(Ic, pj, Ico);
           Real* icr = reinterpret_cast<Real*>(smem + L.cvb) + m2.x * (cvjp_body_rows() * T + block_pad(T, sizeof(Real))) + in;
 #pragma unroll
-          for (int k = 0; k < 10; ++k) icr[k * T] = Ic[k];
+          for (int k = 0; k < 10; ++k) icr[k * T] = Ico[k];
         }
+        const bool rev = tb.meta[bb].y == J_REV;
         for (int d = part; d < m2.w; d += np) {
           const Real* sr = s_l + (m2.z + d) * SD + in;
           Real s[6];
@@ -1106,11 +1161,24 @@ __device__ __forceinline__ void tree_tile(const DevModel& dm, const DevEE& ee, c
             }
           }
           if (CRBA) {
-            Real fcv[6];
-            inertia_mul(Ic, s, fcv);
+            // s_j about p_j (a revolute axis passes through p_j: no linear
+            // part; prismatic columns are the same about every point, and a
+            // free root sits at the base origin), Fc_j = Ic_j s_j about p_j,
+            // then moved to the base origin: n_O = n + p_j x f.
+            Real sp[6], fcv[6], pxf[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              sp[k] = s[k];
+              sp[3 + k] = rev ? Real(0) : s[3 + k];
+            }
+            inertia_mul(Ic, sp, fcv);
+            cross3(pj, fcv + 3, pxf);
             Real* fo = fc_l + (m2.z + d) * SD + in;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) fo[k * T] = fcv[k];
+            for (int k = 0; k < 3; ++k) {
+              fo[k * T] = fcv[k] + pxf[k];
+              fo[(3 + k) * T] = fcv[3 + k];
+            }
           }
         }
       }
@@ -1664,6 +1732,8 @@ hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int bl
                                              hipStream_t);                                                        \
   template hipError_t launch_tree<R, OP_JAC>(const DevModel&, const DevEE&, const Args<R>&, int, int, size_t,      \
                                               hipStream_t);                                                       \
+  template hipError_t launch_tree<R, OP_JAC | OP_KIN>(const DevModel&, const DevEE&, const Args<R>&, int, int,     \
+                                                       size_t, hipStream_t);                                      \
   template hipError_t launch_tree<R, OP_RNEA>(const DevModel&, const DevEE&, const Args<R>&, int, int, size_t,     \
                                                hipStream_t);                                                      \
   template hipError_t launch_tree<R, OP_CRBA>(const DevModel&, const DevEE&, const Args<R>&, int, int, size_t,     \

@@ -8,8 +8,11 @@
 namespace bard {
 
 // OP_CVJP (with OP_CRBA): the reverse-mode product of CRBA, q_bar = d<M_bar, M(q)>/dq,
-// instead of the mass-matrix output.
-enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8, OP_BIAS = 16, OP_CVJP = 32 };
+// instead of the mass-matrix output.  OP_KIN: per-body blocks for the
+// kinematics alone, so that a Jacobian launch on a deep tree takes the
+// kinematics by pointer jumping, as every other operator does there (a
+// kinematics-tier entry one operator stores is then what another computes).
+enum { OP_FK = 1, OP_JAC = 2, OP_RNEA = 4, OP_CRBA = 8, OP_BIAS = 16, OP_CVJP = 32, OP_KIN = 64 };
 
 // Rows of a per-body LDS block: R, p, v, a (24); an RNEA launch that also
 // returns the bias forces RNEA(q, qd, 0) carries the acceleration without the
@@ -186,7 +189,7 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int ops, int n, int nq, in
   L.tin = (kind == 1) ? take(nv * T * rs) : off;
   if (kind == 0) {
     const bool need_s = ops & (OP_JAC | OP_RNEA | OP_CRBA);
-    const bool need_body = ops & (OP_FK | OP_RNEA | OP_CRBA);
+    const bool need_body = ops & (OP_FK | OP_RNEA | OP_CRBA | OP_KIN);
     L.s = need_s ? take((nv + 1) * (6 * T + pad) * rs) : off;
     L.body = need_body ? take(n * (body_rows(ops) * T + pad) * rs) : off;
     // fc: CRBA's Ic_i s blocks; RNEA kernels use them first as the scratch of

@@ -16,7 +16,7 @@ import pytest
 import synth
 from paper_2605_31481_amd import bard
 from parity_util import (TOL, aba_backward_error, assert_chain, assert_jacobian, assert_mass, assert_normwise,
-                         assert_tau, body_terms, fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
+                         assert_tau, entry_scales, fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_edge_forward_operators(name, dtype):
             refused.append(f"jacobian{frame}")
         else:
             assert_jacobian("jacobian", from_dev(out), om.jacobian(q, ee, frame=frame), dtype)
-    st, sm = body_terms(om, tree, q, qd, qdd)
+    st, sm = entry_scales(om, tree, q, qd, qdd)
     out = _run_or_capacity(lambda: m.rnea(dq, dqd, dqdd))
     tau = om.rnea(q, qd, qdd)
     if out is None:
@@ -146,7 +146,7 @@ def test_large_joint_angles(dtype):
     out = m.fk(to_dev(q, dtype))
     assert_normwise("fk", from_dev(out).reshape(B, 7, 12), fk_ref_blocks(om, q), dtype)
     tau = m.rnea(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype))
-    assert_tau("rnea", from_dev(tau), om.rnea(q, qd, qdd), body_terms(om, tree, q, qd, qdd, mass=False)[0], dtype)
+    assert_tau("rnea", from_dev(tau), om.rnea(q, qd, qdd), entry_scales(om, tree, q, qd, qdd, mass=False)[0], dtype)
 
 
 @pytest.mark.parametrize("name", ["humanoid_large", "quadruped_spine"])

@@ -12,7 +12,7 @@ import pytest
 import synth
 from paper_2605_31481_amd import bard
 from parity_util import (aba_backward_error, assert_chain, assert_jacobian, assert_mass, assert_normwise, assert_tau,
-                         body_terms, fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
+                         entry_scales, fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +64,7 @@ def test_rnea(name, dtype, B):
     say(f"[gpu] rnea {name} {dtype} B={B}")
     tree, m, om, q, qd, qdd = _setup(name, dtype, B)
     out = from_dev(m.rnea(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype)))
-    st, _ = body_terms(om, tree, q, qd, qdd, mass=False)
+    st, _ = entry_scales(om, tree, q, qd, qdd, mass=False)
     assert_tau("rnea", out, om.rnea(q, qd, qdd), st, dtype)
 
 
@@ -73,7 +73,7 @@ def test_crba(name, dtype, B):
     say(f"[gpu] crba {name} {dtype} B={B}")
     tree, m, om, q, qd, qdd = _setup(name, dtype, B)
     out = from_dev(m.crba(to_dev(q, dtype)))
-    _, sm = body_terms(om, tree, q, tau=False)
+    _, sm = entry_scales(om, tree, q, tau=False)
     assert_mass("crba", out, om.crba(q), sm, dtype)
     Mg = out.reshape(B, tree.nv, tree.nv)
     assert np.array_equal(Mg, np.transpose(Mg, (0, 2, 1))), "M must be bitwise symmetric"
@@ -117,7 +117,7 @@ def test_single_instance_and_empty():
     say("[gpu] B=1 and B=0")
     tree, m, om, q, qd, qdd = _setup("humanoid_small", "float64", 1)
     tau = from_dev(m.rnea(to_dev(q, "float64"), to_dev(qd, "float64"), to_dev(qdd, "float64")))
-    assert_tau("rnea B=1", tau, om.rnea(q, qd, qdd), body_terms(om, tree, q, qd, qdd, mass=False)[0], "float64")
+    assert_tau("rnea B=1", tau, om.rnea(q, qd, qdd), entry_scales(om, tree, q, qd, qdd, mass=False)[0], "float64")
     import torch
     e = torch.empty((tree.nq, 0), dtype=torch.float32, device="cuda")
     out = m.crba(e)
@@ -141,7 +141,7 @@ def test_inertia_override():
     pit = torch.from_numpy(pi).cuda()
     tau = from_dev(m.rnea(to_dev(q, "float64"), to_dev(qd, "float64"), to_dev(qdd, "float64"), inertia=pit))
     t2 = synth.Tree(**{**tree.__dict__, "inertia": pi})
-    st, _ = body_terms(om, t2, q, qd, qdd, mass=False)
+    st, _ = entry_scales(om, t2, q, qd, qdd, mass=False)
     assert_tau("rnea override", tau, om.rnea(q, qd, qdd, inertia=pi), st, "float64")
 
 

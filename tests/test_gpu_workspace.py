@@ -14,7 +14,7 @@ import pytest
 import synth
 from paper_2605_31481_amd import bard
 from oracle import OracleModel
-from parity_util import (affine_rnea_ok, assert_jacobian, assert_mass, assert_normwise, assert_tau, body_terms,
+from parity_util import (affine_rnea_ok, assert_jacobian, assert_mass, assert_normwise, assert_tau, entry_scales,
                          fk_ref_blocks, from_dev, inputs, oracle_for, say, to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -39,7 +39,7 @@ def test_tier_hits_equal_cold_calls(name, dtype, B):
     cold = {"fk": m.fk(q), "crba": m.crba(q), "rnea": m.rnea(q, qd, qdd), "jw": m.jacobian(q, ee),
             "jl": m.jacobian(q, ee, frame=bard.LOCAL_WORLD_ALIGNED)}
     torch.cuda.synchronize()
-    st, sm = body_terms(om, tree, hq, hqd, hqdd)
+    st, sm = entry_scales(om, tree, hq, hqd, hqdd)
     assert_tau("cold rnea", from_dev(cold["rnea"]), om.rnea(hq, hqd, hqdd), st, dtype)
     assert_mass("cold crba", from_dev(cold["crba"]), om.crba(hq), sm, dtype)
     assert_jacobian("cold jw", from_dev(cold["jw"]), om.jacobian(hq, ee, frame=0), dtype)
@@ -143,14 +143,14 @@ def test_mass_tier(name, dtype, B):
     ws = bard.Workspace(m, B, dtype=getattr(torch, dtype), policy=bard.TIER_KINEMATICS | bard.TIER_MASS)
     M1 = m.crba(q, ws=ws, q_tag=5)
     torch.cuda.synchronize()
-    assert_mass("crba miss", from_dev(M1), om.crba(hq), body_terms(om, tree, hq, tau=False)[1], dtype)
+    assert_mass("crba miss", from_dev(M1), om.crba(hq), entry_scales(om, tree, hq, tau=False)[1], dtype)
     assert torch.equal(m.crba(q, ws=ws, q_tag=5), M1)
     Ma = m.crba(to_dev(hq, dtype, "aos"), ws=ws, q_tag=5, layout="aos")
     assert torch.equal(Ma.t().contiguous(), M1)
     assert torch.equal(m.crba(q2, ws=ws, q_tag=5), M1)          # stale tag: cached M comes back
     M2 = m.crba(q2, ws=ws, q_tag=6)                              # new tag: recomputed
     torch.cuda.synchronize()
-    assert_mass("crba new tag", from_dev(M2), om.crba(hq2), body_terms(om, tree, hq2, tau=False)[1], dtype)
+    assert_mass("crba new tag", from_dev(M2), om.crba(hq2), entry_scales(om, tree, hq2, tau=False)[1], dtype)
     hits, misses = ws.stats()["mass"]["hits"], ws.stats()["mass"]["misses"]
     assert (hits, misses) == (3, 2), ws.stats()
     ws.set_policy(bard.TIER_KINEMATICS)                         # mass tier off: no copy
@@ -176,7 +176,7 @@ def test_bias_tier(name, dtype, B):
     q, qd, qdd, qd2, qdd2 = (to_dev(x, dtype) for x in (hq, hqd, hqdd, hqd2, hqdd2))
 
     def check(label, t, omx, x, xd, xdd):
-        assert_tau(label, from_dev(t), omx.rnea(x, xd, xdd), body_terms(omx, tree, x, xd, xdd, mass=False)[0], dtype)
+        assert_tau(label, from_dev(t), omx.rnea(x, xd, xdd), entry_scales(omx, tree, x, xd, xdd, mass=False)[0], dtype)
 
     ws = bard.Workspace(m, B, dtype=getattr(torch, dtype), policy=7)
     m.crba(q, ws=ws, q_tag=1)
