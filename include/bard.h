@@ -71,9 +71,11 @@ typedef enum {
   BARD_E_DEVICE = -5,      /* a HIP call failed, or an earlier asynchronous fault */
   BARD_E_CAPACITY = -6,    /* batch larger than a workspace/plan capacity, or model too large */
   BARD_E_UNSUPPORTED = -7, /* valid request the library does not implement */
-  BARD_E_CAPTURE = -8      /* the call would allocate or copy synchronously while its stream is
+  BARD_E_CAPTURE = -8,     /* the call would allocate or copy synchronously while its stream is
                               captured into a HIP graph (run it once before capturing, or call
                               bard_model_upload) */
+  BARD_E_STATE = -9        /* a call that allocates nothing found state it needs missing (the model
+                              not yet uploaded to the current device) */
 } bard_status;
 
 typedef enum { BARD_F32 = 0, BARD_F64 = 1 } bard_dtype;
@@ -268,6 +270,26 @@ int bard_rnea_vjp(bard_model_t model, bard_dtype dtype, const void* q, const voi
                   const void* qdd, const void* inertia_override, const void* tau_bar, void* q_bar,
                   void* qd_bar, void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B,
                   void* stream);
+/* rnea_vjp_noalloc: bard_rnea_vjp for callers that cannot allocate device
+ * memory -- code being captured into a HIP graph, tight serving or training
+ * loops, harnesses that forbid allocation.  Same arguments, outputs, layouts
+ * and kernels (its results are bitwise those of bard_rnea_vjp on the same
+ * device), but it calls no allocating routine: the model must already be on
+ * the current device (bard_model_upload, or any earlier operator call there),
+ * else BARD_E_STATE and nothing is launched; and the per-workgroup
+ * inertial-parameter sums go to a file-scope device array of 2048 * 64 * 10
+ * FP64 values (10 MiB), one per GPU the library runs on, held until the
+ * process ends.  That array is shared by every call on a GPU and keeps the
+ * last call's contents (every workgroup overwrites its own sums before they
+ * are read, so nothing needs clearing): calls with inertia_bar != NULL that
+ * overlap on one GPU -- other streams, other models, other threads -- race
+ * and must be serialised by the caller.  A request whose sums would not fit
+ * returns BARD_E_CAPACITY (not reachable with n_bodies <= 64).
+ * Errors: as bard_rnea_vjp, plus BARD_E_STATE. */
+int bard_rnea_vjp_noalloc(bard_model_t model, bard_dtype dtype, const void* q, const void* qd,
+                          const void* qdd, const void* inertia_override, const void* tau_bar,
+                          void* q_bar, void* qd_bar, void* qdd_bar, void* inertia_bar,
+                          const bard_layout* L, int64_t B, void* stream);
 /* fk_vjp: given poses_bar (per body the 3x4 row-major [R_bar | p_bar] of the
  * bard_fk output), writes q_bar [nq] = (d poses / dq)^T poses_bar.
  * Arrays (L order): q, poses_bar [n_bodies*12] in; q_bar out.

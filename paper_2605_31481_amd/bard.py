@@ -42,6 +42,7 @@ F32, F64 = 0, 1
 REVOLUTE, PRISMATIC, FREE, FIXED = 0, 1, 2, 3
 WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
+E_STATE = -9  # bard_status of a call that allocates nothing and found the model not uploaded
 UPLOAD_ADJOINT = 1
 # workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own
 # (see Workspace)
@@ -93,6 +94,8 @@ bard_chain = _sig("bard_chain", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _i32, _c
                                  _LP, _i64, _vp])
 bard_rnea_vjp = _sig("bard_rnea_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64,
                                        _vp])
+bard_rnea_vjp_noalloc = _sig("bard_rnea_vjp_noalloc", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                       _vp, _LP, _i64, _vp])
 bard_fk_vjp = _sig("bard_fk_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
 bard_crba_vjp = _sig("bard_crba_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _LP, _i64, _vp])
 bard_aba_vjp = _sig("bard_aba_vjp", [_vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _LP, _i64, _vp])
@@ -526,6 +529,22 @@ class Model:
         L = _layouts([q, qd, qdd, tau_bar, qb, qdb, qddb], layout)
         _check(bard_rnea_vjp(self._h, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia), _ptr(tau_bar),
                              _ptr(qb), _ptr(qdb), _ptr(qddb), _ptr(pib), L, B, _stream_ptr(q)), "bard_rnea_vjp")
+        return qb, qdb, qddb, pib
+
+    def rnea_vjp_noalloc(self, q, qd, qdd, tau_bar, out, inertia=None, layout: str = "soa"):
+        """rnea_vjp into caller-provided outputs out = (q_bar, qd_bar, qdd_bar,
+        inertia_bar or None) through bard_rnea_vjp_noalloc, which allocates
+        nothing (the model must already be on the device: see upload())."""
+        B = _batch_of(q, self.nq, layout)
+        qb, qdb, qddb, pib = out
+        _check_arrays(q, [(qd, self.nv, "qd"), (qdd, self.nv, "qdd"), (tau_bar, self.nv, "tau_bar"),
+                          (qb, self.nq, "q_bar"), (qdb, self.nv, "qd_bar"), (qddb, self.nv, "qdd_bar")], B, layout)
+        _check_inertia(q, inertia, self.n_bodies)
+        _check_inertia(q, pib, self.n_bodies, "inertia_bar")
+        L = _layouts([q, qd, qdd, tau_bar, qb, qdb, qddb], layout)
+        _check(bard_rnea_vjp_noalloc(self._h, _dtype_code(q), _ptr(q), _ptr(qd), _ptr(qdd), _ptr(inertia),
+                                     _ptr(tau_bar), _ptr(qb), _ptr(qdb), _ptr(qddb), _ptr(pib), L, B, _stream_ptr(q)),
+               "bard_rnea_vjp_noalloc")
         return qb, qdb, qddb, pib
 
     def aba_vjp(self, q, qd, qdd, qdd_bar, layout: str = "soa"):

@@ -41,6 +41,8 @@
 // with vee(G) = (G21 - G12, G02 - G20, G10 - G01).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device.h"
 
 namespace bard {
@@ -577,6 +579,32 @@ __global__ void __launch_bounds__(kAdjMaxThreads, sizeof(Real) == 4 ? 4 : 1) adj
     double* out = ar.partial + (int64_t)blockIdx.x * n * 10;
     for (int i = tid; i < n * 10; i += nt) out[i] = acc_l[i];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of bard_rnea_vjp_noalloc: the per-workgroup inertial-parameter sums
+// live in this file-scope array (one copy per GPU, held until the process
+// ends) instead of a buffer the library allocates.  Host code reaches it only
+// through the device address hipGetSymbolAddress returns for the current
+// device; the array's name in host code is not a device address.
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+hipError_t noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static double* addr[BARD_MAX_DEVICES] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= BARD_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 // Fixed-order batch reduction of the per-workgroup inertial-parameter sums.

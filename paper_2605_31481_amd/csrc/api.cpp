@@ -430,12 +430,9 @@ int run_aba(bard_model* m, Args<Real> ar, hipStream_t st) {
   return BARD_OK;
 }
 
-// Most workgroups of an RNEA adjoint launch that returns the inertial-parameter
-// gradient: each loops over tiles and keeps its own FP64 sums, so the batch
-// reduction is two fixed-order stages and its buffer is bounded by the model.
-// The grid depends only on the batch, the tile and the device, so results
-// are identical run to run on one GPU model.
-constexpr int kAdjGroups = 2048;
+// The adjoint grid (at most kAdjGroups workgroups when the inertial-parameter
+// gradient is returned) depends only on the batch, the tile and the device,
+// so results are identical run to run on one GPU model.
 
 int ensure_adj_partial(bard_model* m, DeviceCopy* dc, hipStream_t st) {
   std::lock_guard<std::mutex> lk(m->mu);
@@ -448,10 +445,27 @@ int ensure_adj_partial(bard_model* m, DeviceCopy* dc, hipStream_t st) {
   return BARD_OK;
 }
 
+// The model's device copy on the current device if it has been uploaded
+// (by an earlier call or bard_model_upload); BARD_E_STATE otherwise.
+int uploaded_copy(bard_model* m, DeviceCopy** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BARD_E_DEVICE, "hipGetDevice failed (no GPU?)");
+  if (dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "device index out of range");
+  DeviceCopy& dc = m->dev[dev];
+  if (!dc.ready)
+    return fail(BARD_E_STATE, "the model's tables are not on the current device: call bard_model_upload (or any "
+                              "operator) with this device current first");
+  *out = &dc;
+  return BARD_OK;
+}
+
+// noalloc: the model must already be on the device and the per-workgroup
+// inertial-parameter sums go to the file-scope scratch array; nothing is
+// allocated.
 template <class Real, bool RNEA>
-int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t st) {
+int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t st, bool noalloc = false) {
   DeviceCopy* dc = nullptr;
-  int rc = ensure_device(m, &dc, st);
+  int rc = noalloc ? uploaded_copy(m, &dc) : ensure_device(m, &dc, st);
   if (rc) return rc;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -474,9 +488,20 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
     return fail(BARD_E_DEVICE, "occupancy query failed");
   int64_t grid = std::min<int64_t>(ar.ntiles, (int64_t)std::max(per_cu, 1) * std::max(cus, 1));
   if (RNEA && inertia_bar) {
-    if ((rc = ensure_adj_partial(m, dc, st))) return rc;
-    ar.partial = dc->adj_partial;
     grid = std::min<int64_t>(grid, kAdjGroups);
+    if (noalloc) {
+      if (grid * m->n * 10 > kNoAllocScratchDoubles)
+        return fail(BARD_E_CAPACITY, "inertial-parameter sums exceed the scratch array");
+      double* p = nullptr;
+      if (noalloc_scratch(&p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(BARD_E_DEVICE, "device address of the scratch array not available");
+      }
+      ar.partial = p;
+    } else {
+      if ((rc = ensure_adj_partial(m, dc, st))) return rc;
+      ar.partial = dc->adj_partial;
+    }
   }
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   hipError_t e = launch_adjoint<Real, RNEA>(dc->dm, ar, (int)grid, waves * 64, lds, st);
@@ -500,6 +525,7 @@ const char* bard_status_str(int s) {
     case BARD_E_CAPACITY: return "BARD_E_CAPACITY";
     case BARD_E_UNSUPPORTED: return "BARD_E_UNSUPPORTED";
     case BARD_E_CAPTURE: return "BARD_E_CAPTURE";
+    case BARD_E_STATE: return "BARD_E_STATE";
     default: return "BARD_E_UNKNOWN";
   }
 }
@@ -868,9 +894,10 @@ int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, co
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
-int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
-                  const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar, void* qdd_bar,
-                  void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
+static int rnea_vjp_impl(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                         const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar,
+                         void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B, void* stream,
+                         bool noalloc) {
   int rc = common_checks(m, nullptr, dtype, B);
   if (rc) return rc;
   if (B == 0) return BARD_OK;
@@ -895,9 +922,23 @@ int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* q
         !layout_of(L, 4, B, m->nq, &a.sqo_b, &a.sqo_k) || !layout_of(L, 5, B, m->nv, &a.sqdo_b, &a.sqdo_k) ||
         !layout_of(L, 6, B, m->nv, &a.sqddo_b, &a.sqddo_k))
       return fail(BARD_E_ARG, "bad layout stride");
-    return run_adjoint<R, true>(m, a, (R*)inertia_bar, (hipStream_t)stream);
+    return run_adjoint<R, true>(m, a, (R*)inertia_bar, (hipStream_t)stream, noalloc);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
+int bard_rnea_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                  const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar, void* qdd_bar,
+                  void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
+  return rnea_vjp_impl(m, dtype, q, qd, qdd, inertia_override, tau_bar, q_bar, qd_bar, qdd_bar, inertia_bar, L, B,
+                       stream, false);
+}
+
+int bard_rnea_vjp_noalloc(bard_model_t m, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
+                          const void* inertia_override, const void* tau_bar, void* q_bar, void* qd_bar,
+                          void* qdd_bar, void* inertia_bar, const bard_layout* L, int64_t B, void* stream) {
+  return rnea_vjp_impl(m, dtype, q, qd, qdd, inertia_override, tau_bar, q_bar, qd_bar, qdd_bar, inertia_bar, L, B,
+                       stream, true);
 }
 
 int bard_fk_vjp(bard_model_t m, bard_dtype dtype, const void* q, const void* poses_bar, void* q_bar,

@@ -282,4 +282,16 @@ hipError_t adjoint_resident(int logT, int free_root, int block, size_t lds, int*
 template <class Real>
 hipError_t launch_param_reduce(const double* partial, int groups, int count, Real* out, hipStream_t st);
 
+// Most workgroups of an RNEA adjoint launch that returns the inertial-parameter
+// gradient: each loops over tiles and keeps its own FP64 sums, so the batch
+// reduction is two fixed-order stages and its buffer is bounded by the model.
+constexpr int kAdjGroups = 2048;
+// Values of the file-scope scratch array that holds those sums for the
+// entry point that allocates nothing: enough for kAdjGroups workgroups of a
+// model of BARD_MAX_BODIES bodies (10 MiB per GPU).
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)kAdjGroups * BARD_MAX_BODIES * 10;
+// Device address of that array on the current device, looked up once per
+// device (with the device current) and kept; never the array's own name.
+hipError_t noalloc_scratch(double** out);
+
 }  // namespace bard
