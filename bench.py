@@ -208,10 +208,10 @@ def bench_sweep(torch, bard, m, tree, bpe):
     return out
 
 
-# FP32 VALU peaks: 256 CU x 4 SIMD x 16 lanes x 2 FLOP per FMA x 2.4 GHz unpacked (the
-# build turns packed FP32 instructions off), twice that packed
-VALU_PEAK_FP32 = 78.6e12
-VALU_PEAK_FP32_PACKED = 157.3e12
+# FP32 vector peak of the spec sheet, 157.3 TFLOP/s (256 CU x 2.4 GHz x 256 FLOP per
+# CU per clock).  Plain (unpacked) FMAs reach it: the peak probe measures
+# 122-131 TFLOP/s with packed FP32 instructions off, as the library builds.
+VALU_PEAK_FP32 = 157.3e12
 
 
 def op_work(tree, n_ee, op):
@@ -297,6 +297,85 @@ def bench_operators(torch, bard):
     out["nv23_B16384_graph_replay_evals_per_s"] = B / time_graph(torch, mk, 20)
     del sets, calls, plain
     torch.cuda.empty_cache()
+    return out
+
+
+def measure_peaks(torch):
+    """The peaks the roofline fractions are taken against, measured on this
+    GPU: FP32 VALU FMA throughput from the peak probe (eight independent FMA
+    chains per lane, packed FP32 off as in the library) and HBM bandwidth of a
+    1 GiB device-to-device copy (bytes read + written)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_31481_amd", "libbard_peaks.so"))
+    lib.bard_peak_fma_fp32.restype = ctypes.c_double
+    lib.bard_peak_fma_fp32.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    blocks, iters = 256 * 32, 256
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    flops = lib.bard_peak_fma_fp32(ctypes.c_void_p(out.data_ptr()), blocks, iters, stream)
+    if flops < 0:
+        raise RuntimeError("peak probe launch failed")
+    best = 0.0
+    for _ in range(5):
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record()
+        lib.bard_peak_fma_fp32(ctypes.c_void_p(out.data_ptr()), blocks, iters, stream)
+        en.record()
+        torch.cuda.synchronize()
+        best = max(best, flops / (st.elapsed_time(en) * 1e-3))
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    bw = 0.0
+    for _ in range(5):
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record()
+        dst.copy_(src)
+        en.record()
+        torch.cuda.synchronize()
+        bw = max(bw, 2 * src.numel() * 4 / (st.elapsed_time(en) * 1e-3))
+    del src, dst, out
+    torch.cuda.empty_cache()
+    return {"peak_fp32_fma_tflops_measured": best / 1e12, "peak_fp32_vector_tflops_spec": VALU_PEAK_FP32 / 1e12,
+            "peak_hbm_copy_gbs_measured": bw / 1e9, "peak_hbm_gbs_spec": HBM_PEAK_GBS}
+
+
+def bench_specialized(torch, bard):
+    """Model-specialised chain kernels (hipRTC, one lane per instance,
+    constants as literals) against the generic kernel: the 36-DOF and 23-DOF
+    humanoids and the 7-DOF chain at B = 4096 .. 262,144, rotating sets past
+    512 MB; then the batch from which bard_chain_autotune routes calls to the
+    specialised kernel."""
+    import synth
+    out = {}
+    for name, batches in (("humanoid_large", (4096, 16384, 65536, 262144)), ("humanoid_small", (4096, 16384, 65536)),
+                          ("chain7", (4096, 16384, 65536))):
+        tree = synth.tree_by_name(name)
+        m = bard.Model.from_tree(tree)
+        ee = tree.ee_bodies
+        bpe = chain_bytes_per_eval(tree, len(ee))
+        m.specialize(ee, route=False)
+        info = m.specialized_info(ee)
+        out[f"spec_{name}_compile_s"] = info["compile_s"]
+        out[f"spec_{name}_vgprs"] = info["vgprs"]
+        out[f"spec_{name}_scratch_bytes"] = info["scratch_bytes"]
+        for B in batches:
+            nsets = max(2, min(64, math.ceil(512e6 / (bpe * B))))
+            sets = make_sets(torch, tree, B, nsets, 13000 + B)
+            calls = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
+            n = max(30, min(400, 2_000_000 // B))
+            m.specialize(ee, route=False)
+            _, kg = time_calls(torch, calls, n, 5)
+            m.specialize(ee, route=True)
+            _, ks = time_calls(torch, calls, n, 5)
+            key = f"spec_{name}_B{B}"
+            out[key + "_generic_us"] = kg * 1e3
+            out[key + "_specialized_us"] = ks * 1e3
+            out[key + "_specialized_evals_per_s"] = B / (ks * 1e-3)
+            out[key + "_specialized_hbm_frac"] = bpe * B / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS
+            del sets, calls
+            torch.cuda.empty_cache()
+        out[f"spec_{name}_autotuned_min_batch"] = m.autotune_chain(ee)
     return out
 
 
@@ -469,6 +548,9 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of the extras to run (chainforms, peaks, ops, sweep, specialized, "
+                         "plan, adjoints, workspace, sysid), e.g. for a profile of one group")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB (a kernel of known traffic "
                          "that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -510,7 +592,9 @@ def main():
     log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us")
 
     extra = {}
-    if not args.no_extra:
+    only = set(x for x in args.only.split(",") if x)
+    want = lambda k: not args.no_extra and (not only or k in only)
+    if want("chainforms"):
         # plain per-operator kernels (three launches) on the same sets
         plain = []
         for (d, o, _) in sets:
@@ -559,11 +643,21 @@ def main():
         extra["nv23_tree_evals_per_s"] = B * args.steps / w3
         extra["nv23_tree_kernel_us"] = k3 * 1e3
         del sets3, calls3
+    if want("peaks"):
+        extra.update(measure_peaks(torch))
+    if want("ops"):
         extra.update(bench_operators(torch, bard))
+    if want("sweep"):
         extra.update(bench_sweep(torch, bard, m, tree, bpe))
+    if want("specialized"):
+        extra.update(bench_specialized(torch, bard))
+    if want("plan"):
         extra.update(bench_plan(torch, bard, args.steps))
+    if want("adjoints"):
         extra.update(bench_adjoints(torch, bard, args.steps))
+    if want("workspace"):
         extra.update(bench_workspace(torch, bard, args.steps))
+    if extra:
         log(f"[bench] extra {extra}")
 
     # The oracle leg: the FP64 oracle's throughput on a bounded sample (the
@@ -575,7 +669,7 @@ def main():
         log(f"[bench] parity {parity}")
         cpu = cpu_baseline(tree)
         log(f"[bench] cpu baseline {cpu}")
-        if not args.no_extra:
+        if want("sysid"):
             extra.update(bench_sysid(torch, bard, sysid_reference_torques()))
             log(f"[bench] sysid {dict((k, v) for k, v in extra.items() if k.startswith('sysid'))}")
 

@@ -44,6 +44,7 @@ WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
 E_STATE = -9  # bard_status of a call that allocates nothing and found the model not uploaded
 UPLOAD_ADJOINT = 1
+SPEC_ROUTE, SPEC_COMPILE_ONLY = 1, 2
 # workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own
 # (see Workspace)
 TIER_KINEMATICS, TIER_MASS, TIER_BIAS, TIER_RESULTS = 1, 2, 4, 8
@@ -80,6 +81,15 @@ bard_model_schedule = _sig("bard_model_schedule", [_vp, _c_i32p, _c_i32p])
 bard_model_joint_transform = _sig("bard_model_joint_transform", [_vp, _i32, _c_dp, _c_dp, _c_dp])
 bard_model_destroy = _sig("bard_model_destroy", [_vp])
 bard_model_upload = _sig("bard_model_upload", [_vp, _i32, _c_i32p, _i32])
+bard_model_specialize = _sig("bard_model_specialize", [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32])
+bard_model_specialized_info = _sig("bard_model_specialized_info",
+                                   [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _c_i32p, _c_i32p,
+                                    ctypes.POINTER(ctypes.c_double), _c_i32p])
+bard_model_specialized_source = _sig("bard_model_specialized_source",
+                                     [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, ctypes.c_char_p, _i64,
+                                      ctypes.POINTER(_i64)])
+bard_chain_autotune = _sig("bard_chain_autotune", [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _vp,
+                                                   ctypes.POINTER(_i64)])
 bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
 bard_ws_destroy = _sig("bard_ws_destroy", [_vp])
 bard_ws_set_policy = _sig("bard_ws_set_policy", [_vp, _i32])
@@ -414,6 +424,60 @@ class Model:
         else:
             ee_a, pee, n = None, None, 0
         _check(bard_model_upload(self._h, n, pee, UPLOAD_ADJOINT if adjoint else 0), "bard_model_upload")
+
+    def specialize(self, ee: Sequence[int], frame: int = WORLD, dtype=None, route: bool = True,
+                   compile_only: bool = False):
+        """Compile the model-specialised chain kernel for (dtype, ee, frame)
+        with hipRTC and load it on the current device; with route=True,
+        matching chain() calls use it (bard_model_specialize)."""
+        ee_a, pee = _i32arr(ee)
+        flags = (SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0)
+        _check(bard_model_specialize(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), flags),
+               "bard_model_specialize")
+
+    def autotune_chain(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> int:
+        """Time the generic and the specialised chain kernels (bard_chain_autotune)
+        and route chain calls from the returned batch size up to the specialised
+        one (-1: never)."""
+        torch = _torch()
+        ee_a, pee = _i32arr(ee)
+        mb = _i64()
+        _check(bard_chain_autotune(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame),
+                                   _vp(torch.cuda.current_stream().cuda_stream), ctypes.byref(mb)),
+               "bard_chain_autotune")
+        return mb.value
+
+    def specialized_info(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> dict:
+        ee_a, pee = _i32arr(ee)
+        vg, sc, rt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cs = ctypes.c_double()
+        _check(bard_model_specialized_info(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame),
+                                           ctypes.byref(vg), ctypes.byref(sc), ctypes.byref(cs), ctypes.byref(rt)),
+               "bard_model_specialized_info")
+        return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value)}
+
+    def specialized_source(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> str:
+        ee_a, pee = _i32arr(ee)
+        n = _i64()
+        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), None, 0,
+                                             ctypes.byref(n)), "bard_model_specialized_source")
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), buf,
+                                             n.value + 1, ctypes.byref(n)), "bard_model_specialized_source")
+        return buf.value.decode()
+
+    @staticmethod
+    def _dtype_arg(dtype) -> int:
+        if dtype is None:
+            return F32
+        if isinstance(dtype, int):
+            return dtype
+        name = str(dtype)
+        if name.endswith("float32"):
+            return F32
+        if name.endswith("float64"):
+            return F64
+        raise ValueError(f"dtype must be float32 or float64, got {dtype}")
 
     def joint_transform(self, body: int, q):
         qa, pq = _f64arr(q)

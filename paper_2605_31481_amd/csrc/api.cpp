@@ -510,6 +510,25 @@ int run_adjoint(bard_model* m, AdjArgs<Real> ar, Real* inertia_bar, hipStream_t 
   return BARD_OK;
 }
 
+// Mean time of `reps` launches after 2 warm-ups, from an event pair on `st`.
+template <class F>
+int time_launches(F launch, hipStream_t st, int reps, double* us) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(BARD_E_DEVICE, "event");
+  int rc = BARD_OK;
+  for (int k = 0; k < 2 && !rc; ++k) rc = launch();
+  if (!rc && hipEventRecord(a, st) != hipSuccess) rc = fail(BARD_E_DEVICE, "event record");
+  for (int k = 0; k < reps && !rc; ++k) rc = launch();
+  if (!rc && hipEventRecord(b, st) != hipSuccess) rc = fail(BARD_E_DEVICE, "event record");
+  float ms = 0.0f;
+  if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+    rc = fail(BARD_E_DEVICE, "event timing");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *us = 1e3 * ms / reps;
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -647,9 +666,170 @@ int bard_model_destroy(bard_model_t m) {
     (void)hipFree(dc.blob);
     for (auto& kv : dc.ee_sets) (void)hipFree(kv.second.first);
     if (dc.adj_partial) (void)hipFree(dc.adj_partial);
+    for (auto& kv : dc.spec)
+      if (kv.second.mod) (void)hipModuleUnload((hipModule_t)kv.second.mod);
   }
   if (cur >= 0) (void)hipSetDevice(cur);
   delete m;
+  return BARD_OK;
+}
+
+static int spec_args(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
+                     std::vector<int>* ee) {
+  if (!m) return fail(BARD_E_ARG, "model is NULL");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
+  if (frame != BARD_WORLD && frame != BARD_LOCAL_WORLD_ALIGNED) return fail(BARD_E_ARG, "bad frame");
+  if (n_ee < 1 || n_ee > BARD_MAX_EE || !ee_body) return fail(BARD_E_ARG, "n_ee must be in 1..16 with ee_body");
+  ee->assign(ee_body, ee_body + n_ee);
+  for (int e : *ee)
+    if (e < 0 || e >= m->n) return fail(BARD_E_ARG, "end-effector body out of range");
+  return BARD_OK;
+}
+
+int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
+                          int32_t flags) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  if (rc) return rc;
+  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY)) return fail(BARD_E_ARG, "unknown flags");
+  // The generated code grows with the ancestor walks of the mass-matrix
+  // columns (one step per dof and ancestor body); past this size the compile
+  // time and register pressure outgrow what specialisation gains.
+  int steps = 0;
+  for (int i = 0; i < m->n; ++i)
+    for (int k = m->parent[i]; k >= 0; k = m->parent[k]) steps += m->nvi[i];
+  if (m->depth > kSpecMaxDepth || steps > kSpecMaxWalkSteps)
+    return fail(BARD_E_UNSUPPORTED, "tree too deep for a specialised kernel (depth " + std::to_string(m->depth) +
+                                        ", " + std::to_string(steps) + " ancestor-walk steps); the generic kernel "
+                                        "serves it");
+  if (flags & BARD_SPEC_COMPILE_ONLY) {
+    std::vector<char> code;
+    std::string log;
+    rc = spec_compile(spec_chain_source(m, ee, (int)frame, dtype == BARD_F64), &code, &log);
+    return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
+  }
+  if ((rc = check_device_state())) return rc;
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, nullptr))) return rc;
+  SpecKernel* sk = nullptr;
+  if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, true, &sk))) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  sk->route = (flags & BARD_SPEC_ROUTE) != 0;
+  sk->route_min_batch = 0;
+  bool any = false;
+  for (const auto& d : m->dev)
+    for (const auto& kv : d.spec) any = any || kv.second.route;
+  m->spec_route.store(any);
+  return BARD_OK;
+}
+
+int bard_model_specialized_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
+                                bard_frame frame, int32_t* vgprs, int32_t* scratch_bytes, double* compile_seconds,
+                                int32_t* routed) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  if (rc) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
+  const std::string key = spec_key((int)dtype, (int)frame, ee);
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = m->dev[dev].spec.find(key);
+  if (it == m->dev[dev].spec.end() || !it->second.fn)
+    return fail(BARD_E_STATE, "no specialised kernel for these arguments on the current device");
+  if (vgprs) *vgprs = it->second.vgprs;
+  if (scratch_bytes) *scratch_bytes = it->second.scratch;
+  if (compile_seconds) *compile_seconds = it->second.compile_s;
+  if (routed) *routed = it->second.route ? 1 : 0;
+  return BARD_OK;
+}
+
+int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
+                        void* stream, int64_t* min_batch) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  if (rc) return rc;
+  if ((rc = check_device_state())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (capturing(st)) return fail(BARD_E_CAPTURE, "autotuning allocates and synchronises; not under capture");
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, st))) return rc;
+  SpecKernel* sk = nullptr;
+  if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, true, &sk))) return rc;
+  // Scratch arrays for the largest batch tried, inputs filled with 0.1 (the
+  // kernels have no data-dependent branches at these values).
+  const int64_t kBatches[4] = {1024, 4096, 16384, 65536};
+  const int64_t Bmax = kBatches[3];
+  const size_t rs = dtype == BARD_F64 ? 8 : 4;
+  const int64_t nin = (int64_t)m->nq + 2 * m->nv, nout = (int64_t)m->nv + (int64_t)m->nv * m->nv + 6LL * m->nv * n_ee;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, (size_t)(nin + nout) * Bmax * rs) != hipSuccess)
+    return fail(BARD_E_NOMEM, "hipMalloc of the autotuning arrays failed");
+  {
+    std::vector<unsigned char> host((size_t)nin * Bmax * rs);
+    for (int64_t k = 0; k < nin * Bmax; ++k) {
+      if (dtype == BARD_F64) reinterpret_cast<double*>(host.data())[k] = 0.1;
+      else reinterpret_cast<float*>(host.data())[k] = 0.1f;
+    }
+    if (hipMemcpy(buf, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(buf);
+      return fail(BARD_E_DEVICE, "upload of the autotuning inputs failed");
+    }
+  }
+  int64_t chosen = INT64_MAX;
+  double t_gen[4] = {0}, t_spec[4] = {0};
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    for (int k = 0; k < 4; ++k) {
+      const int64_t B = kBatches[k];
+      R* base = (R*)buf;
+      Args<R> a = blank_args<R>(B);
+      a.q = base;
+      a.qd = base + m->nq * B;
+      a.qdd = base + (int64_t)(m->nq + m->nv) * B;
+      a.tau = base + nin * Bmax;
+      a.M = a.tau + (int64_t)m->nv * B;
+      a.J = a.M + (int64_t)m->nv * m->nv * B;
+      a.sq_b = a.sqd_b = a.sqdd_b = a.st_b = a.sM_b = a.sJ_b = 1;
+      a.sq_k = a.sqd_k = a.sqdd_k = a.st_k = a.sM_k = a.sJ_k = B;
+      const int reps = B >= 16384 ? 5 : 20;
+      int r = time_launches([&] { return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, st); },
+                            st, reps, &t_gen[k]);
+      if (!r) r = time_launches([&] { return spec_launch<R>(sk, a, m->g, st); }, st, reps, &t_spec[k]);
+      if (r) return r;
+    }
+    return BARD_OK;
+  };
+  rc = dtype == BARD_F32 ? go(0.0f) : go(0.0);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(buf);
+  if (rc) return rc;
+  // the smallest tried batch from which the specialised kernel is faster at every larger one
+  for (int k = 3; k >= 0 && t_spec[k] < t_gen[k]; --k) chosen = kBatches[k];
+  {
+    std::lock_guard<std::mutex> lk(m->mu);
+    sk->route = chosen != INT64_MAX;
+    sk->route_min_batch = chosen;
+    bool any = false;
+    for (const auto& d : m->dev)
+      for (const auto& kv : d.spec) any = any || kv.second.route;
+    m->spec_route.store(any);
+  }
+  if (min_batch) *min_batch = chosen == INT64_MAX ? -1 : chosen;
+  return BARD_OK;
+}
+
+int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
+                                  bard_frame frame, char* buf, int64_t cap, int64_t* len) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  if (rc) return rc;
+  const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64);
+  if (len) *len = (int64_t)src.size();
+  if (buf && cap > 0) {
+    const size_t k = std::min<size_t>((size_t)cap - 1, src.size());
+    std::memcpy(buf, src.data(), k);
+    buf[k] = 0;
+  }
   return BARD_OK;
 }
 
@@ -889,6 +1069,12 @@ int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, co
         !layout_of(L, 4, B, m->nv * m->nv, &a.sM_b, &a.sM_k) ||
         !layout_of(L, 5, B, 6 * m->nv * n_ee, &a.sJ_b, &a.sJ_k))
       return fail(BARD_E_ARG, "bad layout stride");
+    if (m->spec_route.load()) {
+      DeviceCopy* dc = nullptr;
+      if ((rc = ensure_device(m, &dc, (hipStream_t)stream))) return rc;
+      if (SpecKernel* sk = spec_lookup(m, dc, (int)dtype, (int)frame, n_ee, ee_body, B))
+        return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
+    }
     return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);

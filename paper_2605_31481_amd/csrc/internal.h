@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "launch.h"
 #include "status.h"
@@ -25,5 +26,26 @@ int ensure_device(bard_model* m, DeviceCopy** out, hipStream_t st);
 int ensure_ee(bard_model* m, DeviceCopy* dc, int n_ee, const int32_t* ee_body, DevEE* out, hipStream_t st);
 // Waves per workgroup for the phases after the level sweep (rs: scalar bytes).
 int out_waves(int rs);
+
+// Largest trees the specialiser takes: depth, and dofs times ancestor bodies
+// summed over the tree (the mass-matrix walks of the generated code).
+constexpr int kSpecMaxDepth = 32;
+constexpr int kSpecMaxWalkSteps = 1500;
+// Model-specialised chain kernels (specialize.cpp).  Key of one (precision,
+// frame, end-effector set) in DeviceCopy::spec.
+std::string spec_key(int dtype, int frame, const std::vector<int>& ee);
+// Source text of the kernel for one (end-effector set, frame, precision).
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64);
+// Compile source to a gfx950 code object with hipRTC (no device needed).
+int spec_compile(const std::string& src, std::vector<char>* code, std::string* log);
+// Compile (once) and, if `load`, load on the device of `dc`; *out points into dc->spec.
+int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, bool load,
+                 SpecKernel** out);
+// The routed specialised kernel for a chain call of batch B, or null.
+SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int n_ee, const int32_t* ee,
+                        int64_t B);
+// Launch a specialised chain kernel with a chain call's arguments.
+template <class Real>
+int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st);
 
 }  // namespace bard

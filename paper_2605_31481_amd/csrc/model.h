@@ -60,12 +60,26 @@ struct DevEE {
   int n_col, n_zero;
 };
 
+// A model-specialised chain kernel (hipRTC): code object, module and function
+// handles on one device (void* so this header stays free of HIP types), its
+// resources, and whether matching chain calls go to it.
+struct SpecKernel {
+  std::vector<char> code;
+  void* mod = nullptr;  // hipModule_t
+  void* fn = nullptr;   // hipFunction_t
+  int vgprs = 0, scratch = 0;
+  double compile_s = 0.0;
+  bool route = false;
+  int64_t route_min_batch = 0;  // routed chain calls need at least this batch
+};
+
 struct DeviceCopy {
   bool ready = false;
   void* blob = nullptr;
   DevModel dm{};
   std::map<std::vector<int>, std::pair<void*, DevEE>> ee_sets;
   double* adj_partial = nullptr;  // per-workgroup inertial-parameter sums of the RNEA adjoint
+  std::map<std::string, SpecKernel> spec;  // by (dtype, frame, end-effector set)
 };
 
 }  // namespace bard
@@ -91,6 +105,7 @@ struct bard_model {
   int n_mpair = 0, n_mzero = 0;
   std::vector<std::vector<int>> children;
   bard::DeviceCopy dev[BARD_MAX_DEVICES];
+  std::atomic<bool> spec_route{false};  // some specialised kernel takes chain calls
   std::mutex mu;
 };
 

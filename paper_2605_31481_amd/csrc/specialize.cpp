@@ -1,0 +1,500 @@
+// Model-specialised chain kernels: the model compiler writes HIP source for one
+// tree -- RNEA, CRBA and the end-effector Jacobians fused, every model
+// constant a literal, the traversal unrolled body by body -- and compiles it
+// at run time with hipRTC.
+//
+// Mapping.  One lane per instance, all lanes of a wave at the same body at the
+// same time, so every constant is wave-uniform and folds into the
+// instructions; no tables are staged, no lanes exchange state and no barrier
+// separates levels.  The code walks the tree depth first: entering a body it
+// composes the joint transform (eqs. (4)-(5)), the world pose, the axis and
+// the velocity and acceleration; leaving it (after its children) it forms the
+// subtree force and composite inertia, the torque, the mass-matrix column
+// and, walking up the ancestors, the entries that couple it to them.  Every
+// index is known when the code is written, so ancestors' state stays in
+// registers.
+//
+// Frames.  Motion and force vectors are kept about each body's own origin
+// with world axes: a child's state is its parent's moved by the link offset
+// r = R_parent t_pc (a translation-only transform), forces and composite
+// inertias move back up by the same offsets.  Only relative positions enter
+// the dynamics, so no quantity grows with the distance from the base.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace bard {
+
+namespace {
+
+const char kSpatialHeader[] =
+#include "spatial_h.inc"
+    ;
+
+// Emits the source text of one specialised chain kernel.
+class Emitter {
+ public:
+  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64)
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64) {}
+
+  std::string source() {
+    o_ << "// generated: fused RNEA + CRBA + Jacobian for one tree (" << m_->n << " bodies, nv " << m_->nv
+       << ", " << ee_.size() << " end effectors, frame " << frame_ << ", " << (fp64_ ? "FP64" : "FP32")
+       << ")\n#include \"spatial.h\"\n";
+    o_ << "typedef " << (fp64_ ? "double" : "float") << " Real;\n";
+    o_ << "extern \"C\" __global__ void __launch_bounds__(64) bard_spec_chain(\n"
+          "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ qdd,\n"
+          "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
+          "    long long sq_b, long long sq_k, long long sqd_b, long long sqd_k, long long sqdd_b, long long sqdd_k,\n"
+          "    long long st_b, long long st_k, long long sM_b, long long sM_k, long long sJ_b, long long sJ_k,\n"
+          "    long long B, Real g0, Real g1, Real g2) {\n"
+          "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
+          "  if (b >= B) return;\n"
+          "  const Real* qb = q + b * sq_b;\n  const Real* qdb = qd + b * sqd_b;\n"
+          "  const Real* qddb = qdd + b * sqdd_b;\n  Real* tb = tau + b * st_b;\n"
+          "  Real* Mb = M + b * sM_b;\n  Real* Jb = J + b * sJ_b;\n";
+    emit_zero_stores();
+    for (int i = 0; i < m_->n; ++i)
+      if (m_->parent[i] < 0) visit(i);
+    o_ << "}\n";
+    return o_.str();
+  }
+
+ private:
+  const bard_model* m_;
+  std::vector<int> ee_;
+  int frame_;
+  bool fp64_;
+  std::ostringstream o_;
+
+  double c(int body, int k) const { return fp64_ ? m_->cst64[body * CST + k] : (double)m_->cst32[body * CST + k]; }
+  std::string lit(double x) const {
+    char buf[64];
+    if (fp64_) std::snprintf(buf, sizeof buf, "%.17g", x);
+    else std::snprintf(buf, sizeof buf, "%.9g", x);
+    std::string s(buf);
+    if (s.find_first_of(".eEn") == std::string::npos) s += ".0";
+    if (!fp64_) s += "f";
+    return "Real(" + s + ")";
+  }
+  static std::string v(const char* name, int body) { return std::string(name) + std::to_string(body); }
+
+  // sum of terms coef * factor, omitting exact zeros (x + 0 y = x exactly)
+  std::string lin(const std::vector<std::pair<double, std::string>>& t) const {
+    std::string s;
+    for (const auto& [coef, f] : t) {
+      if (coef == 0.0) continue;
+      std::string term = f.empty() ? lit(coef) : (coef == 1.0 ? f : lit(coef) + " * " + f);
+      s += s.empty() ? term : " + " + term;
+    }
+    return s.empty() ? "Real(0)" : s;
+  }
+
+  void emit_zero_stores() {
+    // mass-matrix entries of unrelated dofs and Jacobian rows of dofs off an
+    // end effector's root path are zero for every configuration
+    const int nv = m_->nv;
+    std::vector<int> zm, zj;
+    std::vector<int> body_of(nv);
+    for (int i = 0; i < m_->n; ++i)
+      for (int d = 0; d < m_->nvi[i]; ++d) body_of[m_->vi[i] + d] = i;
+    auto related = [&](int a, int bb) {
+      for (int k = a; k >= 0; k = m_->parent[k])
+        if (k == bb) return true;
+      for (int k = bb; k >= 0; k = m_->parent[k])
+        if (k == a) return true;
+      return false;
+    };
+    for (int r = 0; r < nv; ++r)
+      for (int col = 0; col < nv; ++col)
+        if (!related(body_of[r], body_of[col])) zm.push_back(r * nv + col);
+    for (size_t e = 0; e < ee_.size(); ++e) {
+      std::vector<char> on(nv, 0);
+      for (int k = ee_[e]; k >= 0; k = m_->parent[k])
+        for (int d = 0; d < m_->nvi[k]; ++d) on[m_->vi[k] + d] = 1;
+      for (int r = 0; r < 6; ++r)
+        for (int col = 0; col < nv; ++col)
+          if (!on[col]) zj.push_back(((int)e * 6 + r) * nv + col);
+    }
+    auto table = [&](const char* name, const std::vector<int>& z, const char* out, const char* stride) {
+      if (z.empty()) return;
+      o_ << "  {\n    static constexpr int " << name << "[" << z.size() << "] = {";
+      for (size_t i = 0; i < z.size(); ++i) o_ << (i ? "," : "") << z[i];
+      o_ << "};\n    for (int i = 0; i < " << z.size() << "; ++i) bard::put(&" << out << "[(long long)" << name
+         << "[i] * " << stride << "], Real(0), true);\n  }\n";
+    };
+    table("zm", zm, "Mb", "sM_k");
+    table("zj", zj, "Jb", "sJ_k");
+  }
+
+  // ---- entering body i: pose, axis, velocity, acceleration, body force ----
+  void forward(int i) {
+    const int p = m_->parent[i], t = m_->jtype[i], qi = m_->qi[i], vi = m_->vi[i];
+    o_ << "  // body " << i << " (" << (t == J_REV ? "revolute" : t == J_PRI ? "prismatic" : "free") << ", parent "
+       << p << ")\n";
+    o_ << "  Real " << v("R", i) << "[9], " << v("p", i) << "[3], " << v("r", i) << "[3], " << v("a", i) << "[3], "
+       << v("v", i) << "[6], " << v("c", i) << "[6], " << v("I", i) << "[10], " << v("f", i) << "[6];\n  {\n";
+    if (t == J_FREE) {
+      o_ << "    Real x_ = qb[" << qi + 3 << " * sq_k], y_ = qb[" << qi + 4 << " * sq_k], z_ = qb[" << qi + 5
+         << " * sq_k], w_ = qb[" << qi + 6 << " * sq_k];\n"
+            "    const Real n_ = Real(1) / sqrt(x_ * x_ + y_ * y_ + z_ * z_ + w_ * w_);\n"
+            "    x_ *= n_; y_ *= n_; z_ *= n_; w_ *= n_;\n"
+            "    const Real Rq[9] = {Real(1) - Real(2) * (y_ * y_ + z_ * z_), Real(2) * (x_ * y_ - z_ * w_),"
+            " Real(2) * (x_ * z_ + y_ * w_), Real(2) * (x_ * y_ + z_ * w_), Real(1) - Real(2) * (x_ * x_ + z_ * z_),"
+            " Real(2) * (y_ * z_ - x_ * w_), Real(2) * (x_ * z_ - y_ * w_), Real(2) * (y_ * z_ + x_ * w_),"
+            " Real(1) - Real(2) * (x_ * x_ + y_ * y_)};\n";
+      o_ << "    const Real P_[3] = {qb[" << qi << " * sq_k], qb[" << qi + 1 << " * sq_k], qb[" << qi + 2
+         << " * sq_k]};\n";
+      for (int r = 0; r < 3; ++r)
+        for (int col = 0; col < 3; ++col)
+          o_ << "    " << v("R", i) << "[" << 3 * r + col << "] = "
+             << lin({{c(i, C_R0 + 3 * r), "Rq[" + std::to_string(col) + "]"},
+                     {c(i, C_R0 + 3 * r + 1), "Rq[" + std::to_string(3 + col) + "]"},
+                     {c(i, C_R0 + 3 * r + 2), "Rq[" + std::to_string(6 + col) + "]"}})
+             << ";\n";
+      for (int r = 0; r < 3; ++r)
+        o_ << "    " << v("p", i) << "[" << r << "] = "
+           << lin({{c(i, C_R0 + 3 * r), "P_[0]"}, {c(i, C_R0 + 3 * r + 1), "P_[1]"}, {c(i, C_R0 + 3 * r + 2), "P_[2]"},
+                   {c(i, C_T0 + r), ""}})
+           << ";\n";
+      o_ << "    for (int k = 0; k < 3; ++k) " << v("r", i) << "[k] = " << v("p", i) << "[k];\n";
+      // velocity coordinates [v; w] in the body frame -> world axes at the body origin
+      o_ << "    Real vb_[3], wb_[3], ab_[3], wd_[3];\n";
+      for (int k = 0; k < 3; ++k)
+        o_ << "    vb_[" << k << "] = qdb[" << vi + k << " * sqd_k]; wb_[" << k << "] = qdb[" << vi + 3 + k
+           << " * sqd_k]; ab_[" << k << "] = qddb[" << vi + k << " * sqdd_k]; wd_[" << k << "] = qddb["
+           << vi + 3 + k << " * sqdd_k];\n";
+      const std::string R = v("R", i);
+      for (int r = 0; r < 3; ++r) {
+        auto row = [&](const char* x) {
+          return R + "[" + std::to_string(3 * r) + "] * " + x + "[0] + " + R + "[" + std::to_string(3 * r + 1) +
+                 "] * " + x + "[1] + " + R + "[" + std::to_string(3 * r + 2) + "] * " + x + "[2]";
+        };
+        o_ << "    " << v("v", i) << "[" << r << "] = " << row("wb_") << ";\n";
+        o_ << "    " << v("v", i) << "[" << 3 + r << "] = " << row("vb_") << ";\n";
+        o_ << "    " << v("c", i) << "[" << r << "] = " << row("wd_") << ";\n";
+        o_ << "    " << v("c", i) << "[" << 3 + r << "] = " << row("ab_") << " - g" << r << ";\n";
+      }
+    } else {
+      // joint transform (eqs. (4)-(5))
+      if (t == J_REV)
+        o_ << "    Real s_, c_;\n    bard::sincos_r(qb[" << qi << " * sq_k], &s_, &c_);\n"
+           << "    const Real o_ = Real(1) - c_;\n";
+      else
+        o_ << "    const Real x_ = qb[" << qi << " * sq_k];\n";
+      o_ << "    Real Rpc[9], tpc[3];\n";
+      for (int k = 0; k < 9; ++k)
+        o_ << "    Rpc[" << k << "] = "
+           << (t == J_REV ? lin({{c(i, C_R0 + k), ""}, {c(i, C_A + k), "s_"}, {c(i, C_B + k), "o_"}})
+                          : lin({{c(i, C_R0 + k), ""}}))
+           << ";\n";
+      for (int k = 0; k < 3; ++k)
+        o_ << "    tpc[" << k << "] = "
+           << (t == J_PRI ? lin({{c(i, C_T0 + k), ""}, {c(i, C_D + k), "x_"}}) : lin({{c(i, C_T0 + k), ""}}))
+           << ";\n";
+      // the joint axis in the parent frame: R0 axis (R0 = R_pre, the joint frame
+      // in the parent), taken in FP64 and rounded once by the literal
+      double d[3];
+      for (int k = 0; k < 3; ++k)
+        d[k] = m_->cst64[i * CST + C_R0 + 3 * k] * m_->cst64[i * CST + C_AX] +
+               m_->cst64[i * CST + C_R0 + 3 * k + 1] * m_->cst64[i * CST + C_AX + 1] +
+               m_->cst64[i * CST + C_R0 + 3 * k + 2] * m_->cst64[i * CST + C_AX + 2];
+      if (p < 0) {
+        o_ << "    for (int k = 0; k < 9; ++k) " << v("R", i) << "[k] = Rpc[k];\n";
+        o_ << "    for (int k = 0; k < 3; ++k) { " << v("r", i) << "[k] = tpc[k]; " << v("p", i)
+           << "[k] = tpc[k]; }\n";
+        for (int k = 0; k < 3; ++k) o_ << "    " << v("a", i) << "[" << k << "] = " << lit(d[k]) << ";\n";
+      } else {
+        const std::string Rp = v("R", p);
+        o_ << "    bard::mul33(" << Rp << ", Rpc, " << v("R", i) << ");\n";
+        for (int r = 0; r < 3; ++r) {
+          o_ << "    " << v("r", i) << "[" << r << "] = " << Rp << "[" << 3 * r << "] * tpc[0] + " << Rp << "["
+             << 3 * r + 1 << "] * tpc[1] + " << Rp << "[" << 3 * r + 2 << "] * tpc[2];\n";
+          o_ << "    " << v("p", i) << "[" << r << "] = " << v("p", p) << "[" << r << "] + " << v("r", i) << "[" << r
+             << "];\n";
+          o_ << "    " << v("a", i) << "[" << r << "] = "
+             << lin({{d[0], Rp + "[" + std::to_string(3 * r) + "]"}, {d[1], Rp + "[" + std::to_string(3 * r + 1) + "]"},
+                     {d[2], Rp + "[" + std::to_string(3 * r + 2) + "]"}})
+             << ";\n";
+        }
+      }
+      // parent state moved to this body's origin: u += w x r (velocity and spatial acceleration)
+      o_ << "    Real vs_[6], as_[6];\n";
+      if (p < 0) {
+        o_ << "    for (int k = 0; k < 6; ++k) vs_[k] = Real(0);\n"
+              "    as_[0] = Real(0); as_[1] = Real(0); as_[2] = Real(0); as_[3] = -g0; as_[4] = -g1; as_[5] = -g2;\n";
+      } else {
+        o_ << "    {\n      Real t_[3];\n      bard::cross3(" << v("v", p) << ", " << v("r", i) << ", t_);\n"
+           << "      for (int k = 0; k < 3; ++k) { vs_[k] = " << v("v", p) << "[k]; vs_[3 + k] = " << v("v", p)
+           << "[3 + k] + t_[k]; }\n      bard::cross3(" << v("c", p) << ", " << v("r", i) << ", t_);\n"
+           << "      for (int k = 0; k < 3; ++k) { as_[k] = " << v("c", p) << "[k]; as_[3 + k] = " << v("c", p)
+           << "[3 + k] + t_[k]; }\n    }\n";
+      }
+      o_ << "    const Real qd_ = qdb[" << vi << " * sqd_k], qdd_ = qddb[" << vi << " * sqdd_k];\n"
+         << "    Real sq_[3], t_[3];\n    for (int k = 0; k < 3; ++k) sq_[k] = " << v("a", i) << "[k] * qd_;\n";
+      const int off = (t == J_REV) ? 0 : 3;  // s = [a; 0] revolute, [0; a] prismatic
+      o_ << "    for (int k = 0; k < 6; ++k) " << v("v", i) << "[k] = vs_[k];\n"
+         << "    for (int k = 0; k < 3; ++k) " << v("v", i) << "[" << off << " + k] += sq_[k];\n"
+         << "    for (int k = 0; k < 6; ++k) " << v("c", i) << "[k] = as_[k];\n"
+         << "    for (int k = 0; k < 3; ++k) " << v("c", i) << "[" << off << " + k] += " << v("a", i)
+         << "[k] * qdd_;\n";
+      // v x (s qd): revolute [w x sq; u x sq], prismatic [0; w x sq]
+      if (t == J_REV)
+        o_ << "    bard::cross3(" << v("v", i) << ", sq_, t_);\n    for (int k = 0; k < 3; ++k) " << v("c", i)
+           << "[k] += t_[k];\n    bard::cross3(" << v("v", i) << " + 3, sq_, t_);\n    for (int k = 0; k < 3; ++k) "
+           << v("c", i) << "[3 + k] += t_[k];\n";
+      else
+        o_ << "    bard::cross3(" << v("v", i) << ", sq_, t_);\n    for (int k = 0; k < 3; ++k) " << v("c", i)
+           << "[3 + k] += t_[k];\n";
+    }
+    // body force about the body origin: f = I a + v x* I v
+    o_ << "    const Real pi_[10] = {";
+    for (int k = 0; k < 10; ++k) o_ << (k ? ", " : "") << lit(c(i, C_PI + k));
+    o_ << "};\n    bard::rotate_inertia(pi_, " << v("R", i) << ", " << v("I", i) << ");\n"
+       << "    Real Iv_[6], vIv_[6];\n    bard::inertia_mul(" << v("I", i) << ", " << v("v", i) << ", Iv_);\n"
+       << "    bard::crf(" << v("v", i) << ", Iv_, vIv_);\n    bard::inertia_mul(" << v("I", i) << ", " << v("c", i)
+       << ", " << v("f", i) << ");\n    for (int k = 0; k < 6; ++k) " << v("f", i) << "[k] += vIv_[k];\n  }\n";
+  }
+
+  // motion-subspace column d of body j about the body origin (world axes)
+  std::string s_col(int j, int d) const {
+    const int t = m_->jtype[j];
+    const std::string a = v("a", j), R = v("R", j);
+    auto z = [](int n) { std::string s; for (int k = 0; k < n; ++k) s += "Real(0), "; return s; };
+    if (t == J_REV) return "{" + a + "[0], " + a + "[1], " + a + "[2], Real(0), Real(0), Real(0)}";
+    if (t == J_PRI) return "{Real(0), Real(0), Real(0), " + a + "[0], " + a + "[1], " + a + "[2]}";
+    const int e = d % 3;
+    const std::string col = R + "[" + std::to_string(e) + "], " + R + "[" + std::to_string(3 + e) + "], " + R + "[" +
+                            std::to_string(6 + e) + "]";
+    return d < 3 ? "{" + z(3) + col + "}" : "{" + col + ", Real(0), Real(0), Real(0)}";
+  }
+
+  void store_M(int r, int col, const std::string& val) {
+    const int nv = m_->nv;
+    o_ << "    bard::put(&Mb[" << r * nv + col << " * sM_k], " << val << ", true);\n";
+    if (r != col) o_ << "    bard::put(&Mb[" << col * nv + r << " * sM_k], " << val << ", true);\n";
+  }
+
+  // ---- leaving body i: subtree force, torque, composite inertia, M ----
+  void backward(int i) {
+    const int t = m_->jtype[i], vi = m_->vi[i], nd = m_->nvi[i];
+    o_ << "  // body " << i << ": subtree sums\n  Real " << v("F", i) << "[6], " << v("K", i) << "[10];\n  {\n"
+       << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] = " << v("f", i) << "[k];\n"
+       << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] = " << v("I", i) << "[k];\n";
+    for (int ch : m_->children[i]) {
+      o_ << "    {\n      Real t_[3], S_[10];\n      bard::cross3(" << v("r", ch) << ", " << v("F", ch) << " + 3, t_);\n"
+         << "      for (int k = 0; k < 3; ++k) { " << v("F", i) << "[k] += " << v("F", ch) << "[k] + t_[k]; "
+         << v("F", i) << "[3 + k] += " << v("F", ch) << "[3 + k]; }\n      bard::shift_inertia(" << v("K", ch) << ", "
+         << v("r", ch) << ", S_);\n      for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += S_[k];\n    }\n";
+    }
+    // torque
+    const std::string F = v("F", i), a = v("a", i), R = v("R", i);
+    if (t == J_REV)
+      o_ << "    bard::put(&tb[" << vi << " * st_k], " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
+         << a << "[2] * " << F << "[2], true);\n";
+    else if (t == J_PRI)
+      o_ << "    bard::put(&tb[" << vi << " * st_k], " << a << "[0] * " << F << "[3] + " << a << "[1] * " << F << "[4] + "
+         << a << "[2] * " << F << "[5], true);\n";
+    else
+      for (int d = 0; d < 6; ++d) {
+        const int e = d % 3, base = d < 3 ? 3 : 0;  // [f; n] in the body frame: R^T f, R^T n
+        o_ << "    bard::put(&tb[" << vi + d << " * st_k], " << R << "[" << e << "] * " << F << "[" << base << "] + " << R
+           << "[" << 3 + e << "] * " << F << "[" << base + 1 << "] + " << R << "[" << 6 + e << "] * " << F << "["
+           << base + 2 << "], true);\n";
+      }
+    // mass-matrix columns of this body's dofs
+    for (int d = 0; d < nd; ++d) {
+      o_ << "    {\n      const Real s_[6] = " << s_col(i, d) << ";\n      Real fc_[6];\n      bard::inertia_mul("
+         << v("K", i) << ", s_, fc_);\n";
+      for (int d2 = 0; d2 <= d; ++d2) {
+        o_ << "      {\n        const Real u_[6] = " << s_col(i, d2) << ";\n";
+        o_ << "        const Real m_ = u_[0] * fc_[0] + u_[1] * fc_[1] + u_[2] * fc_[2] + u_[3] * fc_[3] + u_[4] * fc_[4]"
+              " + u_[5] * fc_[5];\n";
+        store_M(vi + d2, vi + d, "m_");
+        o_ << "      }\n";
+      }
+      // up the ancestors: the force moves to the parent's origin, n += r x f
+      int ch = i;
+      for (int j = m_->parent[i]; j >= 0; ch = j, j = m_->parent[j]) {
+        o_ << "      {\n        Real t_[3];\n        bard::cross3(" << v("r", ch) << ", fc_ + 3, t_);\n"
+           << "        for (int k = 0; k < 3; ++k) fc_[k] += t_[k];\n";
+        for (int e = 0; e < m_->nvi[j]; ++e) {
+          o_ << "        {\n          const Real u_[6] = " << s_col(j, e) << ";\n"
+             << "          const Real m_ = u_[0] * fc_[0] + u_[1] * fc_[1] + u_[2] * fc_[2] + u_[3] * fc_[3] + u_[4] *"
+                " fc_[4] + u_[5] * fc_[5];\n";
+          store_M(m_->vi[j] + e, vi + d, "m_");
+          o_ << "        }\n";
+        }
+        o_ << "      }\n";
+      }
+      o_ << "    }\n";
+    }
+    o_ << "  }\n";
+  }
+
+  // Jacobian columns of end effector e (rows [linear; angular]).
+  void jacobian(int ei) {
+    const int e = ee_[ei], nv = m_->nv;
+    o_ << "  // Jacobian of end effector " << ei << " (body " << e << ")\n  {\n";
+    for (int j = e; j >= 0; j = m_->parent[j]) {
+      const int t = m_->jtype[j];
+      for (int d = 0; d < m_->nvi[j]; ++d) {
+        const int col = m_->vi[j] + d;
+        o_ << "    {\n      const Real s_[6] = " << s_col(j, d) << ";\n      Real l_[3];\n";
+        // angular part w = s[0..2]; linear part: velocity of the chosen point
+        if (t == J_PRI || (t == J_FREE && d < 3)) {
+          o_ << "      for (int k = 0; k < 3; ++k) l_[k] = s_[3 + k];\n";
+        } else if (frame_ == 0) {  // the body-fixed point at the world origin: p_j x w
+          o_ << "      bard::cross3(" << v("p", j) << ", s_, l_);\n";
+        } else {  // the end effector's origin: w x (p_e - p_j)
+          o_ << "      Real d_[3];\n      for (int k = 0; k < 3; ++k) d_[k] = " << v("p", e) << "[k] - " << v("p", j)
+             << "[k];\n      bard::cross3(s_, d_, l_);\n";
+        }
+        for (int r = 0; r < 6; ++r)
+          o_ << "      bard::put(&Jb[" << (ei * 6 + r) * nv + col << " * sJ_k], " << (r < 3 ? "l_[" : "s_[")
+             << (r % 3) << "], true);\n";
+        o_ << "    }\n";
+      }
+    }
+    o_ << "  }\n";
+  }
+
+  void visit(int i) {
+    forward(i);
+    for (size_t e = 0; e < ee_.size(); ++e)
+      if (ee_[e] == i) jacobian((int)e);
+    for (int ch : m_->children[i]) visit(ch);
+    backward(i);
+  }
+};
+
+}  // namespace
+
+std::string spec_key(int dtype, int frame, const std::vector<int>& ee) {
+  std::string k = std::to_string(dtype) + ":" + std::to_string(frame) + ":";
+  for (int e : ee) k += std::to_string(e) + ",";
+  return k;
+}
+
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64) {
+  return Emitter(m, ee, frame, fp64).source();
+}
+
+int spec_compile(const std::string& src, std::vector<char>* code, std::string* log) {
+  hiprtcProgram prog;
+  const char* hdr[] = {kSpatialHeader};
+  const char* hdr_name[] = {"spatial.h"};
+  if (hiprtcCreateProgram(&prog, src.c_str(), "bard_spec_chain.hip", 1, hdr, hdr_name) != HIPRTC_SUCCESS) {
+    *log = "hiprtcCreateProgram failed";
+    return BARD_E_DEVICE;
+  }
+  // the library's own flags: multiply-adds fused within an expression only,
+  // packed FP32 instructions off
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops"};
+  const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  size_t ls = 0;
+  hiprtcGetProgramLogSize(prog, &ls);
+  if (ls > 1) {
+    log->resize(ls);
+    hiprtcGetProgramLog(prog, &(*log)[0]);
+  }
+  if (rc != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return BARD_E_DEVICE;
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code->resize(cs);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return BARD_OK;
+}
+
+// Compiles (once per key) and loads on the current device.
+int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, bool load,
+                 SpecKernel** out) {
+  const std::string key = spec_key(dtype, frame, ee);
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = dc->spec.find(key);
+  if (it != dc->spec.end() && (it->second.fn || !load)) {
+    *out = &it->second;
+    return BARD_OK;
+  }
+  SpecKernel sk;
+  if (it != dc->spec.end()) sk = it->second;
+  if (sk.code.empty()) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string log;
+    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64), &sk.code, &log);
+    sk.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc) return fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000));
+  }
+  if (load) {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    if (hipModuleLoadData(&mod, sk.code.data()) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BARD_E_DEVICE, "hipModuleLoadData of the specialised kernel failed");
+    }
+    if (hipModuleGetFunction(&fn, mod, "bard_spec_chain") != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipModuleUnload(mod);
+      return fail(BARD_E_DEVICE, "specialised kernel not found in its module");
+    }
+    sk.mod = mod;
+    sk.fn = fn;
+    int regs = 0, local = 0;
+    if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn) != hipSuccess ||
+        hipFuncGetAttribute(&local, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn) != hipSuccess)
+      (void)hipGetLastError();
+    sk.vgprs = regs;
+    sk.scratch = local;
+  }
+  dc->spec[key] = sk;
+  *out = &dc->spec[key];
+  return BARD_OK;
+}
+
+SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int n_ee, const int32_t* ee,
+                        int64_t B) {
+  if (!m->spec_route.load()) return nullptr;
+  std::vector<int> v(ee, ee + n_ee);
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = dc->spec.find(spec_key(dtype, frame, v));
+  if (it == dc->spec.end() || !it->second.fn || !it->second.route || B < it->second.route_min_batch) return nullptr;
+  return &it->second;
+}
+
+template <class Real>
+int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st) {
+  long long sq_b = a.sq_b, sq_k = a.sq_k, sqd_b = a.sqd_b, sqd_k = a.sqd_k, sqdd_b = a.sqdd_b, sqdd_k = a.sqdd_k;
+  long long st_b = a.st_b, st_k = a.st_k, sM_b = a.sM_b, sM_k = a.sM_k, sJ_b = a.sJ_b, sJ_k = a.sJ_k, B = a.B;
+  Real g0 = (Real)g[0], g1 = (Real)g[1], g2 = (Real)g[2];
+  const Real *q = a.q, *qd = a.qd, *qdd = a.qdd;
+  Real *tau = a.tau, *M = a.M, *J = a.J;
+  void* args[] = {&q, &qd, &qdd, &tau, &M, &J, &sq_b, &sq_k, &sqd_b, &sqd_k, &sqdd_b, &sqdd_k,
+                  &st_b, &st_k, &sM_b, &sM_k, &sJ_b, &sJ_k, &B, &g0, &g1, &g2};
+  const int64_t grid = (a.B + 63) / 64;
+  if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
+  if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, st, args, nullptr) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BARD_E_DEVICE, "launch of the specialised kernel failed");
+  }
+  return BARD_OK;
+}
+
+template int spec_launch<float>(const SpecKernel*, const Args<float>&, const double*, hipStream_t);
+template int spec_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
+
+}  // namespace bard

@@ -1,0 +1,143 @@
+"""Model-specialised chain kernels (bard_model_specialize): hipRTC-compiled
+per-tree code behind bard_chain, through the C ABI.
+
+Parity: the routed chain call against the FP64 oracle under the per-entry
+contract (parity_util), FP32 and FP64, both Jacobian frames, fixed and free
+roots, revolute and prismatic joints, single-body trees, batches with a
+ragged tail (the kernel runs 64 instances per workgroup), the instance-major
+layout, a gravity change after compilation, and the headline tree at the
+benchmark's batches (sampled).  Routing: without BARD_SPEC_ROUTE the generic
+kernel keeps the calls (bitwise its own results); trees past the size bound
+are refused with BARD_E_UNSUPPORTED.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2605_31481_amd import bard
+from parity_util import assert_chain, from_dev, inputs, oracle_for, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("chain7", "float32", 1000, 0), ("chain7", "float64", 65, 1), ("quadruped_spine", "float32", 513, 1),
+         ("random11", "float32", 300, 0), ("random18", "float64", 97, 0), ("random23", "float32", 300, 1),
+         ("humanoid_small", "float32", 777, 0), ("humanoid_small", "float64", 40, 1),
+         ("humanoid_large", "float32", 1000, 1), ("humanoid_large", "float64", 64, 0),
+         ("prismatic8", "float32", 129, 0), ("star64", "float32", 70, 1), ("free_branches61", "float32", 100, 0),
+         ("rev1", "float32", 5, 1), ("pri1", "float64", 3, 0), ("free1", "float32", 65, 1)]
+
+
+@pytest.mark.parametrize("name,dtype,B,frame", CASES)
+def test_specialized_chain_matches_oracle(name, dtype, B, frame):
+    say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize(ee, frame=frame, dtype=dtype)
+    assert m.specialized_info(ee, frame=frame, dtype=dtype)["routed"]
+    q, qd, qdd = inputs(tree, B, 5300, dtype)
+    tau, M, J = m.chain(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype), ee, frame=frame)
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, from_dev(tau), from_dev(M), from_dev(J), dtype,
+                 frame=frame, label=f"spec {name}")
+    Mh = from_dev(M).reshape(B, tree.nv, tree.nv)
+    assert (Mh == np.transpose(Mh, (0, 2, 1))).all(), "M is bitwise symmetric"
+
+
+def test_routing_and_generic_results():
+    import torch
+    say("[gpu] specialised chain routing")
+    tree = synth.humanoid_small()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    q, qd, qdd = inputs(tree, 300, 5400, "float32")
+    d = [to_dev(x, "float32") for x in (q, qd, qdd)]
+    generic = m.chain(*d, ee)
+    m.specialize(ee, route=False)
+    info = m.specialized_info(ee)
+    assert not info["routed"] and info["scratch_bytes"] == 0 and info["vgprs"] > 0
+    kept = m.chain(*d, ee)
+    m.specialize(ee, route=True)
+    spec = m.chain(*d, ee)
+    m.specialize(ee, route=False)
+    back = m.chain(*d, ee)
+    torch.cuda.synchronize()
+    for a, b in zip(generic, kept):
+        assert torch.equal(a, b)
+    for a, b in zip(generic, back):
+        assert torch.equal(a, b)
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in spec), "float32", label="routed")
+    # another end-effector set or frame is not routed
+    other = m.chain(*d, ee[:2])
+    torch.cuda.synchronize()
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee[:2], *(from_dev(x) for x in other), "float32",
+                 label="other set")
+
+
+def test_instance_major_layout_and_gravity_change():
+    say("[gpu] specialised chain aos layout, gravity change")
+    from oracle import OracleModel
+    tree = synth.quadruped_spine()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize(ee)
+    q, qd, qdd = inputs(tree, 333, 5500, "float32")
+    d = [to_dev(x, "float32", "aos") for x in (q, qd, qdd)]
+    out = m.chain(*d, ee, layout="aos")
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x, "aos") for x in out), "float32",
+                 label="aos")
+    g = (1.0, -2.0, -9.0)
+    m.set_gravity(g)
+    out = m.chain(*[to_dev(x, "float32") for x in (q, qd, qdd)], ee)
+    om = OracleModel(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, gravity=g)
+    assert_chain(om, tree, q, qd, qdd, ee, *(from_dev(x) for x in out), "float32", label="new gravity")
+
+
+@pytest.mark.parametrize("B", [4096, 16384])
+def test_headline_tree_at_benchmark_batches(B):
+    say(f"[gpu] specialised chain humanoid_large B={B} (sampled)")
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize(ee)
+    q, qd, qdd = inputs(tree, B, 5600 + B, "float32")
+    tau, M, J = m.chain(to_dev(q, "float32"), to_dev(qd, "float32"), to_dev(qdd, "float32"), ee)
+    idx = np.sort(np.random.default_rng(B).choice(B, 256, replace=False))
+    idx[-1] = B - 1
+    assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee, from_dev(tau)[idx], from_dev(M)[idx],
+                 from_dev(J)[idx], "float32", label=f"spec B={B}")
+
+
+def test_deep_tree_refused():
+    say("[gpu] specialised chain refuses chain64")
+    tree = synth.tree_by_name("chain64")
+    m = bard.Model.from_tree(tree)
+    with pytest.raises(bard.BardError) as ei:
+        m.specialize(tree.ee_bodies)
+    assert ei.value.status == -7
+
+
+def test_autotune_routes_by_batch():
+    """bard_chain_autotune times both kernels and routes chain calls from the
+    chosen batch up; below it the generic kernel answers (bitwise its own
+    result), and every call meets the contract either way."""
+    import torch
+    tree = synth.humanoid_small()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    ref = bard.Model.from_tree(tree)   # never specialised: the generic kernel
+    mb = m.autotune_chain(ee)
+    say(f"[gpu] autotuned chain on humanoid_small: specialised from B = {mb}")
+    assert mb in (-1, 1024, 4096, 16384, 65536)
+    for B in (300, 20000):
+        q, qd, qdd = inputs(tree, B, 5700 + B, "float32")
+        d = [to_dev(x, "float32") for x in (q, qd, qdd)]
+        out = m.chain(*d, ee)
+        gen = ref.chain(*d, ee)
+        torch.cuda.synchronize()
+        if mb == -1 or B < mb:
+            for a, b in zip(out, gen):
+                assert torch.equal(a, b)
+        idx = np.sort(np.random.default_rng(B).choice(B, min(B, 200), replace=False))
+        assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee, *(from_dev(x)[idx] for x in out),
+                     "float32", label=f"autotuned B={B}")
