@@ -445,35 +445,65 @@ def sysid_data():
     return tree, [synth.to_fp32_grid(x) for x in synth.random_state(tree, 10000, 9100)]
 
 
-def sysid_reference_torques():
-    """Torques of the identification data at the true parameters, from the
-    FP64 oracle (part of the oracle leg)."""
+def sysid_reference():
+    """The oracle's part of the identification experiment (run in the oracle
+    leg): the torques at the true parameters, and the regressor of the masses
+    -- with pi(m) = A + m D per link, tau = RNEA(A) + sum_k m_k RNEA(D_k) --
+    from which each seed's least-squares optimum, the best any optimiser can
+    reach on that noisy data, is solved directly."""
     from oracle import OracleModel
+    from paper_2605_31481_amd.sysid import mass_map
     tree, (q, qd, qdd) = sysid_data()
-    return OracleModel.from_tree(tree).rnea(q, qd, qdd)
+    om = OracleModel.from_tree(tree)
+    A, D, m_true = mass_map(tree.inertia)
+    tau_a = om.rnea(q, qd, qdd, inertia=A)
+    cols = []
+    for k in range(tree.n_bodies):
+        pi = np.zeros_like(A)
+        pi[k] = D[k]
+        cols.append(om.rnea(q, qd, qdd, inertia=pi).ravel())
+    return {"tau": om.rnea(q, qd, qdd), "tau_a": tau_a, "phi": np.stack(cols, axis=1), "m_true": m_true}
 
 
-def bench_sysid(torch, bard, tau_ref):
+def bench_sysid(torch, bard, ref):
     """Mass identification (Sec. 4.3's experiment) on 10,000 random
-    configurations of the 11-DOF quadruped, FP32: torques from the true
-    parameters by the FP64 oracle plus 5% Gaussian noise per joint, masses
-    started 30% away from the truth, L-BFGS, 10 seeds."""
+    configurations of the 11-DOF quadruped: torques from the true parameters
+    by the FP64 oracle plus 5% Gaussian noise per joint, masses started 30%
+    away from the truth, L-BFGS, 10 seeds; in FP32 with and without the
+    diagonal scaling of the masses, and in FP64.  The least-squares optimum of
+    each seed's data gives the noise floor of the error and the optimiser's
+    remaining distance."""
     from paper_2605_31481_amd import sysid
     tree, host = sysid_data()
     m = bard.Model.from_tree(tree)
-    q, qd, qdd = (torch.from_numpy(x.T.copy()).float().cuda() for x in host)
-    tau_true = torch.from_numpy(tau_ref.T.copy()).float().cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = sysid.identify(m, tree.inertia, q, qd, qdd, seeds=range(10), noise=0.05, max_iter=60, tau_true=tau_true)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    per_seed = out["rel_error"].mean(axis=1) * 100
-    return {"sysid_mean_mass_error_pct": float(per_seed.mean()), "sysid_std_over_seeds_pct": float(per_seed.std()),
-            "sysid_worst_link_error_pct": float(out["rel_error"].max() * 100),
-            "sysid_iterations_mean": float(np.mean(out["iterations"])),
-            "sysid_evaluations_total": int(np.sum(out["evaluations"])),
-            "sysid_seconds_10_seeds": el}
+    out = {}
+    phi, tau_a, m_true = ref["phi"], ref["tau_a"], ref["m_true"]
+    for label, dtype, pre in (("fp32", torch.float32, True), ("fp32_unscaled", torch.float32, False),
+                              ("fp64", torch.float64, True)):
+        q, qd, qdd = (torch.from_numpy(x.T.copy()).to(dtype).cuda() for x in host)
+        tau_true = torch.from_numpy(ref["tau"].T.copy()).to(dtype).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sysid.identify(m, tree.inertia, q, qd, qdd, seeds=range(10), noise=0.05, max_iter=60,
+                             tau_true=tau_true, precondition=pre)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        per_seed = res["rel_error"].mean(axis=1) * 100
+        dist, floor = [], []
+        for k in range(10):
+            meas = sysid.noisy_torques(tau_true, 0.05, 7000 + k).double().cpu().numpy().T
+            m_ls = np.linalg.lstsq(phi, (meas - tau_a).ravel(), rcond=None)[0]
+            dist.append(float(np.abs(res["masses"][k] - m_ls).max() / np.abs(m_ls).max()))
+            floor.append(float((np.abs(m_ls - m_true) / m_true).max()))
+        out[f"sysid_{label}_mean_mass_error_pct"] = float(per_seed.mean())
+        out[f"sysid_{label}_std_over_seeds_pct"] = float(per_seed.std())
+        out[f"sysid_{label}_worst_link_error_pct"] = float(res["rel_error"].max() * 100)
+        out[f"sysid_{label}_iterations_mean"] = float(np.mean(res["iterations"]))
+        out[f"sysid_{label}_evaluations_total"] = int(np.sum(res["evaluations"]))
+        out[f"sysid_{label}_seconds_10_seeds"] = el
+        out[f"sysid_{label}_max_distance_to_least_squares"] = max(dist)
+        out[f"sysid_{label}_least_squares_worst_link_error_pct"] = 100 * max(floor)
+    return out
 
 
 def bench_workspace(torch, bard, steps):
@@ -670,7 +700,7 @@ def main():
         cpu = cpu_baseline(tree)
         log(f"[bench] cpu baseline {cpu}")
         if want("sysid"):
-            extra.update(bench_sysid(torch, bard, sysid_reference_torques()))
+            extra.update(bench_sysid(torch, bard, sysid_reference()))
             log(f"[bench] sysid {dict((k, v) for k, v in extra.items() if k.startswith('sysid'))}")
 
     out = {

@@ -5,7 +5,11 @@
 // compile against the same definitions as the library's own kernels.
 #pragma once
 
+// hipRTC provides the device built-ins itself (and may not see the
+// installed headers, e.g. under a profiler's environment)
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 namespace bard {
 

@@ -15,6 +15,13 @@ adjoint launch whose cotangent is the residual over B (the batch sum of the
 inertial-parameter gradient is reduced on the device).  The optimiser is
 PyTorch's L-BFGS over the n link masses; all per-instance work runs in the
 library's kernels.
+
+Because pi is affine in m and RNEA is linear in pi, L is a quadratic in m
+with Hessian H = Phi^T Phi / B, Phi_k = RNEA(q, qd, qdd; D_k) the torques of
+link k's mass direction alone.  Link masses excite the torques very unevenly
+(a distal link's column is far smaller than a base link's), so H is badly
+scaled; L-BFGS runs on u = m / s with s_k = 1 / sqrt(H_kk), the diagonal
+(Jacobi) scaling, whose n columns cost n RNEA launches once per problem.
 """
 
 from __future__ import annotations
@@ -54,7 +61,7 @@ class MassIdentification:
     the operators) of one dtype; inertia: the nominal [n, 10] parameters whose
     COM and rotational inertia are kept."""
 
-    def __init__(self, model: bard.Model, inertia, q, qd, qdd, tau_meas):
+    def __init__(self, model: bard.Model, inertia, q, qd, qdd, tau_meas, precondition: bool = True):
         torch = bard._torch()
         A, D, m = mass_map(inertia)
         self.model = model
@@ -65,6 +72,22 @@ class MassIdentification:
         self.q, self.qd, self.qdd, self.tau_meas = q, qd, qdd, tau_meas
         self.B = int(q.shape[1])
         self.evaluations = 0
+        self.scale = self.jacobi_scale() if precondition else np.ones(len(m))
+
+    def jacobi_scale(self) -> np.ndarray:
+        """s_k = 1 / sqrt(H_kk), H_kk = |RNEA(q, qd, qdd; D_k)|^2 / B: one RNEA
+        launch per link with that link's mass direction as its only
+        parameters."""
+        torch = bard._torch()
+        n = self.D.shape[0]
+        s = np.ones(n)
+        for k in range(n):
+            pi = torch.zeros_like(self.D)
+            pi[k] = self.D[k]
+            t = self.model.rnea(self.q, self.qd, self.qdd, inertia=pi)
+            h = float((t.double() * t.double()).sum()) / self.B
+            s[k] = 1.0 / np.sqrt(h) if h > 0 else 1.0
+        return s
 
     def inertia(self, m):
         """Body-origin parameters [n, 10] for the masses m (device tensor [n])."""
@@ -86,23 +109,26 @@ class MassIdentification:
         identified masses, the final loss, the iterations and the number of
         loss/gradient evaluations."""
         torch = bard._torch()
-        # the optimiser keeps its state in FP64; evaluations run in the batch dtype
-        m = torch.nn.Parameter(torch.tensor(np.asarray(m0, dtype=np.float64), dtype=torch.float64,
-                                            device=self.device))
-        opt = torch.optim.LBFGS([m], lr=1.0, max_iter=max_iter, history_size=history,
+        # the optimiser works on u = m / s and keeps its state in FP64;
+        # evaluations run in the batch dtype
+        s = torch.tensor(self.scale, dtype=torch.float64, device=self.device)
+        u = torch.nn.Parameter(torch.tensor(np.asarray(m0, dtype=np.float64), dtype=torch.float64,
+                                            device=self.device) / s)
+        opt = torch.optim.LBFGS([u], lr=1.0, max_iter=max_iter, history_size=history,
                                 line_search_fn="strong_wolfe", tolerance_grad=tolerance_grad,
                                 tolerance_change=tolerance_change)
         e0 = self.evaluations
 
         def closure():
-            loss, g = self.loss_and_grad(m.detach().to(self.dtype))
-            m.grad = g.to(torch.float64)
+            loss, g = self.loss_and_grad((u.detach() * s).to(self.dtype))
+            u.grad = g.to(torch.float64) * s
             return loss.to(torch.float64)
 
         opt.step(closure)
         state = opt.state[opt._params[0]]
-        loss, _ = self.loss_and_grad(m.detach().to(self.dtype))
-        return {"masses": m.detach().cpu().numpy(), "loss": float(loss),
+        m = (u.detach() * s)
+        loss, _ = self.loss_and_grad(m.to(self.dtype))
+        return {"masses": m.cpu().numpy(), "loss": float(loss),
                 "iterations": int(state.get("n_iter", 0)), "evaluations": self.evaluations - e0}
 
 
@@ -126,7 +152,7 @@ def perturbed_masses(m_true, fraction: float, seed: int) -> np.ndarray:
 
 
 def identify(model: bard.Model, inertia_true, q, qd, qdd, seeds=range(10), perturbation: float = 0.3,
-             noise: float = 0.05, max_iter: int = 20, tau_true=None) -> dict:
+             noise: float = 0.05, max_iter: int = 20, tau_true=None, precondition: bool = True) -> dict:
     """The identification experiment: torques from the true parameters
     (computed by the library unless tau_true is given) plus `noise` x RMS
     Gaussian noise per joint, masses started `perturbation` away from the
@@ -140,7 +166,7 @@ def identify(model: bard.Model, inertia_true, q, qd, qdd, seeds=range(10), pertu
     out = {"m_true": m_true, "masses": [], "rel_error": [], "iterations": [], "evaluations": []}
     for s in seeds:
         tau_meas = noisy_torques(tau_true, noise, 7000 + s) if noise > 0 else tau_true
-        prob = MassIdentification(model, inertia_true, q, qd, qdd, tau_meas)
+        prob = MassIdentification(model, inertia_true, q, qd, qdd, tau_meas, precondition=precondition)
         res = prob.run(perturbed_masses(m_true, perturbation, 8000 + s), max_iter=max_iter)
         out["masses"].append(res["masses"])
         out["rel_error"].append(np.abs(res["masses"] - m_true) / m_true)
