@@ -36,6 +36,9 @@ constexpr int kSpecMaxWalkSteps = 1500;
 std::string spec_key(int dtype, int frame, const std::vector<int>& ee);
 // Source text of the kernel for one (end-effector set, frame, precision).
 std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64);
+// Number of structural-zero rows (M entries of unrelated dofs, J rows off an
+// end effector's path) the kernel writes.
+int spec_zero_rows(const bard_model* m, const std::vector<int>& ee);
 // Compile source to a gfx950 code object with hipRTC (no device needed).
 int spec_compile(const std::string& src, std::vector<char>* code, std::string* log);
 // Compile (once) and, if `load`, load on the device of `dc`; *out points into dc->spec.

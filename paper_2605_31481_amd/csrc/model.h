@@ -68,6 +68,8 @@ struct SpecKernel {
   void* mod = nullptr;  // hipModule_t
   void* fn = nullptr;   // hipFunction_t
   int vgprs = 0, scratch = 0;
+  int zero_rows = 0;  // structural-zero rows of M and J
+  int64_t slots = 0;  // 64-lane workgroups the device holds at once at this register count
   double compile_s = 0.0;
   bool route = false;
   int64_t route_min_batch = 0;  // routed chain calls need at least this batch

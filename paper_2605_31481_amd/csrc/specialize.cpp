@@ -22,7 +22,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,12 +53,30 @@ class Emitter {
        << ", " << ee_.size() << " end effectors, frame " << frame_ << ", " << (fp64_ ? "FP64" : "FP32")
        << ")\n#include \"spatial.h\"\n";
     o_ << "typedef " << (fp64_ ? "double" : "float") << " Real;\n";
+    emit_zero_tables();
     o_ << "extern \"C\" __global__ void __launch_bounds__(64) bard_spec_chain(\n"
           "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ qdd,\n"
           "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
           "    long long sq_b, long long sq_k, long long sqd_b, long long sqd_k, long long sqdd_b, long long sqdd_k,\n"
           "    long long st_b, long long st_k, long long sM_b, long long sM_k, long long sJ_b, long long sJ_k,\n"
-          "    long long B, Real g0, Real g1, Real g2) {\n"
+          "    long long B, Real g0, Real g1, Real g2, int main_blocks, int zero_blocks) {\n"
+          "  if ((int)blockIdx.x >= main_blocks) {\n"
+          "    // structural zeros, instance-minor layout: the zero rows cut into\n"
+          "    // chunks of 1024 16-byte vectors, one chunk per workgroup in turn\n"
+          "    constexpr int V = 16 / (int)sizeof(Real);\n"
+          "    typedef Real Zv __attribute__((vector_size(16)));\n"
+          "    const Zv zero = {};\n"
+          "    const long long per = B / V;\n"
+          "    const long long nch = (per + 1023) / 1024;\n"
+          "    for (long long u = blockIdx.x - main_blocks; u < (NZM + NZJ) * nch; u += zero_blocks) {\n"
+          "      const long long r = u / nch, c = u - r * nch;\n"
+          "      Real* row = r < NZM ? M + (long long)ZM[r] * sM_k : J + (long long)ZJ[r - NZM] * sJ_k;\n"
+          "      const long long end = per < (c + 1) * 1024 ? per : (c + 1) * 1024;\n"
+          "      for (long long j = c * 1024 + threadIdx.x; j < end; j += 64)\n"
+          "        *reinterpret_cast<Zv*>(row + j * V) = zero;\n"
+          "    }\n"
+          "    return;\n"
+          "  }\n"
           "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
           "  if (b >= B) return;\n"
           "  const Real* qb = q + b * sq_b;\n  const Real* qdb = qd + b * sqd_b;\n"
@@ -99,7 +119,32 @@ class Emitter {
     return s.empty() ? "Real(0)" : s;
   }
 
+  // The zero rows of M and J as tables (NZM, ZM, NZJ, ZJ); the kernel writes
+  // them either from its computing lanes (zero_blocks == 0) or from extra
+  // workgroups when the layout is instance-minor.
+  void emit_zero_tables() {
+    zero_lists();
+    auto table = [&](const char* name, const char* count, const std::vector<int>& z) {
+      o_ << "static constexpr int " << count << " = " << z.size() << ";\n";
+      o_ << "static __device__ constexpr int " << name << "[" << (z.empty() ? 1 : z.size()) << "] = {";
+      if (z.empty()) o_ << "0";
+      for (size_t i = 0; i < z.size(); ++i) o_ << (i ? "," : "") << z[i];
+      o_ << "};\n";
+    };
+    table("ZM", "NZM", zm_);
+    table("ZJ", "NZJ", zj_);
+  }
+
   void emit_zero_stores() {
+    o_ << "  if (zero_blocks == 0) {\n"
+          "    for (int i = 0; i < NZM; ++i) bard::put(&Mb[(long long)ZM[i] * sM_k], Real(0), true);\n"
+          "    for (int i = 0; i < NZJ; ++i) bard::put(&Jb[(long long)ZJ[i] * sJ_k], Real(0), true);\n"
+          "  }\n";
+  }
+
+  std::vector<int> zm_, zj_;
+
+  void zero_lists() {
     // mass-matrix entries of unrelated dofs and Jacobian rows of dofs off an
     // end effector's root path are zero for every configuration
     const int nv = m_->nv;
@@ -125,15 +170,8 @@ class Emitter {
         for (int col = 0; col < nv; ++col)
           if (!on[col]) zj.push_back(((int)e * 6 + r) * nv + col);
     }
-    auto table = [&](const char* name, const std::vector<int>& z, const char* out, const char* stride) {
-      if (z.empty()) return;
-      o_ << "  {\n    static constexpr int " << name << "[" << z.size() << "] = {";
-      for (size_t i = 0; i < z.size(); ++i) o_ << (i ? "," : "") << z[i];
-      o_ << "};\n    for (int i = 0; i < " << z.size() << "; ++i) bard::put(&" << out << "[(long long)" << name
-         << "[i] * " << stride << "], Real(0), true);\n  }\n";
-    };
-    table("zm", zm, "Mb", "sM_k");
-    table("zj", zj, "Jb", "sJ_k");
+    zm_ = zm;
+    zj_ = zj;
   }
 
   // ---- entering body i: pose, axis, velocity, acceleration, body force ----
@@ -389,6 +427,29 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
   return Emitter(m, ee, frame, fp64).source();
 }
 
+int spec_zero_rows(const bard_model* m, const std::vector<int>& ee) {
+  // unrelated dof pairs of M plus the off-path rows of J
+  const int nv = m->nv;
+  std::vector<int> body_of(nv);
+  for (int i = 0; i < m->n; ++i)
+    for (int d = 0; d < m->nvi[i]; ++d) body_of[m->vi[i] + d] = i;
+  auto anc = [&](int a, int b) {
+    for (int k = a; k >= 0; k = m->parent[k])
+      if (k == b) return true;
+    return false;
+  };
+  int z = 0;
+  for (int r = 0; r < nv; ++r)
+    for (int c = 0; c < nv; ++c)
+      if (!anc(body_of[r], body_of[c]) && !anc(body_of[c], body_of[r])) ++z;
+  for (int e : ee) {
+    int on = 0;
+    for (int k = e; k >= 0; k = m->parent[k]) on += m->nvi[k];
+    z += 6 * (nv - on);
+  }
+  return z;
+}
+
 int spec_compile(const std::string& src, std::vector<char>* code, std::string* log) {
   hiprtcProgram prog;
   const char* hdr[] = {kSpatialHeader};
@@ -436,6 +497,7 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
     const auto t0 = std::chrono::steady_clock::now();
     std::string log;
     const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64), &sk.code, &log);
+    sk.zero_rows = spec_zero_rows(m, ee);
     sk.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000));
   }
@@ -459,6 +521,16 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
       (void)hipGetLastError();
     sk.vgprs = regs;
     sk.scratch = local;
+    // workgroups of 64 lanes resident at once: four SIMDs per compute unit,
+    // each holding as many waves as its 512 registers per lane allow
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      cus = 0;
+    }
+    const int per_simd = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 1;
+    sk.slots = (int64_t)cus * 4 * per_simd;
   }
   dc->spec[key] = sk;
   *out = &dc->spec[key];
@@ -482,9 +554,26 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   Real g0 = (Real)g[0], g1 = (Real)g[1], g2 = (Real)g[2];
   const Real *q = a.q, *qd = a.qd, *qdd = a.qdd;
   Real *tau = a.tau, *M = a.M, *J = a.J;
+  const int64_t main = (a.B + 63) / 64;
+  // Structural zeros: when every zero row is a run of B contiguous, 16-byte
+  // aligned values (instance-minor M and J) and the computing workgroups fill
+  // at most a quarter of the device's wave slots, extra workgroups of the same
+  // launch write them beside the computing waves (a few waves storing one
+  // value per lane per zero entry are bound by instruction issue, not by
+  // HBM); with more computing waves than that each lane writes its own,
+  // coalesced across the wavefront, and the launch is bound by HBM writes.
+  const int64_t V = 16 / (int64_t)sizeof(Real);
+  const bool rows = a.sM_b == 1 && a.sJ_b == 1 && a.B % V == 0 && a.sM_k % V == 0 && a.sJ_k % V == 0 &&
+                    ((uintptr_t)a.M % 16) == 0 && ((uintptr_t)a.J % 16) == 0;
+  int64_t zb = 0;
+  if (rows && sk->zero_rows > 0 && main * 4 <= sk->slots) {
+    const int64_t chunks = (int64_t)sk->zero_rows * ((a.B / V + 1023) / 1024);
+    zb = std::min<int64_t>(chunks, sk->slots - main);
+  }
+  int main_blocks = (int)main, zero_blocks = (int)zb;
   void* args[] = {&q, &qd, &qdd, &tau, &M, &J, &sq_b, &sq_k, &sqd_b, &sqd_k, &sqdd_b, &sqdd_k,
-                  &st_b, &st_k, &sM_b, &sM_k, &sJ_b, &sJ_k, &B, &g0, &g1, &g2};
-  const int64_t grid = (a.B + 63) / 64;
+                  &st_b, &st_k, &sM_b, &sM_k, &sJ_b, &sJ_k, &B, &g0, &g1, &g2, &main_blocks, &zero_blocks};
+  const int64_t grid = main + zb;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, st, args, nullptr) !=
       hipSuccess) {

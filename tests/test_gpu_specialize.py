@@ -141,3 +141,37 @@ def test_autotune_routes_by_batch():
         idx = np.sort(np.random.default_rng(B).choice(B, min(B, 200), replace=False))
         assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee, *(from_dev(x)[idx] for x in out),
                      "float32", label=f"autotuned B={B}")
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype):
+    """With instance-minor outputs, a batch that is a multiple of the 16-byte
+    vector width and a grid that leaves wave slots free, the structural zeros
+    of M and J come from extra workgroups; a ragged batch (B + 1) makes every
+    lane write its own.  Outputs start as NaN, so an unwritten zero shows; the
+    first B instances agree bitwise between the two calls."""
+    import torch
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize(ee, dtype=dtype)
+    B = 4096
+    q, qd, qdd = inputs(tree, B + 1, 5800, dtype)
+    res = []
+    for n in (B, B + 1):
+        say(f"[gpu] specialised zero rows humanoid_large {dtype} B={n}")
+        d = [to_dev(x[:n], dtype) for x in (q, qd, qdd)]
+        nan = float("nan")
+        out = tuple(torch.full((k, n), nan, dtype=getattr(torch, dtype), device="cuda")
+                    for k in (tree.nv, tree.nv * tree.nv, 6 * tree.nv * len(ee)))
+        m.chain(*d, ee, out=out)
+        torch.cuda.synchronize()
+        for t in out:
+            assert not torch.isnan(t).any()
+        res.append(out)
+    for a, b in zip(*res):
+        assert torch.equal(a, b[:, :B])
+    idx = np.sort(np.random.default_rng(3).choice(B + 1, 200, replace=False))
+    idx[-1] = B
+    assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee, *(from_dev(x)[idx] for x in res[1]), dtype,
+                 label="ragged")

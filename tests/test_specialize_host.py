@@ -20,6 +20,13 @@ def test_generated_source_compiles(name, dtype, frame):
     m.specialize(tree.ee_bodies, frame=frame, dtype=dtype, compile_only=True)
 
 
+def _table(src, which):
+    """The structural-zero rows of M or J listed in the generated source."""
+    n = int(re.search(rf"NZ{which} = (\d+);", src).group(1))
+    vals = re.search(rf"Z{which}\[\d+\] = \{{([0-9, ]*)\}}", src).group(1).split(",")
+    return [int(x) for x in vals[:n]]
+
+
 def test_generated_source_covers_every_output():
     tree = synth.humanoid_small()
     m = bard.Model.from_tree(tree)
@@ -29,10 +36,10 @@ def test_generated_source_covers_every_output():
     tau = {int(k) for k in re.findall(r"&tb\[(\d+) \* st_k\]", src)}
     assert tau == set(range(nv))
     stored = [int(k) for k in re.findall(r"&Mb\[(\d+) \* sM_k\]", src)]
-    zeros = [int(x) for x in re.search(r"zm\[\d+\] = \{([0-9,]*)\}", src).group(1).split(",")]
+    zeros = _table(src, "M")
     assert sorted(stored + zeros) == list(range(nv * nv))
     jcols = [int(k) for k in re.findall(r"&Jb\[(\d+) \* sJ_k\]", src)]
-    jz = [int(x) for x in re.search(r"zj\[\d+\] = \{([0-9,]*)\}", src).group(1).split(",")]
+    jz = _table(src, "J")
     assert sorted(jcols + jz) == list(range(len(ee) * 6 * nv))
     assert "float" in src and "double" not in src
 
