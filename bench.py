@@ -30,6 +30,8 @@ METRIC = "evals/sec RNEA+CRBA+Jacobian, 23-DOF tree, batch 4096 FP32 (err vs FP6
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_humanoid_large_b4096.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_31481_amd", "csrc", "kernels.hip")
+SPEC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_spec_humanoid_large_b4096.json")
+SPEC_SRCS = [os.path.join(ROOT, "paper_2605_31481_amd", "csrc", f) for f in ("spatial.h", "specialize.cpp")]
 
 
 def log(*a):
@@ -341,41 +343,45 @@ def measure_peaks(torch):
 
 
 def bench_specialized(torch, bard):
-    """Model-specialised chain kernels (hipRTC, one lane per instance,
-    constants as literals) against the generic kernel: the 36-DOF and 23-DOF
-    humanoids and the 7-DOF chain at B = 4096 .. 262,144, rotating sets past
-    512 MB; then the batch from which bard_chain_autotune routes calls to the
-    specialised kernel."""
+    """Model-specialised chain kernels (hipRTC, constants as literals) against
+    the generic kernel: both forms (split over waves by limbs, and the whole
+    tree per wave) on the 36-DOF and 23-DOF humanoids and the 7-DOF chain at
+    B = 1024 .. 262,144, rotating sets past 512 MB; then the tiers
+    bard_chain_autotune routes to each form."""
     import synth
     out = {}
-    for name, batches in (("humanoid_large", (4096, 16384, 65536, 262144)), ("humanoid_small", (4096, 16384, 65536)),
-                          ("chain7", (4096, 16384, 65536))):
+    for name, batches in (("humanoid_large", (1024, 4096, 16384, 65536, 262144)),
+                          ("humanoid_small", (1024, 4096, 16384, 65536)), ("chain7", (1024, 4096, 16384, 65536))):
         tree = synth.tree_by_name(name)
         m = bard.Model.from_tree(tree)
         ee = tree.ee_bodies
         bpe = chain_bytes_per_eval(tree, len(ee))
-        m.specialize(ee, route=False)
-        info = m.specialized_info(ee)
-        out[f"spec_{name}_compile_s"] = info["compile_s"]
-        out[f"spec_{name}_vgprs"] = info["vgprs"]
-        out[f"spec_{name}_scratch_bytes"] = info["scratch_bytes"]
+        forms = ("split", "whole")
+        for f in forms:
+            m.specialize(ee, route=False, whole=f == "whole")
+            info = m.specialized_info(ee, whole=f == "whole")
+            for k in ("compile_s", "vgprs", "scratch_bytes", "waves"):
+                out[f"spec_{name}_{f}_{k}"] = info[k]
         for B in batches:
             nsets = max(2, min(64, math.ceil(512e6 / (bpe * B))))
             sets = make_sets(torch, tree, B, nsets, 13000 + B)
             calls = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
             n = max(30, min(400, 2_000_000 // B))
-            m.specialize(ee, route=False)
-            _, kg = time_calls(torch, calls, n, 5)
-            m.specialize(ee, route=True)
-            _, ks = time_calls(torch, calls, n, 5)
             key = f"spec_{name}_B{B}"
+            m.specialize(ee, route=False)
+            m.specialize(ee, route=False, whole=True)
+            _, kg = time_calls(torch, calls, n, 5)
             out[key + "_generic_us"] = kg * 1e3
-            out[key + "_specialized_us"] = ks * 1e3
-            out[key + "_specialized_evals_per_s"] = B / (ks * 1e-3)
-            out[key + "_specialized_hbm_frac"] = bpe * B / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS
+            for f in forms:
+                m.specialize(ee, route=True, whole=f == "whole")
+                _, ks = time_calls(torch, calls, n, 5)
+                out[key + f"_{f}_us"] = ks * 1e3
+                out[key + f"_{f}_hbm_frac"] = bpe * B / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS
             del sets, calls
             torch.cuda.empty_cache()
-        out[f"spec_{name}_autotuned_min_batch"] = m.autotune_chain(ee)
+        out[f"spec_{name}_autotuned_first_batch"] = m.autotune_chain(ee)
+        out[f"spec_{name}_autotuned_tiers"] = {f: m.specialized_info(ee, whole=f == "whole")["route_tiers"]
+                                               for f in forms}
     return out
 
 
@@ -560,11 +566,23 @@ def bench_workspace(torch, bard, steps):
     return out
 
 
-def traffic_if_current():
-    if not os.path.exists(TRAFFIC_FILE):
+def spec_source_sha(m, ee, whole):
+    """SHA-256 of what a specialised kernel is built and launched from: its
+    generated source, the device header it includes and the generator."""
+    h = hashlib.sha256(m.specialized_source(ee, whole=whole).encode())
+    for f in SPEC_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def traffic_if_current(spec_sha=None):
+    """The counted HBM bytes per launch of the timed kernel, if the record was
+    taken on the current source (None otherwise)."""
+    path = SPEC_TRAFFIC_FILE if spec_sha else TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    rec = json.load(open(path))
+    sha = spec_sha or hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if rec.get("kernels_sha256") != sha:
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -612,6 +630,19 @@ def main():
     nsets = max(14, math.ceil(512e6 / per_call))
     log(f"[bench] workload humanoid_large nv={tree.nv} B={B} bytes/call={per_call/1e6:.1f} MB sets={nsets}")
     sets = make_sets(torch, tree, B, nsets, 2002)
+    # bard_chain_autotune (untimed, once) routes each batch tier to the fastest
+    # of the generic kernel and the two specialised forms
+    t0 = time.perf_counter()
+    first = m.autotune_chain(ee)
+    tiers = {"split": m.specialized_info(ee)["route_tiers"], "whole": m.specialized_info(ee, whole=True)["route_tiers"]}
+    tier = sum(B >= t for t in bard.SPEC_TIERS[1:])
+    route = next((f for f, bits in tiers.items() if (bits >> tier) & 1), "generic")
+    spec_sha = spec_source_sha(m, ee, route == "whole") if route != "generic" else None
+    kernel = {"generic": "tree_kernel<float, RNEA|CRBA|JAC>",
+              "split": f"bard_spec_chain (specialised, split over {m.specialized_info(ee)['waves']} waves)",
+              "whole": "bard_spec_chain (specialised, whole tree per wave)"}[route]
+    log(f"[bench] autotune {time.perf_counter() - t0:.1f} s: tiers {tiers}, first specialised batch {first}; "
+        f"B={B} runs {kernel}")
     def make_calls():
         return [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
     calls = make_calls()
@@ -621,7 +652,20 @@ def main():
     achieved = per_call / (kavg * 1e-3) / 1e9
     log(f"[bench] chain: {value:.4g} evals/s, kernel avg {kavg*1e3:.2f} us")
 
-    extra = {}
+    extra = {"autotune_route_tiers": tiers, "autotune_first_specialised_batch": first}
+    if route != "generic":
+        # the generic kernel on the same sets, for comparison
+        mg = bard.Model.from_tree(tree)
+        gcalls = [mg.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
+        gw, gk = time_calls(torch, gcalls, args.steps, args.warmup)
+        extra["generic_kernel_evals_per_s"] = B * args.steps / gw
+        extra["generic_kernel_us"] = gk * 1e3
+        extra["generic_kernel_hbm_frac"] = per_call / (gk * 1e-3) / 1e9 / HBM_PEAK_GBS
+        log(f"[bench] generic chain kernel on the same sets: {gk*1e3:.2f} us")
+        # the routed calls write the outputs the parity leg samples
+        for c in calls[:nsets]:
+            c()
+        torch.cuda.synchronize()
     only = set(x for x in args.only.split(",") if x)
     want = lambda k: not args.no_extra and (not only or k in only)
     if want("chainforms"):
@@ -718,12 +762,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "humanoid tree: free root + 3-DOF waist + 1-DOF neck + two 7-DOF arms + "
                                "two 6-DOF legs (31 bodies, nq 37, nv 36, depth 9), 4 end effectors; "
-                               "fused RNEA+CRBA+Jacobian, eager C-ABI launches, fresh inputs every step",
+                               "fused RNEA+CRBA+Jacobian through bard_chain after bard_chain_autotune, eager "
+                               "C-ABI launches, fresh inputs every step",
                    "batch": B, "tree": "humanoid_large", "rotating_sets": nsets,
-                   "bytes_per_eval": bpe},
+                   "bytes_per_eval": bpe, "kernel": kernel},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_if_current(),
-                     "kernel": "tree_kernel<float, RNEA|CRBA|JAC>", "kernel_avg_us": kavg * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_if_current(spec_sha),
+                     "kernel": kernel, "kernel_avg_us": kavg * 1e3},
         "cpu_baseline": cpu,
         "parity": parity,
         "extra": extra,

@@ -138,51 +138,67 @@ int bard_model_destroy(bard_model_t model);
 /* ------------------------------------------------- specialised kernels ----
  * The fused chain of bard_chain (RNEA + CRBA + Jacobian) written for one
  * tree: the model compiler emits HIP source in which every model constant is
- * a literal and the traversal is unrolled body by body, one lane per instance
- * (the generated, model-specific kernels Sec. 2 cites as prior art), and
- * hipRTC compiles it for gfx950 at run time.
+ * a literal and the traversal is unrolled body by body (the generated,
+ * model-specific kernels Sec. 2 cites as prior art), and hipRTC compiles it
+ * for gfx950 at run time.  Two forms, 64 instances per workgroup, one lane
+ * per instance:
+ *   split (default): a tree with branches is cut into its trunk (the bodies
+ *     with two or more children and their ancestors) and limbs (the chains
+ *     hanging off it); each wave of the workgroup computes the trunk's
+ *     kinematics and then whole limbs, and after one barrier one wave sums the
+ *     trunk.  A tree that is a single chain runs as one wave.
+ *   whole (BARD_SPEC_WHOLE): one wave walks the whole tree; fewer
+ *     instructions in all, so it can win once the batch fills the device.
  *
- * specialize: compiles the kernel for (dtype, end-effector set ee_body [n_ee,
- * host], frame) and loads it on the current device (once; later calls only
- * change the routing).  flags: BARD_SPEC_ROUTE -- bard_chain calls with these
- * arguments on this device then launch the specialised kernel instead of the
- * generic one (without it, the generic kernel keeps them); results agree
- * within the tolerance contract, not bitwise (different summation order).
- * BARD_SPEC_COMPILE_ONLY -- generate and compile only, needing no GPU, and
- * keep nothing (a check that the generator's output compiles).  Uploads the
- * model's tables as bard_model_upload does; synchronous; call it outside any
- * graph capture.  The kernel is unloaded by bard_model_destroy.
+ * specialize: compiles the kernel of one form for (dtype, end-effector set
+ * ee_body [n_ee, host], frame) and loads it on the current device (once; later
+ * calls only change the routing).  flags: BARD_SPEC_ROUTE -- bard_chain calls
+ * with these arguments on this device then launch this kernel for every batch
+ * (and not the other form); without it, this form takes no calls.  Results
+ * agree with the generic kernel's within the tolerance contract, not bitwise
+ * (different summation order).  BARD_SPEC_COMPILE_ONLY -- generate and
+ * compile only, needing no GPU, and keep nothing (a check that the
+ * generator's output compiles).  BARD_SPEC_WHOLE -- the whole form.  Uploads
+ * the model's tables as bard_model_upload does; synchronous; call it outside
+ * any graph capture.  The kernels are unloaded by bard_model_destroy.
  * Errors: BARD_E_ARG, BARD_E_DEVICE (a hipRTC compile or module load failed;
  * bard_last_error holds the compiler log), BARD_E_NOMEM, BARD_E_UNSUPPORTED
  * (trees deeper than 32 or with more than 1500 dof-ancestor pairs, whose
  * generated code would take minutes to compile: the generic kernel serves
- * them). */
+ * them).  Routed calls whose per-instance byte offset into an array reaches
+ * 4 GiB run the generic kernel (the generated code addresses with 32-bit
+ * lane offsets). */
 #define BARD_SPEC_ROUTE 1
 #define BARD_SPEC_COMPILE_ONLY 2
+#define BARD_SPEC_WHOLE 4
 int bard_model_specialize(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                           bard_frame frame, int32_t flags);
-/* Resources of a loaded specialised kernel on the current device: registers
- * per lane, scratch bytes per lane (spills), hipRTC compile time, and whether
- * chain calls are routed to it.  Any output may be NULL.  BARD_E_STATE if
- * none is loaded for these arguments. */
+/* Resources of a loaded specialised kernel (form by flags: 0 or
+ * BARD_SPEC_WHOLE) on the current device: registers per lane, scratch bytes
+ * per lane (spills), hipRTC compile time, the batch tiers routed to it (bit k
+ * for tier k: [0, 4096), [4096, 16384), [16384, 65536), [65536, inf)) and
+ * waves per workgroup.  Any output may be NULL.  BARD_E_STATE if none is
+ * loaded for these arguments. */
 int bard_model_specialized_info(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
-                                bard_frame frame, int32_t* vgprs, int32_t* scratch_bytes,
-                                double* compile_seconds, int32_t* routed);
-/* Choose between the generic and the specialised chain kernel by timing:
- * compiles and loads the specialised kernel if needed, times both on scratch
- * arrays (allocated here and freed before returning) at B = 1024, 4096,
- * 16384 and 65536 on `stream`, and routes chain calls with these arguments
- * and a batch of at least *min_batch to the specialised kernel, where
- * *min_batch is the smallest tried batch from which it is faster at every
- * larger one (-1, no routing, if it never is).  Synchronous; not under graph
- * capture (BARD_E_CAPTURE).  A later bard_model_specialize call resets the
- * routing.  Errors: as bard_model_specialize, BARD_E_NOMEM, BARD_E_CAPTURE. */
+                                bard_frame frame, int32_t flags, int32_t* vgprs, int32_t* scratch_bytes,
+                                double* compile_seconds, int32_t* routed_tiers, int32_t* waves);
+/* Choose between the generic chain kernel and the specialised forms by
+ * timing: compiles and loads both forms if needed (one, for a tree that does
+ * not split), times every candidate on scratch arrays (allocated here and
+ * freed before returning) at B = 1024, 4096, 16384 and 65536 on `stream`, and
+ * routes each batch tier (as in bard_model_specialized_info; the tier of
+ * 1024 covers every batch below 4096) to the fastest.  *min_batch receives
+ * the smallest batch any specialised form takes (0, 4096, 16384 or 65536),
+ * or -1.  Synchronous; not under graph capture (BARD_E_CAPTURE).  A later
+ * bard_model_specialize call resets the routing.  Errors: as
+ * bard_model_specialize, BARD_E_NOMEM, BARD_E_CAPTURE. */
 int bard_chain_autotune(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                         bard_frame frame, void* stream, int64_t* min_batch);
-/* The generated source text (NUL-terminated, truncated to cap - 1 bytes);
- * *len receives its full length.  Host only. */
+/* The generated source text of one form (flags: 0 or BARD_SPEC_WHOLE;
+ * NUL-terminated, truncated to cap - 1 bytes); *len receives its full length.
+ * Host only. */
 int bard_model_specialized_source(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
-                                  bard_frame frame, char* buf, int64_t cap, int64_t* len);
+                                  bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len);
 
 /* ------------------------------------------------------------ workspace ----
  * A workspace holds cached state of one stream for up to max_batch instances

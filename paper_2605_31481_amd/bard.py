@@ -44,7 +44,9 @@ WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
 E_STATE = -9  # bard_status of a call that allocates nothing and found the model not uploaded
 UPLOAD_ADJOINT = 1
-SPEC_ROUTE, SPEC_COMPILE_ONLY = 1, 2
+SPEC_ROUTE, SPEC_COMPILE_ONLY, SPEC_WHOLE = 1, 2, 4
+# batch tiers of the specialised-kernel routing (lower bounds)
+SPEC_TIERS = (0, 4096, 16384, 65536)
 # workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own
 # (see Workspace)
 TIER_KINEMATICS, TIER_MASS, TIER_BIAS, TIER_RESULTS = 1, 2, 4, 8
@@ -83,10 +85,10 @@ bard_model_destroy = _sig("bard_model_destroy", [_vp])
 bard_model_upload = _sig("bard_model_upload", [_vp, _i32, _c_i32p, _i32])
 bard_model_specialize = _sig("bard_model_specialize", [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32])
 bard_model_specialized_info = _sig("bard_model_specialized_info",
-                                   [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _c_i32p, _c_i32p,
-                                    ctypes.POINTER(ctypes.c_double), _c_i32p])
+                                   [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32, _c_i32p, _c_i32p,
+                                    ctypes.POINTER(ctypes.c_double), _c_i32p, _c_i32p])
 bard_model_specialized_source = _sig("bard_model_specialized_source",
-                                     [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, ctypes.c_char_p, _i64,
+                                     [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32, ctypes.c_char_p, _i64,
                                       ctypes.POINTER(_i64)])
 bard_chain_autotune = _sig("bard_chain_autotune", [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _vp,
                                                    ctypes.POINTER(_i64)])
@@ -426,19 +428,22 @@ class Model:
         _check(bard_model_upload(self._h, n, pee, UPLOAD_ADJOINT if adjoint else 0), "bard_model_upload")
 
     def specialize(self, ee: Sequence[int], frame: int = WORLD, dtype=None, route: bool = True,
-                   compile_only: bool = False):
+                   compile_only: bool = False, whole: bool = False):
         """Compile the model-specialised chain kernel for (dtype, ee, frame)
         with hipRTC and load it on the current device; with route=True,
-        matching chain() calls use it (bard_model_specialize)."""
+        matching chain() calls use it at every batch (bard_model_specialize).
+        whole=True selects the form that walks the whole tree in one wave
+        instead of splitting it over waves by limbs."""
         ee_a, pee = _i32arr(ee)
-        flags = (SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0)
+        flags = ((SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0) |
+                 (SPEC_WHOLE if whole else 0))
         _check(bard_model_specialize(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), flags),
                "bard_model_specialize")
 
     def autotune_chain(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> int:
-        """Time the generic and the specialised chain kernels (bard_chain_autotune)
-        and route chain calls from the returned batch size up to the specialised
-        one (-1: never)."""
+        """Time the generic chain kernel and both specialised forms
+        (bard_chain_autotune) and route each batch tier to the fastest;
+        returns the smallest batch a specialised form takes (-1: none)."""
         torch = _torch()
         ee_a, pee = _i32arr(ee)
         mb = _i64()
@@ -447,22 +452,25 @@ class Model:
                "bard_chain_autotune")
         return mb.value
 
-    def specialized_info(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> dict:
+    def specialized_info(self, ee: Sequence[int], frame: int = WORLD, dtype=None, whole: bool = False) -> dict:
         ee_a, pee = _i32arr(ee)
-        vg, sc, rt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        vg, sc, rt, nw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         cs = ctypes.c_double()
         _check(bard_model_specialized_info(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame),
-                                           ctypes.byref(vg), ctypes.byref(sc), ctypes.byref(cs), ctypes.byref(rt)),
+                                           SPEC_WHOLE if whole else 0, ctypes.byref(vg), ctypes.byref(sc),
+                                           ctypes.byref(cs), ctypes.byref(rt), ctypes.byref(nw)),
                "bard_model_specialized_info")
-        return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value)}
+        return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
+                "route_tiers": rt.value, "waves": nw.value}
 
-    def specialized_source(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> str:
+    def specialized_source(self, ee: Sequence[int], frame: int = WORLD, dtype=None, whole: bool = False) -> str:
         ee_a, pee = _i32arr(ee)
+        fl = SPEC_WHOLE if whole else 0
         n = _i64()
-        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), None, 0,
-                                             ctypes.byref(n)), "bard_model_specialized_source")
+        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), fl, None,
+                                             0, ctypes.byref(n)), "bard_model_specialized_source")
         buf = ctypes.create_string_buffer(n.value + 1)
-        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), buf,
+        _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), fl, buf,
                                              n.value + 1, ctypes.byref(n)), "bard_model_specialized_source")
         return buf.value.decode()
 

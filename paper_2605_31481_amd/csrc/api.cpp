@@ -686,12 +686,22 @@ static int spec_args(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32
   return BARD_OK;
 }
 
+// Whether any loaded specialised kernel takes chain calls (m->mu held).
+static void spec_refresh_route(bard_model* m) {
+  bool any = false;
+  for (const auto& d : m->dev)
+    for (const auto& kv : d.spec) any = any || kv.second.route_tiers != 0;
+  m->spec_route.store(any);
+}
+
+static int spec_form(int32_t flags) { return (flags & BARD_SPEC_WHOLE) ? 1 : 0; }
+
 int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
                           int32_t flags) {
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY)) return fail(BARD_E_ARG, "unknown flags");
+  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY | BARD_SPEC_WHOLE)) return fail(BARD_E_ARG, "unknown flags");
   // The generated code grows with the ancestor walks of the mass-matrix
   // columns (one step per dof and ancestor body); past this size the compile
   // time and register pressure outgrow what specialisation gains.
@@ -702,36 +712,41 @@ int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const 
     return fail(BARD_E_UNSUPPORTED, "tree too deep for a specialised kernel (depth " + std::to_string(m->depth) +
                                         ", " + std::to_string(steps) + " ancestor-walk steps); the generic kernel "
                                         "serves it");
+  const int form = spec_form(flags);
   if (flags & BARD_SPEC_COMPILE_ONLY) {
     std::vector<char> code;
     std::string log;
-    rc = spec_compile(spec_chain_source(m, ee, (int)frame, dtype == BARD_F64), &code, &log);
+    rc = spec_compile(spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, form == 1), &code, &log);
     return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
   }
   if ((rc = check_device_state())) return rc;
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, nullptr))) return rc;
   SpecKernel* sk = nullptr;
-  if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, true, &sk))) return rc;
+  if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, form, true, &sk))) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
-  sk->route = (flags & BARD_SPEC_ROUTE) != 0;
-  sk->route_min_batch = 0;
-  bool any = false;
-  for (const auto& d : m->dev)
-    for (const auto& kv : d.spec) any = any || kv.second.route;
-  m->spec_route.store(any);
+  if (flags & BARD_SPEC_ROUTE) {
+    // every batch to this form; the other form of the same arguments keeps none
+    auto other = dc->spec.find(spec_key((int)dtype, (int)frame, ee, 1 - form));
+    if (other != dc->spec.end()) other->second.route_tiers = 0;
+    sk->route_tiers = (1 << kSpecTiers) - 1;
+  } else {
+    sk->route_tiers = 0;
+  }
+  spec_refresh_route(m);
   return BARD_OK;
 }
 
 int bard_model_specialized_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
-                                bard_frame frame, int32_t* vgprs, int32_t* scratch_bytes, double* compile_seconds,
-                                int32_t* routed) {
+                                bard_frame frame, int32_t flags, int32_t* vgprs, int32_t* scratch_bytes,
+                                double* compile_seconds, int32_t* routed_tiers, int32_t* waves) {
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
+  if (flags & ~BARD_SPEC_WHOLE) return fail(BARD_E_ARG, "unknown flags");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
-  const std::string key = spec_key((int)dtype, (int)frame, ee);
+  const std::string key = spec_key((int)dtype, (int)frame, ee, spec_form(flags));
   std::lock_guard<std::mutex> lk(m->mu);
   auto it = m->dev[dev].spec.find(key);
   if (it == m->dev[dev].spec.end() || !it->second.fn)
@@ -739,7 +754,8 @@ int bard_model_specialized_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, 
   if (vgprs) *vgprs = it->second.vgprs;
   if (scratch_bytes) *scratch_bytes = it->second.scratch;
   if (compile_seconds) *compile_seconds = it->second.compile_s;
-  if (routed) *routed = it->second.route ? 1 : 0;
+  if (routed_tiers) *routed_tiers = it->second.route_tiers;
+  if (waves) *waves = it->second.waves;
   return BARD_OK;
 }
 
@@ -753,12 +769,14 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   if (capturing(st)) return fail(BARD_E_CAPTURE, "autotuning allocates and synchronises; not under capture");
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, st))) return rc;
-  SpecKernel* sk = nullptr;
-  if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, true, &sk))) return rc;
+  // both forms when the tree splits over several waves; else the one form
+  const int nforms = spec_waves(m, dtype == BARD_F64, false) > 1 ? 2 : 1;
+  SpecKernel* sk[2] = {nullptr, nullptr};
+  for (int f = 0; f < nforms; ++f)
+    if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, f, true, &sk[f]))) return rc;
   // Scratch arrays for the largest batch tried, inputs filled with 0.1 (the
   // kernels have no data-dependent branches at these values).
-  const int64_t kBatches[4] = {1024, 4096, 16384, 65536};
-  const int64_t Bmax = kBatches[3];
+  const int64_t Bmax = kSpecTierBatch[kSpecTiers - 1];
   const size_t rs = dtype == BARD_F64 ? 8 : 4;
   const int64_t nin = (int64_t)m->nq + 2 * m->nv, nout = (int64_t)m->nv + (int64_t)m->nv * m->nv + 6LL * m->nv * n_ee;
   void* buf = nullptr;
@@ -775,12 +793,11 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
       return fail(BARD_E_DEVICE, "upload of the autotuning inputs failed");
     }
   }
-  int64_t chosen = INT64_MAX;
-  double t_gen[4] = {0}, t_spec[4] = {0};
+  double t[kSpecTiers][3] = {};  // generic, split, whole
   auto go = [&](auto zero) -> int {
     using R = decltype(zero);
-    for (int k = 0; k < 4; ++k) {
-      const int64_t B = kBatches[k];
+    for (int k = 0; k < kSpecTiers; ++k) {
+      const int64_t B = kSpecTierBatch[k];
       R* base = (R*)buf;
       Args<R> a = blank_args<R>(B);
       a.q = base;
@@ -793,8 +810,9 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
       a.sq_k = a.sqd_k = a.sqdd_k = a.st_k = a.sM_k = a.sJ_k = B;
       const int reps = B >= 16384 ? 5 : 20;
       int r = time_launches([&] { return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, st); },
-                            st, reps, &t_gen[k]);
-      if (!r) r = time_launches([&] { return spec_launch<R>(sk, a, m->g, st); }, st, reps, &t_spec[k]);
+                            st, reps, &t[k][0]);
+      for (int f = 0; f < nforms && !r; ++f)
+        r = time_launches([&] { return spec_launch<R>(sk[f], a, m->g, st); }, st, reps, &t[k][1 + f]);
       if (r) return r;
     }
     return BARD_OK;
@@ -803,27 +821,38 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   (void)hipDeviceSynchronize();
   (void)hipFree(buf);
   if (rc) return rc;
-  // the smallest tried batch from which the specialised kernel is faster at every larger one
-  for (int k = 3; k >= 0 && t_spec[k] < t_gen[k]; --k) chosen = kBatches[k];
+  // each tier to the fastest of the generic kernel and the forms
+  int tiers[2] = {0, 0};
+  int64_t first = -1;
+  for (int k = 0; k < kSpecTiers; ++k) {
+    int best = 0;
+    for (int f = 0; f < nforms; ++f)
+      if (t[k][1 + f] < t[k][best]) best = 1 + f;
+    if (best > 0) {
+      tiers[best - 1] |= 1 << k;
+      if (first < 0) first = k == 0 ? 0 : kSpecTierBatch[k];
+    }
+  }
   {
     std::lock_guard<std::mutex> lk(m->mu);
-    sk->route = chosen != INT64_MAX;
-    sk->route_min_batch = chosen;
-    bool any = false;
-    for (const auto& d : m->dev)
-      for (const auto& kv : d.spec) any = any || kv.second.route;
-    m->spec_route.store(any);
+    for (int f = 0; f < nforms; ++f) sk[f]->route_tiers = tiers[f];
+    for (int f = nforms; f < 2; ++f) {  // a form not timed (same code as the split one) takes no calls
+      auto it = dc->spec.find(spec_key((int)dtype, (int)frame, ee, f));
+      if (it != dc->spec.end()) it->second.route_tiers = 0;
+    }
+    spec_refresh_route(m);
   }
-  if (min_batch) *min_batch = chosen == INT64_MAX ? -1 : chosen;
+  if (min_batch) *min_batch = first;
   return BARD_OK;
 }
 
 int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
-                                  bard_frame frame, char* buf, int64_t cap, int64_t* len) {
+                                  bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len) {
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64);
+  if (flags & ~BARD_SPEC_WHOLE) return fail(BARD_E_ARG, "unknown flags");
+  const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, spec_form(flags) == 1);
   if (len) *len = (int64_t)src.size();
   if (buf && cap > 0) {
     const size_t k = std::min<size_t>((size_t)cap - 1, src.size());
@@ -1072,8 +1101,8 @@ int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, co
     if (m->spec_route.load()) {
       DeviceCopy* dc = nullptr;
       if ((rc = ensure_device(m, &dc, (hipStream_t)stream))) return rc;
-      if (SpecKernel* sk = spec_lookup(m, dc, (int)dtype, (int)frame, n_ee, ee_body, B))
-        return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
+      SpecKernel* sk = spec_lookup(m, dc, (int)dtype, (int)frame, n_ee, ee_body, B);
+      if (sk && spec_fits(a)) return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
     }
     return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
   };

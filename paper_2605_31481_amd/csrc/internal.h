@@ -33,22 +33,34 @@ constexpr int kSpecMaxDepth = 32;
 constexpr int kSpecMaxWalkSteps = 1500;
 // Model-specialised chain kernels (specialize.cpp).  Key of one (precision,
 // frame, end-effector set) in DeviceCopy::spec.
-std::string spec_key(int dtype, int frame, const std::vector<int>& ee);
-// Source text of the kernel for one (end-effector set, frame, precision).
-std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64);
+std::string spec_key(int dtype, int frame, const std::vector<int>& ee, int form);
+// Batch tiers of the routing: [0, 4096), [4096, 16384), [16384, 65536),
+// [65536, inf); autotuning times each at its lower bound (1024 for the first).
+constexpr int kSpecTiers = 4;
+constexpr int64_t kSpecTierBatch[kSpecTiers] = {1024, 4096, 16384, 65536};
+int spec_tier(int64_t B);
+// Source text of the kernel for one (end-effector set, frame, precision);
+// whole: one wave walks the whole tree (no split over limbs).
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole);
+// Waves per workgroup of that kernel (64 instances per workgroup).
+int spec_waves(const bard_model* m, bool fp64, bool whole);
 // Number of structural-zero rows (M entries of unrelated dofs, J rows off an
 // end effector's path) the kernel writes.
 int spec_zero_rows(const bard_model* m, const std::vector<int>& ee);
 // Compile source to a gfx950 code object with hipRTC (no device needed).
 int spec_compile(const std::string& src, std::vector<char>* code, std::string* log);
 // Compile (once) and, if `load`, load on the device of `dc`; *out points into dc->spec.
-int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, bool load,
-                 SpecKernel** out);
+int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, int form,
+                 bool load, SpecKernel** out);
 // The routed specialised kernel for a chain call of batch B, or null.
 SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int n_ee, const int32_t* ee,
                         int64_t B);
 // Launch a specialised chain kernel with a chain call's arguments.
 template <class Real>
 int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st);
+// Whether every lane's byte offset into each array of a chain call fits the
+// 32 bits the specialised kernels address with (else the generic kernel runs).
+template <class Real>
+bool spec_fits(const Args<Real>& a);
 
 }  // namespace bard

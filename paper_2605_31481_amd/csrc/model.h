@@ -69,10 +69,11 @@ struct SpecKernel {
   void* fn = nullptr;   // hipFunction_t
   int vgprs = 0, scratch = 0;
   int zero_rows = 0;  // structural-zero rows of M and J
+  int waves = 1;      // waves per workgroup (64 instances)
   int64_t slots = 0;  // 64-lane workgroups the device holds at once at this register count
   double compile_s = 0.0;
-  bool route = false;
-  int64_t route_min_batch = 0;  // routed chain calls need at least this batch
+  int form = 0;         // 0: split over waves by limbs, 1: one wave per instance over the whole tree
+  int route_tiers = 0;  // bit k: chain calls whose batch falls in tier k (spec_tier) launch this kernel
 };
 
 struct DeviceCopy {

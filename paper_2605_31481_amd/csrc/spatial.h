@@ -21,9 +21,26 @@ namespace bard {
 // x^17), then the quadrant k mod 4 selects and signs the pair.  Arguments
 // beyond 1e5 rad (where the three-part reduction loses accuracy) fall back to
 // the device library.
+// The large-argument path stays out of line: it is rarely taken and would
+// otherwise be inlined at every revolute joint of unrolled code.
+struct SinCos32 { float s, c; };
+struct SinCos64 { double s, c; };
+__device__ __noinline__ SinCos32 sincos_big(float x) {
+  SinCos32 r;
+  sincosf(x, &r.s, &r.c);
+  return r;
+}
+__device__ __noinline__ SinCos64 sincos_big(double x) {
+  SinCos64 r;
+  sincos(x, &r.s, &r.c);
+  return r;
+}
+
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) {
   if (fabsf(x) > 1e5f) {
-    sincosf(x, s, c);
+    const SinCos32 r = sincos_big(x);
+    *s = r.s;
+    *c = r.c;
     return;
   }
   const float k = rintf(x * 0.6366197466850281f);
@@ -49,7 +66,9 @@ __device__ __forceinline__ void sincos_r(float x, float* s, float* c) {
 
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) {
   if (fabs(x) > 1e5) {
-    sincos(x, s, c);
+    const SinCos64 r = sincos_big(x);
+    *s = r.s;
+    *c = r.c;
     return;
   }
   const double k = rint(x * 0.6366197723675814);

@@ -3,16 +3,21 @@
 // constant a literal, the traversal unrolled body by body -- and compiles it
 // at run time with hipRTC.
 //
-// Mapping.  One lane per instance, all lanes of a wave at the same body at the
-// same time, so every constant is wave-uniform and folds into the
-// instructions; no tables are staged, no lanes exchange state and no barrier
-// separates levels.  The code walks the tree depth first: entering a body it
-// composes the joint transform (eqs. (4)-(5)), the world pose, the axis and
-// the velocity and acceleration; leaving it (after its children) it forms the
-// subtree force and composite inertia, the torque, the mass-matrix column
+// Mapping.  One lane per instance, 64 instances per workgroup, all lanes of a
+// wave at the same body at the same time, so every constant is wave-uniform
+// and folds into the instructions; no tables are staged.  Entering a body the
+// code composes the joint transform (eqs. (4)-(5)), the world pose, the axis
+// and the velocity and acceleration; leaving it (after its children) it forms
+// the subtree force and composite inertia, the torque, the mass-matrix column
 // and, walking up the ancestors, the entries that couple it to them.  Every
 // index is known when the code is written, so ancestors' state stays in
-// registers.
+// registers.  Two forms: the whole tree in one wave, or split over the waves
+// of the workgroup by limbs (SplitPlan below), which shortens the serial
+// chain of instructions each wave issues -- the bound when a batch leaves most
+// of the device idle.  Products with the zero half of a motion-subspace
+// column and with zero inertial parameters are not emitted; every input is
+// loaded ahead of the code that uses it; every output is addressed by a
+// wave-uniform row base plus a 32-bit per-lane offset.
 //
 // Frames.  Motion and force vectors are kept about each body's own origin
 // with world axes: a child's state is its parent's moved by the link offset
@@ -42,19 +47,129 @@ const char kSpatialHeader[] =
 #include "spatial_h.inc"
     ;
 
+// How one instance's work is spread over the waves of a workgroup.  The
+// trunk is every body with two or more children and all their ancestors; what
+// hangs off it (or off the world, outside the trunk) are limbs, each a chain.
+// Every wave computes the trunk's kinematics, then one or more whole limbs:
+// their poses, torques, Jacobians, mass-matrix columns and the entries coupling
+// them to the trunk (the walks go up through the trunk's state, which each wave
+// holds).  A limb's subtree force and composite inertia, moved to its trunk
+// parent's origin, go to LDS; after one barrier the last wave (the least
+// loaded one, which also forms the trunk's body forces beforehand) sums the
+// trunk.  Limbs are dealt to at most kMaxWaves waves, longest first, onto the
+// least loaded wave.  A tree that is one chain keeps a single wave.
+struct SplitPlan {
+  static constexpr int kMaxWaves = 8;
+  bool split = false;
+  int waves = 1;
+  std::vector<char> trunk;
+  std::vector<std::vector<int>> limbs;  // bodies root first
+  std::vector<std::vector<int>> bins;   // limbs per wave; the last wave merges
+  std::vector<int> limb_slot;           // LDS slot of each limb's sum, -1 for a root limb
+  std::vector<char> limb_first;         // first limb writing its slot
+  std::vector<int> slot_body;           // trunk body each slot adds into
+};
+
+SplitPlan make_plan(const bard_model* m, bool whole, bool fp64) {
+  SplitPlan pl;
+  const int n = m->n;
+  pl.trunk.assign(n, 0);
+  if (whole) return pl;
+  for (int i = 0; i < n; ++i)
+    if (m->children[i].size() >= 2)
+      for (int k = i; k >= 0 && !pl.trunk[k]; k = m->parent[k]) pl.trunk[k] = 1;
+  std::vector<double> cost;
+  for (int i = 0; i < n; ++i) {
+    if (pl.trunk[i] || (m->parent[i] >= 0 && !pl.trunk[m->parent[i]])) continue;
+    std::vector<int> chain;
+    double c = 0;
+    for (int k = i;; k = m->children[k][0]) {
+      chain.push_back(k);
+      int depth = 0;
+      for (int a = m->parent[k]; a >= 0; a = m->parent[a]) ++depth;
+      c += 12.0 + (double)m->nvi[k] * depth;  // a body's forward pass ~ 12 steps of its mass-matrix walks
+      if (m->children[k].empty()) break;
+    }
+    pl.limbs.push_back(chain);
+    cost.push_back(c);
+  }
+  const int nl = (int)pl.limbs.size();
+  if (nl < 2) {
+    pl.trunk.assign(n, 0);
+    pl.limbs.clear();
+    return pl;
+  }
+  pl.waves = std::min(nl, SplitPlan::kMaxWaves);
+  std::vector<int> order(nl);
+  for (int l = 0; l < nl; ++l) order[l] = l;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<std::vector<int>> bins(pl.waves);
+  std::vector<double> load(pl.waves, 0.0);
+  for (int l : order) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    bins[w].push_back(l);
+    load[w] += cost[l];
+  }
+  std::vector<int> wo(pl.waves);
+  for (int w = 0; w < pl.waves; ++w) wo[w] = w;
+  std::stable_sort(wo.begin(), wo.end(), [&](int a, int b) { return load[a] > load[b]; });
+  for (int w : wo) pl.bins.push_back(bins[w]);
+  pl.limb_slot.assign(nl, -1);
+  pl.limb_first.assign(nl, 0);
+  for (const auto& bin : pl.bins) {
+    std::vector<std::pair<int, int>> seen;  // (trunk body, slot) within this wave
+    for (int l : bin) {
+      const int at = m->parent[pl.limbs[l][0]];
+      if (at < 0) continue;
+      int sl = -1;
+      for (const auto& [body, slot] : seen)
+        if (body == at) sl = slot;
+      if (sl < 0) {
+        sl = (int)pl.slot_body.size();
+        pl.slot_body.push_back(at);
+        seen.push_back({at, sl});
+        pl.limb_first[l] = 1;
+      }
+      pl.limb_slot[l] = sl;
+    }
+  }
+  // LDS: 16 values per slot and lane; keep within 64 KB
+  if (pl.slot_body.size() * 16 * 64 * (fp64 ? 8 : 4) > 65536) return make_plan(m, true, fp64);
+  pl.split = true;
+  return pl;
+}
+
 // Emits the source text of one specialised chain kernel.
 class Emitter {
  public:
-  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64)
-      : m_(m), ee_(ee), frame_(frame), fp64_(fp64) {}
+  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole)
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), pl_(make_plan(m, whole, fp64)), split_(pl_.split) {
+    trunk_ = pl_.trunk;
+    slot_body_ = pl_.slot_body;
+  }
 
   std::string source() {
     o_ << "// generated: fused RNEA + CRBA + Jacobian for one tree (" << m_->n << " bodies, nv " << m_->nv
        << ", " << ee_.size() << " end effectors, frame " << frame_ << ", " << (fp64_ ? "FP64" : "FP32")
        << ")\n#include \"spatial.h\"\n";
     o_ << "typedef " << (fp64_ ? "double" : "float") << " Real;\n";
+    o_ << "template <class T>\n"
+          "__device__ __forceinline__ T* bard_at(T* base, long long k, long long sk, unsigned ob) {\n"
+          "  return (T*)((const char*)(base + k * sk) + ob);\n"
+          "}\n"
+          "#define Q(k) (*bard_at(q, (k), sq_k, oq_))\n"
+          "#define QD(k) (*bard_at(qd, (k), sqd_k, oqd_))\n"
+          "#define QDD(k) (*bard_at(qdd, (k), sqdd_k, oqdd_))\n"
+          "#define TAU(k) bard_at(tau, (k), st_k, ot_)\n"
+          "#define MA(k) bard_at(M, (k), sM_k, oM_)\n"
+          "#define JA(k) bard_at(J, (k), sJ_k, oJ_)\n"
+          "#define Qv(k) Qv_##k\n"
+          "#define QDv(k) QDv_##k\n"
+          "#define QDDv(k) QDDv_##k\n";
     emit_zero_tables();
-    o_ << "extern \"C\" __global__ void __launch_bounds__(64) bard_spec_chain(\n"
+    const int nw = pl_.waves;
+    o_ << "static constexpr int NW = " << nw << ";  // waves per workgroup, 64 instances\n";
+    o_ << "extern \"C\" __global__ void __launch_bounds__(" << 64 * nw << ") bard_spec_chain(\n"
           "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ qdd,\n"
           "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
           "    long long sq_b, long long sq_k, long long sqd_b, long long sqd_k, long long sqdd_b, long long sqdd_k,\n"
@@ -72,21 +187,116 @@ class Emitter {
           "      const long long r = u / nch, c = u - r * nch;\n"
           "      Real* row = r < NZM ? M + (long long)ZM[r] * sM_k : J + (long long)ZJ[r - NZM] * sJ_k;\n"
           "      const long long end = per < (c + 1) * 1024 ? per : (c + 1) * 1024;\n"
-          "      for (long long j = c * 1024 + threadIdx.x; j < end; j += 64)\n"
+          "      for (long long j = c * 1024 + threadIdx.x; j < end; j += 64 * NW)\n"
           "        *reinterpret_cast<Zv*>(row + j * V) = zero;\n"
           "    }\n"
           "    return;\n"
           "  }\n"
-          "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
-          "  if (b >= B) return;\n"
-          "  const Real* qb = q + b * sq_b;\n  const Real* qdb = qd + b * sqd_b;\n"
-          "  const Real* qddb = qdd + b * sqdd_b;\n  Real* tb = tau + b * st_b;\n"
-          "  Real* Mb = M + b * sM_b;\n  Real* Jb = J + b * sJ_b;\n";
+          ;
+    if (!split_) {
+      o_ << "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
+            "  if (b >= B) return;\n";
+      pointers();
+      std::vector<int> all(m_->n);
+      for (int i = 0; i < m_->n; ++i) all[i] = i;
+      loads(all);
+      emit_zero_stores();
+      for (int i = 0; i < m_->n; ++i)
+        if (m_->parent[i] < 0) visit(i);
+      o_ << "}\n";
+      return o_.str();
+    }
+    // Every lane of every wave reaches the barrier: lanes past the batch
+    // repeat the last instance (the same values to the same addresses).
+    o_ << "  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);\n"
+          "  const int lane = (int)threadIdx.x & 63;\n"
+          "  long long b = (long long)blockIdx.x * 64 + lane;\n"
+          "  if (b > B - 1) b = B - 1;\n";
+    pointers();
     emit_zero_stores();
+    if (!slot_body_.empty()) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
+    std::vector<int> tb;
     for (int i = 0; i < m_->n; ++i)
-      if (m_->parent[i] < 0) visit(i);
+      if (trunk_[i]) tb.push_back(i);
+    loads(tb);
+    bool any_trunk = false;
+    for (int i = 0; i < m_->n; ++i)
+      if (trunk_[i]) {
+        forward_kin(i);
+        o_ << "  Real " << v("I", i) << "[10], " << v("f", i) << "[6];\n";
+        any_trunk = true;
+      }
+    const int merge = nw - 1;
+    for (int w = 0; w < nw; ++w) {
+      o_ << (w ? "  else if" : "  if") << " (wave == " << w << ") {\n";
+      std::vector<int> lb;
+      for (int l : pl_.bins[w]) lb.insert(lb.end(), pl_.limbs[l].begin(), pl_.limbs[l].end());
+      loads(lb);
+      for (int l : pl_.bins[w]) limb(l);
+      if (w == merge) {
+        for (int i = 0; i < m_->n; ++i)
+          if (trunk_[i]) body_force(i, false);
+        for (size_t e = 0; e < ee_.size(); ++e)
+          if (trunk_[ee_[e]]) jacobian((int)e);
+      }
+      o_ << "  }\n";
+    }
+    if (any_trunk) {
+      o_ << "  __syncthreads();\n  if (wave == " << merge << ") {\n";
+      for (int i = m_->n - 1; i >= 0; --i)
+        if (trunk_[i]) backward(i);
+      o_ << "  }\n";
+    }
     o_ << "}\n";
     return o_.str();
+  }
+
+  // Each lane's byte offset of its instance in every array (32 bits; the
+  // host routes only batches where they fit), added to a wave-uniform row
+  // base: entries are addressed by a scalar base and one per-lane offset.
+  // The inputs of the given bodies, loaded at once ahead of the code that
+  // uses them (one memory round trip instead of one per body).
+  void loads(const std::vector<int>& bodies) {
+    for (int i : bodies) {
+      const int nq = m_->jtype[i] == J_FREE ? 7 : 1;
+      for (int k = 0; k < nq; ++k) o_ << "  const Real Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
+      for (int k = 0; k < m_->nvi[i]; ++k)
+        o_ << "  const Real QDv_" << m_->vi[i] + k << " = QD(" << m_->vi[i] + k << "), QDDv_" << m_->vi[i] + k
+           << " = QDD(" << m_->vi[i] + k << ");\n";
+    }
+  }
+
+  void pointers() {
+    o_ << "  const unsigned oq_ = (unsigned)(b * sq_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oqd_ = (unsigned)(b * sqd_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oqdd_ = (unsigned)(b * sqdd_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned ot_ = (unsigned)(b * st_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oM_ = (unsigned)(b * sM_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oJ_ = (unsigned)(b * sJ_b) * (unsigned)sizeof(Real);\n";
+  }
+
+  // One limb (a chain): forward, its end effectors' Jacobians, backward with
+  // the mass-matrix walks up to the root, then its sum moved to the trunk
+  // parent's origin into its LDS slot.
+  void limb(int l) {
+    const std::vector<int>& ch = pl_.limbs[l];
+    o_ << "  {\n";
+    for (int i : ch) {
+      forward(i);
+      for (size_t e = 0; e < ee_.size(); ++e)
+        if (ee_[e] == i) jacobian((int)e);
+    }
+    for (auto it = ch.rbegin(); it != ch.rend(); ++it) backward(*it);
+    const int sl = pl_.limb_slot[l], r = ch[0];
+    if (sl >= 0) {
+      const char* op = pl_.limb_first[l] ? " = " : " += ";
+      o_ << "  {\n    Real t_[3], S_[10];\n    bard::cross3(" << v("r", r) << ", " << v("F", r) << " + 3, t_);\n"
+         << "    for (int k = 0; k < 3; ++k) {\n      xch_[(" << sl * 16 << " + k) * 64 + lane]" << op << v("F", r)
+         << "[k] + t_[k];\n      xch_[(" << sl * 16 + 3 << " + k) * 64 + lane]" << op << v("F", r)
+         << "[3 + k];\n    }\n    bard::shift_inertia(" << v("K", r) << ", " << v("r", r) << ", S_);\n"
+         << "    for (int k = 0; k < 10; ++k) xch_[(" << sl * 16 + 6 << " + k) * 64 + lane]" << op << "S_[k];\n  }\n";
+    }
+    o_ << "  }\n";
   }
 
  private:
@@ -94,6 +304,10 @@ class Emitter {
   std::vector<int> ee_;
   int frame_;
   bool fp64_;
+  SplitPlan pl_;
+  bool split_;
+  std::vector<char> trunk_;
+  std::vector<int> slot_body_;
   std::ostringstream o_;
 
   double c(int body, int k) const { return fp64_ ? m_->cst64[body * CST + k] : (double)m_->cst32[body * CST + k]; }
@@ -136,9 +350,10 @@ class Emitter {
   }
 
   void emit_zero_stores() {
+    const char* first = split_ ? "wave" : "0";
     o_ << "  if (zero_blocks == 0) {\n"
-          "    for (int i = 0; i < NZM; ++i) bard::put(&Mb[(long long)ZM[i] * sM_k], Real(0), true);\n"
-          "    for (int i = 0; i < NZJ; ++i) bard::put(&Jb[(long long)ZJ[i] * sJ_k], Real(0), true);\n"
+          "    for (int i = " << first << "; i < NZM; i += NW) bard::put(MA(ZM[i]), Real(0), true);\n"
+          "    for (int i = " << first << "; i < NZJ; i += NW) bard::put(JA(ZJ[i]), Real(0), true);\n"
           "  }\n";
   }
 
@@ -176,22 +391,27 @@ class Emitter {
 
   // ---- entering body i: pose, axis, velocity, acceleration, body force ----
   void forward(int i) {
+    forward_kin(i);
+    body_force(i, true);
+  }
+
+  void forward_kin(int i) {
     const int p = m_->parent[i], t = m_->jtype[i], qi = m_->qi[i], vi = m_->vi[i];
     o_ << "  // body " << i << " (" << (t == J_REV ? "revolute" : t == J_PRI ? "prismatic" : "free") << ", parent "
        << p << ")\n";
     o_ << "  Real " << v("R", i) << "[9], " << v("p", i) << "[3], " << v("r", i) << "[3], " << v("a", i) << "[3], "
-       << v("v", i) << "[6], " << v("c", i) << "[6], " << v("I", i) << "[10], " << v("f", i) << "[6];\n  {\n";
+       << v("v", i) << "[6], " << v("c", i) << "[6];\n  {\n";
     if (t == J_FREE) {
-      o_ << "    Real x_ = qb[" << qi + 3 << " * sq_k], y_ = qb[" << qi + 4 << " * sq_k], z_ = qb[" << qi + 5
-         << " * sq_k], w_ = qb[" << qi + 6 << " * sq_k];\n"
+      o_ << "    Real x_ = Qv(" << qi + 3 << "), y_ = Qv(" << qi + 4 << "), z_ = Qv(" << qi + 5
+         << "), w_ = Qv(" << qi + 6 << ");\n"
             "    const Real n_ = Real(1) / sqrt(x_ * x_ + y_ * y_ + z_ * z_ + w_ * w_);\n"
             "    x_ *= n_; y_ *= n_; z_ *= n_; w_ *= n_;\n"
             "    const Real Rq[9] = {Real(1) - Real(2) * (y_ * y_ + z_ * z_), Real(2) * (x_ * y_ - z_ * w_),"
             " Real(2) * (x_ * z_ + y_ * w_), Real(2) * (x_ * y_ + z_ * w_), Real(1) - Real(2) * (x_ * x_ + z_ * z_),"
             " Real(2) * (y_ * z_ - x_ * w_), Real(2) * (x_ * z_ - y_ * w_), Real(2) * (y_ * z_ + x_ * w_),"
             " Real(1) - Real(2) * (x_ * x_ + y_ * y_)};\n";
-      o_ << "    const Real P_[3] = {qb[" << qi << " * sq_k], qb[" << qi + 1 << " * sq_k], qb[" << qi + 2
-         << " * sq_k]};\n";
+      o_ << "    const Real P_[3] = {Qv(" << qi << "), Qv(" << qi + 1 << "), Qv(" << qi + 2
+         << ")};\n";
       for (int r = 0; r < 3; ++r)
         for (int col = 0; col < 3; ++col)
           o_ << "    " << v("R", i) << "[" << 3 * r + col << "] = "
@@ -208,9 +428,9 @@ class Emitter {
       // velocity coordinates [v; w] in the body frame -> world axes at the body origin
       o_ << "    Real vb_[3], wb_[3], ab_[3], wd_[3];\n";
       for (int k = 0; k < 3; ++k)
-        o_ << "    vb_[" << k << "] = qdb[" << vi + k << " * sqd_k]; wb_[" << k << "] = qdb[" << vi + 3 + k
-           << " * sqd_k]; ab_[" << k << "] = qddb[" << vi + k << " * sqdd_k]; wd_[" << k << "] = qddb["
-           << vi + 3 + k << " * sqdd_k];\n";
+        o_ << "    vb_[" << k << "] = QDv(" << vi + k << "); wb_[" << k << "] = QDv(" << vi + 3 + k
+           << "); ab_[" << k << "] = QDDv(" << vi + k << "); wd_[" << k << "] = QDDv("
+           << vi + 3 + k << ");\n";
       const std::string R = v("R", i);
       for (int r = 0; r < 3; ++r) {
         auto row = [&](const char* x) {
@@ -225,10 +445,10 @@ class Emitter {
     } else {
       // joint transform (eqs. (4)-(5))
       if (t == J_REV)
-        o_ << "    Real s_, c_;\n    bard::sincos_r(qb[" << qi << " * sq_k], &s_, &c_);\n"
+        o_ << "    Real s_, c_;\n    bard::sincos_r(Qv(" << qi << "), &s_, &c_);\n"
            << "    const Real o_ = Real(1) - c_;\n";
       else
-        o_ << "    const Real x_ = qb[" << qi << " * sq_k];\n";
+        o_ << "    const Real x_ = Qv(" << qi << ");\n";
       o_ << "    Real Rpc[9], tpc[3];\n";
       for (int k = 0; k < 9; ++k)
         o_ << "    Rpc[" << k << "] = "
@@ -277,7 +497,7 @@ class Emitter {
            << "      for (int k = 0; k < 3; ++k) { as_[k] = " << v("c", p) << "[k]; as_[3 + k] = " << v("c", p)
            << "[3 + k] + t_[k]; }\n    }\n";
       }
-      o_ << "    const Real qd_ = qdb[" << vi << " * sqd_k], qdd_ = qddb[" << vi << " * sqdd_k];\n"
+      o_ << "    const Real qd_ = QDv(" << vi << "), qdd_ = QDDv(" << vi << ");\n"
          << "    Real sq_[3], t_[3];\n    for (int k = 0; k < 3; ++k) sq_[k] = " << v("a", i) << "[k] * qd_;\n";
       const int off = (t == J_REV) ? 0 : 3;  // s = [a; 0] revolute, [0; a] prismatic
       o_ << "    for (int k = 0; k < 6; ++k) " << v("v", i) << "[k] = vs_[k];\n"
@@ -294,11 +514,36 @@ class Emitter {
         o_ << "    bard::cross3(" << v("v", i) << ", sq_, t_);\n    for (int k = 0; k < 3; ++k) " << v("c", i)
            << "[3 + k] += t_[k];\n";
     }
-    // body force about the body origin: f = I a + v x* I v
-    o_ << "    const Real pi_[10] = {";
-    for (int k = 0; k < 10; ++k) o_ << (k ? ", " : "") << lit(c(i, C_PI + k));
-    o_ << "};\n    bard::rotate_inertia(pi_, " << v("R", i) << ", " << v("I", i) << ");\n"
-       << "    Real Iv_[6], vIv_[6];\n    bard::inertia_mul(" << v("I", i) << ", " << v("v", i) << ", Iv_);\n"
+    o_ << "  }\n";
+  }
+
+  // body force about the body origin, f = I a + v x* I v, into I_i and f_i
+  // (declared here, or beforehand in an outer scope)
+  void body_force(int i, bool declare) {
+    if (declare) o_ << "  Real " << v("I", i) << "[10], " << v("f", i) << "[6];\n";
+    // [m, R h, R Ibar R^T] about the body origin, world axes; the constant
+    // parameters as literals, zero ones left out
+    const std::string R = v("R", i), I = v("I", i);
+    auto Rk = [&](int k) { return R + "[" + std::to_string(k) + "]"; };
+    const double pi[10] = {c(i, C_PI), c(i, C_PI + 1), c(i, C_PI + 2), c(i, C_PI + 3), c(i, C_PI + 4),
+                           c(i, C_PI + 5), c(i, C_PI + 6), c(i, C_PI + 7), c(i, C_PI + 8), c(i, C_PI + 9)};
+    const double Ib[9] = {pi[4], pi[5], pi[7], pi[5], pi[6], pi[8], pi[7], pi[8], pi[9]};
+    o_ << "  {\n    " << I << "[0] = " << lit(pi[0]) << ";\n";
+    for (int r = 0; r < 3; ++r)
+      o_ << "    " << I << "[" << 1 + r << "] = "
+         << lin({{pi[1], Rk(3 * r)}, {pi[2], Rk(3 * r + 1)}, {pi[3], Rk(3 * r + 2)}}) << ";\n";
+    o_ << "    Real X_[9];\n";
+    for (int r = 0; r < 3; ++r)
+      for (int col = 0; col < 3; ++col)
+        o_ << "    X_[" << 3 * r + col << "] = "
+           << lin({{Ib[col], Rk(3 * r)}, {Ib[3 + col], Rk(3 * r + 1)}, {Ib[6 + col], Rk(3 * r + 2)}}) << ";\n";
+    const int ij[6][2] = {{0, 0}, {0, 1}, {1, 1}, {0, 2}, {1, 2}, {2, 2}};
+    for (int k = 0; k < 6; ++k) {
+      const int a = ij[k][0], b = ij[k][1];
+      o_ << "    " << I << "[" << 4 + k << "] = X_[" << 3 * a << "] * " << Rk(3 * b) << " + X_[" << 3 * a + 1 << "] * "
+         << Rk(3 * b + 1) << " + X_[" << 3 * a + 2 << "] * " << Rk(3 * b + 2) << ";\n";
+    }
+    o_ << "    Real Iv_[6], vIv_[6];\n    bard::inertia_mul(" << v("I", i) << ", " << v("v", i) << ", Iv_);\n"
        << "    bard::crf(" << v("v", i) << ", Iv_, vIv_);\n    bard::inertia_mul(" << v("I", i) << ", " << v("c", i)
        << ", " << v("f", i) << ");\n    for (int k = 0; k < 6; ++k) " << v("f", i) << "[k] += vIv_[k];\n  }\n";
   }
@@ -316,10 +561,62 @@ class Emitter {
     return d < 3 ? "{" + z(3) + col + "}" : "{" + col + ", Real(0), Real(0), Real(0)}";
   }
 
+  // The non-zero halves of motion-subspace column d of body j: angular
+  // (w) and linear (u) parts as three expressions each, empty when zero.
+  void s_parts(int j, int d, std::vector<std::string>* w, std::vector<std::string>* u) const {
+    const int t = m_->jtype[j];
+    const std::string a = v("a", j), R = v("R", j);
+    w->clear();
+    u->clear();
+    auto col = [&](int e) {
+      return std::vector<std::string>{R + "[" + std::to_string(e) + "]", R + "[" + std::to_string(3 + e) + "]",
+                                      R + "[" + std::to_string(6 + e) + "]"};
+    };
+    if (t == J_REV) *w = {a + "[0]", a + "[1]", a + "[2]"};
+    else if (t == J_PRI) *u = {a + "[0]", a + "[1]", a + "[2]"};
+    else if (d < 3) *u = col(d);
+    else *w = col(d - 3);
+  }
+
+  // s_j,d . f for a force f (name[0..5]), structural zeros left out
+  std::string dot_s(int j, int d, const std::string& f) const {
+    std::vector<std::string> w, u;
+    s_parts(j, d, &w, &u);
+    std::string e;
+    for (int k = 0; k < 3 && !w.empty(); ++k) e += (e.empty() ? "" : " + ") + w[k] + " * " + f + "[" + std::to_string(k) + "]";
+    for (int k = 0; k < 3 && !u.empty(); ++k)
+      e += (e.empty() ? "" : " + ") + u[k] + " * " + f + "[" + std::to_string(3 + k) + "]";
+    return e;
+  }
+
+  // out = K s_j,d for a rigid-body inertia K = [m, h, Ibar]:
+  // [Ibar w + h x u; m u - h x w], with the zero half of s left out
+  void emit_Ks(const std::string& K, int j, int d, const std::string& out) {
+    std::vector<std::string> w, u;
+    s_parts(j, d, &w, &u);
+    auto k = [&](int i) { return K + "[" + std::to_string(i) + "]"; };
+    if (!w.empty()) {
+      o_ << "      " << out << "[0] = " << k(4) << " * " << w[0] << " + " << k(5) << " * " << w[1] << " + " << k(7)
+         << " * " << w[2] << ";\n";
+      o_ << "      " << out << "[1] = " << k(5) << " * " << w[0] << " + " << k(6) << " * " << w[1] << " + " << k(8)
+         << " * " << w[2] << ";\n";
+      o_ << "      " << out << "[2] = " << k(7) << " * " << w[0] << " + " << k(8) << " * " << w[1] << " + " << k(9)
+         << " * " << w[2] << ";\n";
+      o_ << "      " << out << "[3] = " << w[1] << " * " << k(3) << " - " << w[2] << " * " << k(2) << ";\n";
+      o_ << "      " << out << "[4] = " << w[2] << " * " << k(1) << " - " << w[0] << " * " << k(3) << ";\n";
+      o_ << "      " << out << "[5] = " << w[0] << " * " << k(2) << " - " << w[1] << " * " << k(1) << ";\n";
+    } else {
+      o_ << "      " << out << "[0] = " << k(2) << " * " << u[2] << " - " << k(3) << " * " << u[1] << ";\n";
+      o_ << "      " << out << "[1] = " << k(3) << " * " << u[0] << " - " << k(1) << " * " << u[2] << ";\n";
+      o_ << "      " << out << "[2] = " << k(1) << " * " << u[1] << " - " << k(2) << " * " << u[0] << ";\n";
+      for (int i = 0; i < 3; ++i) o_ << "      " << out << "[" << 3 + i << "] = " << k(0) << " * " << u[i] << ";\n";
+    }
+  }
+
   void store_M(int r, int col, const std::string& val) {
     const int nv = m_->nv;
-    o_ << "    bard::put(&Mb[" << r * nv + col << " * sM_k], " << val << ", true);\n";
-    if (r != col) o_ << "    bard::put(&Mb[" << col * nv + r << " * sM_k], " << val << ", true);\n";
+    o_ << "    bard::put(MA(" << r * nv + col << "), " << val << ", true);\n";
+    if (r != col) o_ << "    bard::put(MA(" << col * nv + r << "), " << val << ", true);\n";
   }
 
   // ---- leaving body i: subtree force, torque, composite inertia, M ----
@@ -329,34 +626,38 @@ class Emitter {
        << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] = " << v("f", i) << "[k];\n"
        << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] = " << v("I", i) << "[k];\n";
     for (int ch : m_->children[i]) {
+      if (split_ && trunk_[i] && !trunk_[ch]) continue;  // a limb: its wave's sum arrives through LDS
       o_ << "    {\n      Real t_[3], S_[10];\n      bard::cross3(" << v("r", ch) << ", " << v("F", ch) << " + 3, t_);\n"
          << "      for (int k = 0; k < 3; ++k) { " << v("F", i) << "[k] += " << v("F", ch) << "[k] + t_[k]; "
          << v("F", i) << "[3 + k] += " << v("F", ch) << "[3 + k]; }\n      bard::shift_inertia(" << v("K", ch) << ", "
          << v("r", ch) << ", S_);\n      for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += S_[k];\n    }\n";
     }
+    for (size_t sl = 0; sl < slot_body_.size(); ++sl)
+      if (split_ && slot_body_[sl] == i)
+        o_ << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] += xch_[(" << sl * 16 << " + k) * 64 + lane];\n"
+           << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += xch_[(" << sl * 16 + 6
+           << " + k) * 64 + lane];\n";
     // torque
     const std::string F = v("F", i), a = v("a", i), R = v("R", i);
     if (t == J_REV)
-      o_ << "    bard::put(&tb[" << vi << " * st_k], " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
+      o_ << "    bard::put(TAU(" << vi << "), " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
          << a << "[2] * " << F << "[2], true);\n";
     else if (t == J_PRI)
-      o_ << "    bard::put(&tb[" << vi << " * st_k], " << a << "[0] * " << F << "[3] + " << a << "[1] * " << F << "[4] + "
+      o_ << "    bard::put(TAU(" << vi << "), " << a << "[0] * " << F << "[3] + " << a << "[1] * " << F << "[4] + "
          << a << "[2] * " << F << "[5], true);\n";
     else
       for (int d = 0; d < 6; ++d) {
         const int e = d % 3, base = d < 3 ? 3 : 0;  // [f; n] in the body frame: R^T f, R^T n
-        o_ << "    bard::put(&tb[" << vi + d << " * st_k], " << R << "[" << e << "] * " << F << "[" << base << "] + " << R
+        o_ << "    bard::put(TAU(" << vi + d << "), " << R << "[" << e << "] * " << F << "[" << base << "] + " << R
            << "[" << 3 + e << "] * " << F << "[" << base + 1 << "] + " << R << "[" << 6 + e << "] * " << F << "["
            << base + 2 << "], true);\n";
       }
     // mass-matrix columns of this body's dofs
     for (int d = 0; d < nd; ++d) {
-      o_ << "    {\n      const Real s_[6] = " << s_col(i, d) << ";\n      Real fc_[6];\n      bard::inertia_mul("
-         << v("K", i) << ", s_, fc_);\n";
+      o_ << "    {\n      Real fc_[6];\n";
+      emit_Ks(v("K", i), i, d, "fc_");
       for (int d2 = 0; d2 <= d; ++d2) {
-        o_ << "      {\n        const Real u_[6] = " << s_col(i, d2) << ";\n";
-        o_ << "        const Real m_ = u_[0] * fc_[0] + u_[1] * fc_[1] + u_[2] * fc_[2] + u_[3] * fc_[3] + u_[4] * fc_[4]"
-              " + u_[5] * fc_[5];\n";
+        o_ << "      {\n        const Real m_ = " << dot_s(i, d2, "fc_") << ";\n";
         store_M(vi + d2, vi + d, "m_");
         o_ << "      }\n";
       }
@@ -366,9 +667,7 @@ class Emitter {
         o_ << "      {\n        Real t_[3];\n        bard::cross3(" << v("r", ch) << ", fc_ + 3, t_);\n"
            << "        for (int k = 0; k < 3; ++k) fc_[k] += t_[k];\n";
         for (int e = 0; e < m_->nvi[j]; ++e) {
-          o_ << "        {\n          const Real u_[6] = " << s_col(j, e) << ";\n"
-             << "          const Real m_ = u_[0] * fc_[0] + u_[1] * fc_[1] + u_[2] * fc_[2] + u_[3] * fc_[3] + u_[4] *"
-                " fc_[4] + u_[5] * fc_[5];\n";
+          o_ << "        {\n          const Real m_ = " << dot_s(j, e, "fc_") << ";\n";
           store_M(m_->vi[j] + e, vi + d, "m_");
           o_ << "        }\n";
         }
@@ -398,7 +697,7 @@ class Emitter {
              << "[k];\n      bard::cross3(s_, d_, l_);\n";
         }
         for (int r = 0; r < 6; ++r)
-          o_ << "      bard::put(&Jb[" << (ei * 6 + r) * nv + col << " * sJ_k], " << (r < 3 ? "l_[" : "s_[")
+          o_ << "      bard::put(JA(" << (ei * 6 + r) * nv + col << "), " << (r < 3 ? "l_[" : "s_[")
              << (r % 3) << "], true);\n";
         o_ << "    }\n";
       }
@@ -417,15 +716,25 @@ class Emitter {
 
 }  // namespace
 
-std::string spec_key(int dtype, int frame, const std::vector<int>& ee) {
-  std::string k = std::to_string(dtype) + ":" + std::to_string(frame) + ":";
+int spec_tier(int64_t B) {
+  int t = 0;
+  while (t + 1 < kSpecTiers && B >= kSpecTierBatch[t + 1]) ++t;
+  return t;
+}
+
+std::string spec_key(int dtype, int frame, const std::vector<int>& ee, int form) {
+  std::string k = std::to_string(form) + ":" + std::to_string(dtype) + ":" + std::to_string(frame) + ":";
   for (int e : ee) k += std::to_string(e) + ",";
   return k;
 }
 
-std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64) {
-  return Emitter(m, ee, frame, fp64).source();
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole) {
+  return Emitter(m, ee, frame, fp64, whole).source();
 }
+
+int spec_waves(const bard_model* m, bool fp64, bool whole) { return make_plan(m, whole, fp64).waves; }
+
+
 
 int spec_zero_rows(const bard_model* m, const std::vector<int>& ee) {
   // unrelated dof pairs of M plus the off-path rows of J
@@ -482,9 +791,9 @@ int spec_compile(const std::string& src, std::vector<char>* code, std::string* l
 }
 
 // Compiles (once per key) and loads on the current device.
-int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, bool load,
-                 SpecKernel** out) {
-  const std::string key = spec_key(dtype, frame, ee);
+int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, int form,
+                 bool load, SpecKernel** out) {
+  const std::string key = spec_key(dtype, frame, ee, form);
   std::lock_guard<std::mutex> lk(m->mu);
   auto it = dc->spec.find(key);
   if (it != dc->spec.end() && (it->second.fn || !load)) {
@@ -496,8 +805,11 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
   if (sk.code.empty()) {
     const auto t0 = std::chrono::steady_clock::now();
     std::string log;
-    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64), &sk.code, &log);
+    const bool whole = form == 1;
+    sk.form = form;
+    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64, whole), &sk.code, &log);
     sk.zero_rows = spec_zero_rows(m, ee);
+    sk.waves = spec_waves(m, dtype == BARD_F64, whole);
     sk.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000));
   }
@@ -530,7 +842,7 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
       cus = 0;
     }
     const int per_simd = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 1;
-    sk.slots = (int64_t)cus * 4 * per_simd;
+    sk.slots = std::max<int64_t>(1, (int64_t)cus * 4 * per_simd / sk.waves);
   }
   dc->spec[key] = sk;
   *out = &dc->spec[key];
@@ -541,10 +853,13 @@ SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int
                         int64_t B) {
   if (!m->spec_route.load()) return nullptr;
   std::vector<int> v(ee, ee + n_ee);
+  const int bit = 1 << spec_tier(B);
   std::lock_guard<std::mutex> lk(m->mu);
-  auto it = dc->spec.find(spec_key(dtype, frame, v));
-  if (it == dc->spec.end() || !it->second.fn || !it->second.route || B < it->second.route_min_batch) return nullptr;
-  return &it->second;
+  for (int form = 0; form < 2; ++form) {
+    auto it = dc->spec.find(spec_key(dtype, frame, v, form));
+    if (it != dc->spec.end() && it->second.fn && (it->second.route_tiers & bit)) return &it->second;
+  }
+  return nullptr;
 }
 
 template <class Real>
@@ -575,7 +890,8 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
                   &st_b, &st_k, &sM_b, &sM_k, &sJ_b, &sJ_k, &B, &g0, &g1, &g2, &main_blocks, &zero_blocks};
   const int64_t grid = main + zb;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
-  if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, st, args, nullptr) !=
+  if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64 * sk->waves, 1, 1, 0, st, args,
+                            nullptr) !=
       hipSuccess) {
     (void)hipGetLastError();
     return fail(BARD_E_DEVICE, "launch of the specialised kernel failed");
@@ -583,6 +899,17 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   return BARD_OK;
 }
 
+template <class Real>
+bool spec_fits(const Args<Real>& a) {
+  const int64_t last = a.B > 0 ? a.B - 1 : 0;
+  const int64_t s[6] = {a.sq_b, a.sqd_b, a.sqdd_b, a.st_b, a.sM_b, a.sJ_b};
+  for (int64_t x : s)
+    if (x < 0 || last * x > (int64_t)(0xffffffffu / sizeof(Real))) return false;
+  return true;
+}
+
+template bool spec_fits<float>(const Args<float>&);
+template bool spec_fits<double>(const Args<double>&);
 template int spec_launch<float>(const SpecKernel*, const Args<float>&, const double*, hipStream_t);
 template int spec_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
 

@@ -2,13 +2,16 @@
 per-tree code behind bard_chain, through the C ABI.
 
 Parity: the routed chain call against the FP64 oracle under the per-entry
-contract (parity_util), FP32 and FP64, both Jacobian frames, fixed and free
-roots, revolute and prismatic joints, single-body trees, batches with a
-ragged tail (the kernel runs 64 instances per workgroup), the instance-major
-layout, a gravity change after compilation, and the headline tree at the
-benchmark's batches (sampled).  Routing: without BARD_SPEC_ROUTE the generic
-kernel keeps the calls (bitwise its own results); trees past the size bound
-are refused with BARD_E_UNSUPPORTED.
+contract (parity_util), both forms (split over waves by limbs, and whole),
+FP32 and FP64, both Jacobian frames, fixed and free roots, revolute and
+prismatic joints, single-body trees, batches with a ragged tail (64 instances
+per workgroup), the instance-major layout, a gravity change after
+compilation, joint angles past 1e5 rad, structural zeros written by extra
+workgroups and by the lanes, and the headline tree at the benchmark's batches
+(sampled).  Routing: without BARD_SPEC_ROUTE the generic kernel keeps the
+calls (bitwise its own results); routing one form takes the calls from the
+other; autotuning routes batch tiers; trees past the size bound are refused
+with BARD_E_UNSUPPORTED.
 """
 
 import numpy as np
@@ -28,14 +31,15 @@ CASES = [("chain7", "float32", 1000, 0), ("chain7", "float64", 65, 1), ("quadrup
          ("rev1", "float32", 5, 1), ("pri1", "float64", 3, 0), ("free1", "float32", 65, 1)]
 
 
+@pytest.mark.parametrize("whole", [False, True])
 @pytest.mark.parametrize("name,dtype,B,frame", CASES)
-def test_specialized_chain_matches_oracle(name, dtype, B, frame):
-    say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame}")
+def test_specialized_chain_matches_oracle(name, dtype, B, frame, whole):
+    say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame} whole={whole}")
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
-    m.specialize(ee, frame=frame, dtype=dtype)
-    assert m.specialized_info(ee, frame=frame, dtype=dtype)["routed"]
+    m.specialize(ee, frame=frame, dtype=dtype, whole=whole)
+    assert m.specialized_info(ee, frame=frame, dtype=dtype, whole=whole)["routed"]
     q, qd, qdd = inputs(tree, B, 5300, dtype)
     tau, M, J = m.chain(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype), ee, frame=frame)
     assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, from_dev(tau), from_dev(M), from_dev(J), dtype,
@@ -61,7 +65,15 @@ def test_routing_and_generic_results():
     spec = m.chain(*d, ee)
     m.specialize(ee, route=False)
     back = m.chain(*d, ee)
+    # routing one form takes every batch from the other
+    m.specialize(ee, route=True)
+    m.specialize(ee, route=True, whole=True)
+    assert not m.specialized_info(ee)["routed"]
+    assert m.specialized_info(ee, whole=True)["route_tiers"] == 15
+    whole = m.chain(*d, ee)
     torch.cuda.synchronize()
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in whole), "float32", label="whole")
+    m.specialize(ee, route=False, whole=True)
     for a, b in zip(generic, kept):
         assert torch.equal(a, b)
     for a, b in zip(generic, back):
@@ -118,24 +130,28 @@ def test_deep_tree_refused():
 
 
 def test_autotune_routes_by_batch():
-    """bard_chain_autotune times both kernels and routes chain calls from the
-    chosen batch up; below it the generic kernel answers (bitwise its own
-    result), and every call meets the contract either way."""
+    """bard_chain_autotune times the generic kernel and both specialised forms
+    and routes each batch tier to the fastest; a tier no form takes runs the
+    generic kernel (bitwise its own result), and every call meets the
+    contract either way."""
     import torch
     tree = synth.humanoid_small()
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
     ref = bard.Model.from_tree(tree)   # never specialised: the generic kernel
     mb = m.autotune_chain(ee)
-    say(f"[gpu] autotuned chain on humanoid_small: specialised from B = {mb}")
-    assert mb in (-1, 1024, 4096, 16384, 65536)
-    for B in (300, 20000):
+    split, whole = m.specialized_info(ee), m.specialized_info(ee, whole=True)
+    say(f"[gpu] autotuned chain on humanoid_small: first specialised batch {mb}, tiers split "
+        f"{split['route_tiers']:04b} whole {whole['route_tiers']:04b}")
+    assert mb in (-1,) + bard.SPEC_TIERS
+    assert split["route_tiers"] & whole["route_tiers"] == 0
+    for B, tier in ((300, 0), (20000, 2)):
         q, qd, qdd = inputs(tree, B, 5700 + B, "float32")
         d = [to_dev(x, "float32") for x in (q, qd, qdd)]
         out = m.chain(*d, ee)
         gen = ref.chain(*d, ee)
         torch.cuda.synchronize()
-        if mb == -1 or B < mb:
+        if not ((split["route_tiers"] | whole["route_tiers"]) >> tier) & 1:
             for a, b in zip(out, gen):
                 assert torch.equal(a, b)
         idx = np.sort(np.random.default_rng(B).choice(B, min(B, 200), replace=False))
@@ -175,3 +191,22 @@ def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype):
     idx[-1] = B
     assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee, *(from_dev(x)[idx] for x in res[1]), dtype,
                  label="ragged")
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_large_joint_angles(dtype):
+    """Angles beyond 1e5 rad take the out-of-line library sine and cosine in
+    the generated code too."""
+    say(f"[gpu] specialised chain, large joint angles {dtype}")
+    tree = synth.chain7()
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize(ee, dtype=dtype)
+    B = 96
+    rng = np.random.default_rng(12)
+    q = rng.uniform(-1.0, 1.0, size=(B, 7)) * np.array([1e6, 3e5, 2e5, np.pi, -np.pi, 1e5, 7e5])
+    qd, qdd = rng.standard_normal((B, 7)), rng.standard_normal((B, 7))
+    if dtype == "float32":
+        q, qd, qdd = (synth.to_fp32_grid(x) for x in (q, qd, qdd))
+    out = m.chain(*(to_dev(x, dtype) for x in (q, qd, qdd)), ee)
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in out), dtype, label="large angles")

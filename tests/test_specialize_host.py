@@ -1,8 +1,9 @@
 """Host side of the model specialiser (no GPU): the generated chain source for
-a tree names every dof's torque, every mass-matrix entry and every Jacobian
-column once or as a structural zero, and hipRTC compiles it for gfx950
-(BARD_SPEC_COMPILE_ONLY), in FP32 and FP64 and both Jacobian frames; trees
-past the size bound are refused."""
+a tree, in both forms (split over waves by limbs, and whole), names every
+dof's torque, every mass-matrix entry and every Jacobian column once or as a
+structural zero, and hipRTC compiles it for gfx950 (BARD_SPEC_COMPILE_ONLY),
+in FP32 and FP64 and both Jacobian frames; the split form gives each limb to
+one wave; trees past the size bound are refused."""
 
 import re
 
@@ -12,12 +13,14 @@ import synth
 from paper_2605_31481_amd import bard
 
 
-@pytest.mark.parametrize("name,dtype,frame", [("chain7", "float32", 0), ("chain7", "float64", 1),
-                                              ("quadruped_spine", "float32", 1), ("free1", "float64", 0)])
-def test_generated_source_compiles(name, dtype, frame):
+@pytest.mark.parametrize("name,dtype,frame,whole", [("chain7", "float32", 0, False), ("chain7", "float64", 1, True),
+                                                    ("quadruped_spine", "float32", 1, False),
+                                                    ("quadruped_spine", "float64", 0, True),
+                                                    ("free1", "float64", 0, False), ("star64", "float32", 0, False)])
+def test_generated_source_compiles(name, dtype, frame, whole):
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
-    m.specialize(tree.ee_bodies, frame=frame, dtype=dtype, compile_only=True)
+    m.specialize(tree.ee_bodies, frame=frame, dtype=dtype, compile_only=True, whole=whole)
 
 
 def _table(src, which):
@@ -27,18 +30,19 @@ def _table(src, which):
     return [int(x) for x in vals[:n]]
 
 
-def test_generated_source_covers_every_output():
+@pytest.mark.parametrize("whole", [False, True])
+def test_generated_source_covers_every_output(whole):
     tree = synth.humanoid_small()
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
-    src = m.specialized_source(ee)
+    src = m.specialized_source(ee, whole=whole)
     nv = tree.nv
-    tau = {int(k) for k in re.findall(r"&tb\[(\d+) \* st_k\]", src)}
+    tau = {int(k) for k in re.findall(r"TAU\((\d+)\)", src)}
     assert tau == set(range(nv))
-    stored = [int(k) for k in re.findall(r"&Mb\[(\d+) \* sM_k\]", src)]
+    stored = [int(k) for k in re.findall(r"MA\((\d+)\)", src)]
     zeros = _table(src, "M")
     assert sorted(stored + zeros) == list(range(nv * nv))
-    jcols = [int(k) for k in re.findall(r"&Jb\[(\d+) \* sJ_k\]", src)]
+    jcols = [int(k) for k in re.findall(r"JA\((\d+)\)", src)]
     jz = _table(src, "J")
     assert sorted(jcols + jz) == list(range(len(ee) * 6 * nv))
     assert "float" in src and "double" not in src
@@ -50,3 +54,18 @@ def test_deep_tree_refused_on_the_host():
     with pytest.raises(bard.BardError) as ei:
         m.specialize(tree.ee_bodies, compile_only=True)
     assert ei.value.status == -7
+
+
+@pytest.mark.parametrize("name,waves", [("humanoid_large", 5), ("humanoid_small", 3), ("quadruped_spine", 4),
+                                        ("chain7", 1), ("free1", 1),
+                                        ("star64", 8)])
+def test_split_form_waves(name, waves):
+    """A branched tree's split form has one wave per limb (at most 8, limbs
+    dealt longest first); a chain keeps one wave; the whole form has one."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    src = m.specialized_source(tree.ee_bodies)
+    assert int(re.search(r"NW = (\d+);", src).group(1)) == waves
+    assert ("__syncthreads" in src) == (waves > 1)
+    whole = m.specialized_source(tree.ee_bodies, whole=True)
+    assert int(re.search(r"NW = (\d+);", whole).group(1)) == 1
