@@ -1102,7 +1102,7 @@ int bard_chain(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, co
       DeviceCopy* dc = nullptr;
       if ((rc = ensure_device(m, &dc, (hipStream_t)stream))) return rc;
       SpecKernel* sk = spec_lookup(m, dc, (int)dtype, (int)frame, n_ee, ee_body, B);
-      if (sk && spec_fits(a)) return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
+      if (sk && spec_fits(a, m->nv, n_ee)) return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
     }
     return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream);
   };

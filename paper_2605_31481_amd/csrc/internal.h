@@ -58,9 +58,10 @@ SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int
 // Launch a specialised chain kernel with a chain call's arguments.
 template <class Real>
 int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st);
-// Whether every lane's byte offset into each array of a chain call fits the
-// 32 bits the specialised kernels address with (else the generic kernel runs).
+// Whether every lane's byte offset into each array of a chain call, and every
+// output row's offset plus the lane's, fits the 32 bits the specialised
+// kernels address with (else the generic kernel runs).
 template <class Real>
-bool spec_fits(const Args<Real>& a);
+bool spec_fits(const Args<Real>& a, int nv, int n_ee);
 
 }  // namespace bard

@@ -160,9 +160,16 @@ class Emitter {
           "#define Q(k) (*bard_at(q, (k), sq_k, oq_))\n"
           "#define QD(k) (*bard_at(qd, (k), sqd_k, oqd_))\n"
           "#define QDD(k) (*bard_at(qdd, (k), sqdd_k, oqdd_))\n"
-          "#define TAU(k) bard_at(tau, (k), st_k, ot_)\n"
-          "#define MA(k) bard_at(M, (k), sM_k, oM_)\n"
-          "#define JA(k) bard_at(J, (k), sJ_k, oJ_)\n"
+          "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, float v) {\n"
+          "  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)ob, (int)row, 2);\n"
+          "}\n"
+          "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, double v) {\n"
+          "  typedef unsigned U2 __attribute__((ext_vector_type(2)));\n"
+          "  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)ob, (int)row, 2);\n"
+          "}\n"
+          "#define TAU(k, v) bard_st(rt_, (unsigned)(k) * ut_, ot_, (v))\n"
+          "#define MA(k, v) bard_st(rM_, (unsigned)(k) * uM_, oM_, (v))\n"
+          "#define JA(k, v) bard_st(rJ_, (unsigned)(k) * uJ_, oJ_, (v))\n"
           "#define Qv(k) Qv_##k\n"
           "#define QDv(k) QDv_##k\n"
           "#define QDDv(k) QDDv_##k\n";
@@ -215,15 +222,18 @@ class Emitter {
     pointers();
     emit_zero_stores();
     if (!slot_body_.empty()) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
+    // The trunk's state lives at function scope (the merging wave reads it
+    // after the barrier); each wave's branch issues all its loads -- its
+    // limbs' and the trunk's -- before computing anything (one memory round
+    // trip), then computes the trunk's kinematics and its limbs.
     std::vector<int> tb;
-    for (int i = 0; i < m_->n; ++i)
-      if (trunk_[i]) tb.push_back(i);
-    loads(tb);
     bool any_trunk = false;
     for (int i = 0; i < m_->n; ++i)
       if (trunk_[i]) {
-        forward_kin(i);
-        o_ << "  Real " << v("I", i) << "[10], " << v("f", i) << "[6];\n";
+        tb.push_back(i);
+        o_ << "  Real " << v("R", i) << "[9], " << v("p", i) << "[3], " << v("r", i) << "[3], " << v("a", i)
+           << "[3], " << v("v", i) << "[6], " << v("c", i) << "[6], " << v("I", i) << "[10], " << v("f", i)
+           << "[6];\n";
         any_trunk = true;
       }
     const int merge = nw - 1;
@@ -232,6 +242,8 @@ class Emitter {
       std::vector<int> lb;
       for (int l : pl_.bins[w]) lb.insert(lb.end(), pl_.limbs[l].begin(), pl_.limbs[l].end());
       loads(lb);
+      loads(tb);
+      for (int i : tb) forward_kin(i, false);
       for (int l : pl_.bins[w]) limb(l);
       if (w == merge) {
         for (int i = 0; i < m_->n; ++i)
@@ -251,20 +263,25 @@ class Emitter {
     return o_.str();
   }
 
-  // Each lane's byte offset of its instance in every array (32 bits; the
-  // host routes only batches where they fit), added to a wave-uniform row
-  // base: entries are addressed by a scalar base and one per-lane offset.
+  // Each lane's byte offset of its instance in every array and each output
+  // row's byte offset (32 bits; the host routes only calls where every such
+  // offset fits): inputs are read from a wave-uniform row base plus the lane
+  // offset, outputs are written by buffer stores (resource + scalar row
+  // offset + lane offset).
   // The inputs of the given bodies, loaded at once ahead of the code that
   // uses them (one memory round trip instead of one per body).
   void loads(const std::vector<int>& bodies) {
+    const char* d = "  const Real ";
     for (int i : bodies) {
       const int nq = m_->jtype[i] == J_FREE ? 7 : 1;
-      for (int k = 0; k < nq; ++k) o_ << "  const Real Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
+      for (int k = 0; k < nq; ++k) o_ << d << "Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
       for (int k = 0; k < m_->nvi[i]; ++k)
-        o_ << "  const Real QDv_" << m_->vi[i] + k << " = QD(" << m_->vi[i] + k << "), QDDv_" << m_->vi[i] + k
+        o_ << d << "QDv_" << m_->vi[i] + k << " = QD(" << m_->vi[i] + k << ");\n" << d << "QDDv_" << m_->vi[i] + k
            << " = QDD(" << m_->vi[i] + k << ");\n";
     }
   }
+
+
 
   void pointers() {
     o_ << "  const unsigned oq_ = (unsigned)(b * sq_b) * (unsigned)sizeof(Real);\n"
@@ -272,7 +289,15 @@ class Emitter {
           "  const unsigned oqdd_ = (unsigned)(b * sqdd_b) * (unsigned)sizeof(Real);\n"
           "  const unsigned ot_ = (unsigned)(b * st_b) * (unsigned)sizeof(Real);\n"
           "  const unsigned oM_ = (unsigned)(b * sM_b) * (unsigned)sizeof(Real);\n"
-          "  const unsigned oJ_ = (unsigned)(b * sJ_b) * (unsigned)sizeof(Real);\n";
+          "  const unsigned oJ_ = (unsigned)(b * sJ_b) * (unsigned)sizeof(Real);\n"
+          // outputs: buffer stores from a resource per array, the row's byte
+          // offset in a scalar register and the lane's in a vector register
+          "  const __amdgpu_buffer_rsrc_t rt_ = __builtin_amdgcn_make_buffer_rsrc(tau, (short)0, -1, 0x00020000);\n"
+          "  const __amdgpu_buffer_rsrc_t rM_ = __builtin_amdgcn_make_buffer_rsrc(M, (short)0, -1, 0x00020000);\n"
+          "  const __amdgpu_buffer_rsrc_t rJ_ = __builtin_amdgcn_make_buffer_rsrc(J, (short)0, -1, 0x00020000);\n"
+          "  const unsigned ut_ = (unsigned)st_k * (unsigned)sizeof(Real);\n"
+          "  const unsigned uM_ = (unsigned)sM_k * (unsigned)sizeof(Real);\n"
+          "  const unsigned uJ_ = (unsigned)sJ_k * (unsigned)sizeof(Real);\n";
   }
 
   // One limb (a chain): forward, its end effectors' Jacobians, backward with
@@ -352,8 +377,8 @@ class Emitter {
   void emit_zero_stores() {
     const char* first = split_ ? "wave" : "0";
     o_ << "  if (zero_blocks == 0) {\n"
-          "    for (int i = " << first << "; i < NZM; i += NW) bard::put(MA(ZM[i]), Real(0), true);\n"
-          "    for (int i = " << first << "; i < NZJ; i += NW) bard::put(JA(ZJ[i]), Real(0), true);\n"
+          "    for (int i = " << first << "; i < NZM; i += NW) MA(ZM[i], Real(0));\n"
+          "    for (int i = " << first << "; i < NZJ; i += NW) JA(ZJ[i], Real(0));\n"
           "  }\n";
   }
 
@@ -395,12 +420,16 @@ class Emitter {
     body_force(i, true);
   }
 
-  void forward_kin(int i) {
+  // declare: define the body's state here; otherwise assign variables
+  // declared beforehand in an outer scope
+  void forward_kin(int i, bool declare = true) {
     const int p = m_->parent[i], t = m_->jtype[i], qi = m_->qi[i], vi = m_->vi[i];
     o_ << "  // body " << i << " (" << (t == J_REV ? "revolute" : t == J_PRI ? "prismatic" : "free") << ", parent "
        << p << ")\n";
-    o_ << "  Real " << v("R", i) << "[9], " << v("p", i) << "[3], " << v("r", i) << "[3], " << v("a", i) << "[3], "
-       << v("v", i) << "[6], " << v("c", i) << "[6];\n  {\n";
+    if (declare)
+      o_ << "  Real " << v("R", i) << "[9], " << v("p", i) << "[3], " << v("r", i) << "[3], " << v("a", i)
+         << "[3], " << v("v", i) << "[6], " << v("c", i) << "[6];\n";
+    o_ << "  {\n";
     if (t == J_FREE) {
       o_ << "    Real x_ = Qv(" << qi + 3 << "), y_ = Qv(" << qi + 4 << "), z_ = Qv(" << qi + 5
          << "), w_ = Qv(" << qi + 6 << ");\n"
@@ -615,8 +644,8 @@ class Emitter {
 
   void store_M(int r, int col, const std::string& val) {
     const int nv = m_->nv;
-    o_ << "    bard::put(MA(" << r * nv + col << "), " << val << ", true);\n";
-    if (r != col) o_ << "    bard::put(MA(" << col * nv + r << "), " << val << ", true);\n";
+    o_ << "    MA(" << r * nv + col << ", " << val << ");\n";
+    if (r != col) o_ << "    MA(" << col * nv + r << ", " << val << ");\n";
   }
 
   // ---- leaving body i: subtree force, torque, composite inertia, M ----
@@ -640,17 +669,17 @@ class Emitter {
     // torque
     const std::string F = v("F", i), a = v("a", i), R = v("R", i);
     if (t == J_REV)
-      o_ << "    bard::put(TAU(" << vi << "), " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
-         << a << "[2] * " << F << "[2], true);\n";
+      o_ << "    TAU(" << vi << ", " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
+         << a << "[2] * " << F << "[2]);\n";
     else if (t == J_PRI)
-      o_ << "    bard::put(TAU(" << vi << "), " << a << "[0] * " << F << "[3] + " << a << "[1] * " << F << "[4] + "
-         << a << "[2] * " << F << "[5], true);\n";
+      o_ << "    TAU(" << vi << ", " << a << "[0] * " << F << "[3] + " << a << "[1] * " << F << "[4] + "
+         << a << "[2] * " << F << "[5]);\n";
     else
       for (int d = 0; d < 6; ++d) {
         const int e = d % 3, base = d < 3 ? 3 : 0;  // [f; n] in the body frame: R^T f, R^T n
-        o_ << "    bard::put(TAU(" << vi + d << "), " << R << "[" << e << "] * " << F << "[" << base << "] + " << R
+        o_ << "    TAU(" << vi + d << ", " << R << "[" << e << "] * " << F << "[" << base << "] + " << R
            << "[" << 3 + e << "] * " << F << "[" << base + 1 << "] + " << R << "[" << 6 + e << "] * " << F << "["
-           << base + 2 << "], true);\n";
+           << base + 2 << "]);\n";
       }
     // mass-matrix columns of this body's dofs
     for (int d = 0; d < nd; ++d) {
@@ -697,8 +726,8 @@ class Emitter {
              << "[k];\n      bard::cross3(s_, d_, l_);\n";
         }
         for (int r = 0; r < 6; ++r)
-          o_ << "      bard::put(JA(" << (ei * 6 + r) * nv + col << "), " << (r < 3 ? "l_[" : "s_[")
-             << (r % 3) << "], true);\n";
+          o_ << "      JA(" << (ei * 6 + r) * nv + col << ", " << (r < 3 ? "l_[" : "s_[")
+             << (r % 3) << "]);\n";
         o_ << "    }\n";
       }
     }
@@ -900,16 +929,22 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
 }
 
 template <class Real>
-bool spec_fits(const Args<Real>& a) {
+bool spec_fits(const Args<Real>& a, int nv, int n_ee) {
   const int64_t last = a.B > 0 ? a.B - 1 : 0;
+  const int64_t lim = (int64_t)(0xffffffffu / sizeof(Real));
   const int64_t s[6] = {a.sq_b, a.sqd_b, a.sqdd_b, a.st_b, a.sM_b, a.sJ_b};
   for (int64_t x : s)
-    if (x < 0 || last * x > (int64_t)(0xffffffffu / sizeof(Real))) return false;
+    if (x < 0 || last * x > lim) return false;
+  // outputs: last row's offset plus the last lane's
+  const int64_t rows[3] = {nv, (int64_t)nv * nv, 6LL * nv * n_ee};
+  const int64_t sk[3] = {a.st_k, a.sM_k, a.sJ_k}, sb[3] = {a.st_b, a.sM_b, a.sJ_b};
+  for (int k = 0; k < 3; ++k)
+    if (sk[k] < 0 || (rows[k] - 1) * sk[k] + last * sb[k] > lim) return false;
   return true;
 }
 
-template bool spec_fits<float>(const Args<float>&);
-template bool spec_fits<double>(const Args<double>&);
+template bool spec_fits<float>(const Args<float>&, int, int);
+template bool spec_fits<double>(const Args<double>&, int, int);
 template int spec_launch<float>(const SpecKernel*, const Args<float>&, const double*, hipStream_t);
 template int spec_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
 

@@ -37,15 +37,15 @@ def test_generated_source_covers_every_output(whole):
     ee = tree.ee_bodies
     src = m.specialized_source(ee, whole=whole)
     nv = tree.nv
-    tau = {int(k) for k in re.findall(r"TAU\((\d+)\)", src)}
+    tau = {int(k) for k in re.findall(r"TAU\((\d+), ", src)}
     assert tau == set(range(nv))
-    stored = [int(k) for k in re.findall(r"MA\((\d+)\)", src)]
+    stored = [int(k) for k in re.findall(r"MA\((\d+), ", src)]
     zeros = _table(src, "M")
     assert sorted(stored + zeros) == list(range(nv * nv))
-    jcols = [int(k) for k in re.findall(r"JA\((\d+)\)", src)]
+    jcols = [int(k) for k in re.findall(r"JA\((\d+), ", src)]
     jz = _table(src, "J")
     assert sorted(jcols + jz) == list(range(len(ee) * 6 * nv))
-    assert "float" in src and "double" not in src
+    assert "typedef float Real;" in src and "typedef double Real;" not in src
 
 
 def test_deep_tree_refused_on_the_host():
