@@ -344,7 +344,8 @@ def measure_peaks(torch):
 
 def bench_specialized(torch, bard):
     """Model-specialised chain kernels (hipRTC, constants as literals) against
-    the generic kernel: both forms (split over waves by limbs, and the whole
+    the generic kernel: the three forms (split over waves by limbs, dual:
+    split with torques and mass matrix + Jacobians in two workgroups, and the whole
     tree per wave) on the 36-DOF and 23-DOF humanoids and the 7-DOF chain at
     B = 1024 .. 262,144, rotating sets past 512 MB; then the tiers
     bard_chain_autotune routes to each form."""
@@ -356,10 +357,10 @@ def bench_specialized(torch, bard):
         m = bard.Model.from_tree(tree)
         ee = tree.ee_bodies
         bpe = chain_bytes_per_eval(tree, len(ee))
-        forms = ("split", "whole")
+        forms = bard.SPEC_FORMS
         for f in forms:
-            m.specialize(ee, route=False, whole=f == "whole")
-            info = m.specialized_info(ee, whole=f == "whole")
+            m.specialize(ee, route=False, form=f)
+            info = m.specialized_info(ee, form=f)
             for k in ("compile_s", "vgprs", "scratch_bytes", "waves"):
                 out[f"spec_{name}_{f}_{k}"] = info[k]
         for B in batches:
@@ -368,20 +369,19 @@ def bench_specialized(torch, bard):
             calls = [m.bind_chain(d[0], d[1], d[2], ee, tuple(o)) for (d, o, _) in sets]
             n = max(30, min(400, 2_000_000 // B))
             key = f"spec_{name}_B{B}"
-            m.specialize(ee, route=False)
-            m.specialize(ee, route=False, whole=True)
+            for f in forms:
+                m.specialize(ee, route=False, form=f)
             _, kg = time_calls(torch, calls, n, 5)
             out[key + "_generic_us"] = kg * 1e3
             for f in forms:
-                m.specialize(ee, route=True, whole=f == "whole")
+                m.specialize(ee, route=True, form=f)
                 _, ks = time_calls(torch, calls, n, 5)
                 out[key + f"_{f}_us"] = ks * 1e3
                 out[key + f"_{f}_hbm_frac"] = bpe * B / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS
             del sets, calls
             torch.cuda.empty_cache()
         out[f"spec_{name}_autotuned_first_batch"] = m.autotune_chain(ee)
-        out[f"spec_{name}_autotuned_tiers"] = {f: m.specialized_info(ee, whole=f == "whole")["route_tiers"]
-                                               for f in forms}
+        out[f"spec_{name}_autotuned_tiers"] = {f: m.specialized_info(ee, form=f)["route_tiers"] for f in forms}
     return out
 
 
@@ -566,10 +566,10 @@ def bench_workspace(torch, bard, steps):
     return out
 
 
-def spec_source_sha(m, ee, whole):
+def spec_source_sha(m, ee, form):
     """SHA-256 of what a specialised kernel is built and launched from: its
     generated source, the device header it includes and the generator."""
-    h = hashlib.sha256(m.specialized_source(ee, whole=whole).encode())
+    h = hashlib.sha256(m.specialized_source(ee, form=form).encode())
     for f in SPEC_SRCS:
         h.update(open(f, "rb").read())
     return h.hexdigest()
@@ -634,13 +634,15 @@ def main():
     # of the generic kernel and the two specialised forms
     t0 = time.perf_counter()
     first = m.autotune_chain(ee)
-    tiers = {"split": m.specialized_info(ee)["route_tiers"], "whole": m.specialized_info(ee, whole=True)["route_tiers"]}
+    tiers = {f: m.specialized_info(ee, form=f)["route_tiers"] for f in bard.SPEC_FORMS}
     tier = sum(B >= t for t in bard.SPEC_TIERS[1:])
     route = next((f for f, bits in tiers.items() if (bits >> tier) & 1), "generic")
-    spec_sha = spec_source_sha(m, ee, route == "whole") if route != "generic" else None
+    spec_sha = spec_source_sha(m, ee, route) if route != "generic" else None
     kernel = {"generic": "tree_kernel<float, RNEA|CRBA|JAC>",
               "split": f"bard_spec_chain (specialised, split over {m.specialized_info(ee)['waves']} waves)",
-              "whole": "bard_spec_chain (specialised, whole tree per wave)"}[route]
+              "whole": "bard_spec_chain (specialised, whole tree per wave)",
+              "dual": f"bard_spec_chain (specialised, split over {m.specialized_info(ee, form='dual')['waves']} waves, "
+                      "torques and mass matrix + Jacobians in two workgroups)"}[route]
     log(f"[bench] autotune {time.perf_counter() - t0:.1f} s: tiers {tiers}, first specialised batch {first}; "
         f"B={B} runs {kernel}")
     def make_calls():

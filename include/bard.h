@@ -149,6 +149,13 @@ int bard_model_destroy(bard_model_t model);
  *     trunk.  A tree that is a single chain runs as one wave.
  *   whole (BARD_SPEC_WHOLE): one wave walks the whole tree; fewer
  *     instructions in all, so it can win once the batch fills the device.
+ *   dual (BARD_SPEC_DUAL): split, and each group of 64 instances runs as two
+ *     workgroups of the launch: one computes the torques (kinematics, body
+ *     forces, subtree forces), the other the mass matrix and the Jacobians
+ *     (kinematics, composite inertias).  Each computes the kinematics it
+ *     needs, so the instructions per wave drop and twice the compute units
+ *     take part; for small batches.  Refused (BARD_E_UNSUPPORTED) when no
+ *     split plan fits in LDS.
  *
  * specialize: compiles the kernel of one form for (dtype, end-effector set
  * ee_body [n_ee, host], frame) and loads it on the current device (once; later
@@ -158,7 +165,8 @@ int bard_model_destroy(bard_model_t model);
  * agree with the generic kernel's within the tolerance contract, not bitwise
  * (different summation order).  BARD_SPEC_COMPILE_ONLY -- generate and
  * compile only, needing no GPU, and keep nothing (a check that the
- * generator's output compiles).  BARD_SPEC_WHOLE -- the whole form.  Uploads
+ * generator's output compiles).  BARD_SPEC_WHOLE, BARD_SPEC_DUAL -- the
+ * whole or the dual form (at most one of them).  Uploads
  * the model's tables as bard_model_upload does; synchronous; call it outside
  * any graph capture.  The kernels are unloaded by bard_model_destroy.
  * Errors: BARD_E_ARG, BARD_E_DEVICE (a hipRTC compile or module load failed;
@@ -171,10 +179,11 @@ int bard_model_destroy(bard_model_t model);
 #define BARD_SPEC_ROUTE 1
 #define BARD_SPEC_COMPILE_ONLY 2
 #define BARD_SPEC_WHOLE 4
+#define BARD_SPEC_DUAL 8
 int bard_model_specialize(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                           bard_frame frame, int32_t flags);
-/* Resources of a loaded specialised kernel (form by flags: 0 or
- * BARD_SPEC_WHOLE) on the current device: registers per lane, scratch bytes
+/* Resources of a loaded specialised kernel (form by flags: 0,
+ * BARD_SPEC_WHOLE or BARD_SPEC_DUAL) on the current device: registers per lane, scratch bytes
  * per lane (spills), hipRTC compile time, the batch tiers routed to it (bit k
  * for tier k: [0, 4096), [4096, 16384), [16384, 65536), [65536, inf)) and
  * waves per workgroup.  Any output may be NULL.  BARD_E_STATE if none is
@@ -183,8 +192,8 @@ int bard_model_specialized_info(bard_model_t model, bard_dtype dtype, int32_t n_
                                 bard_frame frame, int32_t flags, int32_t* vgprs, int32_t* scratch_bytes,
                                 double* compile_seconds, int32_t* routed_tiers, int32_t* waves);
 /* Choose between the generic chain kernel and the specialised forms by
- * timing: compiles and loads both forms if needed (one, for a tree that does
- * not split), times every candidate on scratch arrays (allocated here and
+ * timing: compiles and loads the forms if needed (split and dual; whole too
+ * when the tree splits over several waves), times every candidate on scratch arrays (allocated here and
  * freed before returning) at B = 1024, 4096, 16384 and 65536 on `stream`, and
  * routes each batch tier (as in bard_model_specialized_info; the tier of
  * 1024 covers every batch below 4096) to the fastest.  *min_batch receives
@@ -194,7 +203,8 @@ int bard_model_specialized_info(bard_model_t model, bard_dtype dtype, int32_t n_
  * bard_model_specialize, BARD_E_NOMEM, BARD_E_CAPTURE. */
 int bard_chain_autotune(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                         bard_frame frame, void* stream, int64_t* min_batch);
-/* The generated source text of one form (flags: 0 or BARD_SPEC_WHOLE;
+/* The generated source text of one form (flags: 0, BARD_SPEC_WHOLE or
+ * BARD_SPEC_DUAL;
  * NUL-terminated, truncated to cap - 1 bytes); *len receives its full length.
  * Host only. */
 int bard_model_specialized_source(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,

@@ -44,7 +44,14 @@ WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
 E_STATE = -9  # bard_status of a call that allocates nothing and found the model not uploaded
 UPLOAD_ADJOINT = 1
-SPEC_ROUTE, SPEC_COMPILE_ONLY, SPEC_WHOLE = 1, 2, 4
+SPEC_ROUTE, SPEC_COMPILE_ONLY, SPEC_WHOLE, SPEC_DUAL = 1, 2, 4, 8
+SPEC_FORMS = ("split", "whole", "dual")
+
+
+def _spec_form_flag(form: str) -> int:
+    if form not in SPEC_FORMS:
+        raise ValueError(f"form must be one of {SPEC_FORMS}, got {form!r}")
+    return {"split": 0, "whole": SPEC_WHOLE, "dual": SPEC_DUAL}[form]
 # batch tiers of the specialised-kernel routing (lower bounds)
 SPEC_TIERS = (0, 4096, 16384, 65536)
 # workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own
@@ -428,20 +435,21 @@ class Model:
         _check(bard_model_upload(self._h, n, pee, UPLOAD_ADJOINT if adjoint else 0), "bard_model_upload")
 
     def specialize(self, ee: Sequence[int], frame: int = WORLD, dtype=None, route: bool = True,
-                   compile_only: bool = False, whole: bool = False):
+                   compile_only: bool = False, form: str = "split"):
         """Compile the model-specialised chain kernel for (dtype, ee, frame)
         with hipRTC and load it on the current device; with route=True,
         matching chain() calls use it at every batch (bard_model_specialize).
-        whole=True selects the form that walks the whole tree in one wave
-        instead of splitting it over waves by limbs."""
+        form: "split" (waves by limbs), "whole" (one wave over the whole
+        tree) or "dual" (split, torques and mass matrix + Jacobians in two
+        workgroups)."""
         ee_a, pee = _i32arr(ee)
         flags = ((SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0) |
-                 (SPEC_WHOLE if whole else 0))
+                 _spec_form_flag(form))
         _check(bard_model_specialize(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), flags),
                "bard_model_specialize")
 
     def autotune_chain(self, ee: Sequence[int], frame: int = WORLD, dtype=None) -> int:
-        """Time the generic chain kernel and both specialised forms
+        """Time the generic chain kernel and the specialised forms
         (bard_chain_autotune) and route each batch tier to the fastest;
         returns the smallest batch a specialised form takes (-1: none)."""
         torch = _torch()
@@ -452,20 +460,20 @@ class Model:
                "bard_chain_autotune")
         return mb.value
 
-    def specialized_info(self, ee: Sequence[int], frame: int = WORLD, dtype=None, whole: bool = False) -> dict:
+    def specialized_info(self, ee: Sequence[int], frame: int = WORLD, dtype=None, form: str = "split") -> dict:
         ee_a, pee = _i32arr(ee)
         vg, sc, rt, nw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         cs = ctypes.c_double()
         _check(bard_model_specialized_info(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame),
-                                           SPEC_WHOLE if whole else 0, ctypes.byref(vg), ctypes.byref(sc),
+                                           _spec_form_flag(form), ctypes.byref(vg), ctypes.byref(sc),
                                            ctypes.byref(cs), ctypes.byref(rt), ctypes.byref(nw)),
                "bard_model_specialized_info")
         return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
                 "route_tiers": rt.value, "waves": nw.value}
 
-    def specialized_source(self, ee: Sequence[int], frame: int = WORLD, dtype=None, whole: bool = False) -> str:
+    def specialized_source(self, ee: Sequence[int], frame: int = WORLD, dtype=None, form: str = "split") -> str:
         ee_a, pee = _i32arr(ee)
-        fl = SPEC_WHOLE if whole else 0
+        fl = _spec_form_flag(form)
         n = _i64()
         _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), fl, None,
                                              0, ctypes.byref(n)), "bard_model_specialized_source")

@@ -694,14 +694,16 @@ static void spec_refresh_route(bard_model* m) {
   m->spec_route.store(any);
 }
 
-static int spec_form(int32_t flags) { return (flags & BARD_SPEC_WHOLE) ? 1 : 0; }
+static int spec_form(int32_t flags) { return (flags & BARD_SPEC_WHOLE) ? 1 : (flags & BARD_SPEC_DUAL) ? 2 : 0; }
 
 int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
                           int32_t flags) {
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY | BARD_SPEC_WHOLE)) return fail(BARD_E_ARG, "unknown flags");
+  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY | BARD_SPEC_WHOLE | BARD_SPEC_DUAL))
+    return fail(BARD_E_ARG, "unknown flags");
+  if ((flags & BARD_SPEC_WHOLE) && (flags & BARD_SPEC_DUAL)) return fail(BARD_E_ARG, "one form at a time");
   // The generated code grows with the ancestor walks of the mass-matrix
   // columns (one step per dof and ancestor body); past this size the compile
   // time and register pressure outgrow what specialisation gains.
@@ -713,10 +715,12 @@ int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const 
                                         ", " + std::to_string(steps) + " ancestor-walk steps); the generic kernel "
                                         "serves it");
   const int form = spec_form(flags);
+  if (!spec_form_ok(m, dtype == BARD_F64, form))
+    return fail(BARD_E_UNSUPPORTED, "the dual form needs a split plan whose limb sums fit in LDS");
   if (flags & BARD_SPEC_COMPILE_ONLY) {
     std::vector<char> code;
     std::string log;
-    rc = spec_compile(spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, form == 1), &code, &log);
+    rc = spec_compile(spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, form), &code, &log);
     return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
   }
   if ((rc = check_device_state())) return rc;
@@ -726,9 +730,11 @@ int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const 
   if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, form, true, &sk))) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
   if (flags & BARD_SPEC_ROUTE) {
-    // every batch to this form; the other form of the same arguments keeps none
-    auto other = dc->spec.find(spec_key((int)dtype, (int)frame, ee, 1 - form));
-    if (other != dc->spec.end()) other->second.route_tiers = 0;
+    // every batch to this form; the other forms of the same arguments keep none
+    for (int f = 0; f < kSpecForms; ++f) {
+      auto other = dc->spec.find(spec_key((int)dtype, (int)frame, ee, f));
+      if (f != form && other != dc->spec.end()) other->second.route_tiers = 0;
+    }
     sk->route_tiers = (1 << kSpecTiers) - 1;
   } else {
     sk->route_tiers = 0;
@@ -743,7 +749,8 @@ int bard_model_specialized_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, 
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if (flags & ~BARD_SPEC_WHOLE) return fail(BARD_E_ARG, "unknown flags");
+  if ((flags & ~(BARD_SPEC_WHOLE | BARD_SPEC_DUAL)) || (flags & BARD_SPEC_WHOLE && flags & BARD_SPEC_DUAL))
+    return fail(BARD_E_ARG, "unknown flags");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
   const std::string key = spec_key((int)dtype, (int)frame, ee, spec_form(flags));
@@ -769,11 +776,13 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   if (capturing(st)) return fail(BARD_E_CAPTURE, "autotuning allocates and synchronises; not under capture");
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, st))) return rc;
-  // both forms when the tree splits over several waves; else the one form
-  const int nforms = spec_waves(m, dtype == BARD_F64, false) > 1 ? 2 : 1;
-  SpecKernel* sk[2] = {nullptr, nullptr};
-  for (int f = 0; f < nforms; ++f)
-    if ((rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, f, true, &sk[f]))) return rc;
+  // the candidates: the split form, the whole form when the tree splits
+  // over several waves (else it is the same code), the dual form when the
+  // tree has a plan for it
+  bool use[kSpecForms] = {true, spec_waves(m, dtype == BARD_F64, 0) > 1, spec_form_ok(m, dtype == BARD_F64, 2)};
+  SpecKernel* sk[kSpecForms] = {nullptr, nullptr, nullptr};
+  for (int f = 0; f < kSpecForms; ++f)
+    if (use[f] && (rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, f, true, &sk[f]))) return rc;
   // Scratch arrays for the largest batch tried, inputs filled with 0.1 (the
   // kernels have no data-dependent branches at these values).
   const int64_t Bmax = kSpecTierBatch[kSpecTiers - 1];
@@ -793,7 +802,7 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
       return fail(BARD_E_DEVICE, "upload of the autotuning inputs failed");
     }
   }
-  double t[kSpecTiers][3] = {};  // generic, split, whole
+  double t[kSpecTiers][1 + kSpecForms] = {};  // generic, then each form
   auto go = [&](auto zero) -> int {
     using R = decltype(zero);
     for (int k = 0; k < kSpecTiers; ++k) {
@@ -811,8 +820,8 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
       const int reps = B >= 16384 ? 5 : 20;
       int r = time_launches([&] { return run_tree<R, OP_RNEA | OP_CRBA | OP_JAC>(m, a, n_ee, ee_body, (int)frame, st); },
                             st, reps, &t[k][0]);
-      for (int f = 0; f < nforms && !r; ++f)
-        r = time_launches([&] { return spec_launch<R>(sk[f], a, m->g, st); }, st, reps, &t[k][1 + f]);
+      for (int f = 0; f < kSpecForms && !r; ++f)
+        if (use[f]) r = time_launches([&] { return spec_launch<R>(sk[f], a, m->g, st); }, st, reps, &t[k][1 + f]);
       if (r) return r;
     }
     return BARD_OK;
@@ -822,12 +831,12 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   (void)hipFree(buf);
   if (rc) return rc;
   // each tier to the fastest of the generic kernel and the forms
-  int tiers[2] = {0, 0};
+  int tiers[kSpecForms] = {0, 0, 0};
   int64_t first = -1;
   for (int k = 0; k < kSpecTiers; ++k) {
     int best = 0;
-    for (int f = 0; f < nforms; ++f)
-      if (t[k][1 + f] < t[k][best]) best = 1 + f;
+    for (int f = 0; f < kSpecForms; ++f)
+      if (use[f] && t[k][1 + f] < t[k][best]) best = 1 + f;
     if (best > 0) {
       tiers[best - 1] |= 1 << k;
       if (first < 0) first = k == 0 ? 0 : kSpecTierBatch[k];
@@ -835,10 +844,13 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   }
   {
     std::lock_guard<std::mutex> lk(m->mu);
-    for (int f = 0; f < nforms; ++f) sk[f]->route_tiers = tiers[f];
-    for (int f = nforms; f < 2; ++f) {  // a form not timed (same code as the split one) takes no calls
-      auto it = dc->spec.find(spec_key((int)dtype, (int)frame, ee, f));
-      if (it != dc->spec.end()) it->second.route_tiers = 0;
+    for (int f = 0; f < kSpecForms; ++f) {
+      if (use[f]) {
+        sk[f]->route_tiers = tiers[f];
+      } else {  // a form not timed takes no calls
+        auto it = dc->spec.find(spec_key((int)dtype, (int)frame, ee, f));
+        if (it != dc->spec.end()) it->second.route_tiers = 0;
+      }
     }
     spec_refresh_route(m);
   }
@@ -851,8 +863,11 @@ int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if (flags & ~BARD_SPEC_WHOLE) return fail(BARD_E_ARG, "unknown flags");
-  const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, spec_form(flags) == 1);
+  if ((flags & ~(BARD_SPEC_WHOLE | BARD_SPEC_DUAL)) || (flags & BARD_SPEC_WHOLE && flags & BARD_SPEC_DUAL))
+    return fail(BARD_E_ARG, "unknown flags");
+  if (!spec_form_ok(m, dtype == BARD_F64, spec_form(flags)))
+    return fail(BARD_E_UNSUPPORTED, "the dual form needs a split plan whose limb sums fit in LDS");
+  const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, spec_form(flags));
   if (len) *len = (int64_t)src.size();
   if (buf && cap > 0) {
     const size_t k = std::min<size_t>((size_t)cap - 1, src.size());

@@ -39,11 +39,16 @@ std::string spec_key(int dtype, int frame, const std::vector<int>& ee, int form)
 constexpr int kSpecTiers = 4;
 constexpr int64_t kSpecTierBatch[kSpecTiers] = {1024, 4096, 16384, 65536};
 int spec_tier(int64_t B);
-// Source text of the kernel for one (end-effector set, frame, precision);
-// whole: one wave walks the whole tree (no split over limbs).
-std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole);
+// Forms of a specialised kernel: 0 split over waves by limbs, 1 one wave
+// over the whole tree, 2 split and, per 64 instances, two workgroups (the
+// torques in one, the mass matrix and Jacobians in the other).
+constexpr int kSpecForms = 3;
+// Source text of the kernel for one (end-effector set, frame, precision, form).
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form);
 // Waves per workgroup of that kernel (64 instances per workgroup).
-int spec_waves(const bard_model* m, bool fp64, bool whole);
+int spec_waves(const bard_model* m, bool fp64, int form);
+// Whether the tree has a plan for the form (the dual form needs a split plan).
+bool spec_form_ok(const bard_model* m, bool fp64, int form);
 // Number of structural-zero rows (M entries of unrelated dofs, J rows off an
 // end effector's path) the kernel writes.
 int spec_zero_rows(const bard_model* m, const std::vector<int>& ee);

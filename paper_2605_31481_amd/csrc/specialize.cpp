@@ -70,7 +70,7 @@ struct SplitPlan {
   std::vector<int> slot_body;           // trunk body each slot adds into
 };
 
-SplitPlan make_plan(const bard_model* m, bool whole, bool fp64) {
+SplitPlan make_plan(const bard_model* m, bool whole, bool fp64, int max_waves = SplitPlan::kMaxWaves) {
   SplitPlan pl;
   const int n = m->n;
   pl.trunk.assign(n, 0);
@@ -94,12 +94,7 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64) {
     cost.push_back(c);
   }
   const int nl = (int)pl.limbs.size();
-  if (nl < 2) {
-    pl.trunk.assign(n, 0);
-    pl.limbs.clear();
-    return pl;
-  }
-  pl.waves = std::min(nl, SplitPlan::kMaxWaves);
+  pl.waves = std::min(nl, max_waves);
   std::vector<int> order(nl);
   for (int l = 0; l < nl; ++l) order[l] = l;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -133,8 +128,10 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64) {
       pl.limb_slot[l] = sl;
     }
   }
-  // LDS: 16 values per slot and lane; keep within 64 KB
-  if (pl.slot_body.size() * 16 * 64 * (fp64 ? 8 : 4) > 65536) return make_plan(m, true, fp64);
+  // LDS: 16 values per slot and lane; keep within 64 KB (with one wave, a
+  // slot per trunk body that has limbs; past that no split plan)
+  if (pl.slot_body.size() * 16 * 64 * (fp64 ? 8 : 4) > 65536)
+    return max_waves > 1 ? make_plan(m, false, fp64, 1) : make_plan(m, true, fp64);
   pl.split = true;
   return pl;
 }
@@ -142,8 +139,9 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64) {
 // Emits the source text of one specialised chain kernel.
 class Emitter {
  public:
-  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole)
-      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), pl_(make_plan(m, whole, fp64)), split_(pl_.split) {
+  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form)
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), dual_(form == 2), pl_(make_plan(m, form == 1, fp64)),
+        split_(pl_.split || dual_) {
     trunk_ = pl_.trunk;
     slot_body_ = pl_.slot_body;
   }
@@ -176,6 +174,7 @@ class Emitter {
     emit_zero_tables();
     const int nw = pl_.waves;
     o_ << "static constexpr int NW = " << nw << ";  // waves per workgroup, 64 instances\n";
+    o_ << "static constexpr int WG_PER_GROUP = " << (dual_ ? 2 : 1) << ";  // workgroups per 64 instances\n";
     o_ << "extern \"C\" __global__ void __launch_bounds__(" << 64 * nw << ") bard_spec_chain(\n"
           "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ qdd,\n"
           "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
@@ -216,16 +215,46 @@ class Emitter {
     // Every lane of every wave reaches the barrier: lanes past the batch
     // repeat the last instance (the same values to the same addresses).
     o_ << "  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);\n"
-          "  const int lane = (int)threadIdx.x & 63;\n"
-          "  long long b = (long long)blockIdx.x * 64 + lane;\n"
-          "  if (b > B - 1) b = B - 1;\n";
+          "  const int lane = (int)threadIdx.x & 63;\n";
+    if (dual_)
+      o_ << "  const int part = (int)blockIdx.x & 1;  // 0: torques, 1: mass matrix and Jacobians\n"
+            "  long long b = ((long long)blockIdx.x >> 1) * 64 + lane;\n";
+    else
+      o_ << "  long long b = (long long)blockIdx.x * 64 + lane;\n";
+    o_ << "  if (b > B - 1) b = B - 1;\n";
     pointers();
-    emit_zero_stores();
     if (!slot_body_.empty()) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
-    // The trunk's state lives at function scope (the merging wave reads it
-    // after the barrier); each wave's branch issues all its loads -- its
-    // limbs' and the trunk's -- before computing anything (one memory round
-    // trip), then computes the trunk's kinematics and its limbs.
+    if (dual_) {
+      o_ << "  if (part == 0) {\n";
+      do_rnea_ = true;
+      do_crba_ = false;
+      split_body();
+      o_ << "  } else {\n";
+      do_rnea_ = false;
+      do_crba_ = true;
+      split_body();
+      o_ << "  }\n";
+      do_rnea_ = do_crba_ = true;
+    } else {
+      split_body();
+    }
+    o_ << "}\n";
+    return o_.str();
+  }
+
+  // The workgroup's code for the parts selected by do_rnea_ / do_crba_: the
+  // waves' branches (loads, trunk kinematics, limbs), one barrier, the
+  // trunk's sums in the merging wave.  The trunk's state lives at the scope
+  // of this code (the merging wave reads it after the barrier); each wave's
+  // branch issues all its loads -- its limbs' and the trunk's -- before
+  // computing anything (one memory round trip).
+  void split_body() {
+    const int nw = pl_.waves;
+    o_ << "  {\n";
+    // the lanes' structural-zero stores (when no extra workgroups write
+    // them) go with the part that stores little else: the torques' in the
+    // dual form
+    if (dual_ ? do_rnea_ : do_crba_) emit_zero_stores();
     std::vector<int> tb;
     bool any_trunk = false;
     for (int i = 0; i < m_->n; ++i)
@@ -248,8 +277,9 @@ class Emitter {
       if (w == merge) {
         for (int i = 0; i < m_->n; ++i)
           if (trunk_[i]) body_force(i, false);
-        for (size_t e = 0; e < ee_.size(); ++e)
-          if (trunk_[ee_[e]]) jacobian((int)e);
+        if (do_crba_)
+          for (size_t e = 0; e < ee_.size(); ++e)
+            if (trunk_[ee_[e]]) jacobian((int)e);
       }
       o_ << "  }\n";
     }
@@ -259,29 +289,22 @@ class Emitter {
         if (trunk_[i]) backward(i);
       o_ << "  }\n";
     }
-    o_ << "}\n";
-    return o_.str();
+    o_ << "  }\n";
   }
 
-  // Each lane's byte offset of its instance in every array and each output
-  // row's byte offset (32 bits; the host routes only calls where every such
-  // offset fits): inputs are read from a wave-uniform row base plus the lane
-  // offset, outputs are written by buffer stores (resource + scalar row
-  // offset + lane offset).
   // The inputs of the given bodies, loaded at once ahead of the code that
-  // uses them (one memory round trip instead of one per body).
+  // uses them (one memory round trip instead of one per body); velocities
+  // and accelerations only where the torques are computed.
   void loads(const std::vector<int>& bodies) {
-    const char* d = "  const Real ";
     for (int i : bodies) {
       const int nq = m_->jtype[i] == J_FREE ? 7 : 1;
-      for (int k = 0; k < nq; ++k) o_ << d << "Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
-      for (int k = 0; k < m_->nvi[i]; ++k)
-        o_ << d << "QDv_" << m_->vi[i] + k << " = QD(" << m_->vi[i] + k << ");\n" << d << "QDDv_" << m_->vi[i] + k
-           << " = QDD(" << m_->vi[i] + k << ");\n";
+      for (int k = 0; k < nq; ++k) o_ << "  const Real Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
+      if (do_rnea_)
+        for (int k = 0; k < m_->nvi[i]; ++k)
+          o_ << "  const Real QDv_" << m_->vi[i] + k << " = QD(" << m_->vi[i] + k << ");\n  const Real QDDv_"
+             << m_->vi[i] + k << " = QDD(" << m_->vi[i] + k << ");\n";
     }
   }
-
-
 
   void pointers() {
     o_ << "  const unsigned oq_ = (unsigned)(b * sq_b) * (unsigned)sizeof(Real);\n"
@@ -308,18 +331,24 @@ class Emitter {
     o_ << "  {\n";
     for (int i : ch) {
       forward(i);
-      for (size_t e = 0; e < ee_.size(); ++e)
-        if (ee_[e] == i) jacobian((int)e);
+      if (do_crba_)
+        for (size_t e = 0; e < ee_.size(); ++e)
+          if (ee_[e] == i) jacobian((int)e);
     }
     for (auto it = ch.rbegin(); it != ch.rend(); ++it) backward(*it);
     const int sl = pl_.limb_slot[l], r = ch[0];
     if (sl >= 0) {
       const char* op = pl_.limb_first[l] ? " = " : " += ";
-      o_ << "  {\n    Real t_[3], S_[10];\n    bard::cross3(" << v("r", r) << ", " << v("F", r) << " + 3, t_);\n"
-         << "    for (int k = 0; k < 3; ++k) {\n      xch_[(" << sl * 16 << " + k) * 64 + lane]" << op << v("F", r)
-         << "[k] + t_[k];\n      xch_[(" << sl * 16 + 3 << " + k) * 64 + lane]" << op << v("F", r)
-         << "[3 + k];\n    }\n    bard::shift_inertia(" << v("K", r) << ", " << v("r", r) << ", S_);\n"
-         << "    for (int k = 0; k < 10; ++k) xch_[(" << sl * 16 + 6 << " + k) * 64 + lane]" << op << "S_[k];\n  }\n";
+      o_ << "  {\n    Real t_[3], S_[10];\n";
+      if (do_rnea_)
+        o_ << "    bard::cross3(" << v("r", r) << ", " << v("F", r) << " + 3, t_);\n"
+           << "    for (int k = 0; k < 3; ++k) {\n      xch_[(" << sl * 16 << " + k) * 64 + lane]" << op << v("F", r)
+           << "[k] + t_[k];\n      xch_[(" << sl * 16 + 3 << " + k) * 64 + lane]" << op << v("F", r)
+           << "[3 + k];\n    }\n";
+      if (do_crba_)
+        o_ << "    bard::shift_inertia(" << v("K", r) << ", " << v("r", r) << ", S_);\n"
+           << "    for (int k = 0; k < 10; ++k) xch_[(" << sl * 16 + 6 << " + k) * 64 + lane]" << op << "S_[k];\n";
+      o_ << "  }\n";
     }
     o_ << "  }\n";
   }
@@ -329,6 +358,8 @@ class Emitter {
   std::vector<int> ee_;
   int frame_;
   bool fp64_;
+  bool dual_;        // two workgroups per 64 instances: RNEA in one, CRBA and Jacobians in the other
+  bool do_rnea_ = true, do_crba_ = true;  // parts of the output the code being emitted computes
   SplitPlan pl_;
   bool split_;
   std::vector<char> trunk_;
@@ -454,6 +485,8 @@ class Emitter {
                    {c(i, C_T0 + r), ""}})
            << ";\n";
       o_ << "    for (int k = 0; k < 3; ++k) " << v("r", i) << "[k] = " << v("p", i) << "[k];\n";
+    }
+    if (t == J_FREE && do_rnea_) {
       // velocity coordinates [v; w] in the body frame -> world axes at the body origin
       o_ << "    Real vb_[3], wb_[3], ab_[3], wd_[3];\n";
       for (int k = 0; k < 3; ++k)
@@ -471,7 +504,8 @@ class Emitter {
         o_ << "    " << v("c", i) << "[" << r << "] = " << row("wd_") << ";\n";
         o_ << "    " << v("c", i) << "[" << 3 + r << "] = " << row("ab_") << " - g" << r << ";\n";
       }
-    } else {
+    }
+    if (t != J_FREE) {
       // joint transform (eqs. (4)-(5))
       if (t == J_REV)
         o_ << "    Real s_, c_;\n    bard::sincos_r(Qv(" << qi << "), &s_, &c_);\n"
@@ -514,6 +548,8 @@ class Emitter {
              << ";\n";
         }
       }
+    }
+    if (t != J_FREE && do_rnea_) {
       // parent state moved to this body's origin: u += w x r (velocity and spatial acceleration)
       o_ << "    Real vs_[6], as_[6];\n";
       if (p < 0) {
@@ -550,6 +586,7 @@ class Emitter {
   // (declared here, or beforehand in an outer scope)
   void body_force(int i, bool declare) {
     if (declare) o_ << "  Real " << v("I", i) << "[10], " << v("f", i) << "[6];\n";
+
     // [m, R h, R Ibar R^T] about the body origin, world axes; the constant
     // parameters as literals, zero ones left out
     const std::string R = v("R", i), I = v("I", i);
@@ -572,9 +609,11 @@ class Emitter {
       o_ << "    " << I << "[" << 4 + k << "] = X_[" << 3 * a << "] * " << Rk(3 * b) << " + X_[" << 3 * a + 1 << "] * "
          << Rk(3 * b + 1) << " + X_[" << 3 * a + 2 << "] * " << Rk(3 * b + 2) << ";\n";
     }
-    o_ << "    Real Iv_[6], vIv_[6];\n    bard::inertia_mul(" << v("I", i) << ", " << v("v", i) << ", Iv_);\n"
-       << "    bard::crf(" << v("v", i) << ", Iv_, vIv_);\n    bard::inertia_mul(" << v("I", i) << ", " << v("c", i)
-       << ", " << v("f", i) << ");\n    for (int k = 0; k < 6; ++k) " << v("f", i) << "[k] += vIv_[k];\n  }\n";
+    if (do_rnea_)
+      o_ << "    Real Iv_[6], vIv_[6];\n    bard::inertia_mul(" << v("I", i) << ", " << v("v", i) << ", Iv_);\n"
+         << "    bard::crf(" << v("v", i) << ", Iv_, vIv_);\n    bard::inertia_mul(" << v("I", i) << ", " << v("c", i)
+         << ", " << v("f", i) << ");\n    for (int k = 0; k < 6; ++k) " << v("f", i) << "[k] += vIv_[k];\n";
+    o_ << "  }\n";
   }
 
   // motion-subspace column d of body j about the body origin (world axes)
@@ -651,22 +690,36 @@ class Emitter {
   // ---- leaving body i: subtree force, torque, composite inertia, M ----
   void backward(int i) {
     const int t = m_->jtype[i], vi = m_->vi[i], nd = m_->nvi[i];
-    o_ << "  // body " << i << ": subtree sums\n  Real " << v("F", i) << "[6], " << v("K", i) << "[10];\n  {\n"
-       << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] = " << v("f", i) << "[k];\n"
-       << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] = " << v("I", i) << "[k];\n";
+    o_ << "  // body " << i << ": subtree sums\n  Real " << v("F", i) << "[6], " << v("K", i) << "[10];\n  {\n";
+    if (do_rnea_) o_ << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] = " << v("f", i) << "[k];\n";
+    if (do_crba_) o_ << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] = " << v("I", i) << "[k];\n";
     for (int ch : m_->children[i]) {
       if (split_ && trunk_[i] && !trunk_[ch]) continue;  // a limb: its wave's sum arrives through LDS
-      o_ << "    {\n      Real t_[3], S_[10];\n      bard::cross3(" << v("r", ch) << ", " << v("F", ch) << " + 3, t_);\n"
-         << "      for (int k = 0; k < 3; ++k) { " << v("F", i) << "[k] += " << v("F", ch) << "[k] + t_[k]; "
-         << v("F", i) << "[3 + k] += " << v("F", ch) << "[3 + k]; }\n      bard::shift_inertia(" << v("K", ch) << ", "
-         << v("r", ch) << ", S_);\n      for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += S_[k];\n    }\n";
+      o_ << "    {\n      Real t_[3], S_[10];\n";
+      if (do_rnea_)
+        o_ << "      bard::cross3(" << v("r", ch) << ", " << v("F", ch) << " + 3, t_);\n"
+           << "      for (int k = 0; k < 3; ++k) { " << v("F", i) << "[k] += " << v("F", ch) << "[k] + t_[k]; "
+           << v("F", i) << "[3 + k] += " << v("F", ch) << "[3 + k]; }\n";
+      if (do_crba_)
+        o_ << "      bard::shift_inertia(" << v("K", ch) << ", " << v("r", ch) << ", S_);\n"
+           << "      for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += S_[k];\n";
+      o_ << "    }\n";
     }
     for (size_t sl = 0; sl < slot_body_.size(); ++sl)
-      if (split_ && slot_body_[sl] == i)
-        o_ << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] += xch_[(" << sl * 16 << " + k) * 64 + lane];\n"
-           << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += xch_[(" << sl * 16 + 6
-           << " + k) * 64 + lane];\n";
-    // torque
+      if (split_ && slot_body_[sl] == i) {
+        if (do_rnea_)
+          o_ << "    for (int k = 0; k < 6; ++k) " << v("F", i) << "[k] += xch_[(" << sl * 16 << " + k) * 64 + lane];\n";
+        if (do_crba_)
+          o_ << "    for (int k = 0; k < 10; ++k) " << v("K", i) << "[k] += xch_[(" << sl * 16 + 6
+             << " + k) * 64 + lane];\n";
+      }
+    if (do_rnea_) torque(i);
+    if (do_crba_) mass_columns(i);
+    o_ << "  }\n";
+  }
+
+  void torque(int i) {
+    const int t = m_->jtype[i], vi = m_->vi[i];
     const std::string F = v("F", i), a = v("a", i), R = v("R", i);
     if (t == J_REV)
       o_ << "    TAU(" << vi << ", " << a << "[0] * " << F << "[0] + " << a << "[1] * " << F << "[1] + "
@@ -681,7 +734,11 @@ class Emitter {
            << "[" << 3 + e << "] * " << F << "[" << base + 1 << "] + " << R << "[" << 6 + e << "] * " << F << "["
            << base + 2 << "]);\n";
       }
-    // mass-matrix columns of this body's dofs
+  }
+
+  // mass-matrix columns of this body's dofs, and up the ancestors
+  void mass_columns(int i) {
+    const int vi = m_->vi[i], nd = m_->nvi[i];
     for (int d = 0; d < nd; ++d) {
       o_ << "    {\n      Real fc_[6];\n";
       emit_Ks(v("K", i), i, d, "fc_");
@@ -704,7 +761,6 @@ class Emitter {
       }
       o_ << "    }\n";
     }
-    o_ << "  }\n";
   }
 
   // Jacobian columns of end effector e (rows [linear; angular]).
@@ -757,11 +813,15 @@ std::string spec_key(int dtype, int frame, const std::vector<int>& ee, int form)
   return k;
 }
 
-std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, bool whole) {
-  return Emitter(m, ee, frame, fp64, whole).source();
+std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form) {
+  return Emitter(m, ee, frame, fp64, form).source();
 }
 
-int spec_waves(const bard_model* m, bool fp64, bool whole) { return make_plan(m, whole, fp64).waves; }
+int spec_waves(const bard_model* m, bool fp64, int form) { return make_plan(m, form == 1, fp64).waves; }
+
+bool spec_form_ok(const bard_model* m, bool fp64, int form) {
+  return form != 2 || make_plan(m, false, fp64).split;
+}
 
 
 
@@ -834,11 +894,10 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
   if (sk.code.empty()) {
     const auto t0 = std::chrono::steady_clock::now();
     std::string log;
-    const bool whole = form == 1;
     sk.form = form;
-    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64, whole), &sk.code, &log);
+    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64, form), &sk.code, &log);
     sk.zero_rows = spec_zero_rows(m, ee);
-    sk.waves = spec_waves(m, dtype == BARD_F64, whole);
+    sk.waves = spec_waves(m, dtype == BARD_F64, form);
     sk.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000));
   }
@@ -884,7 +943,7 @@ SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int
   std::vector<int> v(ee, ee + n_ee);
   const int bit = 1 << spec_tier(B);
   std::lock_guard<std::mutex> lk(m->mu);
-  for (int form = 0; form < 2; ++form) {
+  for (int form = 0; form < kSpecForms; ++form) {
     auto it = dc->spec.find(spec_key(dtype, frame, v, form));
     if (it != dc->spec.end() && it->second.fn && (it->second.route_tiers & bit)) return &it->second;
   }
@@ -898,10 +957,10 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   Real g0 = (Real)g[0], g1 = (Real)g[1], g2 = (Real)g[2];
   const Real *q = a.q, *qd = a.qd, *qdd = a.qdd;
   Real *tau = a.tau, *M = a.M, *J = a.J;
-  const int64_t main = (a.B + 63) / 64;
+  const int64_t main = (a.B + 63) / 64 * (sk->form == 2 ? 2 : 1);
   // Structural zeros: when every zero row is a run of B contiguous, 16-byte
   // aligned values (instance-minor M and J) and the computing workgroups fill
-  // at most a quarter of the device's wave slots, extra workgroups of the same
+  // at most a third of the device's wave slots, extra workgroups of the same
   // launch write them beside the computing waves (a few waves storing one
   // value per lane per zero entry are bound by instruction issue, not by
   // HBM); with more computing waves than that each lane writes its own,
@@ -910,7 +969,7 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   const bool rows = a.sM_b == 1 && a.sJ_b == 1 && a.B % V == 0 && a.sM_k % V == 0 && a.sJ_k % V == 0 &&
                     ((uintptr_t)a.M % 16) == 0 && ((uintptr_t)a.J % 16) == 0;
   int64_t zb = 0;
-  if (rows && sk->zero_rows > 0 && main * 4 <= sk->slots) {
+  if (rows && sk->zero_rows > 0 && main * 3 <= sk->slots) {
     const int64_t chunks = (int64_t)sk->zero_rows * ((a.B / V + 1023) / 1024);
     zb = std::min<int64_t>(chunks, sk->slots - main);
   }

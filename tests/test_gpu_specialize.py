@@ -2,7 +2,9 @@
 per-tree code behind bard_chain, through the C ABI.
 
 Parity: the routed chain call against the FP64 oracle under the per-entry
-contract (parity_util), both forms (split over waves by limbs, and whole),
+contract (parity_util), the three forms (split over waves by limbs, dual:
+split with the torques and the mass matrix + Jacobians in two workgroups, and
+whole),
 FP32 and FP64, both Jacobian frames, fixed and free roots, revolute and
 prismatic joints, single-body trees, batches with a ragged tail (64 instances
 per workgroup), the instance-major layout, a gravity change after
@@ -31,15 +33,15 @@ CASES = [("chain7", "float32", 1000, 0), ("chain7", "float64", 65, 1), ("quadrup
          ("rev1", "float32", 5, 1), ("pri1", "float64", 3, 0), ("free1", "float32", 65, 1)]
 
 
-@pytest.mark.parametrize("whole", [False, True])
+@pytest.mark.parametrize("form", ["split", "whole", "dual"])
 @pytest.mark.parametrize("name,dtype,B,frame", CASES)
-def test_specialized_chain_matches_oracle(name, dtype, B, frame, whole):
-    say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame} whole={whole}")
+def test_specialized_chain_matches_oracle(name, dtype, B, frame, form):
+    say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame} form={form}")
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
-    m.specialize(ee, frame=frame, dtype=dtype, whole=whole)
-    assert m.specialized_info(ee, frame=frame, dtype=dtype, whole=whole)["routed"]
+    m.specialize(ee, frame=frame, dtype=dtype, form=form)
+    assert m.specialized_info(ee, frame=frame, dtype=dtype, form=form)["routed"]
     q, qd, qdd = inputs(tree, B, 5300, dtype)
     tau, M, J = m.chain(to_dev(q, dtype), to_dev(qd, dtype), to_dev(qdd, dtype), ee, frame=frame)
     assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, from_dev(tau), from_dev(M), from_dev(J), dtype,
@@ -67,13 +69,13 @@ def test_routing_and_generic_results():
     back = m.chain(*d, ee)
     # routing one form takes every batch from the other
     m.specialize(ee, route=True)
-    m.specialize(ee, route=True, whole=True)
+    m.specialize(ee, route=True, form="whole")
     assert not m.specialized_info(ee)["routed"]
-    assert m.specialized_info(ee, whole=True)["route_tiers"] == 15
+    assert m.specialized_info(ee, form="whole")["route_tiers"] == 15
     whole = m.chain(*d, ee)
     torch.cuda.synchronize()
     assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in whole), "float32", label="whole")
-    m.specialize(ee, route=False, whole=True)
+    m.specialize(ee, route=False, form="whole")
     for a, b in zip(generic, kept):
         assert torch.equal(a, b)
     for a, b in zip(generic, back):
@@ -140,18 +142,18 @@ def test_autotune_routes_by_batch():
     ee = tree.ee_bodies
     ref = bard.Model.from_tree(tree)   # never specialised: the generic kernel
     mb = m.autotune_chain(ee)
-    split, whole = m.specialized_info(ee), m.specialized_info(ee, whole=True)
-    say(f"[gpu] autotuned chain on humanoid_small: first specialised batch {mb}, tiers split "
-        f"{split['route_tiers']:04b} whole {whole['route_tiers']:04b}")
+    tiers = {f: m.specialized_info(ee, form=f)["route_tiers"] for f in bard.SPEC_FORMS}
+    say(f"[gpu] autotuned chain on humanoid_small: first specialised batch {mb}, tiers " +
+        ", ".join(f"{f} {t:04b}" for f, t in tiers.items()))
     assert mb in (-1,) + bard.SPEC_TIERS
-    assert split["route_tiers"] & whole["route_tiers"] == 0
+    assert sum(bin(t).count("1") for t in tiers.values()) == bin(tiers["split"] | tiers["whole"] | tiers["dual"]).count("1")
     for B, tier in ((300, 0), (20000, 2)):
         q, qd, qdd = inputs(tree, B, 5700 + B, "float32")
         d = [to_dev(x, "float32") for x in (q, qd, qdd)]
         out = m.chain(*d, ee)
         gen = ref.chain(*d, ee)
         torch.cuda.synchronize()
-        if not ((split["route_tiers"] | whole["route_tiers"]) >> tier) & 1:
+        if not ((tiers["split"] | tiers["whole"] | tiers["dual"]) >> tier) & 1:
             for a, b in zip(out, gen):
                 assert torch.equal(a, b)
         idx = np.sort(np.random.default_rng(B).choice(B, min(B, 200), replace=False))
@@ -159,8 +161,9 @@ def test_autotune_routes_by_batch():
                      "float32", label=f"autotuned B={B}")
 
 
+@pytest.mark.parametrize("form", ["split", "dual"])
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype):
+def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype, form):
     """With instance-minor outputs, a batch that is a multiple of the 16-byte
     vector width and a grid that leaves wave slots free, the structural zeros
     of M and J come from extra workgroups; a ragged batch (B + 1) makes every
@@ -170,12 +173,12 @@ def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype):
     tree = synth.humanoid_large()
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
-    m.specialize(ee, dtype=dtype)
+    m.specialize(ee, dtype=dtype, form=form)
     B = 4096
     q, qd, qdd = inputs(tree, B + 1, 5800, dtype)
     res = []
     for n in (B, B + 1):
-        say(f"[gpu] specialised zero rows humanoid_large {dtype} B={n}")
+        say(f"[gpu] specialised zero rows humanoid_large {dtype} {form} B={n}")
         d = [to_dev(x[:n], dtype) for x in (q, qd, qdd)]
         nan = float("nan")
         out = tuple(torch.full((k, n), nan, dtype=getattr(torch, dtype), device="cuda")

@@ -1,5 +1,5 @@
 """Host side of the model specialiser (no GPU): the generated chain source for
-a tree, in both forms (split over waves by limbs, and whole), names every
+a tree, in each form (split over waves by limbs, dual, whole), names every
 dof's torque, every mass-matrix entry and every Jacobian column once or as a
 structural zero, and hipRTC compiles it for gfx950 (BARD_SPEC_COMPILE_ONLY),
 in FP32 and FP64 and both Jacobian frames; the split form gives each limb to
@@ -13,14 +13,16 @@ import synth
 from paper_2605_31481_amd import bard
 
 
-@pytest.mark.parametrize("name,dtype,frame,whole", [("chain7", "float32", 0, False), ("chain7", "float64", 1, True),
-                                                    ("quadruped_spine", "float32", 1, False),
-                                                    ("quadruped_spine", "float64", 0, True),
-                                                    ("free1", "float64", 0, False), ("star64", "float32", 0, False)])
-def test_generated_source_compiles(name, dtype, frame, whole):
+@pytest.mark.parametrize("name,dtype,frame,form", [("chain7", "float32", 0, "split"), ("chain7", "float64", 1, "whole"),
+                                                   ("chain7", "float32", 1, "dual"),
+                                                   ("quadruped_spine", "float32", 1, "split"),
+                                                   ("quadruped_spine", "float64", 0, "whole"),
+                                                   ("humanoid_small", "float32", 0, "dual"),
+                                                   ("free1", "float64", 0, "dual"), ("star64", "float32", 0, "split")])
+def test_generated_source_compiles(name, dtype, frame, form):
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
-    m.specialize(tree.ee_bodies, frame=frame, dtype=dtype, compile_only=True, whole=whole)
+    m.specialize(tree.ee_bodies, frame=frame, dtype=dtype, compile_only=True, form=form)
 
 
 def _table(src, which):
@@ -30,12 +32,12 @@ def _table(src, which):
     return [int(x) for x in vals[:n]]
 
 
-@pytest.mark.parametrize("whole", [False, True])
-def test_generated_source_covers_every_output(whole):
+@pytest.mark.parametrize("form", ["split", "whole", "dual"])
+def test_generated_source_covers_every_output(form):
     tree = synth.humanoid_small()
     m = bard.Model.from_tree(tree)
     ee = tree.ee_bodies
-    src = m.specialized_source(ee, whole=whole)
+    src = m.specialized_source(ee, form=form)
     nv = tree.nv
     tau = {int(k) for k in re.findall(r"TAU\((\d+), ", src)}
     assert tau == set(range(nv))
@@ -67,5 +69,8 @@ def test_split_form_waves(name, waves):
     src = m.specialized_source(tree.ee_bodies)
     assert int(re.search(r"NW = (\d+);", src).group(1)) == waves
     assert ("__syncthreads" in src) == (waves > 1)
-    whole = m.specialized_source(tree.ee_bodies, whole=True)
+    whole = m.specialized_source(tree.ee_bodies, form="whole")
     assert int(re.search(r"NW = (\d+);", whole).group(1)) == 1
+    dual = m.specialized_source(tree.ee_bodies, form="dual")
+    assert int(re.search(r"NW = (\d+);", dual).group(1)) == waves
+    assert int(re.search(r"WG_PER_GROUP = (\d+);", dual).group(1)) == 2
