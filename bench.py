@@ -348,7 +348,9 @@ def bench_specialized(torch, bard):
     split with torques and mass matrix + Jacobians in two workgroups, and the whole
     tree per wave) on the 36-DOF and 23-DOF humanoids and the 7-DOF chain at
     B = 1024 .. 262,144, rotating sets past 512 MB; then the tiers
-    bard_chain_autotune routes to each form."""
+    bard_chain_autotune routes to each form; then the specialised
+    forward-dynamics (ABA) kernel against the generic one at the same
+    batches, and the tiers bard_aba_autotune routes to it."""
     import synth
     out = {}
     for name, batches in (("humanoid_large", (1024, 4096, 16384, 65536, 262144)),
@@ -382,6 +384,34 @@ def bench_specialized(torch, bard):
             torch.cuda.empty_cache()
         out[f"spec_{name}_autotuned_first_batch"] = m.autotune_chain(ee)
         out[f"spec_{name}_autotuned_tiers"] = {f: m.specialized_info(ee, form=f)["route_tiers"] for f in forms}
+        # forward dynamics (ABA): generic and specialised kernel on rotating sets
+        m.specialize_aba(route=False)
+        info = m.specialized_aba_info()
+        out[f"spec_aba_{name}_vgprs"] = info["vgprs"]
+        out[f"spec_aba_{name}_scratch_bytes"] = info["scratch_bytes"]
+        out[f"spec_aba_{name}_compile_s"] = info["compile_s"]
+        abpe = 4 * (tree.nq + 3 * tree.nv)
+        for B in batches:
+            nsets = max(2, min(64, math.ceil(512e6 / (abpe * B))))
+            sets = []
+            for k in range(nsets):
+                q, qd, _ = synth.random_state(tree, B, 14000 + B + k)
+                d = [torch.from_numpy(x.T.copy()).float().cuda() for x in (q, qd, qd)]   # qd's values as torques
+                sets.append((d, torch.empty((tree.nv, B), device="cuda")))
+            calls = [m.bind_aba(d[0], d[1], d[2], o) for (d, o) in sets]
+            n = max(30, min(400, 2_000_000 // B))
+            key = f"spec_aba_{name}_B{B}"
+            m.specialize_aba(route=False)
+            _, kg = time_calls(torch, calls, n, 5)
+            m.specialize_aba(route=True)
+            _, ks = time_calls(torch, calls, n, 5)
+            out[key + "_generic_us"] = kg * 1e3
+            out[key + "_specialized_us"] = ks * 1e3
+            out[key + "_specialized_evals_per_s"] = B / (ks * 1e-3)
+            del sets, calls
+            torch.cuda.empty_cache()
+        out[f"spec_aba_{name}_autotuned_first_batch"] = m.autotune_aba()
+        out[f"spec_aba_{name}_autotuned_tiers"] = m.specialized_aba_info()["route_tiers"]
     return out
 
 
@@ -709,9 +739,10 @@ def main():
         extra["batch16384_kernel_us"] = k2 * 1e3
         extra["batch16384_hbm_frac"] = bpe * B2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS
         del sets2, calls2
-        # the 23-velocity-DOF companion tree
+        # the 23-velocity-DOF companion tree, autotuned as the headline is
         ts = synth.humanoid_small()
         ms = bard.Model.from_tree(ts)
+        extra["nv23_autotuned_first_specialised_batch"] = ms.autotune_chain(ts.ee_bodies)
         bpe_s = chain_bytes_per_eval(ts, len(ts.ee_bodies))
         sets3 = make_sets(torch, ts, B, max(14, math.ceil(512e6 / (bpe_s * B))), 5002)
         calls3 = [ms.bind_chain(d[0], d[1], d[2], ts.ee_bodies, tuple(o)) for (d, o, _) in sets3]

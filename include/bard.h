@@ -210,6 +210,29 @@ int bard_chain_autotune(bard_model_t model, bard_dtype dtype, int32_t n_ee, cons
 int bard_model_specialized_source(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                                   bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len);
 
+/* The forward dynamics of bard_aba written for one tree in the same way (one
+ * wave per 64 instances over the whole tree, constants as literals; the
+ * articulated-body algorithm's three passes of Sec. 3, in the base frame as
+ * the generic kernel computes them): passes 1 and 2 in one depth-first walk
+ * holding only the current path's state, pass 3 with what each body's
+ * articulated solve leaves (U / D and the scaled bias) and its kinematics
+ * recomputed.
+ * specialize_aba: compile and load (flags BARD_SPEC_ROUTE: bard_aba calls of
+ * this dtype on this device then launch it at every batch;
+ * BARD_SPEC_COMPILE_ONLY: compile only, no GPU).  Errors as
+ * bard_model_specialize; BARD_E_UNSUPPORTED for trees deeper than 16.
+ * aba_info: resources and routed batch tiers of the loaded kernel.
+ * aba_autotune: times the generic and the specialised kernel at B = 1024,
+ * 4096, 16384, 65536 and routes each tier to the faster; *min_batch as for
+ * bard_chain_autotune.  aba_source: the generated text.  Routed calls whose
+ * per-instance byte offset into an array reaches 4 GiB run the generic
+ * kernel. */
+int bard_model_specialize_aba(bard_model_t model, bard_dtype dtype, int32_t flags);
+int bard_model_specialized_aba_info(bard_model_t model, bard_dtype dtype, int32_t* vgprs, int32_t* scratch_bytes,
+                                    double* compile_seconds, int32_t* routed_tiers);
+int bard_aba_autotune(bard_model_t model, bard_dtype dtype, void* stream, int64_t* min_batch);
+int bard_model_specialized_aba_source(bard_model_t model, bard_dtype dtype, char* buf, int64_t cap, int64_t* len);
+
 /* ------------------------------------------------------------ workspace ----
  * A workspace holds cached state of one stream for up to max_batch instances
  * (Sec. 3.1's tiered lazy evaluation, extended to dynamics results), in

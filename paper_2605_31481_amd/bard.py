@@ -97,6 +97,12 @@ bard_model_specialized_info = _sig("bard_model_specialized_info",
 bard_model_specialized_source = _sig("bard_model_specialized_source",
                                      [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32, ctypes.c_char_p, _i64,
                                       ctypes.POINTER(_i64)])
+bard_model_specialize_aba = _sig("bard_model_specialize_aba", [_vp, ctypes.c_int, _i32])
+bard_model_specialized_aba_info = _sig("bard_model_specialized_aba_info",
+                                       [_vp, ctypes.c_int, _c_i32p, _c_i32p, ctypes.POINTER(ctypes.c_double), _c_i32p])
+bard_aba_autotune = _sig("bard_aba_autotune", [_vp, ctypes.c_int, _vp, ctypes.POINTER(_i64)])
+bard_model_specialized_aba_source = _sig("bard_model_specialized_aba_source",
+                                         [_vp, ctypes.c_int, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
 bard_chain_autotune = _sig("bard_chain_autotune", [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _vp,
                                                    ctypes.POINTER(_i64)])
 bard_ws_create = _sig("bard_ws_create", [_vp, ctypes.c_int, _i64, ctypes.POINTER(_vp)])
@@ -480,6 +486,38 @@ class Model:
         buf = ctypes.create_string_buffer(n.value + 1)
         _check(bard_model_specialized_source(self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame), fl, buf,
                                              n.value + 1, ctypes.byref(n)), "bard_model_specialized_source")
+        return buf.value.decode()
+
+    def specialize_aba(self, dtype=None, route: bool = True, compile_only: bool = False):
+        """Compile the model-specialised forward-dynamics kernel with hipRTC
+        and load it; with route=True, aba() calls use it at every batch."""
+        flags = (SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0)
+        _check(bard_model_specialize_aba(self._h, self._dtype_arg(dtype), flags), "bard_model_specialize_aba")
+
+    def autotune_aba(self, dtype=None) -> int:
+        """Time the generic and the specialised forward-dynamics kernels and
+        route each batch tier to the faster (bard_aba_autotune)."""
+        torch = _torch()
+        mb = _i64()
+        _check(bard_aba_autotune(self._h, self._dtype_arg(dtype), _vp(torch.cuda.current_stream().cuda_stream),
+                                 ctypes.byref(mb)), "bard_aba_autotune")
+        return mb.value
+
+    def specialized_aba_info(self, dtype=None) -> dict:
+        vg, sc, rt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cs = ctypes.c_double()
+        _check(bard_model_specialized_aba_info(self._h, self._dtype_arg(dtype), ctypes.byref(vg), ctypes.byref(sc),
+                                               ctypes.byref(cs), ctypes.byref(rt)), "bard_model_specialized_aba_info")
+        return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
+                "route_tiers": rt.value}
+
+    def specialized_aba_source(self, dtype=None) -> str:
+        n = _i64()
+        _check(bard_model_specialized_aba_source(self._h, self._dtype_arg(dtype), None, 0, ctypes.byref(n)),
+               "bard_model_specialized_aba_source")
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(bard_model_specialized_aba_source(self._h, self._dtype_arg(dtype), buf, n.value + 1, ctypes.byref(n)),
+               "bard_model_specialized_aba_source")
         return buf.value.decode()
 
     @staticmethod

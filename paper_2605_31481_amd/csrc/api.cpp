@@ -877,6 +877,135 @@ int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee
   return BARD_OK;
 }
 
+static int spec_aba_args(bard_model_t m, bard_dtype dtype) {
+  if (!m) return fail(BARD_E_ARG, "NULL model");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
+  if (m->depth > kSpecAbaMaxDepth)
+    return fail(BARD_E_UNSUPPORTED, "tree too deep for a specialised forward-dynamics kernel (depth " +
+                                        std::to_string(m->depth) + "); the generic kernel serves it");
+  return BARD_OK;
+}
+
+int bard_model_specialize_aba(bard_model_t m, bard_dtype dtype, int32_t flags) {
+  int rc = spec_aba_args(m, dtype);
+  if (rc) return rc;
+  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY)) return fail(BARD_E_ARG, "unknown flags");
+  if (flags & BARD_SPEC_COMPILE_ONLY) {
+    std::vector<char> code;
+    std::string log;
+    rc = spec_compile(spec_aba_source(m, dtype == BARD_F64, true), &code, &log);
+    return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
+  }
+  if ((rc = check_device_state())) return rc;
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, nullptr))) return rc;
+  SpecKernel* sk = nullptr;
+  if ((rc = spec_prepare_aba(m, dc, (int)dtype, true, &sk))) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  sk->route_tiers = (flags & BARD_SPEC_ROUTE) ? (1 << kSpecTiers) - 1 : 0;
+  spec_refresh_route(m);
+  return BARD_OK;
+}
+
+int bard_model_specialized_aba_info(bard_model_t m, bard_dtype dtype, int32_t* vgprs, int32_t* scratch_bytes,
+                                    double* compile_seconds, int32_t* routed_tiers) {
+  if (!m) return fail(BARD_E_ARG, "NULL model");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = m->dev[dev].spec.find(spec_aba_key((int)dtype));
+  if (it == m->dev[dev].spec.end() || !it->second.fn)
+    return fail(BARD_E_STATE, "no specialised forward-dynamics kernel on the current device");
+  if (vgprs) *vgprs = it->second.vgprs;
+  if (scratch_bytes) *scratch_bytes = it->second.scratch;
+  if (compile_seconds) *compile_seconds = it->second.compile_s;
+  if (routed_tiers) *routed_tiers = it->second.route_tiers;
+  return BARD_OK;
+}
+
+int bard_aba_autotune(bard_model_t m, bard_dtype dtype, void* stream, int64_t* min_batch) {
+  int rc = spec_aba_args(m, dtype);
+  if (rc) return rc;
+  if ((rc = check_device_state())) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (capturing(st)) return fail(BARD_E_CAPTURE, "autotuning allocates and synchronises; not under capture");
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, st))) return rc;
+  SpecKernel* sk = nullptr;
+  if ((rc = spec_prepare_aba(m, dc, (int)dtype, true, &sk))) return rc;
+  const int64_t Bmax = kSpecTierBatch[kSpecTiers - 1];
+  const size_t rs = dtype == BARD_F64 ? 8 : 4;
+  const int64_t nin = (int64_t)m->nq + 2 * m->nv, nout = m->nv;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, (size_t)(nin + nout) * Bmax * rs) != hipSuccess)
+    return fail(BARD_E_NOMEM, "hipMalloc of the autotuning arrays failed");
+  {
+    // q = 0.1 everywhere (a unit quaternion is not needed: the kernels
+    // normalise), qd = 0.1, tau = 0.1
+    std::vector<unsigned char> host((size_t)nin * Bmax * rs);
+    for (int64_t k = 0; k < nin * Bmax; ++k) {
+      if (dtype == BARD_F64) reinterpret_cast<double*>(host.data())[k] = 0.1;
+      else reinterpret_cast<float*>(host.data())[k] = 0.1f;
+    }
+    if (hipMemcpy(buf, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(buf);
+      return fail(BARD_E_DEVICE, "upload of the autotuning inputs failed");
+    }
+  }
+  double t[kSpecTiers][2] = {};
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    for (int k = 0; k < kSpecTiers; ++k) {
+      const int64_t B = kSpecTierBatch[k];
+      R* base = (R*)buf;
+      Args<R> a = blank_args<R>(B);
+      a.q = base;
+      a.qd = base + m->nq * B;
+      a.tau_in = base + (int64_t)(m->nq + m->nv) * B;
+      a.qdd_out = base + nin * Bmax;
+      a.sq_b = a.sqd_b = a.sti_b = a.sqo_b = 1;
+      a.sq_k = a.sqd_k = a.sti_k = a.sqo_k = B;
+      const int reps = B >= 16384 ? 5 : 20;
+      int r = time_launches([&] { return run_aba<R>(m, a, st); }, st, reps, &t[k][0]);
+      if (!r) r = time_launches([&] { return spec_aba_launch<R>(sk, a, m->g, st); }, st, reps, &t[k][1]);
+      if (r) return r;
+    }
+    return BARD_OK;
+  };
+  rc = dtype == BARD_F32 ? go(0.0f) : go(0.0);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(buf);
+  if (rc) return rc;
+  int tiers = 0;
+  int64_t first = -1;
+  for (int k = 0; k < kSpecTiers; ++k)
+    if (t[k][1] < t[k][0]) {
+      tiers |= 1 << k;
+      if (first < 0) first = k == 0 ? 0 : kSpecTierBatch[k];
+    }
+  {
+    std::lock_guard<std::mutex> lk(m->mu);
+    sk->route_tiers = tiers;
+    spec_refresh_route(m);
+  }
+  if (min_batch) *min_batch = first;
+  return BARD_OK;
+}
+
+int bard_model_specialized_aba_source(bard_model_t m, bard_dtype dtype, char* buf, int64_t cap, int64_t* len) {
+  int rc = spec_aba_args(m, dtype);
+  if (rc) return rc;
+  const std::string src = spec_aba_source(m, dtype == BARD_F64, true);
+  if (len) *len = (int64_t)src.size();
+  if (buf && cap > 0) {
+    const size_t k = std::min<size_t>((size_t)cap - 1, src.size());
+    std::memcpy(buf, src.data(), k);
+    buf[k] = 0;
+  }
+  return BARD_OK;
+}
+
 int bard_ws_create(bard_model_t m, bard_dtype dtype, int64_t max_batch, bard_ws_t* out) {
   if (!m || !out) return fail(BARD_E_ARG, "NULL argument");
   if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
@@ -1084,6 +1213,12 @@ int bard_aba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, cons
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, m->nv, &a.sqd_b, &a.sqd_k) ||
         !layout_of(L, 2, B, m->nv, &a.sti_b, &a.sti_k) || !layout_of(L, 3, B, m->nv, &a.sqo_b, &a.sqo_k))
       return fail(BARD_E_ARG, "bad layout stride");
+    if (m->spec_route.load()) {
+      DeviceCopy* dc = nullptr;
+      if ((rc = ensure_device(m, &dc, (hipStream_t)stream))) return rc;
+      SpecKernel* sk = spec_lookup_aba(m, dc, (int)dtype, B);
+      if (sk && spec_aba_fits(a)) return spec_aba_launch<R>(sk, a, m->g, (hipStream_t)stream);
+    }
     return run_aba<R>(m, a, (hipStream_t)stream);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);

@@ -45,6 +45,9 @@ int spec_tier(int64_t B);
 constexpr int kSpecForms = 3;
 // Source text of the kernel for one (end-effector set, frame, precision, form).
 std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form);
+// Source text of the specialised forward-dynamics (ABA) kernel of a tree.
+std::string spec_aba_source(const bard_model* m, bool fp64, bool split);
+int spec_aba_waves(const bard_model* m, bool fp64, bool split);
 // Waves per workgroup of that kernel (64 instances per workgroup).
 int spec_waves(const bard_model* m, bool fp64, int form);
 // Whether the tree has a plan for the form (the dual form needs a split plan).
@@ -60,6 +63,19 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
 // The routed specialised kernel for a chain call of batch B, or null.
 SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int n_ee, const int32_t* ee,
                         int64_t B);
+// The specialised forward-dynamics kernel: compile/load, routed lookup for a
+// batch, whether a call's lane offsets fit 32 bits, launch with bard_aba's
+// arguments.
+std::string spec_aba_key(int dtype);
+int spec_prepare_aba(bard_model* m, DeviceCopy* dc, int dtype, bool load, SpecKernel** out);
+SpecKernel* spec_lookup_aba(bard_model* m, DeviceCopy* dc, int dtype, int64_t B);
+template <class Real>
+bool spec_aba_fits(const Args<Real>& a);
+template <class Real>
+int spec_aba_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st);
+// Largest tree depth the specialised forward-dynamics kernel takes (the state
+// of the bodies on the current path stays in registers).
+constexpr int kSpecAbaMaxDepth = 16;
 // Launch a specialised chain kernel with a chain call's arguments.
 template <class Real>
 int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st);

@@ -139,8 +139,9 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64, int max_waves = 
 // Emits the source text of one specialised chain kernel.
 class Emitter {
  public:
-  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form)
-      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), dual_(form == 2), pl_(make_plan(m, form == 1, fp64)),
+  Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form,
+          int max_waves = SplitPlan::kMaxWaves)
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), dual_(form == 2), pl_(make_plan(m, form == 1, fp64, max_waves)),
         split_(pl_.split || dual_) {
     trunk_ = pl_.trunk;
     slot_body_ = pl_.slot_body;
@@ -353,7 +354,7 @@ class Emitter {
     o_ << "  }\n";
   }
 
- private:
+ protected:
   const bard_model* m_;
   std::vector<int> ee_;
   int frame_;
@@ -799,6 +800,446 @@ class Emitter {
   }
 };
 
+
+// Emits the source of one specialised forward-dynamics (ABA) kernel: one
+// wave per 64 instances over the whole tree, in base-frame coordinates (world
+// axes, vectors about the root's origin -- a fixed base's world origin, a
+// free root's own origin), so a child's articulated inertia and bias force
+// add to its parent's without a transform, as in the generic kernel.
+// Passes 1 and 2 run in one depth-first walk: entering a body its pose,
+// motion subspace, velocity, velocity-product acceleration, rigid inertia
+// and bias force; leaving it (after its children) its articulated inertia,
+// U = IA s, D = s^T U, u = tau - s^T pA, and what it hands to its parent, so
+// only the state of the bodies on the current path is held.  Pass 3 needs
+// per body only W = U / D and e = (u - U.c) / D (qdd = e - W.a_parent) and
+// recomputes the kinematics and velocities on a second walk.  A free root
+// factors its 6x6 D by Cholesky.
+class AbaEmitter : public Emitter {
+ public:
+  // split: limbs in waves of their own (the chain kernel's plan) when the
+  // tree has one and its LDS hand-over fits; otherwise the whole tree in one
+  // wave
+  AbaEmitter(const bard_model* m, bool fp64, bool split) : Emitter(m, {}, 0, fp64, split ? 0 : 1) {
+    do_rnea_ = false;
+    aba_split_ = split && split_ && split_fits();
+  }
+
+  bool is_split() const { return aba_split_; }
+  int waves() const { return aba_split_ ? pl_.waves : 1; }
+
+  // every loop of the generated code has constant bounds; unrolled, the
+  // arrays it indexes stay in registers
+  std::string source() {
+    std::string src = aba_split_ ? source_split() : source_whole();
+    std::string out;
+    const std::string pat = "for (int ";
+    size_t at = 0;
+    for (size_t k; (k = src.find(pat, at)) != std::string::npos; at = k + pat.size()) {
+      out.append(src, at, k - at);
+      out += "_Pragma(\"unroll\") " + pat;
+    }
+    out.append(src, at, std::string::npos);
+    return out;
+  }
+
+  void header() {
+    const int n = m_->n;
+    o_ << "// generated: forward dynamics (ABA) for one tree (" << n << " bodies, nv " << m_->nv << ", "
+       << (fp64_ ? "FP64" : "FP32") << (aba_split_ ? ", split over waves by limbs" : ", one wave per instance group")
+       << ")\n#include \"spatial.h\"\n";
+    o_ << "typedef " << (fp64_ ? "double" : "float") << " Real;\n";
+    o_ << "template <class T>\n"
+          "__device__ __forceinline__ T* bard_at(T* base, long long k, long long sk, unsigned ob) {\n"
+          "  return (T*)((const char*)(base + k * sk) + ob);\n"
+          "}\n"
+          "#define Q(k) (*bard_at(q, (k), sq_k, oq_))\n"
+          "#define QD(k) (*bard_at(qd, (k), sqd_k, oqd_))\n"
+          "#define TIN(k) (*bard_at(tau, (k), st_k, ot_))\n"
+          "#define QDDO(k, v) (*bard_at(qdd, (k), so_k, oo_) = (v))\n"
+          "#define WL(slot, k) wl_[((slot) * 7 + (k)) * 64 + lane]\n"
+          "#define Qv(k) Qv_##k\n"
+          "#define QDv(k) QDv_##k\n"
+          "#define TAUv(k) TAUv_##k\n"
+          // upper-triangle index of a symmetric 6x6 matrix
+          "__device__ constexpr int SI(int r, int c) { return r <= c ? r * 6 - r * (r - 1) / 2 + (c - r)"
+          " : c * 6 - c * (c - 1) / 2 + (r - c); }\n";
+  }
+
+  void params() {
+    o_ << "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ tau,\n"
+          "    Real* __restrict__ qdd, long long sq_b, long long sq_k, long long sqd_b, long long sqd_k,\n"
+          "    long long st_b, long long st_k, long long so_b, long long so_k, long long B, Real g0, Real g1,\n"
+          "    Real g2) {\n";
+  }
+
+  void offsets() {
+    o_ << "  const unsigned oq_ = (unsigned)(b * sq_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oqd_ = (unsigned)(b * sqd_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned ot_ = (unsigned)(b * st_b) * (unsigned)sizeof(Real);\n"
+          "  const unsigned oo_ = (unsigned)(b * so_b) * (unsigned)sizeof(Real);\n"
+          "  const Real a0_[6] = {Real(0), Real(0), Real(0), -g0, -g1, -g2};\n";
+  }
+
+  std::string source_whole() {
+    const int n = m_->n;
+    header();
+    o_ << "static constexpr int NW = 1;  // waves per workgroup, 64 instances\n";
+    o_ << "extern \"C\" __global__ void __launch_bounds__(64) bard_spec_aba(\n";
+    params();
+    o_ << "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
+          "  if (b >= B) return;\n"
+          "  const int lane = (int)threadIdx.x;\n";
+    offsets();
+    // what pass 3 needs of each body: W = U / D and e in LDS (7 values per
+    // lane; each lane reads only its own), a free root's factors in registers
+    // (formed last in pass 2, used first in pass 3)
+    slot_.assign(n, -1);
+    int ns = 0;
+    for (int i = 0; i < n; ++i)
+      if (m_->jtype[i] == J_FREE) o_ << "  Real Ur" << i << "[36], Lr" << i << "[21], ur" << i << "[6];\n";
+      else slot_[i] = ns++;
+    if (ns) o_ << "  __shared__ Real wl_[" << ns * 7 * 64 << "];\n";
+    o_ << "  // passes 1 and 2\n";
+    for (int i = 0; i < n; ++i)
+      if (m_->parent[i] < 0) walk12(i);
+    o_ << "  // pass 3\n";
+    for (int i = 0; i < n; ++i)
+      if (m_->parent[i] < 0) walk3(i);
+    o_ << "}\n";
+    return o_.str();
+  }
+
+ private:
+  // upper-triangle index of a symmetric 6x6 matrix, at generation time
+  static int si(int r, int c) {
+    if (r > c) std::swap(r, c);
+    return r * 6 - r * (r - 1) / 2 + (c - r);
+  }
+  static std::string ix(const std::string& a, int k) { return a + "[" + std::to_string(k) + "]"; }
+
+  std::vector<int> slot_;  // LDS slot of each body's W and e
+  bool aba_split_ = false;
+  enum Mode { WHOLE, LIMB, TRUNK };
+  Mode mode_ = WHOLE;
+  std::vector<int> at_slot_;  // LDS slot of the acceleration of each trunk body with limbs attached
+
+  // LDS of the split form: W and e of every non-free body, a limb sum (21 +
+  // 6) per (wave, trunk body) slot, a trunk body's acceleration per attach
+  // body; a free root inside a limb would need its factors across barriers
+  bool split_fits() {
+    const int n = m_->n;
+    int nwl = 0, nat = 0;
+    std::vector<char> has_limb(n, 0);
+    for (size_t l = 0; l < pl_.limbs.size(); ++l) {
+      const int r = pl_.limbs[l][0], at = m_->parent[r];
+      if (at >= 0) has_limb[at] = 1;
+      else if (m_->jtype[r] == J_FREE && !pl_.slot_body.empty()) return false;
+    }
+    bool any_trunk = false;
+    for (int i = 0; i < n; ++i) {
+      if (m_->jtype[i] != J_FREE) ++nwl;
+      nat += has_limb[i];
+      any_trunk = any_trunk || trunk_[i];
+    }
+    if (!any_trunk) nat = 0;
+    const size_t bytes = (size_t)(nwl * 7 + pl_.slot_body.size() * 27 + nat * 6) * 64 * (fp64_ ? 8 : 4);
+    return bytes <= 150 * 1024;
+  }
+
+  // pose, motion subspace s (or the free root's S), velocity v, velocity-
+  // product acceleration cJ, all about the reference point; the body's joint
+  // inputs loaded here
+  void kin_vel(int i) {
+    const int p = m_->parent[i], t = m_->jtype[i], vi = m_->vi[i];
+    const int nq = t == J_FREE ? 7 : 1;
+    for (int k = 0; k < nq; ++k) o_ << "  const Real Qv_" << m_->qi[i] + k << " = Q(" << m_->qi[i] + k << ");\n";
+    for (int k = 0; k < m_->nvi[i]; ++k) o_ << "  const Real QDv_" << vi + k << " = QD(" << vi + k << ");\n";
+    forward_kin(i);
+    if (t == J_FREE && p < 0)
+      o_ << "  for (int k = 0; k < 3; ++k) { " << v("p", i) << "[k] = Real(0); " << v("r", i) << "[k] = Real(0); }\n";
+    const std::string R = v("R", i);
+    if (t == J_FREE) {
+      // columns [0; R e_d] for the linear dofs, [R e_d; 0] for the angular ones
+      o_ << "  Real " << v("S", i) << "[36], " << v("V", i) << "[6], " << v("cJ", i) << "[6];\n  {\n";
+      for (int d = 0; d < 6; ++d)
+        for (int k = 0; k < 6; ++k) {
+          const bool lin_dof = d < 3;
+          const bool nz = lin_dof ? k >= 3 : k < 3;
+          const int e = d % 3, row = k % 3;
+          o_ << "    " << v("S", i) << "[" << d * 6 + k << "] = "
+             << (nz ? R + "[" + std::to_string(3 * row + e) + "]" : std::string("Real(0)")) << ";\n";
+        }
+      o_ << "    for (int k = 0; k < 6; ++k) { " << v("V", i) << "[k] = Real(0);";
+      for (int d = 0; d < 6; ++d) o_ << " " << v("V", i) << "[k] += " << v("S", i) << "[" << d * 6 << " + k] * QDv(" << vi + d << ");";
+      o_ << " }\n";
+      if (p >= 0) o_ << "    // (a free joint below the root is refused by the model compiler)\n";
+      o_ << "    for (int k = 0; k < 6; ++k) " << v("cJ", i) << "[k] = Real(0);\n  }\n";
+      return;
+    }
+    o_ << "  Real " << v("s", i) << "[6], " << v("V", i) << "[6], " << v("cJ", i) << "[6];\n  {\n";
+    const std::string a = v("a", i), pp = v("p", i), s = v("s", i);
+    if (t == J_REV)
+      o_ << "    for (int k = 0; k < 3; ++k) " << s << "[k] = " << a << "[k];\n    bard::cross3(" << pp << ", " << a
+         << ", " << s << " + 3);\n";
+    else
+      o_ << "    for (int k = 0; k < 3; ++k) { " << s << "[k] = Real(0); " << s << "[3 + k] = " << a << "[k]; }\n";
+    o_ << "    Real vJ_[6];\n    for (int k = 0; k < 6; ++k) vJ_[k] = " << s << "[k] * QDv(" << vi << ");\n";
+    if (p >= 0)
+      o_ << "    bard::crm(" << v("V", p) << ", vJ_, " << v("cJ", i) << ");\n    for (int k = 0; k < 6; ++k) "
+         << v("V", i) << "[k] = " << v("V", p) << "[k] + vJ_[k];\n";
+    else
+      o_ << "    for (int k = 0; k < 6; ++k) { " << v("cJ", i) << "[k] = Real(0); " << v("V", i) << "[k] = vJ_[k]; }\n";
+    o_ << "  }\n";
+  }
+
+  // whether body i hands its articulated inertia to its parent through LDS
+  bool to_slot(int i) const { return mode_ == LIMB && m_->parent[i] >= 0 && trunk_[m_->parent[i]]; }
+
+  void walk12(int i) {
+    const int t = m_->jtype[i], vi = m_->vi[i];
+    if (m_->parent[i] >= 0 && !to_slot(i)) o_ << "  Real " << v("Ia", i) << "[21], " << v("pa", i) << "[6];\n";
+    o_ << "  {\n";
+    kin_vel(i);
+    for (int ch : m_->children[i])
+      if (!(mode_ == TRUNK && !trunk_[ch])) walk12(ch);
+    // leaving the body: its rigid inertia about the body origin (world axes),
+    // about the reference point, and its bias force pA = v x* (I v)
+    body_force(i, true);
+    o_ << "  Real " << v("I0", i) << "[10], " << v("pA", i) << "[6];\n  {\n    bard::shift_inertia(" << v("I", i)
+       << ", " << v("p", i) << ", " << v("I0", i) << ");\n    Real Iv_[6];\n    bard::inertia_mul(" << v("I0", i)
+       << ", " << v("V", i) << ", Iv_);\n    bard::crf(" << v("V", i) << ", Iv_, " << v("pA", i) << ");\n  }\n";
+    // leaving the body: articulated inertia and bias force with the children's
+    const std::string I0 = v("I0", i);
+    // the rigid inertia [Ibar, h x; -h x, m 1] as a symmetric 6x6
+    const std::string ent[6][6] = {
+        {ix(I0, 4), ix(I0, 5), ix(I0, 7), "Real(0)", "-" + ix(I0, 3), ix(I0, 2)},
+        {"", ix(I0, 6), ix(I0, 8), ix(I0, 3), "Real(0)", "-" + ix(I0, 1)},
+        {"", "", ix(I0, 9), "-" + ix(I0, 2), ix(I0, 1), "Real(0)"},
+        {"", "", "", ix(I0, 0), "Real(0)", "Real(0)"},
+        {"", "", "", "", ix(I0, 0), "Real(0)"},
+        {"", "", "", "", "", ix(I0, 0)}};
+    o_ << "  {\n    Real IA_[21], pA_[6];\n";
+    for (int r = 0; r < 6; ++r)
+      for (int c = r; c < 6; ++c) o_ << "    IA_[" << si(r, c) << "] = " << ent[r][c] << ";\n";
+    o_ << "    for (int k = 0; k < 6; ++k) pA_[k] = " << v("pA", i) << "[k];\n";
+    for (int ch : m_->children[i])
+      if (!(mode_ == TRUNK && !trunk_[ch]))
+        o_ << "    for (int k = 0; k < 21; ++k) IA_[k] += " << v("Ia", ch) << "[k];\n    for (int k = 0; k < 6; ++k) pA_[k] += "
+           << v("pa", ch) << "[k];\n";
+    if (mode_ == TRUNK)
+      for (size_t sl = 0; sl < pl_.slot_body.size(); ++sl)
+        if (pl_.slot_body[sl] == i)
+          o_ << "    for (int k = 0; k < 21; ++k) IA_[k] += xa_[(" << sl * 27 << " + k) * 64 + lane];\n"
+             << "    for (int k = 0; k < 6; ++k) pA_[k] += xa_[(" << sl * 27 + 21 << " + k) * 64 + lane];\n";
+    for (int k = 0; k < m_->nvi[i]; ++k) o_ << "    const Real TAUv_" << vi + k << " = TIN(" << vi + k << ");\n";
+    if (t == J_FREE) {
+      const std::string S = v("S", i), U = "Ur" + std::to_string(i), L = "Lr" + std::to_string(i),
+                        u = "ur" + std::to_string(i);
+      o_ << "    Real D_[21];\n";
+      for (int d = 0; d < 6; ++d)
+        for (int r = 0; r < 6; ++r) {
+          o_ << "    " << ix(U, d * 6 + r) << " = ";
+          for (int c = 0; c < 6; ++c) o_ << (c ? " + " : "") << "IA_[" << si(r, c) << "] * " << ix(S, d * 6 + c);
+          o_ << ";\n";
+        }
+      for (int d = 0; d < 6; ++d) {
+        o_ << "    " << ix(u, d) << " = TAUv(" << vi + d << ") - (";
+        for (int k = 0; k < 6; ++k) o_ << (k ? " + " : "") << ix(S, d * 6 + k) << " * pA_[" << k << "]";
+        o_ << ");\n";
+      }
+      for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c) {
+          o_ << "    D_[" << si(r, c) << "] = ";
+          for (int k = 0; k < 6; ++k) o_ << (k ? " + " : "") << ix(S, r * 6 + k) << " * " << ix(U, c * 6 + k);
+          o_ << ";\n";
+        }
+      // D = L L^T
+      for (int jj = 0; jj < 6; ++jj) {
+        o_ << "    {\n      Real d_ = D_[" << si(jj, jj) << "];\n";
+        for (int k = 0; k < jj; ++k) o_ << "      d_ -= " << ix(L, si(jj, k)) << " * " << ix(L, si(jj, k)) << ";\n";
+        o_ << "      " << ix(L, si(jj, jj)) << " = sqrt(d_);\n      const Real il_ = Real(1) / " << ix(L, si(jj, jj))
+           << ";\n";
+        for (int r = jj + 1; r < 6; ++r) {
+          o_ << "      " << ix(L, si(r, jj)) << " = (D_[" << si(r, jj) << "]";
+          for (int k = 0; k < jj; ++k) o_ << " - " << ix(L, si(r, k)) << " * " << ix(L, si(jj, k));
+          o_ << ") * il_;\n";
+        }
+        o_ << "    }\n";
+      }
+      if (m_->parent[i] >= 0) o_ << "    // (not reached: a free joint is always a root)\n";
+      o_ << "  }\n  }\n";
+      return;
+    }
+    const std::string s = v("s", i), cJ = v("cJ", i), sl = std::to_string(slot_[i]);
+    o_ << "    Real U_[6];\n";
+    for (int r = 0; r < 6; ++r) {
+      o_ << "    U_[" << r << "] = ";
+      for (int c = 0; c < 6; ++c) o_ << (c ? " + " : "") << "IA_[" << si(r, c) << "] * " << ix(s, c);
+      o_ << ";\n";
+    }
+    o_
+       << "    const Real D_ = " << s << "[0] * U_[0] + " << s << "[1] * U_[1] + " << s << "[2] * U_[2] + " << s
+       << "[3] * U_[3] + " << s << "[4] * U_[4] + " << s << "[5] * U_[5];\n"
+       << "    const Real Di_ = Real(1) / D_;\n"
+       << "    const Real u_ = TAUv(" << vi << ") - (" << s << "[0] * pA_[0] + " << s << "[1] * pA_[1] + " << s
+       << "[2] * pA_[2] + " << s << "[3] * pA_[3] + " << s << "[4] * pA_[4] + " << s << "[5] * pA_[5]);\n"
+       << "    for (int k = 0; k < 6; ++k) WL(" << sl << ", k) = U_[k] * Di_;\n"
+       << "    WL(" << sl << ", 6) = (u_ - (U_[0] * " << cJ << "[0] + U_[1] * " << cJ << "[1] + U_[2] * " << cJ
+       << "[2] + U_[3] * " << cJ << "[3] + U_[4] * " << cJ << "[4] + U_[5] * " << cJ << "[5])) * Di_;\n";
+    if (m_->parent[i] >= 0) {
+      const bool lds = to_slot(i);
+      const std::string Ia = lds ? std::string("Ia_") : v("Ia", i), pa = lds ? std::string("pa_") : v("pa", i);
+      if (lds) o_ << "    Real Ia_[21], pa_[6];\n";
+      for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c)
+          o_ << "    " << ix(Ia, si(r, c)) << " = IA_[" << si(r, c) << "] - U_[" << r << "] * U_[" << c << "] * Di_;\n";
+      o_ << "    const Real uD_ = u_ * Di_;\n";
+      for (int r = 0; r < 6; ++r) {
+        o_ << "    " << ix(pa, r) << " = pA_[" << r << "] + U_[" << r << "] * uD_";
+        for (int c = 0; c < 6; ++c) o_ << " + " << ix(Ia, si(r, c)) << " * " << ix(cJ, c);
+        o_ << ";\n";
+      }
+      if (lds) {
+        int l = -1;
+        for (size_t k = 0; k < pl_.limbs.size(); ++k)
+          if (pl_.limbs[k][0] == i) l = (int)k;
+        const int sl = pl_.limb_slot[l];
+        const char* op = pl_.limb_first[l] ? " = " : " += ";
+        o_ << "    for (int k = 0; k < 21; ++k) xa_[(" << sl * 27 << " + k) * 64 + lane]" << op << "Ia_[k];\n"
+           << "    for (int k = 0; k < 6; ++k) xa_[(" << sl * 27 + 21 << " + k) * 64 + lane]" << op << "pa_[k];\n";
+      }
+    }
+    o_ << "  }\n  }\n";
+  }
+
+  void walk3(int i) {
+    const int p = m_->parent[i], t = m_->jtype[i], vi = m_->vi[i];
+    o_ << "  {\n";
+    kin_vel(i);
+    o_ << "  Real " << v("A", i) << "[6];\n  {\n";
+    const std::string ap = p >= 0 ? v("A", p) : std::string("a0_");
+    if (t == J_FREE) {
+      const std::string S = v("S", i), U = "Ur" + std::to_string(i), L = "Lr" + std::to_string(i),
+                        u = "ur" + std::to_string(i);
+      o_ << "    Real x_[6];\n";
+      for (int d = 0; d < 6; ++d) {
+        o_ << "    x_[" << d << "] = " << ix(u, d);
+        for (int k = 0; k < 6; ++k) o_ << " - " << ix(U, d * 6 + k) << " * " << ap << "[" << k << "]";
+        o_ << ";\n";
+      }
+      for (int r = 0; r < 6; ++r) {  // L y = x
+        o_ << "    x_[" << r << "] = (x_[" << r << "]";
+        for (int k = 0; k < r; ++k) o_ << " - " << ix(L, si(r, k)) << " * x_[" << k << "]";
+        o_ << ") / " << ix(L, si(r, r)) << ";\n";
+      }
+      for (int r = 5; r >= 0; --r) {  // L^T z = y
+        o_ << "    x_[" << r << "] = (x_[" << r << "]";
+        for (int k = r + 1; k < 6; ++k) o_ << " - " << ix(L, si(k, r)) << " * x_[" << k << "]";
+        o_ << ") / " << ix(L, si(r, r)) << ";\n";
+      }
+      for (int k = 0; k < 6; ++k) {
+        o_ << "    " << v("A", i) << "[" << k << "] = " << ap << "[" << k << "] + " << v("cJ", i) << "[" << k << "]";
+        for (int d = 0; d < 6; ++d) o_ << " + " << ix(S, d * 6 + k) << " * x_[" << d << "]";
+        o_ << ";\n";
+      }
+      for (int d = 0; d < 6; ++d) o_ << "    QDDO(" << vi + d << ", x_[" << d << "]);\n";
+    } else {
+      const std::string s = v("s", i), sl = std::to_string(slot_[i]);
+      o_ << "    Real qdd_ = WL(" << sl << ", 6);\n"
+         << "    for (int k = 0; k < 6; ++k) qdd_ -= WL(" << sl << ", k) * " << ap << "[k];\n"
+         << "    for (int k = 0; k < 6; ++k) " << v("A", i) << "[k] = " << ap << "[k] + " << v("cJ", i) << "[k] + " << s
+         << "[k] * qdd_;\n    QDDO(" << vi << ", qdd_);\n";
+    }
+    if (mode_ == TRUNK && at_slot_[i] >= 0)
+      o_ << "  for (int k = 0; k < 6; ++k) at_[(" << at_slot_[i] * 6 << " + k) * 64 + lane] = " << v("A", i) << "[k];\n";
+    o_ << "  }\n";
+    for (int ch : m_->children[i])
+      if (!(mode_ == TRUNK && !trunk_[ch])) walk3(ch);
+    o_ << "  }\n";
+  }
+
+  // The split form: phase A (every wave: the trunk's kinematics, its limbs'
+  // passes 1 and 2, each limb's articulated inertia and bias force moved into
+  // LDS), phase B (the merging wave: the trunk's passes 2 and 3, the
+  // accelerations of the trunk bodies with limbs attached into LDS), phase C
+  // (every wave: the kinematics again and its limbs' pass 3).  A tree without
+  // a trunk runs A and C back to back in each wave, with no barrier.
+  std::string source_split() {
+    const int n = m_->n, nw = pl_.waves;
+    header();
+    o_ << "static constexpr int NW = " << nw << ";  // waves per workgroup, 64 instances\n";
+    o_ << "extern \"C\" __global__ void __launch_bounds__(" << 64 * nw << ") bard_spec_aba(\n";
+    params();
+    o_ << "  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);\n"
+          "  const int lane = (int)threadIdx.x & 63;\n"
+          "  long long b = (long long)blockIdx.x * 64 + lane;\n"
+          "  if (b > B - 1) b = B - 1;  // every lane reaches the barriers\n";
+    offsets();
+    slot_.assign(n, -1);
+    at_slot_.assign(n, -1);
+    int ns = 0, nat = 0;
+    bool any_trunk = false;
+    for (int i = 0; i < n; ++i) {
+      if (m_->jtype[i] != J_FREE) slot_[i] = ns++;
+      any_trunk = any_trunk || trunk_[i];
+    }
+    for (const auto& limb : pl_.limbs) {
+      const int at = m_->parent[limb[0]];
+      if (at >= 0 && at_slot_[at] < 0) at_slot_[at] = nat++;
+    }
+    if (ns) o_ << "  __shared__ Real wl_[" << ns * 7 * 64 << "];\n";
+    if (!pl_.slot_body.empty()) o_ << "  __shared__ Real xa_[" << pl_.slot_body.size() * 27 * 64 << "];\n";
+    if (nat) o_ << "  __shared__ Real at_[" << nat * 6 * 64 << "];\n";
+    std::vector<int> tb;
+    for (int i = 0; i < n; ++i)
+      if (trunk_[i]) tb.push_back(i);
+    auto free_roots = [&](const std::vector<int>& bodies) {
+      for (int i : bodies)
+        if (m_->jtype[i] == J_FREE) o_ << "  Real Ur" << i << "[36], Lr" << i << "[21], ur" << i << "[6];\n";
+    };
+    const int merge = nw - 1;
+    for (int w = 0; w < nw; ++w) {
+      o_ << (w ? "  else if" : "  if") << " (wave == " << w << ") {\n";
+      mode_ = LIMB;
+      for (int i : tb) kin_vel(i);
+      std::vector<int> roots;
+      for (int l : pl_.bins[w]) roots.push_back(pl_.limbs[l][0]);
+      if (!any_trunk) free_roots(roots);
+      for (int r : roots) walk12(r);
+      if (!any_trunk)
+        for (int r : roots) walk3(r);
+      o_ << "  }\n";
+    }
+    if (any_trunk) {
+      o_ << "  __syncthreads();\n  if (wave == " << merge << ") {\n";
+      mode_ = TRUNK;
+      free_roots(tb);
+      for (int i : tb)
+        if (m_->parent[i] < 0) walk12(i);
+      for (int i : tb)
+        if (m_->parent[i] < 0) walk3(i);
+      o_ << "  }\n  __syncthreads();\n";
+      for (int w = 0; w < nw; ++w) {
+        o_ << (w ? "  else if" : "  if") << " (wave == " << w << ") {\n";
+        mode_ = LIMB;
+        for (int i : tb) kin_vel(i);
+        std::vector<int> ats;
+        for (int l : pl_.bins[w]) {
+          const int at = m_->parent[pl_.limbs[l][0]];
+          if (at >= 0 && std::find(ats.begin(), ats.end(), at) == ats.end()) ats.push_back(at);
+        }
+        for (int at : ats)
+          o_ << "  Real " << v("A", at) << "[6];\n  for (int k = 0; k < 6; ++k) " << v("A", at) << "[k] = at_[("
+             << at_slot_[at] * 6 << " + k) * 64 + lane];\n";
+        for (int l : pl_.bins[w]) walk3(pl_.limbs[l][0]);
+        o_ << "  }\n";
+      }
+    }
+    o_ << "}\n";
+    mode_ = WHOLE;
+    return o_.str();
+  }
+};
 }  // namespace
 
 int spec_tier(int64_t B) {
@@ -816,6 +1257,12 @@ std::string spec_key(int dtype, int frame, const std::vector<int>& ee, int form)
 std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form) {
   return Emitter(m, ee, frame, fp64, form).source();
 }
+
+std::string spec_aba_source(const bard_model* m, bool fp64, bool split) {
+  return AbaEmitter(m, fp64, split).source();
+}
+
+int spec_aba_waves(const bard_model* m, bool fp64, bool split) { return AbaEmitter(m, fp64, split).waves(); }
 
 int spec_waves(const bard_model* m, bool fp64, int form) { return make_plan(m, form == 1, fp64).waves; }
 
@@ -880,9 +1327,14 @@ int spec_compile(const std::string& src, std::vector<char>* code, std::string* l
 }
 
 // Compiles (once per key) and loads on the current device.
-int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, int form,
-                 bool load, SpecKernel** out) {
-  const std::string key = spec_key(dtype, frame, ee, form);
+namespace {
+
+// Compiles (once per key) and, if `load`, loads on the current device the
+// kernel `fname` of the source `gen` writes; `init` fills the kernel's launch
+// facts at compile time.
+template <class Gen, class Init>
+int prepare_kernel(bard_model* m, DeviceCopy* dc, const std::string& key, Gen gen, const char* fname, Init init,
+                   bool load, SpecKernel** out) {
   std::lock_guard<std::mutex> lk(m->mu);
   auto it = dc->spec.find(key);
   if (it != dc->spec.end() && (it->second.fn || !load)) {
@@ -894,10 +1346,8 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
   if (sk.code.empty()) {
     const auto t0 = std::chrono::steady_clock::now();
     std::string log;
-    sk.form = form;
-    const int rc = spec_compile(spec_chain_source(m, ee, frame, dtype == BARD_F64, form), &sk.code, &log);
-    sk.zero_rows = spec_zero_rows(m, ee);
-    sk.waves = spec_waves(m, dtype == BARD_F64, form);
+    init(&sk);
+    const int rc = spec_compile(gen(), &sk.code, &log);
     sk.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000));
   }
@@ -908,7 +1358,7 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
       (void)hipGetLastError();
       return fail(BARD_E_DEVICE, "hipModuleLoadData of the specialised kernel failed");
     }
-    if (hipModuleGetFunction(&fn, mod, "bard_spec_chain") != hipSuccess) {
+    if (hipModuleGetFunction(&fn, mod, fname) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipModuleUnload(mod);
       return fail(BARD_E_DEVICE, "specialised kernel not found in its module");
@@ -935,6 +1385,41 @@ int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std:
   dc->spec[key] = sk;
   *out = &dc->spec[key];
   return BARD_OK;
+}
+
+}  // namespace
+
+int spec_prepare(bard_model* m, DeviceCopy* dc, int dtype, int frame, const std::vector<int>& ee, int form,
+                 bool load, SpecKernel** out) {
+  return prepare_kernel(
+      m, dc, spec_key(dtype, frame, ee, form), [&] { return spec_chain_source(m, ee, frame, dtype == BARD_F64, form); },
+      "bard_spec_chain",
+      [&](SpecKernel* sk) {
+        sk->form = form;
+        sk->zero_rows = spec_zero_rows(m, ee);
+        sk->waves = spec_waves(m, dtype == BARD_F64, form);
+      },
+      load, out);
+}
+
+std::string spec_aba_key(int dtype) { return "aba:" + std::to_string(dtype); }
+
+int spec_prepare_aba(bard_model* m, DeviceCopy* dc, int dtype, bool load, SpecKernel** out) {
+  return prepare_kernel(
+      m, dc, spec_aba_key(dtype), [&] { return spec_aba_source(m, dtype == BARD_F64, true); }, "bard_spec_aba",
+      [&](SpecKernel* sk) {
+        sk->waves = spec_aba_waves(m, dtype == BARD_F64, true);
+        sk->form = sk->waves > 1 ? 0 : 1;
+      },
+      load, out);
+}
+
+SpecKernel* spec_lookup_aba(bard_model* m, DeviceCopy* dc, int dtype, int64_t B) {
+  if (!m->spec_route.load()) return nullptr;
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = dc->spec.find(spec_aba_key(dtype));
+  if (it == dc->spec.end() || !it->second.fn || !(it->second.route_tiers & (1 << spec_tier(B)))) return nullptr;
+  return &it->second;
 }
 
 SpecKernel* spec_lookup(bard_model* m, DeviceCopy* dc, int dtype, int frame, int n_ee, const int32_t* ee,
@@ -986,6 +1471,39 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   }
   return BARD_OK;
 }
+
+template <class Real>
+bool spec_aba_fits(const Args<Real>& a) {
+  const int64_t last = a.B > 0 ? a.B - 1 : 0;
+  const int64_t lim = (int64_t)(0xffffffffu / sizeof(Real));
+  const int64_t s[4] = {a.sq_b, a.sqd_b, a.sti_b, a.sqo_b};
+  for (int64_t x : s)
+    if (x < 0 || last * x > lim) return false;
+  return true;
+}
+
+template <class Real>
+int spec_aba_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hipStream_t st) {
+  long long sq_b = a.sq_b, sq_k = a.sq_k, sqd_b = a.sqd_b, sqd_k = a.sqd_k, st_b = a.sti_b, st_k = a.sti_k;
+  long long so_b = a.sqo_b, so_k = a.sqo_k, B = a.B;
+  Real g0 = (Real)g[0], g1 = (Real)g[1], g2 = (Real)g[2];
+  const Real *q = a.q, *qd = a.qd, *tau = a.tau_in;
+  Real* qdd = a.qdd_out;
+  void* args[] = {&q, &qd, &tau, &qdd, &sq_b, &sq_k, &sqd_b, &sqd_k, &st_b, &st_k, &so_b, &so_k, &B, &g0, &g1, &g2};
+  const int64_t grid = (a.B + 63) / 64;
+  if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
+  if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64 * sk->waves, 1, 1, 0, st, args,
+                            nullptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BARD_E_DEVICE, "launch of the specialised kernel failed");
+  }
+  return BARD_OK;
+}
+
+template bool spec_aba_fits<float>(const Args<float>&);
+template bool spec_aba_fits<double>(const Args<double>&);
+template int spec_aba_launch<float>(const SpecKernel*, const Args<float>&, const double*, hipStream_t);
+template int spec_aba_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
 
 template <class Real>
 bool spec_fits(const Args<Real>& a, int nv, int n_ee) {

@@ -74,3 +74,30 @@ def test_split_form_waves(name, waves):
     dual = m.specialized_source(tree.ee_bodies, form="dual")
     assert int(re.search(r"NW = (\d+);", dual).group(1)) == waves
     assert int(re.search(r"WG_PER_GROUP = (\d+);", dual).group(1)) == 2
+
+
+@pytest.mark.parametrize("name,dtype,waves,compile_", [("humanoid_large", "float32", 5, True),
+                                                       ("humanoid_large", "float64", 1, False),
+                                                       ("chain7", "float32", 1, True), ("free1", "float64", 1, True),
+                                                       ("quadruped_spine", "float32", 4, True),
+                                                       ("star64", "float32", 1, False)])
+def test_generated_aba_source(name, dtype, waves, compile_):
+    """The forward-dynamics kernel's source stores every acceleration once,
+    splits over waves by limbs where its LDS hand-over fits (the FP64
+    humanoid and the 64-body star keep one wave), and compiles for gfx950."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    src = m.specialized_aba_source(dtype=dtype)
+    stored = sorted(int(k) for k in re.findall(r"QDDO\((\d+), ", src))
+    assert stored == list(range(tree.nv))
+    assert int(re.search(r"NW = (\d+);", src).group(1)) == waves
+    assert src.count("__syncthreads") == (2 if waves > 1 and name != "chain7" else 0)
+    if compile_:  # (the one-wave forms of the large trees take minutes on the host; the GPU tests load them)
+        m.specialize_aba(dtype=dtype, compile_only=True)
+
+
+def test_deep_tree_refused_for_aba():
+    m = bard.Model.from_tree(synth.tree_by_name("chain64"))
+    with pytest.raises(bard.BardError) as ei:
+        m.specialize_aba(compile_only=True)
+    assert ei.value.status == -7
