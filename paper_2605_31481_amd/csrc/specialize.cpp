@@ -898,7 +898,12 @@ class AbaEmitter : public Emitter {
     for (int i = 0; i < n; ++i)
       if (m_->jtype[i] == J_FREE) o_ << "  Real Ur" << i << "[36], Lr" << i << "[21], ur" << i << "[6];\n";
       else slot_[i] = ns++;
-    if (ns) o_ << "  __shared__ Real wl_[" << ns * 7 * 64 << "];\n";
+    // W and e in LDS while it fits, else in registers (they then spill)
+    we_lds_ = (size_t)ns * 7 * 64 * (fp64_ ? 8 : 4) <= 150 * 1024;
+    if (ns && we_lds_) o_ << "  __shared__ Real wl_[" << ns * 7 * 64 << "];\n";
+    if (!we_lds_)
+      for (int i = 0; i < n; ++i)
+        if (slot_[i] >= 0) o_ << "  Real W" << i << "[6], e" << i << ";\n";
     o_ << "  // passes 1 and 2\n";
     for (int i = 0; i < n; ++i)
       if (m_->parent[i] < 0) walk12(i);
@@ -918,6 +923,7 @@ class AbaEmitter : public Emitter {
   static std::string ix(const std::string& a, int k) { return a + "[" + std::to_string(k) + "]"; }
 
   std::vector<int> slot_;  // LDS slot of each body's W and e
+  bool we_lds_ = true;     // W and e in LDS (else in registers, whole form only)
   bool aba_split_ = false;
   enum Mode { WHOLE, LIMB, TRUNK };
   Mode mode_ = WHOLE;
@@ -1083,9 +1089,13 @@ class AbaEmitter : public Emitter {
        << "    const Real Di_ = Real(1) / D_;\n"
        << "    const Real u_ = TAUv(" << vi << ") - (" << s << "[0] * pA_[0] + " << s << "[1] * pA_[1] + " << s
        << "[2] * pA_[2] + " << s << "[3] * pA_[3] + " << s << "[4] * pA_[4] + " << s << "[5] * pA_[5]);\n"
-       << "    for (int k = 0; k < 6; ++k) WL(" << sl << ", k) = U_[k] * Di_;\n"
-       << "    WL(" << sl << ", 6) = (u_ - (U_[0] * " << cJ << "[0] + U_[1] * " << cJ << "[1] + U_[2] * " << cJ
-       << "[2] + U_[3] * " << cJ << "[3] + U_[4] * " << cJ << "[4] + U_[5] * " << cJ << "[5])) * Di_;\n";
+       ;
+    const std::string Wk = we_lds_ ? "WL(" + sl + ", " : "W" + std::to_string(i) + "[";
+    const std::string Wc = we_lds_ ? ")" : "]";
+    for (int k = 0; k < 6; ++k) o_ << "    " << Wk << k << Wc << " = U_[" << k << "] * Di_;\n";
+    o_ << "    " << (we_lds_ ? "WL(" + sl + ", 6)" : "e" + std::to_string(i)) << " = (u_ - (U_[0] * " << cJ
+       << "[0] + U_[1] * " << cJ << "[1] + U_[2] * " << cJ << "[2] + U_[3] * " << cJ << "[3] + U_[4] * " << cJ
+       << "[4] + U_[5] * " << cJ << "[5])) * Di_;\n";
     if (m_->parent[i] >= 0) {
       const bool lds = to_slot(i);
       const std::string Ia = lds ? std::string("Ia_") : v("Ia", i), pa = lds ? std::string("pa_") : v("pa", i);
@@ -1145,8 +1155,11 @@ class AbaEmitter : public Emitter {
       for (int d = 0; d < 6; ++d) o_ << "    QDDO(" << vi + d << ", x_[" << d << "]);\n";
     } else {
       const std::string s = v("s", i), sl = std::to_string(slot_[i]);
-      o_ << "    Real qdd_ = WL(" << sl << ", 6);\n"
-         << "    for (int k = 0; k < 6; ++k) qdd_ -= WL(" << sl << ", k) * " << ap << "[k];\n"
+      const std::string Wk = we_lds_ ? "WL(" + sl + ", " : "W" + std::to_string(i) + "[";
+      const std::string Wc = we_lds_ ? ")" : "]";
+      o_ << "    Real qdd_ = " << (we_lds_ ? "WL(" + sl + ", 6)" : "e" + std::to_string(i)) << ";\n";
+      for (int k = 0; k < 6; ++k) o_ << "    qdd_ -= " << Wk << k << Wc << " * " << ap << "[" << k << "];\n";
+      o_
          << "    for (int k = 0; k < 6; ++k) " << v("A", i) << "[k] = " << ap << "[k] + " << v("cJ", i) << "[k] + " << s
          << "[k] * qdd_;\n    QDDO(" << vi << ", qdd_);\n";
     }

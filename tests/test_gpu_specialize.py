@@ -213,3 +213,23 @@ def test_large_joint_angles(dtype):
         q, qd, qdd = (synth.to_fp32_grid(x) for x in (q, qd, qdd))
     out = m.chain(*(to_dev(x, dtype) for x in (q, qd, qdd)), ee)
     assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in out), dtype, label="large angles")
+
+
+@pytest.mark.parametrize("name", ["star64", "free_branches61"])
+def test_fp64_trees_past_the_generic_capacity(name):
+    """The generic FP64 chain kernel refuses trees of 60 or more bodies
+    (BARD_E_CAPACITY: its per-tile LDS); a routed specialised kernel keeps no
+    per-tree state in LDS beyond the limb hand-over and serves them."""
+    say(f"[gpu] specialised FP64 chain on {name}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    B = 130
+    q, qd, qdd = inputs(tree, B, 5900, "float64")
+    d = [to_dev(x, "float64") for x in (q, qd, qdd)]
+    with pytest.raises(bard.BardError) as ei:
+        m.chain(*d, ee)
+    assert ei.value.status == -6  # BARD_E_CAPACITY
+    m.specialize(ee, dtype="float64")
+    out = m.chain(*d, ee)
+    assert_chain(oracle_for(tree), tree, q, qd, qdd, ee, *(from_dev(x) for x in out), "float64", label=name)

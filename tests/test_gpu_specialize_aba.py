@@ -114,3 +114,25 @@ def test_autotune_and_deep_tree_refused():
     with pytest.raises(bard.BardError) as ei:
         deep.specialize_aba()
     assert ei.value.status == -7
+
+
+@pytest.mark.parametrize("name", ["star64", "free_branches61"])
+def test_fp64_trees_past_the_generic_capacity(name):
+    """The generic FP64 forward-dynamics kernel refuses trees of 60 or more
+    bodies (BARD_E_CAPACITY); the routed specialised kernel serves them."""
+    say(f"[gpu] specialised FP64 aba on {name}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    om = oracle_for(tree)
+    B = 130
+    q, qd, qdd = inputs(tree, B, 6600, "float64")
+    tau = om.rnea(q, qd, qdd)
+    d = [to_dev(x, "float64") for x in (q, qd, tau)]
+    with pytest.raises(bard.BardError) as ei:
+        m.aba(*d)
+    assert ei.value.status == -6  # BARD_E_CAPACITY
+    m.specialize_aba(dtype="float64")
+    out = from_dev(m.aba(*d))
+    ok, worst = aba_backward_error(om, q, qd, tau, out, "float64")
+    assert ok.all(), worst
+    np.testing.assert_allclose(out, om.aba(q, qd, tau), rtol=1e-8, atol=1e-8 * np.abs(out).max())

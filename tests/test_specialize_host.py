@@ -76,15 +76,19 @@ def test_split_form_waves(name, waves):
     assert int(re.search(r"WG_PER_GROUP = (\d+);", dual).group(1)) == 2
 
 
-@pytest.mark.parametrize("name,dtype,waves,compile_", [("humanoid_large", "float32", 5, True),
-                                                       ("humanoid_large", "float64", 1, False),
-                                                       ("chain7", "float32", 1, True), ("free1", "float64", 1, True),
-                                                       ("quadruped_spine", "float32", 4, True),
-                                                       ("star64", "float32", 1, False)])
-def test_generated_aba_source(name, dtype, waves, compile_):
+@pytest.mark.parametrize("name,dtype,waves,lds,compile_", [("humanoid_large", "float32", 5, True, True),
+                                                           ("humanoid_large", "float64", 1, True, False),
+                                                           ("chain7", "float32", 1, True, True),
+                                                           ("free1", "float64", 1, False, True),
+                                                           ("quadruped_spine", "float32", 4, True, True),
+                                                           ("star64", "float32", 1, True, False),
+                                                           ("star64", "float64", 1, False, False)])
+def test_generated_aba_source(name, dtype, waves, lds, compile_):
     """The forward-dynamics kernel's source stores every acceleration once,
     splits over waves by limbs where its LDS hand-over fits (the FP64
-    humanoid and the 64-body star keep one wave), and compiles for gfx950."""
+    humanoid and the 64-body star keep one wave), keeps the one-wave form's
+    per-body W and e in LDS while they fit in 150 KB (in registers for the
+    FP64 64-body star, whose copy would take 224 KB), and compiles for gfx950."""
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
     src = m.specialized_aba_source(dtype=dtype)
@@ -92,6 +96,7 @@ def test_generated_aba_source(name, dtype, waves, compile_):
     assert stored == list(range(tree.nv))
     assert int(re.search(r"NW = (\d+);", src).group(1)) == waves
     assert src.count("__syncthreads") == (2 if waves > 1 and name != "chain7" else 0)
+    assert ("__shared__" in src) == lds
     if compile_:  # (the one-wave forms of the large trees take minutes on the host; the GPU tests load them)
         m.specialize_aba(dtype=dtype, compile_only=True)
 
