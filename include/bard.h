@@ -296,6 +296,22 @@ int bard_jacobian(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void
                   const int32_t* ee_body, bard_frame frame, void* J, const bard_layout* L,
                   uint64_t q_tag, int64_t B, void* stream);
 
+/* Standalone FK and Jacobian of one kinematic chain (Sec. 3.1: path-only
+ * functions for a root-to-end-effector chain).  Visits only the bodies on the
+ * path from ee_body's root to ee_body, uses no workspace and caches nothing;
+ * each lane of the launch walks one instance's path.  pose and J hold the
+ * same values (up to rounding) as the ee_body block of bard_fk's poses and
+ * of bard_jacobian's J for the one end effector ee_body.
+ * Arrays (L order, three entries): q [nq] in; pose [12] out, the 3x4
+ * [R | p] of ee_body (NULL: not computed); J [6*nv] out, the eq. (7)
+ * columns of the dofs on the path and zeros elsewhere (NULL: not computed).
+ * At least one of pose and J is given.
+ * Errors: BARD_E_ARG (NULL model or q, no output, ee_body outside
+ * 0..n_bodies-1, bad frame or stride), BARD_E_CAPTURE (first use of the model
+ * on a device while capturing), BARD_E_DEVICE. */
+int bard_path_kinematics(bard_model_t model, bard_dtype dtype, const void* q, int32_t ee_body, bard_frame frame,
+                         void* pose, void* J, const bard_layout* L, int64_t B, void* stream);
+
 /* Inverse dynamics tau = M(q) qdd + C(q, qd) qd + g(q) (RNEA, Sec. 3.3).
  * inertia_override: NULL or a DEVICE array [n_bodies][10] (same dtype, shared by
  * all instances) replacing the model's inertial parameters.

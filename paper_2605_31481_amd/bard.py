@@ -112,6 +112,8 @@ bard_ws_stats = _sig("bard_ws_stats", [_vp, ctypes.POINTER(_u64), ctypes.POINTER
 bard_fk = _sig("bard_fk", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
 bard_jacobian = _sig("bard_jacobian", [_vp, _vp, ctypes.c_int, _vp, _i32, _c_i32p, ctypes.c_int, _vp, _LP, _u64,
                                        _i64, _vp])
+bard_path_kinematics = _sig("bard_path_kinematics", [_vp, ctypes.c_int, _vp, _i32, ctypes.c_int, _vp, _vp, _LP,
+                                                     _i64, _vp])
 bard_rnea = _sig("bard_rnea", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _LP, _u64, _u64, _i64, _vp])
 bard_crba = _sig("bard_crba", [_vp, _vp, ctypes.c_int, _vp, _vp, _LP, _u64, _i64, _vp])
 bard_aba = _sig("bard_aba", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _LP, _u64, _u64, _i64, _vp])
@@ -243,7 +245,9 @@ def _check_inertia(q, inertia, n_bodies: int, name: str = "inertia"):
 def _layouts(tensors, layout: str):
     arr = (Layout * len(tensors))()
     for i, t in enumerate(tensors):
-        if layout == "soa":
+        if t is None:  # an absent optional array (its pointer is NULL)
+            arr[i].stride_b = arr[i].stride_k = 1
+        elif layout == "soa":
             arr[i].stride_k, arr[i].stride_b = t.stride(0), t.stride(1)
         else:
             arr[i].stride_b, arr[i].stride_k = t.stride(0), t.stride(1)
@@ -572,6 +576,22 @@ class Model:
         if key is not None:
             ws._remember("jacobian", key, (out,))
         return out
+
+    def path_kinematics(self, q, ee: int, frame: int = WORLD, pose: bool = True, jacobian: bool = True,
+                        out_pose=None, out_J=None, layout: str = "soa"):
+        """Pose [12] and Jacobian [6*nv] of one end effector from a walk of
+        its root-to-body path only (bard_path_kinematics).  Returns
+        (pose, J), None for an output not asked for."""
+        B = _batch_of(q, self.nq, layout)
+        if not (pose or jacobian):
+            raise ValueError("path_kinematics needs pose or jacobian")
+        po = (out_pose if out_pose is not None else _new(q, 12, B, layout)) if pose else None
+        J = (out_J if out_J is not None else _new(q, 6 * self.nv, B, layout)) if jacobian else None
+        _check_arrays(q, [(po, 12, "out_pose"), (J, 6 * self.nv, "out_J")], B, layout)
+        L = _layouts([q, po, J], layout)
+        _check(bard_path_kinematics(self._h, _dtype_code(q), _ptr(q), int(ee), int(frame), _ptr(po), _ptr(J), L, B,
+                                    _stream_ptr(q)), "bard_path_kinematics")
+        return po, J
 
     def rnea(self, q, qd, qdd, inertia=None, out=None, layout: str = "soa", ws: Optional[Workspace] = None,
              q_tag=None, qd_tag=None):

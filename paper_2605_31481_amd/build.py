@@ -11,7 +11,7 @@ _SRC = os.path.join(_HERE, "csrc")
 _OUT = os.path.join(_HERE, "libbard.so")
 _BUILD = os.path.join(os.path.dirname(_HERE), "_build", "bard")
 
-SOURCES = ["kernels.hip", "adjoint.hip", "tiers.hip", "api.cpp", "compiler.cpp", "plan.cpp", "specialize.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "tiers.hip", "path.hip", "api.cpp", "compiler.cpp", "plan.cpp", "specialize.cpp"]
 _GEN = os.path.join(_BUILD, "gen")
 
 # Packed FP32 instructions are turned off for every HIP translation unit.

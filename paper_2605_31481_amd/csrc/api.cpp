@@ -1099,6 +1099,54 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
+int bard_path_kinematics(bard_model_t m, bard_dtype dtype, const void* q, int32_t ee_body, bard_frame frame,
+                          void* pose, void* J, const bard_layout* L, int64_t B, void* stream) {
+  int rc = common_checks(m, nullptr, dtype, B);
+  if (rc) return rc;
+  if (frame != BARD_WORLD && frame != BARD_LOCAL_WORLD_ALIGNED) return fail(BARD_E_ARG, "bad frame");
+  if (ee_body < 0 || ee_body >= m->n) return fail(BARD_E_ARG, "ee_body out of range");
+  if (B == 0) return BARD_OK;
+  if (!q || (!pose && !J)) return fail(BARD_E_ARG, "NULL q, or neither pose nor J given");
+  if ((rc = check_device_state())) return rc;
+  auto go = [&](auto zero) -> int {
+    using R = decltype(zero);
+    PathArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.B = B;
+    a.q = (const R*)q;
+    a.pose = (R*)pose;
+    a.J = (R*)J;
+    if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 12, &a.sp_b, &a.sp_k) ||
+        !layout_of(L, 2, B, 6 * m->nv, &a.sJ_b, &a.sJ_k))
+      return fail(BARD_E_ARG, "bad layout stride");
+    std::vector<int> path;
+    for (int j = ee_body; j >= 0; j = m->parent[j]) path.push_back(j);
+    std::reverse(path.begin(), path.end());
+    a.len = (int)path.size();
+    for (int s = 0; s < a.len; ++s) {
+      const int j = path[s];
+      a.body[s] = (int8_t)j;
+      a.vcol[s] = (uint8_t)m->vi[j];
+      for (int k = 0; k < (m->jtype[j] == J_FREE ? 7 : 1); ++k) a.qsrc[a.nqp++] = (uint8_t)(m->qi[j] + k);
+    }
+    if (J) {
+      std::vector<char> on(m->nv, 0);
+      for (int j : path)
+        for (int d = 0; d < m->nvi[j]; ++d) on[m->vi[j] + d] = 1;
+      for (int c = 0; c < m->nv; ++c)
+        if (!on[c]) a.zcol[a.n_zero++] = (uint8_t)c;
+      a.zero_groups = (a.n_zero + 3) / 4;
+    }
+    DeviceCopy* dc = nullptr;
+    int rc2 = ensure_device(m, &dc, (hipStream_t)stream);
+    if (rc2) return rc2;
+    hipError_t e = launch_path<R>(dc->dm, a, frame == BARD_LOCAL_WORLD_ALIGNED, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return BARD_OK;
+  };
+  return dtype == BARD_F32 ? go(0.0f) : go(0.0);
+}
+
 int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, const void* qd, const void* qdd,
               const void* inertia_override, void* tau, const bard_layout* L, uint64_t q_tag, uint64_t qd_tag,
               int64_t B, void* stream) {

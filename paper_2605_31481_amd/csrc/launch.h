@@ -87,6 +87,29 @@ hipError_t launch_plan(const PlanPtrs<Real>& pp, int logT, int grid, int block, 
 template <class Real>
 hipError_t launch_aba(const DevModel& dm, const Args<Real>& ar, int grid, int block, size_t lds, hipStream_t st);
 
+// Standalone kinematics of one chain (path.hip): the bodies on the path from
+// the root to one end effector, root first, and the Jacobian columns that
+// path leaves zero.  Passed by value (kernel arguments, no device tables of
+// its own).
+template <class Real>
+struct PathArgs {
+  const Real* q;
+  Real* pose;  // [12] or NULL
+  Real* J;     // [6*nv] or NULL
+  int64_t sq_b, sq_k, sp_b, sp_k, sJ_b, sJ_k;
+  int64_t B;
+  int len;           // bodies on the path
+  int nqp;           // position coordinates of the path's joints
+  int n_zero;        // columns off the path
+  int zero_groups;   // workgroup rows (gridDim.y - 1) that store those columns
+  int8_t body[64];   // the path, root first
+  uint8_t vcol[64];  // first velocity column of each path body
+  uint8_t qsrc[72];  // q index of each of the path's nqp coordinates, in path order
+  uint8_t zcol[128];  // the columns off the path
+};
+template <class Real>
+hipError_t launch_path(const DevModel& dm, const PathArgs<Real>& pa, bool lwa, hipStream_t st);
+
 __host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
 
 // Threads per workgroup the tree kernels are compiled for: 16 waves in FP32

@@ -1,0 +1,188 @@
+// Standalone kinematics of one chain: Sec. 3.1 provides FK and Jacobian
+// functions for a single root-to-end-effector chain that visit only that
+// path and fill no cache.  One lane per instance walks the path with the
+// joint transforms of eqs. (4)-(5) and writes the end effector's world pose
+// and the Jacobian columns of eq. (7) for the joints on the path; further
+// workgroup rows of the same launch store the zero columns of the joints off
+// the path, so the instance lanes write only what the path computes.
+//
+// Columns ([linear; angular], world axes): a revolute joint with world axis
+// w through the point p contributes [p x w; w] at the world origin
+// (BARD_WORLD) and [w x (p_e - p); w] at the end effector's origin p_e
+// (BARD_LOCAL_WORLD_ALIGNED); a prismatic joint [u; 0]; a free root its
+// body-frame translation axes [R e_k; 0] and rotation axes as revolute
+// columns.  The end-effector point form needs p_e before the first column,
+// so that frame walks the path twice (poses only, then columns); the
+// arithmetic of the walk is a few hundred operations per body against
+// 6 nv output values, so at large batches the kernel is bound by its stores
+// and at small ones by the latency of one memory round trip.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "launch.h"
+
+namespace bard {
+
+namespace {
+
+constexpr int kPathThreads = 64;  // one wave per workgroup: many workgroups at small batches
+constexpr int kZeroCols = 4;      // zero columns per workgroup row
+constexpr int kPathCst = 36;      // R0, A, B, t0, axis, d of a body (the first 36 constants)
+
+// World pose of a body from its parent's (Rw, pw), in place; c its
+// constants, qv its coordinates (7 for a free root).
+template <class Real>
+__device__ __forceinline__ void path_step(const Real* c, int jt, const Real* qv, Real* Rw, Real* pw) {
+  if (jt == J_FREE) {
+    const Real qf[7] = {qv[0], qv[64], qv[128], qv[192], qv[256], qv[320], qv[384]};
+    free_root_pose(c, qf, Rw, pw);
+    return;
+  }
+  Real Rpc[9], tpc[3], Rn[9];
+  joint_transform(c, qv[0], Rpc, tpc);
+  mul33(Rw, Rpc, Rn);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pw[i] += Rw[3 * i] * tpc[0] + Rw[3 * i + 1] * tpc[1] + Rw[3 * i + 2] * tpc[2];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rw[k] = Rn[k];
+}
+
+template <class Real>
+__device__ __forceinline__ void store_col(Real* Jb, int64_t sJ_k, int nv, int col, const Real* lin, const Real* ang) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Jb[(int64_t)(r * nv + col) * sJ_k] = lin[r];
+    Jb[(int64_t)((3 + r) * nv + col) * sJ_k] = ang[r];
+  }
+}
+
+// The linear part of a rotation column about the point p for the chosen frame.
+template <bool LWA, class Real>
+__device__ __forceinline__ void rot_lin(const Real* w, const Real* p, const Real* pe, Real* lin) {
+  if (LWA) {
+    const Real d[3] = {pe[0] - p[0], pe[1] - p[1], pe[2] - p[2]};
+    cross3(w, d, lin);
+  } else {
+    cross3(p, w, lin);
+  }
+}
+
+// Dynamic LDS: the path's constants (len x 36) and joint types, then each
+// lane's path coordinates (nqp x 64, lane-minor).  The constants are read at
+// wave-uniform addresses (broadcast); every load of the walk is issued before
+// the walk starts, so a workgroup waits for one memory round trip.
+template <class Real, bool LWA>
+__global__ void __launch_bounds__(kPathThreads) path_kernel(DevModel dm, PathArgs<Real> a) {
+  const int tid = threadIdx.x;
+  const int64_t b = (int64_t)blockIdx.x * kPathThreads + tid;
+  const bool live = b < a.B;
+  const int nv = dm.nv;
+  if (blockIdx.y > 0) {  // zero columns of the joints off the path
+    if (!live) return;
+    Real* Jb = a.J + b * a.sJ_b;
+    const int c0 = (blockIdx.y - 1) * kZeroCols, c1 = min(c0 + kZeroCols, a.n_zero);
+    for (int z = c0; z < c1; ++z)
+#pragma unroll
+      for (int r = 0; r < 6; ++r) Jb[(int64_t)(r * nv + a.zcol[z]) * a.sJ_k] = Real(0);
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char path_lds[];
+  Real* cs = reinterpret_cast<Real*>(path_lds);
+  Real* qs = cs + a.len * kPathCst;
+  int* jts = reinterpret_cast<int*>(qs + a.nqp * kPathThreads);
+  const unsigned char* img = image<Real>(dm);
+  const TabLayout tl = tab_layout(dm.n, dm.P, dm.depth, dm.kmax, dm.nv, (int)sizeof(Real));
+  const Real* cst = reinterpret_cast<const Real*>(img + tl.cst);
+  const I4* meta = reinterpret_cast<const I4*>(img + tl.meta);
+  const int64_t bc = live ? b : a.B - 1;
+  const Real* qb = a.q + bc * a.sq_b;
+  for (int k = 0; k < a.nqp; ++k) qs[k * kPathThreads + tid] = qb[(int64_t)a.qsrc[k] * a.sq_k];
+  for (int i = tid; i < a.len * kPathCst; i += kPathThreads) {
+    const int s = i / kPathCst;
+    cs[i] = cst[a.body[s] * CST + (i - s * kPathCst)];
+  }
+  for (int s = tid; s < a.len; s += kPathThreads) jts[s] = meta[a.body[s]].y;
+  __syncthreads();
+
+  Real pe[3] = {Real(0), Real(0), Real(0)};
+  Real Rw[9], pw[3];
+  auto reset = [&]() {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rw[k] = (k % 4 == 0) ? Real(1) : Real(0);
+    pw[0] = pw[1] = pw[2] = Real(0);
+  };
+  if (LWA && a.J) {  // first walk: the end effector's origin
+    reset();
+    for (int s = 0, qo = 0; s < a.len; ++s) {
+      const int jt = jts[s];
+      path_step(cs + s * kPathCst, jt, qs + qo * kPathThreads + tid, Rw, pw);
+      qo += jt == J_FREE ? 7 : 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pe[k] = pw[k];
+  }
+  reset();
+  Real* Jb = a.J ? a.J + bc * a.sJ_b : nullptr;
+  for (int s = 0, qo = 0; s < a.len; ++s) {
+    const Real* c = cs + s * kPathCst;
+    const int jt = jts[s];
+    path_step(c, jt, qs + qo * kPathThreads + tid, Rw, pw);
+    qo += jt == J_FREE ? 7 : 1;
+    if (!Jb || !live) continue;
+    const int v0 = a.vcol[s];
+    const Real zero[3] = {Real(0), Real(0), Real(0)};
+    if (jt == J_FREE) {
+      for (int e = 0; e < 3; ++e) {
+        const Real u[3] = {Rw[e], Rw[3 + e], Rw[6 + e]};
+        store_col(Jb, a.sJ_k, nv, v0 + e, u, zero);
+        Real lin[3];
+        rot_lin<LWA>(u, pw, pe, lin);
+        store_col(Jb, a.sJ_k, nv, v0 + 3 + e, lin, u);
+      }
+      continue;
+    }
+    const Real* ax = c + C_AX;
+    Real u[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u[i] = Rw[3 * i] * ax[0] + Rw[3 * i + 1] * ax[1] + Rw[3 * i + 2] * ax[2];
+    if (jt == J_PRI) {
+      store_col(Jb, a.sJ_k, nv, v0, u, zero);
+    } else {
+      Real lin[3];
+      rot_lin<LWA>(u, pw, pe, lin);
+      store_col(Jb, a.sJ_k, nv, v0, lin, u);
+    }
+  }
+  if (a.pose && live) {
+    Real* po = a.pose + b * a.sp_b;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) po[(int64_t)(4 * r + k) * a.sp_k] = Rw[3 * r + k];
+      po[(int64_t)(4 * r + 3) * a.sp_k] = pw[r];
+    }
+  }
+}
+
+}  // namespace
+
+template <class Real>
+hipError_t launch_path(const DevModel& dm, const PathArgs<Real>& pa, bool lwa, hipStream_t st) {
+  if (pa.B < 1 || pa.len < 1 || pa.len > 64 || pa.nqp < 1 || pa.nqp > 72 || (!pa.J && pa.zero_groups) ||
+      pa.zero_groups > 32 || pa.n_zero > 4 * pa.zero_groups)
+    return hipErrorInvalidValue;
+  const int64_t gx = (pa.B + kPathThreads - 1) / kPathThreads;
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gx, (unsigned)(1 + pa.zero_groups));
+  const size_t lds = ((size_t)pa.len * kPathCst + (size_t)pa.nqp * kPathThreads) * sizeof(Real) + 4 * pa.len;
+  if (lwa)
+    hipLaunchKernelGGL((path_kernel<Real, true>), grid, dim3(kPathThreads), lds, st, dm, pa);
+  else
+    hipLaunchKernelGGL((path_kernel<Real, false>), grid, dim3(kPathThreads), lds, st, dm, pa);
+  return hipGetLastError();
+}
+
+template hipError_t launch_path<float>(const DevModel&, const PathArgs<float>&, bool, hipStream_t);
+template hipError_t launch_path<double>(const DevModel&, const PathArgs<double>&, bool, hipStream_t);
+
+}  // namespace bard

@@ -135,6 +135,19 @@ def test_operator_argument_errors_without_device():
     assert "frame" in bard.bard_last_error().decode() or bard.bard_last_error()
 
 
+def test_path_kinematics_argument_errors_without_device():
+    m = bard.Model.from_tree(synth.humanoid_small())
+    h = m.handle
+    f = bard.bard_path_kinematics
+    assert f(h, 0, None, 3, 0, None, None, None, 0, None) == 0        # B = 0
+    assert f(h, 0, None, 3, 0, None, None, None, 8, None) == -1       # NULL q, no output
+    assert f(h, 0, None, m.n_bodies, 0, None, None, None, 8, None) == -1  # ee_body out of range
+    assert f(h, 0, None, -1, 0, None, None, None, 8, None) == -1
+    assert f(h, 0, None, 3, 2, None, None, None, 8, None) == -1       # bad frame
+    assert f(h, 2, None, 3, 0, None, None, None, 8, None) == -1       # bad dtype
+    assert f(None, 0, None, 3, 0, None, None, None, 8, None) == -1    # NULL model
+
+
 def test_workspace_capacity_checked_on_host():
     m = bard.Model.from_tree(synth.chain7())
     ws = ctypes.c_void_p()
