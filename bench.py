@@ -231,6 +231,14 @@ def op_work(tree, n_ee, op):
         return 4 * (nq + 3 * nv), 2 * n * (24 + 130 + 33)
     if op == "crba":
         return 4 * (nq + nv * nv), None
+    if op == "path":  # one end effector's pose and Jacobian from its path's coordinates
+        import synth
+        e = tree.ee_bodies[0]
+        nqp = 0
+        while e >= 0:
+            nqp += 7 if tree.joint_type[e] == synth.FREE else 1
+            e = tree.parent[e]
+        return 4 * (nqp + 12 + 6 * nv), None
     if op == "aba":
         return 4 * (nq + 3 * nv), 2 * n * (24 + 380)
     raise ValueError(op)
@@ -238,7 +246,8 @@ def op_work(tree, n_ee, op):
 
 def bench_operators(torch, bard):
     """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA, CRBA,
-    ABA) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
+    ABA, and the standalone pose and Jacobian of the first end effector's
+    path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
     at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
     evaluations per second from the kernel time, the HBM fraction of its
     algorithmic bytes, and for RNEA and ABA the FP32 VALU fraction of the
@@ -260,13 +269,17 @@ def bench_operators(torch, bard):
                  "jacobian": torch.empty((6 * tree.nv * len(ee), B), device="cuda"),
                  "rnea": torch.empty((tree.nv, B), device="cuda"),
                  "crba": torch.empty((tree.nv * tree.nv, B), device="cuda"),
-                 "aba": torch.empty((tree.nv, B), device="cuda")}
+                 "aba": torch.empty((tree.nv, B), device="cuda"),
+                 "path_pose": torch.empty((12, B), device="cuda"),
+                 "path_J": torch.empty((6 * tree.nv, B), device="cuda")}
             sets.append((d, o))
         binders = {"fk": lambda d, o: m.bind_fk(d[0], o["fk"]),
                    "jacobian": lambda d, o: m.bind_jacobian(d[0], ee, o["jacobian"]),
                    "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "crba": lambda d, o: m.bind_crba(d[0], o["crba"]),
-                   "aba": lambda d, o: m.bind_aba(d[0], d[1], d[2], o["aba"])}   # qdd's values as torques
+                   "aba": lambda d, o: m.bind_aba(d[0], d[1], d[2], o["aba"]),   # qdd's values as torques
+                   "path": lambda d, o: m.bind_path_kinematics(d[0], ee[0], o["path_pose"], o["path_J"],
+                                                               frame=bard.LOCAL_WORLD_ALIGNED)}
         n = max(100, min(1000, 4_000_000 // B))
         for op, bind in binders.items():
             calls = [bind(d, o) for (d, o) in sets]
@@ -281,6 +294,26 @@ def bench_operators(torch, bard):
                 out[key + "_valu_frac"] = flops * B / t / VALU_PEAK_FP32
         del sets
         torch.cuda.empty_cache()
+    # the standalone path kinematics where it is bound by HBM: the humanoid's
+    # first end effector at B = 262144, both frames
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    B = 262144
+    nbytes, _ = op_work(tree, 1, "path")
+    sets = []
+    for k in range(3):
+        q = synth.random_state(tree, B, 11500 + k)[0]
+        sets.append((torch.from_numpy(q.T.copy()).float().cuda(), torch.empty((12, B), device="cuda"),
+                     torch.empty((6 * tree.nv, B), device="cuda")))
+    for frame, fname in ((bard.WORLD, "world"), (bard.LOCAL_WORLD_ALIGNED, "lwa")):
+        calls = [m.bind_path_kinematics(q, tree.ee_bodies[0], po, J, frame=frame) for (q, po, J) in sets]
+        _, kavg = time_calls(torch, calls, 200, 10)
+        key = f"op_humanoid_large_B{B}_path_{fname}"
+        out[key + "_kernel_us"] = kavg * 1e3
+        out[key + "_evals_per_s"] = B / (kavg * 1e-3)
+        out[key + "_hbm_frac"] = nbytes * B / (kavg * 1e-3) / 1e9 / HBM_PEAK_GBS
+    del sets
+    torch.cuda.empty_cache()
     # the 23-velocity-DOF humanoid at B = 16384: fused, plain and graph forms
     ts = synth.humanoid_small()
     ms = bard.Model.from_tree(ts)

@@ -462,7 +462,8 @@ int bard_aba_vjp(bard_model_t model, bard_dtype dtype, const void* q, const void
  * after bard_plan_configure or bard_plan_autotune) synchronizes the device.
  * bard_plan_autotune: times every valid configuration (tile 8, 16 or 32 instances;
  * fusion 0 = one launch for all models, 1 = one launch per model, 2 = one
- * launch per operator; item order 0 = longest first, 1 = model order; lanes
+ * launch per operator, 3 = one launch of a kernel generated for the plan's
+ * trees; item order 0 = longest first, 1 = model order; lanes
  * per instance at the model's minimum or twice that) on
  * zero-filled scratch arrays for about budget_ms, keeps the fastest and
  * records it in a JSON cache (file $BARD_TUNE_CACHE, else
@@ -479,15 +480,30 @@ int bard_plan_autotune(bard_plan_t plan, void* stream, int32_t budget_ms);
 int bard_plan_run(bard_plan_t plan, const void* const* io, void* stream);
 int bard_plan_destroy(bard_plan_t plan);
 /* Pin a configuration (what bard_plan_autotune chooses): tile 8, 16 or 32,
- * fusion 0..2, order 0..1 as above, lanes 0 or 1 (twice the lanes per
+ * fusion 0..3, order 0..1 as above, lanes 0 or 1 (twice the lanes per
  * instance of the level sweep when 1: each instance's bodies spread over
  * more lanes, so a tile occupies more waves).  Fusion 0 and 1 need op_mask to
  * be one operator or all three.  A configuration whose sweep needs more than
- * 8 waves is refused by the first run with BARD_E_CAPACITY. */
+ * 8 waves is refused by the first run with BARD_E_CAPACITY.
+ * Fusion 3 (all three operators only; tile, order and lanes are ignored): the
+ * model compiler emits one kernel holding every tree's model-specialised
+ * chain code (as bard_model_specialize does for one model: every constant a
+ * literal, one lane per instance, the dual form where a tree has limbs),
+ * compiled with hipRTC on the plan's first run in this configuration (which
+ * may take seconds); its workgroups take the trees' 64-instance groups,
+ * trees of larger nv first.  bard_plan_autotune always includes it when the
+ * plan has all three operators and does not count its compilation against
+ * budget_ms. */
 int bard_plan_configure(bard_plan_t plan, int32_t tile, int32_t fusion, int32_t order, int32_t lanes);
 /* Current configuration; from_cache = 1 if it came from the tuning cache. */
 int bard_plan_get_config(bard_plan_t plan, int32_t* tile, int32_t* fusion, int32_t* order, int32_t* lanes,
                          int32_t* from_cache);
+/* The generated source of the plan's fusion-3 kernel (NUL-terminated into
+ * buf when cap > 0; *len its length without the NUL); compile_only = 1 also
+ * compiles it for gfx950 with hipRTC (no GPU needed) and reports a failure as
+ * BARD_E_DEVICE.  Errors: BARD_E_ARG, BARD_E_UNSUPPORTED (op_mask not all
+ * three operators), BARD_E_DEVICE. */
+int bard_plan_specialized_source(bard_plan_t plan, int32_t compile_only, char* buf, int64_t cap, int64_t* len);
 /* Tip end effectors of model `model_index` (ee_body: room for 4 entries). */
 int bard_plan_ee(bard_plan_t plan, int32_t model_index, int32_t* n_ee, int32_t* ee_body);
 

@@ -134,6 +134,8 @@ bard_plan_destroy = _sig("bard_plan_destroy", [_vp])
 bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32, _i32])
 bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
 bard_plan_ee = _sig("bard_plan_ee", [_vp, _i32, _c_i32p, _c_i32p])
+bard_plan_specialized_source = _sig("bard_plan_specialized_source", [_vp, _i32, ctypes.c_char_p, _i64,
+                                                                     ctypes.POINTER(_i64)])
 
 PLAN_RNEA, PLAN_CRBA, PLAN_JACOBIAN = 1, 2, 4
 
@@ -799,6 +801,23 @@ class Model:
             return keep
         return call
 
+    def bind_path_kinematics(self, q, ee: int, out_pose, out_J, frame: int = WORLD, layout: str = "soa"):
+        B = _batch_of(q, self.nq, layout)
+        _check_arrays(q, [(out_pose, 12, "out_pose"), (out_J, 6 * self.nv, "out_J")], B, layout)
+        if out_pose is None and out_J is None:
+            raise ValueError("path_kinematics needs an output")
+        L = _layouts([q, out_pose, out_J], layout)
+        args = (self._h, _dtype_code(q), _ptr(q), int(ee), int(frame), _ptr(out_pose), _ptr(out_J), L, B,
+                _stream_ptr(q))
+        keep = (L, q, out_pose, out_J)
+
+        def call():
+            rc = bard_path_kinematics(*args)
+            if rc:
+                raise BardError(rc, "bard_path_kinematics")
+            return keep
+        return call
+
     def bind_jacobian(self, q, ee: Sequence[int], out, frame: int = WORLD, layout: str = "soa"):
         B = _batch_of(q, self.nq, layout)
         ee_a, pee = _i32arr(ee)
@@ -850,6 +869,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def specialized_source(self, compile_only: bool = False) -> str:
+        """Source of the plan's generated multi-tree kernel (fusion 3);
+        compile_only also compiles it for gfx950 with hipRTC."""
+        n = _i64()
+        _check(bard_plan_specialized_source(self._h, 0, None, 0, ctypes.byref(n)), "bard_plan_specialized_source")
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(bard_plan_specialized_source(self._h, int(compile_only), buf, n.value + 1, ctypes.byref(n)),
+               "bard_plan_specialized_source")
+        return buf.value.decode()
 
     def ee(self, i: int) -> list:
         n = ctypes.c_int32()

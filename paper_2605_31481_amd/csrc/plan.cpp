@@ -29,7 +29,9 @@ namespace {
 constexpr int kMaxPlanModels = 64;
 constexpr int kPlanMaxEE = 4;
 
-enum { FUSE_ALL = 0, FUSE_PER_MODEL = 1, FUSE_PER_OP = 2 };
+// FUSE_SPEC: one launch of a kernel generated for the plan's trees (every
+// model constant a literal, each tree's code specialised; hipRTC).
+enum { FUSE_ALL = 0, FUSE_PER_MODEL = 1, FUSE_PER_OP = 2, FUSE_SPEC = 3 };
 enum { ORDER_LONGEST_FIRST = 0, ORDER_MODEL = 1 };
 
 struct PlanConfig {
@@ -105,6 +107,9 @@ struct bard_plan {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // FUSE_SPEC: the generated kernel (loaded on `device`) and its launch size
+  SpecKernel spk;
+  int64_t spk_blocks = 0;
 };
 
 namespace {
@@ -189,11 +194,62 @@ void write_cache(const std::string& path, const std::map<std::string, std::pair<
 
 bool valid_config(const bard_plan* p, const PlanConfig& c) {
   if (c.logT < 3 || c.logT > 5) return false;
-  if (c.fusion < FUSE_ALL || c.fusion > FUSE_PER_OP) return false;
+  if (c.fusion < FUSE_ALL || c.fusion > FUSE_SPEC) return false;
+  if (c.fusion == FUSE_SPEC && mask_to_ops(p->op_mask) != (OP_RNEA | OP_CRBA | OP_JAC)) return false;
   if (c.order != ORDER_LONGEST_FIRST && c.order != ORDER_MODEL) return false;
   if (c.lanes < 0 || c.lanes > 1) return false;
   if (c.fusion != FUSE_PER_OP && !fusable(mask_to_ops(p->op_mask))) return false;
   return true;
+}
+
+// Host-side buffers every configuration uses: the pinned staging copy of
+// the arguments, its event and the capture stream.
+int plan_host_state(bard_plan* p) {
+  if (!p->h_stage) {
+    const size_t hb = kMaxPlanModels * sizeof(Args<double>);
+    if (hipHostMalloc((void**)&p->h_stage, hb, hipHostMallocDefault) != hipSuccess)
+      return fail(BARD_E_NOMEM, "hipHostMalloc of the plan staging buffer failed");
+  }
+  if (!p->staged && hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
+    return fail(BARD_E_DEVICE, "hipEventCreate failed");
+  if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+    return fail(BARD_E_DEVICE, "hipStreamCreate failed");
+  return BARD_OK;
+}
+
+// FUSE_SPEC: generate and compile the plan's kernel once per plan (on its
+// device); its descriptor holds one SpecPlanIO per model.
+template <class Real>
+int prepare_spec(bard_plan* p) {
+  if (!p->spk.fn) {
+    std::vector<bard_model*> ms(p->models.begin(), p->models.end());
+    int rc = spec_plan_build(ms, p->ee, p->batch, sizeof(Real) == 8, &p->spk, &p->spk_blocks);
+    if (rc) return rc;
+  }
+  const int nm = (int)p->models.size();
+  p->args_bytes = nm * sizeof(SpecPlanIO<Real>);
+  p->off_args = 0;
+  p->n_items = 0;
+  p->groups.clear();
+  if (p->spk_blocks > 0) p->groups.push_back(Group{-1, 0, 0, 64 * p->spk.waves, 0});
+  if (p->spk_blocks > 0x7fffffff) return fail(BARD_E_CAPACITY, "too many workgroups for one launch");
+  if (p->args_bytes > p->d_bytes) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(BARD_E_DEVICE, "device error before plan upload");
+    if (p->d_buf) (void)hipFree(p->d_buf);
+    p->d_buf = nullptr;
+    p->d_bytes = 0;
+    if (hipMalloc((void**)&p->d_buf, p->args_bytes) != hipSuccess)
+      return fail(BARD_E_NOMEM, "hipMalloc of the plan failed");
+    p->d_bytes = p->args_bytes;
+  }
+  int rc = plan_host_state(p);
+  if (rc) return rc;
+  p->g_gen.assign(nm, 0);
+  for (int i = 0; i < nm; ++i) p->g_gen[i] = p->models[i]->g_gen;
+  p->h_last.clear();
+  p->runs = 0;
+  p->ready = true;
+  return BARD_OK;
 }
 
 template <class Real>
@@ -204,6 +260,7 @@ int prepare_t(bard_plan* p) {
   p->device = dev;
   if (p->ready) return BARD_OK;
   drop_graph(p);
+  if (p->cfg.fusion == FUSE_SPEC) return prepare_spec<Real>(p);
   const int nm = (int)p->models.size();
   const int T = 1 << p->cfg.logT;
   const int all_ops = mask_to_ops(p->op_mask);
@@ -306,15 +363,8 @@ int prepare_t(bard_plan* p) {
     if (hipMalloc((void**)&p->d_buf, need) != hipSuccess) return fail(BARD_E_NOMEM, "hipMalloc of the plan failed");
     p->d_bytes = need;
   }
-  if (!p->h_stage) {
-    const size_t hb = kMaxPlanModels * sizeof(Args<double>);
-    if (hipHostMalloc((void**)&p->h_stage, hb, hipHostMallocDefault) != hipSuccess)
-      return fail(BARD_E_NOMEM, "hipHostMalloc of the plan staging buffer failed");
-  }
-  if (!p->staged && hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
-    return fail(BARD_E_DEVICE, "hipEventCreate failed");
-  if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
-    return fail(BARD_E_DEVICE, "hipStreamCreate failed");
+  rc = plan_host_state(p);
+  if (rc) return rc;
   // the descriptor may still be read by earlier work of this plan
   if (hipDeviceSynchronize() != hipSuccess) return fail(BARD_E_DEVICE, "device error before plan upload");
   bool ok = hipMemcpy(p->d_buf, dms.data(), nm * sizeof(DevModel), hipMemcpyHostToDevice) == hipSuccess &&
@@ -332,7 +382,31 @@ int prepare(bard_plan* p) { return p->dtype == BARD_F32 ? prepare_t<float>(p) : 
 
 // Per-model kernel arguments from io (per model: q, qd, qdd, tau, M, J).
 template <class Real>
+int build_spec_args(const bard_plan* p, const void* const* io, std::vector<unsigned char>* out) {
+  const int nm = (int)p->models.size();
+  out->assign(nm * sizeof(SpecPlanIO<Real>), 0);
+  SpecPlanIO<Real>* a = reinterpret_cast<SpecPlanIO<Real>*>(out->data());
+  for (int i = 0; i < nm; ++i) {
+    bard_model* m = p->models[i];
+    const void* const* v = io + 6 * i;
+    if (p->batch[i] > 0)
+      for (int k = 0; k < 6; ++k)
+        if (!v[k]) return fail(BARD_E_ARG, "NULL array in plan io");
+    a[i].q = (const Real*)v[0];
+    a[i].qd = (const Real*)v[1];
+    a[i].qdd = (const Real*)v[2];
+    a[i].tau = (Real*)v[3];
+    a[i].M = (Real*)v[4];
+    a[i].J = (Real*)v[5];
+    std::lock_guard<std::mutex> lk(m->mu);
+    for (int k = 0; k < 3; ++k) a[i].g[k] = (Real)m->g[k];
+  }
+  return BARD_OK;
+}
+
+template <class Real>
 int build_args(const bard_plan* p, const void* const* io, std::vector<unsigned char>* out) {
+  if (p->cfg.fusion == FUSE_SPEC) return build_spec_args<Real>(p, io, out);
   const int nm = (int)p->models.size();
   const int ops = mask_to_ops(p->op_mask);
   out->assign(p->args_bytes, 0);
@@ -383,6 +457,13 @@ int stage_args(bard_plan* p, const std::vector<unsigned char>& args, hipStream_t
 
 template <class Real>
 hipError_t launch_groups_t(const bard_plan* p, hipStream_t st) {
+  if (p->cfg.fusion == FUSE_SPEC) {
+    if (p->groups.empty()) return hipSuccess;
+    void* io = p->d_buf + p->off_args;
+    void* args[] = {&io};
+    return hipModuleLaunchKernel((hipFunction_t)p->spk.fn, (unsigned)p->spk_blocks, 1, 1, 64 * p->spk.waves, 1, 1, 0,
+                                 st, args, nullptr);
+  }
   for (const Group& g : p->groups) {
     PlanPtrs<Real> pp;
     pp.dm = reinterpret_cast<const DevModel*>(p->d_buf);
@@ -585,32 +666,38 @@ int bard_plan_autotune(bard_plan_t p, void* stream, int32_t budget_ms) {
   const PlanConfig start = p->cfg;
   PlanConfig best = start;
   double best_us = 1e300;
-  const auto t_start = std::chrono::steady_clock::now();
+  auto t_start = std::chrono::steady_clock::now();
+  // the generated multi-tree kernel first (it is tried whatever the budget;
+  // its compilation is not timed), then the generic configurations
+  std::vector<PlanConfig> cands;
+  cands.push_back(PlanConfig{4, FUSE_SPEC, ORDER_LONGEST_FIRST, 0});
   for (int ln = 0; ln <= 1; ++ln)
-  for (int lt = 3; lt <= 5; ++lt)
-    for (int fu = FUSE_ALL; fu <= FUSE_PER_OP; ++fu)
-      for (int od = ORDER_LONGEST_FIRST; od <= ORDER_MODEL; ++od) {
-        const double spent =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-        if (spent > budget_ms && best_us < 1e300) continue;
-        PlanConfig c{lt, fu, od, ln};
-        if (!valid_config(p, c) || (fu == FUSE_PER_MODEL && od == ORDER_MODEL)) continue;
-        p->cfg = c;
-        p->ready = false;
-        if (run_plan(p, io.data(), st, false) != BARD_OK) continue;  // infeasible (LDS) or failed: skip
-        const int reps = 10;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps; ++r) (void)launch_groups(p, st);
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) continue;
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double us = 1e3 * ms / reps;
-        if (us < best_us) {
-          best_us = us;
-          best = c;
-        }
-      }
+    for (int lt = 3; lt <= 5; ++lt)
+      for (int fu = FUSE_ALL; fu <= FUSE_PER_OP; ++fu)
+        for (int od = ORDER_LONGEST_FIRST; od <= ORDER_MODEL; ++od) cands.push_back(PlanConfig{lt, fu, od, ln});
+  for (const PlanConfig& c : cands) {
+    const int fu = c.fusion, od = c.order;
+    const double spent =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (spent > budget_ms && best_us < 1e300 && fu != FUSE_SPEC) continue;
+    if (!valid_config(p, c) || (fu == FUSE_PER_MODEL && od == ORDER_MODEL)) continue;
+    p->cfg = c;
+    p->ready = false;
+    if (run_plan(p, io.data(), st, false) != BARD_OK) continue;  // infeasible (LDS) or failed: skip
+    const int reps = 10;
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps; ++r) (void)launch_groups(p, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) continue;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double us = 1e3 * ms / reps;
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+    if (fu == FUSE_SPEC) t_start = std::chrono::steady_clock::now();
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   cleanup();
@@ -630,6 +717,29 @@ int bard_plan_autotune(bard_plan_t p, void* stream, int32_t budget_ms) {
   return BARD_OK;
 }
 
+int bard_plan_specialized_source(bard_plan_t p, int32_t compile_only, char* buf, int64_t cap, int64_t* len) {
+  if (!p || !len) return fail(BARD_E_ARG, "NULL argument");
+  if (mask_to_ops(p->op_mask) != (OP_RNEA | OP_CRBA | OP_JAC))
+    return fail(BARD_E_UNSUPPORTED, "the generated multi-tree kernel covers plans of all three operators");
+  std::vector<bard_model*> ms(p->models.begin(), p->models.end());
+  int waves = 1;
+  int64_t blocks = 0;
+  const std::string src = spec_plan_source(ms, p->ee, p->batch, p->dtype == BARD_F64, &waves, &blocks);
+  *len = (int64_t)src.size();
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
+    std::memcpy(buf, src.data(), n);
+    buf[n] = 0;
+  }
+  if (compile_only) {
+    std::vector<char> code;
+    std::string log;
+    const int rc = spec_compile(src, &code, &log);
+    if (rc) return fail(rc, "hipRTC compile of the multi-tree kernel failed: " + log.substr(0, 2000));
+  }
+  return BARD_OK;
+}
+
 int bard_plan_destroy(bard_plan_t p) {
   if (!p) return fail(BARD_E_ARG, "plan is NULL");
   if (p->device >= 0) {
@@ -642,6 +752,7 @@ int bard_plan_destroy(bard_plan_t p) {
     if (p->staged) (void)hipEventDestroy(p->staged);
     if (p->d_buf) (void)hipFree(p->d_buf);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->spk.mod) (void)hipModuleUnload((hipModule_t)p->spk.mod);
     if (cur >= 0) (void)hipSetDevice(cur);
   }
   delete p;

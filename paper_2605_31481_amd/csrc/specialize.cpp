@@ -147,31 +147,38 @@ class Emitter {
     slot_body_ = pl_.slot_body;
   }
 
+  // Helpers and accessor macros every generated chain source starts with.
+  static std::string prologue(bool fp64) {
+    std::ostringstream o;
+    o << "#include \"spatial.h\"\n";
+    o << "typedef " << (fp64 ? "double" : "float") << " Real;\n";
+    o << "template <class T>\n"
+         "__device__ __forceinline__ T* bard_at(T* base, long long k, long long sk, unsigned ob) {\n"
+         "  return (T*)((const char*)(base + k * sk) + ob);\n"
+         "}\n"
+         "#define Q(k) (*bard_at(q, (k), sq_k, oq_))\n"
+         "#define QD(k) (*bard_at(qd, (k), sqd_k, oqd_))\n"
+         "#define QDD(k) (*bard_at(qdd, (k), sqdd_k, oqdd_))\n"
+         "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, float v) {\n"
+         "  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)ob, (int)row, 2);\n"
+         "}\n"
+         "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, double v) {\n"
+         "  typedef unsigned U2 __attribute__((ext_vector_type(2)));\n"
+         "  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)ob, (int)row, 2);\n"
+         "}\n"
+         "#define TAU(k, v) bard_st(rt_, (unsigned)(k) * ut_, ot_, (v))\n"
+         "#define MA(k, v) bard_st(rM_, (unsigned)(k) * uM_, oM_, (v))\n"
+         "#define JA(k, v) bard_st(rJ_, (unsigned)(k) * uJ_, oJ_, (v))\n"
+         "#define Qv(k) Qv_##k\n"
+         "#define QDv(k) QDv_##k\n"
+         "#define QDDv(k) QDDv_##k\n";
+    return o.str();
+  }
+
   std::string source() {
     o_ << "// generated: fused RNEA + CRBA + Jacobian for one tree (" << m_->n << " bodies, nv " << m_->nv
-       << ", " << ee_.size() << " end effectors, frame " << frame_ << ", " << (fp64_ ? "FP64" : "FP32")
-       << ")\n#include \"spatial.h\"\n";
-    o_ << "typedef " << (fp64_ ? "double" : "float") << " Real;\n";
-    o_ << "template <class T>\n"
-          "__device__ __forceinline__ T* bard_at(T* base, long long k, long long sk, unsigned ob) {\n"
-          "  return (T*)((const char*)(base + k * sk) + ob);\n"
-          "}\n"
-          "#define Q(k) (*bard_at(q, (k), sq_k, oq_))\n"
-          "#define QD(k) (*bard_at(qd, (k), sqd_k, oqd_))\n"
-          "#define QDD(k) (*bard_at(qdd, (k), sqdd_k, oqdd_))\n"
-          "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, float v) {\n"
-          "  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)ob, (int)row, 2);\n"
-          "}\n"
-          "__device__ __forceinline__ void bard_st(__amdgpu_buffer_rsrc_t r, unsigned row, unsigned ob, double v) {\n"
-          "  typedef unsigned U2 __attribute__((ext_vector_type(2)));\n"
-          "  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, (int)ob, (int)row, 2);\n"
-          "}\n"
-          "#define TAU(k, v) bard_st(rt_, (unsigned)(k) * ut_, ot_, (v))\n"
-          "#define MA(k, v) bard_st(rM_, (unsigned)(k) * uM_, oM_, (v))\n"
-          "#define JA(k, v) bard_st(rJ_, (unsigned)(k) * uJ_, oJ_, (v))\n"
-          "#define Qv(k) Qv_##k\n"
-          "#define QDv(k) QDv_##k\n"
-          "#define QDDv(k) QDDv_##k\n";
+       << ", " << ee_.size() << " end effectors, frame " << frame_ << ", " << (fp64_ ? "FP64" : "FP32") << ")\n";
+    o_ << prologue(fp64_);
     emit_zero_tables();
     const int nw = pl_.waves;
     o_ << "static constexpr int NW = " << nw << ";  // waves per workgroup, 64 instances\n";
@@ -198,10 +205,50 @@ class Emitter {
           "        *reinterpret_cast<Zv*>(row + j * V) = zero;\n"
           "    }\n"
           "    return;\n"
-          "  }\n"
-          ;
+          "  }\n";
+    body();
+    o_ << "}\n";
+    return o_.str();
+  }
+
+  // The tree's code as a member of a multi-tree kernel: namespace bard_t<k>
+  // with its tables and run(io, blk, xch_), which evaluates the 64-instance
+  // group (or dual half) `blk` of a batch of B instances held instance-minor
+  // ([K][B], the layout of plans); xch_ is the kernel's LDS hand-over area.
+  // The kernel's workgroups may have more waves than this tree uses: those
+  // skip the tree's work and still reach its barrier.
+  std::string member(int k, int64_t B) {
+    member_ = true;
+    blk_ = "blk";
+    o_ << "namespace bard_t" << k << " {  // " << m_->n << " bodies, nv " << m_->nv << ", batch " << B << "\n";
+    emit_zero_tables();
+    o_ << "static constexpr int NW = " << pl_.waves << ";\n";
+    o_ << "__device__ __forceinline__ void run(const PlanIO& io, long long blk, Real* xch_) {\n";
+    const long long ld = std::max<int64_t>(B, 1);
+    o_ << "  const Real* __restrict__ q = io.q;\n  const Real* __restrict__ qd = io.qd;\n"
+          "  const Real* __restrict__ qdd = io.qdd;\n  Real* __restrict__ tau = io.tau;\n"
+          "  Real* __restrict__ M = io.M;\n  Real* __restrict__ J = io.J;\n"
+       << "  const long long B = " << B << "LL;\n"
+       << "  const long long sq_b = 1, sqd_b = 1, sqdd_b = 1, st_b = 1, sM_b = 1, sJ_b = 1;\n"
+       << "  const long long sq_k = " << ld << "LL, sqd_k = " << ld << "LL, sqdd_k = " << ld << "LL, st_k = " << ld
+       << "LL, sM_k = " << ld << "LL, sJ_k = " << ld << "LL;\n"
+       << "  const Real g0 = io.g[0], g1 = io.g[1], g2 = io.g[2];\n"
+          "  const int zero_blocks = 0;\n";
+    body();
+    o_ << "}\n}  // namespace bard_t" << k << "\n";
+    return o_.str();
+  }
+
+  int waves() const { return pl_.waves; }
+  int wg_per_group() const { return dual_ ? 2 : 1; }
+  // LDS values of the hand-over area (trunk slots x 16 x 64 lanes)
+  int xch_values() const { return split_ ? (int)slot_body_.size() * 16 * 64 : 0; }
+
+  // The code of one workgroup after the structural-zero workgroups.
+  void body() {
     if (!split_) {
-      o_ << "  const long long b = (long long)blockIdx.x * 64 + threadIdx.x;\n"
+      if (member_) o_ << "  if (threadIdx.x >= 64) return;\n";
+      o_ << "  const long long b = (long long)" << blk_ << " * 64 + threadIdx.x;\n"
             "  if (b >= B) return;\n";
       pointers();
       std::vector<int> all(m_->n);
@@ -210,21 +257,20 @@ class Emitter {
       emit_zero_stores();
       for (int i = 0; i < m_->n; ++i)
         if (m_->parent[i] < 0) visit(i);
-      o_ << "}\n";
-      return o_.str();
+      return;
     }
     // Every lane of every wave reaches the barrier: lanes past the batch
     // repeat the last instance (the same values to the same addresses).
     o_ << "  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);\n"
           "  const int lane = (int)threadIdx.x & 63;\n";
     if (dual_)
-      o_ << "  const int part = (int)blockIdx.x & 1;  // 0: torques, 1: mass matrix and Jacobians\n"
-            "  long long b = ((long long)blockIdx.x >> 1) * 64 + lane;\n";
+      o_ << "  const int part = (int)" << blk_ << " & 1;  // 0: torques, 1: mass matrix and Jacobians\n"
+         << "  long long b = ((long long)" << blk_ << " >> 1) * 64 + lane;\n";
     else
-      o_ << "  long long b = (long long)blockIdx.x * 64 + lane;\n";
+      o_ << "  long long b = (long long)" << blk_ << " * 64 + lane;\n";
     o_ << "  if (b > B - 1) b = B - 1;\n";
     pointers();
-    if (!slot_body_.empty()) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
+    if (!slot_body_.empty() && !member_) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
     if (dual_) {
       o_ << "  if (part == 0) {\n";
       do_rnea_ = true;
@@ -239,8 +285,6 @@ class Emitter {
     } else {
       split_body();
     }
-    o_ << "}\n";
-    return o_.str();
   }
 
   // The workgroup's code for the parts selected by do_rnea_ / do_crba_: the
@@ -366,6 +410,8 @@ class Emitter {
   std::vector<char> trunk_;
   std::vector<int> slot_body_;
   std::ostringstream o_;
+  bool member_ = false;             // emitting a member of a multi-tree kernel
+  std::string blk_ = "blockIdx.x";  // the workgroup's group index in the emitted code
 
   double c(int body, int k) const { return fp64_ ? m_->cst64[body * CST + k] : (double)m_->cst32[body * CST + k]; }
   std::string lit(double x) const {
@@ -408,8 +454,8 @@ class Emitter {
 
   void emit_zero_stores() {
     const char* first = split_ ? "wave" : "0";
-    o_ << "  if (zero_blocks == 0) {\n"
-          "    for (int i = " << first << "; i < NZM; i += NW) MA(ZM[i], Real(0));\n"
+    o_ << (split_ ? "  if (zero_blocks == 0 && wave < NW) {\n" : "  if (zero_blocks == 0) {\n")
+       << "    for (int i = " << first << "; i < NZM; i += NW) MA(ZM[i], Real(0));\n"
           "    for (int i = " << first << "; i < NZJ; i += NW) JA(ZJ[i], Real(0));\n"
           "  }\n";
   }
@@ -1271,6 +1317,49 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
   return Emitter(m, ee, frame, fp64, form).source();
 }
 
+std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
+                             const std::vector<int64_t>& batch, bool fp64, int* waves, int64_t* blocks) {
+  std::ostringstream o;
+  const int n = (int)ms.size();
+  o << "// generated: fused RNEA + CRBA + Jacobian of " << n << " trees in one launch ("
+    << (fp64 ? "FP64" : "FP32") << ")\n"
+    << Emitter::prologue(fp64)
+    << "struct PlanIO {\n  const Real* q;\n  const Real* qd;\n  const Real* qdd;\n  Real* tau;\n  Real* M;\n"
+       "  Real* J;\n  Real g[4];\n};\n";
+  // trees of larger nv first: their workgroups run longest, and the
+  // dispatcher hands workgroups out in order
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ms[a]->nv > ms[b]->nv; });
+  int nwb = 1, xmax = 0;
+  std::vector<int64_t> first(n, 0), count(n, 0);
+  int64_t at = 0;
+  for (int k : order) {
+    if (batch[k] <= 0) continue;
+    const int form = spec_form_ok(ms[k], fp64, 2) ? 2 : 0;
+    Emitter e(ms[k], ee[k], 0, fp64, form);
+    o << e.member(k, batch[k]);
+    nwb = std::max(nwb, e.waves());
+    xmax = std::max(xmax, e.xch_values());
+    first[k] = at;
+    count[k] = (batch[k] + 63) / 64 * e.wg_per_group();
+    at += count[k];
+  }
+  o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * nwb
+    << ") bard_spec_plan(const PlanIO* __restrict__ io) {\n";
+  if (xmax) o << "  __shared__ Real xch_[" << xmax << "];\n";
+  else o << "  Real* xch_ = nullptr;\n";
+  o << "  const long long blk = blockIdx.x;\n";
+  for (int k : order)
+    if (count[k])
+      o << "  if (blk < " << first[k] + count[k] << "LL) {\n    bard_t" << k << "::run(io[" << k << "], blk - "
+        << first[k] << "LL, xch_);\n    return;\n  }\n";
+  o << "}\n";
+  *waves = nwb;
+  *blocks = at;
+  return o.str();
+}
+
 std::string spec_aba_source(const bard_model* m, bool fp64, bool split) {
   return AbaEmitter(m, fp64, split).source();
 }
@@ -1425,6 +1514,54 @@ int spec_prepare_aba(bard_model* m, DeviceCopy* dc, int dtype, bool load, SpecKe
         sk->form = sk->waves > 1 ? 0 : 1;
       },
       load, out);
+}
+
+int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
+                    const std::vector<int64_t>& batch, bool fp64, SpecKernel* sk, int64_t* blocks) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int waves = 1;
+  const std::string src = spec_plan_source(ms, ee, batch, fp64, &waves, blocks);
+  SpecKernel out;
+  out.waves = waves;
+  {
+    // code objects by source: plans over the same trees and batches share one
+    // compilation per process
+    static std::mutex mu;
+    static std::map<std::string, std::vector<char>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(src);
+    if (it != done.end()) {
+      out.code = it->second;
+    } else {
+      std::string log;
+      const int rc = spec_compile(src, &out.code, &log);
+      if (rc) return fail(rc, "hipRTC compile of the multi-tree kernel failed: " + log.substr(0, 2000));
+      if (done.size() >= 16) done.clear();
+      done[src] = out.code;
+    }
+  }
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  if (hipModuleLoadData(&mod, out.code.data()) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BARD_E_DEVICE, "hipModuleLoadData of the multi-tree kernel failed");
+  }
+  if (hipModuleGetFunction(&fn, mod, "bard_spec_plan") != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipModuleUnload(mod);
+    return fail(BARD_E_DEVICE, "multi-tree kernel not found in its module");
+  }
+  out.mod = mod;
+  out.fn = fn;
+  int regs = 0, local = 0;
+  if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn) != hipSuccess ||
+      hipFuncGetAttribute(&local, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn) != hipSuccess)
+    (void)hipGetLastError();
+  out.vgprs = regs;
+  out.scratch = local;
+  out.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *sk = std::move(out);
+  return BARD_OK;
 }
 
 SpecKernel* spec_lookup_aba(bard_model* m, DeviceCopy* dc, int dtype, int64_t B) {

@@ -209,8 +209,10 @@ def test_plan_host_side():
     assert p.config["tile"] == 32 and p.config["fusion"] == 2
     with pytest.raises(bard.BardError):
         p.configure(12, 0, 0)
+    p.configure(16, 3, 0)                      # the generated multi-tree kernel
+    assert p.config["fusion"] == 3
     with pytest.raises(bard.BardError):
-        p.configure(16, 3, 0)
+        p.configure(16, 4, 0)
     with pytest.raises(bard.BardError):
         p.configure(16, 0, 0, 2)
     # two operators have no fused kernel: only one launch per operator is valid
@@ -218,6 +220,8 @@ def test_plan_host_side():
     assert p2.config["fusion"] == 2
     with pytest.raises(bard.BardError):
         p2.configure(16, 0, 0)
+    with pytest.raises(bard.BardError):          # the generated kernel needs all three operators
+        p2.configure(16, 3, 0)
     h = ctypes.c_void_p()
     hs = (ctypes.c_void_p * 1)(ms[0].handle)
     bs = (ctypes.c_int64 * 1)(8)

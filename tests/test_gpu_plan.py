@@ -33,6 +33,8 @@ def _check(plan, trees, host, outs, dtype, n_sample=96, seed=0):
     rng = np.random.default_rng(seed)
     for k, (tree, (q, qd, qdd), (tau, M, J)) in enumerate(zip(trees, host, outs)):
         B = q.shape[0]
+        if B == 0:
+            continue
         idx = np.sort(rng.choice(B, min(n_sample, B), replace=False))
         ee = plan.ee(k)
         assert_chain(oracle_for(tree), tree, q[idx], qd[idx], qdd[idx], ee,
@@ -41,7 +43,7 @@ def _check(plan, trees, host, outs, dtype, n_sample=96, seed=0):
 
 
 CONFIGS = [(16, 0, 0, 0), (8, 1, 0, 0), (32, 2, 1, 0), (16, 2, 0, 0), (8, 0, 1, 0), (32, 0, 0, 0), (16, 0, 0, 1),
-           (8, 2, 0, 1)]
+           (8, 2, 0, 1), (16, 3, 0, 0)]
 
 
 @pytest.mark.parametrize("tile,fusion,order,lanes", CONFIGS)
@@ -62,12 +64,14 @@ def test_plan_configurations(tile, fusion, order, lanes):
                 assert torch.equal(x, y)
 
 
-def test_plan_graph_replay_with_new_inputs():
+@pytest.mark.parametrize("fusion", [0, 3])
+def test_plan_graph_replay_with_new_inputs(fusion):
     import torch
-    say("[gpu] plan graph replay, inputs swapped between replays")
+    say(f"[gpu] plan graph replay, inputs swapped between replays, fusion {fusion}")
     trees, models, batches, host_a, dev_a = _setup(seed=2400)
     _, _, _, host_b, dev_b = _setup(seed=2500)
     plan = bard.Plan(models, batches)
+    plan.configure(16, fusion)
     ref_a = _snapshot(plan.run(dev_a))
     torch.cuda.synchronize()
     for rep in range(3):
@@ -120,7 +124,7 @@ def test_plan_autotune_and_cache(tmp_path, monkeypatch):
     plan = bard.Plan(models, batches)
     plan.autotune(1500)
     cfg = plan.config
-    assert cfg["tile"] in (8, 16, 32) and cfg["fusion"] in (0, 1, 2) and not cfg["from_cache"]
+    assert cfg["tile"] in (8, 16, 32) and cfg["fusion"] in (0, 1, 2, 3) and not cfg["from_cache"]
     outs = plan.run(dev)
     torch.cuda.synchronize()
     _check(plan, trees, host, outs, "float32", n_sample=48)
@@ -149,6 +153,53 @@ def test_plan_follows_gravity_changes():
         outs = plan.run(dev)
         torch.cuda.synchronize()
         rng = np.random.default_rng(5)
+        for k, (tree, (q, qd, qdd)) in enumerate(zip(trees, host)):
+            idx = np.sort(rng.choice(q.shape[0], min(32, q.shape[0]), replace=False))
+            om = OracleModel(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, g_new)
+            tg = synth.Tree(**{**tree.__dict__, "gravity": g_new})
+            assert_chain(om, tg, q[idx], qd[idx], qdd[idx], [], from_dev(outs[k][0])[idx], None, None, "float32",
+                         label=f"tau[{k}] after set_gravity")
+
+
+@pytest.mark.parametrize("dtype,batches", [("float64", [64, 37, 129, 8, 200]), ("float32", [300, 17, 0, 1000, 64])])
+def test_generated_multi_tree_kernel_ragged_and_empty_batches(dtype, batches):
+    """Fusion 3 (one generated kernel for the five trees): FP64 with batches
+    below and past one 64-instance group, FP32 with an empty batch; every
+    instance of every tree against the oracle, then a graph replay."""
+    import torch
+    say(f"[gpu] generated multi-tree kernel {dtype} batches {batches}")
+    trees, models, batches, host, dev = _setup(dtype, seed=2900, batches=batches)
+    plan = bard.Plan(models, batches, dtype=getattr(torch, dtype))
+    plan.configure(16, 3)
+    first = _snapshot(plan.run(dev))
+    torch.cuda.synchronize()
+    _check(plan, trees, host, first, dtype, n_sample=400)
+    for _ in range(2):
+        again = plan.run(dev)
+        torch.cuda.synchronize()
+        for a, b in zip(first, again):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y)
+
+
+def test_generated_multi_tree_kernel_follows_gravity():
+    """The generated kernel reads each model's gravity from the plan's
+    descriptor: after bard_model_set_gravity the next replay uses it."""
+    import torch
+    say("[gpu] generated multi-tree kernel after a gravity change")
+    trees, models, batches, host, dev = _setup(seed=3000)
+    plan = bard.Plan(models, batches)
+    plan.configure(16, 3)
+    for _ in range(3):
+        plan.run(dev)
+    torch.cuda.synchronize()
+    g_new = np.array([0.7, 2.5, -4.1])
+    for m in models:
+        m.set_gravity(g_new)
+    for _ in range(2):
+        outs = plan.run(dev)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(6)
         for k, (tree, (q, qd, qdd)) in enumerate(zip(trees, host)):
             idx = np.sort(rng.choice(q.shape[0], min(32, q.shape[0]), replace=False))
             om = OracleModel(tree.parent, tree.joint_type, tree.axis, tree.X_tree, tree.inertia, g_new)

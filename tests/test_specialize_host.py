@@ -7,6 +7,7 @@ one wave; trees past the size bound are refused."""
 
 import re
 
+import numpy as np
 import pytest
 
 import synth
@@ -105,4 +106,31 @@ def test_deep_tree_refused_for_aba():
     m = bard.Model.from_tree(synth.tree_by_name("chain64"))
     with pytest.raises(bard.BardError) as ei:
         m.specialize_aba(compile_only=True)
+    assert ei.value.status == -7
+
+
+def test_generated_multi_tree_plan_source():
+    """The plan's generated kernel (fusion 3) holds each tree's code in a
+    namespace of its own, dispatches the trees' 64-instance groups (two
+    workgroups each in the dual form) with trees of larger nv first, sizes
+    its workgroups for the widest member, and compiles for gfx950."""
+    trees = synth.multi_trees()
+    models = [bard.Model.from_tree(t) for t in trees]
+    plan = bard.Plan(models, synth.MULTI_BATCHES)
+    src = plan.specialized_source()
+    order = [int(k) for k in re.findall(r"bard_t(\d+)::run", src)]
+    assert order == sorted(range(len(trees)), key=lambda k: -trees[k].nv)
+    ends = [int(e) for e in re.findall(r"if \(blk < (\d+)LL\)", src)]
+    groups = [(B + 63) // 64 * 2 for B in synth.MULTI_BATCHES]   # dual form: two workgroups per group
+    assert ends == list(np.cumsum([groups[k] for k in order]))
+    nw = [int(w) for w in re.findall(r"static constexpr int NW = (\d+);", src)]
+    assert int(re.search(r"__launch_bounds__\((\d+)\) bard_spec_plan", src).group(1)) == 64 * max(nw)
+    for k, t in enumerate(trees):   # every torque stored once per tree
+        body = src.split(f"namespace bard_t{k} {{")[1].split(f"}}  // namespace bard_t{k}")[0]
+        assert sorted(set(int(x) for x in re.findall(r"TAU\((\d+), ", body))) == list(range(t.nv))
+    plan.specialized_source(compile_only=True)
+    # plans without all three operators have no generated kernel
+    p1 = bard.Plan(models, synth.MULTI_BATCHES, op_mask=bard.PLAN_RNEA)
+    with pytest.raises(bard.BardError) as ei:
+        p1.specialized_source()
     assert ei.value.status == -7
