@@ -450,9 +450,12 @@ def bench_specialized(torch, bard):
 
 def bench_plan(torch, bard, steps):
     """Five random trees (7, 11, 12, 18, 23 DOF; batches 512..8192 = 15,872
-    instances; RNEA + CRBA + tip Jacobians): one plan (graph replay) with the
-    schedule the autotuner picks, against the untuned default and five
-    separate chain launches."""
+    instances; RNEA + CRBA + tip Jacobians): one plan with the configuration
+    the autotuner picks (generic work-item kernel or the generated
+    multi-tree kernel), device time from graph replay, against the untuned
+    default and five separate chain launches (graph replay too).  Every run
+    reads and writes the same arrays (58 MB, within the 256 MB Infinity
+    Cache), as a captured plan run must use the io of the run before it."""
     import synth
     trees = synth.multi_trees()
     batches = synth.MULTI_BATCHES
@@ -474,15 +477,24 @@ def bench_plan(torch, bard, steps):
     plan.run(ins)
     torch.cuda.synchronize()
     n = max(50, steps // 4)
-    t_plan, k_plan = _rate(torch, [lambda: plan.run(ins)], n)
+    # device time per run from replays of a graph of 20 runs (an eager run
+    # costs tens of microseconds of Python and ctypes, more than the kernel);
+    # the eager rate beside it includes that host time
+    g_plan = time_graph(torch, lambda: [lambda: plan.run(ins)] * 20, 20)
+    t_plan, _ = _rate(torch, [lambda: plan.run(ins)], n)
     outs = [tuple(torch.empty((K, B), device="cuda") for K in (t.nv, t.nv * t.nv, 6 * t.nv * len(plan.ee(k))))
             for k, (t, B) in enumerate(zip(trees, batches))]
-    sep = [m.bind_chain(i[0], i[1], i[2], plan.ee(k), o) for k, (m, i, o) in enumerate(zip(models, ins, outs))]
-    t_sep, k_sep = _rate(torch, [lambda: [c() for c in sep]], n)
-    return {"plan5_evals_per_s": total / t_plan, "plan5_gpu_us": k_plan * 1e6,
-            "plan5_hbm_frac": nbytes / k_plan / 1e9 / HBM_PEAK_GBS, "plan5_config": plan.config,
-            "plan5_default_config": default_cfg, "plan5_default_gpu_us": k_def * 1e6,
-            "separate5_evals_per_s": total / t_sep, "separate5_gpu_us": k_sep * 1e6}
+    mk_sep = lambda: [m.bind_chain(i[0], i[1], i[2], plan.ee(k), o)
+                      for k, (m, i, o) in enumerate(zip(models, ins, outs))]
+    g_sep = time_graph(torch, lambda: mk_sep() * 4, 20) * 5
+    out = {"plan5_evals_per_s": total / g_plan, "plan5_gpu_us": g_plan * 1e6,
+           "plan5_hbm_frac": nbytes / g_plan / 1e9 / HBM_PEAK_GBS, "plan5_config": plan.config,
+           "plan5_eager_evals_per_s": total / t_plan,
+           "plan5_default_config": default_cfg, "plan5_default_eager_us": k_def * 1e6,
+           "separate5_evals_per_s": total / g_sep, "separate5_gpu_us": g_sep * 1e6}
+    if plan.config["fusion"] == 3:
+        out["plan5_generated_kernel"] = plan.specialized_info()
+    return out
 
 
 def bench_adjoints(torch, bard, steps):

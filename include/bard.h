@@ -485,25 +485,34 @@ int bard_plan_destroy(bard_plan_t plan);
  * more lanes, so a tile occupies more waves).  Fusion 0 and 1 need op_mask to
  * be one operator or all three.  A configuration whose sweep needs more than
  * 8 waves is refused by the first run with BARD_E_CAPACITY.
- * Fusion 3 (all three operators only; tile, order and lanes are ignored): the
+ * Fusion 3 (all three operators only; tile and order are ignored): the
  * model compiler emits one kernel holding every tree's model-specialised
  * chain code (as bard_model_specialize does for one model: every constant a
  * literal, one lane per instance, the dual form where a tree has limbs),
  * compiled with hipRTC on the plan's first run in this configuration (which
  * may take seconds); its workgroups take the trees' 64-instance groups,
- * trees of larger nv first.  bard_plan_autotune always includes it when the
- * plan has all three operators and does not count its compilation against
+ * trees of larger nv first; each tree is split over at most 8 waves (lanes
+ * 0) or 4 (lanes 1: narrower workgroups, two of which fit a CU where one of
+ * 8 waves did).  bard_plan_autotune always includes both when the plan has
+ * all three operators and does not count their compilation against
  * budget_ms. */
 int bard_plan_configure(bard_plan_t plan, int32_t tile, int32_t fusion, int32_t order, int32_t lanes);
 /* Current configuration; from_cache = 1 if it came from the tuning cache. */
 int bard_plan_get_config(bard_plan_t plan, int32_t* tile, int32_t* fusion, int32_t* order, int32_t* lanes,
                          int32_t* from_cache);
-/* The generated source of the plan's fusion-3 kernel (NUL-terminated into
- * buf when cap > 0; *len its length without the NUL); compile_only = 1 also
- * compiles it for gfx950 with hipRTC (no GPU needed) and reports a failure as
- * BARD_E_DEVICE.  Errors: BARD_E_ARG, BARD_E_UNSUPPORTED (op_mask not all
+/* The generated source of the plan's fusion-3 kernel for its current lanes
+ * setting (NUL-terminated into buf when cap > 0; *len its length without
+ * the NUL); compile_only = 1 also compiles it for gfx950 with hipRTC (no GPU
+ * needed) and reports a failure as BARD_E_DEVICE.  Errors: BARD_E_ARG, BARD_E_UNSUPPORTED (op_mask not all
  * three operators), BARD_E_DEVICE. */
 int bard_plan_specialized_source(bard_plan_t plan, int32_t compile_only, char* buf, int64_t cap, int64_t* len);
+/* Resources of the plan's fusion-3 kernel once built (any argument may be
+ * NULL): registers per lane, scratch bytes per lane, waves per workgroup,
+ * workgroups per launch and the seconds its generation and compilation took
+ * (0 when the code object came from an earlier plan with the same source).
+ * Errors: BARD_E_ARG, BARD_E_STATE (not built yet). */
+int bard_plan_specialized_info(bard_plan_t plan, int32_t* vgprs, int32_t* scratch_bytes, int32_t* waves,
+                               int64_t* workgroups, double* compile_s);
 /* Tip end effectors of model `model_index` (ee_body: room for 4 entries). */
 int bard_plan_ee(bard_plan_t plan, int32_t model_index, int32_t* n_ee, int32_t* ee_body);
 

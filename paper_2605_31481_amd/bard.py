@@ -134,6 +134,9 @@ bard_plan_destroy = _sig("bard_plan_destroy", [_vp])
 bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32, _i32])
 bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
 bard_plan_ee = _sig("bard_plan_ee", [_vp, _i32, _c_i32p, _c_i32p])
+bard_plan_specialized_info = _sig("bard_plan_specialized_info", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                                                 ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                                                 ctypes.POINTER(ctypes.c_double)])
 bard_plan_specialized_source = _sig("bard_plan_specialized_source", [_vp, _i32, ctypes.c_char_p, _i64,
                                                                      ctypes.POINTER(_i64)])
 
@@ -869,6 +872,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def specialized_info(self) -> dict:
+        """Resources of the plan's generated multi-tree kernel (built by its
+        first run in fusion 3)."""
+        r, sc, w = _i32(), _i32(), _i32()
+        g, c = _i64(), ctypes.c_double()
+        _check(bard_plan_specialized_info(self._h, ctypes.byref(r), ctypes.byref(sc), ctypes.byref(w), ctypes.byref(g),
+                                          ctypes.byref(c)), "bard_plan_specialized_info")
+        return {"vgprs": r.value, "scratch_bytes": sc.value, "waves": w.value, "workgroups": g.value,
+                "compile_s": c.value}
 
     def specialized_source(self, compile_only: bool = False) -> str:
         """Source of the plan's generated multi-tree kernel (fusion 3);

@@ -48,13 +48,15 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
 // Source text of the specialised forward-dynamics (ABA) kernel of a tree.
 std::string spec_aba_source(const bard_model* m, bool fp64, bool split);
 // Multi-tree plan kernel (bard_spec_plan): every model's specialised chain
-// code in one launch over [K][batch] arrays; *waves per workgroup and
-// *blocks of the launch.  spec_plan_build compiles and loads it on the
-// current device (sk->mod, sk->fn; the caller unloads sk->mod).
+// code in one launch over [K][batch] arrays, each tree split over at most
+// max_waves waves; *waves per workgroup and *blocks of the launch.
+// spec_plan_build compiles and loads it on the current device (sk->mod,
+// sk->fn; the caller unloads sk->mod).
 std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
-                             const std::vector<int64_t>& batch, bool fp64, int* waves, int64_t* blocks);
+                             const std::vector<int64_t>& batch, bool fp64, int max_waves, int* waves,
+                             int64_t* blocks);
 int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
-                    const std::vector<int64_t>& batch, bool fp64, SpecKernel* sk, int64_t* blocks);
+                    const std::vector<int64_t>& batch, bool fp64, int max_waves, SpecKernel* sk, int64_t* blocks);
 // The per-model argument record of the multi-tree kernel (its PlanIO).
 template <class Real>
 struct SpecPlanIO {

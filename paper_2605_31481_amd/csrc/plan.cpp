@@ -110,6 +110,7 @@ struct bard_plan {
   // FUSE_SPEC: the generated kernel (loaded on `device`) and its launch size
   SpecKernel spk;
   int64_t spk_blocks = 0;
+  int spk_max_waves = 0;  // the wave cap spk was generated for
 };
 
 namespace {
@@ -217,14 +218,25 @@ int plan_host_state(bard_plan* p) {
   return BARD_OK;
 }
 
-// FUSE_SPEC: generate and compile the plan's kernel once per plan (on its
-// device); its descriptor holds one SpecPlanIO per model.
+// FUSE_SPEC: waves per tree at most 8, or 4 with cfg.lanes = 1 (two
+// workgroups of a wide tree then fit a CU where one of 8 waves did).
+int spec_plan_waves(const PlanConfig& c) { return c.lanes ? 4 : 8; }
+
+// FUSE_SPEC: generate and compile the plan's kernel once per plan and wave
+// cap (on its device); its descriptor holds one SpecPlanIO per model.
 template <class Real>
 int prepare_spec(bard_plan* p) {
+  const int mw = spec_plan_waves(p->cfg);
+  if (p->spk.fn && p->spk_max_waves != mw) {
+    if (hipDeviceSynchronize() != hipSuccess) return fail(BARD_E_DEVICE, "device error before a kernel change");
+    (void)hipModuleUnload((hipModule_t)p->spk.mod);
+    p->spk = SpecKernel();
+  }
   if (!p->spk.fn) {
     std::vector<bard_model*> ms(p->models.begin(), p->models.end());
-    int rc = spec_plan_build(ms, p->ee, p->batch, sizeof(Real) == 8, &p->spk, &p->spk_blocks);
+    int rc = spec_plan_build(ms, p->ee, p->batch, sizeof(Real) == 8, mw, &p->spk, &p->spk_blocks);
     if (rc) return rc;
+    p->spk_max_waves = mw;
   }
   const int nm = (int)p->models.size();
   p->args_bytes = nm * sizeof(SpecPlanIO<Real>);
@@ -671,6 +683,7 @@ int bard_plan_autotune(bard_plan_t p, void* stream, int32_t budget_ms) {
   // its compilation is not timed), then the generic configurations
   std::vector<PlanConfig> cands;
   cands.push_back(PlanConfig{4, FUSE_SPEC, ORDER_LONGEST_FIRST, 0});
+  cands.push_back(PlanConfig{4, FUSE_SPEC, ORDER_LONGEST_FIRST, 1});
   for (int ln = 0; ln <= 1; ++ln)
     for (int lt = 3; lt <= 5; ++lt)
       for (int fu = FUSE_ALL; fu <= FUSE_PER_OP; ++fu)
@@ -724,7 +737,8 @@ int bard_plan_specialized_source(bard_plan_t p, int32_t compile_only, char* buf,
   std::vector<bard_model*> ms(p->models.begin(), p->models.end());
   int waves = 1;
   int64_t blocks = 0;
-  const std::string src = spec_plan_source(ms, p->ee, p->batch, p->dtype == BARD_F64, &waves, &blocks);
+  const std::string src =
+      spec_plan_source(ms, p->ee, p->batch, p->dtype == BARD_F64, spec_plan_waves(p->cfg), &waves, &blocks);
   *len = (int64_t)src.size();
   if (buf && cap > 0) {
     const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
@@ -737,6 +751,18 @@ int bard_plan_specialized_source(bard_plan_t p, int32_t compile_only, char* buf,
     const int rc = spec_compile(src, &code, &log);
     if (rc) return fail(rc, "hipRTC compile of the multi-tree kernel failed: " + log.substr(0, 2000));
   }
+  return BARD_OK;
+}
+
+int bard_plan_specialized_info(bard_plan_t p, int32_t* vgprs, int32_t* scratch_bytes, int32_t* waves,
+                               int64_t* workgroups, double* compile_s) {
+  if (!p) return fail(BARD_E_ARG, "plan is NULL");
+  if (!p->spk.fn) return fail(BARD_E_STATE, "the plan's generated kernel is not built (run it in fusion 3 first)");
+  if (vgprs) *vgprs = p->spk.vgprs;
+  if (scratch_bytes) *scratch_bytes = p->spk.scratch;
+  if (waves) *waves = p->spk.waves;
+  if (workgroups) *workgroups = p->spk_blocks;
+  if (compile_s) *compile_s = p->spk.compile_s;
   return BARD_OK;
 }
 

@@ -1318,7 +1318,8 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
 }
 
 std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
-                             const std::vector<int64_t>& batch, bool fp64, int* waves, int64_t* blocks) {
+                             const std::vector<int64_t>& batch, bool fp64, int max_waves, int* waves,
+                             int64_t* blocks) {
   std::ostringstream o;
   const int n = (int)ms.size();
   o << "// generated: fused RNEA + CRBA + Jacobian of " << n << " trees in one launch ("
@@ -1337,7 +1338,7 @@ std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vect
   for (int k : order) {
     if (batch[k] <= 0) continue;
     const int form = spec_form_ok(ms[k], fp64, 2) ? 2 : 0;
-    Emitter e(ms[k], ee[k], 0, fp64, form);
+    Emitter e(ms[k], ee[k], 0, fp64, form, max_waves);
     o << e.member(k, batch[k]);
     nwb = std::max(nwb, e.waves());
     xmax = std::max(xmax, e.xch_values());
@@ -1517,10 +1518,10 @@ int spec_prepare_aba(bard_model* m, DeviceCopy* dc, int dtype, bool load, SpecKe
 }
 
 int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
-                    const std::vector<int64_t>& batch, bool fp64, SpecKernel* sk, int64_t* blocks) {
+                    const std::vector<int64_t>& batch, bool fp64, int max_waves, SpecKernel* sk, int64_t* blocks) {
   const auto t0 = std::chrono::steady_clock::now();
   int waves = 1;
-  const std::string src = spec_plan_source(ms, ee, batch, fp64, &waves, blocks);
+  const std::string src = spec_plan_source(ms, ee, batch, fp64, max_waves, &waves, blocks);
   SpecKernel out;
   out.waves = waves;
   {
@@ -1532,6 +1533,7 @@ int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::v
     auto it = done.find(src);
     if (it != done.end()) {
       out.code = it->second;
+      out.compile_s = -1.0;  // reused
     } else {
       std::string log;
       const int rc = spec_compile(src, &out.code, &log);
@@ -1559,7 +1561,7 @@ int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::v
     (void)hipGetLastError();
   out.vgprs = regs;
   out.scratch = local;
-  out.compile_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  out.compile_s = out.compile_s < 0 ? 0.0 : std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *sk = std::move(out);
   return BARD_OK;
 }

@@ -43,7 +43,7 @@ def _check(plan, trees, host, outs, dtype, n_sample=96, seed=0):
 
 
 CONFIGS = [(16, 0, 0, 0), (8, 1, 0, 0), (32, 2, 1, 0), (16, 2, 0, 0), (8, 0, 1, 0), (32, 0, 0, 0), (16, 0, 0, 1),
-           (8, 2, 0, 1), (16, 3, 0, 0)]
+           (8, 2, 0, 1), (16, 3, 0, 0), (16, 3, 0, 1)]
 
 
 @pytest.mark.parametrize("tile,fusion,order,lanes", CONFIGS)
