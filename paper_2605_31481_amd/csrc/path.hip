@@ -96,12 +96,30 @@ __global__ void __launch_bounds__(kPathThreads) path_kernel(DevModel dm, PathArg
   const I4* meta = reinterpret_cast<const I4*>(img + tl.meta);
   const int64_t bc = live ? b : a.B - 1;
   const Real* qb = a.q + bc * a.sq_b;
-  for (int k = 0; k < a.nqp; ++k) qs[k * kPathThreads + tid] = qb[(int64_t)a.qsrc[k] * a.sq_k];
-  for (int i = tid; i < a.len * kPathCst; i += kPathThreads) {
-    const int s = i / kPathCst;
-    cs[i] = cst[a.body[s] * CST + (i - s * kPathCst)];
+  // Loads in batches of kBatch issued before their LDS stores: a loop of
+  // load-then-store waits one memory round trip per element.
+  constexpr int kBatch = 16;
+  for (int k0 = 0; k0 < a.nqp; k0 += kBatch) {
+    Real v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = qb[(int64_t)a.qsrc[min(k0 + j, a.nqp - 1)] * a.sq_k];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (k0 + j < a.nqp) qs[(k0 + j) * kPathThreads + tid] = v[j];
   }
-  for (int s = tid; s < a.len; s += kPathThreads) jts[s] = meta[a.body[s]].y;
+  const int ncs = a.len * kPathCst;
+  for (int i0 = tid; i0 < ncs; i0 += kBatch * kPathThreads) {
+    Real v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int i = min(i0 + j * kPathThreads, ncs - 1), s = i / kPathCst;
+      v[j] = cst[a.body[s] * CST + (i - s * kPathCst)];
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j)
+      if (i0 + j * kPathThreads < ncs) cs[i0 + j * kPathThreads] = v[j];
+  }
+  if (tid < a.len) jts[tid] = meta[a.body[tid]].y;
   __syncthreads();
 
   Real pe[3] = {Real(0), Real(0), Real(0)};
