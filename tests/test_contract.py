@@ -109,3 +109,34 @@ def test_per_body_term_sums_are_not_an_attainable_scale():
     assert (err / (atol + rtol * np.maximum(np.abs(rM), S))).max() > 1.0
     # the contract's scale for M bounds every per-body term sum from above
     assert (mass_scales(rM.reshape(B, tree.nv, tree.nv)) >= S * (1 - 1e-12)).all()
+
+
+@pytest.mark.parametrize("name,B", [("quadruped_spine", 300), ("humanoid_large", 129)])
+def test_rounding_of_the_aba_adjoint_product_alone(name, B):
+    """The FP32 ABA adjoint's second stage is q_bar = D^T c with D = dtau/dq
+    and c = -M^-1 qdd_bar.  On the instances of its GPU test, the exact D and
+    c rounded to single precision and the product summed in single precision
+    stay within the normwise bound relative to the result: rounding of the
+    product alone does not need the wider |D|^T |c| scale the GPU test uses;
+    what exceeds the normwise bound there comes from the entries of D, which
+    the adjoint sweeps form in single precision."""
+    tree = synth.tree_by_name(name)
+    om = OracleModel.from_tree(tree)
+    q, qd, qdd0 = inputs(tree, B, 3700, "float32")
+    tau = synth.to_fp32_grid(om.rnea(q, qd, qdd0))
+    qdd = synth.to_fp32_grid(om.aba(q, qd, tau))
+    cot = synth.to_fp32_grid(np.random.default_rng(3701).standard_normal((B, tree.nv)))
+    c = -np.linalg.solve(om.crba(q), cot[..., None])[..., 0]
+    D = np.zeros((B, tree.nv, om.nq))
+    for i in range(tree.nv):
+        e = np.zeros((B, tree.nv))
+        e[:, i] = 1.0
+        D[:, i, :] = om.rnea_vjp(q, qd, qdd, e)[0]
+    g = np.einsum("bi,biq->bq", c, D)
+    terms = D.astype(np.float32) * c.astype(np.float32)[:, :, None]
+    g32 = np.zeros((B, om.nq), np.float32)
+    for i in range(tree.nv):
+        g32 = (g32 + terms[:, i, :]).astype(np.float32)
+    rtol, atol = TOL["float32"]
+    err = np.abs(g32 - g).max(axis=1)
+    assert (err / (atol + rtol * np.abs(g).max(axis=1))).max() < 0.5
