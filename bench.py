@@ -717,7 +717,9 @@ def main():
               "split": f"bard_spec_chain (specialised, split over {m.specialized_info(ee)['waves']} waves)",
               "whole": "bard_spec_chain (specialised, whole tree per wave)",
               "dual": f"bard_spec_chain (specialised, split over {m.specialized_info(ee, form='dual')['waves']} waves, "
-                      "torques and mass matrix + Jacobians in two workgroups)"}[route]
+                      "torques and mass matrix + Jacobians in two workgroups)",
+              "triple": f"bard_spec_chain (specialised, split over {m.specialized_info(ee, form='triple')['waves']} "
+                        "waves, torques, mass matrix and Jacobians in three workgroups)"}[route]
     log(f"[bench] autotune {time.perf_counter() - t0:.1f} s: tiers {tiers}, first specialised batch {first}; "
         f"B={B} runs {kernel}")
     def make_calls():

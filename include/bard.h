@@ -140,7 +140,7 @@ int bard_model_destroy(bard_model_t model);
  * tree: the model compiler emits HIP source in which every model constant is
  * a literal and the traversal is unrolled body by body (the generated,
  * model-specific kernels Sec. 2 cites as prior art), and hipRTC compiles it
- * for gfx950 at run time.  Two forms, 64 instances per workgroup, one lane
+ * for gfx950 at run time.  Four forms, 64 instances per workgroup, one lane
  * per instance:
  *   split (default): a tree with branches is cut into its trunk (the bodies
  *     with two or more children and their ancestors) and limbs (the chains
@@ -156,6 +156,9 @@ int bard_model_destroy(bard_model_t model);
  *     needs, so the instructions per wave drop and twice the compute units
  *     take part; for small batches.  Refused (BARD_E_UNSUPPORTED) when no
  *     split plan fits in LDS.
+ *   triple (BARD_SPEC_TRIPLE): as dual with three workgroups per 64
+ *     instances: torques, mass matrix, Jacobians (the last needs only the
+ *     kinematics and has no barrier).  Refused as dual is.
  *
  * specialize: compiles the kernel of one form for (dtype, end-effector set
  * ee_body [n_ee, host], frame) and loads it on the current device (once; later
@@ -165,8 +168,8 @@ int bard_model_destroy(bard_model_t model);
  * agree with the generic kernel's within the tolerance contract, not bitwise
  * (different summation order).  BARD_SPEC_COMPILE_ONLY -- generate and
  * compile only, needing no GPU, and keep nothing (a check that the
- * generator's output compiles).  BARD_SPEC_WHOLE, BARD_SPEC_DUAL -- the
- * whole or the dual form (at most one of them).  Uploads
+ * generator's output compiles).  BARD_SPEC_WHOLE, BARD_SPEC_DUAL,
+ * BARD_SPEC_TRIPLE -- that form (at most one of them).  Uploads
  * the model's tables as bard_model_upload does; synchronous; call it outside
  * any graph capture.  The kernels are unloaded by bard_model_destroy.
  * Errors: BARD_E_ARG, BARD_E_DEVICE (a hipRTC compile or module load failed;
@@ -180,10 +183,11 @@ int bard_model_destroy(bard_model_t model);
 #define BARD_SPEC_COMPILE_ONLY 2
 #define BARD_SPEC_WHOLE 4
 #define BARD_SPEC_DUAL 8
+#define BARD_SPEC_TRIPLE 16
 int bard_model_specialize(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                           bard_frame frame, int32_t flags);
 /* Resources of a loaded specialised kernel (form by flags: 0,
- * BARD_SPEC_WHOLE or BARD_SPEC_DUAL) on the current device: registers per lane, scratch bytes
+ * BARD_SPEC_WHOLE, BARD_SPEC_DUAL or BARD_SPEC_TRIPLE) on the current device: registers per lane, scratch bytes
  * per lane (spills), hipRTC compile time, the batch tiers routed to it (bit k
  * for tier k: [0, 4096), [4096, 16384), [16384, 65536), [65536, inf)) and
  * waves per workgroup.  Any output may be NULL.  BARD_E_STATE if none is
@@ -192,8 +196,8 @@ int bard_model_specialized_info(bard_model_t model, bard_dtype dtype, int32_t n_
                                 bard_frame frame, int32_t flags, int32_t* vgprs, int32_t* scratch_bytes,
                                 double* compile_seconds, int32_t* routed_tiers, int32_t* waves);
 /* Choose between the generic chain kernel and the specialised forms by
- * timing: compiles and loads the forms if needed (split and dual; whole too
- * when the tree splits over several waves), times every candidate on scratch arrays (allocated here and
+ * timing: compiles and loads the forms if needed (split, dual and triple;
+ * whole too when the tree splits over several waves), times every candidate on scratch arrays (allocated here and
  * freed before returning) at B = 1024, 4096, 16384 and 65536 on `stream`, and
  * routes each batch tier (as in bard_model_specialized_info; the tier of
  * 1024 covers every batch below 4096) to the fastest.  *min_batch receives
@@ -203,9 +207,8 @@ int bard_model_specialized_info(bard_model_t model, bard_dtype dtype, int32_t n_
  * bard_model_specialize, BARD_E_NOMEM, BARD_E_CAPTURE. */
 int bard_chain_autotune(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                         bard_frame frame, void* stream, int64_t* min_batch);
-/* The generated source text of one form (flags: 0, BARD_SPEC_WHOLE or
- * BARD_SPEC_DUAL;
- * NUL-terminated, truncated to cap - 1 bytes); *len receives its full length.
+/* The generated source text of one form (flags: 0, BARD_SPEC_WHOLE,
+ * BARD_SPEC_DUAL or BARD_SPEC_TRIPLE; NUL-terminated, truncated to cap - 1 bytes); *len receives its full length.
  * Host only. */
 int bard_model_specialized_source(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                                   bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len);

@@ -44,14 +44,14 @@ WORLD, LOCAL_WORLD_ALIGNED = 0, 1
 E_CAPTURE = -8  # bard_status of a call that would allocate under graph capture
 E_STATE = -9  # bard_status of a call that allocates nothing and found the model not uploaded
 UPLOAD_ADJOINT = 1
-SPEC_ROUTE, SPEC_COMPILE_ONLY, SPEC_WHOLE, SPEC_DUAL = 1, 2, 4, 8
-SPEC_FORMS = ("split", "whole", "dual")
+SPEC_ROUTE, SPEC_COMPILE_ONLY, SPEC_WHOLE, SPEC_DUAL, SPEC_TRIPLE = 1, 2, 4, 8, 16
+SPEC_FORMS = ("split", "whole", "dual", "triple")
 
 
 def _spec_form_flag(form: str) -> int:
     if form not in SPEC_FORMS:
         raise ValueError(f"form must be one of {SPEC_FORMS}, got {form!r}")
-    return {"split": 0, "whole": SPEC_WHOLE, "dual": SPEC_DUAL}[form]
+    return {"split": 0, "whole": SPEC_WHOLE, "dual": SPEC_DUAL, "triple": SPEC_TRIPLE}[form]
 # batch tiers of the specialised-kernel routing (lower bounds)
 SPEC_TIERS = (0, 4096, 16384, 65536)
 # workspace tiers (bard_ws_set_policy bits); TIER_RESULTS is the binding's own

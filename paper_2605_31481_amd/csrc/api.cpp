@@ -694,16 +694,25 @@ static void spec_refresh_route(bard_model* m) {
   m->spec_route.store(any);
 }
 
-static int spec_form(int32_t flags) { return (flags & BARD_SPEC_WHOLE) ? 1 : (flags & BARD_SPEC_DUAL) ? 2 : 0; }
+static int spec_form(int32_t flags) {
+  return (flags & BARD_SPEC_WHOLE) ? 1 : (flags & BARD_SPEC_DUAL) ? 2 : (flags & BARD_SPEC_TRIPLE) ? 3 : 0;
+}
+
+// flags: only the form bits (and `extra`), at most one form
+static bool spec_flags_ok(int32_t flags, int32_t extra) {
+  const int32_t forms = BARD_SPEC_WHOLE | BARD_SPEC_DUAL | BARD_SPEC_TRIPLE;
+  if (flags & ~(forms | extra)) return false;
+  const int32_t f = flags & forms;
+  return (f & (f - 1)) == 0;
+}
 
 int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body, bard_frame frame,
                           int32_t flags) {
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if (flags & ~(BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY | BARD_SPEC_WHOLE | BARD_SPEC_DUAL))
-    return fail(BARD_E_ARG, "unknown flags");
-  if ((flags & BARD_SPEC_WHOLE) && (flags & BARD_SPEC_DUAL)) return fail(BARD_E_ARG, "one form at a time");
+  if (!spec_flags_ok(flags, BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY))
+    return fail(BARD_E_ARG, "unknown flags, or more than one form");
   // The generated code grows with the ancestor walks of the mass-matrix
   // columns (one step per dof and ancestor body); past this size the compile
   // time and register pressure outgrow what specialisation gains.
@@ -716,7 +725,7 @@ int bard_model_specialize(bard_model_t m, bard_dtype dtype, int32_t n_ee, const 
                                         "serves it");
   const int form = spec_form(flags);
   if (!spec_form_ok(m, dtype == BARD_F64, form))
-    return fail(BARD_E_UNSUPPORTED, "the dual form needs a split plan whose limb sums fit in LDS");
+    return fail(BARD_E_UNSUPPORTED, "the dual and triple forms need a split plan whose limb sums fit in LDS");
   if (flags & BARD_SPEC_COMPILE_ONLY) {
     std::vector<char> code;
     std::string log;
@@ -749,8 +758,7 @@ int bard_model_specialized_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, 
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if ((flags & ~(BARD_SPEC_WHOLE | BARD_SPEC_DUAL)) || (flags & BARD_SPEC_WHOLE && flags & BARD_SPEC_DUAL))
-    return fail(BARD_E_ARG, "unknown flags");
+  if (!spec_flags_ok(flags, 0)) return fail(BARD_E_ARG, "unknown flags, or more than one form");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
   const std::string key = spec_key((int)dtype, (int)frame, ee, spec_form(flags));
@@ -777,10 +785,11 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, st))) return rc;
   // the candidates: the split form, the whole form when the tree splits
-  // over several waves (else it is the same code), the dual form when the
-  // tree has a plan for it
-  bool use[kSpecForms] = {true, spec_waves(m, dtype == BARD_F64, 0) > 1, spec_form_ok(m, dtype == BARD_F64, 2)};
-  SpecKernel* sk[kSpecForms] = {nullptr, nullptr, nullptr};
+  // over several waves (else it is the same code), the dual and triple
+  // forms when the tree has a plan for them
+  bool use[kSpecForms] = {true, spec_waves(m, dtype == BARD_F64, 0) > 1, spec_form_ok(m, dtype == BARD_F64, 2),
+                          spec_form_ok(m, dtype == BARD_F64, 3)};
+  SpecKernel* sk[kSpecForms] = {};
   for (int f = 0; f < kSpecForms; ++f)
     if (use[f] && (rc = spec_prepare(m, dc, (int)dtype, (int)frame, ee, f, true, &sk[f]))) return rc;
   // Scratch arrays for the largest batch tried, inputs filled with 0.1 (the
@@ -831,7 +840,7 @@ int bard_chain_autotune(bard_model_t m, bard_dtype dtype, int32_t n_ee, const in
   (void)hipFree(buf);
   if (rc) return rc;
   // each tier to the fastest of the generic kernel and the forms
-  int tiers[kSpecForms] = {0, 0, 0};
+  int tiers[kSpecForms] = {};
   int64_t first = -1;
   for (int k = 0; k < kSpecTiers; ++k) {
     int best = 0;
@@ -863,10 +872,9 @@ int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee
   std::vector<int> ee;
   int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
   if (rc) return rc;
-  if ((flags & ~(BARD_SPEC_WHOLE | BARD_SPEC_DUAL)) || (flags & BARD_SPEC_WHOLE && flags & BARD_SPEC_DUAL))
-    return fail(BARD_E_ARG, "unknown flags");
+  if (!spec_flags_ok(flags, 0)) return fail(BARD_E_ARG, "unknown flags, or more than one form");
   if (!spec_form_ok(m, dtype == BARD_F64, spec_form(flags)))
-    return fail(BARD_E_UNSUPPORTED, "the dual form needs a split plan whose limb sums fit in LDS");
+    return fail(BARD_E_UNSUPPORTED, "the dual and triple forms need a split plan whose limb sums fit in LDS");
   const std::string src = spec_chain_source(m, ee, (int)frame, dtype == BARD_F64, spec_form(flags));
   if (len) *len = (int64_t)src.size();
   if (buf && cap > 0) {

@@ -41,8 +41,9 @@ constexpr int64_t kSpecTierBatch[kSpecTiers] = {1024, 4096, 16384, 65536};
 int spec_tier(int64_t B);
 // Forms of a specialised kernel: 0 split over waves by limbs, 1 one wave
 // over the whole tree, 2 split and, per 64 instances, two workgroups (the
-// torques in one, the mass matrix and Jacobians in the other).
-constexpr int kSpecForms = 3;
+// torques in one, the mass matrix and Jacobians in the other), 3 split and
+// three workgroups (torques, mass matrix, Jacobians).
+constexpr int kSpecForms = 4;
 // Source text of the kernel for one (end-effector set, frame, precision, form).
 std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form);
 // Source text of the specialised forward-dynamics (ABA) kernel of a tree.

@@ -141,8 +141,8 @@ class Emitter {
  public:
   Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form,
           int max_waves = SplitPlan::kMaxWaves)
-      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), dual_(form == 2), pl_(make_plan(m, form == 1, fp64, max_waves)),
-        split_(pl_.split || dual_) {
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), parts_(form == 2 ? 2 : form == 3 ? 3 : 1),
+        dual_(parts_ > 1), pl_(make_plan(m, form == 1, fp64, max_waves)), split_(pl_.split || dual_) {
     trunk_ = pl_.trunk;
     slot_body_ = pl_.slot_body;
   }
@@ -182,7 +182,7 @@ class Emitter {
     emit_zero_tables();
     const int nw = pl_.waves;
     o_ << "static constexpr int NW = " << nw << ";  // waves per workgroup, 64 instances\n";
-    o_ << "static constexpr int WG_PER_GROUP = " << (dual_ ? 2 : 1) << ";  // workgroups per 64 instances\n";
+    o_ << "static constexpr int WG_PER_GROUP = " << parts_ << ";  // workgroups per 64 instances\n";
     o_ << "extern \"C\" __global__ void __launch_bounds__(" << 64 * nw << ") bard_spec_chain(\n"
           "    const Real* __restrict__ q, const Real* __restrict__ qd, const Real* __restrict__ qdd,\n"
           "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
@@ -240,7 +240,7 @@ class Emitter {
   }
 
   int waves() const { return pl_.waves; }
-  int wg_per_group() const { return dual_ ? 2 : 1; }
+  int wg_per_group() const { return parts_; }
   // LDS values of the hand-over area (trunk slots x 16 x 64 lanes)
   int xch_values() const { return split_ ? (int)slot_body_.size() * 16 * 64 : 0; }
 
@@ -263,31 +263,51 @@ class Emitter {
     // repeat the last instance (the same values to the same addresses).
     o_ << "  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);\n"
           "  const int lane = (int)threadIdx.x & 63;\n";
-    if (dual_)
+    if (parts_ == 2)
       o_ << "  const int part = (int)" << blk_ << " & 1;  // 0: torques, 1: mass matrix and Jacobians\n"
          << "  long long b = ((long long)" << blk_ << " >> 1) * 64 + lane;\n";
+    else if (parts_ == 3)
+      o_ << "  const int part = (int)((long long)" << blk_ << " % 3);  // 0: torques, 1: mass matrix, 2: Jacobians\n"
+         << "  long long b = ((long long)" << blk_ << " / 3) * 64 + lane;\n";
     else
       o_ << "  long long b = (long long)" << blk_ << " * 64 + lane;\n";
     o_ << "  if (b > B - 1) b = B - 1;\n";
     pointers();
     if (!slot_body_.empty() && !member_) o_ << "  __shared__ Real xch_[" << slot_body_.size() * 16 * 64 << "];\n";
-    if (dual_) {
+    if (parts_ == 2) {
       o_ << "  if (part == 0) {\n";
-      do_rnea_ = true;
-      do_crba_ = false;
+      set_parts(true, false, false);
       split_body();
       o_ << "  } else {\n";
-      do_rnea_ = false;
-      do_crba_ = true;
+      set_parts(false, true, true);
       split_body();
       o_ << "  }\n";
-      do_rnea_ = do_crba_ = true;
+      set_parts(true, true, true);
+    } else if (parts_ == 3) {
+      o_ << "  if (part == 0) {\n";
+      set_parts(true, false, false);
+      split_body();
+      o_ << "  } else if (part == 1) {\n";
+      set_parts(false, true, false);
+      split_body();
+      o_ << "  } else {\n";
+      set_parts(false, false, true);
+      split_body();
+      o_ << "  }\n";
+      set_parts(true, true, true);
     } else {
       split_body();
     }
   }
 
-  // The workgroup's code for the parts selected by do_rnea_ / do_crba_: the
+  void set_parts(bool rnea, bool crba, bool jac) {
+    do_rnea_ = rnea;
+    do_crba_ = crba;
+    do_jac_ = jac;
+  }
+
+  // The workgroup's code for the parts selected by do_rnea_ / do_crba_ /
+  // do_jac_: the
   // waves' branches (loads, trunk kinematics, limbs), one barrier, the
   // trunk's sums in the merging wave.  The trunk's state lives at the scope
   // of this code (the merging wave reads it after the barrier); each wave's
@@ -298,8 +318,8 @@ class Emitter {
     o_ << "  {\n";
     // the lanes' structural-zero stores (when no extra workgroups write
     // them) go with the part that stores little else: the torques' in the
-    // dual form
-    if (dual_ ? do_rnea_ : do_crba_) emit_zero_stores();
+    // dual form, the Jacobians' in the triple form
+    if (parts_ == 1 || (parts_ == 2 && do_rnea_) || (parts_ == 3 && !do_rnea_ && !do_crba_)) emit_zero_stores();
     std::vector<int> tb;
     bool any_trunk = false;
     for (int i = 0; i < m_->n; ++i)
@@ -322,13 +342,13 @@ class Emitter {
       if (w == merge) {
         for (int i = 0; i < m_->n; ++i)
           if (trunk_[i]) body_force(i, false);
-        if (do_crba_)
+        if (do_jac_)
           for (size_t e = 0; e < ee_.size(); ++e)
             if (trunk_[ee_[e]]) jacobian((int)e);
       }
       o_ << "  }\n";
     }
-    if (any_trunk) {
+    if (any_trunk && (do_rnea_ || do_crba_)) {
       o_ << "  __syncthreads();\n  if (wave == " << merge << ") {\n";
       for (int i = m_->n - 1; i >= 0; --i)
         if (trunk_[i]) backward(i);
@@ -376,11 +396,12 @@ class Emitter {
     o_ << "  {\n";
     for (int i : ch) {
       forward(i);
-      if (do_crba_)
+      if (do_jac_)
         for (size_t e = 0; e < ee_.size(); ++e)
           if (ee_[e] == i) jacobian((int)e);
     }
-    for (auto it = ch.rbegin(); it != ch.rend(); ++it) backward(*it);
+    if (do_rnea_ || do_crba_)
+      for (auto it = ch.rbegin(); it != ch.rend(); ++it) backward(*it);
     const int sl = pl_.limb_slot[l], r = ch[0];
     if (sl >= 0) {
       const char* op = pl_.limb_first[l] ? " = " : " += ";
@@ -403,8 +424,9 @@ class Emitter {
   std::vector<int> ee_;
   int frame_;
   bool fp64_;
-  bool dual_;        // two workgroups per 64 instances: RNEA in one, CRBA and Jacobians in the other
-  bool do_rnea_ = true, do_crba_ = true;  // parts of the output the code being emitted computes
+  int parts_;        // workgroups per 64 instances: 1; 2 (RNEA | CRBA + Jacobians); 3 (RNEA | CRBA | Jacobians)
+  bool dual_;        // parts_ > 1
+  bool do_rnea_ = true, do_crba_ = true, do_jac_ = true;  // parts of the output the code being emitted computes
   SplitPlan pl_;
   bool split_;
   std::vector<char> trunk_;
@@ -633,6 +655,7 @@ class Emitter {
   // (declared here, or beforehand in an outer scope)
   void body_force(int i, bool declare) {
     if (declare) o_ << "  Real " << v("I", i) << "[10], " << v("f", i) << "[6];\n";
+    if (!do_rnea_ && !do_crba_) return;  // the Jacobians' part needs only poses
 
     // [m, R h, R Ibar R^T] about the body origin, world axes; the constant
     // parameters as literals, zero ones left out
@@ -1370,7 +1393,7 @@ int spec_aba_waves(const bard_model* m, bool fp64, bool split) { return AbaEmitt
 int spec_waves(const bard_model* m, bool fp64, int form) { return make_plan(m, form == 1, fp64).waves; }
 
 bool spec_form_ok(const bard_model* m, bool fp64, int form) {
-  return form != 2 || make_plan(m, false, fp64).split;
+  return (form != 2 && form != 3) || make_plan(m, false, fp64).split;
 }
 
 
@@ -1594,7 +1617,7 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   Real g0 = (Real)g[0], g1 = (Real)g[1], g2 = (Real)g[2];
   const Real *q = a.q, *qd = a.qd, *qdd = a.qdd;
   Real *tau = a.tau, *M = a.M, *J = a.J;
-  const int64_t main = (a.B + 63) / 64 * (sk->form == 2 ? 2 : 1);
+  const int64_t main = (a.B + 63) / 64 * (sk->form == 2 ? 2 : sk->form == 3 ? 3 : 1);
   // Structural zeros: when every zero row is a run of B contiguous, 16-byte
   // aligned values (instance-minor M and J) and the computing workgroups fill
   // at most a third of the device's wave slots, extra workgroups of the same

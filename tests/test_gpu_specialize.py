@@ -33,8 +33,13 @@ CASES = [("chain7", "float32", 1000, 0), ("chain7", "float64", 65, 1), ("quadrup
          ("rev1", "float32", 5, 1), ("pri1", "float64", 3, 0), ("free1", "float32", 65, 1)]
 
 
-@pytest.mark.parametrize("form", ["split", "whole", "dual"])
-@pytest.mark.parametrize("name,dtype,B,frame", CASES)
+TRIPLE_CASES = [("chain7", "float32", 1000, 0), ("quadruped_spine", "float32", 513, 1), ("random23", "float32", 300, 1),
+                ("humanoid_small", "float64", 40, 1), ("humanoid_large", "float32", 1000, 1),
+                ("humanoid_large", "float64", 64, 0), ("star64", "float32", 70, 1), ("free1", "float32", 65, 1)]
+
+
+@pytest.mark.parametrize("name,dtype,B,frame,form", [c + (f,) for f in ("split", "whole", "dual") for c in CASES] +
+                         [c + ("triple",) for c in TRIPLE_CASES])
 def test_specialized_chain_matches_oracle(name, dtype, B, frame, form):
     say(f"[gpu] specialised chain {name} {dtype} B={B} frame={frame} form={form}")
     tree = synth.tree_by_name(name)
@@ -146,14 +151,17 @@ def test_autotune_routes_by_batch():
     say(f"[gpu] autotuned chain on humanoid_small: first specialised batch {mb}, tiers " +
         ", ".join(f"{f} {t:04b}" for f, t in tiers.items()))
     assert mb in (-1,) + bard.SPEC_TIERS
-    assert sum(bin(t).count("1") for t in tiers.values()) == bin(tiers["split"] | tiers["whole"] | tiers["dual"]).count("1")
+    routed = 0
+    for t in tiers.values():
+        routed |= t
+    assert sum(bin(t).count("1") for t in tiers.values()) == bin(routed).count("1")
     for B, tier in ((300, 0), (20000, 2)):
         q, qd, qdd = inputs(tree, B, 5700 + B, "float32")
         d = [to_dev(x, "float32") for x in (q, qd, qdd)]
         out = m.chain(*d, ee)
         gen = ref.chain(*d, ee)
         torch.cuda.synchronize()
-        if not ((tiers["split"] | tiers["whole"] | tiers["dual"]) >> tier) & 1:
+        if not (routed >> tier) & 1:
             for a, b in zip(out, gen):
                 assert torch.equal(a, b)
         idx = np.sort(np.random.default_rng(B).choice(B, min(B, 200), replace=False))
@@ -161,7 +169,7 @@ def test_autotune_routes_by_batch():
                      "float32", label=f"autotuned B={B}")
 
 
-@pytest.mark.parametrize("form", ["split", "dual"])
+@pytest.mark.parametrize("form", ["split", "dual", "triple"])
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
 def test_zero_rows_from_extra_workgroups_and_from_lanes(dtype, form):
     """With instance-minor outputs, a batch that is a multiple of the 16-byte

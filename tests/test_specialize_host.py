@@ -19,7 +19,9 @@ from paper_2605_31481_amd import bard
                                                    ("quadruped_spine", "float32", 1, "split"),
                                                    ("quadruped_spine", "float64", 0, "whole"),
                                                    ("humanoid_small", "float32", 0, "dual"),
-                                                   ("free1", "float64", 0, "dual"), ("star64", "float32", 0, "split")])
+                                                   ("free1", "float64", 0, "dual"), ("star64", "float32", 0, "split"),
+                                                   ("quadruped_spine", "float32", 0, "triple"),
+                                                   ("humanoid_small", "float64", 1, "triple")])
 def test_generated_source_compiles(name, dtype, frame, form):
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
@@ -33,7 +35,7 @@ def _table(src, which):
     return [int(x) for x in vals[:n]]
 
 
-@pytest.mark.parametrize("form", ["split", "whole", "dual"])
+@pytest.mark.parametrize("form", ["split", "whole", "dual", "triple"])
 def test_generated_source_covers_every_output(form):
     tree = synth.humanoid_small()
     m = bard.Model.from_tree(tree)
