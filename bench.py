@@ -377,9 +377,10 @@ def measure_peaks(torch):
 
 def bench_specialized(torch, bard):
     """Model-specialised chain kernels (hipRTC, constants as literals) against
-    the generic kernel: the three forms (split over waves by limbs, dual:
-    split with torques and mass matrix + Jacobians in two workgroups, and the whole
-    tree per wave) on the 36-DOF and 23-DOF humanoids and the 7-DOF chain at
+    the generic kernel: the four forms (split over waves by limbs, dual:
+    split with torques and mass matrix + Jacobians in two workgroups, triple:
+    torques, mass matrix and Jacobians in three, and the whole tree per
+    wave) on the 36-DOF and 23-DOF humanoids and the 7-DOF chain at
     B = 1024 .. 262,144, rotating sets past 512 MB; then the tiers
     bard_chain_autotune routes to each form; then the specialised
     forward-dynamics (ABA) kernel against the generic one at the same
