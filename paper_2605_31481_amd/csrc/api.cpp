@@ -1107,6 +1107,9 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);
 }
 
+// Batch from which the path kinematics runs one lane per instance.
+constexpr int64_t kPathParBatch = 65536;
+
 int bard_path_kinematics(bard_model_t m, bard_dtype dtype, const void* q, int32_t ee_body, bard_frame frame,
                           void* pose, void* J, const bard_layout* L, int64_t B, void* stream) {
   int rc = common_checks(m, nullptr, dtype, B);
@@ -1148,7 +1151,15 @@ int bard_path_kinematics(bard_model_t m, bard_dtype dtype, const void* q, int32_
     DeviceCopy* dc = nullptr;
     int rc2 = ensure_device(m, &dc, (hipStream_t)stream);
     if (rc2) return rc2;
-    hipError_t e = launch_path<R>(dc->dm, a, frame == BARD_LOCAL_WORLD_ALIGNED, (hipStream_t)stream);
+    // several lanes per instance below kPathParBatch instances (the walk's
+    // latency sets the time there): 4 with segments of up to 4 bodies when
+    // the path has at most 16, else 16; one lane per instance above (the
+    // stores do).  BARD_PATH_LANES=1 or 16 pins the form (16: the
+    // lane-parallel one)
+    a.seg = a.len <= 16 ? (a.len + 3) / 4 : (a.len + 15) / 16;
+    bool par = B < kPathParBatch;
+    if (const char* env = getenv("BARD_PATH_LANES")) par = atoi(env) == 16;
+    hipError_t e = launch_path<R>(dc->dm, a, frame == BARD_LOCAL_WORLD_ALIGNED, par, (hipStream_t)stream);
     if (e != hipSuccess) return fail(BARD_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
     return BARD_OK;
   };

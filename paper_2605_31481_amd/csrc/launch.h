@@ -99,6 +99,7 @@ struct PathArgs {
   int64_t sq_b, sq_k, sp_b, sp_k, sJ_b, sJ_k;
   int64_t B;
   int len;           // bodies on the path
+  int seg;           // lane-parallel form: path bodies per lane (16 lanes per instance)
   int nqp;           // position coordinates of the path's joints
   int n_zero;        // columns off the path
   int zero_groups;   // workgroup rows (gridDim.y - 1) that store those columns
@@ -107,8 +108,10 @@ struct PathArgs {
   uint8_t qsrc[72];  // q index of each of the path's nqp coordinates, in path order
   uint8_t zcol[128];  // the columns off the path
 };
+// par: the lane-parallel form (16 lanes per instance, the path's poses by a
+// scan across the lanes) instead of one lane per instance.
 template <class Real>
-hipError_t launch_path(const DevModel& dm, const PathArgs<Real>& pa, bool lwa, hipStream_t st);
+hipError_t launch_path(const DevModel& dm, const PathArgs<Real>& pa, bool lwa, bool par, hipStream_t st);
 
 __host__ __device__ inline int lds_align(int x) { return (x + 15) & ~15; }
 

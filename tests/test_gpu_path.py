@@ -41,10 +41,17 @@ def _ees(tree):
     return sorted(set(ee + [0, tree.n_bodies - 1]))
 
 
+@pytest.fixture(params=["1", "16"], ids=["lane_per_instance", "16_lanes_per_instance"])
+def lanes(request, monkeypatch):
+    """Both forms of the kernel whatever the batch (BARD_PATH_LANES pins one)."""
+    monkeypatch.setenv("BARD_PATH_LANES", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("frame", [0, 1])
 @pytest.mark.parametrize("name,dtype,B", CASES)
-def test_path_kinematics_matches_oracle(name, dtype, B, frame):
-    say(f"[gpu] path kinematics {name} {dtype} B={B} frame={frame}")
+def test_path_kinematics_matches_oracle(name, dtype, B, frame, lanes):
+    say(f"[gpu] path kinematics {name} {dtype} B={B} frame={frame} lanes={lanes}")
     tree = synth.tree_by_name(name)
     m = bard.Model.from_tree(tree)
     om = oracle_for(tree)
@@ -58,7 +65,7 @@ def test_path_kinematics_matches_oracle(name, dtype, B, frame):
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
-def test_path_outputs_alone_layouts_and_full_tree_operators(dtype):
+def test_path_outputs_alone_layouts_and_full_tree_operators(dtype, lanes):
     """Pose only, Jacobian only, batch-major arrays, and agreement with the
     full-tree operators' blocks for the same end effector."""
     tree = synth.humanoid_large()
@@ -88,17 +95,22 @@ def test_path_outputs_alone_layouts_and_full_tree_operators(dtype):
     assert_normwise("pose vs bard_fk", from_dev(pose, layout="aos")[:, None, :], Tf, dtype)
 
 
-def test_path_large_batch_sampled():
-    """262,144 instances of the free-root humanoid (1024 workgroups of
-    instance lanes plus the zero-column rows), sampled against the oracle."""
+@pytest.mark.parametrize("pin", [None, "16"])
+def test_path_large_batch_sampled(pin, monkeypatch):
+    """262,144 instances of the free-root humanoid, sampled against the
+    oracle: the form the batch selects (one lane per instance, 4096
+    workgroups plus the zero-column rows) and the 16-lane form (65,536
+    workgroups)."""
     import torch
+    if pin:
+        monkeypatch.setenv("BARD_PATH_LANES", pin)
     tree = synth.humanoid_large()
     m = bard.Model.from_tree(tree)
     om = oracle_for(tree)
     B = 262144
     q, _, _ = inputs(tree, B, 4102, "float32")
     e = tree.ee_bodies[0]
-    say(f"[gpu] path kinematics humanoid_large float32 B={B} sampled")
+    say(f"[gpu] path kinematics humanoid_large float32 B={B} sampled, lanes {pin or 'by batch'}")
     pose, J = m.path_kinematics(to_dev(q, "float32"), e, frame=0)
     torch.cuda.synchronize()
     rng = np.random.default_rng(4103)
