@@ -301,8 +301,10 @@ int bard_jacobian(bard_model_t model, bard_ws_t ws, bard_dtype dtype, const void
 
 /* Standalone FK and Jacobian of one kinematic chain (Sec. 3.1: path-only
  * functions for a root-to-end-effector chain).  Visits only the bodies on the
- * path from ee_body's root to ee_body, uses no workspace and caches nothing;
- * each lane of the launch walks one instance's path.  pose and J hold the
+ * path from ee_body's root to ee_body, uses no workspace and caches nothing.
+ * Below 65,536 instances 4 or 16 lanes share an instance's path (segments
+ * combined by a scan across lanes); from there one lane walks it (the
+ * environment variable BARD_PATH_LANES = 1 or 16 pins either form).  pose and J hold the
  * same values (up to rounding) as the ee_body block of bard_fk's poses and
  * of bard_jacobian's J for the one end effector ee_body.
  * Arrays (L order, three entries): q [nq] in; pose [12] out, the 3x4
