@@ -846,6 +846,10 @@ class Plan:
     tensors and returns per model (tau, M, J) (entries the op mask does not
     produce are None).  Output tensors are allocated once per plan and reused
     by every run, so the replayed graph keeps writing to the same memory.
+    ``configure(tile, fusion, order, lanes)``: fusion 0 one generic launch,
+    1 one per model, 2 one per operator, 3 one generated kernel holding every
+    tree's specialised code (lanes 1: each tree over at most 4 waves);
+    ``autotune`` times them all and keeps the fastest.
     """
 
     def __init__(self, models: Sequence[Model], batches: Sequence[int], op_mask: int = 7, dtype=None):
