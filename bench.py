@@ -245,9 +245,9 @@ def op_work(tree, n_ee, op):
 
 
 def bench_operators(torch, bard):
-    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA, CRBA,
-    ABA, and the standalone pose and Jacobian of the first end effector's
-    path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
+    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA, the
+    model-specialised RNEA, CRBA, ABA, and the standalone pose and Jacobian
+    of the first end effector's path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
     at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
     evaluations per second from the kernel time, the HBM fraction of its
     algorithmic bytes, and for RNEA and ABA the FP32 VALU fraction of the
@@ -258,6 +258,8 @@ def bench_operators(torch, bard):
     for name, B in (("humanoid_large", 4096), ("humanoid_large", 16384), ("chain7", 4096)):
         tree = synth.tree_by_name(name)
         m = bard.Model.from_tree(tree)
+        mr = bard.Model.from_tree(tree)   # its rnea() calls routed to the specialised kernel
+        mr.specialize_rnea()
         ee = tree.ee_bodies
         per_eval = 4 * (tree.nq + 4 * tree.nv + 12 * tree.n_bodies + tree.nv * tree.nv + 6 * tree.nv * len(ee))
         nsets = max(3, min(64, math.ceil(512e6 / (per_eval * B))))
@@ -276,6 +278,7 @@ def bench_operators(torch, bard):
         binders = {"fk": lambda d, o: m.bind_fk(d[0], o["fk"]),
                    "jacobian": lambda d, o: m.bind_jacobian(d[0], ee, o["jacobian"]),
                    "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),
+                   "rnea_specialized": lambda d, o: mr.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "crba": lambda d, o: m.bind_crba(d[0], o["crba"]),
                    "aba": lambda d, o: m.bind_aba(d[0], d[1], d[2], o["aba"]),   # qdd's values as torques
                    "path": lambda d, o: m.bind_path_kinematics(d[0], ee[0], o["path_pose"], o["path_J"],
@@ -285,7 +288,7 @@ def bench_operators(torch, bard):
             calls = [bind(d, o) for (d, o) in sets]
             _, kavg = time_calls(torch, calls, n, 10)
             t = kavg * 1e-3
-            nbytes, flops = op_work(tree, len(ee), op)
+            nbytes, flops = op_work(tree, len(ee), op.replace("_specialized", ""))
             key = f"op_{name}_B{B}_{op}"
             out[key + "_evals_per_s"] = B / t
             out[key + "_kernel_us"] = kavg * 1e3

@@ -213,6 +213,28 @@ int bard_chain_autotune(bard_model_t model, bard_dtype dtype, int32_t n_ee, cons
 int bard_model_specialized_source(bard_model_t model, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                                   bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len);
 
+/* Inverse dynamics alone written for one tree in the same way (Sec. 3.3's
+ * RNEA, the torque code of the chain kernels: poses and velocities forward,
+ * body forces, subtree forces back, tau_i = s_i . F_i), for RL loops that
+ * call bard_rnea only.  flags: BARD_SPEC_ROUTE (bard_rnea calls without a
+ * workspace and without an inertia override then launch it, at every
+ * batch), BARD_SPEC_COMPILE_ONLY (compile only, no GPU needed),
+ * BARD_SPEC_WHOLE (one wave over the whole tree instead of the split form).
+ * Routing one form takes the calls from the other.  Results agree with the
+ * generic kernel's within the tolerance contract, not bitwise.
+ * Errors: as bard_model_specialize (trees deeper than 32: BARD_E_UNSUPPORTED). */
+int bard_model_specialize_rnea(bard_model_t model, bard_dtype dtype, int32_t flags);
+/* Resources of the loaded inverse-dynamics kernel of the form flags selects
+ * (0 or BARD_SPEC_WHOLE), as bard_model_specialized_info.  BARD_E_STATE if
+ * none is loaded. */
+int bard_model_specialized_rnea_info(bard_model_t model, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                     int32_t* waves);
+/* Its generated source (flags 0 or BARD_SPEC_WHOLE), as
+ * bard_model_specialized_source.  Host only. */
+int bard_model_specialized_rnea_source(bard_model_t model, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                       int64_t* len);
+
 /* The forward dynamics of bard_aba written for one tree in the same way (one
  * wave per 64 instances over the whole tree, constants as literals; the
  * articulated-body algorithm's three passes of Sec. 3, in the base frame as

@@ -134,6 +134,12 @@ bard_plan_destroy = _sig("bard_plan_destroy", [_vp])
 bard_plan_configure = _sig("bard_plan_configure", [_vp, _i32, _i32, _i32, _i32])
 bard_plan_get_config = _sig("bard_plan_get_config", [_vp, _c_i32p, _c_i32p, _c_i32p, _c_i32p, _c_i32p])
 bard_plan_ee = _sig("bard_plan_ee", [_vp, _i32, _c_i32p, _c_i32p])
+bard_model_specialize_rnea = _sig("bard_model_specialize_rnea", [_vp, ctypes.c_int, _i32])
+bard_model_specialized_rnea_info = _sig("bard_model_specialized_rnea_info",
+                                        [_vp, ctypes.c_int, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+bard_model_specialized_rnea_source = _sig("bard_model_specialized_rnea_source",
+                                          [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
 bard_plan_specialized_info = _sig("bard_plan_specialized_info", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64),
                                                                  ctypes.POINTER(ctypes.c_double)])
@@ -527,6 +533,35 @@ class Model:
         buf = ctypes.create_string_buffer(n.value + 1)
         _check(bard_model_specialized_aba_source(self._h, self._dtype_arg(dtype), buf, n.value + 1, ctypes.byref(n)),
                "bard_model_specialized_aba_source")
+        return buf.value.decode()
+
+    def specialize_rnea(self, dtype=None, route: bool = True, compile_only: bool = False, form: str = "split"):
+        """Compile the model-specialised inverse-dynamics kernel (form "split"
+        or "whole") with hipRTC and load it; with route=True, rnea() calls
+        without a workspace or inertia override use it at every batch."""
+        if form not in ("split", "whole"):
+            raise ValueError("form must be 'split' or 'whole'")
+        flags = ((SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0) |
+                 (SPEC_WHOLE if form == "whole" else 0))
+        _check(bard_model_specialize_rnea(self._h, self._dtype_arg(dtype), flags), "bard_model_specialize_rnea")
+
+    def specialized_rnea_info(self, dtype=None, form: str = "split") -> dict:
+        vg, sc, rt, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cs = ctypes.c_double()
+        _check(bard_model_specialized_rnea_info(self._h, self._dtype_arg(dtype), SPEC_WHOLE if form == "whole" else 0,
+                                                ctypes.byref(vg), ctypes.byref(sc), ctypes.byref(cs),
+                                                ctypes.byref(rt), ctypes.byref(w)), "bard_model_specialized_rnea_info")
+        return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
+                "route_tiers": rt.value, "waves": w.value}
+
+    def specialized_rnea_source(self, dtype=None, form: str = "split") -> str:
+        flags = SPEC_WHOLE if form == "whole" else 0
+        n = _i64()
+        _check(bard_model_specialized_rnea_source(self._h, self._dtype_arg(dtype), flags, None, 0, ctypes.byref(n)),
+               "bard_model_specialized_rnea_source")
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(bard_model_specialized_rnea_source(self._h, self._dtype_arg(dtype), flags, buf, n.value + 1,
+                                                  ctypes.byref(n)), "bard_model_specialized_rnea_source")
         return buf.value.decode()
 
     @staticmethod

@@ -885,6 +885,75 @@ int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee
   return BARD_OK;
 }
 
+// ---- the inverse-dynamics-only specialised kernel ----
+
+static int spec_rnea_args(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t extra) {
+  if (!m) return fail(BARD_E_ARG, "NULL model");
+  if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
+  if (flags & ~(BARD_SPEC_WHOLE | extra)) return fail(BARD_E_ARG, "unknown flags");
+  if (m->depth > kSpecMaxDepth)
+    return fail(BARD_E_UNSUPPORTED, "tree too deep for a specialised kernel (depth " + std::to_string(m->depth) +
+                                        "); the generic kernel serves it");
+  return BARD_OK;
+}
+
+int bard_model_specialize_rnea(bard_model_t m, bard_dtype dtype, int32_t flags) {
+  int rc = spec_rnea_args(m, dtype, flags, BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY);
+  if (rc) return rc;
+  const int form = (flags & BARD_SPEC_WHOLE) ? 1 : 0;
+  if (flags & BARD_SPEC_COMPILE_ONLY) {
+    std::vector<char> code;
+    std::string log;
+    rc = spec_compile(spec_rnea_source(m, dtype == BARD_F64, form), &code, &log);
+    return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
+  }
+  if ((rc = check_device_state())) return rc;
+  DeviceCopy* dc = nullptr;
+  if ((rc = ensure_device(m, &dc, nullptr))) return rc;
+  SpecKernel* sk = nullptr;
+  if ((rc = spec_prepare_rnea(m, dc, (int)dtype, form, true, &sk))) return rc;
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto other = dc->spec.find(spec_rnea_key((int)dtype, 1 - form));
+  if ((flags & BARD_SPEC_ROUTE) && other != dc->spec.end()) other->second.route_tiers = 0;
+  sk->route_tiers = (flags & BARD_SPEC_ROUTE) ? (1 << kSpecTiers) - 1 : 0;
+  spec_refresh_route(m);
+  return BARD_OK;
+}
+
+int bard_model_specialized_rnea_info(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                     int32_t* waves) {
+  int rc = spec_rnea_args(m, dtype, flags, 0);
+  if (rc) return rc;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = m->dev[dev].spec.find(spec_rnea_key((int)dtype, (flags & BARD_SPEC_WHOLE) ? 1 : 0));
+  if (it == m->dev[dev].spec.end() || !it->second.fn)
+    return fail(BARD_E_STATE, "no specialised inverse-dynamics kernel of this form on the current device");
+  if (vgprs) *vgprs = it->second.vgprs;
+  if (scratch_bytes) *scratch_bytes = it->second.scratch;
+  if (compile_seconds) *compile_seconds = it->second.compile_s;
+  if (routed_tiers) *routed_tiers = it->second.route_tiers;
+  if (waves) *waves = it->second.waves;
+  return BARD_OK;
+}
+
+int bard_model_specialized_rnea_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                       int64_t* len) {
+  int rc = spec_rnea_args(m, dtype, flags, 0);
+  if (rc) return rc;
+  if (!len) return fail(BARD_E_ARG, "len is NULL");
+  const std::string src = spec_rnea_source(m, dtype == BARD_F64, (flags & BARD_SPEC_WHOLE) ? 1 : 0);
+  *len = (int64_t)src.size();
+  if (buf && cap > 0) {
+    const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
+    std::memcpy(buf, src.data(), n);
+    buf[n] = 0;
+  }
+  return BARD_OK;
+}
+
 static int spec_aba_args(bard_model_t m, bard_dtype dtype) {
   if (!m) return fail(BARD_E_ARG, "NULL model");
   if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
@@ -1186,6 +1255,15 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
         !layout_of(L, 2, B, m->nv, &a.sqdd_b, &a.sqdd_k) || !layout_of(L, 3, B, m->nv, &a.st_b, &a.st_k))
       return fail(BARD_E_ARG, "bad layout stride");
     const hipStream_t st = (hipStream_t)stream;
+    if (!ws && !inertia_override && m->spec_route.load()) {
+      // a routed inverse-dynamics-only specialised kernel (calls without a
+      // workspace and with the model's own inertial parameters)
+      DeviceCopy* dc = nullptr;
+      int rc2 = ensure_device(m, &dc, st);
+      if (rc2) return rc2;
+      SpecKernel* sk = spec_lookup_rnea(m, dc, (int)dtype, B);
+      if (sk && spec_fits(a, m->nv, 0)) return spec_launch<R>(sk, a, m->g, st);
+    }
     if (!ws || !(ws->policy & BARD_TIER_BIAS) || q_tag == 0 || qd_tag == 0 || inertia_override)
       return run_tree<R, OP_RNEA>(m, a, 0, nullptr, 0, st, ws, q_tag);
     DeviceCopy* dc = nullptr;

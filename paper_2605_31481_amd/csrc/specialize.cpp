@@ -139,9 +139,11 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64, int max_waves = 
 // Emits the source text of one specialised chain kernel.
 class Emitter {
  public:
+  // ops: the outputs the kernel computes (1 torques, 2 mass matrix, 4
+  // Jacobians; the split and whole forms only)
   Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form,
-          int max_waves = SplitPlan::kMaxWaves)
-      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), parts_(form == 2 ? 2 : form == 3 ? 3 : 1),
+          int max_waves = SplitPlan::kMaxWaves, int ops = 7)
+      : m_(m), ee_(ee), frame_(frame), fp64_(fp64), ops_(ops), parts_(form == 2 ? 2 : form == 3 ? 3 : 1),
         dual_(parts_ > 1), pl_(make_plan(m, form == 1, fp64, max_waves)), split_(pl_.split || dual_) {
     trunk_ = pl_.trunk;
     slot_body_ = pl_.slot_body;
@@ -247,6 +249,7 @@ class Emitter {
   // The code of one workgroup after the structural-zero workgroups.
   void body() {
     if (!split_) {
+      set_parts(ops_ & 1, ops_ & 2, ops_ & 4);
       if (member_) o_ << "  if (threadIdx.x >= 64) return;\n";
       o_ << "  const long long b = (long long)" << blk_ << " * 64 + threadIdx.x;\n"
             "  if (b >= B) return;\n";
@@ -257,6 +260,7 @@ class Emitter {
       emit_zero_stores();
       for (int i = 0; i < m_->n; ++i)
         if (m_->parent[i] < 0) visit(i);
+      set_parts(true, true, true);
       return;
     }
     // Every lane of every wave reaches the barrier: lanes past the batch
@@ -296,7 +300,9 @@ class Emitter {
       o_ << "  }\n";
       set_parts(true, true, true);
     } else {
+      set_parts(ops_ & 1, ops_ & 2, ops_ & 4);
       split_body();
+      set_parts(true, true, true);
     }
   }
 
@@ -424,6 +430,7 @@ class Emitter {
   std::vector<int> ee_;
   int frame_;
   bool fp64_;
+  int ops_;          // outputs computed (1 torques, 2 mass matrix, 4 Jacobians)
   int parts_;        // workgroups per 64 instances: 1; 2 (RNEA | CRBA + Jacobians); 3 (RNEA | CRBA | Jacobians)
   bool dual_;        // parts_ > 1
   bool do_rnea_ = true, do_crba_ = true, do_jac_ = true;  // parts of the output the code being emitted computes
@@ -510,8 +517,8 @@ class Emitter {
         for (int col = 0; col < nv; ++col)
           if (!on[col]) zj.push_back(((int)e * 6 + r) * nv + col);
     }
-    zm_ = zm;
-    zj_ = zj;
+    zm_ = (ops_ & 2) ? zm : std::vector<int>();
+    zj_ = (ops_ & 4) ? zj : std::vector<int>();
   }
 
   // ---- entering body i: pose, axis, velocity, acceleration, body force ----
@@ -862,10 +869,11 @@ class Emitter {
 
   void visit(int i) {
     forward(i);
-    for (size_t e = 0; e < ee_.size(); ++e)
-      if (ee_[e] == i) jacobian((int)e);
+    if (do_jac_)
+      for (size_t e = 0; e < ee_.size(); ++e)
+        if (ee_[e] == i) jacobian((int)e);
     for (int ch : m_->children[i]) visit(ch);
-    backward(i);
+    if (do_rnea_ || do_crba_) backward(i);
   }
 };
 
@@ -1340,6 +1348,12 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
   return Emitter(m, ee, frame, fp64, form).source();
 }
 
+std::string spec_rnea_source(const bard_model* m, bool fp64, int form) {
+  return Emitter(m, {}, 0, fp64, form, SplitPlan::kMaxWaves, 1).source();
+}
+
+std::string spec_rnea_key(int dtype, int form) { return "rnea:" + std::to_string(form) + ":" + std::to_string(dtype); }
+
 std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
                              const std::vector<int64_t>& batch, bool fp64, int max_waves, int* waves,
                              int64_t* blocks) {
@@ -1587,6 +1601,29 @@ int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::v
   out.compile_s = out.compile_s < 0 ? 0.0 : std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *sk = std::move(out);
   return BARD_OK;
+}
+
+int spec_prepare_rnea(bard_model* m, DeviceCopy* dc, int dtype, int form, bool load, SpecKernel** out) {
+  return prepare_kernel(
+      m, dc, spec_rnea_key(dtype, form), [&] { return spec_rnea_source(m, dtype == BARD_F64, form); },
+      "bard_spec_chain",
+      [&](SpecKernel* sk) {
+        sk->form = form;
+        sk->zero_rows = 0;
+        sk->waves = spec_waves(m, dtype == BARD_F64, form);
+      },
+      load, out);
+}
+
+SpecKernel* spec_lookup_rnea(bard_model* m, DeviceCopy* dc, int dtype, int64_t B) {
+  if (!m->spec_route.load()) return nullptr;
+  const int bit = 1 << spec_tier(B);
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (int form = 0; form < 2; ++form) {
+    auto it = dc->spec.find(spec_rnea_key(dtype, form));
+    if (it != dc->spec.end() && it->second.fn && (it->second.route_tiers & bit)) return &it->second;
+  }
+  return nullptr;
 }
 
 SpecKernel* spec_lookup_aba(bard_model* m, DeviceCopy* dc, int dtype, int64_t B) {

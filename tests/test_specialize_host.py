@@ -136,3 +136,19 @@ def test_generated_multi_tree_plan_source():
     with pytest.raises(bard.BardError) as ei:
         p1.specialized_source()
     assert ei.value.status == -7
+
+
+@pytest.mark.parametrize("name,form", [("humanoid_large", "split"), ("humanoid_large", "whole"),
+                                       ("quadruped_spine", "split"), ("chain7", "split")])
+def test_generated_rnea_only_source(name, form):
+    """The inverse-dynamics-only kernel stores every torque once and no
+    mass-matrix or Jacobian entry (only the accessor macros name them), and
+    compiles for gfx950."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    src = m.specialized_rnea_source(form=form)
+    tau = [int(k) for k in re.findall(r"TAU\((\d+), ", src)]
+    assert sorted(tau) == list(range(tree.nv))
+    assert re.findall(r"\bMA\((\d+), ", src) == [] and re.findall(r"\bJA\((\d+), ", src) == []
+    assert int(re.search(r"NZM = (\d+);", src).group(1)) == 0
+    m.specialize_rnea(compile_only=True, form=form)
