@@ -245,8 +245,8 @@ def op_work(tree, n_ee, op):
 
 
 def bench_operators(torch, bard):
-    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA, the
-    model-specialised RNEA, CRBA, ABA, and the standalone pose and Jacobian
+    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA and CRBA
+    with the generic and the model-specialised kernels, ABA, and the standalone pose and Jacobian
     of the first end effector's path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
     at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
     evaluations per second from the kernel time, the HBM fraction of its
@@ -258,8 +258,9 @@ def bench_operators(torch, bard):
     for name, B in (("humanoid_large", 4096), ("humanoid_large", 16384), ("chain7", 4096)):
         tree = synth.tree_by_name(name)
         m = bard.Model.from_tree(tree)
-        mr = bard.Model.from_tree(tree)   # its rnea() calls routed to the specialised kernel
+        mr = bard.Model.from_tree(tree)   # its rnea() and crba() calls routed to the specialised kernels
         mr.specialize_rnea()
+        mr.specialize_op("crba")
         ee = tree.ee_bodies
         per_eval = 4 * (tree.nq + 4 * tree.nv + 12 * tree.n_bodies + tree.nv * tree.nv + 6 * tree.nv * len(ee))
         nsets = max(3, min(64, math.ceil(512e6 / (per_eval * B))))
@@ -280,6 +281,7 @@ def bench_operators(torch, bard):
                    "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "rnea_specialized": lambda d, o: mr.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "crba": lambda d, o: m.bind_crba(d[0], o["crba"]),
+                   "crba_specialized": lambda d, o: mr.bind_crba(d[0], o["crba"]),
                    "aba": lambda d, o: m.bind_aba(d[0], d[1], d[2], o["aba"]),   # qdd's values as torques
                    "path": lambda d, o: m.bind_path_kinematics(d[0], ee[0], o["path_pose"], o["path_J"],
                                                                frame=bard.LOCAL_WORLD_ALIGNED)}

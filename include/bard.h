@@ -234,6 +234,18 @@ int bard_model_specialized_rnea_info(bard_model_t model, bard_dtype dtype, int32
  * bard_model_specialized_source.  Host only. */
 int bard_model_specialized_rnea_source(bard_model_t model, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
                                        int64_t* len);
+/* The joint-space mass matrix alone written for one tree in the same way
+ * (Sec. 3's CRBA: poses forward, composite inertias back, M_ij = s_i . Ic_j
+ * s_j over each dof's ancestors, the structural zeros from tables, by extra
+ * workgroups for instance-minor 16-byte-aligned outputs); routes bard_crba
+ * calls without a workspace.  Flags, errors and the two companions as for
+ * the inverse-dynamics kernel above. */
+int bard_model_specialize_crba(bard_model_t model, bard_dtype dtype, int32_t flags);
+int bard_model_specialized_crba_info(bard_model_t model, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                     int32_t* waves);
+int bard_model_specialized_crba_source(bard_model_t model, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                       int64_t* len);
 
 /* The forward dynamics of bard_aba written for one tree in the same way (one
  * wave per 64 instances over the whole tree, constants as literals; the

@@ -140,6 +140,12 @@ bard_model_specialized_rnea_info = _sig("bard_model_specialized_rnea_info",
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
 bard_model_specialized_rnea_source = _sig("bard_model_specialized_rnea_source",
                                           [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
+bard_model_specialize_crba = _sig("bard_model_specialize_crba", [_vp, ctypes.c_int, _i32])
+bard_model_specialized_crba_info = _sig("bard_model_specialized_crba_info",
+                                        [_vp, ctypes.c_int, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+bard_model_specialized_crba_source = _sig("bard_model_specialized_crba_source",
+                                          [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
 bard_plan_specialized_info = _sig("bard_plan_specialized_info", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64),
                                                                  ctypes.POINTER(ctypes.c_double)])
@@ -535,34 +541,56 @@ class Model:
                "bard_model_specialized_aba_source")
         return buf.value.decode()
 
-    def specialize_rnea(self, dtype=None, route: bool = True, compile_only: bool = False, form: str = "split"):
-        """Compile the model-specialised inverse-dynamics kernel (form "split"
-        or "whole") with hipRTC and load it; with route=True, rnea() calls
-        without a workspace or inertia override use it at every batch."""
+    _SPEC_OP_FNS = {"rnea": ("bard_model_specialize_rnea", "bard_model_specialized_rnea_info",
+                             "bard_model_specialized_rnea_source"),
+                    "crba": ("bard_model_specialize_crba", "bard_model_specialized_crba_info",
+                             "bard_model_specialized_crba_source")}
+
+    def _spec_op_fns(self, op: str):
+        if op not in self._SPEC_OP_FNS:
+            raise ValueError("op must be 'rnea' or 'crba'")
+        g = globals()
+        return tuple(g[n] for n in self._SPEC_OP_FNS[op])
+
+    def specialize_op(self, op: str, dtype=None, route: bool = True, compile_only: bool = False,
+                      form: str = "split"):
+        """Compile the model-specialised kernel of one operator ("rnea" or
+        "crba"; form "split" or "whole") with hipRTC and load it; with
+        route=True, that operator's calls without a workspace (and, for
+        rnea, without an inertia override) use it at every batch."""
         if form not in ("split", "whole"):
             raise ValueError("form must be 'split' or 'whole'")
         flags = ((SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0) |
                  (SPEC_WHOLE if form == "whole" else 0))
-        _check(bard_model_specialize_rnea(self._h, self._dtype_arg(dtype), flags), "bard_model_specialize_rnea")
+        fn, _, _ = self._spec_op_fns(op)
+        _check(fn(self._h, self._dtype_arg(dtype), flags), fn.__name__)
 
-    def specialized_rnea_info(self, dtype=None, form: str = "split") -> dict:
+    def specialized_op_info(self, op: str, dtype=None, form: str = "split") -> dict:
+        _, fn, _ = self._spec_op_fns(op)
         vg, sc, rt, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         cs = ctypes.c_double()
-        _check(bard_model_specialized_rnea_info(self._h, self._dtype_arg(dtype), SPEC_WHOLE if form == "whole" else 0,
-                                                ctypes.byref(vg), ctypes.byref(sc), ctypes.byref(cs),
-                                                ctypes.byref(rt), ctypes.byref(w)), "bard_model_specialized_rnea_info")
+        _check(fn(self._h, self._dtype_arg(dtype), SPEC_WHOLE if form == "whole" else 0, ctypes.byref(vg),
+                  ctypes.byref(sc), ctypes.byref(cs), ctypes.byref(rt), ctypes.byref(w)), fn.__name__)
         return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
                 "route_tiers": rt.value, "waves": w.value}
 
-    def specialized_rnea_source(self, dtype=None, form: str = "split") -> str:
+    def specialized_op_source(self, op: str, dtype=None, form: str = "split") -> str:
+        _, _, fn = self._spec_op_fns(op)
         flags = SPEC_WHOLE if form == "whole" else 0
         n = _i64()
-        _check(bard_model_specialized_rnea_source(self._h, self._dtype_arg(dtype), flags, None, 0, ctypes.byref(n)),
-               "bard_model_specialized_rnea_source")
+        _check(fn(self._h, self._dtype_arg(dtype), flags, None, 0, ctypes.byref(n)), fn.__name__)
         buf = ctypes.create_string_buffer(n.value + 1)
-        _check(bard_model_specialized_rnea_source(self._h, self._dtype_arg(dtype), flags, buf, n.value + 1,
-                                                  ctypes.byref(n)), "bard_model_specialized_rnea_source")
+        _check(fn(self._h, self._dtype_arg(dtype), flags, buf, n.value + 1, ctypes.byref(n)), fn.__name__)
         return buf.value.decode()
+
+    def specialize_rnea(self, dtype=None, route: bool = True, compile_only: bool = False, form: str = "split"):
+        self.specialize_op("rnea", dtype, route, compile_only, form)
+
+    def specialized_rnea_info(self, dtype=None, form: str = "split") -> dict:
+        return self.specialized_op_info("rnea", dtype, form)
+
+    def specialized_rnea_source(self, dtype=None, form: str = "split") -> str:
+        return self.specialized_op_source("rnea", dtype, form)
 
     @staticmethod
     def _dtype_arg(dtype) -> int:

@@ -885,9 +885,9 @@ int bard_model_specialized_source(bard_model_t m, bard_dtype dtype, int32_t n_ee
   return BARD_OK;
 }
 
-// ---- the inverse-dynamics-only specialised kernel ----
+// ---- single-operator specialised kernels (inverse dynamics, mass matrix) ----
 
-static int spec_rnea_args(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t extra) {
+static int spec_op_args(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t extra) {
   if (!m) return fail(BARD_E_ARG, "NULL model");
   if (dtype != BARD_F32 && dtype != BARD_F64) return fail(BARD_E_ARG, "bad dtype");
   if (flags & ~(BARD_SPEC_WHOLE | extra)) return fail(BARD_E_ARG, "unknown flags");
@@ -897,40 +897,39 @@ static int spec_rnea_args(bard_model_t m, bard_dtype dtype, int32_t flags, int32
   return BARD_OK;
 }
 
-int bard_model_specialize_rnea(bard_model_t m, bard_dtype dtype, int32_t flags) {
-  int rc = spec_rnea_args(m, dtype, flags, BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY);
+static int spec_op_specialize(bard_model_t m, bard_dtype dtype, int32_t flags, int ops) {
+  int rc = spec_op_args(m, dtype, flags, BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY);
   if (rc) return rc;
   const int form = (flags & BARD_SPEC_WHOLE) ? 1 : 0;
   if (flags & BARD_SPEC_COMPILE_ONLY) {
     std::vector<char> code;
     std::string log;
-    rc = spec_compile(spec_rnea_source(m, dtype == BARD_F64, form), &code, &log);
+    rc = spec_compile(spec_op_source(m, dtype == BARD_F64, form, ops), &code, &log);
     return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
   }
   if ((rc = check_device_state())) return rc;
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, nullptr))) return rc;
   SpecKernel* sk = nullptr;
-  if ((rc = spec_prepare_rnea(m, dc, (int)dtype, form, true, &sk))) return rc;
+  if ((rc = spec_prepare_op(m, dc, (int)dtype, form, ops, true, &sk))) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
-  auto other = dc->spec.find(spec_rnea_key((int)dtype, 1 - form));
+  auto other = dc->spec.find(spec_op_key(ops, (int)dtype, 1 - form));
   if ((flags & BARD_SPEC_ROUTE) && other != dc->spec.end()) other->second.route_tiers = 0;
   sk->route_tiers = (flags & BARD_SPEC_ROUTE) ? (1 << kSpecTiers) - 1 : 0;
   spec_refresh_route(m);
   return BARD_OK;
 }
 
-int bard_model_specialized_rnea_info(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t* vgprs,
-                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
-                                     int32_t* waves) {
-  int rc = spec_rnea_args(m, dtype, flags, 0);
+static int spec_op_info(bard_model_t m, bard_dtype dtype, int32_t flags, int ops, int32_t* vgprs,
+                        int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers, int32_t* waves) {
+  int rc = spec_op_args(m, dtype, flags, 0);
   if (rc) return rc;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
   std::lock_guard<std::mutex> lk(m->mu);
-  auto it = m->dev[dev].spec.find(spec_rnea_key((int)dtype, (flags & BARD_SPEC_WHOLE) ? 1 : 0));
+  auto it = m->dev[dev].spec.find(spec_op_key(ops, (int)dtype, (flags & BARD_SPEC_WHOLE) ? 1 : 0));
   if (it == m->dev[dev].spec.end() || !it->second.fn)
-    return fail(BARD_E_STATE, "no specialised inverse-dynamics kernel of this form on the current device");
+    return fail(BARD_E_STATE, "no specialised kernel of this operator and form on the current device");
   if (vgprs) *vgprs = it->second.vgprs;
   if (scratch_bytes) *scratch_bytes = it->second.scratch;
   if (compile_seconds) *compile_seconds = it->second.compile_s;
@@ -939,12 +938,12 @@ int bard_model_specialized_rnea_info(bard_model_t m, bard_dtype dtype, int32_t f
   return BARD_OK;
 }
 
-int bard_model_specialized_rnea_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
-                                       int64_t* len) {
-  int rc = spec_rnea_args(m, dtype, flags, 0);
+static int spec_op_source_copy(bard_model_t m, bard_dtype dtype, int32_t flags, int ops, char* buf, int64_t cap,
+                               int64_t* len) {
+  int rc = spec_op_args(m, dtype, flags, 0);
   if (rc) return rc;
   if (!len) return fail(BARD_E_ARG, "len is NULL");
-  const std::string src = spec_rnea_source(m, dtype == BARD_F64, (flags & BARD_SPEC_WHOLE) ? 1 : 0);
+  const std::string src = spec_op_source(m, dtype == BARD_F64, (flags & BARD_SPEC_WHOLE) ? 1 : 0, ops);
   *len = (int64_t)src.size();
   if (buf && cap > 0) {
     const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
@@ -952,6 +951,36 @@ int bard_model_specialized_rnea_source(bard_model_t m, bard_dtype dtype, int32_t
     buf[n] = 0;
   }
   return BARD_OK;
+}
+
+int bard_model_specialize_rnea(bard_model_t m, bard_dtype dtype, int32_t flags) {
+  return spec_op_specialize(m, dtype, flags, 1);
+}
+
+int bard_model_specialized_rnea_info(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                     int32_t* waves) {
+  return spec_op_info(m, dtype, flags, 1, vgprs, scratch_bytes, compile_seconds, routed_tiers, waves);
+}
+
+int bard_model_specialized_rnea_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                       int64_t* len) {
+  return spec_op_source_copy(m, dtype, flags, 1, buf, cap, len);
+}
+
+int bard_model_specialize_crba(bard_model_t m, bard_dtype dtype, int32_t flags) {
+  return spec_op_specialize(m, dtype, flags, 2);
+}
+
+int bard_model_specialized_crba_info(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                     int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                     int32_t* waves) {
+  return spec_op_info(m, dtype, flags, 2, vgprs, scratch_bytes, compile_seconds, routed_tiers, waves);
+}
+
+int bard_model_specialized_crba_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                       int64_t* len) {
+  return spec_op_source_copy(m, dtype, flags, 2, buf, cap, len);
 }
 
 static int spec_aba_args(bard_model_t m, bard_dtype dtype) {
@@ -1261,7 +1290,7 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
       DeviceCopy* dc = nullptr;
       int rc2 = ensure_device(m, &dc, st);
       if (rc2) return rc2;
-      SpecKernel* sk = spec_lookup_rnea(m, dc, (int)dtype, B);
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 1, B);
       if (sk && spec_fits(a, m->nv, 0)) return spec_launch<R>(sk, a, m->g, st);
     }
     if (!ws || !(ws->policy & BARD_TIER_BIAS) || q_tag == 0 || qd_tag == 0 || inertia_override)
@@ -1313,6 +1342,14 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
       return fail(BARD_E_ARG, "bad layout stride");
     const hipStream_t st = (hipStream_t)stream;
     const int nn = m->nv * m->nv;
+    if (!ws && m->spec_route.load()) {
+      // a routed mass-matrix-only specialised kernel (calls without a workspace)
+      DeviceCopy* dc = nullptr;
+      int rc2 = ensure_device(m, &dc, st);
+      if (rc2) return rc2;
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 2, B);
+      if (sk && spec_fits(a, m->nv, 0)) return spec_launch<R>(sk, a, m->g, st);
+    }
     if (!ws || !(ws->policy & BARD_TIER_MASS) || q_tag == 0)
       return run_tree<R, OP_CRBA>(m, a, 0, nullptr, 0, st, ws, q_tag);
     int rc2 = ensure_tier<R>(ws, &ws->mt, nn, st);

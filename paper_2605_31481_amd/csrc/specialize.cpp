@@ -1348,11 +1348,13 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
   return Emitter(m, ee, frame, fp64, form).source();
 }
 
-std::string spec_rnea_source(const bard_model* m, bool fp64, int form) {
-  return Emitter(m, {}, 0, fp64, form, SplitPlan::kMaxWaves, 1).source();
+std::string spec_op_source(const bard_model* m, bool fp64, int form, int ops) {
+  return Emitter(m, {}, 0, fp64, form, SplitPlan::kMaxWaves, ops).source();
 }
 
-std::string spec_rnea_key(int dtype, int form) { return "rnea:" + std::to_string(form) + ":" + std::to_string(dtype); }
+std::string spec_op_key(int ops, int dtype, int form) {
+  return "op" + std::to_string(ops) + ":" + std::to_string(form) + ":" + std::to_string(dtype);
+}
 
 std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
                              const std::vector<int64_t>& batch, bool fp64, int max_waves, int* waves,
@@ -1603,24 +1605,24 @@ int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::v
   return BARD_OK;
 }
 
-int spec_prepare_rnea(bard_model* m, DeviceCopy* dc, int dtype, int form, bool load, SpecKernel** out) {
+int spec_prepare_op(bard_model* m, DeviceCopy* dc, int dtype, int form, int ops, bool load, SpecKernel** out) {
   return prepare_kernel(
-      m, dc, spec_rnea_key(dtype, form), [&] { return spec_rnea_source(m, dtype == BARD_F64, form); },
+      m, dc, spec_op_key(ops, dtype, form), [&] { return spec_op_source(m, dtype == BARD_F64, form, ops); },
       "bard_spec_chain",
       [&](SpecKernel* sk) {
         sk->form = form;
-        sk->zero_rows = 0;
+        sk->zero_rows = (ops & 2) ? spec_zero_rows(m, {}) : 0;  // the mass matrix's zero rows
         sk->waves = spec_waves(m, dtype == BARD_F64, form);
       },
       load, out);
 }
 
-SpecKernel* spec_lookup_rnea(bard_model* m, DeviceCopy* dc, int dtype, int64_t B) {
+SpecKernel* spec_lookup_op(bard_model* m, DeviceCopy* dc, int dtype, int ops, int64_t B) {
   if (!m->spec_route.load()) return nullptr;
   const int bit = 1 << spec_tier(B);
   std::lock_guard<std::mutex> lk(m->mu);
   for (int form = 0; form < 2; ++form) {
-    auto it = dc->spec.find(spec_rnea_key(dtype, form));
+    auto it = dc->spec.find(spec_op_key(ops, dtype, form));
     if (it != dc->spec.end() && it->second.fn && (it->second.route_tiers & bit)) return &it->second;
   }
   return nullptr;
@@ -1663,8 +1665,10 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
   // HBM); with more computing waves than that each lane writes its own,
   // coalesced across the wavefront, and the launch is bound by HBM writes.
   const int64_t V = 16 / (int64_t)sizeof(Real);
-  const bool rows = a.sM_b == 1 && a.sJ_b == 1 && a.B % V == 0 && a.sM_k % V == 0 && a.sJ_k % V == 0 &&
-                    ((uintptr_t)a.M % 16) == 0 && ((uintptr_t)a.J % 16) == 0;
+  // (an array the kernel does not write, NULL, imposes nothing)
+  const bool rows = a.B % V == 0 &&
+                    (!a.M || (a.sM_b == 1 && a.sM_k % V == 0 && ((uintptr_t)a.M % 16) == 0)) &&
+                    (!a.J || (a.sJ_b == 1 && a.sJ_k % V == 0 && ((uintptr_t)a.J % 16) == 0));
   int64_t zb = 0;
   if (rows && sk->zero_rows > 0 && main * 3 <= sk->slots) {
     const int64_t chunks = (int64_t)sk->zero_rows * ((a.B / V + 1023) / 1024);

@@ -152,3 +152,19 @@ def test_generated_rnea_only_source(name, form):
     assert re.findall(r"\bMA\((\d+), ", src) == [] and re.findall(r"\bJA\((\d+), ", src) == []
     assert int(re.search(r"NZM = (\d+);", src).group(1)) == 0
     m.specialize_rnea(compile_only=True, form=form)
+
+
+@pytest.mark.parametrize("name,form", [("humanoid_large", "split"), ("humanoid_small", "whole"),
+                                       ("quadruped_spine", "split")])
+def test_generated_crba_only_source(name, form):
+    """The mass-matrix-only kernel names every entry of M once, as a stored
+    value or as a structural zero of its table, and no torque or Jacobian
+    entry; it compiles for gfx950."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    src = m.specialized_op_source("crba", form=form)
+    stored = [int(k) for k in re.findall(r"\bMA\((\d+), ", src)]
+    assert sorted(stored + _table(src, "M")) == list(range(tree.nv * tree.nv))
+    assert re.findall(r"\bTAU\((\d+), ", src) == [] and re.findall(r"\bJA\((\d+), ", src) == []
+    assert "QD(" not in src.split("bard_spec_chain(")[1]     # velocities and accelerations are not read
+    m.specialize_op("crba", compile_only=True, form=form)
