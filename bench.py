@@ -245,8 +245,8 @@ def op_work(tree, n_ee, op):
 
 
 def bench_operators(torch, bard):
-    """Each plain operator alone (FK, 4-end-effector Jacobian, RNEA and CRBA
-    with the generic and the model-specialised kernels, ABA, and the standalone pose and Jacobian
+    """Each plain operator alone (FK; the 4-end-effector Jacobian, RNEA and
+    CRBA with the generic and the model-specialised kernels; ABA; and the standalone pose and Jacobian
     of the first end effector's path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
     at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
     evaluations per second from the kernel time, the HBM fraction of its
@@ -258,10 +258,11 @@ def bench_operators(torch, bard):
     for name, B in (("humanoid_large", 4096), ("humanoid_large", 16384), ("chain7", 4096)):
         tree = synth.tree_by_name(name)
         m = bard.Model.from_tree(tree)
-        mr = bard.Model.from_tree(tree)   # its rnea() and crba() calls routed to the specialised kernels
+        ee = tree.ee_bodies
+        mr = bard.Model.from_tree(tree)   # its rnea(), crba(), jacobian() calls routed to specialised kernels
         mr.specialize_rnea()
         mr.specialize_op("crba")
-        ee = tree.ee_bodies
+        mr.specialize_op("jacobian", ee=ee)
         per_eval = 4 * (tree.nq + 4 * tree.nv + 12 * tree.n_bodies + tree.nv * tree.nv + 6 * tree.nv * len(ee))
         nsets = max(3, min(64, math.ceil(512e6 / (per_eval * B))))
         sets = []
@@ -278,6 +279,7 @@ def bench_operators(torch, bard):
             sets.append((d, o))
         binders = {"fk": lambda d, o: m.bind_fk(d[0], o["fk"]),
                    "jacobian": lambda d, o: m.bind_jacobian(d[0], ee, o["jacobian"]),
+                   "jacobian_specialized": lambda d, o: mr.bind_jacobian(d[0], ee, o["jacobian"]),
                    "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "rnea_specialized": lambda d, o: mr.bind_rnea(d[0], d[1], d[2], o["rnea"]),
                    "crba": lambda d, o: m.bind_crba(d[0], o["crba"]),

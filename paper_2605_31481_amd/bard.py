@@ -146,6 +146,16 @@ bard_model_specialized_crba_info = _sig("bard_model_specialized_crba_info",
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
 bard_model_specialized_crba_source = _sig("bard_model_specialized_crba_source",
                                           [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
+bard_model_specialize_jacobian = _sig("bard_model_specialize_jacobian", [_vp, ctypes.c_int, _i32, _c_i32p,
+                                                                         ctypes.c_int, _i32])
+bard_model_specialized_jacobian_info = _sig("bard_model_specialized_jacobian_info",
+                                            [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32,
+                                             ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32),
+                                             ctypes.POINTER(_i32)])
+bard_model_specialized_jacobian_source = _sig("bard_model_specialized_jacobian_source",
+                                              [_vp, ctypes.c_int, _i32, _c_i32p, ctypes.c_int, _i32,
+                                               ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
 bard_plan_specialized_info = _sig("bard_plan_specialized_info", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64),
                                                                  ctypes.POINTER(ctypes.c_double)])
@@ -544,43 +554,62 @@ class Model:
     _SPEC_OP_FNS = {"rnea": ("bard_model_specialize_rnea", "bard_model_specialized_rnea_info",
                              "bard_model_specialized_rnea_source"),
                     "crba": ("bard_model_specialize_crba", "bard_model_specialized_crba_info",
-                             "bard_model_specialized_crba_source")}
+                             "bard_model_specialized_crba_source"),
+                    "jacobian": ("bard_model_specialize_jacobian", "bard_model_specialized_jacobian_info",
+                                 "bard_model_specialized_jacobian_source")}
 
     def _spec_op_fns(self, op: str):
         if op not in self._SPEC_OP_FNS:
-            raise ValueError("op must be 'rnea' or 'crba'")
+            raise ValueError("op must be 'rnea', 'crba' or 'jacobian'")
         g = globals()
         return tuple(g[n] for n in self._SPEC_OP_FNS[op])
 
+    def _spec_op_pre(self, op: str, dtype, ee, frame):
+        """Leading arguments of the op's C calls (the Jacobian's take its end
+        effectors and frame)."""
+        if op != "jacobian":
+            return (self._h, self._dtype_arg(dtype)), ()
+        if ee is None:
+            raise ValueError("the Jacobian kernel needs ee")
+        ee_a, pee = _i32arr(ee)
+        return (self._h, self._dtype_arg(dtype), len(ee_a), pee, int(frame)), (ee_a,)
+
     def specialize_op(self, op: str, dtype=None, route: bool = True, compile_only: bool = False,
-                      form: str = "split"):
-        """Compile the model-specialised kernel of one operator ("rnea" or
-        "crba"; form "split" or "whole") with hipRTC and load it; with
-        route=True, that operator's calls without a workspace (and, for
-        rnea, without an inertia override) use it at every batch."""
+                      form: str = "split", ee: Optional[Sequence[int]] = None, frame: int = WORLD):
+        """Compile the model-specialised kernel of one operator ("rnea",
+        "crba" or "jacobian" with its end effectors ``ee`` and ``frame``;
+        form "split" or "whole") with hipRTC and load it; with route=True,
+        that operator's calls without a workspace (and, for rnea, without an
+        inertia override; for the Jacobian, with the same ee and frame) use
+        it at every batch."""
         if form not in ("split", "whole"):
             raise ValueError("form must be 'split' or 'whole'")
         flags = ((SPEC_ROUTE if route else 0) | (SPEC_COMPILE_ONLY if compile_only else 0) |
                  (SPEC_WHOLE if form == "whole" else 0))
         fn, _, _ = self._spec_op_fns(op)
-        _check(fn(self._h, self._dtype_arg(dtype), flags), fn.__name__)
+        pre, keep = self._spec_op_pre(op, dtype, ee, frame)
+        _check(fn(*pre, flags), fn.__name__)
 
-    def specialized_op_info(self, op: str, dtype=None, form: str = "split") -> dict:
+    def specialized_op_info(self, op: str, dtype=None, form: str = "split", ee: Optional[Sequence[int]] = None,
+                            frame: int = WORLD) -> dict:
         _, fn, _ = self._spec_op_fns(op)
+        pre, keep = self._spec_op_pre(op, dtype, ee, frame)
         vg, sc, rt, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         cs = ctypes.c_double()
-        _check(fn(self._h, self._dtype_arg(dtype), SPEC_WHOLE if form == "whole" else 0, ctypes.byref(vg),
-                  ctypes.byref(sc), ctypes.byref(cs), ctypes.byref(rt), ctypes.byref(w)), fn.__name__)
+        _check(fn(*pre, SPEC_WHOLE if form == "whole" else 0, ctypes.byref(vg), ctypes.byref(sc), ctypes.byref(cs),
+                  ctypes.byref(rt), ctypes.byref(w)), fn.__name__)
         return {"vgprs": vg.value, "scratch_bytes": sc.value, "compile_s": cs.value, "routed": bool(rt.value),
                 "route_tiers": rt.value, "waves": w.value}
 
-    def specialized_op_source(self, op: str, dtype=None, form: str = "split") -> str:
+    def specialized_op_source(self, op: str, dtype=None, form: str = "split", ee: Optional[Sequence[int]] = None,
+                              frame: int = WORLD) -> str:
         _, _, fn = self._spec_op_fns(op)
+        pre, keep = self._spec_op_pre(op, dtype, ee, frame)
         flags = SPEC_WHOLE if form == "whole" else 0
         n = _i64()
-        _check(fn(self._h, self._dtype_arg(dtype), flags, None, 0, ctypes.byref(n)), fn.__name__)
+        _check(fn(*pre, flags, None, 0, ctypes.byref(n)), fn.__name__)
         buf = ctypes.create_string_buffer(n.value + 1)
-        _check(fn(self._h, self._dtype_arg(dtype), flags, buf, n.value + 1, ctypes.byref(n)), fn.__name__)
+        _check(fn(*pre, flags, buf, n.value + 1, ctypes.byref(n)), fn.__name__)
         return buf.value.decode()
 
     def specialize_rnea(self, dtype=None, route: bool = True, compile_only: bool = False, form: str = "split"):

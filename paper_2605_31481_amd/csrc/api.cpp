@@ -897,23 +897,24 @@ static int spec_op_args(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t
   return BARD_OK;
 }
 
-static int spec_op_specialize(bard_model_t m, bard_dtype dtype, int32_t flags, int ops) {
+static int spec_op_specialize(bard_model_t m, bard_dtype dtype, int32_t flags, int ops,
+                              const std::vector<int>& ee = {}, int frame = 0) {
   int rc = spec_op_args(m, dtype, flags, BARD_SPEC_ROUTE | BARD_SPEC_COMPILE_ONLY);
   if (rc) return rc;
   const int form = (flags & BARD_SPEC_WHOLE) ? 1 : 0;
   if (flags & BARD_SPEC_COMPILE_ONLY) {
     std::vector<char> code;
     std::string log;
-    rc = spec_compile(spec_op_source(m, dtype == BARD_F64, form, ops), &code, &log);
+    rc = spec_compile(spec_op_source(m, dtype == BARD_F64, form, ops, ee, frame), &code, &log);
     return rc ? fail(rc, "hipRTC compile of the specialised kernel failed: " + log.substr(0, 2000)) : BARD_OK;
   }
   if ((rc = check_device_state())) return rc;
   DeviceCopy* dc = nullptr;
   if ((rc = ensure_device(m, &dc, nullptr))) return rc;
   SpecKernel* sk = nullptr;
-  if ((rc = spec_prepare_op(m, dc, (int)dtype, form, ops, true, &sk))) return rc;
+  if ((rc = spec_prepare_op(m, dc, (int)dtype, form, ops, ee, frame, true, &sk))) return rc;
   std::lock_guard<std::mutex> lk(m->mu);
-  auto other = dc->spec.find(spec_op_key(ops, (int)dtype, 1 - form));
+  auto other = dc->spec.find(spec_op_key(ops, (int)dtype, 1 - form, ee, frame));
   if ((flags & BARD_SPEC_ROUTE) && other != dc->spec.end()) other->second.route_tiers = 0;
   sk->route_tiers = (flags & BARD_SPEC_ROUTE) ? (1 << kSpecTiers) - 1 : 0;
   spec_refresh_route(m);
@@ -921,13 +922,14 @@ static int spec_op_specialize(bard_model_t m, bard_dtype dtype, int32_t flags, i
 }
 
 static int spec_op_info(bard_model_t m, bard_dtype dtype, int32_t flags, int ops, int32_t* vgprs,
-                        int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers, int32_t* waves) {
+                        int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers, int32_t* waves,
+                        const std::vector<int>& ee = {}, int frame = 0) {
   int rc = spec_op_args(m, dtype, flags, 0);
   if (rc) return rc;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= BARD_MAX_DEVICES) return fail(BARD_E_DEVICE, "no device");
   std::lock_guard<std::mutex> lk(m->mu);
-  auto it = m->dev[dev].spec.find(spec_op_key(ops, (int)dtype, (flags & BARD_SPEC_WHOLE) ? 1 : 0));
+  auto it = m->dev[dev].spec.find(spec_op_key(ops, (int)dtype, (flags & BARD_SPEC_WHOLE) ? 1 : 0, ee, frame));
   if (it == m->dev[dev].spec.end() || !it->second.fn)
     return fail(BARD_E_STATE, "no specialised kernel of this operator and form on the current device");
   if (vgprs) *vgprs = it->second.vgprs;
@@ -939,11 +941,11 @@ static int spec_op_info(bard_model_t m, bard_dtype dtype, int32_t flags, int ops
 }
 
 static int spec_op_source_copy(bard_model_t m, bard_dtype dtype, int32_t flags, int ops, char* buf, int64_t cap,
-                               int64_t* len) {
+                               int64_t* len, const std::vector<int>& ee = {}, int frame = 0) {
   int rc = spec_op_args(m, dtype, flags, 0);
   if (rc) return rc;
   if (!len) return fail(BARD_E_ARG, "len is NULL");
-  const std::string src = spec_op_source(m, dtype == BARD_F64, (flags & BARD_SPEC_WHOLE) ? 1 : 0, ops);
+  const std::string src = spec_op_source(m, dtype == BARD_F64, (flags & BARD_SPEC_WHOLE) ? 1 : 0, ops, ee, frame);
   *len = (int64_t)src.size();
   if (buf && cap > 0) {
     const size_t n = std::min<size_t>(src.size(), (size_t)cap - 1);
@@ -981,6 +983,30 @@ int bard_model_specialized_crba_info(bard_model_t m, bard_dtype dtype, int32_t f
 int bard_model_specialized_crba_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
                                        int64_t* len) {
   return spec_op_source_copy(m, dtype, flags, 2, buf, cap, len);
+}
+
+int bard_model_specialize_jacobian(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
+                                   bard_frame frame, int32_t flags) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  return rc ? rc : spec_op_specialize(m, dtype, flags, 4, ee, (int)frame);
+}
+
+int bard_model_specialized_jacobian_info(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
+                                         bard_frame frame, int32_t flags, int32_t* vgprs, int32_t* scratch_bytes,
+                                         double* compile_seconds, int32_t* routed_tiers, int32_t* waves) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  return rc ? rc
+            : spec_op_info(m, dtype, flags, 4, vgprs, scratch_bytes, compile_seconds, routed_tiers, waves, ee,
+                           (int)frame);
+}
+
+int bard_model_specialized_jacobian_source(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
+                                           bard_frame frame, int32_t flags, char* buf, int64_t cap, int64_t* len) {
+  std::vector<int> ee;
+  int rc = spec_args(m, dtype, n_ee, ee_body, frame, &ee);
+  return rc ? rc : spec_op_source_copy(m, dtype, flags, 4, buf, cap, len, ee, (int)frame);
 }
 
 static int spec_aba_args(bard_model_t m, bard_dtype dtype) {
@@ -1198,6 +1224,11 @@ int bard_jacobian(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q,
     DeviceCopy* dc = nullptr;
     int rc2 = ensure_device(m, &dc, (hipStream_t)stream);
     if (rc2) return rc2;
+    if (!ws && m->spec_route.load()) {
+      // a routed Jacobian-only specialised kernel for these end effectors and frame
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 4, std::vector<int>(ee_body, ee_body + n_ee), (int)frame, B);
+      if (sk && spec_fits(a, m->nv, n_ee)) return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
+    }
     if (dc->dm.use_scan)
       return run_tree<R, OP_JAC | OP_KIN>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream, ws, q_tag);
     return run_tree<R, OP_JAC>(m, a, n_ee, ee_body, (int)frame, (hipStream_t)stream, ws, q_tag);
@@ -1290,7 +1321,7 @@ int bard_rnea(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, con
       DeviceCopy* dc = nullptr;
       int rc2 = ensure_device(m, &dc, st);
       if (rc2) return rc2;
-      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 1, B);
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 1, {}, 0, B);
       if (sk && spec_fits(a, m->nv, 0)) return spec_launch<R>(sk, a, m->g, st);
     }
     if (!ws || !(ws->policy & BARD_TIER_BIAS) || q_tag == 0 || qd_tag == 0 || inertia_override)
@@ -1347,7 +1378,7 @@ int bard_crba(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, voi
       DeviceCopy* dc = nullptr;
       int rc2 = ensure_device(m, &dc, st);
       if (rc2) return rc2;
-      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 2, B);
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 2, {}, 0, B);
       if (sk && spec_fits(a, m->nv, 0)) return spec_launch<R>(sk, a, m->g, st);
     }
     if (!ws || !(ws->policy & BARD_TIER_MASS) || q_tag == 0)

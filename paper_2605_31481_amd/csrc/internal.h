@@ -48,13 +48,16 @@ constexpr int kSpecForms = 4;
 std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form);
 // Source text of the specialised forward-dynamics (ABA) kernel of a tree.
 // Single-operator specialised kernels (the chain kernel's code for one
-// output: ops 1 torques, 2 mass matrix; split over waves by limbs for form
-// 0, one wave for form 1): source, key, compile-and-load, and the kernel a
-// bard_rnea / bard_crba call routes to.
-std::string spec_op_source(const bard_model* m, bool fp64, int form, int ops);
-std::string spec_op_key(int ops, int dtype, int form);
-int spec_prepare_op(bard_model* m, DeviceCopy* dc, int dtype, int form, int ops, bool load, SpecKernel** out);
-SpecKernel* spec_lookup_op(bard_model* m, DeviceCopy* dc, int dtype, int ops, int64_t B);
+// output: ops 1 torques, 2 mass matrix, 4 Jacobians of ee in frame; split
+// over waves by limbs for form 0, one wave for form 1): source, key,
+// compile-and-load, and the kernel a bard_rnea / bard_crba / bard_jacobian
+// call routes to.
+std::string spec_op_source(const bard_model* m, bool fp64, int form, int ops, const std::vector<int>& ee, int frame);
+std::string spec_op_key(int ops, int dtype, int form, const std::vector<int>& ee, int frame);
+int spec_prepare_op(bard_model* m, DeviceCopy* dc, int dtype, int form, int ops, const std::vector<int>& ee,
+                    int frame, bool load, SpecKernel** out);
+SpecKernel* spec_lookup_op(bard_model* m, DeviceCopy* dc, int dtype, int ops, const std::vector<int>& ee, int frame,
+                           int64_t B);
 std::string spec_aba_source(const bard_model* m, bool fp64, bool split);
 // Multi-tree plan kernel (bard_spec_plan): every model's specialised chain
 // code in one launch over [K][batch] arrays, each tree split over at most

@@ -1348,12 +1348,15 @@ std::string spec_chain_source(const bard_model* m, const std::vector<int>& ee, i
   return Emitter(m, ee, frame, fp64, form).source();
 }
 
-std::string spec_op_source(const bard_model* m, bool fp64, int form, int ops) {
-  return Emitter(m, {}, 0, fp64, form, SplitPlan::kMaxWaves, ops).source();
+std::string spec_op_source(const bard_model* m, bool fp64, int form, int ops, const std::vector<int>& ee, int frame) {
+  return Emitter(m, ee, frame, fp64, form, SplitPlan::kMaxWaves, ops).source();
 }
 
-std::string spec_op_key(int ops, int dtype, int form) {
-  return "op" + std::to_string(ops) + ":" + std::to_string(form) + ":" + std::to_string(dtype);
+std::string spec_op_key(int ops, int dtype, int form, const std::vector<int>& ee, int frame) {
+  std::string k = "op" + std::to_string(ops) + ":" + std::to_string(form) + ":" + std::to_string(dtype) + ":" +
+                  std::to_string(frame) + ":";
+  for (int e : ee) k += std::to_string(e) + ",";
+  return k;
 }
 
 std::string spec_plan_source(const std::vector<bard_model*>& ms, const std::vector<std::vector<int>>& ee,
@@ -1605,24 +1608,28 @@ int spec_plan_build(const std::vector<bard_model*>& ms, const std::vector<std::v
   return BARD_OK;
 }
 
-int spec_prepare_op(bard_model* m, DeviceCopy* dc, int dtype, int form, int ops, bool load, SpecKernel** out) {
+int spec_prepare_op(bard_model* m, DeviceCopy* dc, int dtype, int form, int ops, const std::vector<int>& ee,
+                    int frame, bool load, SpecKernel** out) {
   return prepare_kernel(
-      m, dc, spec_op_key(ops, dtype, form), [&] { return spec_op_source(m, dtype == BARD_F64, form, ops); },
-      "bard_spec_chain",
+      m, dc, spec_op_key(ops, dtype, form, ee, frame),
+      [&] { return spec_op_source(m, dtype == BARD_F64, form, ops, ee, frame); }, "bard_spec_chain",
       [&](SpecKernel* sk) {
         sk->form = form;
-        sk->zero_rows = (ops & 2) ? spec_zero_rows(m, {}) : 0;  // the mass matrix's zero rows
+        // the zero rows of the outputs written: M's, the Jacobians'
+        const int zm = spec_zero_rows(m, {});
+        sk->zero_rows = ((ops & 2) ? zm : 0) + ((ops & 4) ? spec_zero_rows(m, ee) - zm : 0);
         sk->waves = spec_waves(m, dtype == BARD_F64, form);
       },
       load, out);
 }
 
-SpecKernel* spec_lookup_op(bard_model* m, DeviceCopy* dc, int dtype, int ops, int64_t B) {
+SpecKernel* spec_lookup_op(bard_model* m, DeviceCopy* dc, int dtype, int ops, const std::vector<int>& ee, int frame,
+                           int64_t B) {
   if (!m->spec_route.load()) return nullptr;
   const int bit = 1 << spec_tier(B);
   std::lock_guard<std::mutex> lk(m->mu);
   for (int form = 0; form < 2; ++form) {
-    auto it = dc->spec.find(spec_op_key(ops, dtype, form));
+    auto it = dc->spec.find(spec_op_key(ops, dtype, form, ee, frame));
     if (it != dc->spec.end() && it->second.fn && (it->second.route_tiers & bit)) return &it->second;
   }
   return nullptr;

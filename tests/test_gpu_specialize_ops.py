@@ -1,6 +1,7 @@
 """GPU parity of the model-specialised single-operator kernels: inverse
-dynamics (bard_model_specialize_rnea) and the mass matrix
-(bard_model_specialize_crba), against the FP64 oracle entry by entry on
+dynamics (bard_model_specialize_rnea), the mass matrix
+(bard_model_specialize_crba) and the Jacobians
+(bard_model_specialize_jacobian), against the FP64 oracle entry by entry on
 workload and edge trees, split and whole forms, FP32 and FP64, sizes
 spanning several 64-instance groups with a ragged tail; the mass matrix's
 structural zeros from extra workgroups and from the lanes; routing (calls
@@ -12,7 +13,8 @@ import pytest
 
 import synth
 from paper_2605_31481_amd import bard
-from parity_util import assert_mass, assert_tau, entry_scales, from_dev, inputs, oracle_for, say, to_dev
+from parity_util import (assert_jacobian, assert_mass, assert_tau, entry_scales, from_dev, inputs, oracle_for, say,
+                         to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +134,49 @@ def test_specialized_crba_routing():
     m.specialize_op("crba", route=False)
     assert torch.equal(m.crba(d[0]), gen)
     assert not torch.equal(m.rnea(*d), ref.rnea(*d))  # the inverse-dynamics route stays
+
+
+@pytest.mark.parametrize("form", ["split", "whole"])
+@pytest.mark.parametrize("name,dtype,B", CASES)
+def test_specialized_jacobian_matches_oracle(name, dtype, B, form):
+    tree = synth.tree_by_name(name)
+    ee = list(tree.ee_bodies) if len(tree.ee_bodies) else [tree.n_bodies - 1]
+    frame = B % 2   # both frames over the cases
+    say(f"[gpu] specialised jacobian {name} {dtype} B={B} form={form} frame={frame}")
+    m = bard.Model.from_tree(tree)
+    m.specialize_op("jacobian", dtype=dtype, form=form, ee=ee, frame=frame)
+    assert m.specialized_op_info("jacobian", dtype=dtype, form=form, ee=ee, frame=frame)["routed"]
+    om = oracle_for(tree)
+    q, _, _ = inputs(tree, B, 6600, dtype)
+    J = from_dev(m.jacobian(to_dev(q, dtype), ee, frame=frame))
+    assert_jacobian("spec jacobian", J, om.jacobian(q, ee, frame=frame), dtype)
+
+
+def test_specialized_jacobian_zero_rows_and_routing():
+    import torch
+    say("[gpu] specialised jacobian zero rows and routing")
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    ref = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    m.specialize_op("jacobian", ee=ee, frame=1)
+    om = oracle_for(tree)
+    for B in (4096, 4097):        # zero rows from extra workgroups, then from the lanes
+        q, _, _ = inputs(tree, B, 6700 + B, "float32")
+        out = torch.full((6 * tree.nv * len(ee), B), float("nan"), device="cuda")
+        m.jacobian(to_dev(q, "float32"), ee, frame=1, out=out)
+        torch.cuda.synchronize()
+        assert not torch.isnan(out).any()
+        idx = np.sort(np.random.default_rng(B).choice(B, 200, replace=False))
+        assert_jacobian("zero rows", from_dev(out)[idx], om.jacobian(q[idx], ee, frame=1), "float32")
+    q, _, _ = inputs(tree, 300, 6800, "float32")
+    qd = to_dev(q, "float32")
+    assert not torch.equal(m.jacobian(qd, ee, frame=1), ref.jacobian(qd, ee, frame=1))
+    # another frame, another end-effector set or a workspace keep the generic kernel
+    assert torch.equal(m.jacobian(qd, ee, frame=0), ref.jacobian(qd, ee, frame=0))
+    assert torch.equal(m.jacobian(qd, ee[:2], frame=1), ref.jacobian(qd, ee[:2], frame=1))
+    ws = bard.Workspace(m, 300)
+    ws.set_policy(0)
+    assert torch.equal(m.jacobian(qd, ee, frame=1, ws=ws), ref.jacobian(qd, ee, frame=1))
+    m.specialize_op("jacobian", ee=ee, frame=1, route=False)
+    assert torch.equal(m.jacobian(qd, ee, frame=1), ref.jacobian(qd, ee, frame=1))

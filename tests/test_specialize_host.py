@@ -168,3 +168,20 @@ def test_generated_crba_only_source(name, form):
     assert re.findall(r"\bTAU\((\d+), ", src) == [] and re.findall(r"\bJA\((\d+), ", src) == []
     assert "QD(" not in src.split("bard_spec_chain(")[1]     # velocities and accelerations are not read
     m.specialize_op("crba", compile_only=True, form=form)
+
+
+@pytest.mark.parametrize("name,frame,form", [("humanoid_large", 0, "split"), ("humanoid_small", 1, "whole"),
+                                             ("quadruped_spine", 1, "split")])
+def test_generated_jacobian_only_source(name, frame, form):
+    """The Jacobian-only kernel names every Jacobian entry once, as a stored
+    value or an off-path zero of its table, no torque or mass-matrix entry,
+    reads no velocity, has no barrier, and compiles for gfx950."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    ee = tree.ee_bodies
+    src = m.specialized_op_source("jacobian", form=form, ee=ee, frame=frame)
+    stored = [int(k) for k in re.findall(r"\bJA\((\d+), ", src)]
+    assert sorted(stored + _table(src, "J")) == list(range(len(ee) * 6 * tree.nv))
+    assert re.findall(r"\bTAU\((\d+), ", src) == [] and re.findall(r"\bMA\((\d+), ", src) == []
+    assert "QD(" not in src.split("bard_spec_chain(")[1] and "__syncthreads" not in src
+    m.specialize_op("jacobian", compile_only=True, form=form, ee=ee, frame=frame)
