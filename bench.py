@@ -245,7 +245,7 @@ def op_work(tree, n_ee, op):
 
 
 def bench_operators(torch, bard):
-    """Each plain operator alone (FK; the 4-end-effector Jacobian, RNEA and
+    """Each plain operator alone (FK, the 4-end-effector Jacobian, RNEA and
     CRBA with the generic and the model-specialised kernels; ABA; and the standalone pose and Jacobian
     of the first end effector's path) on the 36-DOF humanoid at B = 4096 and 16384 and on the 7-DOF chain
     at B = 4096, FP32, rotating input/output sets past 512 MB.  Per operator:
@@ -263,6 +263,7 @@ def bench_operators(torch, bard):
         mr.specialize_rnea()
         mr.specialize_op("crba")
         mr.specialize_op("jacobian", ee=ee)
+        mr.specialize_op("fk")
         per_eval = 4 * (tree.nq + 4 * tree.nv + 12 * tree.n_bodies + tree.nv * tree.nv + 6 * tree.nv * len(ee))
         nsets = max(3, min(64, math.ceil(512e6 / (per_eval * B))))
         sets = []
@@ -278,6 +279,7 @@ def bench_operators(torch, bard):
                  "path_J": torch.empty((6 * tree.nv, B), device="cuda")}
             sets.append((d, o))
         binders = {"fk": lambda d, o: m.bind_fk(d[0], o["fk"]),
+                   "fk_specialized": lambda d, o: mr.bind_fk(d[0], o["fk"]),
                    "jacobian": lambda d, o: m.bind_jacobian(d[0], ee, o["jacobian"]),
                    "jacobian_specialized": lambda d, o: mr.bind_jacobian(d[0], ee, o["jacobian"]),
                    "rnea": lambda d, o: m.bind_rnea(d[0], d[1], d[2], o["rnea"]),

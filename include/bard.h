@@ -246,6 +246,15 @@ int bard_model_specialized_crba_info(bard_model_t model, bard_dtype dtype, int32
                                      int32_t* waves);
 int bard_model_specialized_crba_source(bard_model_t model, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
                                        int64_t* len);
+/* The world pose of every body alone (FK, Sec. 3.1 tier 3) written for one
+ * tree in the same way; routes bard_fk calls without a workspace.  Flags,
+ * errors and the two companions as above. */
+int bard_model_specialize_fk(bard_model_t model, bard_dtype dtype, int32_t flags);
+int bard_model_specialized_fk_info(bard_model_t model, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                   int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                   int32_t* waves);
+int bard_model_specialized_fk_source(bard_model_t model, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                     int64_t* len);
 /* The Jacobians of n_ee end-effector bodies (host array ee_body) in
  * `frame` alone written for one tree in the same way (eq. (7) columns from
  * each path joint's world axis and position, the off-path rows from tables);

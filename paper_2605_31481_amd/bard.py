@@ -146,6 +146,12 @@ bard_model_specialized_crba_info = _sig("bard_model_specialized_crba_info",
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
 bard_model_specialized_crba_source = _sig("bard_model_specialized_crba_source",
                                           [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
+bard_model_specialize_fk = _sig("bard_model_specialize_fk", [_vp, ctypes.c_int, _i32])
+bard_model_specialized_fk_info = _sig("bard_model_specialized_fk_info",
+                                      [_vp, ctypes.c_int, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+bard_model_specialized_fk_source = _sig("bard_model_specialized_fk_source",
+                                        [_vp, ctypes.c_int, _i32, ctypes.c_char_p, _i64, ctypes.POINTER(_i64)])
 bard_model_specialize_jacobian = _sig("bard_model_specialize_jacobian", [_vp, ctypes.c_int, _i32, _c_i32p,
                                                                          ctypes.c_int, _i32])
 bard_model_specialized_jacobian_info = _sig("bard_model_specialized_jacobian_info",
@@ -556,11 +562,13 @@ class Model:
                     "crba": ("bard_model_specialize_crba", "bard_model_specialized_crba_info",
                              "bard_model_specialized_crba_source"),
                     "jacobian": ("bard_model_specialize_jacobian", "bard_model_specialized_jacobian_info",
-                                 "bard_model_specialized_jacobian_source")}
+                                 "bard_model_specialized_jacobian_source"),
+                    "fk": ("bard_model_specialize_fk", "bard_model_specialized_fk_info",
+                           "bard_model_specialized_fk_source")}
 
     def _spec_op_fns(self, op: str):
         if op not in self._SPEC_OP_FNS:
-            raise ValueError("op must be 'rnea', 'crba' or 'jacobian'")
+            raise ValueError("op must be 'fk', 'rnea', 'crba' or 'jacobian'")
         g = globals()
         return tuple(g[n] for n in self._SPEC_OP_FNS[op])
 
@@ -576,8 +584,8 @@ class Model:
 
     def specialize_op(self, op: str, dtype=None, route: bool = True, compile_only: bool = False,
                       form: str = "split", ee: Optional[Sequence[int]] = None, frame: int = WORLD):
-        """Compile the model-specialised kernel of one operator ("rnea",
-        "crba" or "jacobian" with its end effectors ``ee`` and ``frame``;
+        """Compile the model-specialised kernel of one operator ("fk",
+        "rnea", "crba" or "jacobian" with its end effectors ``ee`` and ``frame``;
         form "split" or "whole") with hipRTC and load it; with route=True,
         that operator's calls without a workspace (and, for rnea, without an
         inertia override; for the Jacobian, with the same ee and frame) use

@@ -985,6 +985,21 @@ int bard_model_specialized_crba_source(bard_model_t m, bard_dtype dtype, int32_t
   return spec_op_source_copy(m, dtype, flags, 2, buf, cap, len);
 }
 
+int bard_model_specialize_fk(bard_model_t m, bard_dtype dtype, int32_t flags) {
+  return spec_op_specialize(m, dtype, flags, 8);
+}
+
+int bard_model_specialized_fk_info(bard_model_t m, bard_dtype dtype, int32_t flags, int32_t* vgprs,
+                                   int32_t* scratch_bytes, double* compile_seconds, int32_t* routed_tiers,
+                                   int32_t* waves) {
+  return spec_op_info(m, dtype, flags, 8, vgprs, scratch_bytes, compile_seconds, routed_tiers, waves);
+}
+
+int bard_model_specialized_fk_source(bard_model_t m, bard_dtype dtype, int32_t flags, char* buf, int64_t cap,
+                                     int64_t* len) {
+  return spec_op_source_copy(m, dtype, flags, 8, buf, cap, len);
+}
+
 int bard_model_specialize_jacobian(bard_model_t m, bard_dtype dtype, int32_t n_ee, const int32_t* ee_body,
                                    bard_frame frame, int32_t flags) {
   std::vector<int> ee;
@@ -1199,6 +1214,14 @@ int bard_fk(bard_model_t m, bard_ws_t ws, bard_dtype dtype, const void* q, void*
     a.poses = (R*)poses;
     if (!layout_of(L, 0, B, m->nq, &a.sq_b, &a.sq_k) || !layout_of(L, 1, B, 12 * m->n, &a.sp_b, &a.sp_k))
       return fail(BARD_E_ARG, "bad layout stride");
+    if (!ws && m->spec_route.load()) {
+      // a routed pose-only specialised kernel (calls without a workspace)
+      DeviceCopy* dc = nullptr;
+      int rc2 = ensure_device(m, &dc, (hipStream_t)stream);
+      if (rc2) return rc2;
+      SpecKernel* sk = spec_lookup_op(m, dc, (int)dtype, 8, {}, 0, B);
+      if (sk && spec_fits(a, m->nv, 0, m->n)) return spec_launch<R>(sk, a, m->g, (hipStream_t)stream);
+    }
     return run_tree<R, OP_FK>(m, a, 0, nullptr, 0, (hipStream_t)stream, ws, q_tag);
   };
   return dtype == BARD_F32 ? go(0.0f) : go(0.0);

@@ -117,6 +117,6 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
 // output row's offset plus the lane's, fits the 32 bits the specialised
 // kernels address with (else the generic kernel runs).
 template <class Real>
-bool spec_fits(const Args<Real>& a, int nv, int n_ee);
+bool spec_fits(const Args<Real>& a, int nv, int n_ee, int n_pose = 0);  // n_pose: bodies whose poses are written
 
 }  // namespace bard

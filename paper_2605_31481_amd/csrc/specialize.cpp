@@ -140,7 +140,7 @@ SplitPlan make_plan(const bard_model* m, bool whole, bool fp64, int max_waves = 
 class Emitter {
  public:
   // ops: the outputs the kernel computes (1 torques, 2 mass matrix, 4
-  // Jacobians; the split and whole forms only)
+  // Jacobians, 8 world poses; the split and whole forms only)
   Emitter(const bard_model* m, const std::vector<int>& ee, int frame, bool fp64, int form,
           int max_waves = SplitPlan::kMaxWaves, int ops = 7)
       : m_(m), ee_(ee), frame_(frame), fp64_(fp64), ops_(ops), parts_(form == 2 ? 2 : form == 3 ? 3 : 1),
@@ -171,6 +171,7 @@ class Emitter {
          "#define TAU(k, v) bard_st(rt_, (unsigned)(k) * ut_, ot_, (v))\n"
          "#define MA(k, v) bard_st(rM_, (unsigned)(k) * uM_, oM_, (v))\n"
          "#define JA(k, v) bard_st(rJ_, (unsigned)(k) * uJ_, oJ_, (v))\n"
+         "#define PA(k, v) bard_st(rP_, (unsigned)(k) * uP_, oP_, (v))\n"
          "#define Qv(k) Qv_##k\n"
          "#define QDv(k) QDv_##k\n"
          "#define QDDv(k) QDDv_##k\n";
@@ -190,7 +191,8 @@ class Emitter {
           "    Real* __restrict__ tau, Real* __restrict__ M, Real* __restrict__ J,\n"
           "    long long sq_b, long long sq_k, long long sqd_b, long long sqd_k, long long sqdd_b, long long sqdd_k,\n"
           "    long long st_b, long long st_k, long long sM_b, long long sM_k, long long sJ_b, long long sJ_k,\n"
-          "    long long B, Real g0, Real g1, Real g2, int main_blocks, int zero_blocks) {\n"
+          "    long long B, Real g0, Real g1, Real g2, int main_blocks, int zero_blocks,\n"
+          "    Real* __restrict__ P, long long sp_b, long long sp_k) {\n"
           "  if ((int)blockIdx.x >= main_blocks) {\n"
           "    // structural zeros, instance-minor layout: the zero rows cut into\n"
           "    // chunks of 1024 16-byte vectors, one chunk per workgroup in turn\n"
@@ -235,7 +237,8 @@ class Emitter {
        << "  const long long sq_k = " << ld << "LL, sqd_k = " << ld << "LL, sqdd_k = " << ld << "LL, st_k = " << ld
        << "LL, sM_k = " << ld << "LL, sJ_k = " << ld << "LL;\n"
        << "  const Real g0 = io.g[0], g1 = io.g[1], g2 = io.g[2];\n"
-          "  const int zero_blocks = 0;\n";
+          "  const int zero_blocks = 0;\n"
+          "  Real* const P = nullptr;\n  const long long sp_b = 0, sp_k = 0;\n";
     body();
     o_ << "}\n}  // namespace bard_t" << k << "\n";
     return o_.str();
@@ -346,6 +349,8 @@ class Emitter {
       for (int i : tb) forward_kin(i, false);
       for (int l : pl_.bins[w]) limb(l);
       if (w == merge) {
+        if (ops_ & 8)
+          for (int i : tb) store_pose(i);
         for (int i = 0; i < m_->n; ++i)
           if (trunk_[i]) body_force(i, false);
         if (do_jac_)
@@ -392,6 +397,20 @@ class Emitter {
           "  const unsigned ut_ = (unsigned)st_k * (unsigned)sizeof(Real);\n"
           "  const unsigned uM_ = (unsigned)sM_k * (unsigned)sizeof(Real);\n"
           "  const unsigned uJ_ = (unsigned)sJ_k * (unsigned)sizeof(Real);\n";
+    if (ops_ & 8)
+      o_ << "  const unsigned oP_ = (unsigned)(b * sp_b) * (unsigned)sizeof(Real);\n"
+            "  const __amdgpu_buffer_rsrc_t rP_ = __builtin_amdgcn_make_buffer_rsrc(P, (short)0, -1, 0x00020000);\n"
+            "  const unsigned uP_ = (unsigned)sp_k * (unsigned)sizeof(Real);\n";
+  }
+
+  // FK output: body i's world pose [R | p], 3x4 row-major (p about the world
+  // origin: the kinematics keep world positions)
+  void store_pose(int i) {
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k)
+        o_ << "  PA(" << 12 * i + 4 * r + k << ", " << v("R", i) << "[" << 3 * r + k << "]);\n";
+      o_ << "  PA(" << 12 * i + 4 * r + 3 << ", " << v("p", i) << "[" << r << "]);\n";
+    }
   }
 
   // One limb (a chain): forward, its end effectors' Jacobians, backward with
@@ -524,6 +543,7 @@ class Emitter {
   // ---- entering body i: pose, axis, velocity, acceleration, body force ----
   void forward(int i) {
     forward_kin(i);
+    if (ops_ & 8) store_pose(i);
     body_force(i, true);
   }
 
@@ -1682,8 +1702,11 @@ int spec_launch(const SpecKernel* sk, const Args<Real>& a, const double g[3], hi
     zb = std::min<int64_t>(chunks, sk->slots - main);
   }
   int main_blocks = (int)main, zero_blocks = (int)zb;
-  void* args[] = {&q, &qd, &qdd, &tau, &M, &J, &sq_b, &sq_k, &sqd_b, &sqd_k, &sqdd_b, &sqdd_k,
-                  &st_b, &st_k, &sM_b, &sM_k, &sJ_b, &sJ_k, &B, &g0, &g1, &g2, &main_blocks, &zero_blocks};
+  Real* P = a.poses;
+  long long sp_b = a.sp_b, sp_k = a.sp_k;
+  void* args[] = {&q,     &qd,    &qdd,  &tau,   &M,    &J,    &sq_b, &sq_k,        &sqd_b,       &sqd_k,
+                  &sqdd_b, &sqdd_k, &st_b, &st_k,  &sM_b, &sM_k, &sJ_b, &sJ_k,        &B,           &g0,
+                  &g1,    &g2,    &main_blocks, &zero_blocks, &P, &sp_b, &sp_k};
   const int64_t grid = main + zb;
   if (grid > 0x7fffffff) return fail(BARD_E_CAPACITY, "batch too large for one launch");
   if (hipModuleLaunchKernel((hipFunction_t)sk->fn, (unsigned)grid, 1, 1, 64 * sk->waves, 1, 1, 0, st, args,
@@ -1729,9 +1752,10 @@ template int spec_aba_launch<float>(const SpecKernel*, const Args<float>&, const
 template int spec_aba_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
 
 template <class Real>
-bool spec_fits(const Args<Real>& a, int nv, int n_ee) {
+bool spec_fits(const Args<Real>& a, int nv, int n_ee, int n_pose) {
   const int64_t last = a.B > 0 ? a.B - 1 : 0;
   const int64_t lim = (int64_t)(0xffffffffu / sizeof(Real));
+  if (n_pose > 0 && (a.sp_b < 0 || a.sp_k < 0 || (12LL * n_pose - 1) * a.sp_k + last * a.sp_b > lim)) return false;
   const int64_t s[6] = {a.sq_b, a.sqd_b, a.sqdd_b, a.st_b, a.sM_b, a.sJ_b};
   for (int64_t x : s)
     if (x < 0 || last * x > lim) return false;
@@ -1743,8 +1767,8 @@ bool spec_fits(const Args<Real>& a, int nv, int n_ee) {
   return true;
 }
 
-template bool spec_fits<float>(const Args<float>&, int, int);
-template bool spec_fits<double>(const Args<double>&, int, int);
+template bool spec_fits<float>(const Args<float>&, int, int, int);
+template bool spec_fits<double>(const Args<double>&, int, int, int);
 template int spec_launch<float>(const SpecKernel*, const Args<float>&, const double*, hipStream_t);
 template int spec_launch<double>(const SpecKernel*, const Args<double>&, const double*, hipStream_t);
 

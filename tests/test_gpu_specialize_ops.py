@@ -1,7 +1,8 @@
 """GPU parity of the model-specialised single-operator kernels: inverse
 dynamics (bard_model_specialize_rnea), the mass matrix
-(bard_model_specialize_crba) and the Jacobians
-(bard_model_specialize_jacobian), against the FP64 oracle entry by entry on
+(bard_model_specialize_crba), the Jacobians
+(bard_model_specialize_jacobian) and the world poses
+(bard_model_specialize_fk), against the FP64 oracle entry by entry on
 workload and edge trees, split and whole forms, FP32 and FP64, sizes
 spanning several 64-instance groups with a ragged tail; the mass matrix's
 structural zeros from extra workgroups and from the lanes; routing (calls
@@ -13,8 +14,8 @@ import pytest
 
 import synth
 from paper_2605_31481_amd import bard
-from parity_util import (assert_jacobian, assert_mass, assert_tau, entry_scales, from_dev, inputs, oracle_for, say,
-                         to_dev)
+from parity_util import (assert_jacobian, assert_mass, assert_normwise, assert_tau, entry_scales, fk_ref_blocks,
+                         from_dev, inputs, oracle_for, say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -180,3 +181,37 @@ def test_specialized_jacobian_zero_rows_and_routing():
     assert torch.equal(m.jacobian(qd, ee, frame=1, ws=ws), ref.jacobian(qd, ee, frame=1))
     m.specialize_op("jacobian", ee=ee, frame=1, route=False)
     assert torch.equal(m.jacobian(qd, ee, frame=1), ref.jacobian(qd, ee, frame=1))
+
+
+@pytest.mark.parametrize("form", ["split", "whole"])
+@pytest.mark.parametrize("name,dtype,B", CASES + [("free_branches61", "float32", 100)])
+def test_specialized_fk_matches_oracle(name, dtype, B, form):
+    say(f"[gpu] specialised fk {name} {dtype} B={B} form={form}")
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    m.specialize_op("fk", dtype=dtype, form=form)
+    om = oracle_for(tree)
+    q, _, _ = inputs(tree, B, 6900, dtype)
+    poses = from_dev(m.fk(to_dev(q, dtype))).reshape(B, tree.n_bodies, 12)
+    assert_normwise("spec fk", poses, fk_ref_blocks(om, q), dtype)
+
+
+def test_specialized_fk_routing_and_batch_major():
+    import torch
+    say("[gpu] specialised fk routing, batch-major layout")
+    tree = synth.humanoid_large()
+    m = bard.Model.from_tree(tree)
+    ref = bard.Model.from_tree(tree)
+    m.specialize_op("fk")
+    B = 513
+    q, _, _ = inputs(tree, B, 7000, "float32")
+    om = oracle_for(tree)
+    qa = to_dev(q, "float32", layout="aos")
+    out = m.fk(qa, layout="aos")
+    assert_normwise("aos", from_dev(out, layout="aos").reshape(B, tree.n_bodies, 12), fk_ref_blocks(om, q), "float32")
+    qs = to_dev(q, "float32")
+    ws = bard.Workspace(m, B)
+    ws.set_policy(0)
+    assert torch.equal(m.fk(qs, ws=ws), ref.fk(qs))
+    m.specialize_op("fk", route=False)
+    assert torch.equal(m.fk(qs), ref.fk(qs))

@@ -185,3 +185,19 @@ def test_generated_jacobian_only_source(name, frame, form):
     assert re.findall(r"\bTAU\((\d+), ", src) == [] and re.findall(r"\bMA\((\d+), ", src) == []
     assert "QD(" not in src.split("bard_spec_chain(")[1] and "__syncthreads" not in src
     m.specialize_op("jacobian", compile_only=True, form=form, ee=ee, frame=frame)
+
+
+@pytest.mark.parametrize("name,form", [("humanoid_large", "split"), ("humanoid_small", "whole"),
+                                       ("free_branches61", "split")])
+def test_generated_fk_only_source(name, form):
+    """The pose-only kernel stores the 12 pose values of every body once and
+    nothing else, reads no velocity, has no barrier, and compiles."""
+    tree = synth.tree_by_name(name)
+    m = bard.Model.from_tree(tree)
+    src = m.specialized_op_source("fk", form=form)
+    stored = [int(k) for k in re.findall(r"\bPA\((\d+), ", src)]
+    assert sorted(stored) == list(range(12 * tree.n_bodies))
+    assert not re.findall(r"\b(TAU|MA|JA)\((\d+), ", src)
+    assert "QD(" not in src.split("bard_spec_chain(")[1] and "__syncthreads" not in src
+    if name != "free_branches61":   # (its compile takes a while on the host; the GPU tests load it)
+        m.specialize_op("fk", compile_only=True, form=form)
